@@ -1,0 +1,292 @@
+#!/usr/bin/env python
+"""Benchmark of the editable-Gaussian rasterizer on one MI355X.
+
+Headline: fwd+bwd iterations/s at 1M Gaussians.  One step is one pass of the
+whole hot path over one view: compose the basic models under their edits,
+project, bin + depth sort, composite, L1 loss against the view's target, and
+the backward through the autograd Function (recompute, no per-pixel state).
+The scene is 4 nested isosurface shells of 250k Gaussians (1M total), 800x800,
+100 Fibonacci-sphere cameras at radius 4, one view per step; inputs are
+resident in HBM before timing starts.
+
+Also reported: forward Mpix/s on the composed 8 x 150k scene at 1024x1024
+(60 orbit views), the roofline position of the dominant kernel (its average
+duration from HIP events recorded around every launch in the timed region),
+and the CPU oracle timed on a bounded sample of the same step.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpix/s fwd and fwd+bwd iters/s at 1M Gaussians; culled vs plain speedup at ≤0.1 dB"
+HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK = 78.6      # TFLOP/s without packed FP32 (256 CU x 64 FMA lanes x 2 x 2.4 GHz)
+FP32_VALU_PEAK_PACKED = 157.3
+
+# Algorithmic work per unit.
+FWD_FLOP_EVAL, FWD_FLOP_COMP = 13, 10     # per evaluated / extra per composited pair
+BWD_FLOP_EVAL, BWD_FLOP_COMP = 13, 59
+SORT_BYTES_PAIR = 4 + 4 + 4 + 4 + 4       # scatter write key+id, sort read key+id, write id
+PROJECT_BYTES_G = 84 + 56                  # 21 planes read, record + rect written
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--models", type=int, default=4)
+    ap.add_argument("--width", type=int, default=800)
+    ap.add_argument("--views", type=int, default=100)
+    ap.add_argument("--fwd-px", type=int, default=0)
+    ap.add_argument("--bwd-px", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def h2_scene(n_total, k):
+    from paper_2504_17954_amd import inputs as I
+    levels = np.linspace(-0.12, 0.12, k)
+    per = n_total // k
+    models = [I.isosurface_model(per, I.SEED_SCENE + 2 + 100 * m, float(lv)) for m, lv in enumerate(levels)]
+    edits = [I.identity_edit(m) for m in models]
+    return models, edits
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path to measure.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2504_17954_amd import inputs as I
+    from paper_2504_17954_amd import native as N
+    from paper_2504_17954_amd import raster as R
+
+    N.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    W = H = args.width
+
+    # ---------------------------------------------------------------- setup
+    t0 = time.time()
+    models, edits = h2_scene(args.n, args.models)
+    cams = I.cameras_at(I.fibonacci_sphere(args.views), W, H)
+    log(f"scene: {sum(m.n for m in models)} Gaussians in {len(models)} models ({time.time() - t0:.1f}s)")
+    mdev = [{k: torch.from_numpy(v).to(dev) for k, v in m.planes.items()} for m in models]
+    n = sum(m.n for m in models)
+    composed = {k: torch.empty((d, n), dtype=torch.float32, device=dev) for k, d in R.PLANE_DIMS.items()}
+    mid = torch.empty(n, dtype=torch.int32, device=dev)
+    edits_t = R.edit_table(edits, dev)
+    cams_t = R.camera_table(cams, dev)
+    jobs = [R.Jobs.single(n, camera=v) for v in range(args.views)]
+    g = torch.Generator(device=dev)
+    g.manual_seed(I.SEED_TARGET + 2)
+    targets = torch.rand((args.views, 1, 4, H, W), generator=g, device=dev)
+    settings = R.Settings(W, H, fwd_px=args.fwd_px, bwd_px=args.bwd_px)
+    rnd = R.Renderer(settings, capacity=1 << 24, check="sync")
+
+    # pair capacity from a pass over every view (sync mode grows it)
+    R.compose_into(mdev, edits, composed, mid)
+    max_pairs = 0
+    for v in range(args.views):
+        rnd.forward(composed, cams_t, jobs[v], model_id=mid, edits_t=edits_t)
+        max_pairs = max(max_pairs, rnd.pairs())
+    rnd.grow(int(max_pairs * 1.1) + 4096)
+    rnd.check = "defer"
+    for k in R.PLANES:
+        composed[k].requires_grad_(True)
+
+    def step(v):
+        with torch.no_grad():
+            R.compose_into(mdev, edits, composed, mid)
+        rgba = R.rasterize(composed, cams_t, jobs[v], rnd, model_id=mid, edits_t=edits_t)
+        loss = (rgba - targets[v]).abs().mean()
+        loss.backward()
+        for k in R.PLANES:
+            composed[k].grad = None
+        return loss
+
+    for i in range(args.warmup):
+        step(i % args.views)
+    torch.cuda.synchronize()
+
+    # ---------------------------------------------------------------- timed
+    views = [(args.warmup + i) % args.views for i in range(args.steps)]
+    N.ivrgs_timing_enable(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for v in views:
+        step(v)
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    kern = N.ivrgs_timing_read()
+    N.ivrgs_timing_enable(False)
+    rnd.verify()
+    elapsed = t_end - t_start
+    ms_step = elapsed / args.steps * 1e3
+    value = args.steps / elapsed
+    log(f"fwd+bwd: {ms_step:.3f} ms/step, {value:.1f} it/s")
+
+    # --------------------------------------------- algorithmic counts per view
+    counts = {"pairs": [], "evaluated": [], "composited": []}
+    cnt_settings = R.Settings(W, H, fwd_px=args.fwd_px, bwd_px=args.bwd_px, flags=N.FLAG_COUNT_EVAL)
+    cnt = R.Renderer(cnt_settings, capacity=rnd.capacity, check="sync")
+    with torch.no_grad():
+        for v in sorted(set(views)):
+            cnt.forward({k: t.detach() for k, t in composed.items()}, cams_t, jobs[v], model_id=mid,
+                        edits_t=edits_t)
+            st = cnt.status.cpu().numpy()
+            counts["pairs"].append(int(st[0]))
+            counts["evaluated"].append(int(st[2]))
+            counts["composited"].append(int(st[3]))
+    per_view = {k: float(np.mean(v)) for k, v in counts.items()}
+    avg = {k: (ms / max(nl, 1), nl) for k, (ms, nl) in kern.items()}
+    log("kernels (avg ms, launches): " + ", ".join(f"{k} {a:.4f}/{nl}" for k, (a, nl) in avg.items() if nl))
+
+    work = {
+        "render_bwd": ("alu", (BWD_FLOP_EVAL * per_view["evaluated"] + BWD_FLOP_COMP * per_view["composited"]) / 1e12,
+                       "TFLOP/s", FP32_VALU_PEAK),
+        "render_fwd": ("alu", (FWD_FLOP_EVAL * per_view["evaluated"] + FWD_FLOP_COMP * per_view["composited"]) / 1e12,
+                       "TFLOP/s", FP32_VALU_PEAK),
+        "tile_sort": ("hbm", 12 * per_view["pairs"] / 1e9, "GB/s", HBM_PEAK_GBS),
+        "scatter": ("hbm", 8 * per_view["pairs"] / 1e9, "GB/s", HBM_PEAK_GBS),
+        "project": ("hbm", PROJECT_BYTES_G * n / 1e9, "GB/s", HBM_PEAK_GBS),
+        "project_bwd": ("hbm", (84 + 36 + 84) * n / 1e9, "GB/s", HBM_PEAK_GBS),
+        "compose": ("hbm", (84 + 88) * n / 1e9, "GB/s", HBM_PEAK_GBS),
+    }
+    total = {k: ms for k, (ms, nl) in kern.items()}
+    dominant = max((k for k in work if kern[k][1] > 0), key=lambda k: total[k])
+    bound, amount, unit, peak = work[dominant]
+    dur_s = avg[dominant][0] / 1e3
+    achieved = amount / dur_s
+    roofline = {"kernel": dominant, "bound": bound, "achieved": round(achieved, 3), "peak": peak,
+                "unit": unit, "frac": round(achieved / peak, 4), "traffic": None,
+                "avg_ms": round(avg[dominant][0], 4)}
+    if bound == "alu":
+        roofline["frac_vs_packed_peak"] = round(achieved / FP32_VALU_PEAK_PACKED, 4)
+
+    result = {
+        "metric": METRIC, "value": round(value, 3), "unit": "iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"isosurface-{len(models)}shells-{n}-{W}px-fwd+bwd",
+                   "gaussians": n, "models": len(models), "width": W, "height": H,
+                   "views": args.views, "views_per_step": 1,
+                   "pairs_per_view": round(per_view["pairs"]),
+                   "evaluated_per_view": round(per_view["evaluated"]),
+                   "composited_per_view": round(per_view["composited"])},
+        "roofline": roofline,
+        "kernels_avg_ms": {k: round(a, 4) for k, (a, nl) in avg.items() if nl},
+    }
+
+    if not args.no_secondary:
+        result["secondary"] = secondary_fwd(dev)
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(models, edits, cams, W, H, views[0], args.cpu_seconds)
+
+    print(json.dumps(result), flush=True)
+
+
+def secondary_fwd(dev):
+    """Forward Mpix/s on the composed scene: 8 nested shells x 150k Gaussians
+    with recolour / opacity / light edits, 1024x1024, 60 orbit views
+    (project + bin_sort + render_fwd per view; compose once per edit)."""
+    import torch
+    from paper_2504_17954_amd import inputs as I
+    from paper_2504_17954_amd import raster as R
+    t0 = time.time()
+    w = I.c3()
+    log(f"composed scene generated ({time.time() - t0:.1f}s)")
+    mdev = [{k: torch.from_numpy(v).to(dev) for k, v in m.planes.items()} for m in w.models]
+    planes, mid = R.compose(mdev, w.edits, dev)
+    edits_t = R.edit_table(w.edits, dev)
+    cams_t = R.camera_table(w.cameras, dev)
+    n = mid.numel()
+    jobs = [R.Jobs.single(n, camera=v) for v in range(len(w.cameras))]
+    rnd = R.Renderer(R.Settings(w.width, w.height), capacity=1 << 25, check="sync")
+    out = torch.empty((1, 4, w.height, w.width), dtype=torch.float32, device=dev)
+    mx = 0
+    for v in range(len(w.cameras)):
+        rnd.forward(planes, cams_t, jobs[v], model_id=mid, edits_t=edits_t, out=out)
+        mx = max(mx, rnd.pairs())
+    rnd.grow(int(mx * 1.1) + 4096)
+    rnd.check = "defer"
+    for v in range(5):
+        rnd.forward(planes, cams_t, jobs[v], model_id=mid, edits_t=edits_t, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for v in range(len(w.cameras)):
+        rnd.forward(planes, cams_t, jobs[v], model_id=mid, edits_t=edits_t, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rnd.verify()
+    nv = len(w.cameras)
+    mpix = nv * w.width * w.height / dt / 1e6
+    log(f"composed forward: {dt / nv * 1e3:.3f} ms/view, {mpix:.1f} Mpix/s")
+    return {"fwd_mpix_s": round(mpix, 2), "fwd_ms_per_view": round(dt / nv * 1e3, 4),
+            "workload": f"compose-{len(w.models)}x{w.models[0].n}-{w.width}px-{nv}views-fwd"}
+
+
+def cpu_baseline(models, edits, cams, W, H, view, seconds):
+    """The CPU oracle on a bounded sample of one step: compose, then forward
+    and backward of the L1 loss restricted to a random pixel sample; the
+    per-pixel cost is scaled to the full image, the per-step fixed cost
+    (projection and sort of every Gaussian) is counted once per pass."""
+    import oracle as O
+    O.build()
+    rows = np.stack([e.row() for e in edits])
+    t0 = time.perf_counter()
+    planes, mid = O.compose([m.planes for m in models], rows)
+    t_compose = time.perf_counter() - t0
+    cam = cams[view]
+    prm = O.Params(W, H)
+    rng = np.random.default_rng(0)
+
+    def run(npx):
+        pix = np.stack([rng.integers(0, W, npx), rng.integers(0, H, npx)], 1)
+        t = time.perf_counter()
+        ref = O.render(planes, cam, prm, model_id=mid, edits=rows, pix=pix)
+        tgt = rng.uniform(0, 1, ref["rgba"].shape)
+        dl = np.sign(ref["rgba"] - tgt) / (4.0 * W * H)
+        O.backward(planes, cam, prm, dl, model_id=mid, edits=rows, pix=pix)
+        return time.perf_counter() - t
+
+    t_fixed = run(1)
+    t_small = run(512)
+    per_px = max((t_small - t_fixed) / 511, 1e-7)
+    npx = int(np.clip((seconds - t_fixed) / per_px, 64, W * H))
+    t_sample = run(npx)
+    per_px = max((t_sample - t_fixed) / max(npx - 1, 1), 1e-9)
+    t_step = t_compose + t_fixed + per_px * W * H
+    log(f"cpu oracle: fixed {t_fixed:.2f}s, {npx} px in {t_sample:.2f}s -> {t_step:.1f}s per step")
+    return {"value": round(1.0 / t_step, 6), "unit": "iters/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"one step of the same workload (view {view}): compose, then forward+backward "
+                      f"of {npx} random pixels of {W}x{H}; per-pixel time scaled to the full image, "
+                      f"projection/sort counted once ({t_sample:.1f}s measured)"}
+
+
+if __name__ == "__main__":
+    main()

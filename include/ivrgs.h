@@ -1,0 +1,255 @@
+/*
+ * ivrgs.h -- C ABI of the MI355X (gfx950) editable-Gaussian rasterizer.
+ *
+ * The library renders editable 3D Gaussians (iVR-GS, Sec. 4.3: geometry
+ * mu, q, s, o, n and shading c_v, k_a, k_d, k_s, beta) with a tile-based
+ * pipeline: EWA projection with per-Gaussian Blinn-Phong shading, tile binning
+ * with a depth sort, front-to-back alpha compositing, the matching backward
+ * pass, and composition of basic models under edits.
+ *
+ * Conventions shared by every entry point
+ *   - Every pointer inside a struct or passed as an array is a DEVICE pointer
+ *     owned by the caller, unless the comment says "host".  The library never
+ *     allocates device memory; scratch space comes from a caller workspace
+ *     whose size ivrgs_workspace_size() returns.
+ *   - Calls are asynchronous on `stream` (a hipStream_t passed as void*).
+ *   - The returned status covers host-side validation only (null pointers,
+ *     sizes, unsupported settings); on an error nothing is launched.  Errors
+ *     found on the device (pair capacity exceeded) are written to the device
+ *     status words of ivrgs_bins and make later kernels of the same view skip.
+ *   - Gaussian attributes are FP32 planes, component-major ("SoA"):
+ *     plane[c * n + i] is component c of Gaussian i.
+ *   - Pixel (x, y) has its centre at (x + 0.5, y + 0.5); camera axes follow
+ *     OpenCV (x right, y down, z forward).
+ *   - Images are planar RGBA, FP32, [job][4][height][width]; RGB is
+ *     premultiplied (C + T_final * bg), A = 1 - T_final.
+ */
+#ifndef IVRGS_H
+#define IVRGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    IVRGS_OK = 0,
+    IVRGS_E_INVALID = 1,     /* null pointer or negative size */
+    IVRGS_E_SHAPE = 2,       /* inconsistent sizes (image, tiles, jobs) */
+    IVRGS_E_CAPACITY = 3,    /* workspace or pair buffer too small (host-checked) */
+    IVRGS_E_HIP = 4,         /* a HIP runtime call failed */
+    IVRGS_E_UNSUPPORTED = 5  /* a setting outside the supported range */
+} ivrgs_status;
+
+/* Device status bits written by ivrgs_bin_sort into ivrgs_bins.status[1]. */
+#define IVRGS_DEV_E_CAPACITY 1u  /* more (tile, Gaussian) pairs than capacity */
+
+/* Parameter flags (ivrgs_params.flags). */
+#define IVRGS_FLAG_PERSISTENT 1u  /* render kernels use the persistent (job, tile) queue */
+#define IVRGS_FLAG_COUNT_EVAL 2u  /* render_fwd counts evaluated (pixel, Gaussian) pairs into
+                                     status[2] and composited ones into status[3] */
+
+/* Editable Gaussians (Sec. 4.3), device SoA planes of length n each:
+ *   mean[3][n]       mu
+ *   log_scale[3][n]  s = exp(log_scale)
+ *   quat[4][n]       q = (w, x, y, z), normalised inside the library
+ *   opacity[1][n]    o, used as given (an edit may scale it beyond 1)
+ *   normal[3][n]     n, normalised inside the library
+ *   color[3][n]      render-ready voxel colour c_v = c_p + delta-c; for
+ *                    ivrgs_compose inputs this plane holds delta-c
+ *   shade[4][n]      k_a, k_d, k_s, beta
+ *   model_id[n]      basic-model index of each Gaussian (selects its light),
+ *                    or NULL for model 0 */
+typedef struct {
+    int64_t n;
+    const float *mean, *log_scale, *quat, *opacity, *normal, *color, *shade;
+    const int32_t *model_id;
+} ivrgs_gaussians;
+
+/* Same layout, writable: outputs of ivrgs_compose and gradients. */
+typedef struct {
+    int64_t n;
+    float *mean, *log_scale, *quat, *opacity, *normal, *color, *shade;
+    int32_t *model_id;
+} ivrgs_gaussians_mut;
+
+/* Pinhole camera, 16 FP32 words: x_cam = R x_world + t (R row-major,
+ * world -> camera); pixel = (fx x/z + cx, fy y/z + cy). */
+typedef struct {
+    float R[9], t[3];
+    float fx, fy, cx, cy;
+} ivrgs_camera;
+
+/* Per-basic-model edit row, 16 words (Sec. 4.5 and Sec. 4.6):
+ *   palette      new palette colour c_p' (recolour)
+ *   opacity_scale  o' = s_o * o
+ *   shade_scale, shade_bias   (k_a, k_d, k_s, beta)' = lambda * k + b
+ *   light_dir    orbital (directional) light direction, world space, pointing
+ *                from the surface toward the light; normalised inside
+ *   headlight    nonzero: point light at the camera, l = v (Sec. 3) */
+typedef struct {
+    float palette[3];
+    float opacity_scale;
+    float shade_scale[4];
+    float shade_bias[4];
+    float light_dir[3];
+    int32_t headlight;
+} ivrgs_model_edit;
+
+/* One render job: one camera over one list of Gaussians.  The Gaussians of
+ * job j are g(k) = gauss_index ? gauss_index[gauss_begin + k]
+ *                              : gauss_begin + k,  k < gauss_count,
+ * and their projected records are rec_begin + k.  Jobs must not overlap in
+ * records; records of all jobs form [0, n_records). */
+typedef struct {
+    int32_t camera;
+    int32_t gauss_begin;
+    int32_t gauss_count;
+    int32_t rec_begin;
+} ivrgs_job;
+
+/* A batch of jobs over one Gaussian set. */
+typedef struct {
+    ivrgs_gaussians g;
+    const int32_t *gauss_index;      /* device, or NULL */
+    const ivrgs_model_edit *edits;   /* device [n_models]: light per model */
+    int32_t n_models;
+    const ivrgs_camera *cameras;     /* device */
+    const ivrgs_job *jobs;           /* device [n_jobs] */
+    int32_t n_jobs;
+    int32_t max_job_count;           /* host-known max gauss_count over jobs */
+    int64_t n_records;               /* host-known sum of gauss_count */
+} ivrgs_batch;
+
+/* Compositing constants and launch shape.  alpha_min, alpha_max, T_min: an
+ * alpha below alpha_min is skipped, alpha is capped at alpha_max and the pass
+ * stops before a Gaussian that would drop the transmittance below T_min.
+ * lowpass: added to the diagonal of the screen covariance (px^2).  z_near:
+ * Gaussians whose depth key is <= z_near are culled.  tile must be 16.
+ * fwd_px / bwd_px: pixels per lane of the render kernels (1, 2 or 4; 0 picks
+ * the default); they change speed, not results. */
+typedef struct {
+    float alpha_min, alpha_max, T_min, lowpass, z_near;
+    float bg[3];
+    int32_t width, height;
+    int32_t tile;
+    uint32_t flags;
+    int32_t fwd_px, bwd_px;
+    int32_t sort_chunk;              /* records per scatter workgroup, 0 = default */
+    int32_t reserved;
+} ivrgs_params;
+
+/* Projected records (device, caller-allocated, n_records entries):
+ *   rec[r][12]  x, y, qa, qb, qc, opacity, r, g, b, depth key, alpha cutoff, 0
+ *               where the 2D Gaussian at offset d = p - (x, y) is
+ *               2^(qa dx^2 + qb dx dy + qc dy^2)  (log2 units), alpha =
+ *               min(alpha_max, opacity * that), and the depth key is the
+ *               FP32 camera-space z of the mean
+ *   rect[r]     tile rectangle [x0, x1) x [y0, y1) packed as
+ *               (x0 | y0 << 16, x1 | y1 << 16); (0, 0) if culled */
+typedef struct {
+    float *rec;
+    uint32_t *rect;
+} ivrgs_projected;
+
+/* Tile bins (device, caller-allocated):
+ *   tile_start[n_jobs * tiles + 1]  start of each tile's list in `sorted`;
+ *                                   the last entry is the pair total
+ *   sorted[capacity]                record ids, each tile front to back by
+ *                                   (depth key, record id)
+ *   status[4]                       [0] pairs required, [1] IVRGS_DEV_E_* bits,
+ *                                   [2] evaluated and [3] composited pixel-
+ *                                   Gaussian pairs (IVRGS_FLAG_COUNT_EVAL);
+ *                                   written by the library */
+typedef struct {
+    uint32_t *tile_start;
+    uint32_t *sorted;
+    int64_t capacity;
+    int64_t *status;
+} ivrgs_bins;
+
+/* Bytes of workspace needed by ivrgs_bin_sort, ivrgs_render_fwd and
+ * ivrgs_render_bwd for this batch and pair capacity. */
+size_t ivrgs_workspace_size(const ivrgs_batch *batch, const ivrgs_params *params,
+                            int64_t capacity);
+
+/* Number of tiles per job for the given image size (ceil(W/16) * ceil(H/16)). */
+int32_t ivrgs_tiles_per_job(const ivrgs_params *params);
+
+/* Composition and editing (Sec. 4.5; light-magnitude edit in the general
+ * lambda * k + b form of Sec. 4.6).  Concatenates `n_models` basic models in
+ * order into `out` (out->n must equal the sum of models[m].n) and applies
+ * edit row m to model m:
+ *   c_v = palette[m] + delta-c,  o' = opacity_scale[m] * o,
+ *   (k_a, k_d, k_s, beta)' = shade_scale[m] * (...) + shade_bias[m];
+ * mean, log_scale, quat and normal are copied; out->model_id[i] = m.
+ * models: HOST array of n_models structs (device planes inside);
+ * edits: HOST array of n_models rows. */
+ivrgs_status ivrgs_compose(const ivrgs_gaussians *models, int32_t n_models,
+                           const ivrgs_model_edit *edits, ivrgs_gaussians_mut *out,
+                           void *stream);
+
+/* Projection (Sec. 3: Eq. 1, Sigma = R S S^T R^T, EWA Sigma' = J W Sigma W^T J^T)
+ * and Blinn-Phong shading (Eq. 3 with I_a = I_d = c_v, I_s = white, v the unit
+ * direction from the Gaussian to the camera, l = v for the headlight or the
+ * model's orbital direction; Sec. 4.3) of every (job, Gaussian) into records.
+ * A Gaussian is culled (empty rect) if its depth key <= z_near, its screen
+ * covariance is not positive definite, opacity < alpha_min, any input is not
+ * finite, or its conservative footprint misses the image. */
+ivrgs_status ivrgs_project(const ivrgs_batch *batch, const ivrgs_params *params,
+                           ivrgs_projected *out, void *stream);
+
+/* Tile binning and depth sort ("sorted by depth", Sec. 3): for each job and
+ * 16x16 tile, the list of records whose rect covers the tile, ordered by
+ * (depth key, record id).  Writes bins->tile_start, bins->sorted and
+ * bins->status.  If the pair total exceeds bins->capacity, status[1] gets
+ * IVRGS_DEV_E_CAPACITY, status[0] the required count, and the lists are not
+ * written (render calls then leave their outputs untouched). */
+ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params,
+                            const ivrgs_projected *proj, ivrgs_bins *bins,
+                            void *workspace, size_t workspace_bytes, void *stream);
+
+/* Front-to-back alpha compositing (Eq. 2): per pixel C = sum T_i alpha_i c_i,
+ * T_i = prod_{j<i} (1 - alpha_j).  out_rgba: [n_jobs][4][H][W].  out_maxw:
+ * [n_records] or NULL; if given it must be zeroed by the caller and receives,
+ * per record, the largest T*alpha over its composited pixels (culling labels). */
+ivrgs_status ivrgs_render_fwd(const ivrgs_batch *batch, const ivrgs_params *params,
+                              const ivrgs_projected *proj, const ivrgs_bins *bins,
+                              float *out_rgba, float *out_maxw,
+                              void *workspace, size_t workspace_bytes, void *stream);
+
+/* Backward of ivrgs_project + ivrgs_render_fwd.  Recomputes the per-pixel
+ * compositing front to back from out_rgba (nothing per pixel is stored by the
+ * forward) and returns dL/d(parameters) for upstream dL/dRGBA (dl_drgba, same
+ * layout as out_rgba).  grads: planes of length batch->g.n (model_id unused);
+ * the callee zeroes them.  Gaussians shared by several jobs accumulate. */
+ivrgs_status ivrgs_render_bwd(const ivrgs_batch *batch, const ivrgs_params *params,
+                              const ivrgs_projected *proj, const ivrgs_bins *bins,
+                              const float *out_rgba, const float *dl_drgba,
+                              ivrgs_gaussians_mut *grads,
+                              void *workspace, size_t workspace_bytes, void *stream);
+
+/* Kernel timing (benchmark instrumentation).  While enabled, every kernel
+ * the library launches is bracketed by a pair of HIP events recorded on its
+ * launch stream; ivrgs_timing_read() waits for those events and returns, per
+ * kernel kind, the summed milliseconds and the number of launches since the
+ * last enable.  Kinds: 0 project, 1 tile counts (difference grid, prefix,
+ * scan), 2 scatter, 3 tile sort, 4 render_fwd, 5 render_bwd, 6 project_bwd,
+ * 7 compose, 8 fills.  Process-wide state; not for concurrent callers. */
+#define IVRGS_TIMING_KINDS 9
+void ivrgs_timing_enable(int32_t on);
+int32_t ivrgs_timing_read(double *ms, int64_t *launches);
+
+/* sizeof of the ABI structs, for binding checks: which = 0 gaussians,
+ * 1 camera, 2 model_edit, 3 job, 4 batch, 5 params, 6 projected, 7 bins. */
+int32_t ivrgs_struct_size(int32_t which);
+
+/* Human-readable name of a status code. */
+const char *ivrgs_status_string(ivrgs_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IVRGS_H */

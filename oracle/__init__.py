@@ -24,10 +24,10 @@ _LIB = os.path.join(_HERE, "libivrgs_oracle.so")
 PLANES = ("mean", "log_scale", "quat", "opacity", "normal", "color", "shade")
 DIMS = (3, 3, 4, 1, 3, 3, 4)
 P_FIELDS = ("valid", "z32", "mx", "my", "cov00", "cov01", "cov11", "q00", "q01", "q11",
-            "o", "r", "g", "b", "extx", "exty", "tx", "ty", "tz", "nl", "nh")
+            "o", "r", "g", "b", "extx", "exty", "tx", "ty", "tz", "nl", "nh", "dm", "kappa", "ergb")
 P_WIDTH = len(P_FIELDS)
 REC_FIELDS = ("mx", "my", "q00", "q01", "q11", "o", "r", "g", "b")
-AMB_ALPHA_MIN, AMB_T_MIN, AMB_ALPHA_MAX = 1, 2, 4
+AMB_ALPHA_MIN, AMB_T_MIN, AMB_ALPHA_MAX, AMB_SHADE, AMB_MANY = 1, 2, 4, 8, 16
 
 
 def build(force: bool = False) -> str:
@@ -151,27 +151,69 @@ def render(planes, cam, params: Params, model_id=None, edits=None, pix=None,
            use_box: bool = True, want_maxw: bool = False, want_proj: bool = False):
     """Render the whole image (pix None -> rgba [4, H, W]) or the listed
     pixels (pix [m, 2] of (x, y) -> rgba [m, 4]).  Returns a dict with
-    rgba, flags (ambiguity bits per pixel), maxw (per Gaussian, optional),
-    stats (composited pairs, kept Gaussians, evaluated pairs)."""
+    rgba, flags (ambiguity bits per pixel), alt / n_alt (the images of the
+    other branches of up to two ambiguous decisions per pixel, [.., 3, 4]),
+    maxw (per Gaussian, optional), stats (composited pairs, kept Gaussians,
+    evaluated pairs)."""
     inp = _Inputs(planes, model_id, edits, cam)
     p = _pix(pix)
     npix = params.width * params.height if p is None else p.shape[0]
     rgba = np.zeros((npix, 4), np.float64)
     flags = np.zeros(npix, np.int32)
+    alt = np.zeros((npix, 3, 4), np.float64)
+    n_alt = np.zeros(npix, np.int32)
     maxw = np.zeros(inp.n, np.float64) if want_maxw else None
     stats = np.zeros(3, np.int64)
     proj = np.zeros((inp.n, P_WIDTH), np.float64) if want_proj else None
     prm = params.c()
+    vp = C.c_void_p
     lib().og_render(*inp.args(), C.byref(prm), C.c_int64(npix),
-                    None if p is None else p.ctypes.data_as(C.c_void_p), C.c_int(int(use_box)),
-                    rgba.ctypes.data_as(C.c_void_p), flags.ctypes.data_as(C.c_void_p),
-                    None if maxw is None else maxw.ctypes.data_as(C.c_void_p),
-                    stats.ctypes.data_as(C.c_void_p),
-                    None if proj is None else proj.ctypes.data_as(C.c_void_p))
+                    None if p is None else p.ctypes.data_as(vp), C.c_int(int(use_box)),
+                    rgba.ctypes.data_as(vp), flags.ctypes.data_as(vp), alt.ctypes.data_as(vp),
+                    n_alt.ctypes.data_as(vp), None if maxw is None else maxw.ctypes.data_as(vp),
+                    stats.ctypes.data_as(vp), None if proj is None else proj.ctypes.data_as(vp))
     if p is None:
-        rgba = rgba.reshape(params.height, params.width, 4).transpose(2, 0, 1).copy()
-        flags = flags.reshape(params.height, params.width)
-    return {"rgba": rgba, "flags": flags, "maxw": maxw, "stats": stats, "proj": proj}
+        H, W = params.height, params.width
+        rgba = rgba.reshape(H, W, 4).transpose(2, 0, 1).copy()
+        flags = flags.reshape(H, W)
+        alt = alt.reshape(H, W, 3, 4)
+        n_alt = n_alt.reshape(H, W)
+    return {"rgba": rgba, "flags": flags, "alt": alt, "n_alt": n_alt, "maxw": maxw,
+            "stats": stats, "proj": proj}
+
+
+def image_error(gpu, ref):
+    """Max-abs error of a GPU image against the oracle, accepting for each
+    pixel the primary result or any of its ambiguous-branch alternatives.
+    Pixels the oracle cannot resolve (more than two ambiguous decisions, or
+    ill-conditioned shading) are excluded.  gpu: [4, H, W] or [m, 4] like
+    ref["rgba"].  Returns (max error, excluded pixel count, pixels that
+    matched an alternative)."""
+    g = np.asarray(gpu, np.float64)
+    r = ref["rgba"]
+    if r.ndim == 3:
+        g = g.transpose(1, 2, 0).reshape(-1, 4)
+        r = r.transpose(1, 2, 0).reshape(-1, 4)
+    flags = ref["flags"].reshape(-1)
+    alt = ref["alt"].reshape(-1, 3, 4)
+    n_alt = ref["n_alt"].reshape(-1)
+    excl = (flags & (AMB_MANY | AMB_SHADE)) != 0
+    err = np.abs(g - r).max(1)
+    used = 0
+    for k in range(3):
+        has = n_alt > k
+        e = np.abs(g - alt[:, k]).max(1)
+        better = has & (e < err)
+        used += int(better.sum())
+        err = np.where(better, e, err)
+    keep = ~excl
+    return (float(err[keep].max()) if keep.any() else 0.0), int(excl.sum()), used
+
+
+def grad_mask(ref):
+    """Pixels whose upstream gradient may be used for a gradient comparison:
+    no ambiguous decision, no active-cap ambiguity, no ill-conditioned shading."""
+    return ref["flags"] == 0
 
 
 def backward(planes, cam, params: Params, dl, model_id=None, edits=None, pix=None):

@@ -75,7 +75,7 @@ typedef struct {
 enum {
     P_VALID = 0, P_Z32, P_MX, P_MY, P_COV00, P_COV01, P_COV11,
     P_Q00, P_Q01, P_Q11, P_O, P_R, P_G, P_B, P_EXTX, P_EXTY,
-    P_TX, P_TY, P_TZ, P_NL, P_NH, P_WIDTH
+    P_TX, P_TY, P_TZ, P_NL, P_NH, P_DM, P_KAPPA, P_ERGB, P_WIDTH
 };
 /* The nine differentiable record values, in this order. */
 enum { R_MX = 0, R_MY, R_Q00, R_Q01, R_Q11, R_O, R_CR, R_CG, R_CB, R_N };
@@ -264,6 +264,29 @@ static int project_one(const cplx p[N_PARAM], float z32, const og_camera *cam,
         }
         aux[P_TX] = creal(t[0]); aux[P_TY] = creal(t[1]); aux[P_TZ] = creal(t[2]);
         aux[P_NL] = creal(nl); aux[P_NH] = creal(nh);
+        /* FP32 error model inputs of a kernel that computes in single
+         * precision: the screen mean carries about one unit in the last place
+         * of the larger coordinate; kappa is the condition number of Sigma'. */
+        {
+            float big = (float)fmax(fabs(creal(mx)), fabs(creal(my)));
+            aux[P_DM] = (double)(nextafterf(big, INFINITY) - big) + 1e-6;
+            double a2 = creal(S2[0]), b2 = creal(S2[1]), c2 = creal(S2[3]);
+            double mid = 0.5 * (a2 + c2), rad = sqrt(0.25 * (a2 - c2) * (a2 - c2) + b2 * b2);
+            aux[P_KAPPA] = (mid - rad) > 0.0 ? (mid + rad) / (mid - rad) : 1e30;
+        }
+        /* Bound on the FP32 error of the colour: about 1e-6 relative, plus the
+         * specular lobe's sensitivity k_s beta |n.h|^(beta-1) times a 4e-7
+         * error in n.h, plus the whole lobe when |n.l| is too close to 0 for
+         * the [|n.l| > 0] gate to be decided in FP32. */
+        {
+            double ahv = fabs(creal(nh)), anlv = fabs(creal(nl));
+            double ks = creal(shd[2]), be = creal(shd[3]);
+            double big = fmax(fabs(creal(rgb[0])), fmax(fabs(creal(rgb[1])), fabs(creal(rgb[2]))));
+            double e = 1e-6 * (big + 1.0);
+            if (creal(spec) != 0.0 && ahv > 0.0) e += ks * be * pow(ahv, be - 1.0) * 4e-7;
+            if (anlv < 1e-6 && ahv > 0.0) e += fabs(ks) * pow(ahv, be);
+            aux[P_ERGB] = e;
+        }
     }
     return valid;
 }
@@ -351,24 +374,46 @@ static int64_t sorted_order(const double *proj, int64_t n, int64_t *order)
     return m;
 }
 
-/* Decision flags of a pixel (bit set = ambiguous within the stated margins). */
-enum { AMB_ALPHA_MIN = 1, AMB_T_MIN = 2, AMB_ALPHA_MAX = 4 };
+/* Decision flags of a pixel (bit set = the FP32 result may take the other
+ * branch, by the error model below). */
+enum { AMB_ALPHA_MIN = 1, AMB_T_MIN = 2, AMB_ALPHA_MAX = 4, AMB_SHADE = 8, AMB_MANY = 16 };
+enum { GATE_ALPHA = 1, GATE_T = 2 };
+#define MAX_AMB 8
+
+typedef struct {
+    int64_t k;   /* position in the sorted order */
+    int gate;    /* GATE_ALPHA or GATE_T */
+} dec_t;
 
 typedef struct {
     int64_t idx;
     double alpha, raw, G, T, dx, dy;
 } hit_t;
 
-/* Composite one pixel front to back.  Fills hits (the composited list) when
- * non-NULL (capacity n).  Returns the number composited. */
+static int flipped(const dec_t *flips, int nflips, int64_t k, int gate)
+{
+    for (int i = 0; i < nflips; ++i)
+        if (flips[i].k == k && flips[i].gate == gate) return 1;
+    return 0;
+}
+
+/*
+ * Composite one pixel front to back.  Fills hits (the composited list) when
+ * non-NULL (capacity m).  flips: decisions to take the other way.  amb (when
+ * non-NULL, capacity MAX_AMB): receives the decisions that an FP32
+ * evaluation could take the other way, by the error model
+ *   |ln alpha error| <= 2e-6 + (3e-7 kappa + 2e-6) |power| + |Q d|_1 dm
+ * (dm, kappa per Gaussian), and for the transmittance the running sum of
+ * alpha/(1-alpha) times those bounds.  Returns the number composited.
+ */
 static int64_t composite_pixel(const double *proj, const int64_t *order, int64_t m,
                                const og_params *prm, double px, double py, int use_box,
-                               double rgba[4], double *T_final, int *flags, hit_t *hits,
-                               int64_t *evaluated)
+                               const dec_t *flips, int nflips, double rgba[4], double *T_final,
+                               int *flags, hit_t *hits, int64_t *evaluated, dec_t *amb, int *namb)
 {
-    double T = 1.0, C[3] = {0, 0, 0}, A = 0.0;
+    double T = 1.0, C[3] = {0, 0, 0}, A = 0.0, eT = 0.0, eshade = 0.0;
     int64_t nh = 0, ev = 0;
-    int fl = 0;
+    int fl = 0, na = 0;
     for (int64_t k = 0; k < m; ++k) {
         const double *g = proj + order[k] * P_WIDTH;
         double dx = px - g[P_MX], dy = py - g[P_MY];
@@ -378,13 +423,29 @@ static int64_t composite_pixel(const double *proj, const int64_t *order, int64_t
         double G = exp(power);
         double raw = g[P_O] * G;
         double alpha = raw < prm->alpha_max ? raw : prm->alpha_max;
-        if (fabs(alpha - prm->alpha_min) <= 1e-5 * prm->alpha_min) fl |= AMB_ALPHA_MIN;
-        if (alpha < prm->alpha_min) continue;
-        if (fabs(raw - prm->alpha_max) <= 1e-5 * prm->alpha_max) fl |= AMB_ALPHA_MAX;
+        double qdx = g[P_Q00] * dx + g[P_Q01] * dy, qdy = g[P_Q01] * dx + g[P_Q11] * dy;
+        double ea = 2e-6 + (3e-7 * g[P_KAPPA] + 2e-6) * fabs(power) + (fabs(qdx) + fabs(qdy)) * g[P_DM];
+        int pass = alpha >= prm->alpha_min;
+        if (alpha > 0.0 && fabs(log(alpha / prm->alpha_min)) <= ea) {
+            fl |= AMB_ALPHA_MIN;
+            if (amb && na < MAX_AMB) amb[na] = (dec_t){k, GATE_ALPHA};
+            ++na;
+        }
+        if (flips && flipped(flips, nflips, k, GATE_ALPHA)) pass = !pass;
+        if (!pass) continue;
+        if (raw > 0.0 && fabs(log(raw / prm->alpha_max)) <= ea) fl |= AMB_ALPHA_MAX;
         double Tn = T * (1.0 - alpha);
-        if (fabs(Tn - prm->T_min) <= 1e-4 * prm->T_min) fl |= AMB_T_MIN;
-        if (Tn < prm->T_min) break;
+        double eTn = eT + alpha / (1.0 - alpha) * ea + 2e-7;
+        int stop = Tn < prm->T_min;
+        if (fabs(log(Tn / prm->T_min)) <= eTn) {
+            fl |= AMB_T_MIN;
+            if (amb && na < MAX_AMB) amb[na] = (dec_t){k, GATE_T};
+            ++na;
+        }
+        if (flips && flipped(flips, nflips, k, GATE_T)) stop = !stop;
+        if (stop) break;
         double w = T * alpha;
+        eshade += w * g[P_ERGB];
         C[0] += w * g[P_R];
         C[1] += w * g[P_G];
         C[2] += w * g[P_B];
@@ -400,7 +461,9 @@ static int64_t composite_pixel(const double *proj, const int64_t *order, int64_t
         }
         ++nh;
         T = Tn;
+        eT = eTn;
     }
+    if (eshade > 2e-5) fl |= AMB_SHADE;
     rgba[0] = C[0] + T * prm->bg[0];
     rgba[1] = C[1] + T * prm->bg[1];
     rgba[2] = C[2] + T * prm->bg[2];
@@ -408,6 +471,7 @@ static int64_t composite_pixel(const double *proj, const int64_t *order, int64_t
     if (T_final) *T_final = T;
     if (flags) *flags = fl;
     if (evaluated) *evaluated = ev;
+    if (namb) *namb = na;
     return nh;
 }
 
@@ -423,6 +487,9 @@ static void pixel_coords(const og_params *prm, const int32_t *pix, int64_t p, do
 /*
  * Exported: render npix pixels (pix = [npix][2] of (x, y), or NULL for the
  * whole image in row-major order).  rgba: [npix][4].  flags: [npix] or NULL.
+ * alt: [npix][3][4] or NULL, with n_alt [npix]: for a pixel with one or two
+ * ambiguous decisions, the images obtained by flipping each non-empty subset
+ * of them (1 or 3 alternatives); a pixel with more gets AMB_MANY and none.
  * maxw: [n] or NULL, the largest T*alpha each Gaussian reaches over the
  * rendered pixels.  stats[0] = composited pairs, stats[1] = Gaussians kept,
  * stats[2] = evaluated (in-box) pairs.  use_box = 0 evaluates every kept
@@ -430,7 +497,8 @@ static void pixel_coords(const og_params *prm, const int32_t *pix, int64_t p, do
  */
 int og_render(const og_gauss *g, const float *edits, int n_models, const og_camera *cam,
               const og_params *prm, int64_t npix, const int32_t *pix, int use_box,
-              double *rgba, int32_t *flags, double *maxw, int64_t *stats, double *proj_out)
+              double *rgba, int32_t *flags, double *alt, int32_t *n_alt, double *maxw,
+              int64_t *stats, double *proj_out)
 {
     int64_t n = g->n;
     double *proj = proj_out ? proj_out : malloc(sizeof(double) * P_WIDTH * (n > 0 ? n : 1));
@@ -439,20 +507,34 @@ int og_render(const og_gauss *g, const float *edits, int n_models, const og_came
     int64_t m = sorted_order(proj, n, order);
     if (maxw) for (int64_t i = 0; i < n; ++i) maxw[i] = 0.0;
     int64_t comp = 0, evald = 0;
-    hit_t *hits_all = NULL;
 #pragma omp parallel reduction(+ : comp, evald)
     {
         hit_t *hits = maxw ? malloc(sizeof(hit_t) * (m > 0 ? m : 1)) : NULL;
 #pragma omp for schedule(dynamic, 16)
         for (int64_t p = 0; p < npix; ++p) {
             double px, py, Tf;
-            int fl;
+            int fl, na;
             int64_t ev;
+            dec_t amb[MAX_AMB];
             pixel_coords(prm, pix, p, &px, &py);
-            int64_t nh = composite_pixel(proj, order, m, prm, px, py, use_box, rgba + 4 * p, &Tf,
-                                         &fl, hits, &ev);
+            int64_t nh = composite_pixel(proj, order, m, prm, px, py, use_box, NULL, 0, rgba + 4 * p,
+                                         &Tf, &fl, hits, &ev, amb, &na);
             comp += nh;
             evald += ev;
+            int nalt = 0;
+            if (na > 2) fl |= AMB_MANY;
+            if (alt && na >= 1 && na <= 2) {
+                for (int mask = 1; mask < (1 << na); ++mask) {
+                    dec_t fl_set[2];
+                    int nf = 0;
+                    for (int b = 0; b < na; ++b)
+                        if (mask & (1 << b)) fl_set[nf++] = amb[b];
+                    composite_pixel(proj, order, m, prm, px, py, use_box, fl_set, nf,
+                                    alt + (p * 3 + nalt) * 4, NULL, NULL, NULL, NULL, NULL, NULL);
+                    ++nalt;
+                }
+            }
+            if (n_alt) n_alt[p] = nalt;
             if (flags) flags[p] = fl;
             if (maxw)
                 for (int64_t k = 0; k < nh; ++k) {
@@ -464,7 +546,6 @@ int og_render(const og_gauss *g, const float *edits, int n_models, const og_came
         }
         free(hits);
     }
-    (void)hits_all;
     if (stats) { stats[0] = comp; stats[1] = m; stats[2] = evald; }
     free(order);
     if (!proj_out) free(proj);
@@ -505,7 +586,8 @@ int og_backward(const og_gauss *g, const float *edits, int n_models, const og_ca
             if (u[0] == 0.0 && u[1] == 0.0 && u[2] == 0.0 && u[3] == 0.0) continue;
             double px, py, Tf, rgba[4];
             pixel_coords(prm, pix, p, &px, &py);
-            int64_t nh = composite_pixel(proj, order, m, prm, px, py, 1, rgba, &Tf, NULL, hits, NULL);
+            int64_t nh = composite_pixel(proj, order, m, prm, px, py, 1, NULL, 0, rgba, &Tf, NULL, hits,
+                                         NULL, NULL, NULL);
             double B[3] = {Tf * prm->bg[0], Tf * prm->bg[1], Tf * prm->bg[2]};
             double D = 0.0;
             for (int64_t k = nh - 1; k >= 0; --k) {

@@ -1,0 +1,351 @@
+// C ABI: host-side validation, workspace layout and launch sequencing.
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "launch.hpp"
+
+namespace ivrgs {
+
+// --------------------------------------------------------------- timing
+namespace {
+struct Timing {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<std::pair<hipEvent_t, int>> open;  // begun, not yet ended
+    double ms[TK_KINDS] = {0};
+    long long n[TK_KINDS] = {0};
+};
+Timing g_timing;
+std::mutex g_timing_mu;
+
+hipEvent_t take_event() {
+    if (!g_timing.pool.empty()) {
+        hipEvent_t e = g_timing.pool.back();
+        g_timing.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+}  // namespace
+
+void timing_begin(int kind, hipStream_t s) {
+    std::lock_guard<std::mutex> lock(g_timing_mu);
+    if (!g_timing.on) return;
+    hipEvent_t e = take_event();
+    if (!e) return;
+    hipEventRecord(e, s);
+    g_timing.open.push_back({e, kind});
+}
+
+void timing_end(int kind, hipStream_t s) {
+    std::lock_guard<std::mutex> lock(g_timing_mu);
+    if (!g_timing.on) return;
+    for (size_t i = g_timing.open.size(); i-- > 0;) {
+        if (g_timing.open[i].second != kind) continue;
+        hipEvent_t b = g_timing.open[i].first;
+        g_timing.open.erase(g_timing.open.begin() + i);
+        hipEvent_t e = take_event();
+        if (!e) {
+            g_timing.pool.push_back(b);
+            return;
+        }
+        hipEventRecord(e, s);
+        g_timing.pending.push_back({kind, {b, e}});
+        return;
+    }
+}
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kDefaultChunk = 4096;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Per-device limits queried once per device.
+struct DeviceLimits {
+    bool ready = false;
+    size_t max_lds = 65536;
+    int sort_cap = 0;
+    size_t sort_lds = 0;
+};
+std::mutex g_mu;
+DeviceLimits g_dev[64];
+
+hipError_t device_limits(DeviceLimits &out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_mu);
+    DeviceLimits &d = g_dev[dev];
+    if (!d.ready) {
+        int lds = 0;
+        e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e != hipSuccess) return e;
+        d.max_lds = (size_t)lds;
+        // leave room for the histogram and the small static arrays
+        const size_t avail = d.max_lds - sort_lds_bytes(0) - 1024;
+        d.sort_cap = (int)(avail / 8 / 128 * 128);
+        d.sort_lds = sort_lds_bytes(d.sort_cap);
+        if (d.sort_lds > 65536) {
+            e = set_sort_lds_limit(d.sort_lds);
+            if (e != hipSuccess) return e;
+        }
+        d.ready = true;
+    }
+    out = d;
+    return hipSuccess;
+}
+
+bool valid_gauss(const ivrgs_gaussians &g) {
+    if (g.n < 0) return false;
+    if (g.n == 0) return true;
+    return g.mean && g.log_scale && g.quat && g.opacity && g.normal && g.color && g.shade;
+}
+
+bool valid_gauss_mut(const ivrgs_gaussians_mut &g) {
+    if (g.n < 0) return false;
+    if (g.n == 0) return true;
+    return g.mean && g.log_scale && g.quat && g.opacity && g.normal && g.color && g.shade;
+}
+
+ivrgs_status check_params(const ivrgs_params *p) {
+    if (!p) return IVRGS_E_INVALID;
+    if (p->tile != 0 && p->tile != kTile) return IVRGS_E_UNSUPPORTED;
+    if (p->width <= 0 || p->height <= 0) return IVRGS_E_SHAPE;
+    const int tx = (p->width + kTile - 1) / kTile, ty = (p->height + kTile - 1) / kTile;
+    if (tx > 65535 || ty > 65535) return IVRGS_E_SHAPE;
+    if (!(p->alpha_min > 0.f) || !(p->alpha_max > p->alpha_min) || !(p->alpha_max < 1.f)) return IVRGS_E_INVALID;
+    if (!(p->T_min > 0.f) || !(p->T_min < 1.f) || !(p->lowpass >= 0.f)) return IVRGS_E_INVALID;
+    for (int px : {p->fwd_px, p->bwd_px})
+        if (px != 0 && px != 1 && px != 2 && px != 4) return IVRGS_E_UNSUPPORTED;
+    if (p->sort_chunk < 0) return IVRGS_E_INVALID;
+    return IVRGS_OK;
+}
+
+ivrgs_status check_batch(const ivrgs_batch *b) {
+    if (!b) return IVRGS_E_INVALID;
+    if (!valid_gauss(b->g)) return IVRGS_E_INVALID;
+    if (b->n_jobs < 0 || b->max_job_count < 0 || b->n_records < 0 || b->n_models <= 0) return IVRGS_E_INVALID;
+    if (b->n_jobs > 0 && (!b->jobs || !b->cameras || !b->edits)) return IVRGS_E_INVALID;
+    if (b->n_records >= (int64_t)0xFFFFFFF0) return IVRGS_E_SHAPE;
+    return IVRGS_OK;
+}
+
+// Workspace regions.
+struct Layout {
+    size_t keys, keys2, vals2, counts, grec, total;
+};
+
+int chunk_of(const ivrgs_params &p) { return p.sort_chunk > 0 ? p.sort_chunk : kDefaultChunk; }
+
+Layout layout(const ivrgs_batch &b, const ivrgs_params &p, int64_t capacity) {
+    Layout L;
+    const Consts k = make_consts(p);
+    size_t off = 0;
+    L.keys = off;
+    off += align_up(sizeof(uint32_t) * (size_t)capacity);
+    L.keys2 = off;
+    off += align_up(sizeof(uint32_t) * (size_t)capacity);
+    L.vals2 = off;
+    off += align_up(sizeof(uint32_t) * (size_t)capacity);
+    L.counts = off;
+    off += align_up(sizeof(uint32_t) * (size_t)b.n_jobs * chunk_rows(b, chunk_of(p)) * k.tiles_per_job);
+    L.grec = off;
+    off += align_up(sizeof(float) * kGradRec * (size_t)b.n_records);
+    L.total = off;
+    return L;
+}
+
+ivrgs_status hip_status(hipError_t e) { return e == hipSuccess ? IVRGS_OK : IVRGS_E_HIP; }
+
+int pick_px(int requested, int fallback) { return requested == 0 ? fallback : requested; }
+
+}  // namespace
+}  // namespace ivrgs
+
+using namespace ivrgs;
+
+extern "C" {
+
+size_t ivrgs_workspace_size(const ivrgs_batch *batch, const ivrgs_params *params, int64_t capacity) {
+    if (check_batch(batch) != IVRGS_OK || check_params(params) != IVRGS_OK || capacity < 0) return 0;
+    return layout(*batch, *params, capacity).total;
+}
+
+int32_t ivrgs_tiles_per_job(const ivrgs_params *params) {
+    if (check_params(params) != IVRGS_OK) return 0;
+    return make_consts(*params).tiles_per_job;
+}
+
+ivrgs_status ivrgs_compose(const ivrgs_gaussians *models, int32_t n_models, const ivrgs_model_edit *edits,
+                           ivrgs_gaussians_mut *out, void *stream) {
+    if (!models || !edits || !out || n_models <= 0) return IVRGS_E_INVALID;
+    if (!valid_gauss_mut(*out) || (out->n > 0 && !out->model_id)) return IVRGS_E_INVALID;
+    int64_t total = 0;
+    for (int m = 0; m < n_models; ++m) {
+        if (!valid_gauss(models[m])) return IVRGS_E_INVALID;
+        total += models[m].n;
+    }
+    if (total != out->n) return IVRGS_E_SHAPE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int64_t off = 0;
+    for (int m = 0; m < n_models; ++m) {
+        hipError_t e = launch_compose(models[m], off, m, edits[m], *out, s);
+        if (e != hipSuccess) return IVRGS_E_HIP;
+        off += models[m].n;
+    }
+    return IVRGS_OK;
+}
+
+ivrgs_status ivrgs_project(const ivrgs_batch *batch, const ivrgs_params *params, ivrgs_projected *out,
+                           void *stream) {
+    ivrgs_status st = check_batch(batch);
+    if (st != IVRGS_OK) return st;
+    if ((st = check_params(params)) != IVRGS_OK) return st;
+    if (!out || (batch->n_records > 0 && (!out->rec || !out->rect))) return IVRGS_E_INVALID;
+    const Consts k = make_consts(*params);
+    return hip_status(launch_project(*batch, k, out->rec, out->rect, reinterpret_cast<hipStream_t>(stream)));
+}
+
+ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
+                            ivrgs_bins *bins, void *workspace, size_t workspace_bytes, void *stream) {
+    ivrgs_status st = check_batch(batch);
+    if (st != IVRGS_OK) return st;
+    if ((st = check_params(params)) != IVRGS_OK) return st;
+    if (!proj || !bins || !bins->tile_start || !bins->status || bins->capacity < 0) return IVRGS_E_INVALID;
+    if (bins->capacity > 0 && !bins->sorted) return IVRGS_E_INVALID;
+    if (batch->n_records > 0 && (!proj->rec || !proj->rect)) return IVRGS_E_INVALID;
+    const Consts k = make_consts(*params);
+    DeviceLimits dl;
+    if (device_limits(dl) != hipSuccess) return IVRGS_E_HIP;
+    if (sizeof(uint32_t) * (size_t)k.tiles_per_job > dl.max_lds) return IVRGS_E_SHAPE;
+    const Layout L = layout(*batch, *params, bins->capacity);
+    if (!workspace || workspace_bytes < L.total) return IVRGS_E_CAPACITY;
+    char *ws = static_cast<char *>(workspace);
+    BinWork w;
+    w.keys = reinterpret_cast<uint32_t *>(ws + L.keys);
+    w.keys2 = reinterpret_cast<uint32_t *>(ws + L.keys2);
+    w.vals2 = reinterpret_cast<uint32_t *>(ws + L.vals2);
+    w.counts = reinterpret_cast<uint32_t *>(ws + L.counts);
+    const int chunk = chunk_of(*params);
+    return hip_status(launch_bin_sort(*batch, k, proj->rec, proj->rect, *bins, w, chunk, dl.sort_cap, dl.sort_lds,
+                                      reinterpret_cast<hipStream_t>(stream)));
+}
+
+ivrgs_status ivrgs_render_fwd(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
+                              const ivrgs_bins *bins, float *out_rgba, float *out_maxw, void *workspace,
+                              size_t workspace_bytes, void *stream) {
+    (void)workspace;
+    (void)workspace_bytes;
+    ivrgs_status st = check_batch(batch);
+    if (st != IVRGS_OK) return st;
+    if ((st = check_params(params)) != IVRGS_OK) return st;
+    if (!proj || !bins || !bins->tile_start || !bins->status || !out_rgba) return IVRGS_E_INVALID;
+    const Consts k = make_consts(*params);
+    const int64_t n_tiles = (int64_t)batch->n_jobs * k.tiles_per_job;
+    const bool count = (params->flags & IVRGS_FLAG_COUNT_EVAL) != 0;
+    return hip_status(launch_render_fwd(k, pick_px(params->fwd_px, 1), n_tiles, proj->rec, bins->tile_start,
+                                        bins->sorted, out_rgba, out_maxw, bins->status, count,
+                                        reinterpret_cast<hipStream_t>(stream)));
+}
+
+ivrgs_status ivrgs_render_bwd(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
+                              const ivrgs_bins *bins, const float *out_rgba, const float *dl_drgba,
+                              ivrgs_gaussians_mut *grads, void *workspace, size_t workspace_bytes, void *stream) {
+    ivrgs_status st = check_batch(batch);
+    if (st != IVRGS_OK) return st;
+    if ((st = check_params(params)) != IVRGS_OK) return st;
+    if (!proj || !bins || !bins->tile_start || !out_rgba || !dl_drgba || !grads) return IVRGS_E_INVALID;
+    if (!valid_gauss_mut(*grads) || grads->n != batch->g.n) return IVRGS_E_SHAPE;
+    const Consts k = make_consts(*params);
+    const Layout L = layout(*batch, *params, bins->capacity);
+    if (!workspace || workspace_bytes < L.total) return IVRGS_E_CAPACITY;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    float *grec = reinterpret_cast<float *>(static_cast<char *>(workspace) + L.grec);
+    const int64_t n_tiles = (int64_t)batch->n_jobs * k.tiles_per_job;
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(grec), kGradRec * batch->n_records, 0u, s);
+    if (e == hipSuccess)
+        e = launch_render_bwd(k, pick_px(params->bwd_px, 1), n_tiles, proj->rec, bins->tile_start, bins->sorted,
+                              out_rgba, dl_drgba, grec, batch->n_records, s);
+    const int64_t n = grads->n;
+    float *planes[7] = {grads->mean, grads->log_scale, grads->quat, grads->opacity,
+                        grads->normal, grads->color, grads->shade};
+    const int dims[7] = {3, 3, 4, 1, 3, 3, 4};
+    for (int p = 0; p < 7 && e == hipSuccess; ++p)
+        e = launch_fill_u32(reinterpret_cast<uint32_t *>(planes[p]), dims[p] * n, 0u, s);
+    // a Gaussian that several jobs share accumulates with atomics
+    const bool shared = batch->n_jobs > 1;
+    if (e == hipSuccess) e = launch_project_bwd(*batch, k, proj->rect, grec, *grads, shared, s);
+    return hip_status(e);
+}
+
+void ivrgs_timing_enable(int32_t on) {
+    std::lock_guard<std::mutex> lock(g_timing_mu);
+    for (auto &p : g_timing.pending) {
+        hipEventSynchronize(p.second.second);
+        g_timing.pool.push_back(p.second.first);
+        g_timing.pool.push_back(p.second.second);
+    }
+    g_timing.pending.clear();
+    for (auto &o : g_timing.open) g_timing.pool.push_back(o.first);
+    g_timing.open.clear();
+    for (int k = 0; k < TK_KINDS; ++k) {
+        g_timing.ms[k] = 0.0;
+        g_timing.n[k] = 0;
+    }
+    g_timing.on = on != 0;
+}
+
+int32_t ivrgs_timing_read(double *ms, int64_t *launches) {
+    std::lock_guard<std::mutex> lock(g_timing_mu);
+    for (auto &p : g_timing.pending) {
+        float t = 0.f;
+        if (hipEventSynchronize(p.second.second) == hipSuccess &&
+            hipEventElapsedTime(&t, p.second.first, p.second.second) == hipSuccess) {
+            g_timing.ms[p.first] += t;
+            g_timing.n[p.first] += 1;
+        }
+        g_timing.pool.push_back(p.second.first);
+        g_timing.pool.push_back(p.second.second);
+    }
+    g_timing.pending.clear();
+    for (int k = 0; k < TK_KINDS; ++k) {
+        if (ms) ms[k] = g_timing.ms[k];
+        if (launches) launches[k] = g_timing.n[k];
+    }
+    return TK_KINDS;
+}
+
+int32_t ivrgs_struct_size(int32_t which) {
+    switch (which) {
+    case 0: return (int32_t)sizeof(ivrgs_gaussians);
+    case 1: return (int32_t)sizeof(ivrgs_camera);
+    case 2: return (int32_t)sizeof(ivrgs_model_edit);
+    case 3: return (int32_t)sizeof(ivrgs_job);
+    case 4: return (int32_t)sizeof(ivrgs_batch);
+    case 5: return (int32_t)sizeof(ivrgs_params);
+    case 6: return (int32_t)sizeof(ivrgs_projected);
+    case 7: return (int32_t)sizeof(ivrgs_bins);
+    default: return -1;
+    }
+}
+
+const char *ivrgs_status_string(ivrgs_status s) {
+    switch (s) {
+    case IVRGS_OK: return "ok";
+    case IVRGS_E_INVALID: return "invalid argument";
+    case IVRGS_E_SHAPE: return "inconsistent shape";
+    case IVRGS_E_CAPACITY: return "workspace or capacity too small";
+    case IVRGS_E_HIP: return "HIP runtime error";
+    case IVRGS_E_UNSUPPORTED: return "unsupported setting";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,424 @@
+// Tile binning and per-tile depth sort.
+//
+// 1. Count: each workgroup owns a chunk of a job's records and counts, in LDS,
+//    the pairs each tile of the job receives from it; the counts form a
+//    [job][chunk][tile] matrix.
+// 2. A column scan over chunks gives every (chunk, tile) its offset inside
+//    the tile's list and each tile its total; one exclusive scan over all
+//    (job, tile) totals gives the list starts, and the pair total is checked
+//    against the capacity on the device.
+// 3. Scatter: each chunk workgroup writes its (depth key, record id) pairs
+//    from per-tile LDS cursors; no global atomics.
+// 4. Per-tile stable LSD radix sort of the depth keys (8-bit digits, only the
+//    digits that vary inside the tile), in LDS when the tile fits, otherwise
+//    through global memory; equal keys are then ordered by record id, so the
+//    result is the unique (depth key, record id) order whatever order the
+//    scatter produced.
+#include "launch.hpp"
+
+namespace ivrgs {
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, int64_t n, uint32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__device__ __forceinline__ void unpack_rect(uint2 rc, int &x0, int &y0, int &x1, int &y1) {
+    x0 = rc.x & 0xFFFF;
+    y0 = rc.x >> 16;
+    x1 = rc.y & 0xFFFF;
+    y1 = rc.y >> 16;
+}
+
+// Pass 1 of the binning: per (job, chunk of records) the number of pairs each
+// tile receives, counted with LDS atomics and written as one row of the
+// count matrix [job][chunk][tile].
+__global__ __launch_bounds__(256) void k_chunk_count(ivrgs_batch b, Consts k, const uint2 *__restrict__ rect,
+                                                     uint32_t *__restrict__ counts, int chunk, int n_chunks) {
+    extern __shared__ uint32_t cnt[];
+    const ivrgs_job job = b.jobs[blockIdx.y];
+    const int begin = blockIdx.x * chunk;
+    if (begin >= job.gauss_count) return;
+    const int end = min(begin + chunk, job.gauss_count);
+    const int tpj = k.tiles_per_job, tx_n = k.tiles_x;
+    for (int t = threadIdx.x; t < tpj; t += blockDim.x) cnt[t] = 0;
+    __syncthreads();
+    for (int l = begin + threadIdx.x; l < end; l += blockDim.x) {
+        const uint2 rc = rect[(int64_t)job.rec_begin + l];
+        if (rc.x == 0u && rc.y == 0u) continue;
+        int x0, y0, x1, y1;
+        unpack_rect(rc, x0, y0, x1, y1);
+        for (int y = y0; y < y1; ++y)
+            for (int x = x0; x < x1; ++x) atomicAdd(&cnt[y * tx_n + x], 1u);
+    }
+    __syncthreads();
+    uint32_t *row = counts + ((int64_t)blockIdx.y * n_chunks + blockIdx.x) * tpj;
+    for (int t = threadIdx.x; t < tpj; t += blockDim.x) row[t] = cnt[t];
+}
+
+// Per (job, tile): exclusive scan of the count column over the job's chunks
+// (in place) and the tile's total.
+__global__ __launch_bounds__(256) void k_col_scan(ivrgs_batch b, Consts k, uint32_t *__restrict__ counts, int chunk,
+                                                  int n_chunks, uint32_t *__restrict__ tile_counts) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= k.tiles_per_job) return;
+    const ivrgs_job job = b.jobs[blockIdx.y];
+    const int rows = (job.gauss_count + chunk - 1) / chunk;
+    uint32_t *col = counts + (int64_t)blockIdx.y * n_chunks * k.tiles_per_job + t;
+    uint32_t acc = 0;
+    for (int c = 0; c < rows; ++c) {
+        const uint32_t v = col[(int64_t)c * k.tiles_per_job];
+        col[(int64_t)c * k.tiles_per_job] = acc;
+        acc += v;
+    }
+    tile_counts[(int64_t)blockIdx.y * k.tiles_per_job + t] = acc;
+}
+
+// Exclusive prefix of 64-bit values over a workgroup of 1024 threads.
+__device__ uint64_t block_exclusive_scan_1024(uint64_t v, uint64_t *tmp /* >= 16 */, uint64_t &total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint64_t incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    if (lane == 63) tmp[wave] = incl;
+    __syncthreads();
+    uint64_t wave_off = 0, all = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        const uint64_t t = tmp[w];
+        if (w < wave) wave_off += t;
+        all += t;
+    }
+    total = all;
+    __syncthreads();
+    return wave_off + incl - v;
+}
+
+// Single workgroup: tile counts -> exclusive starts (in place) and the total,
+// checked against the capacity.
+__global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t *__restrict__ starts, int64_t n_tiles,
+                                                     int64_t *__restrict__ status, int64_t capacity) {
+    __shared__ uint64_t tmp[16];
+    const int64_t per = (n_tiles + blockDim.x - 1) / blockDim.x;
+    const int64_t lo = threadIdx.x * per, hi = min(lo + per, n_tiles);
+    uint64_t sum = 0;
+    for (int64_t i = lo; i < hi; ++i) sum += starts[i];
+    uint64_t total;
+    uint64_t run = block_exclusive_scan_1024(sum, tmp, total);
+    for (int64_t i = lo; i < hi; ++i) {
+        const uint32_t c = starts[i];
+        starts[i] = (uint32_t)run;
+        run += c;
+    }
+    if (threadIdx.x == 0) {
+        const bool over = total > (uint64_t)capacity || total > 0xFFFFFFF0ull;
+        starts[n_tiles] = over ? 0xFFFFFFFFu : (uint32_t)total;
+        status[0] = (int64_t)total;
+        status[1] = over ? (int64_t)IVRGS_DEV_E_CAPACITY : 0;
+        status[2] = 0;
+        status[3] = 0;
+    }
+}
+
+// Pass 2: each (job, chunk) workgroup starts its per-tile cursors at the
+// tile's list start plus the chunk's exclusive column prefix and writes its
+// (depth key, record id) pairs.  No global atomics.
+__global__ __launch_bounds__(256) void k_scatter(ivrgs_batch b, Consts k, const float *__restrict__ rec,
+                                                 const uint2 *__restrict__ rect, const uint32_t *__restrict__ counts,
+                                                 uint32_t *__restrict__ keys, uint32_t *__restrict__ vals, int chunk,
+                                                 int n_chunks, const uint32_t *__restrict__ starts, int64_t n_tiles) {
+    extern __shared__ uint32_t cur[];
+    if (starts[n_tiles] == 0xFFFFFFFFu) return;  // capacity exceeded
+    const ivrgs_job job = b.jobs[blockIdx.y];
+    const int begin = blockIdx.x * chunk;
+    if (begin >= job.gauss_count) return;
+    const int end = min(begin + chunk, job.gauss_count);
+    const int tpj = k.tiles_per_job, tx_n = k.tiles_x;
+    const uint32_t *row = counts + ((int64_t)blockIdx.y * n_chunks + blockIdx.x) * tpj;
+    const uint32_t *st = starts + (int64_t)blockIdx.y * tpj;
+    for (int t = threadIdx.x; t < tpj; t += blockDim.x) cur[t] = st[t] + row[t];
+    __syncthreads();
+    for (int l = begin + threadIdx.x; l < end; l += blockDim.x) {
+        const int64_t r = (int64_t)job.rec_begin + l;
+        const uint2 rc = rect[r];
+        if (rc.x == 0u && rc.y == 0u) continue;
+        const uint32_t z = __float_as_uint(rec[r * kRecWords + RZ]);
+        int x0, y0, x1, y1;
+        unpack_rect(rc, x0, y0, x1, y1);
+        for (int y = y0; y < y1; ++y)
+            for (int x = x0; x < x1; ++x) {
+                const uint32_t slot = atomicAdd(&cur[y * tx_n + x], 1u);
+                keys[slot] = z;
+                vals[slot] = (uint32_t)r;
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-tile sort: 1024 threads; wave w owns the contiguous segment
+// [w * seg, (w + 1) * seg) of the tile's list (seg a multiple of 64), so
+// processing (wave, sub-batch of 64, lane) in order visits the list in order
+// and each counting pass is stable.  Buffers ping-pong between an LDS pair
+// (lists up to half the staging capacity), LDS and global memory (up to the
+// capacity: the list lives in LDS and each pass stages through global
+// memory), or two global arrays (larger lists).  A pass prefetches kU
+// sub-batches per round so that a global source costs one latency per round.
+constexpr int kSortThreads = 1024;
+constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kU = 8;
+constexpr int kHistWords = kSortWaves * 256;
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Lanes of the active mask whose digit equals this lane's digit.
+__device__ __forceinline__ uint64_t match_digit(uint32_t dg, uint64_t active) {
+    uint64_t m = active;
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+        const uint64_t bb = __ballot((dg >> bit) & 1u);
+        m &= ((dg >> bit) & 1u) ? bb : ~bb;
+    }
+    return m;
+}
+
+// Exclusive scan over threads 0..255 (others pass 0); every thread calls it.
+__device__ uint32_t scan256(uint32_t v, uint32_t *tmp /* >= kSortWaves */) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    if (lane == 63) tmp[wave] = incl;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int w = 0; w < wave; ++w) off += tmp[w];
+    __syncthreads();
+    return off + incl - v;
+}
+
+// Turn per-wave digit histograms into per-wave starting offsets.
+__device__ void hist_to_offsets(uint32_t *hist, uint32_t *tmp) {
+    uint32_t c[kSortWaves];
+    uint32_t tot = 0;
+    if (threadIdx.x < 256) {
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) {
+            c[w] = hist[w * 256 + threadIdx.x];
+            tot += c[w];
+        }
+    }
+    const uint32_t pre = scan256(threadIdx.x < 256 ? tot : 0u, tmp);
+    if (threadIdx.x < 256) {
+        uint32_t run = pre;
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) {
+            hist[w * 256 + threadIdx.x] = run;
+            run += c[w];
+        }
+    }
+    __syncthreads();
+}
+
+// One stable counting pass on digit (key >> shift) & 255, src -> dst.
+__device__ void radix_pass(const uint32_t *sk, const uint32_t *sv, uint32_t *dk, uint32_t *dv, int n, int shift,
+                           uint32_t *hist, uint32_t *tmp) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int seg = ((n + kSortWaves - 1) / kSortWaves + 63) / 64 * 64;
+    const int s0 = min(wave * seg, n), s1 = min(s0 + seg, n);
+    uint32_t *h = hist + wave * 256;
+    for (int d = lane; d < 256; d += 64) h[d] = 0;
+    __syncthreads();
+    for (int i = s0 + lane; i < s1; i += 64) atomicAdd(&h[(sk[i] >> shift) & 255u], 1u);
+    __syncthreads();
+    hist_to_offsets(hist, tmp);
+    for (int base = s0; base < s1; base += 64 * kU) {
+        uint32_t kk[kU], vv[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int i = base + u * 64 + lane;
+            kk[u] = i < s1 ? sk[i] : 0u;
+            vv[u] = i < s1 ? sv[i] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (base + u * 64 < s1) {  // wave-uniform
+                const bool act = base + u * 64 + lane < s1;
+                const uint32_t dg = (kk[u] >> shift) & 255u;
+                const uint64_t m = match_digit(dg, __ballot(act));
+                const uint32_t rank = lanes_below(m);
+                const uint32_t pos = h[dg] + rank;
+                if (act) {
+                    dk[pos] = kk[u];
+                    dv[pos] = vv[u];
+                }
+                if (act && rank == 0) h[dg] += (uint32_t)__popcll(m);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Order runs of equal keys by value (record id).  Runs of equal FP32 depth
+// keys are rare and short; each is insertion-sorted by one thread.
+__device__ void fix_ties(const uint32_t *key, uint32_t *val, int n) {
+    int tie = 0;
+    for (int i = threadIdx.x + 1; i < n; i += blockDim.x) tie |= key[i] == key[i - 1];
+    if (!__syncthreads_or(tie)) return;
+    for (int i = threadIdx.x; i + 1 < n; i += blockDim.x) {
+        if (key[i + 1] != key[i] || (i > 0 && key[i - 1] == key[i])) continue;
+        int e = i + 1;
+        while (e < n && key[e] == key[i]) ++e;
+        for (int a = i + 1; a < e; ++a) {
+            const uint32_t v = val[a];
+            int c = a - 1;
+            while (c >= i && val[c] > v) {
+                val[c + 1] = val[c];
+                --c;
+            }
+            val[c + 1] = v;
+        }
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_tile_sort(const uint32_t *__restrict__ starts, int64_t n_tiles,
+                                                            uint32_t *keys, uint32_t *vals, uint32_t *keys2,
+                                                            uint32_t *vals2, int lds_cap) {
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t red_and[kSortWaves], red_or[kSortWaves], tmp[kSortWaves];
+    if (starts[n_tiles] == 0xFFFFFFFFu) return;
+    const uint32_t start = starts[blockIdx.x], end = starts[blockIdx.x + 1];
+    const int n = (int)(end - start);
+    if (n <= 1) return;
+    uint32_t *hist = lds;
+    uint32_t *buf = lds + kHistWords;  // keys [lds_cap] then values [lds_cap]
+    const int half = lds_cap / 2;
+    uint32_t *ka, *va, *kb, *vb;
+    bool copy_back = false;  // list in LDS, staging in global memory
+    if (n <= half) {
+        ka = buf;
+        va = buf + lds_cap;
+        kb = buf + half;
+        vb = buf + lds_cap + half;
+    } else if (n <= lds_cap) {
+        ka = buf;
+        va = buf + lds_cap;
+        kb = keys2 + start;
+        vb = vals2 + start;
+        copy_back = true;
+    } else {
+        ka = keys + start;
+        va = vals + start;
+        kb = keys2 + start;
+        vb = vals2 + start;
+    }
+    const bool in_lds = n <= lds_cap;
+    uint32_t a = 0xFFFFFFFFu, o = 0u;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const uint32_t key = keys[start + i];
+        if (in_lds) {
+            ka[i] = key;
+            va[i] = vals[start + i];
+        }
+        a &= key;
+        o |= key;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        a &= __shfl_xor(a, d, 64);
+        o |= __shfl_xor(o, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red_and[threadIdx.x >> 6] = a;
+        red_or[threadIdx.x >> 6] = o;
+    }
+    __syncthreads();
+    a = 0xFFFFFFFFu;
+    o = 0u;
+    for (int w = 0; w < kSortWaves; ++w) {
+        a &= red_and[w];
+        o |= red_or[w];
+    }
+    const uint32_t varying = a ^ o;
+    for (int d = 0; d < 4; ++d) {
+        if (((varying >> (8 * d)) & 255u) == 0u) continue;
+        radix_pass(ka, va, kb, vb, n, 8 * d, hist, tmp);
+        if (copy_back) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                ka[i] = kb[i];
+                va[i] = vb[i];
+            }
+            __syncthreads();
+        } else {
+            uint32_t *t0 = ka, *t1 = va;
+            ka = kb;
+            va = vb;
+            kb = t0;
+            vb = t1;
+        }
+    }
+    fix_ties(ka, va, n);
+    if (va != vals + start)
+        for (int i = threadIdx.x; i < n; i += blockDim.x) vals[start + i] = va[i];
+}
+
+// ----------------------------------------------------------------------------
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t want = (n + 255) / 256;
+    const int64_t blocks = want < 4096 ? want : 4096;
+    TimedScope ts(TK_FILL, s);
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+int chunk_rows(const ivrgs_batch &b, int chunk) { return (b.max_job_count + chunk - 1) / chunk; }
+
+hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *rec, const uint32_t *rect,
+                           const ivrgs_bins &bins, const BinWork &w, int chunk, int lds_cap, size_t sort_lds,
+                           hipStream_t s) {
+    const int64_t n_tiles = (int64_t)b.n_jobs * k.tiles_per_job;
+    const int n_chunks = chunk_rows(b, chunk);
+    const size_t cnt_lds = sizeof(uint32_t) * k.tiles_per_job;
+    {
+        TimedScope ts(TK_COUNT, s);
+        if (n_chunks > 0) {
+            hipLaunchKernelGGL(k_chunk_count, dim3(n_chunks, b.n_jobs), dim3(256), cnt_lds, s, b, k,
+                               reinterpret_cast<const uint2 *>(rect), w.counts, chunk, n_chunks);
+            hipLaunchKernelGGL(k_col_scan, dim3((k.tiles_per_job + 255) / 256, b.n_jobs), dim3(256), 0, s, b, k,
+                               w.counts, chunk, n_chunks, bins.tile_start);
+        } else if (n_tiles > 0) {
+            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, bins.tile_start, n_tiles, 0u);
+        }
+        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, bins.tile_start, n_tiles, bins.status,
+                           bins.capacity);
+    }
+    if (n_chunks > 0) {
+        TimedScope ts(TK_SCATTER, s);
+        hipLaunchKernelGGL(k_scatter, dim3(n_chunks, b.n_jobs), dim3(256), cnt_lds, s, b, k, rec,
+                           reinterpret_cast<const uint2 *>(rect), w.counts, w.keys, bins.sorted, chunk, n_chunks,
+                           bins.tile_start, n_tiles);
+    }
+    if (n_tiles > 0) {
+        TimedScope ts(TK_SORT, s);
+        hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)n_tiles), dim3(kSortThreads), sort_lds, s, bins.tile_start,
+                           n_tiles, w.keys, bins.sorted, w.keys2, w.vals2, lds_cap);
+    }
+    return hipGetLastError();
+}
+
+// LDS bytes of the sort for a staging capacity (elements).
+size_t sort_lds_bytes(int lds_cap) { return sizeof(uint32_t) * (kHistWords + 2 * (size_t)lds_cap); }
+
+hipError_t set_sort_lds_limit(size_t bytes) {
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_tile_sort),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+}  // namespace ivrgs

@@ -1,0 +1,79 @@
+// Device-side helpers shared by the rasterizer kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ivrgs.h"
+
+namespace ivrgs {
+
+constexpr int kTile = 16;             // tile edge in pixels
+constexpr int kTilePix = kTile * kTile;
+constexpr int kRecWords = 12;         // floats per projected record
+constexpr int kGradRec = 9;           // record-gradient components
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+// Record word indices.
+enum { RX = 0, RY, RQA, RQB, RQC, RO, RCR, RCG, RCB, RZ, RCUT, RPAD };
+// Record-gradient planes ([9][n_records]).
+enum { GX = 0, GY, GQA, GQB, GQC, GO, GCR, GCG, GCB };
+
+// Compositing constants passed by value to kernels.
+struct Consts {
+    float alpha_min, alpha_max, T_min, lowpass, z_near;
+    float bg0, bg1, bg2;
+    int width, height, tiles_x, tiles_y, tiles_per_job;
+};
+
+inline Consts make_consts(const ivrgs_params &p) {
+    Consts c;
+    c.alpha_min = p.alpha_min;
+    c.alpha_max = p.alpha_max;
+    c.T_min = p.T_min;
+    c.lowpass = p.lowpass;
+    c.z_near = p.z_near;
+    c.bg0 = p.bg[0];
+    c.bg1 = p.bg[1];
+    c.bg2 = p.bg[2];
+    c.width = p.width;
+    c.height = p.height;
+    c.tiles_x = (p.width + kTile - 1) / kTile;
+    c.tiles_y = (p.height + kTile - 1) / kTile;
+    c.tiles_per_job = c.tiles_x * c.tiles_y;
+    return c;
+}
+
+// The Gaussian id of local entry k of a job.
+__device__ __forceinline__ int64_t job_gaussian(const ivrgs_job &j, const int32_t *index, int k) {
+    return index ? (int64_t)index[j.gauss_begin + k] : (int64_t)j.gauss_begin + k;
+}
+
+// 2D Gaussian exponent in log2 units at offset d = p - mean; the exact same
+// instruction sequence is used by the forward and the backward recompute.
+__device__ __forceinline__ float splat_exponent(float qa, float qb, float qc, float dx, float dy) {
+    float t = qa * dx;
+    t = fmaf(qb, dy, t);
+    float u = qc * dy;
+    return fmaf(t, dx, u * dy);
+}
+
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// Sum over the 64 lanes of a wave; the total lands in lane 63.  DPP row
+// butterflies give every lane its row sum, then row_bcast15 / row_bcast31
+// fold the four rows.
+__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));  // quad_perm [1,0,3,2]
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, false));  // quad_perm [2,3,0,1]
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x141, 0xF, 0xF, false)); // row_half_mirror
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x140, 0xF, 0xF, false)); // row_mirror
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xA, 0xF, false)); // row_bcast15
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x143, 0xC, 0xF, false)); // row_bcast31
+    return v;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+}  // namespace ivrgs

@@ -1,0 +1,44 @@
+// Host-side launchers implemented in the kernel translation units.
+#pragma once
+
+#include "common.hpp"
+
+namespace ivrgs {
+
+// Kernel-timing hooks (no-ops unless timing is enabled).
+enum TimingKind { TK_PROJECT = 0, TK_COUNT, TK_SCATTER, TK_SORT, TK_FWD, TK_BWD, TK_PROJECT_BWD,
+                  TK_COMPOSE, TK_FILL, TK_KINDS };
+void timing_begin(int kind, hipStream_t s);
+void timing_end(int kind, hipStream_t s);
+
+struct TimedScope {
+    int kind;
+    hipStream_t s;
+    TimedScope(int k, hipStream_t st) : kind(k), s(st) { timing_begin(kind, s); }
+    ~TimedScope() { timing_end(kind, s); }
+};
+
+struct BinWork {
+    uint32_t *keys, *keys2, *vals2, *counts;
+};
+int chunk_rows(const ivrgs_batch &b, int chunk);
+
+hipError_t launch_project(const ivrgs_batch &b, const Consts &k, float *rec, uint32_t *rect, hipStream_t s);
+hipError_t launch_project_bwd(const ivrgs_batch &b, const Consts &k, const uint32_t *rect, const float *grec,
+                              const ivrgs_gaussians_mut &out, bool atomic, hipStream_t s);
+hipError_t launch_compose(const ivrgs_gaussians &src, int64_t offset, int32_t model, const ivrgs_model_edit &e,
+                          const ivrgs_gaussians_mut &out, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *rec, const uint32_t *rect,
+                           const ivrgs_bins &bins, const BinWork &w, int chunk, int lds_cap, size_t sort_lds,
+                           hipStream_t s);
+size_t sort_lds_bytes(int lds_cap);
+hipError_t set_sort_lds_limit(size_t bytes);
+hipError_t launch_render_fwd(const Consts &k, int px, int64_t n_tiles, const float *rec, const uint32_t *starts,
+                             const uint32_t *sorted, float *out, float *maxw, int64_t *status, bool count,
+                             hipStream_t s);
+hipError_t launch_render_bwd(const Consts &k, int px, int64_t n_tiles, const float *rec, const uint32_t *starts,
+                             const uint32_t *sorted, const float *rgba, const float *dl, float *grec,
+                             int64_t n_rec, hipStream_t s);
+
+}  // namespace ivrgs

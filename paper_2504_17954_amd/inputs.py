@@ -224,13 +224,27 @@ class ScalarField:
 
 
 def isosurface_means(n: int, rng, field_seed: int, level: float = 0.0,
-                     width: float = 0.01) -> np.ndarray:
-    """Rejection-sample n means in U[-1,1]^3 with |f(x) - level| < width."""
+                     width: float = 0.01, grid: int = 128) -> np.ndarray:
+    """Rejection-sample n means uniformly in {x in [-1,1]^3 : |f(x) - level| < width}.
+
+    Candidates are drawn uniformly from the grid cells that can meet the
+    band: away from the origin f is Lipschitz with constant < 2.5 (tori: 1;
+    noisy sphere: 1 + 0.36/|x|), so a cell whose centre value is farther than
+    width + 2.5 * half-diagonal from the level cannot; cells near the origin
+    are always kept.  Uniform over a superset plus rejection is uniform over
+    the band."""
     fld = ScalarField(field_seed)
+    h = 2.0 / grid
+    c = (np.arange(grid) + 0.5) * h - 1.0
+    centres = np.stack(np.meshgrid(c, c, c, indexing="ij"), -1).reshape(-1, 3)
+    reach = 2.5 * h * math.sqrt(3.0) / 2.0
+    near0 = np.linalg.norm(centres, axis=1) < 0.3 + h
+    cells = centres[(np.abs(fld(centres) - level) <= width + reach) | near0]
     out, have = [], 0
     while have < n:
-        c = rng.uniform(-1.0, 1.0, size=(max(4 * (n - have), 1 << 16) * 8, 3))
-        keep = c[np.abs(fld(c) - level) < width]
+        m = max(8 * (n - have), 1 << 16)
+        p = cells[rng.integers(0, cells.shape[0], m)] + rng.uniform(-h / 2, h / 2, size=(m, 3))
+        keep = p[np.abs(fld(p) - level) < width]
         out.append(keep)
         have += keep.shape[0]
     return np.concatenate(out)[:n].T.copy()

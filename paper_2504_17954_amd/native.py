@@ -1,0 +1,176 @@
+"""ctypes binding of libivrgs.so: the C ABI of include/ivrgs.h, same names.
+
+Argument marshalling only; every step of the rasterizer runs in the HIP
+kernels of the library.  Loading fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libivrgs.so")
+
+PLANES = ("mean", "log_scale", "quat", "opacity", "normal", "color", "shade")
+PLANE_DIMS = (3, 3, 4, 1, 3, 3, 4)
+
+OK, E_INVALID, E_SHAPE, E_CAPACITY, E_HIP, E_UNSUPPORTED = range(6)
+DEV_E_CAPACITY = 1
+FLAG_PERSISTENT = 1
+FLAG_COUNT_EVAL = 2
+EXPORTS = ("ivrgs_workspace_size", "ivrgs_tiles_per_job", "ivrgs_compose", "ivrgs_project",
+           "ivrgs_bin_sort", "ivrgs_render_fwd", "ivrgs_render_bwd", "ivrgs_struct_size",
+           "ivrgs_status_string", "ivrgs_timing_enable", "ivrgs_timing_read")
+TIMING_KINDS = ("project", "tile_count", "scatter", "tile_sort", "render_fwd", "render_bwd",
+                "project_bwd", "compose", "fill")
+
+
+class ivrgs_gaussians(C.Structure):
+    _fields_ = [("n", C.c_int64)] + [(k, C.c_void_p) for k in PLANES] + [("model_id", C.c_void_p)]
+
+
+ivrgs_gaussians_mut = ivrgs_gaussians
+
+
+class ivrgs_camera(C.Structure):
+    _fields_ = [("R", C.c_float * 9), ("t", C.c_float * 3), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float)]
+
+
+class ivrgs_model_edit(C.Structure):
+    _fields_ = [("palette", C.c_float * 3), ("opacity_scale", C.c_float),
+                ("shade_scale", C.c_float * 4), ("shade_bias", C.c_float * 4),
+                ("light_dir", C.c_float * 3), ("headlight", C.c_int32)]
+
+
+class ivrgs_job(C.Structure):
+    _fields_ = [("camera", C.c_int32), ("gauss_begin", C.c_int32), ("gauss_count", C.c_int32),
+                ("rec_begin", C.c_int32)]
+
+
+class ivrgs_batch(C.Structure):
+    _fields_ = [("g", ivrgs_gaussians), ("gauss_index", C.c_void_p), ("edits", C.c_void_p),
+                ("n_models", C.c_int32), ("cameras", C.c_void_p), ("jobs", C.c_void_p),
+                ("n_jobs", C.c_int32), ("max_job_count", C.c_int32), ("n_records", C.c_int64)]
+
+
+class ivrgs_params(C.Structure):
+    _fields_ = [("alpha_min", C.c_float), ("alpha_max", C.c_float), ("T_min", C.c_float),
+                ("lowpass", C.c_float), ("z_near", C.c_float), ("bg", C.c_float * 3),
+                ("width", C.c_int32), ("height", C.c_int32), ("tile", C.c_int32),
+                ("flags", C.c_uint32), ("fwd_px", C.c_int32), ("bwd_px", C.c_int32),
+                ("sort_chunk", C.c_int32), ("reserved", C.c_int32)]
+
+
+class ivrgs_projected(C.Structure):
+    _fields_ = [("rec", C.c_void_p), ("rect", C.c_void_p)]
+
+
+class ivrgs_bins(C.Structure):
+    _fields_ = [("tile_start", C.c_void_p), ("sorted", C.c_void_p), ("capacity", C.c_int64),
+                ("status", C.c_void_p)]
+
+
+STRUCTS = (ivrgs_gaussians, ivrgs_camera, ivrgs_model_edit, ivrgs_job, ivrgs_batch,
+           ivrgs_params, ivrgs_projected, ivrgs_bins)
+
+_lib = None
+
+
+class IvrgsError(RuntimeError):
+    pass
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise IvrgsError(f"{path} is missing: build it with "
+                         f"`python -m paper_2504_17954_amd.build` (no CPU fallback exists)")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    lib.ivrgs_workspace_size.argtypes = [P, P, C.c_int64]
+    lib.ivrgs_workspace_size.restype = C.c_size_t
+    lib.ivrgs_tiles_per_job.argtypes = [P]
+    lib.ivrgs_tiles_per_job.restype = C.c_int32
+    lib.ivrgs_compose.argtypes = [P, C.c_int32, P, P, P]
+    lib.ivrgs_project.argtypes = [P, P, P, P]
+    lib.ivrgs_bin_sort.argtypes = [P, P, P, P, P, C.c_size_t, P]
+    lib.ivrgs_render_fwd.argtypes = [P, P, P, P, P, P, P, C.c_size_t, P]
+    lib.ivrgs_render_bwd.argtypes = [P, P, P, P, P, P, P, P, C.c_size_t, P]
+    for f in ("ivrgs_compose", "ivrgs_project", "ivrgs_bin_sort", "ivrgs_render_fwd",
+              "ivrgs_render_bwd"):
+        getattr(lib, f).restype = C.c_int
+    lib.ivrgs_struct_size.argtypes = [C.c_int32]
+    lib.ivrgs_struct_size.restype = C.c_int32
+    lib.ivrgs_status_string.argtypes = [C.c_int]
+    lib.ivrgs_status_string.restype = C.c_char_p
+    lib.ivrgs_timing_enable.argtypes = [C.c_int32]
+    lib.ivrgs_timing_enable.restype = None
+    lib.ivrgs_timing_read.argtypes = [P, P]
+    lib.ivrgs_timing_read.restype = C.c_int32
+    _lib = lib
+    return lib
+
+
+def check(status: int, what: str):
+    if status != OK:
+        msg = load().ivrgs_status_string(status).decode()
+        raise IvrgsError(f"{what}: {msg} (status {status})")
+
+
+def ref(x):
+    return C.cast(C.byref(x), C.c_void_p)
+
+
+def ivrgs_workspace_size(batch, params, capacity: int) -> int:
+    return int(load().ivrgs_workspace_size(ref(batch), ref(params), C.c_int64(capacity)))
+
+
+def ivrgs_tiles_per_job(params) -> int:
+    return int(load().ivrgs_tiles_per_job(ref(params)))
+
+
+def ivrgs_compose(models, n_models: int, edits, out, stream):
+    arr_m = (ivrgs_gaussians * n_models)(*models)
+    arr_e = (ivrgs_model_edit * n_models)(*edits)
+    check(load().ivrgs_compose(C.cast(arr_m, C.c_void_p), n_models, C.cast(arr_e, C.c_void_p),
+                               ref(out), stream), "ivrgs_compose")
+
+
+def ivrgs_project(batch, params, proj, stream):
+    check(load().ivrgs_project(ref(batch), ref(params), ref(proj), stream), "ivrgs_project")
+
+
+def ivrgs_bin_sort(batch, params, proj, bins, ws_ptr, ws_bytes, stream):
+    check(load().ivrgs_bin_sort(ref(batch), ref(params), ref(proj), ref(bins), ws_ptr, ws_bytes,
+                                stream), "ivrgs_bin_sort")
+
+
+def ivrgs_render_fwd(batch, params, proj, bins, rgba_ptr, maxw_ptr, ws_ptr, ws_bytes, stream):
+    check(load().ivrgs_render_fwd(ref(batch), ref(params), ref(proj), ref(bins), rgba_ptr, maxw_ptr,
+                                  ws_ptr, ws_bytes, stream), "ivrgs_render_fwd")
+
+
+def ivrgs_render_bwd(batch, params, proj, bins, rgba_ptr, dl_ptr, grads, ws_ptr, ws_bytes, stream):
+    check(load().ivrgs_render_bwd(ref(batch), ref(params), ref(proj), ref(bins), rgba_ptr, dl_ptr,
+                                  ref(grads), ws_ptr, ws_bytes, stream), "ivrgs_render_bwd")
+
+
+def ivrgs_struct_size(which: int) -> int:
+    return int(load().ivrgs_struct_size(which))
+
+
+def ivrgs_timing_enable(on: bool):
+    load().ivrgs_timing_enable(1 if on else 0)
+
+
+def ivrgs_timing_read() -> dict:
+    """{kernel kind: (total ms, launches)} since the last enable (syncs)."""
+    import numpy as np
+    ms = np.zeros(len(TIMING_KINDS), np.float64)
+    n = np.zeros(len(TIMING_KINDS), np.int64)
+    load().ivrgs_timing_read(ms.ctypes.data_as(C.c_void_p), n.ctypes.data_as(C.c_void_p))
+    return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(TIMING_KINDS)}
