@@ -59,7 +59,22 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 256 MiB five times (counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain copy kernel of known size: reading FETCH_SIZE / WRITE_SIZE for
+    it gives the scale between those counters and bytes moved."""
+    import torch
+    n = 64 * 1024 * 1024  # float32 elements = 256 MiB
+    src = torch.rand(n, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_dispatch": 4 * n, "dispatches": 5}), flush=True)
 
 
 def h2_scene(n_total, k):
@@ -73,6 +88,9 @@ def h2_scene(n_total, k):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
               "multi-GPU path to measure.", file=sys.stderr)

@@ -129,7 +129,10 @@ typedef struct {
  * lowpass: added to the diagonal of the screen covariance (px^2).  z_near:
  * Gaussians whose depth key is <= z_near are culled.  tile must be 16.
  * fwd_px / bwd_px: pixels per lane of the render kernels (1, 2 or 4; 0 picks
- * the default); they change speed, not results. */
+ * the default); they change speed, not results.  With IVRGS_FLAG_PERSISTENT
+ * (set for ivrgs_bin_sort and the render calls alike) the render kernels run
+ * a fixed grid that takes (job, tile) items, longest lists first, from a
+ * queue that ivrgs_bin_sort builds in the workspace. */
 typedef struct {
     float alpha_min, alpha_max, T_min, lowpass, z_near;
     float bg[3];
@@ -137,8 +140,8 @@ typedef struct {
     int32_t tile;
     uint32_t flags;
     int32_t fwd_px, bwd_px;
-    int32_t sort_chunk;              /* records per scatter workgroup, 0 = default */
-    int32_t reserved;
+    int32_t sort_chunk;              /* records per binning workgroup, 0 = default (1024) */
+    int32_t persist_per_cu;          /* IVRGS_FLAG_PERSISTENT: workgroups per CU, 0 = occupancy */
 } ivrgs_params;
 
 /* Projected records (device, caller-allocated, n_records entries):
@@ -235,15 +238,47 @@ ivrgs_status ivrgs_render_bwd(const ivrgs_batch *batch, const ivrgs_params *para
  * the library launches is bracketed by a pair of HIP events recorded on its
  * launch stream; ivrgs_timing_read() waits for those events and returns, per
  * kernel kind, the summed milliseconds and the number of launches since the
- * last enable.  Kinds: 0 project, 1 tile counts (difference grid, prefix,
- * scan), 2 scatter, 3 tile sort, 4 render_fwd, 5 render_bwd, 6 project_bwd,
- * 7 compose, 8 fills.  Process-wide state; not for concurrent callers. */
-#define IVRGS_TIMING_KINDS 9
+ * last enable.  Kinds: 0 project, 1 tile counts (per-chunk counts, column
+ * and tile scans, work queue), 2 scatter, 3 tile sort, 4 render_fwd,
+ * 5 render_bwd, 6 project_bwd, 7 compose, 8 fills, 9 cull.  Process-wide
+ * state; not for concurrent callers. */
+#define IVRGS_TIMING_KINDS 10
 void ivrgs_timing_enable(int32_t on);
 int32_t ivrgs_timing_read(double *ms, int64_t *launches);
 
+/* Learned culler (device weights): an MLP 16 -> 64 -> 64 -> 1 with ReLU on
+ * the features (mean 3, log_scale 3, opacity 1, unit direction from the
+ * Gaussian to the camera centre 3, then 6 zeros); any input normalisation is
+ * folded into w1/b1.  w1 [64][16] and w2 [64][64] hold BF16 bit patterns
+ * (row = output unit); b1, b2, w3 [64] and b3 are FP32.  A Gaussian is kept
+ * when its logit >= threshold. */
+typedef struct {
+    const uint16_t *w1;
+    const float *b1;
+    const uint16_t *w2;
+    const float *b2;
+    const float *w3;
+    float b3;
+    float threshold;
+} ivrgs_culler;
+
+/* Evaluates the culler for every Gaussian of g (n of them) seen from
+ * cameras[camera], writes the kept ids in ascending order to out_index
+ * ([n], device) and their count into jobs[job].gauss_count (device), so
+ * that ivrgs_project / ivrgs_bin_sort / ivrgs_render_* over a batch with
+ * gauss_index = out_index and that job (gauss_begin = 0, host-side counts
+ * set to n as upper bounds) render only the survivors, with no host sync.
+ * out_logit: [n] or NULL.  workspace: ivrgs_cull_workspace_size(n) bytes.
+ * This is the learned-culling extension of the rasterizer (no paper passage:
+ * the label it predicts is the compositing weight of Eq. 2 reaching 1/255). */
+size_t ivrgs_cull_workspace_size(int64_t n);
+ivrgs_status ivrgs_cull(const ivrgs_gaussians *g, const ivrgs_camera *cameras, int32_t camera,
+                        const ivrgs_culler *mlp, int32_t *out_index, ivrgs_job *jobs, int32_t job,
+                        float *out_logit, void *workspace, size_t workspace_bytes, void *stream);
+
 /* sizeof of the ABI structs, for binding checks: which = 0 gaussians,
- * 1 camera, 2 model_edit, 3 job, 4 batch, 5 params, 6 projected, 7 bins. */
+ * 1 camera, 2 model_edit, 3 job, 4 batch, 5 params, 6 projected, 7 bins,
+ * 8 culler. */
 int32_t ivrgs_struct_size(int32_t which);
 
 /* Human-readable name of a status code. */

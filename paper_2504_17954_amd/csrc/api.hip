@@ -62,7 +62,7 @@ void timing_end(int kind, hipStream_t s) {
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kDefaultChunk = 4096;
+constexpr int kDefaultChunk = 1024;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -124,7 +124,8 @@ ivrgs_status check_params(const ivrgs_params *p) {
     if (!(p->T_min > 0.f) || !(p->T_min < 1.f) || !(p->lowpass >= 0.f)) return IVRGS_E_INVALID;
     for (int px : {p->fwd_px, p->bwd_px})
         if (px != 0 && px != 1 && px != 2 && px != 4) return IVRGS_E_UNSUPPORTED;
-    if (p->sort_chunk < 0) return IVRGS_E_INVALID;
+    if (p->sort_chunk < 0 || p->persist_per_cu < 0) return IVRGS_E_INVALID;
+    if ((p->flags & ~(IVRGS_FLAG_PERSISTENT | IVRGS_FLAG_COUNT_EVAL)) != 0u) return IVRGS_E_UNSUPPORTED;
     return IVRGS_OK;
 }
 
@@ -139,7 +140,7 @@ ivrgs_status check_batch(const ivrgs_batch *b) {
 
 // Workspace regions.
 struct Layout {
-    size_t keys, keys2, vals2, counts, grec, total;
+    size_t keys, keys2, vals2, counts, grec, queue, total;
 };
 
 int chunk_of(const ivrgs_params &p) { return p.sort_chunk > 0 ? p.sort_chunk : kDefaultChunk; }
@@ -158,6 +159,8 @@ Layout layout(const ivrgs_batch &b, const ivrgs_params &p, int64_t capacity) {
     off += align_up(sizeof(uint32_t) * (size_t)b.n_jobs * chunk_rows(b, chunk_of(p)) * k.tiles_per_job);
     L.grec = off;
     off += align_up(sizeof(float) * kGradRec * (size_t)b.n_records);
+    L.queue = off;
+    off += align_up(sizeof(uint32_t) * (size_t)(2 + (int64_t)b.n_jobs * k.tiles_per_job));
     L.total = off;
     return L;
 }
@@ -234,15 +237,17 @@ ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params
     w.vals2 = reinterpret_cast<uint32_t *>(ws + L.vals2);
     w.counts = reinterpret_cast<uint32_t *>(ws + L.counts);
     const int chunk = chunk_of(*params);
-    return hip_status(launch_bin_sort(*batch, k, proj->rec, proj->rect, *bins, w, chunk, dl.sort_cap, dl.sort_lds,
-                                      reinterpret_cast<hipStream_t>(stream)));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = launch_bin_sort(*batch, k, proj->rec, proj->rect, *bins, w, chunk, dl.sort_cap, dl.sort_lds, s);
+    if (e == hipSuccess && (params->flags & IVRGS_FLAG_PERSISTENT))
+        e = launch_work_queue(bins->tile_start, (int64_t)batch->n_jobs * k.tiles_per_job,
+                              reinterpret_cast<uint32_t *>(ws + L.queue), s);
+    return hip_status(e);
 }
 
 ivrgs_status ivrgs_render_fwd(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
                               const ivrgs_bins *bins, float *out_rgba, float *out_maxw, void *workspace,
                               size_t workspace_bytes, void *stream) {
-    (void)workspace;
-    (void)workspace_bytes;
     ivrgs_status st = check_batch(batch);
     if (st != IVRGS_OK) return st;
     if ((st = check_params(params)) != IVRGS_OK) return st;
@@ -250,9 +255,15 @@ ivrgs_status ivrgs_render_fwd(const ivrgs_batch *batch, const ivrgs_params *para
     const Consts k = make_consts(*params);
     const int64_t n_tiles = (int64_t)batch->n_jobs * k.tiles_per_job;
     const bool count = (params->flags & IVRGS_FLAG_COUNT_EVAL) != 0;
+    uint32_t *queue = nullptr;
+    if (params->flags & IVRGS_FLAG_PERSISTENT) {
+        const Layout L = layout(*batch, *params, bins->capacity);
+        if (!workspace || workspace_bytes < L.total) return IVRGS_E_CAPACITY;
+        queue = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + L.queue);
+    }
     return hip_status(launch_render_fwd(k, pick_px(params->fwd_px, 1), n_tiles, proj->rec, bins->tile_start,
-                                        bins->sorted, out_rgba, out_maxw, bins->status, count,
-                                        reinterpret_cast<hipStream_t>(stream)));
+                                        bins->sorted, out_rgba, out_maxw, bins->status, count, queue,
+                                        params->persist_per_cu, reinterpret_cast<hipStream_t>(stream)));
 }
 
 ivrgs_status ivrgs_render_bwd(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
@@ -272,7 +283,11 @@ ivrgs_status ivrgs_render_bwd(const ivrgs_batch *batch, const ivrgs_params *para
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(grec), kGradRec * batch->n_records, 0u, s);
     if (e == hipSuccess)
         e = launch_render_bwd(k, pick_px(params->bwd_px, 1), n_tiles, proj->rec, bins->tile_start, bins->sorted,
-                              out_rgba, dl_drgba, grec, batch->n_records, s);
+                              out_rgba, dl_drgba, grec, batch->n_records,
+                              (params->flags & IVRGS_FLAG_PERSISTENT)
+                                  ? reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + L.queue)
+                                  : nullptr,
+                              params->persist_per_cu, s);
     const int64_t n = grads->n;
     float *planes[7] = {grads->mean, grads->log_scale, grads->quat, grads->opacity,
                         grads->normal, grads->color, grads->shade};
@@ -322,6 +337,23 @@ int32_t ivrgs_timing_read(double *ms, int64_t *launches) {
     return TK_KINDS;
 }
 
+size_t ivrgs_cull_workspace_size(int64_t n) { return n < 0 ? 0 : cull_workspace_bytes(n); }
+
+ivrgs_status ivrgs_cull(const ivrgs_gaussians *g, const ivrgs_camera *cameras, int32_t camera,
+                        const ivrgs_culler *mlp, int32_t *out_index, ivrgs_job *jobs, int32_t job,
+                        float *out_logit, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!g || !valid_gauss(*g) || !cameras || camera < 0 || !mlp || !jobs || job < 0) return IVRGS_E_INVALID;
+    if (!mlp->w1 || !mlp->b1 || !mlp->w2 || !mlp->b2 || !mlp->w3) return IVRGS_E_INVALID;
+    if (g->n > 0 && !out_index) return IVRGS_E_INVALID;
+    if (g->n >= (int64_t)0x7FFFFFFF) return IVRGS_E_SHAPE;
+    const size_t need = cull_workspace_bytes(g->n);
+    if (!workspace || workspace_bytes < need) return IVRGS_E_CAPACITY;
+    uint8_t *keep = static_cast<uint8_t *>(workspace);
+    uint32_t *counts = reinterpret_cast<uint32_t *>(keep + (g->n + 255) / 256 * 256);
+    return hip_status(launch_cull(*g, cameras, camera, *mlp, out_index, jobs, job, out_logit, keep, counts,
+                                  reinterpret_cast<hipStream_t>(stream)));
+}
+
 int32_t ivrgs_struct_size(int32_t which) {
     switch (which) {
     case 0: return (int32_t)sizeof(ivrgs_gaussians);
@@ -332,6 +364,7 @@ int32_t ivrgs_struct_size(int32_t which) {
     case 5: return (int32_t)sizeof(ivrgs_params);
     case 6: return (int32_t)sizeof(ivrgs_projected);
     case 7: return (int32_t)sizeof(ivrgs_bins);
+    case 8: return (int32_t)sizeof(ivrgs_culler);
     default: return -1;
     }
 }

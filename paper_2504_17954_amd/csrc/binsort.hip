@@ -30,10 +30,51 @@ __device__ __forceinline__ void unpack_rect(uint2 rc, int &x0, int &y0, int &x1,
     y1 = rc.y >> 16;
 }
 
+// Whether tile (tx, ty) can hold a pixel where the record reaches
+// alpha >= alpha_min: the largest exponent qa dx^2 + qb dx dy + qc dy^2 over
+// the box of the tile's pixel centres (offsets from the mean) is compared with
+// the record's cutoff.  The exponent is a concave quadratic, so over a box
+// that misses the mean its maximum lies on an edge, where it is a 1D
+// quadratic maximised by clamping its vertex.  A small tolerance keeps the
+// test conservative against FP32 rounding of the per-pixel evaluation.  Both
+// binning passes call this with the same inputs, so they agree exactly.
+struct HitTest {
+    float mx, my, qa, qb, qc, cut, i2qa, i2qc, tol;
+};
+
+__device__ __forceinline__ HitTest make_hit_test(const float4 r0, const float4 r1, const float4 r2) {
+    HitTest h;
+    h.mx = r0.x;
+    h.my = r0.y;
+    h.qa = r0.z;
+    h.qb = r0.w;
+    h.qc = r1.x;
+    h.cut = r2.z;
+    h.i2qa = 0.5f / h.qa;
+    h.i2qc = 0.5f / h.qc;
+    h.tol = h.cut - 1.0e-3f * (1.f + fabsf(h.cut));
+    return h;
+}
+
+__device__ __forceinline__ bool tile_hit(const HitTest &h, int tx, int ty) {
+    const float x0 = (float)(tx * kTile) + 0.5f - h.mx, x1 = x0 + (float)(kTile - 1);
+    const float y0 = (float)(ty * kTile) + 0.5f - h.my, y1 = y0 + (float)(kTile - 1);
+    if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return true;
+    auto q = [&](float dx, float dy) { return fmaf(fmaf(h.qa, dx, h.qb * dy), dx, h.qc * dy * dy); };
+    // on the edge x = xe the exponent is maximal at dy = -qb xe / (2 qc), clamped
+    const float ya = fminf(fmaxf(-h.qb * x0 * h.i2qc, y0), y1);
+    const float yb = fminf(fmaxf(-h.qb * x1 * h.i2qc, y0), y1);
+    const float xa = fminf(fmaxf(-h.qb * y0 * h.i2qa, x0), x1);
+    const float xb = fminf(fmaxf(-h.qb * y1 * h.i2qa, x0), x1);
+    const float best = fmaxf(fmaxf(q(x0, ya), q(x1, yb)), fmaxf(q(xa, y0), q(xb, y1)));
+    return best >= h.tol;
+}
+
 // Pass 1 of the binning: per (job, chunk of records) the number of pairs each
-// tile receives, counted with LDS atomics and written as one row of the
-// count matrix [job][chunk][tile].
-__global__ __launch_bounds__(256) void k_chunk_count(ivrgs_batch b, Consts k, const uint2 *__restrict__ rect,
+// tile receives, counted with LDS atomics and written into the count matrix
+// [job][tile][chunk].
+__global__ __launch_bounds__(256) void k_chunk_count(ivrgs_batch b, Consts k, const float *__restrict__ rec,
+                                                     const uint2 *__restrict__ rect,
                                                      uint32_t *__restrict__ counts, int chunk, int n_chunks) {
     extern __shared__ uint32_t cnt[];
     const ivrgs_job job = b.jobs[blockIdx.y];
@@ -43,35 +84,47 @@ __global__ __launch_bounds__(256) void k_chunk_count(ivrgs_batch b, Consts k, co
     const int tpj = k.tiles_per_job, tx_n = k.tiles_x;
     for (int t = threadIdx.x; t < tpj; t += blockDim.x) cnt[t] = 0;
     __syncthreads();
+    const float4 *rec4 = reinterpret_cast<const float4 *>(rec);
     for (int l = begin + threadIdx.x; l < end; l += blockDim.x) {
-        const uint2 rc = rect[(int64_t)job.rec_begin + l];
+        const int64_t r = (int64_t)job.rec_begin + l;
+        const uint2 rc = rect[r];
         if (rc.x == 0u && rc.y == 0u) continue;
         int x0, y0, x1, y1;
         unpack_rect(rc, x0, y0, x1, y1);
+        const HitTest ht = make_hit_test(rec4[3 * r], rec4[3 * r + 1], rec4[3 * r + 2]);
         for (int y = y0; y < y1; ++y)
-            for (int x = x0; x < x1; ++x) atomicAdd(&cnt[y * tx_n + x], 1u);
+            for (int x = x0; x < x1; ++x)
+                if (tile_hit(ht, x, y)) atomicAdd(&cnt[y * tx_n + x], 1u);
     }
     __syncthreads();
-    uint32_t *row = counts + ((int64_t)blockIdx.y * n_chunks + blockIdx.x) * tpj;
-    for (int t = threadIdx.x; t < tpj; t += blockDim.x) row[t] = cnt[t];
+    uint32_t *col = counts + (int64_t)blockIdx.y * tpj * n_chunks + blockIdx.x;
+    for (int t = threadIdx.x; t < tpj; t += blockDim.x) col[(int64_t)t * n_chunks] = cnt[t];
 }
 
-// Per (job, tile): exclusive scan of the count column over the job's chunks
-// (in place) and the tile's total.
+// Per (job, tile), one wave: exclusive scan of the tile's counts over the
+// job's chunks (contiguous in memory, in place) and the tile's total.
 __global__ __launch_bounds__(256) void k_col_scan(ivrgs_batch b, Consts k, uint32_t *__restrict__ counts, int chunk,
                                                   int n_chunks, uint32_t *__restrict__ tile_counts) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (t >= k.tiles_per_job) return;
     const ivrgs_job job = b.jobs[blockIdx.y];
     const int rows = (job.gauss_count + chunk - 1) / chunk;
-    uint32_t *col = counts + (int64_t)blockIdx.y * n_chunks * k.tiles_per_job + t;
-    uint32_t acc = 0;
-    for (int c = 0; c < rows; ++c) {
-        const uint32_t v = col[(int64_t)c * k.tiles_per_job];
-        col[(int64_t)c * k.tiles_per_job] = acc;
-        acc += v;
+    uint32_t *col = counts + ((int64_t)blockIdx.y * k.tiles_per_job + t) * n_chunks;
+    uint32_t carry = 0;
+    for (int base = 0; base < rows; base += 64) {
+        const int c = base + lane;
+        const uint32_t v = c < rows ? col[c] : 0u;
+        uint32_t incl = v;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t o = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += o;
+        }
+        if (c < rows) col[c] = carry + incl - v;
+        carry += __shfl(incl, 63, 64);
     }
-    tile_counts[(int64_t)blockIdx.y * k.tiles_per_job + t] = acc;
+    if (lane == 0) tile_counts[(int64_t)blockIdx.y * k.tiles_per_job + t] = carry;
 }
 
 // Exclusive prefix of 64-bit values over a workgroup of 1024 threads.
@@ -136,19 +189,23 @@ __global__ __launch_bounds__(256) void k_scatter(ivrgs_batch b, Consts k, const 
     if (begin >= job.gauss_count) return;
     const int end = min(begin + chunk, job.gauss_count);
     const int tpj = k.tiles_per_job, tx_n = k.tiles_x;
-    const uint32_t *row = counts + ((int64_t)blockIdx.y * n_chunks + blockIdx.x) * tpj;
+    const uint32_t *col = counts + (int64_t)blockIdx.y * tpj * n_chunks + blockIdx.x;
     const uint32_t *st = starts + (int64_t)blockIdx.y * tpj;
-    for (int t = threadIdx.x; t < tpj; t += blockDim.x) cur[t] = st[t] + row[t];
+    for (int t = threadIdx.x; t < tpj; t += blockDim.x) cur[t] = st[t] + col[(int64_t)t * n_chunks];
     __syncthreads();
     for (int l = begin + threadIdx.x; l < end; l += blockDim.x) {
         const int64_t r = (int64_t)job.rec_begin + l;
         const uint2 rc = rect[r];
         if (rc.x == 0u && rc.y == 0u) continue;
-        const uint32_t z = __float_as_uint(rec[r * kRecWords + RZ]);
+        const float4 *rec4 = reinterpret_cast<const float4 *>(rec);
+        const float4 r2 = rec4[3 * r + 2];
+        const HitTest ht = make_hit_test(rec4[3 * r], rec4[3 * r + 1], r2);
+        const uint32_t z = __float_as_uint(r2.y);
         int x0, y0, x1, y1;
         unpack_rect(rc, x0, y0, x1, y1);
         for (int y = y0; y < y1; ++y)
             for (int x = x0; x < x1; ++x) {
+                if (!tile_hit(ht, x, y)) continue;
                 const uint32_t slot = atomicAdd(&cur[y * tx_n + x], 1u);
                 keys[slot] = z;
                 vals[slot] = (uint32_t)r;
@@ -157,7 +214,7 @@ __global__ __launch_bounds__(256) void k_scatter(ivrgs_batch b, Consts k, const 
 }
 
 // ---------------------------------------------------------------------------
-// Per-tile sort: 1024 threads; wave w owns the contiguous segment
+// Per-tile sort: wave w of a block owns the contiguous segment
 // [w * seg, (w + 1) * seg) of the tile's list (seg a multiple of 64), so
 // processing (wave, sub-batch of 64, lane) in order visits the list in order
 // and each counting pass is stable.  Buffers ping-pong between an LDS pair
@@ -165,10 +222,10 @@ __global__ __launch_bounds__(256) void k_scatter(ivrgs_batch b, Consts k, const 
 // capacity: the list lives in LDS and each pass stages through global
 // memory), or two global arrays (larger lists).  A pass prefetches kU
 // sub-batches per round so that a global source costs one latency per round.
-constexpr int kSortThreads = 1024;
-constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kBigWaves = 16;       // 1024 threads for lists above kSmallCap
+constexpr int kSmallWaves = 4;      // 256 threads for lists up to kSmallCap
+constexpr int kSmallCap = 4096;     // both ping-pong buffers in LDS
 constexpr int kU = 8;
-constexpr int kHistWords = kSortWaves * 256;
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -186,7 +243,7 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t dg, uint64_t active) {
 }
 
 // Exclusive scan over threads 0..255 (others pass 0); every thread calls it.
-__device__ uint32_t scan256(uint32_t v, uint32_t *tmp /* >= kSortWaves */) {
+__device__ uint32_t scan256(uint32_t v, uint32_t *tmp /* >= waves per block */) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t incl = v;
 #pragma unroll
@@ -203,12 +260,13 @@ __device__ uint32_t scan256(uint32_t v, uint32_t *tmp /* >= kSortWaves */) {
 }
 
 // Turn per-wave digit histograms into per-wave starting offsets.
+template <int NW>
 __device__ void hist_to_offsets(uint32_t *hist, uint32_t *tmp) {
-    uint32_t c[kSortWaves];
+    uint32_t c[NW];
     uint32_t tot = 0;
     if (threadIdx.x < 256) {
 #pragma unroll
-        for (int w = 0; w < kSortWaves; ++w) {
+        for (int w = 0; w < NW; ++w) {
             c[w] = hist[w * 256 + threadIdx.x];
             tot += c[w];
         }
@@ -217,7 +275,7 @@ __device__ void hist_to_offsets(uint32_t *hist, uint32_t *tmp) {
     if (threadIdx.x < 256) {
         uint32_t run = pre;
 #pragma unroll
-        for (int w = 0; w < kSortWaves; ++w) {
+        for (int w = 0; w < NW; ++w) {
             hist[w * 256 + threadIdx.x] = run;
             run += c[w];
         }
@@ -226,17 +284,18 @@ __device__ void hist_to_offsets(uint32_t *hist, uint32_t *tmp) {
 }
 
 // One stable counting pass on digit (key >> shift) & 255, src -> dst.
+template <int NW>
 __device__ void radix_pass(const uint32_t *sk, const uint32_t *sv, uint32_t *dk, uint32_t *dv, int n, int shift,
                            uint32_t *hist, uint32_t *tmp) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int seg = ((n + kSortWaves - 1) / kSortWaves + 63) / 64 * 64;
+    const int seg = ((n + NW - 1) / NW + 63) / 64 * 64;
     const int s0 = min(wave * seg, n), s1 = min(s0 + seg, n);
     uint32_t *h = hist + wave * 256;
     for (int d = lane; d < 256; d += 64) h[d] = 0;
     __syncthreads();
     for (int i = s0 + lane; i < s1; i += 64) atomicAdd(&h[(sk[i] >> shift) & 255u], 1u);
     __syncthreads();
-    hist_to_offsets(hist, tmp);
+    hist_to_offsets<NW>(hist, tmp);
     for (int base = s0; base < s1; base += 64 * kU) {
         uint32_t kk[kU], vv[kU];
 #pragma unroll
@@ -287,17 +346,20 @@ __device__ void fix_ties(const uint32_t *key, uint32_t *val, int n) {
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_tile_sort(const uint32_t *__restrict__ starts, int64_t n_tiles,
-                                                            uint32_t *keys, uint32_t *vals, uint32_t *keys2,
-                                                            uint32_t *vals2, int lds_cap) {
+// NW waves per block.  The small class takes lists of 2..kSmallCap pairs and
+// keeps both buffers in LDS; the big class takes the longer lists.
+template <int NW, bool kSmall>
+__global__ __launch_bounds__(NW * 64) void k_tile_sort(const uint32_t *__restrict__ starts, int64_t n_tiles,
+                                                       uint32_t *keys, uint32_t *vals, uint32_t *keys2,
+                                                       uint32_t *vals2, int lds_cap) {
     extern __shared__ uint32_t lds[];
-    __shared__ uint32_t red_and[kSortWaves], red_or[kSortWaves], tmp[kSortWaves];
+    __shared__ uint32_t red_and[NW], red_or[NW], tmp[NW];
     if (starts[n_tiles] == 0xFFFFFFFFu) return;
     const uint32_t start = starts[blockIdx.x], end = starts[blockIdx.x + 1];
     const int n = (int)(end - start);
-    if (n <= 1) return;
+    if (n <= 1 || (kSmall ? n > kSmallCap : n <= kSmallCap)) return;
     uint32_t *hist = lds;
-    uint32_t *buf = lds + kHistWords;  // keys [lds_cap] then values [lds_cap]
+    uint32_t *buf = lds + NW * 256;  // keys [lds_cap] then values [lds_cap]
     const int half = lds_cap / 2;
     uint32_t *ka, *va, *kb, *vb;
     bool copy_back = false;  // list in LDS, staging in global memory
@@ -341,14 +403,14 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(const uint32_t *__re
     __syncthreads();
     a = 0xFFFFFFFFu;
     o = 0u;
-    for (int w = 0; w < kSortWaves; ++w) {
+    for (int w = 0; w < NW; ++w) {
         a &= red_and[w];
         o |= red_or[w];
     }
     const uint32_t varying = a ^ o;
     for (int d = 0; d < 4; ++d) {
         if (((varying >> (8 * d)) & 255u) == 0u) continue;
-        radix_pass(ka, va, kb, vb, n, 8 * d, hist, tmp);
+        radix_pass<NW>(ka, va, kb, vb, n, 8 * d, hist, tmp);
         if (copy_back) {
             for (int i = threadIdx.x; i < n; i += blockDim.x) {
                 ka[i] = kb[i];
@@ -366,6 +428,46 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(const uint32_t *__re
     fix_ties(ka, va, n);
     if (va != vals + start)
         for (int i = threadIdx.x; i < n; i += blockDim.x) vals[start + i] = va[i];
+}
+
+// Work queue for the persistent render kernels: nonempty tiles ordered by
+// floor(log2(pairs)) descending, so the longest lists start first.
+// queue[1] = number of items, queue[2 + i] = tile of item i; queue[0] is the
+// counter the render kernels advance (reset before each launch).
+__global__ __launch_bounds__(1024) void k_work_queue(const uint32_t *__restrict__ starts, int64_t n_tiles,
+                                                     uint32_t *__restrict__ queue) {
+    __shared__ uint32_t hist[32], base[32];
+    if (starts[n_tiles] == 0xFFFFFFFFu) {
+        if (threadIdx.x == 0) queue[1] = 0;
+        return;
+    }
+    if (threadIdx.x < 32) hist[threadIdx.x] = 0;
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < n_tiles; t += blockDim.x) {
+        const uint32_t c = starts[t + 1] - starts[t];
+        if (c) atomicAdd(&hist[31 - __clz(c)], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int b = 31; b >= 0; --b) {
+            base[b] = run;
+            run += hist[b];
+        }
+        queue[1] = run;
+    }
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < n_tiles; t += blockDim.x) {
+        const uint32_t c = starts[t + 1] - starts[t];
+        if (c) queue[2 + atomicAdd(&base[31 - __clz(c)], 1u)] = (uint32_t)t;
+    }
+}
+
+hipError_t launch_work_queue(const uint32_t *starts, int64_t n_tiles, uint32_t *queue, hipStream_t s) {
+    if (n_tiles == 0) return hipSuccess;
+    TimedScope ts(TK_COUNT, s);
+    hipLaunchKernelGGL(k_work_queue, dim3(1), dim3(1024), 0, s, starts, n_tiles, queue);
+    return hipGetLastError();
 }
 
 // ----------------------------------------------------------------------------
@@ -389,9 +491,9 @@ hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *r
     {
         TimedScope ts(TK_COUNT, s);
         if (n_chunks > 0) {
-            hipLaunchKernelGGL(k_chunk_count, dim3(n_chunks, b.n_jobs), dim3(256), cnt_lds, s, b, k,
+            hipLaunchKernelGGL(k_chunk_count, dim3(n_chunks, b.n_jobs), dim3(256), cnt_lds, s, b, k, rec,
                                reinterpret_cast<const uint2 *>(rect), w.counts, chunk, n_chunks);
-            hipLaunchKernelGGL(k_col_scan, dim3((k.tiles_per_job + 255) / 256, b.n_jobs), dim3(256), 0, s, b, k,
+            hipLaunchKernelGGL(k_col_scan, dim3((k.tiles_per_job + 3) / 4, b.n_jobs), dim3(256), 0, s, b, k,
                                w.counts, chunk, n_chunks, bins.tile_start);
         } else if (n_tiles > 0) {
             hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, bins.tile_start, n_tiles, 0u);
@@ -407,18 +509,26 @@ hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *r
     }
     if (n_tiles > 0) {
         TimedScope ts(TK_SORT, s);
-        hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)n_tiles), dim3(kSortThreads), sort_lds, s, bins.tile_start,
-                           n_tiles, w.keys, bins.sorted, w.keys2, w.vals2, lds_cap);
+        hipLaunchKernelGGL((k_tile_sort<kSmallWaves, true>), dim3((unsigned)n_tiles), dim3(kSmallWaves * 64),
+                           small_sort_lds_bytes(), s, bins.tile_start, n_tiles, w.keys, bins.sorted, w.keys2,
+                           w.vals2, 2 * kSmallCap);
+        hipLaunchKernelGGL((k_tile_sort<kBigWaves, false>), dim3((unsigned)n_tiles), dim3(kBigWaves * 64), sort_lds,
+                           s, bins.tile_start, n_tiles, w.keys, bins.sorted, w.keys2, w.vals2, lds_cap);
     }
     return hipGetLastError();
 }
 
-// LDS bytes of the sort for a staging capacity (elements).
-size_t sort_lds_bytes(int lds_cap) { return sizeof(uint32_t) * (kHistWords + 2 * (size_t)lds_cap); }
+// LDS bytes of the big-list sort for a staging capacity (elements).
+size_t sort_lds_bytes(int lds_cap) { return sizeof(uint32_t) * (kBigWaves * 256 + 2 * (size_t)lds_cap); }
+
+size_t small_sort_lds_bytes() { return sizeof(uint32_t) * (kSmallWaves * 256 + 4 * (size_t)kSmallCap); }
 
 hipError_t set_sort_lds_limit(size_t bytes) {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_tile_sort),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_tile_sort<kBigWaves, false>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_tile_sort<kSmallWaves, true>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)small_sort_lds_bytes());
 }
 
 }  // namespace ivrgs

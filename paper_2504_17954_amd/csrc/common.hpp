@@ -76,4 +76,46 @@ __device__ __forceinline__ float wave_sum_to_lane63(float v) {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Reduce-scatter of 32 per-lane values over the 64 lanes of a wave.  On
+// return, lanes 2m and 2m+1 both hold the wave total of value m.  Each
+// butterfly level pairs every lane with a partner that holds the same set of
+// value indices, keeps one half of the set and adds the partner's copy of it.
+// Partners at lane distance 32 and 16 cross DPP rows and come from lane
+// shuffles; the rest from DPP (row rotate by 8, half-row mirror, quad
+// permutes).
+#define IVRGS_DPP(v, ctrl) __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, (v)), (ctrl), 0xF, 0xF, false))
+
+__device__ __forceinline__ float reduce_scatter32(float v[32]) {
+    const int lane = lane_id();
+    const bool hi5 = (lane >> 5) & 1, hi4 = (lane >> 4) & 1;
+    float a[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const float keep = hi5 ? v[k + 16] : v[k], send = hi5 ? v[k] : v[k + 16];
+        a[k] = keep + __shfl_xor(send, 32, 64);
+    }
+    float b[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const float keep = hi4 ? a[k + 8] : a[k], send = hi4 ? a[k] : a[k + 8];
+        b[k] = keep + __shfl_xor(send, 16, 64);
+    }
+    const bool hi3 = (lane >> 3) & 1, hi2 = (lane >> 2) & 1, hi1 = (lane >> 1) & 1;
+    float c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float keep = hi3 ? b[k + 4] : b[k], send = hi3 ? b[k] : b[k + 4];
+        c[k] = keep + IVRGS_DPP(send, 0x128);  // row_ror:8, partner lane ^ 8
+    }
+    float d[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float keep = hi2 ? c[k + 2] : c[k], send = hi2 ? c[k] : c[k + 2];
+        d[k] = keep + IVRGS_DPP(send, 0x141);  // row_half_mirror, partner 7 - i
+    }
+    const float keep = hi1 ? d[1] : d[0], send = hi1 ? d[0] : d[1];
+    float e = keep + IVRGS_DPP(send, 0x4E);  // quad_perm [2,3,0,1], partner lane ^ 2
+    return e + IVRGS_DPP(e, 0xB1);           // quad_perm [1,0,3,2], partner lane ^ 1
+}
+
 }  // namespace ivrgs

@@ -7,7 +7,7 @@ namespace ivrgs {
 
 // Kernel-timing hooks (no-ops unless timing is enabled).
 enum TimingKind { TK_PROJECT = 0, TK_COUNT, TK_SCATTER, TK_SORT, TK_FWD, TK_BWD, TK_PROJECT_BWD,
-                  TK_COMPOSE, TK_FILL, TK_KINDS };
+                  TK_COMPOSE, TK_FILL, TK_CULL, TK_KINDS };
 void timing_begin(int kind, hipStream_t s);
 void timing_end(int kind, hipStream_t s);
 
@@ -33,12 +33,18 @@ hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *r
                            const ivrgs_bins &bins, const BinWork &w, int chunk, int lds_cap, size_t sort_lds,
                            hipStream_t s);
 size_t sort_lds_bytes(int lds_cap);
+size_t small_sort_lds_bytes();
 hipError_t set_sort_lds_limit(size_t bytes);
 hipError_t launch_render_fwd(const Consts &k, int px, int64_t n_tiles, const float *rec, const uint32_t *starts,
                              const uint32_t *sorted, float *out, float *maxw, int64_t *status, bool count,
-                             hipStream_t s);
+                             uint32_t *queue, int per_cu, hipStream_t s);
 hipError_t launch_render_bwd(const Consts &k, int px, int64_t n_tiles, const float *rec, const uint32_t *starts,
                              const uint32_t *sorted, const float *rgba, const float *dl, float *grec,
-                             int64_t n_rec, hipStream_t s);
+                             int64_t n_rec, uint32_t *queue, int per_cu, hipStream_t s);
+hipError_t launch_cull(const ivrgs_gaussians &g, const ivrgs_camera *cams, int camera, const ivrgs_culler &mlp,
+                       int32_t *out_index, ivrgs_job *jobs, int job, float *logits, uint8_t *keep,
+                       uint32_t *counts, hipStream_t s);
+size_t cull_workspace_bytes(int64_t n);
+hipError_t launch_work_queue(const uint32_t *starts, int64_t n_tiles, uint32_t *queue, hipStream_t s);
 
 }  // namespace ivrgs

@@ -49,19 +49,18 @@ __device__ __forceinline__ float wave_max_to_lane63(float v) {
     return v;
 }
 
+
 // ----------------------------------------------------------------------------
+// Forward of one tile (the whole workgroup takes part).
 template <int PX, bool kMaxw, bool kCount>
-__global__ __launch_bounds__(kTilePix / PX) void k_render_fwd(Consts k, const float4 *__restrict__ rec,
-                                                             const uint32_t *__restrict__ starts,
-                                                             const uint32_t *__restrict__ sorted, int64_t n_tiles,
-                                                             float *__restrict__ out, float *__restrict__ maxw,
-                                                             int64_t *__restrict__ status) {
+__device__ __forceinline__ void fwd_tile(const Consts &k, const float4 *__restrict__ rec,
+                                         const uint32_t *__restrict__ starts, const uint32_t *__restrict__ sorted,
+                                         float *__restrict__ out, float *__restrict__ maxw,
+                                         int64_t *__restrict__ status, int64_t tile) {
     constexpr int NT = kTilePix / PX;
     __shared__ float4 s0[NT], s1[NT];
     __shared__ float2 s2[NT];
     __shared__ uint32_t sid[NT];
-    if (starts[n_tiles] == 0xFFFFFFFFu) return;
-    const int64_t tile = blockIdx.x;
     const TileGeom tg = tile_geom(k, tile);
     const uint32_t start = starts[tile], end = starts[tile + 1];
 
@@ -155,20 +154,50 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_fwd(Consts k, const fl
     }
 }
 
-// ----------------------------------------------------------------------------
-template <int PX>
-__global__ __launch_bounds__(kTilePix / PX) void k_render_bwd(Consts k, const float4 *__restrict__ rec,
+template <int PX, bool kMaxw, bool kCount>
+__global__ __launch_bounds__(kTilePix / PX) void k_render_fwd(Consts k, const float4 *__restrict__ rec,
                                                              const uint32_t *__restrict__ starts,
                                                              const uint32_t *__restrict__ sorted, int64_t n_tiles,
-                                                             const float *__restrict__ rgba,
-                                                             const float *__restrict__ dl, float *__restrict__ grec,
-                                                             int64_t n_rec) {
+                                                             float *__restrict__ out, float *__restrict__ maxw,
+                                                             int64_t *__restrict__ status) {
+    if (starts[n_tiles] == 0xFFFFFFFFu) return;
+    fwd_tile<PX, kMaxw, kCount>(k, rec, starts, sorted, out, maxw, status, blockIdx.x);
+}
+
+// Persistent variant: a fixed grid pops tiles from queue[2 ..] (heaviest
+// first) through the counter queue[0] until queue[1] items are taken.
+__device__ __forceinline__ bool next_item(uint32_t *queue, uint32_t n_items, uint32_t &item) {
+    __shared__ uint32_t s_item;
+    if (threadIdx.x == 0) s_item = atomicAdd(&queue[0], 1u);
+    __syncthreads();
+    item = s_item;
+    __syncthreads();
+    return item < n_items;
+}
+
+template <int PX, bool kMaxw, bool kCount>
+__global__ __launch_bounds__(kTilePix / PX) void k_render_fwd_persistent(
+    Consts k, const float4 *__restrict__ rec, const uint32_t *__restrict__ starts,
+    const uint32_t *__restrict__ sorted, int64_t n_tiles, float *__restrict__ out, float *__restrict__ maxw,
+    int64_t *__restrict__ status, uint32_t *__restrict__ queue) {
+    if (starts[n_tiles] == 0xFFFFFFFFu) return;
+    const uint32_t n_items = queue[1];
+    uint32_t item;
+    while (next_item(queue, n_items, item)) fwd_tile<PX, kMaxw, kCount>(k, rec, starts, sorted, out, maxw, status,
+                                                                          queue[2 + item]);
+}
+
+// ----------------------------------------------------------------------------
+// Backward of one tile (the whole workgroup takes part).
+template <int PX>
+__device__ __forceinline__ void bwd_tile(const Consts &k, const float4 *__restrict__ rec,
+                                         const uint32_t *__restrict__ starts, const uint32_t *__restrict__ sorted,
+                                         const float *__restrict__ rgba, const float *__restrict__ dl,
+                                         float *__restrict__ grec, int64_t n_rec, int64_t tile) {
     constexpr int NT = kTilePix / PX;
     __shared__ float4 s0[NT], s1[NT];
     __shared__ float2 s2[NT];
     __shared__ uint32_t sid[NT];
-    if (starts[n_tiles] == 0xFFFFFFFFu) return;
-    const int64_t tile = blockIdx.x;
     const TileGeom tg = tile_geom(k, tile);
     const uint32_t start = starts[tile], end = starts[tile + 1];
     const size_t plane = (size_t)k.width * k.height;
@@ -178,6 +207,12 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_bwd(Consts k, const fl
     float px[PX], py[PX], T[PX], P0[PX], P1[PX], P2[PX];
     float o0[PX], o1[PX], o2[PX], Tf[PX], g0[PX], g1[PX], g2[PX], gA[PX];
     bool alive[PX];
+    // after the reduce-scatter, lane pair (2m, 2m+1) holds value m = g * 9 + v
+    // of Gaussian g of the group; the even lane issues the atomic
+    constexpr int kGroup = 3;
+    const int my_m = lane_id() >> 1;
+    const bool my_slot = ((lane_id() & 1) == 0) && my_m < kGroup * kGradRec;
+    const int my_g = my_m / kGradRec, my_v = my_m % kGradRec;
 #pragma unroll
     for (int j = 0; j < PX; ++j) {
         int x, y;
@@ -218,76 +253,67 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_bwd(Consts k, const fl
         }
         __syncthreads();
         const int cnt = min((uint32_t)NT, end - base);
-        for (int i = 0; i < cnt; ++i) {
+        for (int i0 = 0; i0 < cnt; i0 += kGroup) {
             if (__ballot(mine) == 0ull) break;
-            const float4 a = s0[i];
-            const float4 c = s1[i];
-            const float2 cc = s2[i];
-            const float cb = cc.x;
-            float ax = 0.f, ay = 0.f, aqa = 0.f, aqb = 0.f, aqc = 0.f, ao = 0.f, ar = 0.f, ag = 0.f, ab = 0.f;
+            float acc[32];
+#pragma unroll
+            for (int q = 0; q < 32; ++q) acc[q] = 0.f;
             bool hit = false;
 #pragma unroll
-            for (int j = 0; j < PX; ++j) {
-                if (!alive[j]) continue;
-                const float dx = px[j] - a.x, dy = py[j] - a.y;
-                const float p2 = splat_exponent(a.z, a.w, c.x, dx, dy);
-                if (p2 < cc.y) continue;  // implies alpha < alpha_min
-                const float G = fast_exp2(p2);
-                const float raw = c.y * G;
-                const float al = fminf(k.alpha_max, raw);
-                if (al < k.alpha_min) continue;
-                const float Tn = T[j] * (1.f - al);
-                if (Tn < k.T_min) {
-                    alive[j] = false;
-                    continue;
+            for (int g = 0; g < kGroup; ++g) {
+                if (i0 + g < cnt) {  // wave-uniform
+                    const int i = i0 + g;
+                    const float4 a = s0[i];
+                    const float4 c = s1[i];
+                    const float2 cc = s2[i];
+                    const float cb = cc.x;
+#pragma unroll
+                    for (int j = 0; j < PX; ++j) {
+                        if (!alive[j]) continue;
+                        const float dx = px[j] - a.x, dy = py[j] - a.y;
+                        const float p2 = splat_exponent(a.z, a.w, c.x, dx, dy);
+                        if (p2 < cc.y) continue;  // implies alpha < alpha_min
+                        const float G = fast_exp2(p2);
+                        const float raw = c.y * G;
+                        const float al = fminf(k.alpha_max, raw);
+                        if (al < k.alpha_min) continue;
+                        const float Tn = T[j] * (1.f - al);
+                        if (Tn < k.T_min) {
+                            alive[j] = false;
+                            continue;
+                        }
+                        const float w = al * T[j];
+                        P0[j] = fmaf(w, c.z, P0[j]);
+                        P1[j] = fmaf(w, c.w, P1[j]);
+                        P2[j] = fmaf(w, cb, P2[j]);
+                        // colour behind this Gaussian, background included
+                        const float b0 = o0[j] - P0[j], b1 = o1[j] - P1[j], b2 = o2[j] - P2[j];
+                        const float gc = g0[j] * c.z + g1[j] * c.w + g2[j] * cb;
+                        const float gb = g0[j] * b0 + g1[j] * b1 + g2[j] * b2;
+                        const float inv = __builtin_amdgcn_rcpf(1.f - al);
+                        const float dLda = T[j] * gc - (gb - gA[j] * Tf[j]) * inv;
+                        float *ag = acc + g * kGradRec;
+                        ag[GCR] = fmaf(w, g0[j], ag[GCR]);
+                        ag[GCG] = fmaf(w, g1[j], ag[GCG]);
+                        ag[GCB] = fmaf(w, g2[j], ag[GCB]);
+                        if (raw <= k.alpha_max) {
+                            ag[GO] = fmaf(dLda, G, ag[GO]);
+                            const float dp = dLda * raw * kLn2;
+                            ag[GQA] = fmaf(dp, dx * dx, ag[GQA]);
+                            ag[GQB] = fmaf(dp, dx * dy, ag[GQB]);
+                            ag[GQC] = fmaf(dp, dy * dy, ag[GQC]);
+                            ag[GX] = fmaf(-dp, fmaf(2.f * a.z, dx, a.w * dy), ag[GX]);
+                            ag[GY] = fmaf(-dp, fmaf(a.w, dx, 2.f * c.x * dy), ag[GY]);
+                        }
+                        hit = true;
+                        T[j] = Tn;
+                    }
                 }
-                const float w = al * T[j];
-                P0[j] = fmaf(w, c.z, P0[j]);
-                P1[j] = fmaf(w, c.w, P1[j]);
-                P2[j] = fmaf(w, cb, P2[j]);
-                // colour behind this Gaussian, background included
-                const float b0 = o0[j] - P0[j], b1 = o1[j] - P1[j], b2 = o2[j] - P2[j];
-                const float gc = g0[j] * c.z + g1[j] * c.w + g2[j] * cb;
-                const float gb = g0[j] * b0 + g1[j] * b1 + g2[j] * b2;
-                const float inv = __builtin_amdgcn_rcpf(1.f - al);
-                const float dLda = T[j] * gc - (gb - gA[j] * Tf[j]) * inv;
-                ar = fmaf(w, g0[j], ar);
-                ag = fmaf(w, g1[j], ag);
-                ab = fmaf(w, g2[j], ab);
-                if (raw <= k.alpha_max) {
-                    ao = fmaf(dLda, G, ao);
-                    const float dp = dLda * raw * kLn2;
-                    aqa = fmaf(dp, dx * dx, aqa);
-                    aqb = fmaf(dp, dx * dy, aqb);
-                    aqc = fmaf(dp, dy * dy, aqc);
-                    ax = fmaf(-dp, fmaf(2.f * a.z, dx, a.w * dy), ax);
-                    ay = fmaf(-dp, fmaf(a.w, dx, 2.f * c.x * dy), ay);
-                }
-                hit = true;
-                T[j] = Tn;
             }
             if (__ballot(hit)) {
-                const float sx = wave_sum_to_lane63(ax);
-                const float sy = wave_sum_to_lane63(ay);
-                const float sqa = wave_sum_to_lane63(aqa);
-                const float sqb = wave_sum_to_lane63(aqb);
-                const float sqc = wave_sum_to_lane63(aqc);
-                const float so = wave_sum_to_lane63(ao);
-                const float sr = wave_sum_to_lane63(ar);
-                const float sg = wave_sum_to_lane63(ag);
-                const float sb = wave_sum_to_lane63(ab);
-                if (lane_id() == 63) {
-                    const size_t r = sid[i];
-                    atomicAdd(&grec[GX * n_rec + r], sx);
-                    atomicAdd(&grec[GY * n_rec + r], sy);
-                    atomicAdd(&grec[GQA * n_rec + r], sqa);
-                    atomicAdd(&grec[GQB * n_rec + r], sqb);
-                    atomicAdd(&grec[GQC * n_rec + r], sqc);
-                    atomicAdd(&grec[GO * n_rec + r], so);
-                    atomicAdd(&grec[GCR * n_rec + r], sr);
-                    atomicAdd(&grec[GCG * n_rec + r], sg);
-                    atomicAdd(&grec[GCB * n_rec + r], sb);
-                }
+                const float tot = reduce_scatter32(acc);
+                if (my_slot && i0 + my_g < cnt && tot != 0.f)
+                    atomicAdd(&grec[(size_t)my_v * n_rec + sid[i0 + my_g]], tot);
             }
             mine = false;
 #pragma unroll
@@ -296,49 +322,138 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_bwd(Consts k, const fl
     }
 }
 
+template <int PX>
+__global__ __launch_bounds__(kTilePix / PX) void k_render_bwd(Consts k, const float4 *__restrict__ rec,
+                                                             const uint32_t *__restrict__ starts,
+                                                             const uint32_t *__restrict__ sorted, int64_t n_tiles,
+                                                             const float *__restrict__ rgba,
+                                                             const float *__restrict__ dl, float *__restrict__ grec,
+                                                             int64_t n_rec) {
+    if (starts[n_tiles] == 0xFFFFFFFFu) return;
+    bwd_tile<PX>(k, rec, starts, sorted, rgba, dl, grec, n_rec, blockIdx.x);
+}
+
+template <int PX>
+__global__ __launch_bounds__(kTilePix / PX) void k_render_bwd_persistent(
+    Consts k, const float4 *__restrict__ rec, const uint32_t *__restrict__ starts,
+    const uint32_t *__restrict__ sorted, int64_t n_tiles, const float *__restrict__ rgba,
+    const float *__restrict__ dl, float *__restrict__ grec, int64_t n_rec, uint32_t *__restrict__ queue) {
+    if (starts[n_tiles] == 0xFFFFFFFFu) return;
+    const uint32_t n_items = queue[1];
+    uint32_t item;
+    while (next_item(queue, n_items, item)) bwd_tile<PX>(k, rec, starts, sorted, rgba, dl, grec, n_rec, queue[2 + item]);
+}
+
 // ----------------------------------------------------------------------------
 template <int PX>
 static void fwd_variant(bool maxw, bool count, dim3 grid, hipStream_t s, const Consts &k, const float4 *rec,
                         const uint32_t *starts, const uint32_t *sorted, int64_t n_tiles, float *out, float *mw,
-                        int64_t *status) {
+                        int64_t *status, uint32_t *queue) {
     constexpr int NT = kTilePix / PX;
-    if (maxw && count)
-        hipLaunchKernelGGL((k_render_fwd<PX, true, true>), grid, dim3(NT), 0, s, k, rec, starts, sorted, n_tiles, out, mw, status);
-    else if (maxw)
-        hipLaunchKernelGGL((k_render_fwd<PX, true, false>), grid, dim3(NT), 0, s, k, rec, starts, sorted, n_tiles, out, mw, status);
-    else if (count)
-        hipLaunchKernelGGL((k_render_fwd<PX, false, true>), grid, dim3(NT), 0, s, k, rec, starts, sorted, n_tiles, out, mw, status);
-    else
-        hipLaunchKernelGGL((k_render_fwd<PX, false, false>), grid, dim3(NT), 0, s, k, rec, starts, sorted, n_tiles, out, mw, status);
+    if (queue) {
+#define IVRGS_FWD_P(M, C)                                                                                          \
+    hipLaunchKernelGGL((k_render_fwd_persistent<PX, M, C>), grid, dim3(NT), 0, s, k, rec, starts, sorted, n_tiles, \
+                       out, mw, status, queue)
+        if (maxw && count) IVRGS_FWD_P(true, true);
+        else if (maxw) IVRGS_FWD_P(true, false);
+        else if (count) IVRGS_FWD_P(false, true);
+        else IVRGS_FWD_P(false, false);
+#undef IVRGS_FWD_P
+        return;
+    }
+#define IVRGS_FWD(M, C) \
+    hipLaunchKernelGGL((k_render_fwd<PX, M, C>), grid, dim3(NT), 0, s, k, rec, starts, sorted, n_tiles, out, mw, status)
+    if (maxw && count) IVRGS_FWD(true, true);
+    else if (maxw) IVRGS_FWD(true, false);
+    else if (count) IVRGS_FWD(false, true);
+    else IVRGS_FWD(false, false);
+#undef IVRGS_FWD
+}
+
+// Workgroups per CU that the persistent variants keep resident.
+template <typename K>
+static int resident_blocks(K kernel, int threads) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess || nb < 1) nb = 1;
+    return nb;
+}
+
+static int cu_count() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+    }
+    return cus;
+}
+
+template <int PX>
+static dim3 persistent_grid_fwd(bool maxw, bool count, int per_cu) {
+    constexpr int NT = kTilePix / PX;
+    static int occ[4] = {0, 0, 0, 0};  // per (maxw, count) variant, queried once
+    const int v = (maxw ? 2 : 0) + (count ? 1 : 0);
+    if (occ[v] == 0) {
+        if (maxw && count) occ[v] = resident_blocks(k_render_fwd_persistent<PX, true, true>, NT);
+        else if (maxw) occ[v] = resident_blocks(k_render_fwd_persistent<PX, true, false>, NT);
+        else if (count) occ[v] = resident_blocks(k_render_fwd_persistent<PX, false, true>, NT);
+        else occ[v] = resident_blocks(k_render_fwd_persistent<PX, false, false>, NT);
+    }
+    const int nb = per_cu > 0 ? per_cu : occ[v];
+    return dim3((unsigned)(nb * cu_count()));
 }
 
 hipError_t launch_render_fwd(const Consts &k, int px, int64_t n_tiles, const float *rec, const uint32_t *starts,
                              const uint32_t *sorted, float *out, float *maxw, int64_t *status, bool count,
-                             hipStream_t s) {
+                             uint32_t *queue, int per_cu, hipStream_t s) {
     if (n_tiles == 0) return hipSuccess;
-    dim3 grid((unsigned)n_tiles);
     const float4 *r4 = reinterpret_cast<const float4 *>(rec);
     const bool mw = maxw != nullptr;
+    if (queue) {
+        hipError_t e = launch_fill_u32(queue, 1, 0u, s);  // reset the work counter
+        if (e != hipSuccess) return e;
+    }
     TimedScope ts(TK_FWD, s);
     switch (px) {
-    case 1: fwd_variant<1>(mw, count, grid, s, k, r4, starts, sorted, n_tiles, out, maxw, status); break;
-    case 2: fwd_variant<2>(mw, count, grid, s, k, r4, starts, sorted, n_tiles, out, maxw, status); break;
-    default: fwd_variant<4>(mw, count, grid, s, k, r4, starts, sorted, n_tiles, out, maxw, status); break;
+    case 1: fwd_variant<1>(mw, count, queue ? persistent_grid_fwd<1>(mw, count, per_cu) : dim3((unsigned)n_tiles), s, k, r4, starts, sorted, n_tiles, out, maxw, status, queue); break;
+    case 2: fwd_variant<2>(mw, count, queue ? persistent_grid_fwd<2>(mw, count, per_cu) : dim3((unsigned)n_tiles), s, k, r4, starts, sorted, n_tiles, out, maxw, status, queue); break;
+    default: fwd_variant<4>(mw, count, queue ? persistent_grid_fwd<4>(mw, count, per_cu) : dim3((unsigned)n_tiles), s, k, r4, starts, sorted, n_tiles, out, maxw, status, queue); break;
     }
     return hipGetLastError();
 }
 
+template <int PX>
+static void bwd_variant(hipStream_t s, const Consts &k, const float4 *rec, const uint32_t *starts,
+                        const uint32_t *sorted, int64_t n_tiles, const float *rgba, const float *dl, float *grec,
+                        int64_t n_rec, uint32_t *queue, int per_cu) {
+    constexpr int NT = kTilePix / PX;
+    if (queue) {
+        static int occ = 0;  // queried once
+        if (occ == 0) occ = resident_blocks(k_render_bwd_persistent<PX>, NT);
+        const int nb = per_cu > 0 ? per_cu : occ;
+        hipLaunchKernelGGL(k_render_bwd_persistent<PX>, dim3((unsigned)(nb * cu_count())), dim3(NT), 0, s, k, rec,
+                           starts, sorted, n_tiles, rgba, dl, grec, n_rec, queue);
+    } else {
+        hipLaunchKernelGGL(k_render_bwd<PX>, dim3((unsigned)n_tiles), dim3(NT), 0, s, k, rec, starts, sorted, n_tiles,
+                           rgba, dl, grec, n_rec);
+    }
+}
+
 hipError_t launch_render_bwd(const Consts &k, int px, int64_t n_tiles, const float *rec, const uint32_t *starts,
                              const uint32_t *sorted, const float *rgba, const float *dl, float *grec,
-                             int64_t n_rec, hipStream_t s) {
+                             int64_t n_rec, uint32_t *queue, int per_cu, hipStream_t s) {
     if (n_tiles == 0) return hipSuccess;
-    dim3 grid((unsigned)n_tiles);
     const float4 *r4 = reinterpret_cast<const float4 *>(rec);
+    if (queue) {
+        hipError_t e = launch_fill_u32(queue, 1, 0u, s);
+        if (e != hipSuccess) return e;
+    }
     TimedScope ts(TK_BWD, s);
     switch (px) {
-    case 1: hipLaunchKernelGGL(k_render_bwd<1>, grid, dim3(256), 0, s, k, r4, starts, sorted, n_tiles, rgba, dl, grec, n_rec); break;
-    case 2: hipLaunchKernelGGL(k_render_bwd<2>, grid, dim3(128), 0, s, k, r4, starts, sorted, n_tiles, rgba, dl, grec, n_rec); break;
-    default: hipLaunchKernelGGL(k_render_bwd<4>, grid, dim3(64), 0, s, k, r4, starts, sorted, n_tiles, rgba, dl, grec, n_rec); break;
+    case 1: bwd_variant<1>(s, k, r4, starts, sorted, n_tiles, rgba, dl, grec, n_rec, queue, per_cu); break;
+    case 2: bwd_variant<2>(s, k, r4, starts, sorted, n_tiles, rgba, dl, grec, n_rec, queue, per_cu); break;
+    default: bwd_variant<4>(s, k, r4, starts, sorted, n_tiles, rgba, dl, grec, n_rec, queue, per_cu); break;
     }
     return hipGetLastError();
 }

@@ -20,9 +20,10 @@ FLAG_PERSISTENT = 1
 FLAG_COUNT_EVAL = 2
 EXPORTS = ("ivrgs_workspace_size", "ivrgs_tiles_per_job", "ivrgs_compose", "ivrgs_project",
            "ivrgs_bin_sort", "ivrgs_render_fwd", "ivrgs_render_bwd", "ivrgs_struct_size",
-           "ivrgs_status_string", "ivrgs_timing_enable", "ivrgs_timing_read")
+           "ivrgs_status_string", "ivrgs_timing_enable", "ivrgs_timing_read",
+           "ivrgs_cull_workspace_size", "ivrgs_cull")
 TIMING_KINDS = ("project", "tile_count", "scatter", "tile_sort", "render_fwd", "render_bwd",
-                "project_bwd", "compose", "fill")
+                "project_bwd", "compose", "fill", "cull")
 
 
 class ivrgs_gaussians(C.Structure):
@@ -59,7 +60,7 @@ class ivrgs_params(C.Structure):
                 ("lowpass", C.c_float), ("z_near", C.c_float), ("bg", C.c_float * 3),
                 ("width", C.c_int32), ("height", C.c_int32), ("tile", C.c_int32),
                 ("flags", C.c_uint32), ("fwd_px", C.c_int32), ("bwd_px", C.c_int32),
-                ("sort_chunk", C.c_int32), ("reserved", C.c_int32)]
+                ("sort_chunk", C.c_int32), ("persist_per_cu", C.c_int32)]
 
 
 class ivrgs_projected(C.Structure):
@@ -71,8 +72,13 @@ class ivrgs_bins(C.Structure):
                 ("status", C.c_void_p)]
 
 
+class ivrgs_culler(C.Structure):
+    _fields_ = [("w1", C.c_void_p), ("b1", C.c_void_p), ("w2", C.c_void_p), ("b2", C.c_void_p),
+                ("w3", C.c_void_p), ("b3", C.c_float), ("threshold", C.c_float)]
+
+
 STRUCTS = (ivrgs_gaussians, ivrgs_camera, ivrgs_model_edit, ivrgs_job, ivrgs_batch,
-           ivrgs_params, ivrgs_projected, ivrgs_bins)
+           ivrgs_params, ivrgs_projected, ivrgs_bins, ivrgs_culler)
 
 _lib = None
 
@@ -107,6 +113,10 @@ def load(path: str = LIB_PATH):
     lib.ivrgs_struct_size.restype = C.c_int32
     lib.ivrgs_status_string.argtypes = [C.c_int]
     lib.ivrgs_status_string.restype = C.c_char_p
+    lib.ivrgs_cull_workspace_size.argtypes = [C.c_int64]
+    lib.ivrgs_cull_workspace_size.restype = C.c_size_t
+    lib.ivrgs_cull.argtypes = [P, P, C.c_int32, P, P, P, C.c_int32, P, P, C.c_size_t, P]
+    lib.ivrgs_cull.restype = C.c_int
     lib.ivrgs_timing_enable.argtypes = [C.c_int32]
     lib.ivrgs_timing_enable.restype = None
     lib.ivrgs_timing_read.argtypes = [P, P]
@@ -174,3 +184,13 @@ def ivrgs_timing_read() -> dict:
     n = np.zeros(len(TIMING_KINDS), np.int64)
     load().ivrgs_timing_read(ms.ctypes.data_as(C.c_void_p), n.ctypes.data_as(C.c_void_p))
     return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(TIMING_KINDS)}
+
+
+def ivrgs_cull_workspace_size(n: int) -> int:
+    return int(load().ivrgs_cull_workspace_size(C.c_int64(n)))
+
+
+def ivrgs_cull(g, cams_ptr, camera: int, mlp, out_index_ptr, jobs_ptr, job: int, logit_ptr, ws_ptr, ws_bytes,
+               stream):
+    check(load().ivrgs_cull(ref(g), cams_ptr, camera, ref(mlp), out_index_ptr, jobs_ptr, job, logit_ptr, ws_ptr,
+                            ws_bytes, stream), "ivrgs_cull")

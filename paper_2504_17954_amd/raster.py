@@ -66,6 +66,7 @@ class Settings:
     bwd_px: int = 0
     sort_chunk: int = 0
     flags: int = 0
+    persist_per_cu: int = 0
 
     def params(self) -> N.ivrgs_params:
         p = N.ivrgs_params()
@@ -74,6 +75,7 @@ class Settings:
         p.bg = (N.C.c_float * 3)(*self.bg)
         p.width, p.height, p.tile = self.width, self.height, 16
         p.flags, p.fwd_px, p.bwd_px, p.sort_chunk = self.flags, self.fwd_px, self.bwd_px, self.sort_chunk
+        p.persist_per_cu = self.persist_per_cu
         return p
 
 

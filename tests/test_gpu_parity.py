@@ -426,3 +426,15 @@ def test_c2_fullsize_sampled(dev, c2_planes, view):
     # untouched Gaussians get exactly zero
     for k in R.PLANES:
         assert np.all(g[k][:, ~touched] == 0), k
+
+
+@pytest.mark.parametrize("n", [4096, 4097, 9152, 9153, 18304, 18305])
+def test_bin_sort_size_class_boundaries(dev, n):
+    """List lengths at the boundaries of the sort's staging paths (both
+    buffers in LDS / list in LDS with global staging / all global)."""
+    say(f"bin_sort exact, {n} records on one tile")
+    rng = np.random.default_rng(n)
+    rects = np.tile(np.array([[0, 0, 1, 1]]), (n, 1))
+    z = (2.0 + rng.random(n) * 3.0).astype(np.float32)
+    z[::97] = np.float32(3.25)  # a run of exact ties
+    _bin_case(dev, 16, 16, rects, z)
