@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--bwd-px", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-culler", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB five times (counter calibration)")
@@ -219,7 +221,11 @@ def main():
     }
 
     if not args.no_secondary:
-        result["secondary"] = secondary_fwd(dev)
+        result["secondary"] = {"composed_forward": secondary_fwd(dev)}
+        if not args.no_batched:
+            result["secondary"]["batched"] = secondary_batched(dev)
+        if not args.no_culler:
+            result["secondary"]["culler"] = secondary_culler(dev)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(models, edits, cams, W, H, views[0], args.cpu_seconds)
@@ -265,6 +271,125 @@ def secondary_fwd(dev):
     log(f"composed forward: {dt / nv * 1e3:.3f} ms/view, {mpix:.1f} Mpix/s")
     return {"fwd_mpix_s": round(mpix, 2), "fwd_ms_per_view": round(dt / nv * 1e3, 4),
             "workload": f"compose-{len(w.models)}x{w.models[0].n}-{w.width}px-{nv}views-fwd"}
+
+
+def secondary_batched(dev):
+    """Batched training step: 4 basic models of 50k / 120k / 250k / 500k
+    Gaussians (nested shells) x 32 Fibonacci views at 800x800 = 128 jobs in
+    one launch sequence with persistent render kernels; launch shape chosen by
+    the autotuner; eager steps and replays of the captured graph."""
+    import torch
+    from paper_2504_17954_amd import autotune as A
+    from paper_2504_17954_amd import batch as B
+    from paper_2504_17954_amd import inputs as I
+    from paper_2504_17954_amd import raster as R
+    t0 = time.time()
+    w = I.c4()
+    log(f"batched scene generated ({time.time() - t0:.1f}s)")
+    sizes = [m.n for m in w.models]
+    planes = {k: torch.from_numpy(np.concatenate([I.plain_planes(m)[k] for m in w.models], 1)).to(dev)
+              for k in R.PLANES}
+    cams_t = R.camera_table(w.cameras, dev)
+    jobs = R.Jobs.models_by_views(sizes, len(w.cameras))
+    g = torch.Generator(device=dev)
+    g.manual_seed(I.SEED_TARGET + 4)
+    targets = torch.rand((jobs.n_jobs, 4, w.height, w.width), generator=g, device=dev)
+    step = B.BatchStep(planes, cams_t, jobs, targets, B.batch_settings(w.width, w.height))
+    base = step.renderer.settings
+
+    def make(cfg):
+        def run():
+            step.renderer.settings = A.apply(base, cfg)
+            step.step()
+        return run
+    best, times = A.tune(make, w.width, w.height, jobs.n_jobs, jobs.n_records, reps=3, use_cache=False)
+    step.renderer.settings = A.apply(base, best)
+    log(f"autotune (ms per candidate): {times} -> {best}")
+    for _ in range(2):
+        step.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        step.step()
+    torch.cuda.synchronize()
+    eager = (time.perf_counter() - t0) / reps
+    step.capture()
+    step.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        step.replay()
+    torch.cuda.synchronize()
+    graph = (time.perf_counter() - t0) / reps
+    pairs = step.verify()
+    log(f"batched: eager {eager * 1e3:.2f} ms/step, graph {graph * 1e3:.2f} ms/step, {pairs} pairs")
+    return {"workload": f"batched-{len(sizes)}models-{len(w.cameras)}views-{w.width}px-fwd+bwd",
+            "jobs": jobs.n_jobs, "records": jobs.n_records, "pairs": int(pairs),
+            "steps_s_eager": round(1.0 / eager, 3), "steps_s_graph": round(1.0 / graph, 3),
+            "images_s_graph": round(jobs.n_jobs / graph, 1), "launch_shape": best}
+
+
+def secondary_culler(dev):
+    """Learned culling on the 300k isosurface scene: labels from 200 random
+    training views (the rasterizer's max T*alpha >= 1/255), MLP training,
+    threshold calibrated for 99.9 % recall on training views, then 60
+    held-out views at 1024x1024: plain vs culled forward time and the PSNR of
+    culled against plain (the loss against ground truth it implies for a model
+    at the paper's best basic-scene PSNR, 36.44 dB)."""
+    import torch
+    from paper_2504_17954_amd import cull as CU
+    from paper_2504_17954_amd import inputs as I
+    from paper_2504_17954_amd import raster as R
+    t0 = time.time()
+    m = I.isosurface_model(300_000, I.SEED_SCENE + 2)
+    planes = {k: torch.from_numpy(v).to(dev) for k, v in I.plain_planes(m).items()}
+    train_c, test_c = I.c5_views()
+    W = H = train_c[0].width
+    tr_t, te_t = R.camera_table(train_c, dev), R.camera_table(test_c, dev)
+    n = m.n
+    labels = CU.collect_labels(planes, tr_t, W, H)
+    model, mean, std = CU.train(planes, tr_t, labels, steps=1500)
+    wts = CU.pack(model, mean, std)
+    culler = CU.Culler(wts, n)
+    recall = 0.999
+    wts.threshold = CU.calibrate_threshold(culler, planes, tr_t, labels, recall=recall, views=range(0, 200, 5))
+    log(f"culler trained ({time.time() - t0:.1f}s), visible fraction {labels.float().mean().item():.3f}, "
+        f"threshold {wts.threshold:.3f}")
+    plain = R.Renderer(R.Settings(W, H), capacity=1 << 24, check="sync")
+    culled = R.Renderer(R.Settings(W, H), capacity=1 << 24, check="sync")
+    edits = R.default_edits(dev)
+    views = list(range(len(test_c)))
+    jobs_p = [R.Jobs.single(n, camera=v) for v in views]
+    jobs_c = [R.Jobs.single(n, camera=v) for v in views]
+    ref = [plain.forward(planes, te_t, jobs_p[v], edits_t=edits).clone() for v in views]
+    got = [culler.render(culled, planes, te_t, jobs_c[v], v).clone() for v in views]
+    q = [min(CU.psnr(a[0], b[0]), 120.0) for a, b in zip(got, ref)]  # identical images: capped
+    kept = float(np.mean([int(j.device[0, 2].item()) for j in jobs_c])) / n
+    plain.check = culled.check = "defer"
+    out = torch.empty((1, 4, H, W), dtype=torch.float32, device=dev)
+
+    def timed(fn):
+        for v in views[:3]:
+            fn(v)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for v in views:
+            fn(v)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / len(views)
+    t_plain = timed(lambda v: plain.forward(planes, te_t, jobs_p[v], edits_t=edits, out=out))
+    t_cull = timed(lambda v: culler.render(culled, planes, te_t, jobs_c[v], v, out=out))
+    plain.verify()
+    culled.verify()
+    qmin = float(np.min(q))
+    log(f"culler: plain {t_plain * 1e3:.3f} ms, culled {t_cull * 1e3:.3f} ms, kept {kept:.3f}, "
+        f"PSNR mean {np.mean(q):.2f} min {qmin:.2f}")
+    return {"workload": f"cull-isosurface-{n}-{W}px-60views-fwd", "speedup": round(t_plain / t_cull, 3),
+            "plain_ms": round(t_plain * 1e3, 4), "culled_ms": round(t_cull * 1e3, 4),
+            "kept_fraction": round(kept, 4), "visible_fraction_train": round(labels.float().mean().item(), 4),
+            "psnr_mean_db": round(float(np.mean(q)), 2), "psnr_min_db": round(qmin, 2),
+            "loss_db_at_36.44": round(CU.loss_from_psnr(qmin), 4), "recall_target": recall}
 
 
 def cpu_baseline(models, edits, cams, W, H, view, seconds):

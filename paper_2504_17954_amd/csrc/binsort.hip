@@ -30,46 +30,6 @@ __device__ __forceinline__ void unpack_rect(uint2 rc, int &x0, int &y0, int &x1,
     y1 = rc.y >> 16;
 }
 
-// Whether tile (tx, ty) can hold a pixel where the record reaches
-// alpha >= alpha_min: the largest exponent qa dx^2 + qb dx dy + qc dy^2 over
-// the box of the tile's pixel centres (offsets from the mean) is compared with
-// the record's cutoff.  The exponent is a concave quadratic, so over a box
-// that misses the mean its maximum lies on an edge, where it is a 1D
-// quadratic maximised by clamping its vertex.  A small tolerance keeps the
-// test conservative against FP32 rounding of the per-pixel evaluation.  Both
-// binning passes call this with the same inputs, so they agree exactly.
-struct HitTest {
-    float mx, my, qa, qb, qc, cut, i2qa, i2qc, tol;
-};
-
-__device__ __forceinline__ HitTest make_hit_test(const float4 r0, const float4 r1, const float4 r2) {
-    HitTest h;
-    h.mx = r0.x;
-    h.my = r0.y;
-    h.qa = r0.z;
-    h.qb = r0.w;
-    h.qc = r1.x;
-    h.cut = r2.z;
-    h.i2qa = 0.5f / h.qa;
-    h.i2qc = 0.5f / h.qc;
-    h.tol = h.cut - 1.0e-3f * (1.f + fabsf(h.cut));
-    return h;
-}
-
-__device__ __forceinline__ bool tile_hit(const HitTest &h, int tx, int ty) {
-    const float x0 = (float)(tx * kTile) + 0.5f - h.mx, x1 = x0 + (float)(kTile - 1);
-    const float y0 = (float)(ty * kTile) + 0.5f - h.my, y1 = y0 + (float)(kTile - 1);
-    if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return true;
-    auto q = [&](float dx, float dy) { return fmaf(fmaf(h.qa, dx, h.qb * dy), dx, h.qc * dy * dy); };
-    // on the edge x = xe the exponent is maximal at dy = -qb xe / (2 qc), clamped
-    const float ya = fminf(fmaxf(-h.qb * x0 * h.i2qc, y0), y1);
-    const float yb = fminf(fmaxf(-h.qb * x1 * h.i2qc, y0), y1);
-    const float xa = fminf(fmaxf(-h.qb * y0 * h.i2qa, x0), x1);
-    const float xb = fminf(fmaxf(-h.qb * y1 * h.i2qa, x0), x1);
-    const float best = fmaxf(fmaxf(q(x0, ya), q(x1, yb)), fmaxf(q(xa, y0), q(xb, y1)));
-    return best >= h.tol;
-}
-
 // Pass 1 of the binning: per (job, chunk of records) the number of pairs each
 // tile receives, counted with LDS atomics and written into the count matrix
 // [job][tile][chunk].
@@ -94,7 +54,7 @@ __global__ __launch_bounds__(256) void k_chunk_count(ivrgs_batch b, Consts k, co
         const HitTest ht = make_hit_test(rec4[3 * r], rec4[3 * r + 1], rec4[3 * r + 2]);
         for (int y = y0; y < y1; ++y)
             for (int x = x0; x < x1; ++x)
-                if (tile_hit(ht, x, y)) atomicAdd(&cnt[y * tx_n + x], 1u);
+                if (box_hit(ht, x * kTile, y * kTile, kTile, kTile)) atomicAdd(&cnt[y * tx_n + x], 1u);
     }
     __syncthreads();
     uint32_t *col = counts + (int64_t)blockIdx.y * tpj * n_chunks + blockIdx.x;
@@ -205,7 +165,7 @@ __global__ __launch_bounds__(256) void k_scatter(ivrgs_batch b, Consts k, const 
         unpack_rect(rc, x0, y0, x1, y1);
         for (int y = y0; y < y1; ++y)
             for (int x = x0; x < x1; ++x) {
-                if (!tile_hit(ht, x, y)) continue;
+                if (!box_hit(ht, x * kTile, y * kTile, kTile, kTile)) continue;
                 const uint32_t slot = atomicAdd(&cur[y * tx_n + x], 1u);
                 keys[slot] = z;
                 vals[slot] = (uint32_t)r;

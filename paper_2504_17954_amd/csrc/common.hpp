@@ -59,6 +59,50 @@ __device__ __forceinline__ float splat_exponent(float qa, float qb, float qc, fl
     return fmaf(t, dx, u * dy);
 }
 
+// Whether a box of pixels can hold a pixel where a record reaches
+// alpha >= alpha_min: the largest exponent qa dx^2 + qb dx dy + qc dy^2 over
+// the box of pixel centres (offsets from the mean) is compared with the
+// record's cutoff.  The exponent is a concave quadratic, so over a box that
+// misses the mean its maximum lies on an edge, where it is a 1D quadratic
+// maximised by clamping its vertex.  The test is conservative against FP32
+// rounding: a relative margin on the cutoff plus a bound on the rounding of
+// the per-pixel evaluation (a few units in the last place of the largest
+// term magnitude |qa| X^2 + |qb| X Y + |qc| Y^2 over the box), so a box that
+// fails has no pixel whose evaluation would pass the cutoff.
+struct HitTest {
+    float mx, my, qa, qb, qc, i2qa, i2qc, tol;
+};
+
+__device__ __forceinline__ HitTest make_hit_test(const float4 r0, const float4 r1, const float4 r2) {
+    HitTest h;
+    h.mx = r0.x;
+    h.my = r0.y;
+    h.qa = r0.z;
+    h.qb = r0.w;
+    h.qc = r1.x;
+    h.i2qa = 0.5f / h.qa;
+    h.i2qc = 0.5f / h.qc;
+    h.tol = r2.z - 1.0e-3f * (1.f + fabsf(r2.z));
+    return h;
+}
+
+// Box of pixels [px0, px0 + w) x [py0, py0 + h).
+__device__ __forceinline__ bool box_hit(const HitTest &h, int px0, int py0, int w, int hgt) {
+    const float x0 = (float)px0 + 0.5f - h.mx, x1 = x0 + (float)(w - 1);
+    const float y0 = (float)py0 + 0.5f - h.my, y1 = y0 + (float)(hgt - 1);
+    if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return true;
+    auto q = [&](float dx, float dy) { return fmaf(fmaf(h.qa, dx, h.qb * dy), dx, h.qc * dy * dy); };
+    // on the edge x = xe the exponent is maximal at dy = -qb xe / (2 qc), clamped
+    const float ya = fminf(fmaxf(-h.qb * x0 * h.i2qc, y0), y1);
+    const float yb = fminf(fmaxf(-h.qb * x1 * h.i2qc, y0), y1);
+    const float xa = fminf(fmaxf(-h.qb * y0 * h.i2qa, x0), x1);
+    const float xb = fminf(fmaxf(-h.qb * y1 * h.i2qa, x0), x1);
+    const float best = fmaxf(fmaxf(q(x0, ya), q(x1, yb)), fmaxf(q(xa, y0), q(xb, y1)));
+    const float X = fmaxf(fabsf(x0), fabsf(x1)), Y = fmaxf(fabsf(y0), fabsf(y1));
+    const float mag = fmaf(fabsf(h.qa) * X, X, fmaf(fabsf(h.qb) * X, Y, fabsf(h.qc) * Y * Y));
+    return fmaf(1.0e-6f, mag, best) >= h.tol;
+}
+
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
 // Sum over the 64 lanes of a wave; the total lands in lane 63.  DPP row

@@ -39,6 +39,20 @@ __device__ __forceinline__ void pixel_of(const TileGeom &g, int j, int &x, int &
     y = g.ty * kTile + p / kTile;
 }
 
+// Which waves of the workgroup own pixels the record can reach.  With one
+// pixel per lane wave w owns rows 4w .. 4w+3 of the tile; with more pixels
+// per lane a wave's pixels are spread over the tile and every wave is marked.
+template <int PX>
+__device__ __forceinline__ uint32_t wave_mask(const TileGeom &tg, float4 r0, float4 r1, float4 r2) {
+    if (PX != 1) return 0xFu;
+    const HitTest h = make_hit_test(r0, r1, r2);
+    uint32_t m = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+        if (box_hit(h, tg.tx * kTile, tg.ty * kTile + 4 * w, kTile, 4)) m |= 1u << w;
+    return m;
+}
+
 __device__ __forceinline__ float wave_max_to_lane63(float v) {
     v = fmaxf(v, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false)));
     v = fmaxf(v, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, false)));
@@ -61,6 +75,7 @@ __device__ __forceinline__ void fwd_tile(const Consts &k, const float4 *__restri
     __shared__ float4 s0[NT], s1[NT];
     __shared__ float2 s2[NT];
     __shared__ uint32_t sid[NT];
+    __shared__ uint32_t smask[NT];  // bit w: the record can reach wave w's pixels
     const TileGeom tg = tile_geom(k, tile);
     const uint32_t start = starts[tile], end = starts[tile + 1];
 
@@ -85,16 +100,25 @@ __device__ __forceinline__ void fwd_tile(const Consts &k, const float4 *__restri
         const uint32_t idx = base + threadIdx.x;
         if (idx < end) {
             const uint32_t r = sorted[idx];
-            s0[threadIdx.x] = rec[3 * (size_t)r];
-            s1[threadIdx.x] = rec[3 * (size_t)r + 1];
-            const float4 r2 = rec[3 * (size_t)r + 2];
+            const float4 r0 = rec[3 * (size_t)r], r1 = rec[3 * (size_t)r + 1], r2 = rec[3 * (size_t)r + 2];
+            s0[threadIdx.x] = r0;
+            s1[threadIdx.x] = r1;
             s2[threadIdx.x] = make_float2(r2.x, r2.z);
             if (kMaxw) sid[threadIdx.x] = r;
+            smask[threadIdx.x] = wave_mask<PX>(tg, r0, r1, r2);
         }
         __syncthreads();
         const int cnt = min((uint32_t)NT, end - base);
+        const uint32_t my_bit = 1u << (threadIdx.x >> 6);
         for (int i = 0; i < cnt; ++i) {
             if (__ballot(mine) == 0ull) break;
+            if (!(__builtin_amdgcn_readfirstlane(smask[i]) & my_bit)) {  // wave-uniform
+                // the record cannot reach this wave's pixels; the evaluations
+                // the plain walk would make are still counted
+                if (kCount)
+                    for (int j = 0; j < PX; ++j) evaluated += alive[j] ? 1u : 0u;
+                continue;
+            }
             const float4 a = s0[i];
             const float4 c = s1[i];
             const float2 cc = s2[i];
@@ -198,6 +222,7 @@ __device__ __forceinline__ void bwd_tile(const Consts &k, const float4 *__restri
     __shared__ float4 s0[NT], s1[NT];
     __shared__ float2 s2[NT];
     __shared__ uint32_t sid[NT];
+    __shared__ uint32_t smask[NT];  // bit w: the record can reach wave w's pixels
     const TileGeom tg = tile_geom(k, tile);
     const uint32_t start = starts[tile], end = starts[tile + 1];
     const size_t plane = (size_t)k.width * k.height;
@@ -245,14 +270,16 @@ __device__ __forceinline__ void bwd_tile(const Consts &k, const float4 *__restri
         const uint32_t idx = base + threadIdx.x;
         if (idx < end) {
             const uint32_t r = sorted[idx];
-            s0[threadIdx.x] = rec[3 * (size_t)r];
-            s1[threadIdx.x] = rec[3 * (size_t)r + 1];
-            const float4 r2 = rec[3 * (size_t)r + 2];
+            const float4 r0 = rec[3 * (size_t)r], r1 = rec[3 * (size_t)r + 1], r2 = rec[3 * (size_t)r + 2];
+            s0[threadIdx.x] = r0;
+            s1[threadIdx.x] = r1;
             s2[threadIdx.x] = make_float2(r2.x, r2.z);
             sid[threadIdx.x] = r;
+            smask[threadIdx.x] = wave_mask<PX>(tg, r0, r1, r2);
         }
         __syncthreads();
         const int cnt = min((uint32_t)NT, end - base);
+        const uint32_t my_bit = 1u << (threadIdx.x >> 6);
         for (int i0 = 0; i0 < cnt; i0 += kGroup) {
             if (__ballot(mine) == 0ull) break;
             float acc[32];
@@ -261,7 +288,7 @@ __device__ __forceinline__ void bwd_tile(const Consts &k, const float4 *__restri
             bool hit = false;
 #pragma unroll
             for (int g = 0; g < kGroup; ++g) {
-                if (i0 + g < cnt) {  // wave-uniform
+                if (i0 + g < cnt && (__builtin_amdgcn_readfirstlane(smask[i0 + g]) & my_bit)) {  // wave-uniform
                     const int i = i0 + g;
                     const float4 a = s0[i];
                     const float4 c = s1[i];
