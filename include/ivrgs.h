@@ -205,9 +205,13 @@ ivrgs_status ivrgs_project(const ivrgs_batch *batch, const ivrgs_params *params,
                            ivrgs_projected *out, void *stream);
 
 /* Tile binning and depth sort ("sorted by depth", Sec. 3): for each job and
- * 16x16 tile, the list of records whose rect covers the tile, ordered by
- * (depth key, record id).  Writes bins->tile_start, bins->sorted and
- * bins->status.  If the pair total exceeds bins->capacity, status[1] gets
+ * 16x16 tile, the list of records whose rect covers the tile and whose
+ * footprint {alpha >= alpha_min} can reach one of the tile's pixel centres
+ * (a conservative test: the exponent's maximum over the tile's pixel box,
+ * with margins for FP32 rounding), ordered by (depth key, record id).
+ * Writes bins->tile_start, bins->sorted and bins->status.  Returns
+ * IVRGS_E_SHAPE if a job has more tiles than the per-tile counters that fit
+ * in one workgroup's LDS (about 37k tiles on a 160 KiB device).  If the pair total exceeds bins->capacity, status[1] gets
  * IVRGS_DEV_E_CAPACITY, status[0] the required count, and the lists are not
  * written (render calls then leave their outputs untouched). */
 ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params,

@@ -72,6 +72,7 @@ struct DeviceLimits {
     size_t max_lds = 65536;
     int sort_cap = 0;
     size_t sort_lds = 0;
+    size_t bin_lds = 0;  // dynamic LDS the binning kernels may take (per-tile counters)
 };
 std::mutex g_mu;
 DeviceLimits g_dev[64];
@@ -94,6 +95,11 @@ hipError_t device_limits(DeviceLimits &out) {
         d.sort_lds = sort_lds_bytes(d.sort_cap);
         if (d.sort_lds > 65536) {
             e = set_sort_lds_limit(d.sort_lds);
+            if (e != hipSuccess) return e;
+        }
+        d.bin_lds = d.max_lds - bin_static_lds_bytes();
+        if (d.bin_lds > 65536) {
+            e = set_bin_lds_limit(d.bin_lds);
             if (e != hipSuccess) return e;
         }
         d.ready = true;
@@ -227,7 +233,7 @@ ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params
     const Consts k = make_consts(*params);
     DeviceLimits dl;
     if (device_limits(dl) != hipSuccess) return IVRGS_E_HIP;
-    if (sizeof(uint32_t) * (size_t)k.tiles_per_job > dl.max_lds) return IVRGS_E_SHAPE;
+    if (sizeof(uint32_t) * (size_t)k.tiles_per_job > dl.bin_lds) return IVRGS_E_SHAPE;
     const Layout L = layout(*batch, *params, bins->capacity);
     if (!workspace || workspace_bytes < L.total) return IVRGS_E_CAPACITY;
     char *ws = static_cast<char *>(workspace);

@@ -30,6 +30,86 @@ __device__ __forceinline__ void unpack_rect(uint2 rc, int &x0, int &y0, int &x1,
     y1 = rc.y >> 16;
 }
 
+// Visits every (record, tile) pair of records [begin, end) of a job whose
+// tile the record's ellipse reaches.  The work of 64 consecutive records is
+// spread evenly over the lanes of one wave: the lanes scan the records' rect
+// areas, then take the flattened (record, tile) items 64 at a time and find
+// each item's record by binary search over the scanned offsets (a lane per
+// record would leave most lanes idle behind the largest rect of the wave).
+// f(record, tile x, tile y, depth key bits) is called once per hit pair; the
+// order of the calls is unspecified.
+constexpr int kBinWaves = 4;  // 256 threads per binning workgroup
+
+struct ExpandLds {
+    float4 h0[kBinWaves][64], h1[kBinWaves][64];  // hit tests of the wave's records
+    uint32_t off[kBinWaves][64];                  // exclusive prefix of rect areas
+    uint32_t org[kBinWaves][64];                  // rect origin, x0 | y0 << 16
+    uint32_t wid[kBinWaves][64];                  // rect width in tiles
+    uint32_t zb[kBinWaves][64];                   // depth key bits
+};
+
+// Orders a wave's LDS writes before its other lanes' reads.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename F>
+__device__ __forceinline__ void for_each_pair(const ivrgs_job &job, int begin, int end, const float4 *rec4,
+                                              const uint2 *rect, ExpandLds &L, F &&f) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int g0 = begin + wave * 64; g0 < end; g0 += kBinWaves * 64) {
+        const int l = g0 + lane;
+        uint32_t n = 0;
+        if (l < end) {
+            const int64_t r = (int64_t)job.rec_begin + l;
+            const uint2 rc = rect[r];
+            if (rc.x | rc.y) {
+                int x0, y0, x1, y1;
+                unpack_rect(rc, x0, y0, x1, y1);
+                n = (uint32_t)((x1 - x0) * (y1 - y0));
+                const float4 r2 = rec4[3 * r + 2];
+                const HitTest h = make_hit_test(rec4[3 * r], rec4[3 * r + 1], r2);
+                L.h0[wave][lane] = make_float4(h.mx, h.my, h.qa, h.qb);
+                L.h1[wave][lane] = make_float4(h.qc, h.i2qa, h.i2qc, h.tol);
+                L.org[wave][lane] = rc.x;
+                L.wid[wave][lane] = (uint32_t)(x1 - x0);
+                L.zb[wave][lane] = __float_as_uint(r2.y);
+            }
+        }
+        uint32_t incl = n;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t o = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += o;
+        }
+        L.off[wave][lane] = incl - n;
+        const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
+        wave_lds_sync();
+        for (uint32_t base = 0; base < total; base += 64) {
+            const uint32_t idx = base + lane;
+            if (idx < total) {
+                // the last record whose offset is <= idx; it has a nonempty rect
+                int j = 0;
+#pragma unroll
+                for (int step = 32; step > 0; step >>= 1)
+                    if (L.off[wave][j + step] <= idx) j += step;
+                const uint32_t t = idx - L.off[wave][j];
+                const uint32_t w = L.wid[wave][j];
+                const uint32_t dy = t / w, dx = t - dy * w;
+                const uint32_t o = L.org[wave][j];
+                const int x = (int)((o & 0xFFFFu) + dx), y = (int)((o >> 16) + dy);
+                const float4 a = L.h0[wave][j], c = L.h1[wave][j];
+                const HitTest h = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
+                if (box_hit(h, x * kTile, y * kTile, kTile, kTile))
+                    f((int64_t)job.rec_begin + g0 + j, x, y, L.zb[wave][j]);
+            }
+        }
+        wave_lds_sync();  // every lane is done with the tables before they are rewritten
+    }
+}
+
 // Pass 1 of the binning: per (job, chunk of records) the number of pairs each
 // tile receives, counted with LDS atomics and written into the count matrix
 // [job][tile][chunk].
@@ -44,18 +124,9 @@ __global__ __launch_bounds__(256) void k_chunk_count(ivrgs_batch b, Consts k, co
     const int tpj = k.tiles_per_job, tx_n = k.tiles_x;
     for (int t = threadIdx.x; t < tpj; t += blockDim.x) cnt[t] = 0;
     __syncthreads();
-    const float4 *rec4 = reinterpret_cast<const float4 *>(rec);
-    for (int l = begin + threadIdx.x; l < end; l += blockDim.x) {
-        const int64_t r = (int64_t)job.rec_begin + l;
-        const uint2 rc = rect[r];
-        if (rc.x == 0u && rc.y == 0u) continue;
-        int x0, y0, x1, y1;
-        unpack_rect(rc, x0, y0, x1, y1);
-        const HitTest ht = make_hit_test(rec4[3 * r], rec4[3 * r + 1], rec4[3 * r + 2]);
-        for (int y = y0; y < y1; ++y)
-            for (int x = x0; x < x1; ++x)
-                if (box_hit(ht, x * kTile, y * kTile, kTile, kTile)) atomicAdd(&cnt[y * tx_n + x], 1u);
-    }
+    __shared__ ExpandLds L;
+    for_each_pair(job, begin, end, reinterpret_cast<const float4 *>(rec), rect, L,
+                  [&](int64_t, int x, int y, uint32_t) { atomicAdd(&cnt[y * tx_n + x], 1u); });
     __syncthreads();
     uint32_t *col = counts + (int64_t)blockIdx.y * tpj * n_chunks + blockIdx.x;
     for (int t = threadIdx.x; t < tpj; t += blockDim.x) col[(int64_t)t * n_chunks] = cnt[t];
@@ -153,24 +224,13 @@ __global__ __launch_bounds__(256) void k_scatter(ivrgs_batch b, Consts k, const 
     const uint32_t *st = starts + (int64_t)blockIdx.y * tpj;
     for (int t = threadIdx.x; t < tpj; t += blockDim.x) cur[t] = st[t] + col[(int64_t)t * n_chunks];
     __syncthreads();
-    for (int l = begin + threadIdx.x; l < end; l += blockDim.x) {
-        const int64_t r = (int64_t)job.rec_begin + l;
-        const uint2 rc = rect[r];
-        if (rc.x == 0u && rc.y == 0u) continue;
-        const float4 *rec4 = reinterpret_cast<const float4 *>(rec);
-        const float4 r2 = rec4[3 * r + 2];
-        const HitTest ht = make_hit_test(rec4[3 * r], rec4[3 * r + 1], r2);
-        const uint32_t z = __float_as_uint(r2.y);
-        int x0, y0, x1, y1;
-        unpack_rect(rc, x0, y0, x1, y1);
-        for (int y = y0; y < y1; ++y)
-            for (int x = x0; x < x1; ++x) {
-                if (!box_hit(ht, x * kTile, y * kTile, kTile, kTile)) continue;
-                const uint32_t slot = atomicAdd(&cur[y * tx_n + x], 1u);
-                keys[slot] = z;
-                vals[slot] = (uint32_t)r;
-            }
-    }
+    __shared__ ExpandLds L;
+    for_each_pair(job, begin, end, reinterpret_cast<const float4 *>(rec), rect, L,
+                  [&](int64_t r, int x, int y, uint32_t z) {
+                      const uint32_t slot = atomicAdd(&cur[y * tx_n + x], 1u);
+                      keys[slot] = z;
+                      vals[slot] = (uint32_t)r;
+                  });
 }
 
 // ---------------------------------------------------------------------------
@@ -476,6 +536,17 @@ hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *r
                            s, bins.tile_start, n_tiles, w.keys, bins.sorted, w.keys2, w.vals2, lds_cap);
     }
     return hipGetLastError();
+}
+
+// Static LDS of the binning kernels (their per-tile counters are dynamic).
+size_t bin_static_lds_bytes() { return sizeof(ExpandLds); }
+
+hipError_t set_bin_lds_limit(size_t bytes) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_chunk_count),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_scatter), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
 }
 
 // LDS bytes of the big-list sort for a staging capacity (elements).

@@ -80,8 +80,8 @@ __device__ __forceinline__ HitTest make_hit_test(const float4 r0, const float4 r
     h.qa = r0.z;
     h.qb = r0.w;
     h.qc = r1.x;
-    h.i2qa = 0.5f / h.qa;
-    h.i2qc = 0.5f / h.qc;
+    h.i2qa = 0.5f * __builtin_amdgcn_rcpf(h.qa);  // locates a vertex; an error there is second order
+    h.i2qc = 0.5f * __builtin_amdgcn_rcpf(h.qc);
     h.tol = r2.z - 1.0e-3f * (1.f + fabsf(r2.z));
     return h;
 }

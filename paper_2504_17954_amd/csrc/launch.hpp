@@ -35,6 +35,8 @@ hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *r
 size_t sort_lds_bytes(int lds_cap);
 size_t small_sort_lds_bytes();
 hipError_t set_sort_lds_limit(size_t bytes);
+size_t bin_static_lds_bytes();
+hipError_t set_bin_lds_limit(size_t bytes);
 hipError_t launch_render_fwd(const Consts &k, int px, int64_t n_tiles, const float *rec, const uint32_t *starts,
                              const uint32_t *sorted, float *out, float *maxw, int64_t *status, bool count,
                              uint32_t *queue, int per_cu, hipStream_t s);

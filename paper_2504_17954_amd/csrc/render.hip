@@ -109,7 +109,7 @@ __device__ __forceinline__ void fwd_tile(const Consts &k, const float4 *__restri
         }
         __syncthreads();
         const int cnt = min((uint32_t)NT, end - base);
-        const uint32_t my_bit = 1u << (threadIdx.x >> 6);
+        const uint32_t my_bit = __builtin_amdgcn_readfirstlane(1u << (threadIdx.x >> 6));  // wave-uniform
         for (int i = 0; i < cnt; ++i) {
             if (__ballot(mine) == 0ull) break;
             if (!(__builtin_amdgcn_readfirstlane(smask[i]) & my_bit)) {  // wave-uniform
@@ -126,25 +126,27 @@ __device__ __forceinline__ void fwd_tile(const Consts &k, const float4 *__restri
             float wmax = 0.f;
 #pragma unroll
             for (int j = 0; j < PX; ++j) {
-                if (!alive[j]) continue;
-                if (kCount) ++evaluated;
+                if (kCount) evaluated += alive[j] ? 1u : 0u;
                 const float dx = px[j] - a.x, dy = py[j] - a.y;
                 const float p2 = splat_exponent(a.z, a.w, c.x, dx, dy);
-                if (p2 < cc.y) continue;  // implies alpha < alpha_min
+                // below the cutoff alpha < alpha_min is certain
+                const bool pass = alive[j] && p2 >= cc.y;
+                if (__ballot(pass) == 0ull) continue;  // wave-uniform
+                // branch-free from here: a lane that does not composite adds
+                // w = 0 times a finite colour, which leaves its sums unchanged
                 const float G = fast_exp2(p2);
                 const float al = fminf(k.alpha_max, c.y * G);
-                if (al < k.alpha_min) continue;
                 const float Tn = T[j] * (1.f - al);
-                if (Tn < k.T_min) {
-                    alive[j] = false;
-                    continue;
-                }
-                const float w = al * T[j];
+                const bool use = pass && al >= k.alpha_min;
+                const bool stop = use && Tn < k.T_min;
+                const bool comp = use && !stop;
+                const float w = comp ? al * T[j] : 0.f;
                 C0[j] = fmaf(w, c.z, C0[j]);
                 C1[j] = fmaf(w, c.w, C1[j]);
                 C2[j] = fmaf(w, cb, C2[j]);
-                T[j] = Tn;
-                if (kCount) ++composited;
+                T[j] = comp ? Tn : T[j];
+                alive[j] = alive[j] && !stop;
+                if (kCount) composited += comp ? 1u : 0u;
                 if (kMaxw) wmax = fmaxf(wmax, w);
             }
             if (kMaxw) {
@@ -279,37 +281,47 @@ __device__ __forceinline__ void bwd_tile(const Consts &k, const float4 *__restri
         }
         __syncthreads();
         const int cnt = min((uint32_t)NT, end - base);
-        const uint32_t my_bit = 1u << (threadIdx.x >> 6);
-        for (int i0 = 0; i0 < cnt; i0 += kGroup) {
+        const uint32_t my_bit = __builtin_amdgcn_readfirstlane(1u << (threadIdx.x >> 6));  // wave-uniform
+        // Records are taken in list order; the next kGroup records that
+        // composite somewhere in this wave fill the slots of one
+        // reduce-scatter, records that do not are passed over.
+        int i = 0;
+        while (i < cnt) {
             if (__ballot(mine) == 0ull) break;
             float acc[32];
 #pragma unroll
             for (int q = 0; q < 32; ++q) acc[q] = 0.f;
-            bool hit = false;
+            int slot[kGroup];
 #pragma unroll
             for (int g = 0; g < kGroup; ++g) {
-                if (i0 + g < cnt && (__builtin_amdgcn_readfirstlane(smask[i0 + g]) & my_bit)) {  // wave-uniform
-                    const int i = i0 + g;
-                    const float4 a = s0[i];
-                    const float4 c = s1[i];
-                    const float2 cc = s2[i];
+                slot[g] = -1;
+                while (i < cnt) {
+                    const int ii = i++;
+                    if (!(__builtin_amdgcn_readfirstlane(smask[ii]) & my_bit)) continue;  // wave-uniform
+                    const float4 a = s0[ii];
+                    const float4 c = s1[ii];
+                    const float2 cc = s2[ii];
                     const float cb = cc.x;
+                    bool hit = false;
 #pragma unroll
                     for (int j = 0; j < PX; ++j) {
-                        if (!alive[j]) continue;
                         const float dx = px[j] - a.x, dy = py[j] - a.y;
                         const float p2 = splat_exponent(a.z, a.w, c.x, dx, dy);
-                        if (p2 < cc.y) continue;  // implies alpha < alpha_min
+                        // below the cutoff alpha < alpha_min is certain
+                        const bool pass = alive[j] && p2 >= cc.y;
+                        if (__ballot(pass) == 0ull) continue;  // wave-uniform
+                        // branch-free from here, with the same arithmetic as
+                        // the forward: a lane that does not composite adds
+                        // zero-weight terms (all operands finite), so a slot
+                        // whose record composites nowhere stays zero
                         const float G = fast_exp2(p2);
                         const float raw = c.y * G;
                         const float al = fminf(k.alpha_max, raw);
-                        if (al < k.alpha_min) continue;
                         const float Tn = T[j] * (1.f - al);
-                        if (Tn < k.T_min) {
-                            alive[j] = false;
-                            continue;
-                        }
-                        const float w = al * T[j];
+                        const bool use = pass && al >= k.alpha_min;
+                        const bool stop = use && Tn < k.T_min;
+                        const bool comp = use && !stop;
+                        const float w = comp ? al * T[j] : 0.f;
                         P0[j] = fmaf(w, c.z, P0[j]);
                         P1[j] = fmaf(w, c.w, P1[j]);
                         P2[j] = fmaf(w, cb, P2[j]);
@@ -318,33 +330,39 @@ __device__ __forceinline__ void bwd_tile(const Consts &k, const float4 *__restri
                         const float gc = g0[j] * c.z + g1[j] * c.w + g2[j] * cb;
                         const float gb = g0[j] * b0 + g1[j] * b1 + g2[j] * b2;
                         const float inv = __builtin_amdgcn_rcpf(1.f - al);
-                        const float dLda = T[j] * gc - (gb - gA[j] * Tf[j]) * inv;
+                        const float dLda = comp ? T[j] * gc - (gb - gA[j] * Tf[j]) * inv : 0.f;
+                        // no gradient through alpha where the cap is active
+                        const float dLdo = raw <= k.alpha_max ? dLda : 0.f;
                         float *ag = acc + g * kGradRec;
                         ag[GCR] = fmaf(w, g0[j], ag[GCR]);
                         ag[GCG] = fmaf(w, g1[j], ag[GCG]);
                         ag[GCB] = fmaf(w, g2[j], ag[GCB]);
-                        if (raw <= k.alpha_max) {
-                            ag[GO] = fmaf(dLda, G, ag[GO]);
-                            const float dp = dLda * raw * kLn2;
-                            ag[GQA] = fmaf(dp, dx * dx, ag[GQA]);
-                            ag[GQB] = fmaf(dp, dx * dy, ag[GQB]);
-                            ag[GQC] = fmaf(dp, dy * dy, ag[GQC]);
-                            ag[GX] = fmaf(-dp, fmaf(2.f * a.z, dx, a.w * dy), ag[GX]);
-                            ag[GY] = fmaf(-dp, fmaf(a.w, dx, 2.f * c.x * dy), ag[GY]);
-                        }
-                        hit = true;
-                        T[j] = Tn;
+                        ag[GO] = fmaf(dLdo, G, ag[GO]);
+                        const float dp = dLdo * raw * kLn2;
+                        ag[GQA] = fmaf(dp, dx * dx, ag[GQA]);
+                        ag[GQB] = fmaf(dp, dx * dy, ag[GQB]);
+                        ag[GQC] = fmaf(dp, dy * dy, ag[GQC]);
+                        ag[GX] = fmaf(-dp, fmaf(2.f * a.z, dx, a.w * dy), ag[GX]);
+                        ag[GY] = fmaf(-dp, fmaf(a.w, dx, 2.f * c.x * dy), ag[GY]);
+                        hit = hit || comp;
+                        T[j] = comp ? Tn : T[j];
+                        alive[j] = alive[j] && !stop;
                     }
+                    mine = false;
+#pragma unroll
+                    for (int j = 0; j < PX; ++j) mine |= alive[j];
+                    const bool filled = __ballot(hit) != 0ull;
+                    if (filled) slot[g] = ii;
+                    if (__ballot(mine) == 0ull) i = cnt;  // every pixel of the wave is done
+                    if (filled) break;
                 }
             }
-            if (__ballot(hit)) {
+            if (slot[0] >= 0) {
                 const float tot = reduce_scatter32(acc);
-                if (my_slot && i0 + my_g < cnt && tot != 0.f)
-                    atomicAdd(&grec[(size_t)my_v * n_rec + sid[i0 + my_g]], tot);
+                const int mine_slot = my_g == 0 ? slot[0] : (my_g == 1 ? slot[1] : slot[2]);
+                if (my_slot && mine_slot >= 0 && tot != 0.f)
+                    atomicAdd(&grec[(size_t)my_v * n_rec + sid[mine_slot]], tot);
             }
-            mine = false;
-#pragma unroll
-            for (int j = 0; j < PX; ++j) mine |= alive[j];
         }
     }
 }

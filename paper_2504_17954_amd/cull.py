@@ -133,9 +133,11 @@ def pack(model: MLP, mean: torch.Tensor, std: torch.Tensor, threshold: float = 0
         b1 = model.l1.bias - (model.l1.weight * (mean / std)[None, :]).sum(1)
         w1 = torch.zeros((HIDDEN, 16), dtype=torch.float32, device=W1.device)
         w1[:, :N_FEAT] = W1
-        return CullWeights(to_bf16_bits(w1).contiguous(), b1.float().contiguous(),
-                           to_bf16_bits(model.l2.weight).contiguous(), model.l2.bias.float().contiguous(),
-                           model.l3.weight[0].float().contiguous(), float(model.l3.bias[0]), threshold)
+        # detached copies: the packed weights must not alias the parameters
+        return CullWeights(to_bf16_bits(w1).contiguous(), b1.detach().float().clone(),
+                           to_bf16_bits(model.l2.weight.detach()).contiguous(),
+                           model.l2.bias.detach().float().clone(),
+                           model.l3.weight[0].detach().float().clone(), float(model.l3.bias[0]), threshold)
 
 
 class Culler:
