@@ -40,6 +40,42 @@ BWD_FLOP_EVAL, BWD_FLOP_COMP = 13, 59
 SORT_BYTES_PAIR = 4 + 4 + 4 + 4 + 4       # scatter write key+id, sort read key+id, write id
 PROJECT_BYTES_G = 84 + 56                  # 21 planes read, record + rect written
 
+# HBM bytes per launch measured with hardware counters (FETCH_SIZE and
+# WRITE_SIZE, scaled by the same counters on a plain copy of known size),
+# valid only for the kernel source they were measured on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+KERNEL_SOURCES = {
+    "render_fwd": ["render.hip"], "render_bwd": ["render.hip"], "project": ["project.hip"],
+    "project_bwd": ["project.hip"], "compose": ["project.hip"], "tile_count": ["binsort.hip"],
+    "scatter": ["binsort.hip"], "depth_sort": ["binsort.hip"],
+}
+
+
+def source_digest(kernel: str) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2504_17954_amd", "csrc")
+    for f in KERNEL_SOURCES.get(kernel, []) + ["common.hpp", "launch.hpp"]:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """Bytes per launch from the committed counter summary, or None when the
+    kernel's source has changed since it was measured (or none exists)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                parts = line.split()
+                if len(parts) >= 3 and parts[0] == kernel and not line.startswith("#"):
+                    fields = dict(p.split("=", 1) for p in parts[1:] if "=" in p)
+                    if fields.get("source") == source_digest(kernel):
+                        return int(float(fields["bytes_per_launch"]))
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -199,9 +235,13 @@ def main():
     bound, amount, unit, peak = work[dominant]
     dur_s = avg[dominant][0] / 1e3
     achieved = amount / dur_s
+    traffic = measured_traffic(dominant)
     roofline = {"kernel": dominant, "bound": bound, "achieved": round(achieved, 3), "peak": peak,
-                "unit": unit, "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": unit, "frac": round(achieved / peak, 4), "traffic": traffic,
                 "avg_ms": round(avg[dominant][0], 4)}
+    if traffic is not None:
+        roofline["traffic_unit"] = "bytes per launch"
+        roofline["traffic_gbs"] = round(traffic / dur_s / 1e9, 1)
     if bound == "alu":
         roofline["frac_vs_packed_peak"] = round(achieved / FP32_VALU_PEAK_PACKED, 4)
 

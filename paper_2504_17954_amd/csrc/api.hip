@@ -164,7 +164,7 @@ Layout layout(const ivrgs_batch &b, const ivrgs_params &p, int64_t capacity) {
     L.counts = off;
     off += align_up(sizeof(uint32_t) * (size_t)b.n_jobs * chunk_rows(b, chunk_of(p)) * k.tiles_per_job);
     L.grec = off;
-    off += align_up(sizeof(float) * kGradRec * (size_t)b.n_records);
+    off += align_up(sizeof(float) * kGradStride * (size_t)b.n_records);
     L.queue = off;
     off += align_up(sizeof(uint32_t) * (size_t)(2 + (int64_t)b.n_jobs * k.tiles_per_job));
     L.total = off;
@@ -286,10 +286,10 @@ ivrgs_status ivrgs_render_bwd(const ivrgs_batch *batch, const ivrgs_params *para
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     float *grec = reinterpret_cast<float *>(static_cast<char *>(workspace) + L.grec);
     const int64_t n_tiles = (int64_t)batch->n_jobs * k.tiles_per_job;
-    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(grec), kGradRec * batch->n_records, 0u, s);
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(grec), kGradStride * batch->n_records, 0u, s);
     if (e == hipSuccess)
         e = launch_render_bwd(k, pick_px(params->bwd_px, 1), n_tiles, proj->rec, bins->tile_start, bins->sorted,
-                              out_rgba, dl_drgba, grec, batch->n_records,
+                              out_rgba, dl_drgba, grec,
                               (params->flags & IVRGS_FLAG_PERSISTENT)
                                   ? reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + L.queue)
                                   : nullptr,

@@ -12,6 +12,7 @@ constexpr int kTile = 16;             // tile edge in pixels
 constexpr int kTilePix = kTile * kTile;
 constexpr int kRecWords = 12;         // floats per projected record
 constexpr int kGradRec = 9;           // record-gradient components
+constexpr int kGradStride = 9;        // floats between the gradient rows of consecutive records
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
 

@@ -42,7 +42,7 @@ hipError_t launch_render_fwd(const Consts &k, int px, int64_t n_tiles, const flo
                              uint32_t *queue, int per_cu, hipStream_t s);
 hipError_t launch_render_bwd(const Consts &k, int px, int64_t n_tiles, const float *rec, const uint32_t *starts,
                              const uint32_t *sorted, const float *rgba, const float *dl, float *grec,
-                             int64_t n_rec, uint32_t *queue, int per_cu, hipStream_t s);
+                             uint32_t *queue, int per_cu, hipStream_t s);
 hipError_t launch_cull(const ivrgs_gaussians &g, const ivrgs_camera *cams, int camera, const ivrgs_culler &mlp,
                        int32_t *out_index, ivrgs_job *jobs, int job, float *logits, uint8_t *keep,
                        uint32_t *counts, hipStream_t s);

@@ -297,8 +297,7 @@ __global__ __launch_bounds__(256) void k_project(ivrgs_batch b, Consts k, float4
 // parameter gradients, by the chain rule through the forward above.
 template <bool kAtomic>
 __global__ __launch_bounds__(256) void k_project_bwd(ivrgs_batch b, Consts k, const uint2 *__restrict__ rect,
-                                                     const float *__restrict__ grec, int64_t n_rec,
-                                                     ivrgs_gaussians_mut out) {
+                                                     const float *__restrict__ grec, ivrgs_gaussians_mut out) {
     const ivrgs_job job = b.jobs[blockIdx.y];
     const int local = blockIdx.x * blockDim.x + threadIdx.x;
     if (local >= job.gauss_count) return;
@@ -307,7 +306,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(ivrgs_batch b, Consts k, co
     if (rc.x == 0u && rc.y == 0u) return;  // culled
     float gr[kGradRec];
 #pragma unroll
-    for (int i = 0; i < kGradRec; ++i) gr[i] = grec[i * n_rec + r];
+    for (int i = 0; i < kGradRec; ++i) gr[i] = grec[r * kGradStride + i];
     bool any = false;
 #pragma unroll
     for (int i = 0; i < kGradRec; ++i) any |= gr[i] != 0.f;
@@ -553,9 +552,9 @@ hipError_t launch_project_bwd(const ivrgs_batch &b, const Consts &k, const uint3
     const uint2 *rc = reinterpret_cast<const uint2 *>(rect);
     TimedScope ts(TK_PROJECT_BWD, s);
     if (atomic)
-        hipLaunchKernelGGL(k_project_bwd<true>, grid, dim3(256), 0, s, b, k, rc, grec, b.n_records, out);
+        hipLaunchKernelGGL(k_project_bwd<true>, grid, dim3(256), 0, s, b, k, rc, grec, out);
     else
-        hipLaunchKernelGGL(k_project_bwd<false>, grid, dim3(256), 0, s, b, k, rc, grec, b.n_records, out);
+        hipLaunchKernelGGL(k_project_bwd<false>, grid, dim3(256), 0, s, b, k, rc, grec, out);
     return hipGetLastError();
 }
 

@@ -1,19 +1,24 @@
 // Front-to-back compositing (forward) and its recompute-based backward.
 //
 // One workgroup per 16x16 tile; each lane owns PX pixels (PX = 1, 2, 4, so a
-// workgroup has 256/PX threads).  The tile's sorted list is consumed in
-// batches: every thread gathers one projected record into LDS, then all lanes
-// walk the batch reading the record by broadcast.  A workgroup-wide OR ends
-// the walk once every pixel has terminated; inside a batch a wave leaves as
-// soon as its own pixels are done.  Compositing is plain FP32 VALU work (not a
-// dense contraction), so no matrix cores are involved.
+// workgroup has 256/PX threads).  With one pixel per lane the forward runs
+// each wave on its own 16x4 strip: the wave gathers 64 records at a time into
+// registers, tests them against the strip, and composites only the records
+// that can reach it, broadcast lane by lane into scalar registers.  The
+// backward (and the forward with more pixels per lane) gathers each batch of
+// records into LDS for the whole workgroup and walks it by broadcast reads,
+// skipping per wave the records that cannot reach the wave's strip.  A
+// workgroup-wide OR ends the walk once every pixel has terminated.
+// Compositing is plain FP32 VALU work (not a dense contraction), so no matrix
+// cores are involved.
 //
 // The backward walks the same list front to back and recomputes alpha and T
 // with the same instruction sequence as the forward.  Nothing per pixel is
 // stored by the forward: the colour behind Gaussian i is out_rgb - P_i with
 // P_i the recomputed prefix sum, and T_final = 1 - A.  Per-Gaussian partial
-// gradients are summed over the wave with DPP and added to the record's
-// gradient with one atomic per value.
+// gradients of three Gaussians are summed over the wave with one
+// reduce-scatter and added to the records' gradients with one atomic per
+// value.
 #include "launch.hpp"
 
 namespace ivrgs {
@@ -180,6 +185,115 @@ __device__ __forceinline__ void fwd_tile(const Consts &k, const float4 *__restri
     }
 }
 
+// Forward of one tile with one pixel per lane, each wave on its own.  Wave
+// w owns the 16x4 strip of rows 4w .. 4w+3 and walks the tile's list 64
+// records at a time: every lane gathers one record into registers and tests
+// it against the strip (the conservative ellipse-box test of the binning),
+// a ballot gives the records that can reach the strip, and the wave visits
+// only those, in list order, broadcasting each record's fields from its
+// lane into scalar registers.  The next 64 records are loaded while the
+// current ones are composited.  No LDS and no workgroup barrier: a wave
+// stops as soon as its own 64 pixels are done.
+template <bool kMaxw, bool kCount>
+__device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__restrict__ rec,
+                                              const uint32_t *__restrict__ starts,
+                                              const uint32_t *__restrict__ sorted, float *__restrict__ out,
+                                              float *__restrict__ maxw, int64_t *__restrict__ status, int64_t tile) {
+    const TileGeom tg = tile_geom(k, tile);
+    const uint32_t start = starts[tile], end = starts[tile + 1];
+    const int lane = lane_id();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int sx = tg.tx * kTile, sy = tg.ty * kTile + 4 * wave;
+    const int x = sx + (lane & 15), y = sy + (lane >> 4);
+    bool alive = x < k.width && y < k.height;
+    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+    float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+    uint32_t stop_at = end;  // list position of this pixel's terminating record
+    uint32_t composited = 0;
+
+    float4 n0, n1, n2;
+    uint32_t nid = 0;
+    auto fetch = [&](uint32_t base) {
+        const uint32_t idx = base + lane;
+        if (idx < end) {
+            nid = sorted[idx];
+            n0 = rec[3 * (size_t)nid];
+            n1 = rec[3 * (size_t)nid + 1];
+            n2 = rec[3 * (size_t)nid + 2];
+        }
+    };
+    if (start < end) fetch(start);
+    for (uint32_t base = start; base < end; base += 64) {
+        if (__ballot(alive) == 0ull) break;
+        const float4 r0 = n0, r1 = n1, r2 = n2;
+        const uint32_t rid = nid;
+        bool touch = false;
+        if (base + lane < end) touch = box_hit(make_hit_test(r0, r1, r2), sx, sy, kTile, 4);
+        if (base + 64 < end) fetch(base + 64);
+        uint64_t m = __ballot(touch);
+        while (m) {
+            const int src = (int)__builtin_ctzll(m);
+            m &= m - 1;
+            const float mx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r0.x), src));
+            const float my = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r0.y), src));
+            const float qa = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r0.z), src));
+            const float qb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r0.w), src));
+            const float qc = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r1.x), src));
+            const float cut = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r2.z), src));
+            const float dx = px - mx, dy = py - my;
+            const float p2 = splat_exponent(qa, qb, qc, dx, dy);
+            // below the cutoff alpha < alpha_min is certain
+            const bool pass = alive && p2 >= cut;
+            if (__ballot(pass) == 0ull) continue;  // wave-uniform
+            const float o = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r1.y), src));
+            const float cr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r1.z), src));
+            const float cg = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r1.w), src));
+            const float cb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r2.x), src));
+            const float G = fast_exp2(p2);
+            const float al = fminf(k.alpha_max, o * G);
+            const float Tn = T * (1.f - al);
+            const bool use = pass && al >= k.alpha_min;
+            const bool stop = use && Tn < k.T_min;
+            const bool comp = use && !stop;
+            const float w = comp ? al * T : 0.f;
+            C0 = fmaf(w, cr, C0);
+            C1 = fmaf(w, cg, C1);
+            C2 = fmaf(w, cb, C2);
+            T = comp ? Tn : T;
+            if (kCount) {
+                composited += comp ? 1u : 0u;
+                if (stop) stop_at = base + (uint32_t)src;
+            }
+            alive = alive && !stop;
+            if (kMaxw) {
+                if (__ballot(w > 0.f)) {
+                    const float wm = wave_max_to_lane63(w);
+                    const uint32_t id = __builtin_amdgcn_readlane(rid, src);
+                    if (lane == 63) atomicMax(reinterpret_cast<int *>(&maxw[id]), __float_as_int(wm));
+                }
+            }
+            if (__ballot(alive) == 0ull) break;
+        }
+    }
+    if (x < k.width && y < k.height) {
+        const size_t plane = (size_t)k.width * k.height;
+        float *img = out + (size_t)tg.job * 4 * plane;
+        const size_t o = (size_t)y * k.width + x;
+        img[o] = C0 + T * k.bg0;
+        img[plane + o] = C1 + T * k.bg1;
+        img[2 * plane + o] = C2 + T * k.bg2;
+        img[3 * plane + o] = 1.f - T;
+        if (kCount) {
+            // every list entry up to and including the terminating one is an
+            // evaluation of the plain walk, skipped or not
+            const uint32_t ev = stop_at < end ? stop_at - start + 1u : end - start;
+            const uint64_t e = ev, c = composited;
+            atomicAdd(reinterpret_cast<unsigned long long *>(&status[2]), (unsigned long long)e);
+            atomicAdd(reinterpret_cast<unsigned long long *>(&status[3]), (unsigned long long)c);
+        }
+    }
+}
+
 template <int PX, bool kMaxw, bool kCount>
 __global__ __launch_bounds__(kTilePix / PX) void k_render_fwd(Consts k, const float4 *__restrict__ rec,
                                                              const uint32_t *__restrict__ starts,
@@ -187,7 +301,8 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_fwd(Consts k, const fl
                                                              float *__restrict__ out, float *__restrict__ maxw,
                                                              int64_t *__restrict__ status) {
     if (starts[n_tiles] == 0xFFFFFFFFu) return;
-    fwd_tile<PX, kMaxw, kCount>(k, rec, starts, sorted, out, maxw, status, blockIdx.x);
+    if constexpr (PX == 1) fwd_tile_wave<kMaxw, kCount>(k, rec, starts, sorted, out, maxw, status, blockIdx.x);
+    else fwd_tile<PX, kMaxw, kCount>(k, rec, starts, sorted, out, maxw, status, blockIdx.x);
 }
 
 // Persistent variant: a fixed grid pops tiles from queue[2 ..] (heaviest
@@ -209,8 +324,10 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_fwd_persistent(
     if (starts[n_tiles] == 0xFFFFFFFFu) return;
     const uint32_t n_items = queue[1];
     uint32_t item;
-    while (next_item(queue, n_items, item)) fwd_tile<PX, kMaxw, kCount>(k, rec, starts, sorted, out, maxw, status,
-                                                                          queue[2 + item]);
+    while (next_item(queue, n_items, item)) {
+        if constexpr (PX == 1) fwd_tile_wave<kMaxw, kCount>(k, rec, starts, sorted, out, maxw, status, queue[2 + item]);
+        else fwd_tile<PX, kMaxw, kCount>(k, rec, starts, sorted, out, maxw, status, queue[2 + item]);
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -219,7 +336,7 @@ template <int PX>
 __device__ __forceinline__ void bwd_tile(const Consts &k, const float4 *__restrict__ rec,
                                          const uint32_t *__restrict__ starts, const uint32_t *__restrict__ sorted,
                                          const float *__restrict__ rgba, const float *__restrict__ dl,
-                                         float *__restrict__ grec, int64_t n_rec, int64_t tile) {
+                                         float *__restrict__ grec, int64_t tile) {
     constexpr int NT = kTilePix / PX;
     __shared__ float4 s0[NT], s1[NT];
     __shared__ float2 s2[NT];
@@ -231,8 +348,10 @@ __device__ __forceinline__ void bwd_tile(const Consts &k, const float4 *__restri
     const float *img = rgba + (size_t)tg.job * 4 * plane;
     const float *gimg = dl + (size_t)tg.job * 4 * plane;
 
-    float px[PX], py[PX], T[PX], P0[PX], P1[PX], P2[PX];
-    float o0[PX], o1[PX], o2[PX], Tf[PX], g0[PX], g1[PX], g2[PX], gA[PX];
+    // Per pixel: the upstream colour gradient g, gA T_final, g . out, and the
+    // running g . P_i with P_i the composited prefix, so that g . (colour
+    // behind Gaussian i) = g . out - g . P_i needs no per-channel prefix.
+    float px[PX], py[PX], T[PX], gP[PX], go[PX], gATf[PX], g0[PX], g1[PX], g2[PX];
     bool alive[PX];
     // after the reduce-scatter, lane pair (2m, 2m+1) holds value m = g * 9 + v
     // of Gaussian g of the group; the even lane issues the atomic
@@ -248,20 +367,18 @@ __device__ __forceinline__ void bwd_tile(const Consts &k, const float4 *__restri
         px[j] = (float)x + 0.5f;
         py[j] = (float)y + 0.5f;
         T[j] = 1.f;
-        P0[j] = P1[j] = P2[j] = 0.f;
-        o0[j] = o1[j] = o2[j] = Tf[j] = g0[j] = g1[j] = g2[j] = gA[j] = 0.f;
+        gP[j] = go[j] = gATf[j] = g0[j] = g1[j] = g2[j] = 0.f;
         if (alive[j]) {
             const size_t o = (size_t)y * k.width + x;
-            o0[j] = img[o];
-            o1[j] = img[plane + o];
-            o2[j] = img[2 * plane + o];
-            Tf[j] = 1.f - img[3 * plane + o];
+            const float Tf = 1.f - img[3 * plane + o];
             g0[j] = gimg[o];
             g1[j] = gimg[plane + o];
             g2[j] = gimg[2 * plane + o];
-            gA[j] = gimg[3 * plane + o];
+            const float gA = gimg[3 * plane + o];
+            go[j] = fmaf(g2[j], img[2 * plane + o], fmaf(g1[j], img[plane + o], g0[j] * img[o]));
+            gATf[j] = gA * Tf;
             // a pixel with no upstream gradient contributes nothing
-            alive[j] = (g0[j] != 0.f) | (g1[j] != 0.f) | (g2[j] != 0.f) | (gA[j] != 0.f);
+            alive[j] = (g0[j] != 0.f) | (g1[j] != 0.f) | (g2[j] != 0.f) | (gA != 0.f);
         }
     }
     for (uint32_t base = start; base < end; base += NT) {
@@ -322,15 +439,12 @@ __device__ __forceinline__ void bwd_tile(const Consts &k, const float4 *__restri
                         const bool stop = use && Tn < k.T_min;
                         const bool comp = use && !stop;
                         const float w = comp ? al * T[j] : 0.f;
-                        P0[j] = fmaf(w, c.z, P0[j]);
-                        P1[j] = fmaf(w, c.w, P1[j]);
-                        P2[j] = fmaf(w, cb, P2[j]);
-                        // colour behind this Gaussian, background included
-                        const float b0 = o0[j] - P0[j], b1 = o1[j] - P1[j], b2 = o2[j] - P2[j];
-                        const float gc = g0[j] * c.z + g1[j] * c.w + g2[j] * cb;
-                        const float gb = g0[j] * b0 + g1[j] * b1 + g2[j] * b2;
+                        const float gc = fmaf(g2[j], cb, fmaf(g1[j], c.w, g0[j] * c.z));
+                        gP[j] = fmaf(w, gc, gP[j]);
+                        // g . (colour behind this Gaussian, background included)
+                        const float gb = go[j] - gP[j];
                         const float inv = __builtin_amdgcn_rcpf(1.f - al);
-                        const float dLda = comp ? T[j] * gc - (gb - gA[j] * Tf[j]) * inv : 0.f;
+                        const float dLda = comp ? T[j] * gc - (gb - gATf[j]) * inv : 0.f;
                         // no gradient through alpha where the cap is active
                         const float dLdo = raw <= k.alpha_max ? dLda : 0.f;
                         float *ag = acc + g * kGradRec;
@@ -361,7 +475,7 @@ __device__ __forceinline__ void bwd_tile(const Consts &k, const float4 *__restri
                 const float tot = reduce_scatter32(acc);
                 const int mine_slot = my_g == 0 ? slot[0] : (my_g == 1 ? slot[1] : slot[2]);
                 if (my_slot && mine_slot >= 0 && tot != 0.f)
-                    atomicAdd(&grec[(size_t)my_v * n_rec + sid[mine_slot]], tot);
+                    atomicAdd(&grec[(size_t)sid[mine_slot] * kGradStride + my_v], tot);
             }
         }
     }
@@ -372,21 +486,20 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_bwd(Consts k, const fl
                                                              const uint32_t *__restrict__ starts,
                                                              const uint32_t *__restrict__ sorted, int64_t n_tiles,
                                                              const float *__restrict__ rgba,
-                                                             const float *__restrict__ dl, float *__restrict__ grec,
-                                                             int64_t n_rec) {
+                                                             const float *__restrict__ dl, float *__restrict__ grec) {
     if (starts[n_tiles] == 0xFFFFFFFFu) return;
-    bwd_tile<PX>(k, rec, starts, sorted, rgba, dl, grec, n_rec, blockIdx.x);
+    bwd_tile<PX>(k, rec, starts, sorted, rgba, dl, grec, blockIdx.x);
 }
 
 template <int PX>
 __global__ __launch_bounds__(kTilePix / PX) void k_render_bwd_persistent(
     Consts k, const float4 *__restrict__ rec, const uint32_t *__restrict__ starts,
     const uint32_t *__restrict__ sorted, int64_t n_tiles, const float *__restrict__ rgba,
-    const float *__restrict__ dl, float *__restrict__ grec, int64_t n_rec, uint32_t *__restrict__ queue) {
+    const float *__restrict__ dl, float *__restrict__ grec, uint32_t *__restrict__ queue) {
     if (starts[n_tiles] == 0xFFFFFFFFu) return;
     const uint32_t n_items = queue[1];
     uint32_t item;
-    while (next_item(queue, n_items, item)) bwd_tile<PX>(k, rec, starts, sorted, rgba, dl, grec, n_rec, queue[2 + item]);
+    while (next_item(queue, n_items, item)) bwd_tile<PX>(k, rec, starts, sorted, rgba, dl, grec, queue[2 + item]);
 }
 
 // ----------------------------------------------------------------------------
@@ -471,23 +584,23 @@ hipError_t launch_render_fwd(const Consts &k, int px, int64_t n_tiles, const flo
 template <int PX>
 static void bwd_variant(hipStream_t s, const Consts &k, const float4 *rec, const uint32_t *starts,
                         const uint32_t *sorted, int64_t n_tiles, const float *rgba, const float *dl, float *grec,
-                        int64_t n_rec, uint32_t *queue, int per_cu) {
+                        uint32_t *queue, int per_cu) {
     constexpr int NT = kTilePix / PX;
     if (queue) {
         static int occ = 0;  // queried once
         if (occ == 0) occ = resident_blocks(k_render_bwd_persistent<PX>, NT);
         const int nb = per_cu > 0 ? per_cu : occ;
         hipLaunchKernelGGL(k_render_bwd_persistent<PX>, dim3((unsigned)(nb * cu_count())), dim3(NT), 0, s, k, rec,
-                           starts, sorted, n_tiles, rgba, dl, grec, n_rec, queue);
+                           starts, sorted, n_tiles, rgba, dl, grec, queue);
     } else {
         hipLaunchKernelGGL(k_render_bwd<PX>, dim3((unsigned)n_tiles), dim3(NT), 0, s, k, rec, starts, sorted, n_tiles,
-                           rgba, dl, grec, n_rec);
+                           rgba, dl, grec);
     }
 }
 
 hipError_t launch_render_bwd(const Consts &k, int px, int64_t n_tiles, const float *rec, const uint32_t *starts,
                              const uint32_t *sorted, const float *rgba, const float *dl, float *grec,
-                             int64_t n_rec, uint32_t *queue, int per_cu, hipStream_t s) {
+                             uint32_t *queue, int per_cu, hipStream_t s) {
     if (n_tiles == 0) return hipSuccess;
     const float4 *r4 = reinterpret_cast<const float4 *>(rec);
     if (queue) {
@@ -496,9 +609,9 @@ hipError_t launch_render_bwd(const Consts &k, int px, int64_t n_tiles, const flo
     }
     TimedScope ts(TK_BWD, s);
     switch (px) {
-    case 1: bwd_variant<1>(s, k, r4, starts, sorted, n_tiles, rgba, dl, grec, n_rec, queue, per_cu); break;
-    case 2: bwd_variant<2>(s, k, r4, starts, sorted, n_tiles, rgba, dl, grec, n_rec, queue, per_cu); break;
-    default: bwd_variant<4>(s, k, r4, starts, sorted, n_tiles, rgba, dl, grec, n_rec, queue, per_cu); break;
+    case 1: bwd_variant<1>(s, k, r4, starts, sorted, n_tiles, rgba, dl, grec, queue, per_cu); break;
+    case 2: bwd_variant<2>(s, k, r4, starts, sorted, n_tiles, rgba, dl, grec, queue, per_cu); break;
+    default: bwd_variant<4>(s, k, r4, starts, sorted, n_tiles, rgba, dl, grec, queue, per_cu); break;
     }
     return hipGetLastError();
 }
