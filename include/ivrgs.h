@@ -140,7 +140,7 @@ typedef struct {
     int32_t tile;
     uint32_t flags;
     int32_t fwd_px, bwd_px;
-    int32_t sort_chunk;              /* records per binning workgroup, 0 = default (1024) */
+    int32_t sort_chunk;              /* records per binning chunk (one wave), 0 = default (512) */
     int32_t persist_per_cu;          /* IVRGS_FLAG_PERSISTENT: workgroups per CU, 0 = occupancy */
 } ivrgs_params;
 
@@ -174,7 +174,11 @@ typedef struct {
 } ivrgs_bins;
 
 /* Bytes of workspace needed by ivrgs_bin_sort, ivrgs_render_fwd and
- * ivrgs_render_bwd for this batch and pair capacity. */
+ * ivrgs_render_bwd for this batch: the depth order (two words per record,
+ * twice), its digit histograms, the per-chunk tile counts, the record
+ * gradients (9 floats per record) and the work queue.  capacity (>= 0) is the
+ * pair capacity of the bins; the workspace does not depend on it.  Returns 0
+ * for invalid arguments. */
 size_t ivrgs_workspace_size(const ivrgs_batch *batch, const ivrgs_params *params,
                             int64_t capacity);
 
@@ -208,10 +212,14 @@ ivrgs_status ivrgs_project(const ivrgs_batch *batch, const ivrgs_params *params,
  * 16x16 tile, the list of records whose rect covers the tile and whose
  * footprint {alpha >= alpha_min} can reach one of the tile's pixel centres
  * (a conservative test: the exponent's maximum over the tile's pixel box,
- * with margins for FP32 rounding), ordered by (depth key, record id).
- * Writes bins->tile_start, bins->sorted and bins->status.  Returns
- * IVRGS_E_SHAPE if a job has more tiles than the per-tile counters that fit
- * in one workgroup's LDS (about 37k tiles on a 160 KiB device).  If the pair total exceeds bins->capacity, status[1] gets
+ * with margins for FP32 rounding), ordered by (depth key, record id).  The
+ * records are put in depth order first and binned in that order, so the
+ * lists need no sort of their own.  params->sort_chunk is the number of
+ * records per binning chunk (0: 512; rounded up to a multiple of 64); it
+ * does not change the result.  Writes bins->tile_start, bins->sorted and
+ * bins->status.  Returns IVRGS_E_SHAPE if a job has more tiles than the
+ * per-tile counters that fit in one workgroup's LDS (about 37k tiles on a
+ * 160 KiB device).  If the pair total exceeds bins->capacity, status[1] gets
  * IVRGS_DEV_E_CAPACITY, status[0] the required count, and the lists are not
  * written (render calls then leave their outputs untouched). */
 ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params,

@@ -17,13 +17,13 @@ import torch
 from . import native as N
 from . import raster as R
 
-DEFAULT = {"fwd_px": 1, "bwd_px": 1, "sort_chunk": 1024, "persistent": False, "persist_per_cu": 0}
+DEFAULT = {"fwd_px": 1, "bwd_px": 1, "sort_chunk": 512, "persistent": False, "persist_per_cu": 0}
 CANDIDATES = [
     dict(DEFAULT),
     {**DEFAULT, "fwd_px": 2},
     {**DEFAULT, "bwd_px": 2},
-    {**DEFAULT, "sort_chunk": 512},
-    {**DEFAULT, "sort_chunk": 2048},
+    {**DEFAULT, "sort_chunk": 256},
+    {**DEFAULT, "sort_chunk": 1024},
     {**DEFAULT, "persistent": True},
     {**DEFAULT, "persistent": True, "persist_per_cu": 4},
     {**DEFAULT, "persistent": True, "persist_per_cu": 8},

@@ -62,7 +62,7 @@ void timing_end(int kind, hipStream_t s) {
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kDefaultChunk = 1024;
+constexpr int kDefaultChunk = 512;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -70,8 +70,6 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct DeviceLimits {
     bool ready = false;
     size_t max_lds = 65536;
-    int sort_cap = 0;
-    size_t sort_lds = 0;
     size_t bin_lds = 0;  // dynamic LDS the binning kernels may take (per-tile counters)
 };
 std::mutex g_mu;
@@ -89,14 +87,6 @@ hipError_t device_limits(DeviceLimits &out) {
         e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
         if (e != hipSuccess) return e;
         d.max_lds = (size_t)lds;
-        // leave room for the histogram and the small static arrays
-        const size_t avail = d.max_lds - sort_lds_bytes(0) - 1024;
-        d.sort_cap = (int)(avail / 8 / 128 * 128);
-        d.sort_lds = sort_lds_bytes(d.sort_cap);
-        if (d.sort_lds > 65536) {
-            e = set_sort_lds_limit(d.sort_lds);
-            if (e != hipSuccess) return e;
-        }
         d.bin_lds = d.max_lds - bin_static_lds_bytes();
         if (d.bin_lds > 65536) {
             e = set_bin_lds_limit(d.bin_lds);
@@ -146,21 +136,32 @@ ivrgs_status check_batch(const ivrgs_batch *b) {
 
 // Workspace regions.
 struct Layout {
-    size_t keys, keys2, vals2, counts, grec, queue, total;
+    size_t key0, val0, key1, val1, hist, rng, counts, grec, queue, total;
 };
 
-int chunk_of(const ivrgs_params &p) { return p.sort_chunk > 0 ? p.sort_chunk : kDefaultChunk; }
+// Records per binning chunk: a multiple of 64 (one wave walks a chunk).
+int chunk_of(const ivrgs_params &p) {
+    const int c = p.sort_chunk > 0 ? p.sort_chunk : kDefaultChunk;
+    return (c + 63) / 64 * 64;
+}
 
-Layout layout(const ivrgs_batch &b, const ivrgs_params &p, int64_t capacity) {
+Layout layout(const ivrgs_batch &b, const ivrgs_params &p) {
     Layout L;
     const Consts k = make_consts(p);
+    const size_t rec_words = align_up(sizeof(uint32_t) * (size_t)b.n_records);
     size_t off = 0;
-    L.keys = off;
-    off += align_up(sizeof(uint32_t) * (size_t)capacity);
-    L.keys2 = off;
-    off += align_up(sizeof(uint32_t) * (size_t)capacity);
-    L.vals2 = off;
-    off += align_up(sizeof(uint32_t) * (size_t)capacity);
+    L.key0 = off;
+    off += rec_words;
+    L.val0 = off;
+    off += rec_words;
+    L.key1 = off;
+    off += rec_words;
+    L.val1 = off;
+    off += rec_words;
+    L.hist = off;
+    off += align_up(sizeof(uint32_t) * depth_sort_hist_words(b));
+    L.rng = off;
+    off += align_up(sizeof(uint32_t) * 2 * (size_t)b.n_jobs);
     L.counts = off;
     off += align_up(sizeof(uint32_t) * (size_t)b.n_jobs * chunk_rows(b, chunk_of(p)) * k.tiles_per_job);
     L.grec = off;
@@ -184,7 +185,7 @@ extern "C" {
 
 size_t ivrgs_workspace_size(const ivrgs_batch *batch, const ivrgs_params *params, int64_t capacity) {
     if (check_batch(batch) != IVRGS_OK || check_params(params) != IVRGS_OK || capacity < 0) return 0;
-    return layout(*batch, *params, capacity).total;
+    return layout(*batch, *params).total;
 }
 
 int32_t ivrgs_tiles_per_job(const ivrgs_params *params) {
@@ -234,17 +235,20 @@ ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params
     DeviceLimits dl;
     if (device_limits(dl) != hipSuccess) return IVRGS_E_HIP;
     if (sizeof(uint32_t) * (size_t)k.tiles_per_job > dl.bin_lds) return IVRGS_E_SHAPE;
-    const Layout L = layout(*batch, *params, bins->capacity);
+    const Layout L = layout(*batch, *params);
     if (!workspace || workspace_bytes < L.total) return IVRGS_E_CAPACITY;
     char *ws = static_cast<char *>(workspace);
     BinWork w;
-    w.keys = reinterpret_cast<uint32_t *>(ws + L.keys);
-    w.keys2 = reinterpret_cast<uint32_t *>(ws + L.keys2);
-    w.vals2 = reinterpret_cast<uint32_t *>(ws + L.vals2);
+    w.key[0] = reinterpret_cast<uint32_t *>(ws + L.key0);
+    w.val[0] = reinterpret_cast<uint32_t *>(ws + L.val0);
+    w.key[1] = reinterpret_cast<uint32_t *>(ws + L.key1);
+    w.val[1] = reinterpret_cast<uint32_t *>(ws + L.val1);
+    w.hist = reinterpret_cast<uint32_t *>(ws + L.hist);
+    w.rng = reinterpret_cast<uint32_t *>(ws + L.rng);
     w.counts = reinterpret_cast<uint32_t *>(ws + L.counts);
     const int chunk = chunk_of(*params);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipError_t e = launch_bin_sort(*batch, k, proj->rec, proj->rect, *bins, w, chunk, dl.sort_cap, dl.sort_lds, s);
+    hipError_t e = launch_bin_sort(*batch, k, proj->rec, proj->rect, *bins, w, chunk, dl.bin_lds, s);
     if (e == hipSuccess && (params->flags & IVRGS_FLAG_PERSISTENT))
         e = launch_work_queue(bins->tile_start, (int64_t)batch->n_jobs * k.tiles_per_job,
                               reinterpret_cast<uint32_t *>(ws + L.queue), s);
@@ -263,7 +267,7 @@ ivrgs_status ivrgs_render_fwd(const ivrgs_batch *batch, const ivrgs_params *para
     const bool count = (params->flags & IVRGS_FLAG_COUNT_EVAL) != 0;
     uint32_t *queue = nullptr;
     if (params->flags & IVRGS_FLAG_PERSISTENT) {
-        const Layout L = layout(*batch, *params, bins->capacity);
+        const Layout L = layout(*batch, *params);
         if (!workspace || workspace_bytes < L.total) return IVRGS_E_CAPACITY;
         queue = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + L.queue);
     }
@@ -281,7 +285,7 @@ ivrgs_status ivrgs_render_bwd(const ivrgs_batch *batch, const ivrgs_params *para
     if (!proj || !bins || !bins->tile_start || !out_rgba || !dl_drgba || !grads) return IVRGS_E_INVALID;
     if (!valid_gauss_mut(*grads) || grads->n != batch->g.n) return IVRGS_E_SHAPE;
     const Consts k = make_consts(*params);
-    const Layout L = layout(*batch, *params, bins->capacity);
+    const Layout L = layout(*batch, *params);
     if (!workspace || workspace_bytes < L.total) return IVRGS_E_CAPACITY;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     float *grec = reinterpret_cast<float *>(static_cast<char *>(workspace) + L.grec);

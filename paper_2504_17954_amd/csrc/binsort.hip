@@ -1,19 +1,21 @@
-// Tile binning and per-tile depth sort.
+// Tile binning in depth order.
 //
-// 1. Count: each workgroup owns a chunk of a job's records and counts, in LDS,
-//    the pairs each tile of the job receives from it; the counts form a
-//    [job][chunk][tile] matrix.
-// 2. A column scan over chunks gives every (chunk, tile) its offset inside
+// 1. Depth order: each job's records are sorted by (FP32 depth key bits,
+//    record id) with a segmented LSD radix sort: 8-bit digits, segments of
+//    4096 records per workgroup, every pass stable, the initial order by id.
+//    A digit that is constant over the job's visible records is skipped.
+// 2. Count: one wave per chunk of consecutive records of the depth order
+//    counts, in LDS, the pairs each tile of the job receives from it; the
+//    counts form a [job][tile][chunk] matrix.
+// 3. A column scan over chunks gives every (chunk, tile) its offset inside
 //    the tile's list and each tile its total; one exclusive scan over all
 //    (job, tile) totals gives the list starts, and the pair total is checked
 //    against the capacity on the device.
-// 3. Scatter: each chunk workgroup writes its (depth key, record id) pairs
-//    from per-tile LDS cursors; no global atomics.
-// 4. Per-tile stable LSD radix sort of the depth keys (8-bit digits, only the
-//    digits that vary inside the tile), in LDS when the tile fits, otherwise
-//    through global memory; equal keys are then ordered by record id, so the
-//    result is the unique (depth key, record id) order whatever order the
-//    scatter produced.
+// 4. Scatter: each chunk walks its records in depth order and appends every
+//    pair to its tile from a per-tile LDS cursor.  Lanes of one step that
+//    append to the same tile hold different records, in depth order by
+//    lane, and are ranked by lane, so each tile's list comes out in
+//    (depth key, record id) order: no per-tile sort.
 #include "launch.hpp"
 
 namespace ivrgs {
@@ -30,23 +32,259 @@ __device__ __forceinline__ void unpack_rect(uint2 rc, int &x0, int &y0, int &x1,
     y1 = rc.y >> 16;
 }
 
-// Visits every (record, tile) pair of records [begin, end) of a job whose
-// tile the record's ellipse reaches.  The work of 64 consecutive records is
-// spread evenly over the lanes of one wave: the lanes scan the records' rect
-// areas, then take the flattened (record, tile) items 64 at a time and find
-// each item's record by binary search over the scanned offsets (a lane per
-// record would leave most lanes idle behind the largest rect of the wave).
-// f(record, tile x, tile y, depth key bits) is called once per hit pair; the
-// order of the calls is unspecified.
-constexpr int kBinWaves = 4;  // 256 threads per binning workgroup
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
 
+// Active lanes whose value v (bits < nbits) equals this lane's.
+__device__ __forceinline__ uint64_t match_bits(uint32_t v, int nbits, uint64_t active) {
+    uint64_t m = active;
+    for (int bit = 0; bit < nbits; ++bit) {
+        const uint64_t bb = __ballot((v >> bit) & 1u);
+        m &= ((v >> bit) & 1u) ? bb : ~bb;
+    }
+    return m;
+}
+
+// ---------------------------------------------------------------------------
+// Depth order.
+constexpr int kSegThreads = 256;
+constexpr int kSegItems = 16;                         // per thread
+constexpr int kSeg = kSegThreads * kSegItems;         // records per segment
+constexpr int kSegWaveItems = kSeg / (kSegThreads / 64);  // contiguous per wave
+
+int seg_rows(const ivrgs_batch &b) { return (b.max_job_count + kSeg - 1) / kSeg; }
+
+__device__ __forceinline__ uint32_t depth_bits(const float *rec, int64_t r) {
+    return __float_as_uint(rec[12 * r + 9]);
+}
+
+// AND and OR of the depth keys of each job's visible records (rng[j] and
+// rng[n_jobs + j], preset to ~0 and 0).
+__global__ __launch_bounds__(kSegThreads) void k_dkey_range(ivrgs_batch b, const float *__restrict__ rec,
+                                                            const uint2 *__restrict__ rect,
+                                                            uint32_t *__restrict__ rng) {
+    const ivrgs_job job = b.jobs[blockIdx.y];
+    const int64_t base = (int64_t)blockIdx.x * kSeg;
+    if (base >= job.gauss_count) return;
+    uint32_t a = 0xFFFFFFFFu, o = 0u;
+    for (int i = threadIdx.x; i < kSeg && base + i < job.gauss_count; i += kSegThreads) {
+        const int64_t r = (int64_t)job.rec_begin + base + i;
+        const uint2 rc = rect[r];
+        if (rc.x | rc.y) {
+            const uint32_t z = depth_bits(rec, r);
+            a &= z;
+            o |= z;
+        }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        a &= __shfl_xor(a, d, 64);
+        o |= __shfl_xor(o, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAnd(&rng[blockIdx.y], a);
+        atomicOr(&rng[b.n_jobs + blockIdx.y], o);
+    }
+}
+
+// Initial (key, id) arrays in id order; a culled record takes the AND of the
+// visible keys, so it adds no varying bit (it is never binned).
+__global__ __launch_bounds__(kSegThreads) void k_dkey_init(ivrgs_batch b, const float *__restrict__ rec,
+                                                           const uint2 *__restrict__ rect,
+                                                           const uint32_t *__restrict__ rng,
+                                                           uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
+    const ivrgs_job job = b.jobs[blockIdx.y];
+    const int64_t base = (int64_t)blockIdx.x * kSeg;
+    if (base >= job.gauss_count) return;
+    const uint32_t fill = rng[blockIdx.y];
+    for (int i = threadIdx.x; i < kSeg && base + i < job.gauss_count; i += kSegThreads) {
+        const int64_t r = (int64_t)job.rec_begin + base + i;
+        const uint2 rc = rect[r];
+        key[r] = (rc.x | rc.y) ? depth_bits(rec, r) : fill;
+        val[r] = (uint32_t)r;
+    }
+}
+
+__device__ __forceinline__ bool digit_varies(const uint32_t *rng, int n_jobs, int job, int shift) {
+    return (((rng[job] ^ rng[n_jobs + job]) >> shift) & 255u) != 0u;
+}
+
+// Buffer (0 or 1) that holds a job's pairs before the pass on digit `shift`:
+// only passes on varying digits move the data.
+__device__ __forceinline__ int parity_before(const uint32_t *rng, int n_jobs, int job, int shift) {
+    const uint32_t v = rng[job] ^ rng[n_jobs + job];
+    int p = 0;
+    for (int sh = 0; sh < shift; sh += 8) p ^= ((v >> sh) & 255u) != 0u;
+    return p;
+}
+
+// Per (job, segment): digit histogram into hist[job][digit][segment].
+__global__ __launch_bounds__(kSegThreads) void k_dsort_hist(ivrgs_batch b, const uint32_t *__restrict__ key0,
+                                                            const uint32_t *__restrict__ key1,
+                                                            const uint32_t *__restrict__ rng, int shift,
+                                                            uint32_t *__restrict__ hist, int n_seg) {
+    __shared__ uint32_t h[256];
+    const ivrgs_job job = b.jobs[blockIdx.y];
+    const int64_t base = (int64_t)blockIdx.x * kSeg;
+    if (base >= job.gauss_count || !digit_varies(rng, b.n_jobs, blockIdx.y, shift)) return;
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t *k = (parity_before(rng, b.n_jobs, blockIdx.y, shift) ? key1 : key0) + job.rec_begin + base;
+    const int n = (int)min((int64_t)kSeg, job.gauss_count - base);
+    for (int i = threadIdx.x; i < n; i += kSegThreads) atomicAdd(&h[(k[i] >> shift) & 255u], 1u);
+    __syncthreads();
+    hist[((int64_t)blockIdx.y * 256 + threadIdx.x) * n_seg + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive prefix of 64-bit values over a workgroup of 1024 threads.
+__device__ uint64_t block_exclusive_scan_1024(uint64_t v, uint64_t *tmp /* >= 16 */, uint64_t &total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint64_t incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    if (lane == 63) tmp[wave] = incl;
+    __syncthreads();
+    uint64_t off = 0;
+    total = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        if (w < wave) off += tmp[w];
+        total += tmp[w];
+    }
+    __syncthreads();
+    return off + incl - v;
+}
+
+// Per (job, digit), one wave: exclusive scan of the digit's counts over the
+// job's segments (contiguous, in place) and the digit's total into
+// tot[job][digit].
+__global__ __launch_bounds__(256) void k_dsort_colscan(ivrgs_batch b, const uint32_t *__restrict__ rng, int shift,
+                                                       uint32_t *__restrict__ hist, uint32_t *__restrict__ tot,
+                                                       int n_seg) {
+    const int d = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const ivrgs_job job = b.jobs[blockIdx.y];
+    const int rows = (job.gauss_count + kSeg - 1) / kSeg;
+    if (rows == 0 || !digit_varies(rng, b.n_jobs, blockIdx.y, shift)) return;
+    uint32_t *col = hist + ((int64_t)blockIdx.y * 256 + d) * n_seg;
+    uint32_t carry = 0;
+    for (int base = 0; base < rows; base += 64) {
+        const int c = base + lane;
+        const uint32_t v = c < rows ? col[c] : 0u;
+        uint32_t incl = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += u;
+        }
+        if (c < rows) col[c] = carry + incl - v;
+        carry += __shfl(incl, 63, 64);
+    }
+    if (lane == 0) tot[(int64_t)blockIdx.y * 256 + d] = carry;
+}
+
+// Per (job, segment): stable scatter of the segment's (key, id) pairs by
+// digit.  Wave w owns the contiguous part [w * kSegWaveItems, ...) of the
+// segment and ranks equal digits by lane inside each step of 64, so the
+// order within a digit is the input order.  A digit that is constant over
+// the job leaves the pairs where they are (see parity_before).
+__global__ __launch_bounds__(kSegThreads) void k_dsort_scatter(ivrgs_batch b, uint32_t *__restrict__ key0,
+                                                               uint32_t *__restrict__ val0,
+                                                               uint32_t *__restrict__ key1,
+                                                               uint32_t *__restrict__ val1,
+                                                               const uint32_t *__restrict__ rng, int shift,
+                                                               const uint32_t *__restrict__ hist,
+                                                               const uint32_t *__restrict__ tot, int n_seg) {
+    __shared__ uint32_t wh[kSegThreads / 64][256];  // per wave: count, then start, per digit
+    __shared__ uint32_t wsum[kSegThreads / 64];
+    const ivrgs_job job = b.jobs[blockIdx.y];
+    const int64_t base = (int64_t)blockIdx.x * kSeg;
+    if (base >= job.gauss_count) return;
+    const int n = (int)min((int64_t)kSeg, job.gauss_count - base);
+    const int64_t off = job.rec_begin + base;
+    if (!digit_varies(rng, b.n_jobs, blockIdx.y, shift)) return;
+    const bool from1 = parity_before(rng, b.n_jobs, blockIdx.y, shift) != 0;
+    const uint32_t *sk = from1 ? key1 : key0, *sv = from1 ? val1 : val0;
+    uint32_t *dk = from1 ? key0 : key1, *dv = from1 ? val0 : val1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int w0 = wave * kSegWaveItems;
+    uint32_t kk[kSegItems], vv[kSegItems];
+#pragma unroll
+    for (int u = 0; u < kSegItems; ++u) {
+        const int i = w0 + u * 64 + lane;
+        kk[u] = i < n ? sk[off + i] : 0u;
+        vv[u] = i < n ? sv[off + i] : 0u;
+    }
+    for (int d = lane; d < 256; d += 64) wh[wave][d] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kSegItems; ++u)
+        if (w0 + u * 64 + lane < n) atomicAdd(&wh[wave][(kk[u] >> shift) & 255u], 1u);
+    __syncthreads();
+    {
+        // thread d: start of digit d in the job (exclusive scan of the digit
+        // totals), plus this segment's offset inside the digit, plus the
+        // counts of the waves before
+        const int d = threadIdx.x;
+        const uint32_t t = tot[(int64_t)blockIdx.y * 256 + d];
+        uint32_t incl = t;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += u;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        uint32_t digit_start = incl - t;
+        for (int w = 0; w < wave; ++w) digit_start += wsum[w];
+        uint32_t run = digit_start + hist[((int64_t)blockIdx.y * 256 + d) * n_seg + blockIdx.x];
+#pragma unroll
+        for (int w = 0; w < kSegThreads / 64; ++w) {
+            const uint32_t c = wh[w][d];
+            wh[w][d] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    uint32_t *dkj = dk + job.rec_begin, *dvj = dv + job.rec_begin;
+#pragma unroll
+    for (int u = 0; u < kSegItems; ++u) {
+        if (w0 + u * 64 < n) {  // wave-uniform
+            const bool act = w0 + u * 64 + lane < n;
+            const uint32_t dg = (kk[u] >> shift) & 255u;
+            const uint64_t m = match_bits(dg, 8, __ballot(act));
+            const uint32_t rank = lanes_below(m);
+            const uint32_t pos = wh[wave][dg] + rank;
+            if (act) {
+                dkj[pos] = kk[u];
+                dvj[pos] = vv[u];
+            }
+            if (act && rank == 0) wh[wave][dg] += (uint32_t)__popcll(m);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Binning over the depth order.
+//
+// Visits every (record, tile) pair of the chunk [begin, end) of a job's depth
+// order whose tile the record's ellipse reaches, in depth order.  The work of
+// 64 consecutive records is spread evenly over the lanes: the lanes scan the
+// records' rect areas, then take the flattened (record, tile) items 64 at a
+// time (record-major, so in depth order) and find each item's record by
+// binary search over the scanned offsets.  f(record, tile x, tile y) is
+// called by the lanes of a hit, all lanes of one step together.
 struct ExpandLds {
-    float4 h0[kBinWaves][64], h1[kBinWaves][64];  // hit tests of the wave's records
-    uint32_t off[kBinWaves][64];                  // exclusive prefix of rect areas
-    uint32_t org[kBinWaves][64];                  // rect origin, x0 | y0 << 16
-    uint32_t wid[kBinWaves][64];                  // rect width in tiles
-    uint32_t zb[kBinWaves][64];                   // depth key bits
+    float4 h0[64], h1[64];  // hit tests of the step's records
+    uint32_t off[64];       // exclusive prefix of rect areas
+    uint32_t org[64];       // rect origin, x0 | y0 << 16
+    uint32_t wid[64];       // rect width in tiles
+    uint32_t rid[64];       // record index
 };
+constexpr int kBinWaves = 4;  // waves (chunks) per binning workgroup at most
 
 // Orders a wave's LDS writes before its other lanes' reads.
 __device__ __forceinline__ void wave_lds_sync() {
@@ -56,26 +294,25 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 template <typename F>
-__device__ __forceinline__ void for_each_pair(const ivrgs_job &job, int begin, int end, const float4 *rec4,
-                                              const uint2 *rect, ExpandLds &L, F &&f) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int g0 = begin + wave * 64; g0 < end; g0 += kBinWaves * 64) {
+__device__ __forceinline__ void for_each_pair(const ivrgs_job &job, int begin, int end, const uint32_t *order,
+                                              const float4 *rec4, const uint2 *rect, ExpandLds &L, F &&f) {
+    const int lane = threadIdx.x & 63;
+    for (int g0 = begin; g0 < end; g0 += 64) {
         const int l = g0 + lane;
         uint32_t n = 0;
         if (l < end) {
-            const int64_t r = (int64_t)job.rec_begin + l;
+            const int64_t r = order[(int64_t)job.rec_begin + l];
             const uint2 rc = rect[r];
             if (rc.x | rc.y) {
                 int x0, y0, x1, y1;
                 unpack_rect(rc, x0, y0, x1, y1);
                 n = (uint32_t)((x1 - x0) * (y1 - y0));
-                const float4 r2 = rec4[3 * r + 2];
-                const HitTest h = make_hit_test(rec4[3 * r], rec4[3 * r + 1], r2);
-                L.h0[wave][lane] = make_float4(h.mx, h.my, h.qa, h.qb);
-                L.h1[wave][lane] = make_float4(h.qc, h.i2qa, h.i2qc, h.tol);
-                L.org[wave][lane] = rc.x;
-                L.wid[wave][lane] = (uint32_t)(x1 - x0);
-                L.zb[wave][lane] = __float_as_uint(r2.y);
+                const HitTest h = make_hit_test(rec4[3 * r], rec4[3 * r + 1], rec4[3 * r + 2]);
+                L.h0[lane] = make_float4(h.mx, h.my, h.qa, h.qb);
+                L.h1[lane] = make_float4(h.qc, h.i2qa, h.i2qc, h.tol);
+                L.org[lane] = rc.x;
+                L.wid[lane] = (uint32_t)(x1 - x0);
+                L.rid[lane] = (uint32_t)r;
             }
         }
         uint32_t incl = n;
@@ -84,7 +321,7 @@ __device__ __forceinline__ void for_each_pair(const ivrgs_job &job, int begin, i
             const uint32_t o = __shfl_up(incl, d, 64);
             if (lane >= d) incl += o;
         }
-        L.off[wave][lane] = incl - n;
+        L.off[lane] = incl - n;
         const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
         wave_lds_sync();
         for (uint32_t base = 0; base < total; base += 64) {
@@ -94,42 +331,51 @@ __device__ __forceinline__ void for_each_pair(const ivrgs_job &job, int begin, i
                 int j = 0;
 #pragma unroll
                 for (int step = 32; step > 0; step >>= 1)
-                    if (L.off[wave][j + step] <= idx) j += step;
-                const uint32_t t = idx - L.off[wave][j];
-                const uint32_t w = L.wid[wave][j];
+                    if (L.off[j + step] <= idx) j += step;
+                const uint32_t t = idx - L.off[j];
+                const uint32_t w = L.wid[j];
                 const uint32_t dy = t / w, dx = t - dy * w;
-                const uint32_t o = L.org[wave][j];
+                const uint32_t o = L.org[j];
                 const int x = (int)((o & 0xFFFFu) + dx), y = (int)((o >> 16) + dy);
-                const float4 a = L.h0[wave][j], c = L.h1[wave][j];
+                const float4 a = L.h0[j], c = L.h1[j];
                 const HitTest h = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
-                if (box_hit(h, x * kTile, y * kTile, kTile, kTile))
-                    f((int64_t)job.rec_begin + g0 + j, x, y, L.zb[wave][j]);
+                if (box_hit(h, x * kTile, y * kTile, kTile, kTile)) f(L.rid[j], x, y);
             }
         }
         wave_lds_sync();  // every lane is done with the tables before they are rewritten
     }
 }
 
-// Pass 1 of the binning: per (job, chunk of records) the number of pairs each
-// tile receives, counted with LDS atomics and written into the count matrix
-// [job][tile][chunk].
-__global__ __launch_bounds__(256) void k_chunk_count(ivrgs_batch b, Consts k, const float *__restrict__ rec,
-                                                     const uint2 *__restrict__ rect,
-                                                     uint32_t *__restrict__ counts, int chunk, int n_chunks) {
-    extern __shared__ uint32_t cnt[];
+// Pairs per tile from each (job, chunk), into counts[job][tile][chunk].  A
+// workgroup of NW waves takes NW consecutive chunks, one per wave, each with
+// its own LDS counters; the NW counts of a tile are adjacent in the matrix.
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_chunk_count(ivrgs_batch b, Consts k, const float *__restrict__ rec,
+                                                         const uint2 *__restrict__ rect,
+                                                         const uint32_t *__restrict__ val0,
+                                                         const uint32_t *__restrict__ val1,
+                                                         const uint32_t *__restrict__ rng,
+                                                         uint32_t *__restrict__ counts, int chunk, int n_chunks) {
+    extern __shared__ uint32_t cnt[];  // [NW][tiles]
+    __shared__ ExpandLds L[NW];
     const ivrgs_job job = b.jobs[blockIdx.y];
-    const int begin = blockIdx.x * chunk;
-    if (begin >= job.gauss_count) return;
-    const int end = min(begin + chunk, job.gauss_count);
+    const int first = blockIdx.x * NW * chunk;
+    if (first >= job.gauss_count) return;
     const int tpj = k.tiles_per_job, tx_n = k.tiles_x;
-    for (int t = threadIdx.x; t < tpj; t += blockDim.x) cnt[t] = 0;
+    const int wave = threadIdx.x >> 6;
+    for (int t = threadIdx.x; t < NW * tpj; t += NW * 64) cnt[t] = 0;
     __syncthreads();
-    __shared__ ExpandLds L;
-    for_each_pair(job, begin, end, reinterpret_cast<const float4 *>(rec), rect, L,
-                  [&](int64_t, int x, int y, uint32_t) { atomicAdd(&cnt[y * tx_n + x], 1u); });
+    const int begin = first + wave * chunk;
+    const int end = min(begin + chunk, job.gauss_count);
+    const uint32_t *order = parity_before(rng, b.n_jobs, blockIdx.y, 32) ? val1 : val0;
+    uint32_t *c = cnt + wave * tpj;
+    for_each_pair(job, begin, end, order, reinterpret_cast<const float4 *>(rec), rect, L[wave],
+                  [&](uint32_t, int x, int y) { atomicAdd(&c[y * tx_n + x], 1u); });
     __syncthreads();
-    uint32_t *col = counts + (int64_t)blockIdx.y * tpj * n_chunks + blockIdx.x;
-    for (int t = threadIdx.x; t < tpj; t += blockDim.x) col[(int64_t)t * n_chunks] = cnt[t];
+    uint32_t *col = counts + (int64_t)blockIdx.y * tpj * n_chunks + blockIdx.x * NW;
+    for (int t = threadIdx.x; t < tpj; t += NW * 64)
+#pragma unroll
+        for (int w = 0; w < NW; ++w) col[(int64_t)t * n_chunks + w] = cnt[w * tpj + t];
 }
 
 // Per (job, tile), one wave: exclusive scan of the tile's counts over the
@@ -158,28 +404,6 @@ __global__ __launch_bounds__(256) void k_col_scan(ivrgs_batch b, Consts k, uint3
     if (lane == 0) tile_counts[(int64_t)blockIdx.y * k.tiles_per_job + t] = carry;
 }
 
-// Exclusive prefix of 64-bit values over a workgroup of 1024 threads.
-__device__ uint64_t block_exclusive_scan_1024(uint64_t v, uint64_t *tmp /* >= 16 */, uint64_t &total) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint64_t incl = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint64_t o = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += o;
-    }
-    if (lane == 63) tmp[wave] = incl;
-    __syncthreads();
-    uint64_t wave_off = 0, all = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-        const uint64_t t = tmp[w];
-        if (w < wave) wave_off += t;
-        all += t;
-    }
-    total = all;
-    __syncthreads();
-    return wave_off + incl - v;
-}
-
 // Single workgroup: tile counts -> exclusive starts (in place) and the total,
 // checked against the capacity.
 __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t *__restrict__ starts, int64_t n_tiles,
@@ -206,248 +430,48 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t *__restrict__ star
     }
 }
 
-// Pass 2: each (job, chunk) workgroup starts its per-tile cursors at the
-// tile's list start plus the chunk's exclusive column prefix and writes its
-// (depth key, record id) pairs.  No global atomics.
-__global__ __launch_bounds__(256) void k_scatter(ivrgs_batch b, Consts k, const float *__restrict__ rec,
-                                                 const uint2 *__restrict__ rect, const uint32_t *__restrict__ counts,
-                                                 uint32_t *__restrict__ keys, uint32_t *__restrict__ vals, int chunk,
-                                                 int n_chunks, const uint32_t *__restrict__ starts, int64_t n_tiles) {
-    extern __shared__ uint32_t cur[];
+// Each (job, chunk) wave starts its per-tile cursors at the tile's list start
+// plus the chunk's exclusive column prefix and appends its record ids in
+// depth order.  No global atomics.
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_scatter(ivrgs_batch b, Consts k, const float *__restrict__ rec,
+                                                     const uint2 *__restrict__ rect,
+                                                     const uint32_t *__restrict__ val0,
+                                                     const uint32_t *__restrict__ val1,
+                                                     const uint32_t *__restrict__ rng,
+                                                     const uint32_t *__restrict__ counts,
+                                                     uint32_t *__restrict__ sorted, int chunk, int n_chunks,
+                                                     const uint32_t *__restrict__ starts, int64_t n_tiles) {
+    extern __shared__ uint32_t cur[];  // [NW][tiles]
+    __shared__ ExpandLds L[NW];
     if (starts[n_tiles] == 0xFFFFFFFFu) return;  // capacity exceeded
     const ivrgs_job job = b.jobs[blockIdx.y];
-    const int begin = blockIdx.x * chunk;
-    if (begin >= job.gauss_count) return;
-    const int end = min(begin + chunk, job.gauss_count);
+    const int first = blockIdx.x * NW * chunk;
+    if (first >= job.gauss_count) return;
     const int tpj = k.tiles_per_job, tx_n = k.tiles_x;
-    const uint32_t *col = counts + (int64_t)blockIdx.y * tpj * n_chunks + blockIdx.x;
+    const int tile_bits = 32 - __clz(max(tpj - 1, 1));
+    const int wave = threadIdx.x >> 6;
+    const uint32_t *col = counts + (int64_t)blockIdx.y * tpj * n_chunks + blockIdx.x * NW;
     const uint32_t *st = starts + (int64_t)blockIdx.y * tpj;
-    for (int t = threadIdx.x; t < tpj; t += blockDim.x) cur[t] = st[t] + col[(int64_t)t * n_chunks];
+    for (int t = threadIdx.x; t < tpj; t += NW * 64) {
+        const uint32_t s0 = st[t];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) cur[w * tpj + t] = s0 + col[(int64_t)t * n_chunks + w];
+    }
     __syncthreads();
-    __shared__ ExpandLds L;
-    for_each_pair(job, begin, end, reinterpret_cast<const float4 *>(rec), rect, L,
-                  [&](int64_t r, int x, int y, uint32_t z) {
-                      const uint32_t slot = atomicAdd(&cur[y * tx_n + x], 1u);
-                      keys[slot] = z;
-                      vals[slot] = (uint32_t)r;
+    const int begin = first + wave * chunk;
+    const int end = min(begin + chunk, job.gauss_count);
+    const uint32_t *order = parity_before(rng, b.n_jobs, blockIdx.y, 32) ? val1 : val0;
+    uint32_t *c = cur + wave * tpj;
+    for_each_pair(job, begin, end, order, reinterpret_cast<const float4 *>(rec), rect, L[wave],
+                  [&](uint32_t r, int x, int y) {
+                      const uint32_t t = (uint32_t)(y * tx_n + x);
+                      const uint64_t m = match_bits(t, tile_bits, __ballot(true));
+                      const uint32_t rank = lanes_below(m);
+                      const uint32_t at = c[t];
+                      sorted[at + rank] = r;
+                      if (rank == 0) c[t] = at + (uint32_t)__popcll(m);
                   });
-}
-
-// ---------------------------------------------------------------------------
-// Per-tile sort: wave w of a block owns the contiguous segment
-// [w * seg, (w + 1) * seg) of the tile's list (seg a multiple of 64), so
-// processing (wave, sub-batch of 64, lane) in order visits the list in order
-// and each counting pass is stable.  Buffers ping-pong between an LDS pair
-// (lists up to half the staging capacity), LDS and global memory (up to the
-// capacity: the list lives in LDS and each pass stages through global
-// memory), or two global arrays (larger lists).  A pass prefetches kU
-// sub-batches per round so that a global source costs one latency per round.
-constexpr int kBigWaves = 16;       // 1024 threads for lists above kSmallCap
-constexpr int kSmallWaves = 4;      // 256 threads for lists up to kSmallCap
-constexpr int kSmallCap = 4096;     // both ping-pong buffers in LDS
-constexpr int kU = 8;
-
-__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
-// Lanes of the active mask whose digit equals this lane's digit.
-__device__ __forceinline__ uint64_t match_digit(uint32_t dg, uint64_t active) {
-    uint64_t m = active;
-#pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
-        const uint64_t bb = __ballot((dg >> bit) & 1u);
-        m &= ((dg >> bit) & 1u) ? bb : ~bb;
-    }
-    return m;
-}
-
-// Exclusive scan over threads 0..255 (others pass 0); every thread calls it.
-__device__ uint32_t scan256(uint32_t v, uint32_t *tmp /* >= waves per block */) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t incl = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t o = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += o;
-    }
-    if (lane == 63) tmp[wave] = incl;
-    __syncthreads();
-    uint32_t off = 0;
-    for (int w = 0; w < wave; ++w) off += tmp[w];
-    __syncthreads();
-    return off + incl - v;
-}
-
-// Turn per-wave digit histograms into per-wave starting offsets.
-template <int NW>
-__device__ void hist_to_offsets(uint32_t *hist, uint32_t *tmp) {
-    uint32_t c[NW];
-    uint32_t tot = 0;
-    if (threadIdx.x < 256) {
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            c[w] = hist[w * 256 + threadIdx.x];
-            tot += c[w];
-        }
-    }
-    const uint32_t pre = scan256(threadIdx.x < 256 ? tot : 0u, tmp);
-    if (threadIdx.x < 256) {
-        uint32_t run = pre;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            hist[w * 256 + threadIdx.x] = run;
-            run += c[w];
-        }
-    }
-    __syncthreads();
-}
-
-// One stable counting pass on digit (key >> shift) & 255, src -> dst.
-template <int NW>
-__device__ void radix_pass(const uint32_t *sk, const uint32_t *sv, uint32_t *dk, uint32_t *dv, int n, int shift,
-                           uint32_t *hist, uint32_t *tmp) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int seg = ((n + NW - 1) / NW + 63) / 64 * 64;
-    const int s0 = min(wave * seg, n), s1 = min(s0 + seg, n);
-    uint32_t *h = hist + wave * 256;
-    for (int d = lane; d < 256; d += 64) h[d] = 0;
-    __syncthreads();
-    for (int i = s0 + lane; i < s1; i += 64) atomicAdd(&h[(sk[i] >> shift) & 255u], 1u);
-    __syncthreads();
-    hist_to_offsets<NW>(hist, tmp);
-    for (int base = s0; base < s1; base += 64 * kU) {
-        uint32_t kk[kU], vv[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int i = base + u * 64 + lane;
-            kk[u] = i < s1 ? sk[i] : 0u;
-            vv[u] = i < s1 ? sv[i] : 0u;
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            if (base + u * 64 < s1) {  // wave-uniform
-                const bool act = base + u * 64 + lane < s1;
-                const uint32_t dg = (kk[u] >> shift) & 255u;
-                const uint64_t m = match_digit(dg, __ballot(act));
-                const uint32_t rank = lanes_below(m);
-                const uint32_t pos = h[dg] + rank;
-                if (act) {
-                    dk[pos] = kk[u];
-                    dv[pos] = vv[u];
-                }
-                if (act && rank == 0) h[dg] += (uint32_t)__popcll(m);
-            }
-        }
-    }
-    __syncthreads();
-}
-
-// Order runs of equal keys by value (record id).  Runs of equal FP32 depth
-// keys are rare and short; each is insertion-sorted by one thread.
-__device__ void fix_ties(const uint32_t *key, uint32_t *val, int n) {
-    int tie = 0;
-    for (int i = threadIdx.x + 1; i < n; i += blockDim.x) tie |= key[i] == key[i - 1];
-    if (!__syncthreads_or(tie)) return;
-    for (int i = threadIdx.x; i + 1 < n; i += blockDim.x) {
-        if (key[i + 1] != key[i] || (i > 0 && key[i - 1] == key[i])) continue;
-        int e = i + 1;
-        while (e < n && key[e] == key[i]) ++e;
-        for (int a = i + 1; a < e; ++a) {
-            const uint32_t v = val[a];
-            int c = a - 1;
-            while (c >= i && val[c] > v) {
-                val[c + 1] = val[c];
-                --c;
-            }
-            val[c + 1] = v;
-        }
-    }
-    __syncthreads();
-}
-
-// NW waves per block.  The small class takes lists of 2..kSmallCap pairs and
-// keeps both buffers in LDS; the big class takes the longer lists.
-template <int NW, bool kSmall>
-__global__ __launch_bounds__(NW * 64) void k_tile_sort(const uint32_t *__restrict__ starts, int64_t n_tiles,
-                                                       uint32_t *keys, uint32_t *vals, uint32_t *keys2,
-                                                       uint32_t *vals2, int lds_cap) {
-    extern __shared__ uint32_t lds[];
-    __shared__ uint32_t red_and[NW], red_or[NW], tmp[NW];
-    if (starts[n_tiles] == 0xFFFFFFFFu) return;
-    const uint32_t start = starts[blockIdx.x], end = starts[blockIdx.x + 1];
-    const int n = (int)(end - start);
-    if (n <= 1 || (kSmall ? n > kSmallCap : n <= kSmallCap)) return;
-    uint32_t *hist = lds;
-    uint32_t *buf = lds + NW * 256;  // keys [lds_cap] then values [lds_cap]
-    const int half = lds_cap / 2;
-    uint32_t *ka, *va, *kb, *vb;
-    bool copy_back = false;  // list in LDS, staging in global memory
-    if (n <= half) {
-        ka = buf;
-        va = buf + lds_cap;
-        kb = buf + half;
-        vb = buf + lds_cap + half;
-    } else if (n <= lds_cap) {
-        ka = buf;
-        va = buf + lds_cap;
-        kb = keys2 + start;
-        vb = vals2 + start;
-        copy_back = true;
-    } else {
-        ka = keys + start;
-        va = vals + start;
-        kb = keys2 + start;
-        vb = vals2 + start;
-    }
-    const bool in_lds = n <= lds_cap;
-    uint32_t a = 0xFFFFFFFFu, o = 0u;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const uint32_t key = keys[start + i];
-        if (in_lds) {
-            ka[i] = key;
-            va[i] = vals[start + i];
-        }
-        a &= key;
-        o |= key;
-    }
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        a &= __shfl_xor(a, d, 64);
-        o |= __shfl_xor(o, d, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        red_and[threadIdx.x >> 6] = a;
-        red_or[threadIdx.x >> 6] = o;
-    }
-    __syncthreads();
-    a = 0xFFFFFFFFu;
-    o = 0u;
-    for (int w = 0; w < NW; ++w) {
-        a &= red_and[w];
-        o |= red_or[w];
-    }
-    const uint32_t varying = a ^ o;
-    for (int d = 0; d < 4; ++d) {
-        if (((varying >> (8 * d)) & 255u) == 0u) continue;
-        radix_pass<NW>(ka, va, kb, vb, n, 8 * d, hist, tmp);
-        if (copy_back) {
-            for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                ka[i] = kb[i];
-                va[i] = vb[i];
-            }
-            __syncthreads();
-        } else {
-            uint32_t *t0 = ka, *t1 = va;
-            ka = kb;
-            va = vb;
-            kb = t0;
-            vb = t1;
-        }
-    }
-    fix_ties(ka, va, n);
-    if (va != vals + start)
-        for (int i = threadIdx.x; i < n; i += blockDim.x) vals[start + i] = va[i];
 }
 
 // Work queue for the persistent render kernels: nonempty tiles ordered by
@@ -490,7 +514,6 @@ hipError_t launch_work_queue(const uint32_t *starts, int64_t n_tiles, uint32_t *
     return hipGetLastError();
 }
 
-// ----------------------------------------------------------------------------
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int64_t want = (n + 255) / 256;
@@ -500,66 +523,91 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
-int chunk_rows(const ivrgs_batch &b, int chunk) { return (b.max_job_count + chunk - 1) / chunk; }
+// Chunks per job, padded to a multiple of kBinWaves (a workgroup takes up
+// to kBinWaves consecutive chunks).
+int chunk_rows(const ivrgs_batch &b, int chunk) {
+    const int rows = (b.max_job_count + chunk - 1) / chunk;
+    return (rows + kBinWaves - 1) / kBinWaves * kBinWaves;
+}
 
-hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *rec, const uint32_t *rect,
-                           const ivrgs_bins &bins, const BinWork &w, int chunk, int lds_cap, size_t sort_lds,
-                           hipStream_t s) {
-    const int64_t n_tiles = (int64_t)b.n_jobs * k.tiles_per_job;
-    const int n_chunks = chunk_rows(b, chunk);
-    const size_t cnt_lds = sizeof(uint32_t) * k.tiles_per_job;
+size_t depth_sort_hist_words(const ivrgs_batch &b) { return (size_t)b.n_jobs * 256 * ((size_t)seg_rows(b) + 1); }
+
+template <int NW>
+static void launch_binning(const ivrgs_batch &b, const Consts &k, const float *rec, const uint2 *rect2,
+                           const ivrgs_bins &bins, const BinWork &w, int chunk, int n_chunks,
+                           int64_t n_tiles, hipStream_t s) {
+    const size_t lds = sizeof(uint32_t) * NW * (size_t)k.tiles_per_job;
+    const dim3 grid((unsigned)(n_chunks / NW), (unsigned)b.n_jobs);
     {
         TimedScope ts(TK_COUNT, s);
-        if (n_chunks > 0) {
-            hipLaunchKernelGGL(k_chunk_count, dim3(n_chunks, b.n_jobs), dim3(256), cnt_lds, s, b, k, rec,
-                               reinterpret_cast<const uint2 *>(rect), w.counts, chunk, n_chunks);
-            hipLaunchKernelGGL(k_col_scan, dim3((k.tiles_per_job + 3) / 4, b.n_jobs), dim3(256), 0, s, b, k,
-                               w.counts, chunk, n_chunks, bins.tile_start);
-        } else if (n_tiles > 0) {
-            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, bins.tile_start, n_tiles, 0u);
-        }
+        hipLaunchKernelGGL(k_chunk_count<NW>, grid, dim3(NW * 64), lds, s, b, k, rec, rect2, w.val[0], w.val[1],
+                           w.rng, w.counts, chunk, n_chunks);
+        hipLaunchKernelGGL(k_col_scan, dim3((k.tiles_per_job + 3) / 4, b.n_jobs), dim3(256), 0, s, b, k, w.counts,
+                           chunk, n_chunks, bins.tile_start);
         hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, bins.tile_start, n_tiles, bins.status,
                            bins.capacity);
     }
-    if (n_chunks > 0) {
-        TimedScope ts(TK_SCATTER, s);
-        hipLaunchKernelGGL(k_scatter, dim3(n_chunks, b.n_jobs), dim3(256), cnt_lds, s, b, k, rec,
-                           reinterpret_cast<const uint2 *>(rect), w.counts, w.keys, bins.sorted, chunk, n_chunks,
-                           bins.tile_start, n_tiles);
-    }
-    if (n_tiles > 0) {
+    TimedScope ts(TK_SCATTER, s);
+    hipLaunchKernelGGL(k_scatter<NW>, grid, dim3(NW * 64), lds, s, b, k, rec, rect2, w.val[0], w.val[1], w.rng,
+                       w.counts, bins.sorted, chunk, n_chunks, bins.tile_start, n_tiles);
+}
+
+hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *rec, const uint32_t *rect,
+                           const ivrgs_bins &bins, const BinWork &w, int chunk, size_t bin_lds, hipStream_t s) {
+    const int64_t n_tiles = (int64_t)b.n_jobs * k.tiles_per_job;
+    const int n_chunks = chunk_rows(b, chunk);
+    const int n_seg = seg_rows(b);
+    const uint2 *rect2 = reinterpret_cast<const uint2 *>(rect);
+    uint32_t *tot = w.hist + (size_t)b.n_jobs * 256 * n_seg;
+    if (n_seg > 0) {
         TimedScope ts(TK_SORT, s);
-        hipLaunchKernelGGL((k_tile_sort<kSmallWaves, true>), dim3((unsigned)n_tiles), dim3(kSmallWaves * 64),
-                           small_sort_lds_bytes(), s, bins.tile_start, n_tiles, w.keys, bins.sorted, w.keys2,
-                           w.vals2, 2 * kSmallCap);
-        hipLaunchKernelGGL((k_tile_sort<kBigWaves, false>), dim3((unsigned)n_tiles), dim3(kBigWaves * 64), sort_lds,
-                           s, bins.tile_start, n_tiles, w.keys, bins.sorted, w.keys2, w.vals2, lds_cap);
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, w.rng, (int64_t)b.n_jobs, 0xFFFFFFFFu);
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, w.rng + b.n_jobs, (int64_t)b.n_jobs, 0u);
+        hipLaunchKernelGGL(k_dkey_range, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, rec, rect2, w.rng);
+        hipLaunchKernelGGL(k_dkey_init, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, rec, rect2, w.rng,
+                           w.key[0], w.val[0]);
+        for (int pass = 0; pass < 4; ++pass) {
+            const int shift = 8 * pass;
+            hipLaunchKernelGGL(k_dsort_hist, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, w.key[0], w.key[1],
+                               w.rng, shift, w.hist, n_seg);
+            hipLaunchKernelGGL(k_dsort_colscan, dim3(64, b.n_jobs), dim3(256), 0, s, b, w.rng, shift, w.hist, tot,
+                               n_seg);
+            hipLaunchKernelGGL(k_dsort_scatter, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, w.key[0], w.val[0],
+                               w.key[1], w.val[1], w.rng, shift, w.hist, tot, n_seg);
+        }
     }
+    if (n_chunks == 0) {
+        TimedScope ts(TK_COUNT, s);
+        if (n_tiles > 0) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, bins.tile_start, n_tiles, 0u);
+        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, bins.tile_start, n_tiles, bins.status,
+                           bins.capacity);
+        return hipGetLastError();
+    }
+    // as many chunks per workgroup as the per-tile counters allow
+    const size_t per_wave = sizeof(uint32_t) * (size_t)k.tiles_per_job;
+    if (4 * per_wave <= bin_lds) launch_binning<4>(b, k, rec, rect2, bins, w, chunk, n_chunks, n_tiles, s);
+    else if (2 * per_wave <= bin_lds) launch_binning<2>(b, k, rec, rect2, bins, w, chunk, n_chunks, n_tiles, s);
+    else launch_binning<1>(b, k, rec, rect2, bins, w, chunk, n_chunks, n_tiles, s);
     return hipGetLastError();
 }
 
 // Static LDS of the binning kernels (their per-tile counters are dynamic).
-size_t bin_static_lds_bytes() { return sizeof(ExpandLds); }
+size_t bin_static_lds_bytes() { return kBinWaves * sizeof(ExpandLds); }
 
-hipError_t set_bin_lds_limit(size_t bytes) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_chunk_count),
+template <int NW>
+static hipError_t set_lds(size_t bytes) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_chunk_count<NW>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_scatter), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)bytes);
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_scatter<NW>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-// LDS bytes of the big-list sort for a staging capacity (elements).
-size_t sort_lds_bytes(int lds_cap) { return sizeof(uint32_t) * (kBigWaves * 256 + 2 * (size_t)lds_cap); }
-
-size_t small_sort_lds_bytes() { return sizeof(uint32_t) * (kSmallWaves * 256 + 4 * (size_t)kSmallCap); }
-
-hipError_t set_sort_lds_limit(size_t bytes) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_tile_sort<kBigWaves, false>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_tile_sort<kSmallWaves, true>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)small_sort_lds_bytes());
+hipError_t set_bin_lds_limit(size_t bytes) {
+    hipError_t e = set_lds<4>(bytes);
+    if (e == hipSuccess) e = set_lds<2>(bytes);
+    if (e == hipSuccess) e = set_lds<1>(bytes);
+    return e;
 }
 
 }  // namespace ivrgs

@@ -19,9 +19,13 @@ struct TimedScope {
 };
 
 struct BinWork {
-    uint32_t *keys, *keys2, *vals2, *counts;
+    uint32_t *key[2], *val[2];  // depth-order ping-pong, one word per record each
+    uint32_t *hist;             // depth_sort_hist_words
+    uint32_t *rng;              // 2 * n_jobs
+    uint32_t *counts;           // [job][tile][chunk]
 };
 int chunk_rows(const ivrgs_batch &b, int chunk);
+size_t depth_sort_hist_words(const ivrgs_batch &b);
 
 hipError_t launch_project(const ivrgs_batch &b, const Consts &k, float *rec, uint32_t *rect, hipStream_t s);
 hipError_t launch_project_bwd(const ivrgs_batch &b, const Consts &k, const uint32_t *rect, const float *grec,
@@ -30,11 +34,7 @@ hipError_t launch_compose(const ivrgs_gaussians &src, int64_t offset, int32_t mo
                           const ivrgs_gaussians_mut &out, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *rec, const uint32_t *rect,
-                           const ivrgs_bins &bins, const BinWork &w, int chunk, int lds_cap, size_t sort_lds,
-                           hipStream_t s);
-size_t sort_lds_bytes(int lds_cap);
-size_t small_sort_lds_bytes();
-hipError_t set_sort_lds_limit(size_t bytes);
+                           const ivrgs_bins &bins, const BinWork &w, int chunk, size_t bin_lds, hipStream_t s);
 size_t bin_static_lds_bytes();
 hipError_t set_bin_lds_limit(size_t bytes);
 hipError_t launch_render_fwd(const Consts &k, int px, int64_t n_tiles, const float *rec, const uint32_t *starts,

@@ -22,7 +22,7 @@ EXPORTS = ("ivrgs_workspace_size", "ivrgs_tiles_per_job", "ivrgs_compose", "ivrg
            "ivrgs_bin_sort", "ivrgs_render_fwd", "ivrgs_render_bwd", "ivrgs_struct_size",
            "ivrgs_status_string", "ivrgs_timing_enable", "ivrgs_timing_read",
            "ivrgs_cull_workspace_size", "ivrgs_cull")
-TIMING_KINDS = ("project", "tile_count", "scatter", "tile_sort", "render_fwd", "render_bwd",
+TIMING_KINDS = ("project", "tile_count", "scatter", "depth_sort", "render_fwd", "render_bwd",
                 "project_bwd", "compose", "fill", "cull")
 
 

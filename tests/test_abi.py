@@ -64,6 +64,9 @@ def test_host_validation(lib):
     b.n_jobs, b.max_job_count, b.n_records = 2, 10, 20
     b.jobs = b.cameras = b.edits = 1  # non-null placeholders, never dereferenced
     ws = N.ivrgs_workspace_size(b, p, 1000)
-    assert ws >= 3 * 4 * 1000 + 9 * 4 * 20
+    # two (key, id) arrays per record for the depth order, 9 gradient floats per record
+    assert ws >= 4 * 4 * 20 + 9 * 4 * 20
+    # the pair capacity lives in the caller's bins, not in the workspace
+    assert N.ivrgs_workspace_size(b, p, 10 ** 6) == ws
     assert N.ivrgs_workspace_size(b, p, -1) == 0
     assert lib.ivrgs_status_string(N.E_CAPACITY).decode().startswith("workspace")

@@ -428,13 +428,34 @@ def test_c2_fullsize_sampled(dev, c2_planes, view):
         assert np.all(g[k][:, ~touched] == 0), k
 
 
-@pytest.mark.parametrize("n", [4096, 4097, 9152, 9153, 18304, 18305])
-def test_bin_sort_size_class_boundaries(dev, n):
-    """List lengths at the boundaries of the sort's staging paths (both
-    buffers in LDS / list in LDS with global staging / all global)."""
+@pytest.mark.parametrize("n", [511, 512, 513, 4095, 4096, 4097, 8193])
+def test_bin_sort_chunk_and_segment_boundaries(dev, n):
+    """List lengths around the binning chunk (512 records), the wave step (64)
+    and the depth-sort segment (4096 records), all on one tile."""
     say(f"bin_sort exact, {n} records on one tile")
     rng = np.random.default_rng(n)
     rects = np.tile(np.array([[0, 0, 1, 1]]), (n, 1))
     z = (2.0 + rng.random(n) * 3.0).astype(np.float32)
     z[::97] = np.float32(3.25)  # a run of exact ties
     _bin_case(dev, 16, 16, rects, z)
+
+
+@pytest.mark.parametrize("pattern", ["all_equal", "top_byte", "low_byte", "mixed_exponents"])
+def test_bin_sort_digit_patterns(dev, pattern):
+    """Depth keys whose varying bits fall in different bytes (every digit
+    pass, or none, of the radix sort is exercised), with ties resolved by id."""
+    say(f"bin_sort exact, digit pattern {pattern}")
+    rng = np.random.default_rng(11)
+    n = 3000
+    rects = np.tile(np.array([[0, 0, 2, 1]]), (n, 1))
+    rects[::5] = [1, 0, 2, 1]
+    if pattern == "all_equal":
+        z = np.full(n, 3.0, np.float32)
+    elif pattern == "top_byte":
+        z = rng.choice(np.float32([2.0, 8.0, 32.0, 128.0]), n).astype(np.float32)
+    elif pattern == "low_byte":
+        base = np.float32(3.0).view(np.uint32)
+        z = (base + rng.integers(0, 256, n).astype(np.uint32)).view(np.float32)
+    else:
+        z = (2.0 ** rng.uniform(-1, 10, n)).astype(np.float32)
+    _bin_case(dev, 32, 16, rects, z)
