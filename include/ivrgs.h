@@ -151,10 +151,13 @@ typedef struct {
  *               min(alpha_max, opacity * that), and the depth key is the
  *               FP32 camera-space z of the mean
  *   rect[r]     tile rectangle [x0, x1) x [y0, y1) packed as
- *               (x0 | y0 << 16, x1 | y1 << 16); (0, 0) if culled */
+ *               (x0 | y0 << 16, x1 | y1 << 16); (0, 0) if culled
+ *   depth[r]    the depth key's FP32 bits (positive, finite) of a visible
+ *               record, 0xFFFFFFFF if culled; ivrgs_bin_sort orders by it */
 typedef struct {
     float *rec;
     uint32_t *rect;
+    uint32_t *depth;
 } ivrgs_projected;
 
 /* Tile bins (device, caller-allocated):

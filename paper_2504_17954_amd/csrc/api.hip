@@ -218,9 +218,9 @@ ivrgs_status ivrgs_project(const ivrgs_batch *batch, const ivrgs_params *params,
     ivrgs_status st = check_batch(batch);
     if (st != IVRGS_OK) return st;
     if ((st = check_params(params)) != IVRGS_OK) return st;
-    if (!out || (batch->n_records > 0 && (!out->rec || !out->rect))) return IVRGS_E_INVALID;
+    if (!out || (batch->n_records > 0 && (!out->rec || !out->rect || !out->depth))) return IVRGS_E_INVALID;
     const Consts k = make_consts(*params);
-    return hip_status(launch_project(*batch, k, out->rec, out->rect, reinterpret_cast<hipStream_t>(stream)));
+    return hip_status(launch_project(*batch, k, out->rec, out->rect, out->depth, reinterpret_cast<hipStream_t>(stream)));
 }
 
 ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
@@ -230,7 +230,7 @@ ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params
     if ((st = check_params(params)) != IVRGS_OK) return st;
     if (!proj || !bins || !bins->tile_start || !bins->status || bins->capacity < 0) return IVRGS_E_INVALID;
     if (bins->capacity > 0 && !bins->sorted) return IVRGS_E_INVALID;
-    if (batch->n_records > 0 && (!proj->rec || !proj->rect)) return IVRGS_E_INVALID;
+    if (batch->n_records > 0 && (!proj->rec || !proj->rect || !proj->depth)) return IVRGS_E_INVALID;
     const Consts k = make_consts(*params);
     DeviceLimits dl;
     if (device_limits(dl) != hipSuccess) return IVRGS_E_HIP;
@@ -248,7 +248,7 @@ ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params
     w.counts = reinterpret_cast<uint32_t *>(ws + L.counts);
     const int chunk = chunk_of(*params);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipError_t e = launch_bin_sort(*batch, k, proj->rec, proj->rect, *bins, w, chunk, dl.bin_lds, s);
+    hipError_t e = launch_bin_sort(*batch, k, proj->rec, proj->rect, proj->depth, *bins, w, chunk, dl.bin_lds, s);
     if (e == hipSuccess && (params->flags & IVRGS_FLAG_PERSISTENT))
         e = launch_work_queue(bins->tile_start, (int64_t)batch->n_jobs * k.tiles_per_job,
                               reinterpret_cast<uint32_t *>(ws + L.queue), s);

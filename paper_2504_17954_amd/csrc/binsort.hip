@@ -55,24 +55,17 @@ constexpr int kSegWaveItems = kSeg / (kSegThreads / 64);  // contiguous per wave
 
 int seg_rows(const ivrgs_batch &b) { return (b.max_job_count + kSeg - 1) / kSeg; }
 
-__device__ __forceinline__ uint32_t depth_bits(const float *rec, int64_t r) {
-    return __float_as_uint(rec[12 * r + 9]);
-}
-
 // AND and OR of the depth keys of each job's visible records (rng[j] and
-// rng[n_jobs + j], preset to ~0 and 0).
-__global__ __launch_bounds__(kSegThreads) void k_dkey_range(ivrgs_batch b, const float *__restrict__ rec,
-                                                            const uint2 *__restrict__ rect,
+// rng[n_jobs + j], preset to ~0 and 0).  Culled records carry the key ~0.
+__global__ __launch_bounds__(kSegThreads) void k_dkey_range(ivrgs_batch b, const uint32_t *__restrict__ depth,
                                                             uint32_t *__restrict__ rng) {
     const ivrgs_job job = b.jobs[blockIdx.y];
     const int64_t base = (int64_t)blockIdx.x * kSeg;
     if (base >= job.gauss_count) return;
     uint32_t a = 0xFFFFFFFFu, o = 0u;
     for (int i = threadIdx.x; i < kSeg && base + i < job.gauss_count; i += kSegThreads) {
-        const int64_t r = (int64_t)job.rec_begin + base + i;
-        const uint2 rc = rect[r];
-        if (rc.x | rc.y) {
-            const uint32_t z = depth_bits(rec, r);
+        const uint32_t z = depth[(int64_t)job.rec_begin + base + i];
+        if (z != 0xFFFFFFFFu) {
             a &= z;
             o |= z;
         }
@@ -88,39 +81,31 @@ __global__ __launch_bounds__(kSegThreads) void k_dkey_range(ivrgs_batch b, const
     }
 }
 
-// Initial (key, id) arrays in id order; a culled record takes the AND of the
-// visible keys, so it adds no varying bit (it is never binned).
-__global__ __launch_bounds__(kSegThreads) void k_dkey_init(ivrgs_batch b, const float *__restrict__ rec,
-                                                           const uint2 *__restrict__ rect,
-                                                           const uint32_t *__restrict__ rng,
-                                                           uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
-    const ivrgs_job job = b.jobs[blockIdx.y];
-    const int64_t base = (int64_t)blockIdx.x * kSeg;
-    if (base >= job.gauss_count) return;
-    const uint32_t fill = rng[blockIdx.y];
-    for (int i = threadIdx.x; i < kSeg && base + i < job.gauss_count; i += kSegThreads) {
-        const int64_t r = (int64_t)job.rec_begin + base + i;
-        const uint2 rc = rect[r];
-        key[r] = (rc.x | rc.y) ? depth_bits(rec, r) : fill;
-        val[r] = (uint32_t)r;
-    }
-}
-
 __device__ __forceinline__ bool digit_varies(const uint32_t *rng, int n_jobs, int job, int shift) {
     return (((rng[job] ^ rng[n_jobs + job]) >> shift) & 255u) != 0u;
 }
 
-// Buffer (0 or 1) that holds a job's pairs before the pass on digit `shift`:
-// only passes on varying digits move the data.
-__device__ __forceinline__ int parity_before(const uint32_t *rng, int n_jobs, int job, int shift) {
+// Passes on varying digits below digit `shift` (only those move the data).
+// The first such pass reads the keys from the projection's depth array with
+// the record ids implicit; pass i (from 0) writes buffer i & 1.
+__device__ __forceinline__ int passes_before(const uint32_t *rng, int n_jobs, int job, int shift) {
     const uint32_t v = rng[job] ^ rng[n_jobs + job];
     int p = 0;
-    for (int sh = 0; sh < shift; sh += 8) p ^= ((v >> sh) & 255u) != 0u;
+    for (int sh = 0; sh < shift; sh += 8) p += ((v >> sh) & 255u) != 0u;
     return p;
 }
 
+// The job's records in depth order (absolute record indices), or nullptr if
+// no digit varies: then the order is the record order itself.
+__device__ __forceinline__ const uint32_t *depth_order(const uint32_t *rng, int n_jobs, int job,
+                                                      const uint32_t *val0, const uint32_t *val1) {
+    const int p = passes_before(rng, n_jobs, job, 32);
+    return p == 0 ? nullptr : ((p - 1) & 1 ? val1 : val0);
+}
+
 // Per (job, segment): digit histogram into hist[job][digit][segment].
-__global__ __launch_bounds__(kSegThreads) void k_dsort_hist(ivrgs_batch b, const uint32_t *__restrict__ key0,
+__global__ __launch_bounds__(kSegThreads) void k_dsort_hist(ivrgs_batch b, const uint32_t *__restrict__ depth,
+                                                            const uint32_t *__restrict__ key0,
                                                             const uint32_t *__restrict__ key1,
                                                             const uint32_t *__restrict__ rng, int shift,
                                                             uint32_t *__restrict__ hist, int n_seg) {
@@ -130,7 +115,8 @@ __global__ __launch_bounds__(kSegThreads) void k_dsort_hist(ivrgs_batch b, const
     if (base >= job.gauss_count || !digit_varies(rng, b.n_jobs, blockIdx.y, shift)) return;
     h[threadIdx.x] = 0;
     __syncthreads();
-    const uint32_t *k = (parity_before(rng, b.n_jobs, blockIdx.y, shift) ? key1 : key0) + job.rec_begin + base;
+    const int before = passes_before(rng, b.n_jobs, blockIdx.y, shift);
+    const uint32_t *k = (before == 0 ? depth : ((before - 1) & 1 ? key1 : key0)) + job.rec_begin + base;
     const int n = (int)min((int64_t)kSeg, job.gauss_count - base);
     for (int i = threadIdx.x; i < n; i += kSegThreads) atomicAdd(&h[(k[i] >> shift) & 255u], 1u);
     __syncthreads();
@@ -190,8 +176,9 @@ __global__ __launch_bounds__(256) void k_dsort_colscan(ivrgs_batch b, const uint
 // digit.  Wave w owns the contiguous part [w * kSegWaveItems, ...) of the
 // segment and ranks equal digits by lane inside each step of 64, so the
 // order within a digit is the input order.  A digit that is constant over
-// the job leaves the pairs where they are (see parity_before).
-__global__ __launch_bounds__(kSegThreads) void k_dsort_scatter(ivrgs_batch b, uint32_t *__restrict__ key0,
+// the job leaves the pairs where they are (see passes_before).
+__global__ __launch_bounds__(kSegThreads) void k_dsort_scatter(ivrgs_batch b, const uint32_t *__restrict__ depth,
+                                                               uint32_t *__restrict__ key0,
                                                                uint32_t *__restrict__ val0,
                                                                uint32_t *__restrict__ key1,
                                                                uint32_t *__restrict__ val1,
@@ -206,9 +193,10 @@ __global__ __launch_bounds__(kSegThreads) void k_dsort_scatter(ivrgs_batch b, ui
     const int n = (int)min((int64_t)kSeg, job.gauss_count - base);
     const int64_t off = job.rec_begin + base;
     if (!digit_varies(rng, b.n_jobs, blockIdx.y, shift)) return;
-    const bool from1 = parity_before(rng, b.n_jobs, blockIdx.y, shift) != 0;
-    const uint32_t *sk = from1 ? key1 : key0, *sv = from1 ? val1 : val0;
-    uint32_t *dk = from1 ? key0 : key1, *dv = from1 ? val0 : val1;
+    const int before = passes_before(rng, b.n_jobs, blockIdx.y, shift);
+    const bool first = before == 0, to1 = (before & 1) != 0;
+    const uint32_t *sk = first ? depth : (to1 ? key0 : key1), *sv = to1 ? val0 : val1;
+    uint32_t *dk = to1 ? key1 : key0, *dv = to1 ? val1 : val0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int w0 = wave * kSegWaveItems;
     uint32_t kk[kSegItems], vv[kSegItems];
@@ -216,7 +204,7 @@ __global__ __launch_bounds__(kSegThreads) void k_dsort_scatter(ivrgs_batch b, ui
     for (int u = 0; u < kSegItems; ++u) {
         const int i = w0 + u * 64 + lane;
         kk[u] = i < n ? sk[off + i] : 0u;
-        vv[u] = i < n ? sv[off + i] : 0u;
+        vv[u] = i < n ? (first ? (uint32_t)(off + i) : sv[off + i]) : 0u;
     }
     for (int d = lane; d < 256; d += 64) wh[wave][d] = 0;
     __syncthreads();
@@ -301,7 +289,7 @@ __device__ __forceinline__ void for_each_pair(const ivrgs_job &job, int begin, i
         const int l = g0 + lane;
         uint32_t n = 0;
         if (l < end) {
-            const int64_t r = order[(int64_t)job.rec_begin + l];
+            const int64_t r = order ? (int64_t)order[(int64_t)job.rec_begin + l] : (int64_t)job.rec_begin + l;
             const uint2 rc = rect[r];
             if (rc.x | rc.y) {
                 int x0, y0, x1, y1;
@@ -367,7 +355,7 @@ __global__ __launch_bounds__(NW * 64) void k_chunk_count(ivrgs_batch b, Consts k
     __syncthreads();
     const int begin = first + wave * chunk;
     const int end = min(begin + chunk, job.gauss_count);
-    const uint32_t *order = parity_before(rng, b.n_jobs, blockIdx.y, 32) ? val1 : val0;
+    const uint32_t *order = depth_order(rng, b.n_jobs, blockIdx.y, val0, val1);
     uint32_t *c = cnt + wave * tpj;
     for_each_pair(job, begin, end, order, reinterpret_cast<const float4 *>(rec), rect, L[wave],
                   [&](uint32_t, int x, int y) { atomicAdd(&c[y * tx_n + x], 1u); });
@@ -461,7 +449,7 @@ __global__ __launch_bounds__(NW * 64) void k_scatter(ivrgs_batch b, Consts k, co
     __syncthreads();
     const int begin = first + wave * chunk;
     const int end = min(begin + chunk, job.gauss_count);
-    const uint32_t *order = parity_before(rng, b.n_jobs, blockIdx.y, 32) ? val1 : val0;
+    const uint32_t *order = depth_order(rng, b.n_jobs, blockIdx.y, val0, val1);
     uint32_t *c = cur + wave * tpj;
     for_each_pair(job, begin, end, order, reinterpret_cast<const float4 *>(rec), rect, L[wave],
                   [&](uint32_t r, int x, int y) {
@@ -553,7 +541,8 @@ static void launch_binning(const ivrgs_batch &b, const Consts &k, const float *r
 }
 
 hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *rec, const uint32_t *rect,
-                           const ivrgs_bins &bins, const BinWork &w, int chunk, size_t bin_lds, hipStream_t s) {
+                           const uint32_t *depth, const ivrgs_bins &bins, const BinWork &w, int chunk,
+                           size_t bin_lds, hipStream_t s) {
     const int64_t n_tiles = (int64_t)b.n_jobs * k.tiles_per_job;
     const int n_chunks = chunk_rows(b, chunk);
     const int n_seg = seg_rows(b);
@@ -563,17 +552,15 @@ hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *r
         TimedScope ts(TK_SORT, s);
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, w.rng, (int64_t)b.n_jobs, 0xFFFFFFFFu);
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, w.rng + b.n_jobs, (int64_t)b.n_jobs, 0u);
-        hipLaunchKernelGGL(k_dkey_range, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, rec, rect2, w.rng);
-        hipLaunchKernelGGL(k_dkey_init, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, rec, rect2, w.rng,
-                           w.key[0], w.val[0]);
+        hipLaunchKernelGGL(k_dkey_range, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, depth, w.rng);
         for (int pass = 0; pass < 4; ++pass) {
             const int shift = 8 * pass;
-            hipLaunchKernelGGL(k_dsort_hist, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, w.key[0], w.key[1],
-                               w.rng, shift, w.hist, n_seg);
+            hipLaunchKernelGGL(k_dsort_hist, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, depth, w.key[0],
+                               w.key[1], w.rng, shift, w.hist, n_seg);
             hipLaunchKernelGGL(k_dsort_colscan, dim3(64, b.n_jobs), dim3(256), 0, s, b, w.rng, shift, w.hist, tot,
                                n_seg);
-            hipLaunchKernelGGL(k_dsort_scatter, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, w.key[0], w.val[0],
-                               w.key[1], w.val[1], w.rng, shift, w.hist, tot, n_seg);
+            hipLaunchKernelGGL(k_dsort_scatter, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, depth, w.key[0],
+                               w.val[0], w.key[1], w.val[1], w.rng, shift, w.hist, tot, n_seg);
         }
     }
     if (n_chunks == 0) {

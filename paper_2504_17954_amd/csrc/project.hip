@@ -236,7 +236,7 @@ __device__ __forceinline__ void camera_center(const Cam &c, float p[3]) {
 
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_project(ivrgs_batch b, Consts k, float4 *__restrict__ rec,
-                                                 uint2 *__restrict__ rect) {
+                                                 uint2 *__restrict__ rect, uint32_t *__restrict__ depth) {
     const ivrgs_job job = b.jobs[blockIdx.y];
     const int local = blockIdx.x * blockDim.x + threadIdx.x;
     if (local >= job.gauss_count) return;
@@ -290,6 +290,7 @@ __global__ __launch_bounds__(256) void k_project(ivrgs_batch b, Consts k, float4
     rec[3 * r + 1] = r1;
     rec[3 * r + 2] = r2;
     rect[r] = rc;
+    depth[r] = (rc.x | rc.y) ? __float_as_uint(z32) : 0xFFFFFFFFu;
 }
 
 // ----------------------------------------------------------------------------
@@ -536,12 +537,13 @@ __global__ __launch_bounds__(256) void k_compose(ComposeArgs a, ivrgs_gaussians_
 
 // ----------------------------------------------------------------------------
 // host launchers
-hipError_t launch_project(const ivrgs_batch &b, const Consts &k, float *rec, uint32_t *rect, hipStream_t s) {
+hipError_t launch_project(const ivrgs_batch &b, const Consts &k, float *rec, uint32_t *rect, uint32_t *depth,
+                          hipStream_t s) {
     if (b.n_jobs == 0 || b.max_job_count == 0) return hipSuccess;
     dim3 grid((b.max_job_count + 255) / 256, b.n_jobs);
     TimedScope ts(TK_PROJECT, s);
     hipLaunchKernelGGL(k_project, grid, dim3(256), 0, s, b, k, reinterpret_cast<float4 *>(rec),
-                       reinterpret_cast<uint2 *>(rect));
+                       reinterpret_cast<uint2 *>(rect), depth);
     return hipGetLastError();
 }
 

@@ -399,11 +399,34 @@ __device__ __forceinline__ void bwd_tile(const Consts &k, const float4 *__restri
         __syncthreads();
         const int cnt = min((uint32_t)NT, end - base);
         const uint32_t my_bit = __builtin_amdgcn_readfirstlane(1u << (threadIdx.x >> 6));  // wave-uniform
-        // Records are taken in list order; the next kGroup records that
-        // composite somewhere in this wave fill the slots of one
-        // reduce-scatter, records that do not are passed over.
-        int i = 0;
-        while (i < cnt) {
+        // The batch records that can reach this wave's strip, as a bitmask
+        // (one 64-bit word per 64 records, wave-uniform), walked in list
+        // order.  The next kGroup records that composite somewhere in the
+        // wave fill the slots of one reduce-scatter; records that do not are
+        // passed over.
+        constexpr int NWORD = NT / 64;
+        uint64_t words[NWORD];
+#pragma unroll
+        for (int q = 0; q < NWORD; ++q) {
+            const int at = q * 64 + lane_id();
+            words[q] = __ballot(at < cnt && (smask[at] & my_bit) != 0u);
+        }
+        int word = 0;
+        uint64_t cur = words[0];
+        // next record of the walk, or false at the end of the batch
+        auto next = [&](int &ii) -> bool {
+            while (cur == 0ull) {
+                if (++word >= NWORD) return false;
+#pragma unroll
+                for (int q = 1; q < NWORD; ++q)
+                    if (word == q) cur = words[q];
+            }
+            ii = word * 64 + (int)__builtin_ctzll(cur);
+            cur &= cur - 1;
+            return true;
+        };
+        bool more = true;
+        while (more) {
             if (__ballot(mine) == 0ull) break;
             float acc[32];
 #pragma unroll
@@ -412,9 +435,12 @@ __device__ __forceinline__ void bwd_tile(const Consts &k, const float4 *__restri
 #pragma unroll
             for (int g = 0; g < kGroup; ++g) {
                 slot[g] = -1;
-                while (i < cnt) {
-                    const int ii = i++;
-                    if (!(__builtin_amdgcn_readfirstlane(smask[ii]) & my_bit)) continue;  // wave-uniform
+                while (more) {
+                    int ii;
+                    if (!next(ii)) {
+                        more = false;
+                        break;
+                    }
                     const float4 a = s0[ii];
                     const float4 c = s1[ii];
                     const float2 cc = s2[ii];
@@ -467,7 +493,7 @@ __device__ __forceinline__ void bwd_tile(const Consts &k, const float4 *__restri
                     for (int j = 0; j < PX; ++j) mine |= alive[j];
                     const bool filled = __ballot(hit) != 0ull;
                     if (filled) slot[g] = ii;
-                    if (__ballot(mine) == 0ull) i = cnt;  // every pixel of the wave is done
+                    if (__ballot(mine) == 0ull) more = false;  // every pixel of the wave is done
                     if (filled) break;
                 }
             }

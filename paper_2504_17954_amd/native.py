@@ -64,7 +64,7 @@ class ivrgs_params(C.Structure):
 
 
 class ivrgs_projected(C.Structure):
-    _fields_ = [("rec", C.c_void_p), ("rect", C.c_void_p)]
+    _fields_ = [("rec", C.c_void_p), ("rect", C.c_void_p), ("depth", C.c_void_p)]
 
 
 class ivrgs_bins(C.Structure):

@@ -159,7 +159,7 @@ class Renderer:
         self.check = check
         self.n_records = -1
         self.n_jobs = -1
-        self.rec = self.rect = self.tile_start = self.sorted = self.status = self.ws = None
+        self.rec = self.rect = self.depth = self.tile_start = self.sorted = self.status = self.ws = None
         self.generation = 0
         self._key = None
 
@@ -174,6 +174,7 @@ class Renderer:
         if self.rec is None or self.rec.shape[0] < max(R, 1):
             self.rec = torch.empty((max(R, 1), 12), dtype=torch.float32, device=dev)
             self.rect = torch.empty((max(R, 1), 2), dtype=torch.int32, device=dev)
+            self.depth = torch.empty(max(R, 1), dtype=torch.int32, device=dev)
         n_tiles = J * tiles
         if self.tile_start is None or self.tile_start.numel() < n_tiles + 1:
             self.tile_start = torch.empty(n_tiles + 1, dtype=torch.int32, device=dev)
@@ -193,7 +194,7 @@ class Renderer:
         self.ws = None
 
     def _structs(self, batch):
-        proj = N.ivrgs_projected(self.rec.data_ptr(), self.rect.data_ptr())
+        proj = N.ivrgs_projected(self.rec.data_ptr(), self.rect.data_ptr(), self.depth.data_ptr())
         bins = N.ivrgs_bins(self.tile_start.data_ptr(), self.sorted.data_ptr(), self.capacity,
                             self.status.data_ptr())
         return proj, bins

@@ -87,6 +87,10 @@ def test_project_parity(dev):
     assert np.all(valid[kept])
     z_ref = ref[:, 1].astype(np.float32)
     assert np.array_equal(rec[kept, 9].view(np.uint32), z_ref[kept].view(np.uint32))
+    # the depth array carries the same key bits, and all-ones for culled records
+    depth = rnd.depth[:10_000].cpu().numpy().view(np.uint32)
+    assert np.array_equal(depth[kept], z_ref[kept].view(np.uint32))
+    assert np.all(depth[~kept] == 0xFFFFFFFF)
     # screen mean within the error model the oracle uses for its decisions
     dm = ref[kept, 21]
     assert np.all(np.abs(rec[kept, 0] - ref[kept, 2]) <= dm)
@@ -126,6 +130,9 @@ def _bin_case(dev, width, height, rects, z, n_jobs=1):
     rnd.rec[:n] = torch.from_numpy(rec).to(dev)
     packed = np.stack([rects[:, 0] | (rects[:, 1] << 16), rects[:, 2] | (rects[:, 3] << 16)], 1)
     rnd.rect[:n] = torch.from_numpy(packed.astype(np.uint32).view(np.int32)).to(dev)
+    culled = (rects[:, 0] == 0) & (rects[:, 1] == 0) & (rects[:, 2] == 0) & (rects[:, 3] == 0)
+    dbits = np.where(culled, np.uint32(0xFFFFFFFF), z.astype(np.float32).view(np.uint32))
+    rnd.depth[:n] = torch.from_numpy(dbits.astype(np.uint32).view(np.int32)).to(dev)
     proj, bins = rnd._structs(batch)
     N.ivrgs_bin_sort(batch, s.params(), proj, bins, rnd.ws.data_ptr(), rnd.ws.numel(), R._stream())
     st = rnd.status.cpu().numpy()
