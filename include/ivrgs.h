@@ -118,7 +118,7 @@ typedef struct {
     int32_t n_models;
     const ivrgs_camera *cameras;     /* device */
     const ivrgs_job *jobs;           /* device [n_jobs] */
-    int32_t n_jobs;
+    int32_t n_jobs;                  /* 0 .. 65535 (a grid dimension) */
     int32_t max_job_count;           /* host-known max gauss_count over jobs */
     int64_t n_records;               /* host-known sum of gauss_count */
 } ivrgs_batch;

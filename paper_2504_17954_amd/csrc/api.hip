@@ -71,6 +71,7 @@ struct DeviceLimits {
     bool ready = false;
     size_t max_lds = 65536;
     size_t bin_lds = 0;  // dynamic LDS the binning kernels may take (per-tile counters)
+    int cus = 1;         // compute units
 };
 std::mutex g_mu;
 DeviceLimits g_dev[64];
@@ -87,6 +88,10 @@ hipError_t device_limits(DeviceLimits &out) {
         e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
         if (e != hipSuccess) return e;
         d.max_lds = (size_t)lds;
+        int cus = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        d.cus = cus > 0 ? cus : 1;
         d.bin_lds = d.max_lds - bin_static_lds_bytes();
         if (d.bin_lds > 65536) {
             e = set_bin_lds_limit(d.bin_lds);
@@ -130,13 +135,14 @@ ivrgs_status check_batch(const ivrgs_batch *b) {
     if (!valid_gauss(b->g)) return IVRGS_E_INVALID;
     if (b->n_jobs < 0 || b->max_job_count < 0 || b->n_records < 0 || b->n_models <= 0) return IVRGS_E_INVALID;
     if (b->n_jobs > 0 && (!b->jobs || !b->cameras || !b->edits)) return IVRGS_E_INVALID;
+    if (b->n_jobs > 65535) return IVRGS_E_SHAPE;  // jobs index a grid dimension
     if (b->n_records >= (int64_t)0xFFFFFFF0) return IVRGS_E_SHAPE;
     return IVRGS_OK;
 }
 
 // Workspace regions.
 struct Layout {
-    size_t key0, val0, key1, val1, hist, rng, counts, grec, queue, total;
+    size_t key0, val0, key1, val1, hist, rng, counts, part, grec, queue, total;
 };
 
 // Records per binning chunk: a multiple of 64 (one wave walks a chunk).
@@ -164,6 +170,8 @@ Layout layout(const ivrgs_batch &b, const ivrgs_params &p) {
     off += align_up(sizeof(uint32_t) * 2 * (size_t)b.n_jobs);
     L.counts = off;
     off += align_up(sizeof(uint32_t) * (size_t)b.n_jobs * chunk_rows(b, chunk_of(p)) * k.tiles_per_job);
+    L.part = off;
+    off += align_up(sizeof(uint32_t) * col_part_words(b, k, chunk_of(p)));
     L.grec = off;
     off += align_up(sizeof(float) * kGradStride * (size_t)b.n_records);
     L.queue = off;
@@ -246,9 +254,10 @@ ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params
     w.hist = reinterpret_cast<uint32_t *>(ws + L.hist);
     w.rng = reinterpret_cast<uint32_t *>(ws + L.rng);
     w.counts = reinterpret_cast<uint32_t *>(ws + L.counts);
+    w.part = reinterpret_cast<uint32_t *>(ws + L.part);
     const int chunk = chunk_of(*params);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipError_t e = launch_bin_sort(*batch, k, proj->rec, proj->rect, proj->depth, *bins, w, chunk, dl.bin_lds, s);
+    hipError_t e = launch_bin_sort(*batch, k, proj->rec, proj->rect, proj->depth, *bins, w, chunk, dl.bin_lds, dl.cus, s);
     if (e == hipSuccess && (params->flags & IVRGS_FLAG_PERSISTENT))
         e = launch_work_queue(bins->tile_start, (int64_t)batch->n_jobs * k.tiles_per_job,
                               reinterpret_cast<uint32_t *>(ws + L.queue), s);

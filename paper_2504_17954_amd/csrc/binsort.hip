@@ -4,18 +4,19 @@
 //    record id) with a segmented LSD radix sort: 8-bit digits, segments of
 //    4096 records per workgroup, every pass stable, the initial order by id.
 //    A digit that is constant over the job's visible records is skipped.
-// 2. Count: one wave per chunk of consecutive records of the depth order
-//    counts, in LDS, the pairs each tile of the job receives from it; the
-//    counts form a [job][tile][chunk] matrix.
+// 2. Count: each workgroup counts, in LDS, the pairs each tile of the job
+//    receives from one chunk of consecutive records of the depth order; the
+//    counts form a [job][chunk][tile] matrix (a chunk's row is contiguous).
 // 3. A column scan over chunks gives every (chunk, tile) its offset inside
 //    the tile's list and each tile its total; one exclusive scan over all
 //    (job, tile) totals gives the list starts, and the pair total is checked
 //    against the capacity on the device.
-// 4. Scatter: each chunk walks its records in depth order and appends every
-//    pair to its tile from a per-tile LDS cursor.  Lanes of one step that
-//    append to the same tile hold different records, in depth order by
-//    lane, and are ranked by lane, so each tile's list comes out in
-//    (depth key, record id) order: no per-tile sort.
+// 4. Scatter: each chunk's workgroup appends its record ids in depth order
+//    from per-tile LDS cursors (one set per wave, each wave taking a quarter
+//    of the chunk).  Lanes of one step that append to the same tile hold
+//    different records, in depth order by lane, and are ranked by lane, so
+//    each tile's list comes out in (depth key, record id) order: no per-tile
+//    sort.
 #include "launch.hpp"
 
 namespace ivrgs {
@@ -258,21 +259,24 @@ __global__ __launch_bounds__(kSegThreads) void k_dsort_scatter(ivrgs_batch b, co
 // ---------------------------------------------------------------------------
 // Binning over the depth order.
 //
-// Visits every (record, tile) pair of the chunk [begin, end) of a job's depth
+// Visits every (record, tile) pair of the range [begin, end) of a job's depth
 // order whose tile the record's ellipse reaches, in depth order.  The work of
 // 64 consecutive records is spread evenly over the lanes: the lanes scan the
 // records' rect areas, then take the flattened (record, tile) items 64 at a
-// time (record-major, so in depth order) and find each item's record by
-// binary search over the scanned offsets.  f(record, tile x, tile y) is
-// called by the lanes of a hit, all lanes of one step together.
+// time (record-major, so in depth order).  Each record that starts inside
+// the current window of 64 items marks its first position in LDS; an item's
+// record is the last mark at or before it (a ballot finds its position), or
+// the record still running from the previous window.  f(record, tile x,
+// tile y) is called by the lanes of a hit, all lanes of one step together.
 struct ExpandLds {
     float4 h0[64], h1[64];  // hit tests of the step's records
     uint32_t off[64];       // exclusive prefix of rect areas
     uint32_t org[64];       // rect origin, x0 | y0 << 16
     uint32_t wid[64];       // rect width in tiles
     uint32_t rid[64];       // record index
+    int32_t mark[64];       // record starting at each position of the current item window, or -1
 };
-constexpr int kBinWaves = 4;  // waves (chunks) per binning workgroup at most
+constexpr int kBinWaves = 4;  // waves per binning workgroup (sharing one chunk)
 
 // Orders a wave's LDS writes before its other lanes' reads.
 __device__ __forceinline__ void wave_lds_sync() {
@@ -281,11 +285,14 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Groups of 64 records start at begin, begin + stride, ... (stride 64: the
+// whole range in order; stride 64 * waves: the waves of a workgroup share it).
 template <typename F>
-__device__ __forceinline__ void for_each_pair(const ivrgs_job &job, int begin, int end, const uint32_t *order,
-                                              const float4 *rec4, const uint2 *rect, ExpandLds &L, F &&f) {
+__device__ __forceinline__ void for_each_pair(const ivrgs_job &job, int begin, int end, int stride,
+                                              const uint32_t *order, const float4 *rec4, const uint2 *rect,
+                                              ExpandLds &L, F &&f) {
     const int lane = threadIdx.x & 63;
-    for (int g0 = begin; g0 < end; g0 += 64) {
+    for (int g0 = begin; g0 < end; g0 += stride) {
         const int l = g0 + lane;
         uint32_t n = 0;
         if (l < end) {
@@ -309,17 +316,22 @@ __device__ __forceinline__ void for_each_pair(const ivrgs_job &job, int begin, i
             const uint32_t o = __shfl_up(incl, d, 64);
             if (lane >= d) incl += o;
         }
-        L.off[lane] = incl - n;
+        const uint32_t my_off = incl - n;
+        L.off[lane] = my_off;
         const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
-        wave_lds_sync();
+        int carry = 0;  // record covering the first item of the window
         for (uint32_t base = 0; base < total; base += 64) {
+            L.mark[lane] = -1;
+            wave_lds_sync();
+            if (n != 0u && my_off >= base && my_off < base + 64u) L.mark[my_off - base] = lane;
+            wave_lds_sync();
+            const int m = L.mark[lane];
+            const uint64_t starts = __ballot(m >= 0);
+            const uint64_t upto = starts & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+            const int j = upto ? __shfl(m, 63 - __clzll(upto), 64) : carry;
+            carry = __builtin_amdgcn_readlane(j, 63);
             const uint32_t idx = base + lane;
             if (idx < total) {
-                // the last record whose offset is <= idx; it has a nonempty rect
-                int j = 0;
-#pragma unroll
-                for (int step = 32; step > 0; step >>= 1)
-                    if (L.off[j + step] <= idx) j += step;
                 const uint32_t t = idx - L.off[j];
                 const uint32_t w = L.wid[j];
                 const uint32_t dy = t / w, dx = t - dy * w;
@@ -334,62 +346,103 @@ __device__ __forceinline__ void for_each_pair(const ivrgs_job &job, int begin, i
     }
 }
 
-// Pairs per tile from each (job, chunk), into counts[job][tile][chunk].  A
-// workgroup of NW waves takes NW consecutive chunks, one per wave, each with
-// its own LDS counters; the NW counts of a tile are adjacent in the matrix.
-template <int NW>
-__global__ __launch_bounds__(NW * 64) void k_chunk_count(ivrgs_batch b, Consts k, const float *__restrict__ rec,
-                                                         const uint2 *__restrict__ rect,
-                                                         const uint32_t *__restrict__ val0,
-                                                         const uint32_t *__restrict__ val1,
-                                                         const uint32_t *__restrict__ rng,
-                                                         uint32_t *__restrict__ counts, int chunk, int n_chunks) {
-    extern __shared__ uint32_t cnt[];  // [NW][tiles]
-    __shared__ ExpandLds L[NW];
+// Pairs per tile from each (job, chunk), into counts[job][chunk][tile].  The
+// four waves of a workgroup share the chunk (the order of counting does not
+// matter) and one set of LDS counters.
+__global__ __launch_bounds__(kBinWaves * 64) void k_chunk_count(ivrgs_batch b, Consts k, const float *__restrict__ rec,
+                                                                const uint2 *__restrict__ rect,
+                                                                const uint32_t *__restrict__ val0,
+                                                                const uint32_t *__restrict__ val1,
+                                                                const uint32_t *__restrict__ rng,
+                                                                uint32_t *__restrict__ counts, int chunk,
+                                                                int n_chunks) {
+    extern __shared__ uint32_t cnt[];  // [tiles]
+    __shared__ ExpandLds L[kBinWaves];
     const ivrgs_job job = b.jobs[blockIdx.y];
-    const int first = blockIdx.x * NW * chunk;
-    if (first >= job.gauss_count) return;
+    const int begin = blockIdx.x * chunk;
+    if (begin >= job.gauss_count) return;
+    const int end = min(begin + chunk, job.gauss_count);
     const int tpj = k.tiles_per_job, tx_n = k.tiles_x;
     const int wave = threadIdx.x >> 6;
-    for (int t = threadIdx.x; t < NW * tpj; t += NW * 64) cnt[t] = 0;
+    for (int t = threadIdx.x; t < tpj; t += kBinWaves * 64) cnt[t] = 0;
     __syncthreads();
-    const int begin = first + wave * chunk;
-    const int end = min(begin + chunk, job.gauss_count);
     const uint32_t *order = depth_order(rng, b.n_jobs, blockIdx.y, val0, val1);
-    uint32_t *c = cnt + wave * tpj;
-    for_each_pair(job, begin, end, order, reinterpret_cast<const float4 *>(rec), rect, L[wave],
-                  [&](uint32_t, int x, int y) { atomicAdd(&c[y * tx_n + x], 1u); });
+    for_each_pair(job, begin + wave * 64, end, kBinWaves * 64, order, reinterpret_cast<const float4 *>(rec), rect,
+                  L[wave], [&](uint32_t, int x, int y) { atomicAdd(&cnt[y * tx_n + x], 1u); });
     __syncthreads();
-    uint32_t *col = counts + (int64_t)blockIdx.y * tpj * n_chunks + blockIdx.x * NW;
-    for (int t = threadIdx.x; t < tpj; t += NW * 64)
-#pragma unroll
-        for (int w = 0; w < NW; ++w) col[(int64_t)t * n_chunks + w] = cnt[w * tpj + t];
+    uint32_t *row = counts + ((int64_t)blockIdx.y * n_chunks + blockIdx.x) * tpj;
+    for (int t = threadIdx.x; t < tpj; t += kBinWaves * 64) row[t] = cnt[t];
 }
 
-// Per (job, tile), one wave: exclusive scan of the tile's counts over the
-// job's chunks (contiguous in memory, in place) and the tile's total.
-__global__ __launch_bounds__(256) void k_col_scan(ivrgs_batch b, Consts k, uint32_t *__restrict__ counts, int chunk,
-                                                  int n_chunks, uint32_t *__restrict__ tile_counts) {
-    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
+// Exclusive scan of every tile's counts down the chunks (a column of the
+// [chunk][tile] matrix), in place, in three steps over segments of `seg`
+// chunks so that the column reads stay coalesced across tiles: the sum of
+// each segment, the scan of the segment sums (giving the tile totals), and
+// the segment-local scan from the segment's start.  Thread = tile.
+constexpr int kColUnroll = 8;
+
+__global__ __launch_bounds__(256) void k_col_sum(ivrgs_batch b, Consts k, const uint32_t *__restrict__ counts,
+                                                 int chunk, int n_chunks, int seg, uint32_t *__restrict__ part,
+                                                 int n_part) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
     if (t >= k.tiles_per_job) return;
-    const ivrgs_job job = b.jobs[blockIdx.y];
+    const ivrgs_job job = b.jobs[blockIdx.z];
     const int rows = (job.gauss_count + chunk - 1) / chunk;
-    uint32_t *col = counts + ((int64_t)blockIdx.y * k.tiles_per_job + t) * n_chunks;
-    uint32_t carry = 0;
-    for (int base = 0; base < rows; base += 64) {
-        const int c = base + lane;
-        const uint32_t v = c < rows ? col[c] : 0u;
-        uint32_t incl = v;
+    const int r0 = blockIdx.y * seg, r1 = min(r0 + seg, rows);
+    const uint32_t *col = counts + (int64_t)blockIdx.z * n_chunks * k.tiles_per_job + t;
+    uint32_t sum = 0;
+    int r = r0;
+    for (; r + kColUnroll <= r1; r += kColUnroll) {
+        uint32_t v[kColUnroll];
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t o = __shfl_up(incl, d, 64);
-            if (lane >= d) incl += o;
-        }
-        if (c < rows) col[c] = carry + incl - v;
-        carry += __shfl(incl, 63, 64);
+        for (int u = 0; u < kColUnroll; ++u) v[u] = col[(int64_t)(r + u) * k.tiles_per_job];
+#pragma unroll
+        for (int u = 0; u < kColUnroll; ++u) sum += v[u];
     }
-    if (lane == 0) tile_counts[(int64_t)blockIdx.y * k.tiles_per_job + t] = carry;
+    for (; r < r1; ++r) sum += col[(int64_t)r * k.tiles_per_job];
+    part[((int64_t)blockIdx.z * n_part + blockIdx.y) * k.tiles_per_job + t] = sum;
+}
+
+__global__ __launch_bounds__(256) void k_col_part_scan(ivrgs_batch b, Consts k, uint32_t *__restrict__ part,
+                                                       int n_part, uint32_t *__restrict__ tile_counts) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= k.tiles_per_job) return;
+    uint32_t *p = part + (int64_t)blockIdx.y * n_part * k.tiles_per_job + t;
+    uint32_t run = 0;
+    for (int i = 0; i < n_part; ++i) {
+        const uint32_t v = p[(int64_t)i * k.tiles_per_job];
+        p[(int64_t)i * k.tiles_per_job] = run;
+        run += v;
+    }
+    tile_counts[(int64_t)blockIdx.y * k.tiles_per_job + t] = run;
+}
+
+__global__ __launch_bounds__(256) void k_col_apply(ivrgs_batch b, Consts k, uint32_t *__restrict__ counts, int chunk,
+                                                   int n_chunks, int seg, const uint32_t *__restrict__ part,
+                                                   int n_part) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= k.tiles_per_job) return;
+    const ivrgs_job job = b.jobs[blockIdx.z];
+    const int rows = (job.gauss_count + chunk - 1) / chunk;
+    const int r0 = blockIdx.y * seg, r1 = min(r0 + seg, rows);
+    uint32_t *col = counts + (int64_t)blockIdx.z * n_chunks * k.tiles_per_job + t;
+    uint32_t run = part[((int64_t)blockIdx.z * n_part + blockIdx.y) * k.tiles_per_job + t];
+    int r = r0;
+    for (; r + kColUnroll <= r1; r += kColUnroll) {
+        uint32_t v[kColUnroll];
+#pragma unroll
+        for (int u = 0; u < kColUnroll; ++u) v[u] = col[(int64_t)(r + u) * k.tiles_per_job];
+#pragma unroll
+        for (int u = 0; u < kColUnroll; ++u) {
+            col[(int64_t)(r + u) * k.tiles_per_job] = run;
+            run += v[u];
+        }
+    }
+    for (; r < r1; ++r) {
+        const uint32_t v = col[(int64_t)r * k.tiles_per_job];
+        col[(int64_t)r * k.tiles_per_job] = run;
+        run += v;
+    }
 }
 
 // Single workgroup: tile counts -> exclusive starts (in place) and the total,
@@ -418,10 +471,16 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t *__restrict__ star
     }
 }
 
-// Each (job, chunk) wave starts its per-tile cursors at the tile's list start
-// plus the chunk's exclusive column prefix and appends its record ids in
-// depth order.  No global atomics.
-template <int NW>
+// Appends each chunk's record ids in depth order.  Two shapes:
+//  - kSplit: one chunk per workgroup; wave w takes the w-th part of the chunk
+//    (whole groups of 64 records), first counts its own pairs per tile, and
+//    the waves' per-tile cursors start at the tile's list start plus the
+//    chunk's column prefix plus the counts of the earlier parts.  Four times
+//    the parallelism for an extra counting pass: for few chunks.
+//  - otherwise: NW consecutive chunks per workgroup, one per wave, each
+//    cursor at the tile's list start plus the chunk's column prefix.
+// Each wave appends its records in order.  No global atomics.
+template <int NW, bool kSplit>
 __global__ __launch_bounds__(NW * 64) void k_scatter(ivrgs_batch b, Consts k, const float *__restrict__ rec,
                                                      const uint2 *__restrict__ rect,
                                                      const uint32_t *__restrict__ val0,
@@ -430,36 +489,61 @@ __global__ __launch_bounds__(NW * 64) void k_scatter(ivrgs_batch b, Consts k, co
                                                      const uint32_t *__restrict__ counts,
                                                      uint32_t *__restrict__ sorted, int chunk, int n_chunks,
                                                      const uint32_t *__restrict__ starts, int64_t n_tiles) {
-    extern __shared__ uint32_t cur[];  // [NW][tiles]
+    extern __shared__ uint32_t cur[];  // [NW][tiles]: counts, then cursors
     __shared__ ExpandLds L[NW];
     if (starts[n_tiles] == 0xFFFFFFFFu) return;  // capacity exceeded
     const ivrgs_job job = b.jobs[blockIdx.y];
-    const int first = blockIdx.x * NW * chunk;
-    if (first >= job.gauss_count) return;
+    const int begin = blockIdx.x * (kSplit ? 1 : NW) * chunk;
+    if (begin >= job.gauss_count) return;
+    const int end = min(begin + chunk, job.gauss_count);
     const int tpj = k.tiles_per_job, tx_n = k.tiles_x;
     const int tile_bits = 32 - __clz(max(tpj - 1, 1));
     const int wave = threadIdx.x >> 6;
-    const uint32_t *col = counts + (int64_t)blockIdx.y * tpj * n_chunks + blockIdx.x * NW;
+    const uint32_t *order = depth_order(rng, b.n_jobs, blockIdx.y, val0, val1);
+    const float4 *rec4 = reinterpret_cast<const float4 *>(rec);
+    uint32_t *c = cur + wave * tpj;
     const uint32_t *st = starts + (int64_t)blockIdx.y * tpj;
-    for (int t = threadIdx.x; t < tpj; t += NW * 64) {
-        const uint32_t s0 = st[t];
+    int qb, qe;
+    if (kSplit) {
+        const int part = (chunk / 64 + NW - 1) / NW * 64;
+        qb = min(begin + wave * part, end);
+        qe = min(qb + part, end);
+        for (int t = threadIdx.x; t < NW * tpj; t += NW * 64) cur[t] = 0;
+        __syncthreads();
+        for_each_pair(job, qb, qe, 64, order, rec4, rect, L[wave],
+                      [&](uint32_t, int x, int y) { atomicAdd(&c[y * tx_n + x], 1u); });
+        __syncthreads();
+        const uint32_t *row = counts + ((int64_t)blockIdx.y * n_chunks + blockIdx.x) * tpj;
+        for (int t = threadIdx.x; t < tpj; t += NW * 64) {
+            uint32_t run = st[t] + row[t];
 #pragma unroll
-        for (int w = 0; w < NW; ++w) cur[w * tpj + t] = s0 + col[(int64_t)t * n_chunks + w];
+            for (int w = 0; w < NW; ++w) {
+                const uint32_t n = cur[w * tpj + t];
+                cur[w * tpj + t] = run;
+                run += n;
+            }
+        }
+    } else {
+        const int ch = blockIdx.x * NW + wave;  // this wave's chunk
+        qb = min(ch * chunk, job.gauss_count);
+        qe = min(qb + chunk, job.gauss_count);
+        const uint32_t *row = counts + ((int64_t)blockIdx.y * n_chunks + blockIdx.x * NW) * tpj;
+        for (int t = threadIdx.x; t < tpj; t += NW * 64) {
+            const uint32_t s0 = st[t];
+#pragma unroll
+            for (int w = 0; w < NW; ++w)
+                if (blockIdx.x * NW + w < n_chunks) cur[w * tpj + t] = s0 + row[(int64_t)w * tpj + t];
+        }
     }
     __syncthreads();
-    const int begin = first + wave * chunk;
-    const int end = min(begin + chunk, job.gauss_count);
-    const uint32_t *order = depth_order(rng, b.n_jobs, blockIdx.y, val0, val1);
-    uint32_t *c = cur + wave * tpj;
-    for_each_pair(job, begin, end, order, reinterpret_cast<const float4 *>(rec), rect, L[wave],
-                  [&](uint32_t r, int x, int y) {
-                      const uint32_t t = (uint32_t)(y * tx_n + x);
-                      const uint64_t m = match_bits(t, tile_bits, __ballot(true));
-                      const uint32_t rank = lanes_below(m);
-                      const uint32_t at = c[t];
-                      sorted[at + rank] = r;
-                      if (rank == 0) c[t] = at + (uint32_t)__popcll(m);
-                  });
+    for_each_pair(job, qb, qe, 64, order, rec4, rect, L[wave], [&](uint32_t r, int x, int y) {
+        const uint32_t t = (uint32_t)(y * tx_n + x);
+        const uint64_t m = match_bits(t, tile_bits, __ballot(true));
+        const uint32_t rank = lanes_below(m);
+        const uint32_t at = c[t];
+        sorted[at + rank] = r;
+        if (rank == 0) c[t] = at + (uint32_t)__popcll(m);
+    });
 }
 
 // Work queue for the persistent render kernels: nonempty tiles ordered by
@@ -511,38 +595,42 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Chunks per job, padded to a multiple of kBinWaves (a workgroup takes up
-// to kBinWaves consecutive chunks).
-int chunk_rows(const ivrgs_batch &b, int chunk) {
-    const int rows = (b.max_job_count + chunk - 1) / chunk;
-    return (rows + kBinWaves - 1) / kBinWaves * kBinWaves;
+int chunk_rows(const ivrgs_batch &b, int chunk) { return (b.max_job_count + chunk - 1) / chunk; }
+
+// Chunks per segment of the column scan: about 32, and at most 64 segments.
+int col_segment(int n_chunks) {
+    const int by_count = (n_chunks + 63) / 64;
+    return by_count > 32 ? by_count : 32;
+}
+
+size_t col_part_words(const ivrgs_batch &b, const Consts &k, int chunk) {
+    const int n_chunks = chunk_rows(b, chunk);
+    const int seg = col_segment(n_chunks);
+    return (size_t)b.n_jobs * ((n_chunks + seg - 1) / seg) * (size_t)k.tiles_per_job;
 }
 
 size_t depth_sort_hist_words(const ivrgs_batch &b) { return (size_t)b.n_jobs * 256 * ((size_t)seg_rows(b) + 1); }
 
 template <int NW>
-static void launch_binning(const ivrgs_batch &b, const Consts &k, const float *rec, const uint2 *rect2,
-                           const ivrgs_bins &bins, const BinWork &w, int chunk, int n_chunks,
-                           int64_t n_tiles, hipStream_t s) {
+static void launch_scatter(const ivrgs_batch &b, const Consts &k, const float *rec, const uint2 *rect2,
+                           const ivrgs_bins &bins, const BinWork &w, int chunk, int n_chunks, int64_t n_tiles,
+                           int cus, hipStream_t s) {
     const size_t lds = sizeof(uint32_t) * NW * (size_t)k.tiles_per_job;
-    const dim3 grid((unsigned)(n_chunks / NW), (unsigned)b.n_jobs);
-    {
-        TimedScope ts(TK_COUNT, s);
-        hipLaunchKernelGGL(k_chunk_count<NW>, grid, dim3(NW * 64), lds, s, b, k, rec, rect2, w.val[0], w.val[1],
-                           w.rng, w.counts, chunk, n_chunks);
-        hipLaunchKernelGGL(k_col_scan, dim3((k.tiles_per_job + 3) / 4, b.n_jobs), dim3(256), 0, s, b, k, w.counts,
-                           chunk, n_chunks, bins.tile_start);
-        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, bins.tile_start, n_tiles, bins.status,
-                           bins.capacity);
+    const int64_t whole = (int64_t)(n_chunks + NW - 1) / NW * b.n_jobs;  // workgroups with one chunk per wave
+    if (NW > 1 && whole < cus) {
+        hipLaunchKernelGGL((k_scatter<NW, true>), dim3((unsigned)n_chunks, (unsigned)b.n_jobs), dim3(NW * 64), lds, s,
+                           b, k, rec, rect2, w.val[0], w.val[1], w.rng, w.counts, bins.sorted, chunk, n_chunks,
+                           bins.tile_start, n_tiles);
+    } else {
+        hipLaunchKernelGGL((k_scatter<NW, false>), dim3((unsigned)((n_chunks + NW - 1) / NW), (unsigned)b.n_jobs),
+                           dim3(NW * 64), lds, s, b, k, rec, rect2, w.val[0], w.val[1], w.rng, w.counts, bins.sorted,
+                           chunk, n_chunks, bins.tile_start, n_tiles);
     }
-    TimedScope ts(TK_SCATTER, s);
-    hipLaunchKernelGGL(k_scatter<NW>, grid, dim3(NW * 64), lds, s, b, k, rec, rect2, w.val[0], w.val[1], w.rng,
-                       w.counts, bins.sorted, chunk, n_chunks, bins.tile_start, n_tiles);
 }
 
 hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *rec, const uint32_t *rect,
                            const uint32_t *depth, const ivrgs_bins &bins, const BinWork &w, int chunk,
-                           size_t bin_lds, hipStream_t s) {
+                           size_t bin_lds, int cus, hipStream_t s) {
     const int64_t n_tiles = (int64_t)b.n_jobs * k.tiles_per_job;
     const int n_chunks = chunk_rows(b, chunk);
     const int n_seg = seg_rows(b);
@@ -563,18 +651,33 @@ hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *r
                                w.val[0], w.key[1], w.val[1], w.rng, shift, w.hist, tot, n_seg);
         }
     }
-    if (n_chunks == 0) {
+    {
         TimedScope ts(TK_COUNT, s);
-        if (n_tiles > 0) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, bins.tile_start, n_tiles, 0u);
+        if (n_chunks > 0) {
+            hipLaunchKernelGGL(k_chunk_count, dim3((unsigned)n_chunks, (unsigned)b.n_jobs), dim3(kBinWaves * 64),
+                               sizeof(uint32_t) * (size_t)k.tiles_per_job, s, b, k, rec, rect2, w.val[0], w.val[1],
+                               w.rng, w.counts, chunk, n_chunks);
+            const int seg = col_segment(n_chunks), n_part = (n_chunks + seg - 1) / seg;
+            const unsigned tg = (unsigned)((k.tiles_per_job + 255) / 256);
+            hipLaunchKernelGGL(k_col_sum, dim3(tg, (unsigned)n_part, (unsigned)b.n_jobs), dim3(256), 0, s, b, k,
+                               w.counts, chunk, n_chunks, seg, w.part, n_part);
+            hipLaunchKernelGGL(k_col_part_scan, dim3(tg, (unsigned)b.n_jobs), dim3(256), 0, s, b, k, w.part, n_part,
+                               bins.tile_start);
+            hipLaunchKernelGGL(k_col_apply, dim3(tg, (unsigned)n_part, (unsigned)b.n_jobs), dim3(256), 0, s, b, k,
+                               w.counts, chunk, n_chunks, seg, w.part, n_part);
+        } else if (n_tiles > 0) {
+            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, bins.tile_start, n_tiles, 0u);
+        }
         hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, bins.tile_start, n_tiles, bins.status,
                            bins.capacity);
-        return hipGetLastError();
     }
-    // as many chunks per workgroup as the per-tile counters allow
+    if (n_chunks == 0) return hipGetLastError();
+    // as many waves per chunk as the per-wave tile counters allow
+    TimedScope ts(TK_SCATTER, s);
     const size_t per_wave = sizeof(uint32_t) * (size_t)k.tiles_per_job;
-    if (4 * per_wave <= bin_lds) launch_binning<4>(b, k, rec, rect2, bins, w, chunk, n_chunks, n_tiles, s);
-    else if (2 * per_wave <= bin_lds) launch_binning<2>(b, k, rec, rect2, bins, w, chunk, n_chunks, n_tiles, s);
-    else launch_binning<1>(b, k, rec, rect2, bins, w, chunk, n_chunks, n_tiles, s);
+    if (4 * per_wave <= bin_lds) launch_scatter<4>(b, k, rec, rect2, bins, w, chunk, n_chunks, n_tiles, cus, s);
+    else if (2 * per_wave <= bin_lds) launch_scatter<2>(b, k, rec, rect2, bins, w, chunk, n_chunks, n_tiles, cus, s);
+    else launch_scatter<1>(b, k, rec, rect2, bins, w, chunk, n_chunks, n_tiles, cus, s);
     return hipGetLastError();
 }
 
@@ -582,18 +685,20 @@ hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *r
 size_t bin_static_lds_bytes() { return kBinWaves * sizeof(ExpandLds); }
 
 template <int NW>
-static hipError_t set_lds(size_t bytes) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_chunk_count<NW>),
+static hipError_t set_scatter_lds(size_t bytes) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_scatter<NW, true>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_scatter<NW>),
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_scatter<NW, false>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 hipError_t set_bin_lds_limit(size_t bytes) {
-    hipError_t e = set_lds<4>(bytes);
-    if (e == hipSuccess) e = set_lds<2>(bytes);
-    if (e == hipSuccess) e = set_lds<1>(bytes);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_chunk_count),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) e = set_scatter_lds<4>(bytes);
+    if (e == hipSuccess) e = set_scatter_lds<2>(bytes);
+    if (e == hipSuccess) e = set_scatter_lds<1>(bytes);
     return e;
 }
 

@@ -22,10 +22,12 @@ struct BinWork {
     uint32_t *key[2], *val[2];  // depth-order ping-pong, one word per record each
     uint32_t *hist;             // depth_sort_hist_words
     uint32_t *rng;              // 2 * n_jobs
-    uint32_t *counts;           // [job][tile][chunk]
+    uint32_t *counts;           // [job][chunk][tile]
+    uint32_t *part;             // col_part_words: per-segment column sums
 };
 int chunk_rows(const ivrgs_batch &b, int chunk);
 size_t depth_sort_hist_words(const ivrgs_batch &b);
+size_t col_part_words(const ivrgs_batch &b, const Consts &k, int chunk);
 
 hipError_t launch_project(const ivrgs_batch &b, const Consts &k, float *rec, uint32_t *rect, uint32_t *depth,
                           hipStream_t s);
@@ -35,7 +37,8 @@ hipError_t launch_compose(const ivrgs_gaussians &src, int64_t offset, int32_t mo
                           const ivrgs_gaussians_mut &out, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *rec, const uint32_t *rect,
-                           const uint32_t *depth, const ivrgs_bins &bins, const BinWork &w, int chunk, size_t bin_lds, hipStream_t s);
+                           const uint32_t *depth, const ivrgs_bins &bins, const BinWork &w, int chunk, size_t bin_lds,
+                           int cus, hipStream_t s);
 size_t bin_static_lds_bytes();
 hipError_t set_bin_lds_limit(size_t bytes);
 hipError_t launch_render_fwd(const Consts &k, int px, int64_t n_tiles, const float *rec, const uint32_t *starts,

@@ -63,6 +63,9 @@ def test_host_validation(lib):
     b.g.n = 0
     b.n_jobs, b.max_job_count, b.n_records = 2, 10, 20
     b.jobs = b.cameras = b.edits = 1  # non-null placeholders, never dereferenced
+    b.n_jobs = 70_000  # beyond a grid dimension
+    assert lib.ivrgs_project(N.ref(b), N.ref(p), None, None) == N.E_SHAPE
+    b.n_jobs = 2
     ws = N.ivrgs_workspace_size(b, p, 1000)
     # two (key, id) arrays per record for the depth order, 9 gradient floats per record
     assert ws >= 4 * 4 * 20 + 9 * 4 * 20

@@ -113,14 +113,14 @@ def test_project_parity(dev):
 
 
 # ------------------------------------------------------------------ bin sort
-def _bin_case(dev, width, height, rects, z, n_jobs=1):
+def _bin_case(dev, width, height, rects, z, n_jobs=1, chunk=0):
     """Run ivrgs_bin_sort on synthetic records and compare with the
     definition: per (job, tile), ids of records whose rect covers it,
     ordered by (depth key bits, id)."""
     n = rects.shape[0]
     per = n // n_jobs
-    s = R.Settings(width, height)
-    rnd = R.Renderer(s, capacity=1 << 16)
+    s = R.Settings(width, height, sort_chunk=chunk)
+    rnd = R.Renderer(s, capacity=1 << 21)
     jobs = R.Jobs.ranges([0] * n_jobs, [0] * n_jobs, [per] * n_jobs)
     planes = {k: torch.zeros((d, per), dtype=torch.float32, device=dev) for k, d in R.PLANE_DIMS.items()}
     batch = rnd.make_batch(planes, None, R.default_edits(dev), R.camera_table([I.look_at((0, -4, 0))]), jobs)
@@ -172,6 +172,24 @@ def test_bin_sort_exact(dev, seed):
     # depth keys with deliberate exact ties and a narrow range
     z = rng.choice(np.linspace(2.5, 5.5, 700).astype(np.float32), n)
     _bin_case(dev, W, H, rects, z, n_jobs=1 if seed == 0 else 3)
+
+
+@pytest.mark.parametrize("chunk", [64, 512])
+def test_bin_sort_many_chunks(dev, chunk):
+    """Enough chunks that each wave of the scatter owns a whole chunk (64
+    records per chunk), and the default chunk where waves share one."""
+    say(f"bin_sort exact, 80k records, {chunk} records per chunk")
+    rng = np.random.default_rng(3)
+    n, W, H = 80_000, 200, 120
+    tx_n, ty_n = 13, 8
+    x0 = rng.integers(0, tx_n, n)
+    y0 = rng.integers(0, ty_n, n)
+    x1 = np.minimum(x0 + rng.integers(1, 4, n), tx_n)
+    y1 = np.minimum(y0 + rng.integers(1, 4, n), ty_n)
+    rects = np.stack([x0, y0, x1, y1], 1).astype(np.int64)
+    rects[rng.random(n) < 0.05] = 0
+    z = rng.choice(np.linspace(2.0, 6.0, 5000).astype(np.float32), n)
+    _bin_case(dev, W, H, rects, z, chunk=chunk)
 
 
 def test_bin_sort_large_tile(dev):
