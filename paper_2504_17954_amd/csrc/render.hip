@@ -231,25 +231,17 @@ __device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__r
         if (base + lane < end) touch = box_hit(make_hit_test(r0, r1, r2), sx, sy, kTile, 4);
         if (base + 64 < end) fetch(base + 64);
         uint64_t m = __ballot(touch);
-        while (m) {
-            const int src = (int)__builtin_ctzll(m);
-            m &= m - 1;
-            const float mx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r0.x), src));
-            const float my = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r0.y), src));
-            const float qa = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r0.z), src));
-            const float qb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r0.w), src));
-            const float qc = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r1.x), src));
+        // Composites the record held by lane `src` whose exponent p2 (and its
+        // power G) are already known; same arithmetic as every other path.
+        auto composite = [&](int src, float p2, float G) {
             const float cut = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r2.z), src));
-            const float dx = px - mx, dy = py - my;
-            const float p2 = splat_exponent(qa, qb, qc, dx, dy);
             // below the cutoff alpha < alpha_min is certain
             const bool pass = alive && p2 >= cut;
-            if (__ballot(pass) == 0ull) continue;  // wave-uniform
+            if (__ballot(pass) == 0ull) return;  // wave-uniform
             const float o = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r1.y), src));
             const float cr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r1.z), src));
             const float cg = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r1.w), src));
             const float cb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r2.x), src));
-            const float G = fast_exp2(p2);
             const float al = fminf(k.alpha_max, o * G);
             const float Tn = T * (1.f - al);
             const bool use = pass && al >= k.alpha_min;
@@ -271,6 +263,32 @@ __device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__r
                     const uint32_t id = __builtin_amdgcn_readlane(rid, src);
                     if (lane == 63) atomicMax(reinterpret_cast<int *>(&maxw[id]), __float_as_int(wm));
                 }
+            }
+        };
+        auto exponent = [&](int src) {
+            const float mx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r0.x), src));
+            const float my = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r0.y), src));
+            const float qa = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r0.z), src));
+            const float qb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r0.w), src));
+            const float qc = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r1.x), src));
+            return splat_exponent(qa, qb, qc, px - mx, py - my);
+        };
+        // two records per step: their exponents and powers are independent
+        // of the compositing order, so they are computed together and the
+        // two dependent compositing steps follow in list order
+        while (m) {
+            const int sa = (int)__builtin_ctzll(m);
+            m &= m - 1;
+            if (m) {
+                const int sb = (int)__builtin_ctzll(m);
+                m &= m - 1;
+                const float pa = exponent(sa), pb = exponent(sb);
+                const float Ga = fast_exp2(pa), Gb = fast_exp2(pb);
+                composite(sa, pa, Ga);
+                composite(sb, pb, Gb);
+            } else {
+                const float pa = exponent(sa);
+                composite(sa, pa, fast_exp2(pa));
             }
             if (__ballot(alive) == 0ull) break;
         }
@@ -425,6 +443,21 @@ __device__ __forceinline__ void bwd_tile(const Consts &k, const float4 *__restri
             cur &= cur - 1;
             return true;
         };
+        // the next record of the walk is read from LDS one step ahead, so its
+        // latency hides behind the current record's arithmetic
+        int pend;
+        float4 pa = make_float4(0.f, 0.f, 0.f, 0.f), pc = pa;
+        float2 pcc = make_float2(0.f, 0.f);
+        auto prefetch = [&]() {
+            if (next(pend)) {
+                pa = s0[pend];
+                pc = s1[pend];
+                pcc = s2[pend];
+            } else {
+                pend = -1;
+            }
+        };
+        prefetch();
         bool more = true;
         while (more) {
             if (__ballot(mine) == 0ull) break;
@@ -436,14 +469,15 @@ __device__ __forceinline__ void bwd_tile(const Consts &k, const float4 *__restri
             for (int g = 0; g < kGroup; ++g) {
                 slot[g] = -1;
                 while (more) {
-                    int ii;
-                    if (!next(ii)) {
+                    if (pend < 0) {
                         more = false;
                         break;
                     }
-                    const float4 a = s0[ii];
-                    const float4 c = s1[ii];
-                    const float2 cc = s2[ii];
+                    const int ii = pend;
+                    const float4 a = pa;
+                    const float4 c = pc;
+                    const float2 cc = pcc;
+                    prefetch();
                     const float cb = cc.x;
                     bool hit = false;
 #pragma unroll
