@@ -41,6 +41,8 @@ SORT_BYTES_PAIR = 4 + 4 + 4 + 4 + 4       # scatter write key+id, sort read key+
 PROJECT_BYTES_G = 84 + 56                  # 21 planes read, record + rect written
 DEPTH_SORT_BYTES_G = 12 + 8 + 3 * 24       # key read, (key, id) written, 3 digit passes of 8 B in + 8 B out (+ hist)
 SCATTER_BYTES_G = 4 + 8 + 48               # order entry, rect, record per Gaussian; then 4 B per pair written
+PROJECT_FLOP_G = 250                       # rotation, covariance, EWA, inverse, shading, bbox
+PROJECT_BWD_FLOP_G = 500
 
 # HBM bytes per launch measured with hardware counters (FETCH_SIZE and
 # WRITE_SIZE, scaled by the same counters on a plain copy of known size),
@@ -227,6 +229,7 @@ def main():
         "render_fwd": ("alu", (FWD_FLOP_EVAL * per_view["evaluated"] + FWD_FLOP_COMP * per_view["composited"]) / 1e12,
                        "TFLOP/s", FP32_VALU_PEAK),
         "depth_sort": ("hbm", DEPTH_SORT_BYTES_G * n / 1e9, "GB/s", HBM_PEAK_GBS),
+        "tile_count": ("hbm", SCATTER_BYTES_G * n / 1e9, "GB/s", HBM_PEAK_GBS),
         "scatter": ("hbm", (SCATTER_BYTES_G * n + 4 * per_view["pairs"]) / 1e9, "GB/s", HBM_PEAK_GBS),
         "project": ("hbm", PROJECT_BYTES_G * n / 1e9, "GB/s", HBM_PEAK_GBS),
         "project_bwd": ("hbm", (84 + 36 + 84) * n / 1e9, "GB/s", HBM_PEAK_GBS),
@@ -247,6 +250,26 @@ def main():
     if bound == "alu":
         roofline["frac_vs_packed_peak"] = round(achieved / FP32_VALU_PEAK_PACKED, 4)
 
+    # whole-step roofline: each stage at the larger of its HBM time and its
+    # FP32 VALU time for its algorithmic work, summed, over the measured step
+    stage_flops = {  # per launch
+        "project": PROJECT_FLOP_G * n, "project_bwd": PROJECT_BWD_FLOP_G * n,
+        "render_fwd": (FWD_FLOP_EVAL * per_view["evaluated"] + FWD_FLOP_COMP * per_view["composited"]),
+        "render_bwd": (BWD_FLOP_EVAL * per_view["evaluated"] + BWD_FLOP_COMP * per_view["composited"]),
+    }
+    ideal_s = 0.0
+    for kname, (_, nl) in kern.items():
+        if not nl or kname not in work and kname not in stage_flops:
+            continue
+        launches_per_step = nl / args.steps
+        t_hbm = work[kname][1] / HBM_PEAK_GBS if kname in work and work[kname][0] == "hbm" else 0.0
+        t_alu = stage_flops.get(kname, 0.0) / (FP32_VALU_PEAK * 1e12)
+        ideal_s += launches_per_step * max(t_hbm, t_alu)
+    step_roofline = {"ideal_ms": round(ideal_s * 1e3, 4), "measured_ms": round(ms_step, 4),
+                     "frac": round(ideal_s * 1e3 / ms_step, 4),
+                     "definition": "sum over stages of max(algorithmic bytes / 8 TB/s, algorithmic flop / "
+                                   "78.6 TFLOP/s) per step, over the measured step time"}
+
     result = {
         "metric": METRIC, "value": round(value, 3), "unit": "iters/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
@@ -259,6 +282,7 @@ def main():
                    "evaluated_per_view": round(per_view["evaluated"]),
                    "composited_per_view": round(per_view["composited"])},
         "roofline": roofline,
+        "step_roofline": step_roofline,
         "kernels_avg_ms": {k: round(a, 4) for k, (a, nl) in avg.items() if nl},
     }
 

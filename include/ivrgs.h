@@ -140,7 +140,7 @@ typedef struct {
     int32_t tile;
     uint32_t flags;
     int32_t fwd_px, bwd_px;
-    int32_t sort_chunk;              /* records per binning chunk (one wave), 0 = default (512) */
+    int32_t sort_chunk;              /* records per binning chunk, 0 = automatic (up to 512) */
     int32_t persist_per_cu;          /* IVRGS_FLAG_PERSISTENT: workgroups per CU, 0 = occupancy */
 } ivrgs_params;
 
@@ -218,8 +218,9 @@ ivrgs_status ivrgs_project(const ivrgs_batch *batch, const ivrgs_params *params,
  * with margins for FP32 rounding), ordered by (depth key, record id).  The
  * records are put in depth order first and binned in that order, so the
  * lists need no sort of their own.  params->sort_chunk is the number of
- * records per binning chunk (0: 512; rounded up to a multiple of 64); it
- * does not change the result.  Writes bins->tile_start, bins->sorted and
+ * records per binning chunk (rounded up to a multiple of 64; 0 picks a power
+ * of two up to 512 that gives about 1024 chunks per batch); it does not
+ * change the result.  Writes bins->tile_start, bins->sorted and
  * bins->status.  Returns IVRGS_E_SHAPE if a job has more tiles than the
  * per-tile counters that fit in one workgroup's LDS (about 37k tiles on a
  * 160 KiB device).  If the pair total exceeds bins->capacity, status[1] gets

@@ -17,13 +17,13 @@ import torch
 from . import native as N
 from . import raster as R
 
-DEFAULT = {"fwd_px": 1, "bwd_px": 1, "sort_chunk": 512, "persistent": False, "persist_per_cu": 0}
+DEFAULT = {"fwd_px": 1, "bwd_px": 1, "sort_chunk": 0, "persistent": False, "persist_per_cu": 0}
 CANDIDATES = [
     dict(DEFAULT),
     {**DEFAULT, "fwd_px": 2},
     {**DEFAULT, "bwd_px": 2},
     {**DEFAULT, "sort_chunk": 256},
-    {**DEFAULT, "sort_chunk": 1024},
+    {**DEFAULT, "sort_chunk": 512},
     {**DEFAULT, "persistent": True},
     {**DEFAULT, "persistent": True, "persist_per_cu": 4},
     {**DEFAULT, "persistent": True, "persist_per_cu": 8},
@@ -66,7 +66,7 @@ def store(k: str, cfg: dict, path=None):
 
 def valid(cfg) -> bool:
     try:
-        return (cfg["fwd_px"] in (1, 2, 4) and cfg["bwd_px"] in (1, 2, 4) and int(cfg["sort_chunk"]) > 0
+        return (cfg["fwd_px"] in (1, 2, 4) and cfg["bwd_px"] in (1, 2, 4) and int(cfg["sort_chunk"]) >= 0
                 and isinstance(cfg["persistent"], bool) and int(cfg["persist_per_cu"]) >= 0)
     except (KeyError, TypeError, ValueError):
         return False

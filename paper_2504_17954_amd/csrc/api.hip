@@ -146,9 +146,18 @@ struct Layout {
 };
 
 // Records per binning chunk: a multiple of 64 (one wave walks a chunk).
-int chunk_of(const ivrgs_params &p) {
-    const int c = p.sort_chunk > 0 ? p.sort_chunk : kDefaultChunk;
-    return (c + 63) / 64 * 64;
+// Records per binning chunk: the caller's choice rounded up to a multiple of
+// 64 (one wave walks a chunk), or by default the largest power of two up to
+// kDefaultChunk that still gives about kChunkTarget chunks over the batch, so
+// that small or culled scenes keep the GPU's waves busy.
+constexpr int64_t kChunkTarget = 1024;
+
+int chunk_of(const ivrgs_params &p, const ivrgs_batch &b) {
+    if (p.sort_chunk > 0) return (p.sort_chunk + 63) / 64 * 64;
+    const int64_t records = (int64_t)b.max_job_count * b.n_jobs;
+    int c = kDefaultChunk;
+    while (c > 64 && records / c < kChunkTarget) c /= 2;
+    return c;
 }
 
 Layout layout(const ivrgs_batch &b, const ivrgs_params &p) {
@@ -169,9 +178,9 @@ Layout layout(const ivrgs_batch &b, const ivrgs_params &p) {
     L.rng = off;
     off += align_up(sizeof(uint32_t) * 2 * (size_t)b.n_jobs);
     L.counts = off;
-    off += align_up(sizeof(uint32_t) * (size_t)b.n_jobs * chunk_rows(b, chunk_of(p)) * k.tiles_per_job);
+    off += align_up(sizeof(uint32_t) * (size_t)b.n_jobs * chunk_rows(b, chunk_of(p, b)) * k.tiles_per_job);
     L.part = off;
-    off += align_up(sizeof(uint32_t) * col_part_words(b, k, chunk_of(p)));
+    off += align_up(sizeof(uint32_t) * col_part_words(b, k, chunk_of(p, b)));
     L.grec = off;
     off += align_up(sizeof(float) * kGradStride * (size_t)b.n_records);
     L.queue = off;
@@ -255,7 +264,7 @@ ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params
     w.rng = reinterpret_cast<uint32_t *>(ws + L.rng);
     w.counts = reinterpret_cast<uint32_t *>(ws + L.counts);
     w.part = reinterpret_cast<uint32_t *>(ws + L.part);
-    const int chunk = chunk_of(*params);
+    const int chunk = chunk_of(*params, *batch);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e = launch_bin_sort(*batch, k, proj->rec, proj->rect, proj->depth, *bins, w, chunk, dl.bin_lds, dl.cus, s);
     if (e == hipSuccess && (params->flags & IVRGS_FLAG_PERSISTENT))

@@ -488,11 +488,18 @@ __global__ __launch_bounds__(NW * 64) void k_scatter(ivrgs_batch b, Consts k, co
                                                      const uint32_t *__restrict__ rng,
                                                      const uint32_t *__restrict__ counts,
                                                      uint32_t *__restrict__ sorted, int chunk, int n_chunks,
-                                                     const uint32_t *__restrict__ starts, int64_t n_tiles) {
+                                                     const uint32_t *__restrict__ starts, int64_t n_tiles,
+                                                     int whole_min) {
     extern __shared__ uint32_t cur[];  // [NW][tiles]: counts, then cursors
     __shared__ ExpandLds L[NW];
     if (starts[n_tiles] == 0xFFFFFFFFu) return;  // capacity exceeded
     const ivrgs_job job = b.jobs[blockIdx.y];
+    // Both shapes are launched; the job's record count on the device picks
+    // the one that works: whole chunks per wave once there are at least
+    // whole_min such workgroups over the batch (estimated from this job).
+    const int rows = (job.gauss_count + chunk - 1) / chunk;
+    const bool whole = NW == 1 || (int64_t)(rows + NW - 1) / NW * b.n_jobs >= whole_min;
+    if (whole == kSplit) return;
     const int begin = blockIdx.x * (kSplit ? 1 : NW) * chunk;
     if (begin >= job.gauss_count) return;
     const int end = min(begin + chunk, job.gauss_count);
@@ -616,16 +623,19 @@ static void launch_scatter(const ivrgs_batch &b, const Consts &k, const float *r
                            const ivrgs_bins &bins, const BinWork &w, int chunk, int n_chunks, int64_t n_tiles,
                            int cus, hipStream_t s) {
     const size_t lds = sizeof(uint32_t) * NW * (size_t)k.tiles_per_job;
-    const int64_t whole = (int64_t)(n_chunks + NW - 1) / NW * b.n_jobs;  // workgroups with one chunk per wave
-    if (NW > 1 && whole < cus) {
+    // the shape is chosen on the device from the job's record count (a
+    // culled job may hold far fewer records than the host's bound), so both
+    // are launched unless even the bound is too small for whole chunks
+    const int whole_min = cus;
+    const int64_t whole_bound = (int64_t)(n_chunks + NW - 1) / NW * b.n_jobs;
+    if (NW > 1)
         hipLaunchKernelGGL((k_scatter<NW, true>), dim3((unsigned)n_chunks, (unsigned)b.n_jobs), dim3(NW * 64), lds, s,
                            b, k, rec, rect2, w.val[0], w.val[1], w.rng, w.counts, bins.sorted, chunk, n_chunks,
-                           bins.tile_start, n_tiles);
-    } else {
+                           bins.tile_start, n_tiles, whole_min);
+    if (NW == 1 || whole_bound >= whole_min)
         hipLaunchKernelGGL((k_scatter<NW, false>), dim3((unsigned)((n_chunks + NW - 1) / NW), (unsigned)b.n_jobs),
                            dim3(NW * 64), lds, s, b, k, rec, rect2, w.val[0], w.val[1], w.rng, w.counts, bins.sorted,
-                           chunk, n_chunks, bins.tile_start, n_tiles);
-    }
+                           chunk, n_chunks, bins.tile_start, n_tiles, whole_min);
 }
 
 hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *rec, const uint32_t *rect,

@@ -17,6 +17,6 @@ def test_store_and_validate(tmp_path):
     A.store("k", dict(A.DEFAULT), p)
     assert A.load_cache(p)["k"] == A.DEFAULT
     assert A.valid(A.DEFAULT)
-    for bad in ({**A.DEFAULT, "fwd_px": 3}, {**A.DEFAULT, "sort_chunk": 0}, {"fwd_px": 1}):
+    for bad in ({**A.DEFAULT, "fwd_px": 3}, {**A.DEFAULT, "sort_chunk": -1}, {"fwd_px": 1}):
         assert not A.valid(bad)
     assert all(A.valid(c) for c in A.CANDIDATES)

@@ -174,7 +174,7 @@ def test_bin_sort_exact(dev, seed):
     _bin_case(dev, W, H, rects, z, n_jobs=1 if seed == 0 else 3)
 
 
-@pytest.mark.parametrize("chunk", [64, 512])
+@pytest.mark.parametrize("chunk", [0, 64, 512])
 def test_bin_sort_many_chunks(dev, chunk):
     """Enough chunks that each wave of the scatter owns a whole chunk (64
     records per chunk), and the default chunk where waves share one."""
