@@ -6,7 +6,9 @@ code with the HIP library; the two only consume the same seeded inputs.
 
 `ivrgs_oracle.c` holds the definition (projection Sec. 3 / Eq. 1, Blinn-Phong
 Eq. 3, compositing Eq. 2, composition and edits Sec. 4.5); this module loads
-it with ctypes and adds the composition step (Sec. 4.5) in numpy FP64.
+it with ctypes and adds the composition step (Sec. 4.5) and the gradients of
+the edit parameters that inverse volume exploration learns (Sec. 4.6) in
+numpy FP64.
 """
 from __future__ import annotations
 
@@ -85,7 +87,7 @@ def lib():
     global _lib
     if _lib is None:
         _lib = C.CDLL(build())
-        for name in ("og_project", "og_jacobian", "og_render", "og_backward"):
+        for name in ("og_project", "og_jacobian", "og_render", "og_backward", "og_light_grad"):
             getattr(_lib, name).restype = C.c_int
         _lib.og_num_threads.restype = C.c_int
     return _lib
@@ -263,6 +265,45 @@ def compose(models_planes, edit_rows):
         mids.append(np.full(n, m, np.int32))
     planes = {k: np.ascontiguousarray(np.concatenate(v, axis=1)) for k, v in out.items()}
     return planes, np.concatenate(mids)
+
+
+def light_grad(planes, cam, params: Params, grad_rec, model_id=None, edits=None):
+    """dL/d(orbital light direction) of each model, [n_models, 3] FP64, with
+    respect to the unnormalised direction stored in the edit row (Sec. 4.6
+    learns the light direction), from the record gradients of backward()."""
+    inp = _Inputs(planes, model_id, edits, cam)
+    gr = np.ascontiguousarray(grad_rec, np.float64).reshape(inp.n, 9)
+    out = np.zeros((inp.edits.shape[0], 3), np.float64)
+    prm = params.c()
+    lib().og_light_grad(*inp.args(), C.byref(prm), gr.ctypes.data_as(C.c_void_p),
+                        out.ctypes.data_as(C.c_void_p))
+    return out
+
+
+def compose_bwd(models_planes, edit_rows, grads):
+    """Gradients of the edit parameters of each model (Sec. 4.5 edits, learned
+    by inverse exploration, Sec. 4.6) from the gradients of the composed set
+    (grads: dict plane -> [d, N] in composition order), FP64:
+      dL/dc_p[m]     = sum_{i in m} dL/dc_v[i]
+      dL/ds_o[m]     = sum_{i in m} dL/do'[i] * o[i]
+      dL/dlambda[m]  = sum_{i in m} dL/dk'[i] * k[i]   (per component)
+      dL/db[m]       = sum_{i in m} dL/dk'[i]
+    Returns [n_models, 12]: palette (3), opacity scale, shade scale (4),
+    shade bias (4), the order of the edit row."""
+    out = np.zeros((len(models_planes), 12), np.float64)
+    off = 0
+    for m, pl in enumerate(models_planes):
+        n = pl["mean"].shape[1]
+        sl = slice(off, off + n)
+        gc = np.asarray(grads["color"], np.float64)[:, sl]
+        go = np.asarray(grads["opacity"], np.float64)[:, sl]
+        gk = np.asarray(grads["shade"], np.float64)[:, sl]
+        out[m, 0:3] = gc.sum(1)
+        out[m, 3] = (go[0] * np.asarray(pl["opacity"], np.float64)[0]).sum()
+        out[m, 4:8] = (gk * np.asarray(pl["shade"], np.float64)).sum(1)
+        out[m, 8:12] = gk.sum(1)
+        off += n
+    return out
 
 
 def l1_loss_grad(rgba, target):

@@ -133,11 +133,13 @@ static void quat_rot(const cplx q[4], cplx R[9])
 /*
  * Project one Gaussian.  p: 21 parameters (complex for the complex step).
  * light: row of the model edit table (dir at [12..14], headlight flag bits
- * at [15]).  Writes the nine record values to rec and, when aux != NULL, the
+ * at [15]); ldir, when not NULL, replaces the row's (unnormalised) orbital
+ * light direction, so that the complex step can differentiate with respect
+ * to it.  Writes the nine record values to rec and, when aux != NULL, the
  * real-valued diagnostics (P_* layout).  Returns 1 if the Gaussian is kept.
  */
 static int project_one(const cplx p[N_PARAM], float z32, const og_camera *cam,
-                       const float *light, const og_params *prm, cplx rec[R_N],
+                       const float *light, const cplx *ldir, const og_params *prm, cplx rec[R_N],
                        double *aux)
 {
     const cplx *mu = p + 0, *ls = p + 3, *q = p + 6, *op = p + 10;
@@ -210,6 +212,9 @@ static int project_one(const cplx p[N_PARAM], float z32, const og_camera *cam,
     memcpy(&head, &light[15], sizeof(head));
     if (head) {
         for (int k = 0; k < 3; ++k) l[k] = v[k];
+    } else if (ldir) {
+        cplx ln = csqrt_pos(ldir[0] * ldir[0] + ldir[1] * ldir[1] + ldir[2] * ldir[2]);
+        for (int k = 0; k < 3; ++k) l[k] = ldir[k] / ln;
     } else {
         double ln = sqrt((double)light[12] * light[12] + (double)light[13] * light[13] +
                          (double)light[14] * light[14]);
@@ -313,7 +318,7 @@ static int project_real(const og_gauss *g, const float *edits, int n_models,
             aux[P_EXTX] = aux[P_EXTY] = -1.0;
             return 0;
         }
-    return project_one(p, z32, cam, light_row(g, edits, n_models, i), prm, rec, aux);
+    return project_one(p, z32, cam, light_row(g, edits, n_models, i), NULL, prm, rec, aux);
 }
 
 /* Exported: per-Gaussian projection diagnostics, out[n][P_WIDTH]. */
@@ -340,7 +345,7 @@ int og_jacobian(const og_gauss *g, const float *edits, int n_models, const og_ca
         double h = 1e-30 * (fabs(pr[k]) > 1.0 ? fabs(pr[k]) : 1.0);
         for (int j = 0; j < N_PARAM; ++j) p[j] = pr[j];
         p[k] = pr[k] + I * h;
-        valid = project_one(p, z32, cam, lr, prm, rec, NULL);
+        valid = project_one(p, z32, cam, lr, NULL, prm, rec, NULL);
         for (int r = 0; r < R_N; ++r) jac[r * N_PARAM + k] = cimag(rec[r]) / h;
     }
     return valid;
@@ -642,6 +647,54 @@ int og_backward(const og_gauss *g, const float *edits, int n_models, const og_ca
     free(gr);
     free(order);
     free(proj);
+    return 0;
+}
+
+/* Exported: gradient of L with respect to each model's orbital light
+ * direction (the unnormalised vector of its edit row; Sec. 4.6 learns the
+ * light direction of the composed scene), given the record gradients
+ * grad_rec[n][9] of og_backward: out[m][3] = sum over the kept Gaussians i of
+ * model m of grad_rec[i] . d rec_i / d dir_m, the derivative by the complex
+ * step of the same projection code.  Headlight models (l = v) get 0. */
+int og_light_grad(const og_gauss *g, const float *edits, int n_models, const og_camera *cam,
+                  const og_params *prm, const double *grad_rec, double *out)
+{
+    int64_t n = g->n;
+    for (int k = 0; k < 3 * n_models; ++k) out[k] = 0.0;
+#pragma omp parallel
+    {
+        double *acc = calloc((size_t)(3 * n_models), sizeof(double));
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < n; ++i) {
+            const double *gr = grad_rec + i * R_N;
+            int any = 0;
+            for (int r = 0; r < R_N; ++r) any |= gr[r] != 0.0;
+            if (!any) continue;
+            int m = g->model_id ? g->model_id[i] : 0;
+            if (m < 0 || m >= n_models) m = 0;
+            const float *lr = edits + 16 * (int64_t)m;
+            int32_t head;
+            memcpy(&head, &lr[15], sizeof(head));
+            if (head) continue;
+            double pr[N_PARAM];
+            cplx p[N_PARAM], rec[R_N];
+            gather_params(g, i, pr);
+            for (int k = 0; k < N_PARAM; ++k) p[k] = pr[k];
+            float z32 = depth_key(cam, g->mean[i], g->mean[g->n + i], g->mean[2 * g->n + i]);
+            for (int k = 0; k < 3; ++k) {
+                cplx ld[3] = {lr[12], lr[13], lr[14]};
+                double h = 1e-30 * (fabs((double)lr[12 + k]) > 1.0 ? fabs((double)lr[12 + k]) : 1.0);
+                ld[k] += I * h;
+                if (!project_one(p, z32, cam, lr, ld, prm, rec, NULL)) break;
+                double d = 0.0;
+                for (int r = 0; r < R_N; ++r) d += gr[r] * (cimag(rec[r]) / h);
+                acc[3 * m + k] += d;
+            }
+        }
+#pragma omp critical
+        for (int k = 0; k < 3 * n_models; ++k) out[k] += acc[k];
+        free(acc);
+    }
     return 0;
 }
 
