@@ -250,15 +250,41 @@ ivrgs_status ivrgs_render_bwd(const ivrgs_batch *batch, const ivrgs_params *para
                               ivrgs_gaussians_mut *grads,
                               void *workspace, size_t workspace_bytes, void *stream);
 
+/* Gradients of the edit parameters that inverse volume exploration learns
+ * for each basic model (Sec. 4.6): the palette colour c_p, the opacity scale
+ * s_o and the light-magnitude transform lambda * (k_a, k_d, k_s, beta) + b
+ * of the composition c_v = c_p + delta-c, o' = s_o o, k' = lambda k + b
+ * (ivrgs_compose).  grads: the gradients of the composed set (as written by
+ * ivrgs_render_bwd, composition order); models: the source models of the
+ * composition (device planes; only opacity and shade are read).  Writes
+ * out_edit_grad[n_models][12] (device, caller-allocated; overwritten):
+ *   [0..2]  dL/dc_p   = sum over the model's Gaussians of dL/dc_v
+ *   [3]     dL/ds_o   = sum dL/do' * o
+ *   [4..7]  dL/dlambda = sum dL/dk' * k   (per component)
+ *   [8..11] dL/db     = sum dL/dk'
+ * Sums are accumulated with float atomics (order unspecified). */
+ivrgs_status ivrgs_compose_bwd(const ivrgs_gaussians *models, int32_t n_models,
+                               const ivrgs_gaussians_mut *grads, float *out_edit_grad, void *stream);
+
+/* Gradient of the loss with respect to each model's orbital light direction
+ * (the unnormalised light_dir of its edit row; Sec. 4.6 learns the light
+ * direction; Eq. 3 uses it normalised): out_light_grad[n_models][3] (device,
+ * caller-allocated; overwritten).  Must follow ivrgs_render_bwd for the same
+ * batch, params, projection and workspace: it reads the record gradients
+ * that call leaves in the workspace.  Headlight models get zeros. */
+ivrgs_status ivrgs_light_bwd(const ivrgs_batch *batch, const ivrgs_params *params,
+                             const ivrgs_projected *proj, float *out_light_grad,
+                             const void *workspace, size_t workspace_bytes, void *stream);
+
 /* Kernel timing (benchmark instrumentation).  While enabled, every kernel
  * the library launches is bracketed by a pair of HIP events recorded on its
  * launch stream; ivrgs_timing_read() waits for those events and returns, per
  * kernel kind, the summed milliseconds and the number of launches since the
  * last enable.  Kinds: 0 project, 1 tile counts (per-chunk counts, column
- * and tile scans, work queue), 2 scatter, 3 tile sort, 4 render_fwd,
- * 5 render_bwd, 6 project_bwd, 7 compose, 8 fills, 9 cull.  Process-wide
- * state; not for concurrent callers. */
-#define IVRGS_TIMING_KINDS 10
+ * and tile scans, work queue), 2 scatter, 3 depth order, 4 render_fwd,
+ * 5 render_bwd, 6 project_bwd, 7 compose, 8 fills, 9 cull, 10 edit and
+ * light gradients.  Process-wide state; not for concurrent callers. */
+#define IVRGS_TIMING_KINDS 11
 void ivrgs_timing_enable(int32_t on);
 int32_t ivrgs_timing_read(double *ms, int64_t *launches);
 

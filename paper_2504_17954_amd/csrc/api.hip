@@ -230,6 +230,43 @@ ivrgs_status ivrgs_compose(const ivrgs_gaussians *models, int32_t n_models, cons
     return IVRGS_OK;
 }
 
+ivrgs_status ivrgs_compose_bwd(const ivrgs_gaussians *models, int32_t n_models, const ivrgs_gaussians_mut *grads,
+                               float *out_edit_grad, void *stream) {
+    if (!models || !grads || !out_edit_grad || n_models <= 0) return IVRGS_E_INVALID;
+    if (!valid_gauss_mut(*grads)) return IVRGS_E_INVALID;
+    int64_t total = 0;
+    for (int m = 0; m < n_models; ++m) {
+        if (!valid_gauss(models[m])) return IVRGS_E_INVALID;
+        total += models[m].n;
+    }
+    if (total != grads->n) return IVRGS_E_SHAPE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(out_edit_grad), 12 * (int64_t)n_models, 0u, s);
+    int64_t off = 0;
+    for (int m = 0; m < n_models && e == hipSuccess; ++m) {
+        e = launch_compose_bwd(models[m], off, *grads, out_edit_grad + 12 * m, s);
+        off += models[m].n;
+    }
+    return hip_status(e);
+}
+
+ivrgs_status ivrgs_light_bwd(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
+                             float *out_light_grad, const void *workspace, size_t workspace_bytes, void *stream) {
+    ivrgs_status st = check_batch(batch);
+    if (st != IVRGS_OK) return st;
+    if ((st = check_params(params)) != IVRGS_OK) return st;
+    if (!proj || !out_light_grad) return IVRGS_E_INVALID;
+    if (batch->n_records > 0 && (!proj->rec || !proj->rect)) return IVRGS_E_INVALID;
+    const Consts k = make_consts(*params);
+    const Layout L = layout(*batch, *params);
+    if (!workspace || workspace_bytes < L.total) return IVRGS_E_CAPACITY;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const float *grec = reinterpret_cast<const float *>(static_cast<const char *>(workspace) + L.grec);
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(out_light_grad), 3 * (int64_t)batch->n_models, 0u, s);
+    if (e == hipSuccess) e = launch_light_bwd(*batch, k, proj->rect, grec, out_light_grad, s);
+    return hip_status(e);
+}
+
 ivrgs_status ivrgs_project(const ivrgs_batch *batch, const ivrgs_params *params, ivrgs_projected *out,
                            void *stream) {
     ivrgs_status st = check_batch(batch);

@@ -7,7 +7,7 @@ namespace ivrgs {
 
 // Kernel-timing hooks (no-ops unless timing is enabled).
 enum TimingKind { TK_PROJECT = 0, TK_COUNT, TK_SCATTER, TK_SORT, TK_FWD, TK_BWD, TK_PROJECT_BWD,
-                  TK_COMPOSE, TK_FILL, TK_CULL, TK_KINDS };
+                  TK_COMPOSE, TK_FILL, TK_CULL, TK_EDIT_BWD, TK_KINDS };
 void timing_begin(int kind, hipStream_t s);
 void timing_end(int kind, hipStream_t s);
 
@@ -36,6 +36,10 @@ hipError_t launch_project_bwd(const ivrgs_batch &b, const Consts &k, const uint3
 hipError_t launch_compose(const ivrgs_gaussians &src, int64_t offset, int32_t model, const ivrgs_model_edit &e,
                           const ivrgs_gaussians_mut &out, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_light_bwd(const ivrgs_batch &b, const Consts &k, const uint32_t *rect, const float *grec,
+                            float *out, hipStream_t s);
+hipError_t launch_compose_bwd(const ivrgs_gaussians &src, int64_t offset, const ivrgs_gaussians_mut &grads,
+                              float *out, hipStream_t s);
 hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *rec, const uint32_t *rect,
                            const uint32_t *depth, const ivrgs_bins &bins, const BinWork &w, int chunk, size_t bin_lds,
                            int cus, hipStream_t s);

@@ -293,6 +293,56 @@ __global__ __launch_bounds__(256) void k_project(ivrgs_batch b, Consts k, float4
     depth[r] = (rc.x | rc.y) ? __float_as_uint(z32) : 0xFFFFFFFFu;
 }
 
+// Shading backward (Eq. 3): from the record's colour gradient gr[GCR..GCB],
+// the gradients with respect to the colour c_v, the coefficients (k_a, k_d,
+// k_s, beta), the unit normal, the unit light direction and (through the
+// half vector only) the unit view direction.
+__device__ __forceinline__ void shade_bwd(const GIn &a, const Fwd &f, const float gr[kGradRec], float g_c[3],
+                                          float g_k[4], float g_nu[3], float g_l[3], float g_v[3]) {
+    // ---- shading: rgb = k_a c + k_d c |n.l| + k_s |n.h|^beta [..]
+    const float anl = fabsf(f.nl);
+    const float gsum = gr[GCR] + gr[GCG] + gr[GCB];
+    const float gcdot = gr[GCR] * a.c[0] + gr[GCG] * a.c[1] + gr[GCB] * a.c[2];
+    g_c[0] = gr[GCR] * (a.k[0] + a.k[1] * anl);
+    g_c[1] = gr[GCG] * (a.k[0] + a.k[1] * anl);
+    g_c[2] = gr[GCB] * (a.k[0] + a.k[1] * anl);
+    g_k[0] = gcdot;
+    g_k[1] = gcdot * anl;
+    g_k[2] = 0.f;
+    g_k[3] = 0.f;
+    float g_h[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) g_nu[i] = g_l[i] = g_v[i] = 0.f;
+    const float sgn_nl = f.nl > 0.f ? 1.f : (f.nl < 0.f ? -1.f : 0.f);
+    const float g_nl = a.k[1] * gcdot * sgn_nl;
+    if (f.spec_on) {
+        const float ah = fabsf(f.nh);
+        g_k[2] = gsum * f.spec_pow;
+        g_k[3] = gsum * a.k[2] * f.spec_pow * logf(ah);
+        const float g_ah = gsum * a.k[2] * a.k[3] * f.spec_pow / ah;  // beta a^(beta-1)
+        const float g_nh = g_ah * (f.nh > 0.f ? 1.f : -1.f);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            g_nu[i] += g_nh * f.h[i];
+            g_h[i] = g_nh * f.nu[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        g_nu[i] += g_nl * f.l[i];
+        g_l[i] += g_nl * f.nu[i];
+    }
+    if (f.hlen > 0.f) {
+        const float hd = f.h[0] * g_h[0] + f.h[1] * g_h[1] + f.h[2] * g_h[2];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const float ghv = (g_h[i] - f.h[i] * hd) / f.hlen;
+            g_v[i] += ghv;
+            g_l[i] += ghv;
+        }
+    }
+}
+
 // ----------------------------------------------------------------------------
 // Backward: record gradients (dL/d mx, my, qa, qb, qc, o, r, g, b) -> the 21
 // parameter gradients, by the chain rule through the forward above.
@@ -326,48 +376,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(ivrgs_batch b, Consts k, co
 
     float g_mu[3] = {0.f, 0.f, 0.f}, g_ls[3], g_q[4], g_n[3], g_c[3], g_k[4];
     const float g_o = gr[GO];
-
-    // ---- shading: rgb = k_a c + k_d c |n.l| + k_s |n.h|^beta [..]
-    const float anl = fabsf(f.nl);
-    const float gsum = gr[GCR] + gr[GCG] + gr[GCB];
-    const float gcdot = gr[GCR] * a.c[0] + gr[GCG] * a.c[1] + gr[GCB] * a.c[2];
-    g_c[0] = gr[GCR] * (a.k[0] + a.k[1] * anl);
-    g_c[1] = gr[GCG] * (a.k[0] + a.k[1] * anl);
-    g_c[2] = gr[GCB] * (a.k[0] + a.k[1] * anl);
-    g_k[0] = gcdot;
-    g_k[1] = gcdot * anl;
-    g_k[2] = 0.f;
-    g_k[3] = 0.f;
-    float g_nu[3] = {0.f, 0.f, 0.f}, g_l[3] = {0.f, 0.f, 0.f}, g_h[3] = {0.f, 0.f, 0.f};
-    const float sgn_nl = f.nl > 0.f ? 1.f : (f.nl < 0.f ? -1.f : 0.f);
-    const float g_nl = a.k[1] * gcdot * sgn_nl;
-    if (f.spec_on) {
-        const float ah = fabsf(f.nh);
-        g_k[2] = gsum * f.spec_pow;
-        g_k[3] = gsum * a.k[2] * f.spec_pow * logf(ah);
-        const float g_ah = gsum * a.k[2] * a.k[3] * f.spec_pow / ah;  // beta a^(beta-1)
-        const float g_nh = g_ah * (f.nh > 0.f ? 1.f : -1.f);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            g_nu[i] += g_nh * f.h[i];
-            g_h[i] = g_nh * f.nu[i];
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        g_nu[i] += g_nl * f.l[i];
-        g_l[i] += g_nl * f.nu[i];
-    }
-    float g_v[3] = {0.f, 0.f, 0.f};
-    if (f.hlen > 0.f) {
-        const float hd = f.h[0] * g_h[0] + f.h[1] * g_h[1] + f.h[2] * g_h[2];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const float ghv = (g_h[i] - f.h[i] * hd) / f.hlen;
-            g_v[i] += ghv;
-            g_l[i] += ghv;
-        }
-    }
+    float g_nu[3], g_l[3], g_v[3];
+    shade_bwd(a, f, gr, g_c, g_k, g_nu, g_l, g_v);
     if (e.headlight) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) g_v[i] += g_l[i];
@@ -536,6 +546,113 @@ __global__ __launch_bounds__(256) void k_compose(ComposeArgs a, ivrgs_gaussians_
 }
 
 // ----------------------------------------------------------------------------
+// Inverse volume exploration (Sec. 4.6) learns, per basic model, the palette
+// colour, the opacity scale and the light-magnitude transform lambda * k + b,
+// and the orbital light direction.  Their gradients are reductions of the
+// per-Gaussian gradients over each model's Gaussians.
+
+// Sum of v over the wave, in every lane.
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// dL/d(light direction of the record's model), the unnormalised vector of
+// the edit row: with l = d / |d|, dL/dd = (dL/dl - l (l . dL/dl)) / |d|.
+// Headlight models get nothing (their light is the view direction).  Waves
+// whose records all belong to one model add one sum per component.
+__global__ __launch_bounds__(256) void k_light_bwd(ivrgs_batch b, Consts k, const uint2 *__restrict__ rect,
+                                                   const float *__restrict__ grec, float *__restrict__ out) {
+    const ivrgs_job job = b.jobs[blockIdx.y];
+    const int local = blockIdx.x * blockDim.x + threadIdx.x;
+    float g[3] = {0.f, 0.f, 0.f};
+    int m = -1;
+    if (local < job.gauss_count) {
+        const int64_t r = (int64_t)job.rec_begin + local;
+        const uint2 rc = rect[r];
+        if (rc.x | rc.y) {
+            float gr[kGradRec];
+            bool any = false;
+#pragma unroll
+            for (int i = 0; i < kGradRec; ++i) {
+                gr[i] = grec[r * kGradStride + i];
+                any |= gr[i] != 0.f;
+            }
+            const int64_t gi = job_gaussian(job, b.gauss_index, local);
+            int mm = b.g.model_id ? b.g.model_id[gi] : 0;
+            mm = (mm >= 0 && mm < b.n_models) ? mm : 0;
+            const ivrgs_model_edit e = b.edits[mm];
+            if (any && !e.headlight) {
+                const Cam cam = load_cam(&b.cameras[job.camera]);
+                const GIn a = load_gaussian(b.g, gi);
+                float cpos[3];
+                camera_center(cam, cpos);
+                Fwd f;
+                forward_gaussian(a, cam, cpos, e, k.lowpass, f);
+                float g_c[3], g_k[4], g_nu[3], g_l[3], g_v[3];
+                shade_bwd(a, f, gr, g_c, g_k, g_nu, g_l, g_v);
+                const float dlen = sqrtf(e.light_dir[0] * e.light_dir[0] + e.light_dir[1] * e.light_dir[1] +
+                                         e.light_dir[2] * e.light_dir[2]);
+                const float ld = f.l[0] * g_l[0] + f.l[1] * g_l[1] + f.l[2] * g_l[2];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) g[i] = (g_l[i] - f.l[i] * ld) / dlen;
+                m = mm;
+            }
+        }
+    }
+    const uint64_t act = __ballot(m >= 0);
+    if (act == 0ull) return;
+    const int m0 = __shfl(m, (int)__builtin_ctzll(act), 64);
+    if (__ballot(m >= 0 && m != m0) == 0ull) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const float s = wave_sum(g[i]);
+            if ((threadIdx.x & 63) == 0) atomicAdd(&out[3 * m0 + i], s);
+        }
+    } else if (m >= 0) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) atomicAdd(&out[3 * m + i], g[i]);
+    }
+}
+
+// One model's 12 edit-parameter gradients (palette 3, opacity scale, shade
+// scale 4, shade bias 4) from the gradients of its slice [offset, offset + n)
+// of the composed set: a grid-stride sum per thread, then the wave, then the
+// workgroup, then one atomic per value per workgroup.
+__global__ __launch_bounds__(256) void k_compose_bwd(ivrgs_gaussians src, int64_t offset,
+                                                     const ivrgs_gaussians_mut grads, float *__restrict__ out) {
+    __shared__ float part[4][12];
+    const int64_t n = src.n, N = grads.n;
+    float v[12];
+#pragma unroll
+    for (int j = 0; j < 12; ++j) v[j] = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = offset + i;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] += grads.color[c * N + o];
+        v[3] = fmaf(grads.opacity[o], src.opacity[i], v[3]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const float gk = grads.shade[c * N + o];
+            v[4 + c] = fmaf(gk, src.shade[c * n + i], v[4 + c]);
+            v[8 + c] += gk;
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+        const float s = wave_sum(v[j]);
+        if (lane == 0) part[wave][j] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 12) {
+        const float s = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] + part[3][threadIdx.x];
+        atomicAdd(&out[threadIdx.x], s);
+    }
+}
+
+// ----------------------------------------------------------------------------
 // host launchers
 hipError_t launch_project(const ivrgs_batch &b, const Consts &k, float *rec, uint32_t *rect, uint32_t *depth,
                           hipStream_t s) {
@@ -576,6 +693,25 @@ hipError_t launch_compose(const ivrgs_gaussians &src, int64_t offset, int32_t mo
     dim3 grid((unsigned)((src.n + 255) / 256));
     TimedScope ts(TK_COMPOSE, s);
     hipLaunchKernelGGL(k_compose, grid, dim3(256), 0, s, a, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_light_bwd(const ivrgs_batch &b, const Consts &k, const uint32_t *rect, const float *grec,
+                            float *out, hipStream_t s) {
+    if (b.n_jobs == 0 || b.max_job_count == 0) return hipSuccess;
+    dim3 grid((b.max_job_count + 255) / 256, b.n_jobs);
+    TimedScope ts(TK_EDIT_BWD, s);
+    hipLaunchKernelGGL(k_light_bwd, grid, dim3(256), 0, s, b, k, reinterpret_cast<const uint2 *>(rect), grec, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_compose_bwd(const ivrgs_gaussians &src, int64_t offset, const ivrgs_gaussians_mut &grads,
+                              float *out, hipStream_t s) {
+    if (src.n == 0) return hipSuccess;
+    const int64_t want = (src.n + 255) / 256;
+    const unsigned blocks = (unsigned)(want < 1024 ? want : 1024);
+    TimedScope ts(TK_EDIT_BWD, s);
+    hipLaunchKernelGGL(k_compose_bwd, dim3(blocks), dim3(256), 0, s, src, offset, grads, out);
     return hipGetLastError();
 }
 

@@ -21,9 +21,9 @@ FLAG_COUNT_EVAL = 2
 EXPORTS = ("ivrgs_workspace_size", "ivrgs_tiles_per_job", "ivrgs_compose", "ivrgs_project",
            "ivrgs_bin_sort", "ivrgs_render_fwd", "ivrgs_render_bwd", "ivrgs_struct_size",
            "ivrgs_status_string", "ivrgs_timing_enable", "ivrgs_timing_read",
-           "ivrgs_cull_workspace_size", "ivrgs_cull")
+           "ivrgs_cull_workspace_size", "ivrgs_cull", "ivrgs_compose_bwd", "ivrgs_light_bwd")
 TIMING_KINDS = ("project", "tile_count", "scatter", "depth_sort", "render_fwd", "render_bwd",
-                "project_bwd", "compose", "fill", "cull")
+                "project_bwd", "compose", "fill", "cull", "edit_bwd")
 
 
 class ivrgs_gaussians(C.Structure):
@@ -117,6 +117,10 @@ def load(path: str = LIB_PATH):
     lib.ivrgs_cull_workspace_size.restype = C.c_size_t
     lib.ivrgs_cull.argtypes = [P, P, C.c_int32, P, P, P, C.c_int32, P, P, C.c_size_t, P]
     lib.ivrgs_cull.restype = C.c_int
+    lib.ivrgs_compose_bwd.argtypes = [P, C.c_int32, P, P, P]
+    lib.ivrgs_compose_bwd.restype = C.c_int
+    lib.ivrgs_light_bwd.argtypes = [P, P, P, P, P, C.c_size_t, P]
+    lib.ivrgs_light_bwd.restype = C.c_int
     lib.ivrgs_timing_enable.argtypes = [C.c_int32]
     lib.ivrgs_timing_enable.restype = None
     lib.ivrgs_timing_read.argtypes = [P, P]
@@ -148,6 +152,17 @@ def ivrgs_compose(models, n_models: int, edits, out, stream):
     arr_e = (ivrgs_model_edit * n_models)(*edits)
     check(load().ivrgs_compose(C.cast(arr_m, C.c_void_p), n_models, C.cast(arr_e, C.c_void_p),
                                ref(out), stream), "ivrgs_compose")
+
+
+def ivrgs_compose_bwd(models, n_models: int, grads, out_ptr, stream):
+    arr_m = (ivrgs_gaussians * n_models)(*models)
+    check(load().ivrgs_compose_bwd(C.cast(arr_m, C.c_void_p), n_models, ref(grads), out_ptr, stream),
+          "ivrgs_compose_bwd")
+
+
+def ivrgs_light_bwd(batch, params, proj, out_ptr, ws_ptr, ws_bytes, stream):
+    check(load().ivrgs_light_bwd(ref(batch), ref(params), ref(proj), out_ptr, ws_ptr, ws_bytes, stream),
+          "ivrgs_light_bwd")
 
 
 def ivrgs_project(batch, params, proj, stream):

@@ -202,8 +202,8 @@ class Renderer:
     @staticmethod
     def make_batch(planes, model_id, edits_t, cams_t, jobs: Jobs, gauss_index=None):
         """Marshal the tensors into an ivrgs_batch.  The struct holds raw
-        device pointers: the caller keeps the tensors alive until the kernels
-        that use it have been enqueued."""
+        device pointers and a reference to every tensor they point into, so
+        the tensors live as long as the struct."""
         g = gaussians_struct(planes, model_id)
         if edits_t is None:
             raise ValueError("an edit table (at least one row) is required")
@@ -231,6 +231,7 @@ class Renderer:
         b.n_jobs = jobs.n_jobs
         b.max_job_count = jobs.max_count
         b.n_records = jobs.n_records
+        b._keep = (planes, model_id, edits_t, cams_t, jobs.device, gauss_index)
         return b
 
     # -- pipeline ---------------------------------------------------------
@@ -283,6 +284,19 @@ class Renderer:
         N.ivrgs_render_bwd(batch, self.settings.params(), proj, bins, rgba.data_ptr(), dl.data_ptr(),
                            gs, self.ws.data_ptr(), self.ws.numel(), _stream())
         return grads
+
+    def light_grad(self, planes, cams_t, jobs: Jobs, model_id=None, edits_t=None, gauss_index=None, out=None):
+        """dL/d(orbital light direction) per model [n_models, 3] for the
+        gradient of the last backward() on the same inputs (reads the record
+        gradients it left in the workspace)."""
+        batch = self.make_batch(planes, model_id, edits_t, cams_t, jobs, gauss_index)
+        self._ensure(batch)
+        proj, _ = self._structs(batch)
+        if out is None:
+            out = torch.empty((batch.n_models, 3), dtype=torch.float32, device=self.device)
+        N.ivrgs_light_bwd(batch, self.settings.params(), proj, out.data_ptr(), self.ws.data_ptr(),
+                          self.ws.numel(), _stream())
+        return out
 
     def verify(self):
         """Raise if the last binning overflowed the pair capacity (syncs)."""
@@ -361,6 +375,21 @@ def compose(models: list, edits, device="cuda"):
     mid = torch.empty(total, dtype=torch.int32, device=device)
     compose_into(models, edits, out, mid)
     return out, mid
+
+
+def compose_bwd(models: list, grads: dict, out=None):
+    """Gradients of each model's edit parameters [n_models, 12] (palette 3,
+    opacity scale, shade scale 4, shade bias 4; Sec. 4.6) from the gradients
+    of the composed set (composition order)."""
+    structs = [gaussians_struct(m) for m in models]
+    total = sum(s.n for s in structs)
+    for k in PLANES:
+        _check_plane(k, grads[k], total)
+    g = N.ivrgs_gaussians(total, *[grads[k].data_ptr() for k in PLANES], None)
+    if out is None:
+        out = torch.empty((len(models), 12), dtype=torch.float32, device=grads["color"].device)
+    N.ivrgs_compose_bwd(structs, len(structs), g, out.data_ptr(), _stream())
+    return out
 
 
 def compose_into(models: list, edits, out: dict, mid: torch.Tensor):
