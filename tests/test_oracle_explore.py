@@ -1,0 +1,122 @@
+"""Pins of the oracle's inverse volume exploration loop (Sec. 4.6): the
+parameter-vector gradient (per-model palette and opacity scale, the shared
+lambda, b and light angles) against central finite differences of the whole
+FP64 pipeline, Adam against its closed forms and a step computed by hand,
+the light-angle convention, and recovery of known parameters.  CPU only."""
+import numpy as np
+
+import oracle as O
+from oracle import explore as X
+from paper_2504_17954_amd import inputs as I
+
+H = 2.0 ** -10
+
+
+def scene(seed=9, K=2, n=40, width=32, height=32, headlight_first=True):
+    rng = np.random.default_rng(seed)
+    models = [I.small_scene(n, seed + 10 * m, log_scale_mu=-2.0, log_scale_sigma=0.3) for m in range(K)]
+    base = []
+    for m in range(K):
+        e = I.identity_edit(models[m])
+        e.headlight = headlight_first and m == 0
+        d = rng.normal(size=3)
+        e.light_dir = (d / np.linalg.norm(d)).astype(np.float32)
+        base.append(e.row())
+    theta = np.concatenate([rng.uniform(0.1, 0.6, 3 * K), rng.uniform(0.7, 1.3, K),
+                            rng.uniform(0.7, 1.3, 4), rng.uniform(-0.1, 0.1, 4), [1.1, 0.4]])
+    cam = I.look_at((0.4, -3.0, 1.2), width=width, height=height)
+    return [m.planes for m in models], np.stack(base), theta, cam
+
+
+def test_param_gradient_matches_finite_differences():
+    planes, base, theta, cam = scene()
+    # thresholds far in the tails: no compositing decision within a step
+    prm = O.Params(32, 32, alpha_min=1e-9, T_min=1e-12, alpha_max=0.999999)
+    dl = np.random.default_rng(3).normal(size=(4, 32, 32))  # linear loss sum(dl * RGBA)
+    g = X.param_grad(planes, base, theta, cam, prm, dl)
+
+    def loss(th):
+        return float((dl * X.render_params(planes, base, th, cam, prm)["rgba"]).sum())
+
+    for j in range(theta.size):
+        up, dn = theta.copy(), theta.copy()
+        up[j] += H
+        dn[j] -= H
+        ref = (loss(up) - loss(dn)) / (2 * H)
+        assert abs(g[j] - ref) <= 2e-3 * abs(ref) + 1e-4 * np.abs(g).max(), (j, g[j], ref)
+    K = len(planes)
+    assert np.abs(g[4 * K + 8:]).min() > 0.0  # the angles do move the image
+
+
+def test_headlight_only_gives_no_angle_gradient():
+    planes, base, theta, cam = scene()
+    base[:, 15] = np.array([1, 1], np.int32).view(np.float32)  # every model on the headlight
+    g = X.param_grad(planes, base, theta, cam, O.Params(32, 32), np.ones((4, 32, 32)))
+    assert np.all(g[-2:] == 0.0)
+
+
+def test_light_angle_convention():
+    np.testing.assert_allclose(X.light_direction(0.0, 1.7), [0, 0, 1], atol=1e-15)
+    np.testing.assert_allclose(X.light_direction(np.pi / 2, 0.0), [1, 0, 0], atol=1e-15)
+    np.testing.assert_allclose(X.light_direction(np.pi / 2, np.pi / 2), [0, 1, 0], atol=1e-15)
+    np.testing.assert_allclose(X.light_direction(np.pi, 0.3), [0, 0, -1], atol=1e-15)
+    planes, base, theta, cam = scene()
+    rows = X.rows_from_params(theta, base)
+    assert np.array_equal(rows[0, 12:16], base[0, 12:16])  # headlight model keeps its row
+    np.testing.assert_allclose(rows[1, 12:15], X.light_direction(theta[-2], theta[-1]), atol=1e-7)
+    assert np.array_equal(rows[:, 4:8], np.tile(theta[8:12].astype(np.float32), (2, 1)))  # shared lambda
+
+
+def test_adam_first_step_and_constant_gradient():
+    """Step 1: m_hat = g and v_hat = g^2, so every entry moves by
+    lr * g / (|g| + eps); under a constant gradient that holds at every step."""
+    rng = np.random.default_rng(1)
+    th = rng.normal(size=7)
+    g = rng.normal(size=7)
+    m = v = np.zeros(7)
+    cur = th
+    for t in range(1, 6):
+        nxt, m, v = X.adam_update(cur, g, m, v, t, lr=0.01, eps=1e-8)
+        np.testing.assert_allclose(cur - nxt, 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-15)
+        cur = nxt
+
+
+def test_adam_two_steps_by_hand():
+    """beta1 0.9, beta2 0.999, eps 0, lr 0.1, gradients 2 then -1:
+    m1 = 0.2, v1 = 0.004, m_hat = 2, v_hat = 4        -> step 0.1
+    m2 = 0.08, v2 = 0.004996, m_hat = 0.08/0.19, v_hat = 0.004996/0.001999
+                                                       -> step 0.0266338..."""
+    th, m, v = X.adam_update([1.0], [2.0], [0.0], [0.0], 1, lr=0.1, eps=0.0)
+    assert abs(th[0] - 0.9) < 1e-15 and abs(m[0] - 0.2) < 1e-15 and abs(v[0] - 0.004) < 1e-15
+    th, m, v = X.adam_update(th, [-1.0], m, v, 2, lr=0.1, eps=0.0)
+    assert abs(m[0] - 0.08) < 1e-15 and abs(v[0] - 0.004996) < 1e-15
+    step2 = 0.1 * (0.08 / 0.19) / np.sqrt(0.004996 / 0.001999)
+    assert abs(step2 - 0.0266338) < 1e-6
+    assert abs(th[0] - (0.9 - step2)) < 1e-14
+
+
+def test_adam_mask_freezes_groups():
+    K = 2
+    mask = X.learn_mask(K, X.LEARN_PALETTE | X.LEARN_LIGHT)
+    assert mask[:6].all() and not mask[6:16].any() and mask[16:].all()
+    th, m, v = X.adam_update(np.ones(18), np.ones(18), np.zeros(18), np.zeros(18), 1, 0.01, mask=mask)
+    assert np.all(th[~mask] == 1.0) and np.all(m[~mask] == 0.0) and np.all(v[~mask] == 0.0)
+
+
+def test_explore_recovers_known_parameters():
+    """Target = render under known parameters; from a perturbed start, Adam
+    at the paper's learning rate lowers the L1 loss and moves the palette and
+    opacity scales toward the known values."""
+    planes, base, truth, cam = scene(seed=21, n=60)
+    prm = O.Params(32, 32)
+    target = X.render_params(planes, base, truth, cam, prm)["rgba"]
+    start = truth.copy()
+    K = len(planes)
+    start[0:3 * K] += 0.15
+    start[3 * K:4 * K] *= 0.7
+    thetas, losses = X.explore(planes, base, start, cam, prm, target, iters=80, lr=0.01,
+                               learn=X.LEARN_PALETTE | X.LEARN_OPACITY)
+    assert losses[-1] < 0.3 * losses[0], (losses[0], losses[-1])
+    err0 = np.abs(start[:4 * K] - truth[:4 * K]).mean()
+    err1 = np.abs(thetas[-1][:4 * K] - truth[:4 * K]).mean()
+    assert err1 < 0.5 * err0, (err0, err1)
