@@ -283,7 +283,8 @@ ivrgs_status ivrgs_light_bwd(const ivrgs_batch *batch, const ivrgs_params *param
  * last enable.  Kinds: 0 project, 1 tile counts (per-chunk counts, column
  * and tile scans, work queue), 2 scatter, 3 depth order, 4 render_fwd,
  * 5 render_bwd, 6 project_bwd, 7 compose, 8 fills, 9 cull, 10 edit and
- * light gradients.  Process-wide state; not for concurrent callers. */
+ * light gradients and the exploration step.  Process-wide state; not for
+ * concurrent callers. */
 #define IVRGS_TIMING_KINDS 11
 void ivrgs_timing_enable(int32_t on);
 int32_t ivrgs_timing_read(double *ms, int64_t *launches);
@@ -318,9 +319,53 @@ ivrgs_status ivrgs_cull(const ivrgs_gaussians *g, const ivrgs_camera *cameras, i
                         const ivrgs_culler *mlp, int32_t *out_index, ivrgs_job *jobs, int32_t job,
                         float *out_logit, void *workspace, size_t workspace_bytes, void *stream);
 
+/* Same as ivrgs_compose, with the edit table in DEVICE memory (edits:
+ * device [n_models]; models: host array as there).  For loops that update the
+ * edit rows on the GPU (ivrgs_explore_step) without a host round trip. */
+ivrgs_status ivrgs_compose_dev(const ivrgs_gaussians *models, int32_t n_models,
+                               const ivrgs_model_edit *edits, ivrgs_gaussians_mut *out, void *stream);
+
+/* Inverse volume exploration (Sec. 4.6): with the Gaussians frozen, learn
+ * per basic model the palette colour c_p and the opacity scale s_o, and for
+ * the composed model one light-magnitude transform lambda, b (R^4 each,
+ * shared by all models) and one orbital light direction given by its polar
+ * and azimuthal angles, d = (sin t cos p, sin t sin p, cos t) in world space.
+ * The optimiser is Adam (Kingma and Ba, 2015).
+ *
+ * State (device float array, ivrgs_explore_state_words(n_models) words,
+ * caller-allocated and initialised; K = n_models, n = 4K + 10):
+ *   [0, n)    parameters: palette[K][3], s_o[K], lambda[4], b[4], t, p
+ *   [n, 2n)   Adam first moments (start at 0)
+ *   [2n, 3n)  Adam second moments (start at 0)
+ *   [3n]      completed steps (starts at 0)
+ * learn: bit 0 palette, bit 1 opacity scale, bit 2 lambda and b, bit 3 light
+ * angles; parameters of an unset group keep their values. */
+typedef struct {
+    float lr, beta1, beta2, eps;
+    uint32_t learn;
+} ivrgs_explore_opts;
+
+int64_t ivrgs_explore_state_words(int32_t n_models);
+
+/* One Adam step of the exploration parameters from the gradients of one
+ * backward: edit_grad (device [K][12], ivrgs_compose_bwd) and light_grad
+ * (device [K][3], ivrgs_light_bwd, or NULL when no model has an orbital
+ * light).  The shared lambda, b and light angles take the sums over the
+ * models; the angles chain through d(t, p).  Then rewrites the edit table
+ * (device [K]) from the parameters: palette, opacity_scale, shade_scale =
+ * lambda, shade_bias = b, and light_dir = d(t, p) for the models whose
+ * headlight word is 0 (headlight words and headlight models' light_dir are
+ * left as they are).  edit_grad may be NULL when learn has none of bits
+ * 0-2.  learn == 0 only rewrites the edit table (no step is counted and the
+ * gradients are not read): the way to initialise it.  One
+ * workgroup; all arrays on the device. */
+ivrgs_status ivrgs_explore_step(const float *edit_grad, const float *light_grad, int32_t n_models,
+                                const ivrgs_explore_opts *opts, float *state, ivrgs_model_edit *edits,
+                                void *stream);
+
 /* sizeof of the ABI structs, for binding checks: which = 0 gaussians,
  * 1 camera, 2 model_edit, 3 job, 4 batch, 5 params, 6 projected, 7 bins,
- * 8 culler. */
+ * 8 culler, 9 explore_opts. */
 int32_t ivrgs_struct_size(int32_t which);
 
 /* Human-readable name of a status code. */

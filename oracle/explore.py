@@ -70,6 +70,17 @@ def param_grad(models_planes, base_rows, theta, cam, prm, dl):
     grads, grad_rec = backward(comp, cam, prm, dl, model_id=mid, edits=rows)
     eg = compose_bwd(models_planes, rows, grads)  # [K, 12]
     lg = light_grad(comp, cam, prm, grad_rec, model_id=mid, edits=rows)  # [K, 3]
+    return assemble(eg, lg, th)
+
+
+def assemble(eg, lg, theta):
+    """Parameter-vector gradient from the per-model edit-row gradients eg
+    [K, 12] (palette 3, opacity scale, shade scale 4, shade bias 4) and the
+    per-model light-direction gradients lg [K, 3]."""
+    eg = np.asarray(eg, np.float64)
+    lg = np.asarray(lg, np.float64)
+    th = np.asarray(theta, np.float64)
+    K = eg.shape[0]
     g = np.zeros(n_params(K))
     g[0:3 * K] = eg[:, 0:3].reshape(-1)
     g[3 * K:4 * K] = eg[:, 3]

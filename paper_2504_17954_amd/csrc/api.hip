@@ -210,9 +210,10 @@ int32_t ivrgs_tiles_per_job(const ivrgs_params *params) {
     return make_consts(*params).tiles_per_job;
 }
 
-ivrgs_status ivrgs_compose(const ivrgs_gaussians *models, int32_t n_models, const ivrgs_model_edit *edits,
-                           ivrgs_gaussians_mut *out, void *stream) {
-    if (!models || !edits || !out || n_models <= 0) return IVRGS_E_INVALID;
+namespace {
+ivrgs_status compose_common(const ivrgs_gaussians *models, int32_t n_models, const ivrgs_model_edit *host_edits,
+                            const ivrgs_model_edit *dev_edits, ivrgs_gaussians_mut *out, void *stream) {
+    if (!models || !out || n_models <= 0) return IVRGS_E_INVALID;
     if (!valid_gauss_mut(*out) || (out->n > 0 && !out->model_id)) return IVRGS_E_INVALID;
     int64_t total = 0;
     for (int m = 0; m < n_models; ++m) {
@@ -223,11 +224,42 @@ ivrgs_status ivrgs_compose(const ivrgs_gaussians *models, int32_t n_models, cons
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     int64_t off = 0;
     for (int m = 0; m < n_models; ++m) {
-        hipError_t e = launch_compose(models[m], off, m, edits[m], *out, s);
+        hipError_t e = launch_compose(models[m], off, m, host_edits ? host_edits + m : nullptr, dev_edits, *out, s);
         if (e != hipSuccess) return IVRGS_E_HIP;
         off += models[m].n;
     }
     return IVRGS_OK;
+}
+}  // namespace
+
+ivrgs_status ivrgs_compose(const ivrgs_gaussians *models, int32_t n_models, const ivrgs_model_edit *edits,
+                           ivrgs_gaussians_mut *out, void *stream) {
+    if (!edits) return IVRGS_E_INVALID;
+    return compose_common(models, n_models, edits, nullptr, out, stream);
+}
+
+ivrgs_status ivrgs_compose_dev(const ivrgs_gaussians *models, int32_t n_models, const ivrgs_model_edit *edits,
+                               ivrgs_gaussians_mut *out, void *stream) {
+    if (!edits) return IVRGS_E_INVALID;
+    return compose_common(models, n_models, nullptr, edits, out, stream);
+}
+
+int64_t ivrgs_explore_state_words(int32_t n_models) {
+    if (n_models <= 0) return 0;
+    return 3 * (4 * (int64_t)n_models + 10) + 1;
+}
+
+ivrgs_status ivrgs_explore_step(const float *edit_grad, const float *light_grad, int32_t n_models,
+                                const ivrgs_explore_opts *opts, float *state, ivrgs_model_edit *edits, void *stream) {
+    if (!opts || !state || !edits || n_models <= 0) return IVRGS_E_INVALID;
+    if (!edit_grad && (opts->learn & 7u)) return IVRGS_E_INVALID;
+    if (n_models > (1 << 20)) return IVRGS_E_SHAPE;
+    if (!(opts->lr >= 0.f) || !(opts->beta1 >= 0.f && opts->beta1 < 1.f) || !(opts->beta2 >= 0.f && opts->beta2 < 1.f) ||
+        !(opts->eps > 0.f) || (opts->learn & ~15u))
+        return IVRGS_E_INVALID;
+    ExploreOpts o = {opts->lr, opts->beta1, opts->beta2, opts->eps, opts->learn};
+    return hip_status(launch_explore_step(edit_grad, light_grad, n_models, o, state, edits,
+                                          reinterpret_cast<hipStream_t>(stream)));
 }
 
 ivrgs_status ivrgs_compose_bwd(const ivrgs_gaussians *models, int32_t n_models, const ivrgs_gaussians_mut *grads,
@@ -430,6 +462,7 @@ int32_t ivrgs_struct_size(int32_t which) {
     case 6: return (int32_t)sizeof(ivrgs_projected);
     case 7: return (int32_t)sizeof(ivrgs_bins);
     case 8: return (int32_t)sizeof(ivrgs_culler);
+    case 9: return (int32_t)sizeof(ivrgs_explore_opts);
     default: return -1;
     }
 }

@@ -33,8 +33,15 @@ hipError_t launch_project(const ivrgs_batch &b, const Consts &k, float *rec, uin
                           hipStream_t s);
 hipError_t launch_project_bwd(const ivrgs_batch &b, const Consts &k, const uint32_t *rect, const float *grec,
                               const ivrgs_gaussians_mut &out, bool atomic, hipStream_t s);
-hipError_t launch_compose(const ivrgs_gaussians &src, int64_t offset, int32_t model, const ivrgs_model_edit &e,
-                          const ivrgs_gaussians_mut &out, hipStream_t s);
+// host_e != nullptr: edit values from the host row; else from dev_table[model].
+hipError_t launch_compose(const ivrgs_gaussians &src, int64_t offset, int32_t model, const ivrgs_model_edit *host_e,
+                          const ivrgs_model_edit *dev_table, const ivrgs_gaussians_mut &out, hipStream_t s);
+struct ExploreOpts {
+    float lr, beta1, beta2, eps;
+    uint32_t learn;
+};
+hipError_t launch_explore_step(const float *edit_grad, const float *light_grad, int n_models, const ExploreOpts &o,
+                               float *state, ivrgs_model_edit *rows, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_light_bwd(const ivrgs_batch &b, const Consts &k, const uint32_t *rect, const float *grec,
                             float *out, hipStream_t s);

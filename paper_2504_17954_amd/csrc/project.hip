@@ -524,10 +524,24 @@ struct ComposeArgs {
     float palette[3], oscale, kscale[4], kbias[4];
 };
 
-__global__ __launch_bounds__(256) void k_compose(ComposeArgs a, ivrgs_gaussians_mut out) {
+// table != nullptr: the edit values come from the device row table[a.model]
+// (the same for every thread; the values in `a` are unused).
+__global__ __launch_bounds__(256) void k_compose(ComposeArgs a, const ivrgs_model_edit *__restrict__ table,
+                                                 ivrgs_gaussians_mut out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = a.src.n;
     if (i >= n) return;
+    if (table) {
+        const ivrgs_model_edit &e = table[a.model];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.palette[c] = e.palette[c];
+        a.oscale = e.opacity_scale;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            a.kscale[c] = e.shade_scale[c];
+            a.kbias[c] = e.shade_bias[c];
+        }
+    }
     const int64_t N = out.n, o = a.offset + i;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -652,6 +666,62 @@ __global__ __launch_bounds__(256) void k_compose_bwd(ivrgs_gaussians src, int64_
     }
 }
 
+// One Adam step (Kingma and Ba, 2015) of the exploration parameters
+// [palette K*3 | s_o K | lambda 4 | b 4 | polar, azimuth], then the edit rows
+// rebuilt from them.  The shared lambda, b and angles sum the per-model
+// gradients; d(t, p) = (sin t cos p, sin t sin p, cos t) gives
+// dL/dt = g.(cos t cos p, cos t sin p, -sin t), dL/dp = g.(-sin t sin p, sin t cos p, 0).
+__global__ __launch_bounds__(256) void k_explore_step(const float *__restrict__ eg, const float *__restrict__ lg,
+                                                      int K, ExploreOpts o, float *__restrict__ st,
+                                                      ivrgs_model_edit *__restrict__ rows) {
+    const int n = 4 * K + 10;
+    float *p = st, *m = st + n, *v = st + 2 * n;
+    const float t = st[3 * n] + 1.f;
+    const float c1 = 1.f - powf(o.beta1, t), c2 = 1.f - powf(o.beta2, t);
+    const float th = p[4 * K + 8], ph = p[4 * K + 9];
+    __syncthreads();  // every wave has read the angles before any update
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const uint32_t group = j < 3 * K ? 1u : j < 4 * K ? 2u : j < 4 * K + 8 ? 4u : 8u;
+        if (!(o.learn & group) || (group == 8u && lg == nullptr)) continue;
+        float g = 0.f;
+        if (group == 1u) {
+            g = eg[(j / 3) * 12 + j % 3];
+        } else if (group == 2u) {
+            g = eg[(j - 3 * K) * 12 + 3];
+        } else if (group == 4u) {
+            const int c = 4 + (j - 4 * K);  // lambda: columns 4..7, b: 8..11
+            for (int k = 0; k < K; ++k) g += eg[k * 12 + c];
+        } else {
+            float gd[3] = {0.f, 0.f, 0.f};
+            for (int k = 0; k < K; ++k)
+                for (int i = 0; i < 3; ++i) gd[i] += lg[k * 3 + i];
+            const float sth = sinf(th), cth = cosf(th), sph = sinf(ph), cph = cosf(ph);
+            g = (j == 4 * K + 8) ? gd[0] * cth * cph + gd[1] * cth * sph - gd[2] * sth
+                                 : -gd[0] * sth * sph + gd[1] * sth * cph;
+        }
+        const float mj = o.beta1 * m[j] + (1.f - o.beta1) * g;
+        const float vj = o.beta2 * v[j] + (1.f - o.beta2) * g * g;
+        m[j] = mj;
+        v[j] = vj;
+        p[j] -= o.lr * (mj / c1) / (sqrtf(vj / c2) + o.eps);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && o.learn != 0u) st[3 * n] = t;
+    const float nth = p[4 * K + 8], nph = p[4 * K + 9];
+    const float d[3] = {sinf(nth) * cosf(nph), sinf(nth) * sinf(nph), cosf(nth)};
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        ivrgs_model_edit &e = rows[k];
+        for (int c = 0; c < 3; ++c) e.palette[c] = p[3 * k + c];
+        e.opacity_scale = p[3 * K + k];
+        for (int c = 0; c < 4; ++c) {
+            e.shade_scale[c] = p[4 * K + c];
+            e.shade_bias[c] = p[4 * K + 4 + c];
+        }
+        if (e.headlight == 0)
+            for (int c = 0; c < 3; ++c) e.light_dir[c] = d[c];
+    }
+}
+
 // ----------------------------------------------------------------------------
 // host launchers
 hipError_t launch_project(const ivrgs_batch &b, const Consts &k, float *rec, uint32_t *rect, uint32_t *depth,
@@ -677,22 +747,24 @@ hipError_t launch_project_bwd(const ivrgs_batch &b, const Consts &k, const uint3
     return hipGetLastError();
 }
 
-hipError_t launch_compose(const ivrgs_gaussians &src, int64_t offset, int32_t model, const ivrgs_model_edit &e,
-                          const ivrgs_gaussians_mut &out, hipStream_t s) {
+hipError_t launch_compose(const ivrgs_gaussians &src, int64_t offset, int32_t model, const ivrgs_model_edit *host_e,
+                          const ivrgs_model_edit *dev_table, const ivrgs_gaussians_mut &out, hipStream_t s) {
     if (src.n == 0) return hipSuccess;
-    ComposeArgs a;
+    ComposeArgs a = {};
     a.src = src;
     a.offset = offset;
     a.model = model;
-    for (int c = 0; c < 3; ++c) a.palette[c] = e.palette[c];
-    a.oscale = e.opacity_scale;
-    for (int c = 0; c < 4; ++c) {
-        a.kscale[c] = e.shade_scale[c];
-        a.kbias[c] = e.shade_bias[c];
+    if (host_e) {
+        for (int c = 0; c < 3; ++c) a.palette[c] = host_e->palette[c];
+        a.oscale = host_e->opacity_scale;
+        for (int c = 0; c < 4; ++c) {
+            a.kscale[c] = host_e->shade_scale[c];
+            a.kbias[c] = host_e->shade_bias[c];
+        }
     }
     dim3 grid((unsigned)((src.n + 255) / 256));
     TimedScope ts(TK_COMPOSE, s);
-    hipLaunchKernelGGL(k_compose, grid, dim3(256), 0, s, a, out);
+    hipLaunchKernelGGL(k_compose, grid, dim3(256), 0, s, a, host_e ? nullptr : dev_table, out);
     return hipGetLastError();
 }
 
@@ -702,6 +774,13 @@ hipError_t launch_light_bwd(const ivrgs_batch &b, const Consts &k, const uint32_
     dim3 grid((b.max_job_count + 255) / 256, b.n_jobs);
     TimedScope ts(TK_EDIT_BWD, s);
     hipLaunchKernelGGL(k_light_bwd, grid, dim3(256), 0, s, b, k, reinterpret_cast<const uint2 *>(rect), grec, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_explore_step(const float *edit_grad, const float *light_grad, int n_models, const ExploreOpts &o,
+                               float *state, ivrgs_model_edit *rows, hipStream_t s) {
+    TimedScope ts(TK_EDIT_BWD, s);
+    hipLaunchKernelGGL(k_explore_step, dim3(1), dim3(256), 0, s, edit_grad, light_grad, n_models, o, state, rows);
     return hipGetLastError();
 }
 

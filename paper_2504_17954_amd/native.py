@@ -21,7 +21,8 @@ FLAG_COUNT_EVAL = 2
 EXPORTS = ("ivrgs_workspace_size", "ivrgs_tiles_per_job", "ivrgs_compose", "ivrgs_project",
            "ivrgs_bin_sort", "ivrgs_render_fwd", "ivrgs_render_bwd", "ivrgs_struct_size",
            "ivrgs_status_string", "ivrgs_timing_enable", "ivrgs_timing_read",
-           "ivrgs_cull_workspace_size", "ivrgs_cull", "ivrgs_compose_bwd", "ivrgs_light_bwd")
+           "ivrgs_cull_workspace_size", "ivrgs_cull", "ivrgs_compose_bwd", "ivrgs_light_bwd",
+           "ivrgs_compose_dev", "ivrgs_explore_state_words", "ivrgs_explore_step")
 TIMING_KINDS = ("project", "tile_count", "scatter", "depth_sort", "render_fwd", "render_bwd",
                 "project_bwd", "compose", "fill", "cull", "edit_bwd")
 
@@ -77,8 +78,13 @@ class ivrgs_culler(C.Structure):
                 ("w3", C.c_void_p), ("b3", C.c_float), ("threshold", C.c_float)]
 
 
+class ivrgs_explore_opts(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("learn", C.c_uint32)]
+
+
 STRUCTS = (ivrgs_gaussians, ivrgs_camera, ivrgs_model_edit, ivrgs_job, ivrgs_batch,
-           ivrgs_params, ivrgs_projected, ivrgs_bins, ivrgs_culler)
+           ivrgs_params, ivrgs_projected, ivrgs_bins, ivrgs_culler, ivrgs_explore_opts)
 
 _lib = None
 
@@ -121,6 +127,12 @@ def load(path: str = LIB_PATH):
     lib.ivrgs_compose_bwd.restype = C.c_int
     lib.ivrgs_light_bwd.argtypes = [P, P, P, P, P, C.c_size_t, P]
     lib.ivrgs_light_bwd.restype = C.c_int
+    lib.ivrgs_compose_dev.argtypes = [P, C.c_int32, P, P, P]
+    lib.ivrgs_compose_dev.restype = C.c_int
+    lib.ivrgs_explore_state_words.argtypes = [C.c_int32]
+    lib.ivrgs_explore_state_words.restype = C.c_int64
+    lib.ivrgs_explore_step.argtypes = [P, P, C.c_int32, P, P, P, P]
+    lib.ivrgs_explore_step.restype = C.c_int
     lib.ivrgs_timing_enable.argtypes = [C.c_int32]
     lib.ivrgs_timing_enable.restype = None
     lib.ivrgs_timing_read.argtypes = [P, P]
@@ -163,6 +175,21 @@ def ivrgs_compose_bwd(models, n_models: int, grads, out_ptr, stream):
 def ivrgs_light_bwd(batch, params, proj, out_ptr, ws_ptr, ws_bytes, stream):
     check(load().ivrgs_light_bwd(ref(batch), ref(params), ref(proj), out_ptr, ws_ptr, ws_bytes, stream),
           "ivrgs_light_bwd")
+
+
+def ivrgs_compose_dev(models, n_models: int, edits_ptr, out, stream):
+    arr_m = (ivrgs_gaussians * n_models)(*models)
+    check(load().ivrgs_compose_dev(C.cast(arr_m, C.c_void_p), n_models, edits_ptr, ref(out), stream),
+          "ivrgs_compose_dev")
+
+
+def ivrgs_explore_state_words(n_models: int) -> int:
+    return int(load().ivrgs_explore_state_words(n_models))
+
+
+def ivrgs_explore_step(edit_grad_ptr, light_grad_ptr, n_models: int, opts, state_ptr, edits_ptr, stream):
+    check(load().ivrgs_explore_step(edit_grad_ptr, light_grad_ptr, n_models, ref(opts), state_ptr, edits_ptr,
+                                    stream), "ivrgs_explore_step")
 
 
 def ivrgs_project(batch, params, proj, stream):
