@@ -125,25 +125,28 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 // return, lanes 2m and 2m+1 both hold the wave total of value m.  Each
 // butterfly level pairs every lane with a partner that holds the same set of
 // value indices, keeps one half of the set and adds the partner's copy of it.
-// Partners at lane distance 32 and 16 cross DPP rows and come from lane
-// shuffles; the rest from DPP (row rotate by 8, half-row mirror, quad
-// permutes).
+// The levels at lane distance 32 and 16 use the permlane swaps: swapping the
+// upper half-wave (odd 16-lane rows) of v[k] with the lower half-wave (even
+// rows) of v[k + half] leaves in the two registers exactly the pair of
+// copies each lane must add, with no select and no trip through LDS.  The
+// rest come from DPP (row rotate by 8, half-row mirror, quad permutes).
 #define IVRGS_DPP(v, ctrl) __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, (v)), (ctrl), 0xF, 0xF, false))
 
 __device__ __forceinline__ float reduce_scatter32(float v[32]) {
     const int lane = lane_id();
-    const bool hi5 = (lane >> 5) & 1, hi4 = (lane >> 4) & 1;
     float a[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        const float keep = hi5 ? v[k + 16] : v[k], send = hi5 ? v[k] : v[k + 16];
-        a[k] = keep + __shfl_xor(send, 32, 64);
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[k]), __float_as_uint(v[k + 16]), false,
+                                                        false);
+        a[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
     float b[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const float keep = hi4 ? a[k + 8] : a[k], send = hi4 ? a[k] : a[k + 8];
-        b[k] = keep + __shfl_xor(send, 16, 64);
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a[k]), __float_as_uint(a[k + 8]), false,
+                                                        false);
+        b[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
     const bool hi3 = (lane >> 3) & 1, hi2 = (lane >> 2) & 1, hi1 = (lane >> 1) & 1;
     float c[4];

@@ -1,14 +1,14 @@
 // Front-to-back compositing (forward) and its recompute-based backward.
 //
 // One workgroup per 16x16 tile; each lane owns PX pixels (PX = 1, 2, 4, so a
-// workgroup has 256/PX threads).  With one pixel per lane the forward runs
-// each wave on its own 16x4 strip: the wave gathers 64 records at a time into
-// registers, tests them against the strip, and composites only the records
-// that can reach it, broadcast lane by lane into scalar registers.  The
-// backward (and the forward with more pixels per lane) gathers each batch of
-// records into LDS for the whole workgroup and walks it by broadcast reads,
-// skipping per wave the records that cannot reach the wave's strip.  A
-// workgroup-wide OR ends the walk once every pixel has terminated.
+// workgroup has 256/PX threads).  With one pixel per lane the forward and the
+// backward run each wave on its own 16x4 strip: the wave gathers 64 records
+// at a time into registers, tests them against the strip, and visits only
+// the records that can reach it, broadcast lane by lane into scalar
+// registers.  With more pixels per lane, each batch of records is gathered
+// into LDS for the whole workgroup and walked by broadcast reads, skipping
+// per wave the records that cannot reach the wave's pixels; a workgroup-wide
+// OR ends the walk once every pixel has terminated.
 // Compositing is plain FP32 VALU work (not a dense contraction), so no matrix
 // cores are involved.
 //
@@ -541,6 +541,158 @@ __device__ __forceinline__ void bwd_tile(const Consts &k, const float4 *__restri
     }
 }
 
+// Backward of one tile with one pixel per lane, each wave on its own (the
+// walk of fwd_tile_wave: 64 records gathered per step into registers, a
+// ballot of the records that can reach the wave's 16x4 strip, fields
+// broadcast from the record's lane).  No LDS and no workgroup barrier, so a
+// wave never waits for the other strips of its tile.  Records that composite
+// somewhere in the wave fill the three slots of one reduce-scatter; their ids
+// are kept in scalar registers for the atomics.
+__device__ __forceinline__ void bwd_tile_wave(const Consts &k, const float4 *__restrict__ rec,
+                                              const uint32_t *__restrict__ starts,
+                                              const uint32_t *__restrict__ sorted, const float *__restrict__ rgba,
+                                              const float *__restrict__ dl, float *__restrict__ grec, int64_t tile) {
+    const TileGeom tg = tile_geom(k, tile);
+    const uint32_t start = starts[tile], end = starts[tile + 1];
+    const int lane = lane_id();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int sx = tg.tx * kTile, sy = tg.ty * kTile + 4 * wave;
+    const int x = sx + (lane & 15), y = sy + (lane >> 4);
+    bool alive = x < k.width && y < k.height;
+    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+    const size_t plane = (size_t)k.width * k.height;
+    // per pixel: upstream colour gradient g, g . out, gA T_final and the
+    // running g . P_i of the composited prefix (as in bwd_tile)
+    float T = 1.f, gP = 0.f, go = 0.f, gATf = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
+    if (alive) {
+        const float *img = rgba + (size_t)tg.job * 4 * plane;
+        const float *gimg = dl + (size_t)tg.job * 4 * plane;
+        const size_t o = (size_t)y * k.width + x;
+        const float Tf = 1.f - img[3 * plane + o];
+        g0 = gimg[o];
+        g1 = gimg[plane + o];
+        g2 = gimg[2 * plane + o];
+        const float gA = gimg[3 * plane + o];
+        go = fmaf(g2, img[2 * plane + o], fmaf(g1, img[plane + o], g0 * img[o]));
+        gATf = gA * Tf;
+        alive = (g0 != 0.f) | (g1 != 0.f) | (g2 != 0.f) | (gA != 0.f);
+    }
+    constexpr int kGroup = 3;
+    const int my_m = lane >> 1;
+    const bool my_slot = ((lane & 1) == 0) && my_m < kGroup * kGradRec;
+    const int my_g = my_m / kGradRec, my_v = my_m % kGradRec;
+
+    // records of the current step (r*, rid) and of the next one (n*, nid)
+    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0, n0 = r0, n1 = r0, n2 = r0;
+    uint32_t rid = 0, nid = 0;
+    uint32_t nbase = start;  // list position of the records held in n*
+    auto fetch = [&]() {
+        const uint32_t idx = nbase + lane;
+        if (idx < end) {
+            nid = sorted[idx];
+            n0 = rec[3 * (size_t)nid];
+            n1 = rec[3 * (size_t)nid + 1];
+            n2 = rec[3 * (size_t)nid + 2];
+        }
+    };
+    if (start < end) fetch();
+    uint64_t m = 0;
+    // the next record that can reach the strip (its lane in r*), moving on to
+    // the next 64 records when the current ones are used up; false at the end
+    auto next = [&](int &src) -> bool {
+        while (m == 0ull) {
+            if (nbase >= end) return false;
+            r0 = n0;
+            r1 = n1;
+            r2 = n2;
+            rid = nid;
+            const bool touch = nbase + lane < end && box_hit(make_hit_test(r0, r1, r2), sx, sy, kTile, 4);
+            nbase += 64;
+            if (nbase < end) fetch();
+            m = __ballot(touch);
+        }
+        src = (int)__builtin_ctzll(m);
+        m &= m - 1;
+        return true;
+    };
+    auto bcast = [&](float v, int src) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src)); };
+
+    bool more = __ballot(alive) != 0ull;
+    while (more) {
+        float acc[32];
+#pragma unroll
+        for (int q = 0; q < 32; ++q) acc[q] = 0.f;
+        uint32_t ids[kGroup];
+        bool filled[kGroup];
+#pragma unroll
+        for (int g = 0; g < kGroup; ++g) {
+            filled[g] = false;
+            ids[g] = 0;
+            while (more) {
+                int src;
+                if (!next(src)) {
+                    more = false;
+                    break;
+                }
+                const float mx = bcast(r0.x, src), my = bcast(r0.y, src);
+                const float qa = bcast(r0.z, src), qb = bcast(r0.w, src), qc = bcast(r1.x, src);
+                const float dx = px - mx, dy = py - my;
+                const float p2 = splat_exponent(qa, qb, qc, dx, dy);
+                // below the cutoff alpha < alpha_min is certain
+                const bool pass = alive && p2 >= bcast(r2.z, src);
+                if (__ballot(pass) == 0ull) continue;  // wave-uniform
+                const float o = bcast(r1.y, src), cr = bcast(r1.z, src), cg = bcast(r1.w, src);
+                const float cb = bcast(r2.x, src);
+                // branch-free from here, with the same arithmetic as the
+                // forward: a lane that does not composite adds zero-weight
+                // terms (all operands finite)
+                const float G = fast_exp2(p2);
+                const float raw = o * G;
+                const float al = fminf(k.alpha_max, raw);
+                const float Tn = T * (1.f - al);
+                const bool use = pass && al >= k.alpha_min;
+                const bool stop = use && Tn < k.T_min;
+                const bool comp = use && !stop;
+                const float w = comp ? al * T : 0.f;
+                const float gc = fmaf(g2, cb, fmaf(g1, cg, g0 * cr));
+                gP = fmaf(w, gc, gP);
+                // g . (colour behind this Gaussian, background included)
+                const float gb = go - gP;
+                const float inv = __builtin_amdgcn_rcpf(1.f - al);
+                const float dLda = comp ? T * gc - (gb - gATf) * inv : 0.f;
+                // no gradient through alpha where the cap is active
+                const float dLdo = raw <= k.alpha_max ? dLda : 0.f;
+                float *ag = acc + g * kGradRec;
+                ag[GCR] = fmaf(w, g0, ag[GCR]);
+                ag[GCG] = fmaf(w, g1, ag[GCG]);
+                ag[GCB] = fmaf(w, g2, ag[GCB]);
+                ag[GO] = fmaf(dLdo, G, ag[GO]);
+                const float dp = dLdo * raw * kLn2;
+                ag[GQA] = fmaf(dp, dx * dx, ag[GQA]);
+                ag[GQB] = fmaf(dp, dx * dy, ag[GQB]);
+                ag[GQC] = fmaf(dp, dy * dy, ag[GQC]);
+                ag[GX] = fmaf(-dp, fmaf(2.f * qa, dx, qb * dy), ag[GX]);
+                ag[GY] = fmaf(-dp, fmaf(qb, dx, 2.f * qc * dy), ag[GY]);
+                T = comp ? Tn : T;
+                alive = alive && !stop;
+                const bool hit = __ballot(comp) != 0ull;
+                if (__ballot(alive) == 0ull) more = false;  // every pixel of the wave is done
+                if (hit) {
+                    filled[g] = true;
+                    ids[g] = __builtin_amdgcn_readlane(rid, src);
+                    break;
+                }
+            }
+        }
+        if (filled[0]) {
+            const float tot = reduce_scatter32(acc);
+            const bool ok = my_g == 0 ? filled[0] : (my_g == 1 ? filled[1] : filled[2]);
+            const uint32_t id = my_g == 0 ? ids[0] : (my_g == 1 ? ids[1] : ids[2]);
+            if (my_slot && ok && tot != 0.f) atomicAdd(&grec[(size_t)id * kGradStride + my_v], tot);
+        }
+    }
+}
+
 template <int PX>
 __global__ __launch_bounds__(kTilePix / PX) void k_render_bwd(Consts k, const float4 *__restrict__ rec,
                                                              const uint32_t *__restrict__ starts,
@@ -548,7 +700,8 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_bwd(Consts k, const fl
                                                              const float *__restrict__ rgba,
                                                              const float *__restrict__ dl, float *__restrict__ grec) {
     if (starts[n_tiles] == 0xFFFFFFFFu) return;
-    bwd_tile<PX>(k, rec, starts, sorted, rgba, dl, grec, blockIdx.x);
+    if constexpr (PX == 1) bwd_tile_wave(k, rec, starts, sorted, rgba, dl, grec, blockIdx.x);
+    else bwd_tile<PX>(k, rec, starts, sorted, rgba, dl, grec, blockIdx.x);
 }
 
 template <int PX>
@@ -559,7 +712,10 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_bwd_persistent(
     if (starts[n_tiles] == 0xFFFFFFFFu) return;
     const uint32_t n_items = queue[1];
     uint32_t item;
-    while (next_item(queue, n_items, item)) bwd_tile<PX>(k, rec, starts, sorted, rgba, dl, grec, queue[2 + item]);
+    while (next_item(queue, n_items, item)) {
+        if constexpr (PX == 1) bwd_tile_wave(k, rec, starts, sorted, rgba, dl, grec, queue[2 + item]);
+        else bwd_tile<PX>(k, rec, starts, sorted, rgba, dl, grec, queue[2 + item]);
+    }
 }
 
 // ----------------------------------------------------------------------------
