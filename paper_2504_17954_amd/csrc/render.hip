@@ -2,13 +2,15 @@
 //
 // One workgroup per 16x16 tile; each lane owns PX pixels (PX = 1, 2, 4, so a
 // workgroup has 256/PX threads).  With one pixel per lane the forward and the
-// backward run each wave on its own 16x4 strip: the wave gathers 64 records
-// at a time into registers, tests them against the strip, and visits only
-// the records that can reach it, broadcast lane by lane into scalar
-// registers.  With more pixels per lane, each batch of records is gathered
-// into LDS for the whole workgroup and walked by broadcast reads, skipping
-// per wave the records that cannot reach the wave's pixels; a workgroup-wide
-// OR ends the walk once every pixel has terminated.
+// backward run each wave on its own 8x8 quadrant of the tile: the wave
+// gathers 64 records at a time into registers, tests them against the
+// quadrant, and visits only the records that can reach it, broadcast lane by
+// lane into scalar registers (the backward with PX > 1 pixels per lane does
+// the same on a 16 x 4PX strip).  The
+// forward with more pixels per lane gathers each batch of records into LDS
+// for the whole workgroup and walks it by broadcast reads, skipping per wave
+// the records that cannot reach the wave's pixels; a workgroup-wide OR ends
+// the walk once every pixel has terminated.
 // Compositing is plain FP32 VALU work (not a dense contraction), so no matrix
 // cores are involved.
 //
@@ -186,10 +188,10 @@ __device__ __forceinline__ void fwd_tile(const Consts &k, const float4 *__restri
 }
 
 // Forward of one tile with one pixel per lane, each wave on its own.  Wave
-// w owns the 16x4 strip of rows 4w .. 4w+3 and walks the tile's list 64
-// records at a time: every lane gathers one record into registers and tests
-// it against the strip (the conservative ellipse-box test of the binning),
-// a ballot gives the records that can reach the strip, and the wave visits
+// w owns the 8x8 quadrant (w % 2, w / 2) of the tile and walks the tile's
+// list 64 records at a time: every lane gathers one record into registers
+// and tests it against the quadrant (the conservative ellipse-box test of the
+// binning), a ballot gives the records that can reach it, and the wave visits
 // only those, in list order, broadcasting each record's fields from its
 // lane into scalar registers.  The next 64 records are loaded while the
 // current ones are composited.  No LDS and no workgroup barrier: a wave
@@ -203,8 +205,8 @@ __device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__r
     const uint32_t start = starts[tile], end = starts[tile + 1];
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int sx = tg.tx * kTile, sy = tg.ty * kTile + 4 * wave;
-    const int x = sx + (lane & 15), y = sy + (lane >> 4);
+    const int sx = tg.tx * kTile + 8 * (wave & 1), sy = tg.ty * kTile + 8 * (wave >> 1);
+    const int x = sx + (lane & 7), y = sy + (lane >> 3);
     bool alive = x < k.width && y < k.height;
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
@@ -228,7 +230,7 @@ __device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__r
         const float4 r0 = n0, r1 = n1, r2 = n2;
         const uint32_t rid = nid;
         bool touch = false;
-        if (base + lane < end) touch = box_hit(make_hit_test(r0, r1, r2), sx, sy, kTile, 4);
+        if (base + lane < end) touch = box_hit(make_hit_test(r0, r1, r2), sx, sy, 8, 8);
         if (base + 64 < end) fetch(base + 64);
         uint64_t m = __ballot(touch);
         // Composites the record held by lane `src` whose exponent p2 (and its
@@ -349,205 +351,18 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_fwd_persistent(
 }
 
 // ----------------------------------------------------------------------------
-// Backward of one tile (the whole workgroup takes part).
+// Backward of one tile, each wave on its own region (the walk of
+// fwd_tile_wave: 64 records gathered per step into registers, a ballot of the
+// records that can reach the region, fields broadcast from the record's
+// lane).  With one pixel per lane the region is the 8x8 quadrant of the
+// forward; with PX > 1, wave w owns the 16 x 4PX strip of rows 4PX w ..
+// 4PX (w+1) - 1 and lane l its pixels (l % 16, l / 16 + 4j), j < PX, so every
+// broadcast, test and reduce-scatter serves PX pixels.  No LDS
+// and no workgroup barrier, so a wave never waits for the other regions of
+// its tile.  Records that composite somewhere in the region fill the three
+// slots of one reduce-scatter; their ids are kept in scalar registers for
+// the atomics.
 template <int PX>
-__device__ __forceinline__ void bwd_tile(const Consts &k, const float4 *__restrict__ rec,
-                                         const uint32_t *__restrict__ starts, const uint32_t *__restrict__ sorted,
-                                         const float *__restrict__ rgba, const float *__restrict__ dl,
-                                         float *__restrict__ grec, int64_t tile) {
-    constexpr int NT = kTilePix / PX;
-    __shared__ float4 s0[NT], s1[NT];
-    __shared__ float2 s2[NT];
-    __shared__ uint32_t sid[NT];
-    __shared__ uint32_t smask[NT];  // bit w: the record can reach wave w's pixels
-    const TileGeom tg = tile_geom(k, tile);
-    const uint32_t start = starts[tile], end = starts[tile + 1];
-    const size_t plane = (size_t)k.width * k.height;
-    const float *img = rgba + (size_t)tg.job * 4 * plane;
-    const float *gimg = dl + (size_t)tg.job * 4 * plane;
-
-    // Per pixel: the upstream colour gradient g, gA T_final, g . out, and the
-    // running g . P_i with P_i the composited prefix, so that g . (colour
-    // behind Gaussian i) = g . out - g . P_i needs no per-channel prefix.
-    float px[PX], py[PX], T[PX], gP[PX], go[PX], gATf[PX], g0[PX], g1[PX], g2[PX];
-    bool alive[PX];
-    // after the reduce-scatter, lane pair (2m, 2m+1) holds value m = g * 9 + v
-    // of Gaussian g of the group; the even lane issues the atomic
-    constexpr int kGroup = 3;
-    const int my_m = lane_id() >> 1;
-    const bool my_slot = ((lane_id() & 1) == 0) && my_m < kGroup * kGradRec;
-    const int my_g = my_m / kGradRec, my_v = my_m % kGradRec;
-#pragma unroll
-    for (int j = 0; j < PX; ++j) {
-        int x, y;
-        pixel_of<PX>(tg, j, x, y);
-        alive[j] = x < k.width && y < k.height;
-        px[j] = (float)x + 0.5f;
-        py[j] = (float)y + 0.5f;
-        T[j] = 1.f;
-        gP[j] = go[j] = gATf[j] = g0[j] = g1[j] = g2[j] = 0.f;
-        if (alive[j]) {
-            const size_t o = (size_t)y * k.width + x;
-            const float Tf = 1.f - img[3 * plane + o];
-            g0[j] = gimg[o];
-            g1[j] = gimg[plane + o];
-            g2[j] = gimg[2 * plane + o];
-            const float gA = gimg[3 * plane + o];
-            go[j] = fmaf(g2[j], img[2 * plane + o], fmaf(g1[j], img[plane + o], g0[j] * img[o]));
-            gATf[j] = gA * Tf;
-            // a pixel with no upstream gradient contributes nothing
-            alive[j] = (g0[j] != 0.f) | (g1[j] != 0.f) | (g2[j] != 0.f) | (gA != 0.f);
-        }
-    }
-    for (uint32_t base = start; base < end; base += NT) {
-        bool mine = false;
-#pragma unroll
-        for (int j = 0; j < PX; ++j) mine |= alive[j];
-        if (!__syncthreads_or(mine)) break;
-        const uint32_t idx = base + threadIdx.x;
-        if (idx < end) {
-            const uint32_t r = sorted[idx];
-            const float4 r0 = rec[3 * (size_t)r], r1 = rec[3 * (size_t)r + 1], r2 = rec[3 * (size_t)r + 2];
-            s0[threadIdx.x] = r0;
-            s1[threadIdx.x] = r1;
-            s2[threadIdx.x] = make_float2(r2.x, r2.z);
-            sid[threadIdx.x] = r;
-            smask[threadIdx.x] = wave_mask<PX>(tg, r0, r1, r2);
-        }
-        __syncthreads();
-        const int cnt = min((uint32_t)NT, end - base);
-        const uint32_t my_bit = __builtin_amdgcn_readfirstlane(1u << (threadIdx.x >> 6));  // wave-uniform
-        // The batch records that can reach this wave's strip, as a bitmask
-        // (one 64-bit word per 64 records, wave-uniform), walked in list
-        // order.  The next kGroup records that composite somewhere in the
-        // wave fill the slots of one reduce-scatter; records that do not are
-        // passed over.
-        constexpr int NWORD = NT / 64;
-        uint64_t words[NWORD];
-#pragma unroll
-        for (int q = 0; q < NWORD; ++q) {
-            const int at = q * 64 + lane_id();
-            words[q] = __ballot(at < cnt && (smask[at] & my_bit) != 0u);
-        }
-        int word = 0;
-        uint64_t cur = words[0];
-        // next record of the walk, or false at the end of the batch
-        auto next = [&](int &ii) -> bool {
-            while (cur == 0ull) {
-                if (++word >= NWORD) return false;
-#pragma unroll
-                for (int q = 1; q < NWORD; ++q)
-                    if (word == q) cur = words[q];
-            }
-            ii = word * 64 + (int)__builtin_ctzll(cur);
-            cur &= cur - 1;
-            return true;
-        };
-        // the next record of the walk is read from LDS one step ahead, so its
-        // latency hides behind the current record's arithmetic
-        int pend;
-        float4 pa = make_float4(0.f, 0.f, 0.f, 0.f), pc = pa;
-        float2 pcc = make_float2(0.f, 0.f);
-        auto prefetch = [&]() {
-            if (next(pend)) {
-                pa = s0[pend];
-                pc = s1[pend];
-                pcc = s2[pend];
-            } else {
-                pend = -1;
-            }
-        };
-        prefetch();
-        bool more = true;
-        while (more) {
-            if (__ballot(mine) == 0ull) break;
-            float acc[32];
-#pragma unroll
-            for (int q = 0; q < 32; ++q) acc[q] = 0.f;
-            int slot[kGroup];
-#pragma unroll
-            for (int g = 0; g < kGroup; ++g) {
-                slot[g] = -1;
-                while (more) {
-                    if (pend < 0) {
-                        more = false;
-                        break;
-                    }
-                    const int ii = pend;
-                    const float4 a = pa;
-                    const float4 c = pc;
-                    const float2 cc = pcc;
-                    prefetch();
-                    const float cb = cc.x;
-                    bool hit = false;
-#pragma unroll
-                    for (int j = 0; j < PX; ++j) {
-                        const float dx = px[j] - a.x, dy = py[j] - a.y;
-                        const float p2 = splat_exponent(a.z, a.w, c.x, dx, dy);
-                        // below the cutoff alpha < alpha_min is certain
-                        const bool pass = alive[j] && p2 >= cc.y;
-                        if (__ballot(pass) == 0ull) continue;  // wave-uniform
-                        // branch-free from here, with the same arithmetic as
-                        // the forward: a lane that does not composite adds
-                        // zero-weight terms (all operands finite), so a slot
-                        // whose record composites nowhere stays zero
-                        const float G = fast_exp2(p2);
-                        const float raw = c.y * G;
-                        const float al = fminf(k.alpha_max, raw);
-                        const float Tn = T[j] * (1.f - al);
-                        const bool use = pass && al >= k.alpha_min;
-                        const bool stop = use && Tn < k.T_min;
-                        const bool comp = use && !stop;
-                        const float w = comp ? al * T[j] : 0.f;
-                        const float gc = fmaf(g2[j], cb, fmaf(g1[j], c.w, g0[j] * c.z));
-                        gP[j] = fmaf(w, gc, gP[j]);
-                        // g . (colour behind this Gaussian, background included)
-                        const float gb = go[j] - gP[j];
-                        const float inv = __builtin_amdgcn_rcpf(1.f - al);
-                        const float dLda = comp ? T[j] * gc - (gb - gATf[j]) * inv : 0.f;
-                        // no gradient through alpha where the cap is active
-                        const float dLdo = raw <= k.alpha_max ? dLda : 0.f;
-                        float *ag = acc + g * kGradRec;
-                        ag[GCR] = fmaf(w, g0[j], ag[GCR]);
-                        ag[GCG] = fmaf(w, g1[j], ag[GCG]);
-                        ag[GCB] = fmaf(w, g2[j], ag[GCB]);
-                        ag[GO] = fmaf(dLdo, G, ag[GO]);
-                        const float dp = dLdo * raw * kLn2;
-                        ag[GQA] = fmaf(dp, dx * dx, ag[GQA]);
-                        ag[GQB] = fmaf(dp, dx * dy, ag[GQB]);
-                        ag[GQC] = fmaf(dp, dy * dy, ag[GQC]);
-                        ag[GX] = fmaf(-dp, fmaf(2.f * a.z, dx, a.w * dy), ag[GX]);
-                        ag[GY] = fmaf(-dp, fmaf(a.w, dx, 2.f * c.x * dy), ag[GY]);
-                        hit = hit || comp;
-                        T[j] = comp ? Tn : T[j];
-                        alive[j] = alive[j] && !stop;
-                    }
-                    mine = false;
-#pragma unroll
-                    for (int j = 0; j < PX; ++j) mine |= alive[j];
-                    const bool filled = __ballot(hit) != 0ull;
-                    if (filled) slot[g] = ii;
-                    if (__ballot(mine) == 0ull) more = false;  // every pixel of the wave is done
-                    if (filled) break;
-                }
-            }
-            if (slot[0] >= 0) {
-                const float tot = reduce_scatter32(acc);
-                const int mine_slot = my_g == 0 ? slot[0] : (my_g == 1 ? slot[1] : slot[2]);
-                if (my_slot && mine_slot >= 0 && tot != 0.f)
-                    atomicAdd(&grec[(size_t)sid[mine_slot] * kGradStride + my_v], tot);
-            }
-        }
-    }
-}
-
-// Backward of one tile with one pixel per lane, each wave on its own (the
-// walk of fwd_tile_wave: 64 records gathered per step into registers, a
-// ballot of the records that can reach the wave's 16x4 strip, fields
-// broadcast from the record's lane).  No LDS and no workgroup barrier, so a
-// wave never waits for the other strips of its tile.  Records that composite
-// somewhere in the wave fill the three slots of one reduce-scatter; their ids
-// are kept in scalar registers for the atomics.
 __device__ __forceinline__ void bwd_tile_wave(const Consts &k, const float4 *__restrict__ rec,
                                               const uint32_t *__restrict__ starts,
                                               const uint32_t *__restrict__ sorted, const float *__restrict__ rgba,
@@ -556,27 +371,45 @@ __device__ __forceinline__ void bwd_tile_wave(const Consts &k, const float4 *__r
     const uint32_t start = starts[tile], end = starts[tile + 1];
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int sx = tg.tx * kTile, sy = tg.ty * kTile + 4 * wave;
-    const int x = sx + (lane & 15), y = sy + (lane >> 4);
-    bool alive = x < k.width && y < k.height;
-    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+    // the wave's region: with one pixel per lane the 8x8 quadrant w of the
+    // tile (the most compact shape, so the fewest records reach it), else the
+    // 16 x 4PX strip w
+    constexpr int RW = PX == 1 ? 8 : kTile, RH = PX == 1 ? 8 : 4 * PX;
+    const int sx = tg.tx * kTile + (PX == 1 ? 8 * (wave & 1) : 0);
+    const int sy = tg.ty * kTile + (PX == 1 ? 8 * (wave >> 1) : RH * wave);
     const size_t plane = (size_t)k.width * k.height;
     // per pixel: upstream colour gradient g, g . out, gA T_final and the
     // running g . P_i of the composited prefix (as in bwd_tile)
-    float T = 1.f, gP = 0.f, go = 0.f, gATf = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
-    if (alive) {
-        const float *img = rgba + (size_t)tg.job * 4 * plane;
-        const float *gimg = dl + (size_t)tg.job * 4 * plane;
-        const size_t o = (size_t)y * k.width + x;
-        const float Tf = 1.f - img[3 * plane + o];
-        g0 = gimg[o];
-        g1 = gimg[plane + o];
-        g2 = gimg[2 * plane + o];
-        const float gA = gimg[3 * plane + o];
-        go = fmaf(g2, img[2 * plane + o], fmaf(g1, img[plane + o], g0 * img[o]));
-        gATf = gA * Tf;
-        alive = (g0 != 0.f) | (g1 != 0.f) | (g2 != 0.f) | (gA != 0.f);
+    float px[PX], py[PX], T[PX], gP[PX], go[PX], gATf[PX], g0[PX], g1[PX], g2[PX];
+    bool alive[PX];
+#pragma unroll
+    for (int j = 0; j < PX; ++j) {
+        const int x = sx + lane % RW, y = sy + lane / RW + (64 / RW) * j;
+        px[j] = (float)x + 0.5f;
+        py[j] = (float)y + 0.5f;
+        T[j] = 1.f;
+        gP[j] = go[j] = gATf[j] = g0[j] = g1[j] = g2[j] = 0.f;
+        alive[j] = x < k.width && y < k.height;
+        if (alive[j]) {
+            const float *img = rgba + (size_t)tg.job * 4 * plane;
+            const float *gimg = dl + (size_t)tg.job * 4 * plane;
+            const size_t o = (size_t)y * k.width + x;
+            const float Tf = 1.f - img[3 * plane + o];
+            g0[j] = gimg[o];
+            g1[j] = gimg[plane + o];
+            g2[j] = gimg[2 * plane + o];
+            const float gA = gimg[3 * plane + o];
+            go[j] = fmaf(g2[j], img[2 * plane + o], fmaf(g1[j], img[plane + o], g0[j] * img[o]));
+            gATf[j] = gA * Tf;
+            alive[j] = (g0[j] != 0.f) | (g1[j] != 0.f) | (g2[j] != 0.f) | (gA != 0.f);
+        }
     }
+    auto any_alive = [&]() {
+        bool a = false;
+#pragma unroll
+        for (int j = 0; j < PX; ++j) a |= alive[j];
+        return __ballot(a) != 0ull;
+    };
     constexpr int kGroup = 3;
     const int my_m = lane >> 1;
     const bool my_slot = ((lane & 1) == 0) && my_m < kGroup * kGradRec;
@@ -597,7 +430,7 @@ __device__ __forceinline__ void bwd_tile_wave(const Consts &k, const float4 *__r
     };
     if (start < end) fetch();
     uint64_t m = 0;
-    // the next record that can reach the strip (its lane in r*), moving on to
+    // the next record that can reach the region (its lane in r*), moving on to
     // the next 64 records when the current ones are used up; false at the end
     auto next = [&](int &src) -> bool {
         while (m == 0ull) {
@@ -606,7 +439,7 @@ __device__ __forceinline__ void bwd_tile_wave(const Consts &k, const float4 *__r
             r1 = n1;
             r2 = n2;
             rid = nid;
-            const bool touch = nbase + lane < end && box_hit(make_hit_test(r0, r1, r2), sx, sy, kTile, 4);
+            const bool touch = nbase + lane < end && box_hit(make_hit_test(r0, r1, r2), sx, sy, RW, RH);
             nbase += 64;
             if (nbase < end) fetch();
             m = __ballot(touch);
@@ -617,7 +450,7 @@ __device__ __forceinline__ void bwd_tile_wave(const Consts &k, const float4 *__r
     };
     auto bcast = [&](float v, int src) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src)); };
 
-    bool more = __ballot(alive) != 0ull;
+    bool more = any_alive();
     while (more) {
         float acc[32];
 #pragma unroll
@@ -636,47 +469,60 @@ __device__ __forceinline__ void bwd_tile_wave(const Consts &k, const float4 *__r
                 }
                 const float mx = bcast(r0.x, src), my = bcast(r0.y, src);
                 const float qa = bcast(r0.z, src), qb = bcast(r0.w, src), qc = bcast(r1.x, src);
-                const float dx = px - mx, dy = py - my;
-                const float p2 = splat_exponent(qa, qb, qc, dx, dy);
-                // below the cutoff alpha < alpha_min is certain
-                const bool pass = alive && p2 >= bcast(r2.z, src);
-                if (__ballot(pass) == 0ull) continue;  // wave-uniform
+                const float cut = bcast(r2.z, src);
+                float dx[PX], dy[PX], p2[PX];
+                bool pass[PX], anyp = false;
+#pragma unroll
+                for (int j = 0; j < PX; ++j) {
+                    dx[j] = px[j] - mx;
+                    dy[j] = py[j] - my;
+                    p2[j] = splat_exponent(qa, qb, qc, dx[j], dy[j]);
+                    // below the cutoff alpha < alpha_min is certain
+                    pass[j] = alive[j] && p2[j] >= cut;
+                    anyp |= pass[j];
+                }
+                if (__ballot(anyp) == 0ull) continue;  // wave-uniform
                 const float o = bcast(r1.y, src), cr = bcast(r1.z, src), cg = bcast(r1.w, src);
                 const float cb = bcast(r2.x, src);
-                // branch-free from here, with the same arithmetic as the
-                // forward: a lane that does not composite adds zero-weight
-                // terms (all operands finite)
-                const float G = fast_exp2(p2);
-                const float raw = o * G;
-                const float al = fminf(k.alpha_max, raw);
-                const float Tn = T * (1.f - al);
-                const bool use = pass && al >= k.alpha_min;
-                const bool stop = use && Tn < k.T_min;
-                const bool comp = use && !stop;
-                const float w = comp ? al * T : 0.f;
-                const float gc = fmaf(g2, cb, fmaf(g1, cg, g0 * cr));
-                gP = fmaf(w, gc, gP);
-                // g . (colour behind this Gaussian, background included)
-                const float gb = go - gP;
-                const float inv = __builtin_amdgcn_rcpf(1.f - al);
-                const float dLda = comp ? T * gc - (gb - gATf) * inv : 0.f;
-                // no gradient through alpha where the cap is active
-                const float dLdo = raw <= k.alpha_max ? dLda : 0.f;
+                bool anyc = false;
                 float *ag = acc + g * kGradRec;
-                ag[GCR] = fmaf(w, g0, ag[GCR]);
-                ag[GCG] = fmaf(w, g1, ag[GCG]);
-                ag[GCB] = fmaf(w, g2, ag[GCB]);
-                ag[GO] = fmaf(dLdo, G, ag[GO]);
-                const float dp = dLdo * raw * kLn2;
-                ag[GQA] = fmaf(dp, dx * dx, ag[GQA]);
-                ag[GQB] = fmaf(dp, dx * dy, ag[GQB]);
-                ag[GQC] = fmaf(dp, dy * dy, ag[GQC]);
-                ag[GX] = fmaf(-dp, fmaf(2.f * qa, dx, qb * dy), ag[GX]);
-                ag[GY] = fmaf(-dp, fmaf(qb, dx, 2.f * qc * dy), ag[GY]);
-                T = comp ? Tn : T;
-                alive = alive && !stop;
-                const bool hit = __ballot(comp) != 0ull;
-                if (__ballot(alive) == 0ull) more = false;  // every pixel of the wave is done
+#pragma unroll
+                for (int j = 0; j < PX; ++j) {
+                    // branch-free, with the same arithmetic as the forward: a
+                    // pixel that does not composite adds zero-weight terms
+                    // (all operands finite)
+                    const float G = fast_exp2(p2[j]);
+                    const float raw = o * G;
+                    const float al = fminf(k.alpha_max, raw);
+                    const float Tn = T[j] * (1.f - al);
+                    const bool use = pass[j] && al >= k.alpha_min;
+                    const bool stop = use && Tn < k.T_min;
+                    const bool comp = use && !stop;
+                    const float w = comp ? al * T[j] : 0.f;
+                    const float gc = fmaf(g2[j], cb, fmaf(g1[j], cg, g0[j] * cr));
+                    gP[j] = fmaf(w, gc, gP[j]);
+                    // g . (colour behind this Gaussian, background included)
+                    const float gb = go[j] - gP[j];
+                    const float inv = __builtin_amdgcn_rcpf(1.f - al);
+                    const float dLda = comp ? T[j] * gc - (gb - gATf[j]) * inv : 0.f;
+                    // no gradient through alpha where the cap is active
+                    const float dLdo = raw <= k.alpha_max ? dLda : 0.f;
+                    ag[GCR] = fmaf(w, g0[j], ag[GCR]);
+                    ag[GCG] = fmaf(w, g1[j], ag[GCG]);
+                    ag[GCB] = fmaf(w, g2[j], ag[GCB]);
+                    ag[GO] = fmaf(dLdo, G, ag[GO]);
+                    const float dp = dLdo * raw * kLn2;
+                    ag[GQA] = fmaf(dp, dx[j] * dx[j], ag[GQA]);
+                    ag[GQB] = fmaf(dp, dx[j] * dy[j], ag[GQB]);
+                    ag[GQC] = fmaf(dp, dy[j] * dy[j], ag[GQC]);
+                    ag[GX] = fmaf(-dp, fmaf(2.f * qa, dx[j], qb * dy[j]), ag[GX]);
+                    ag[GY] = fmaf(-dp, fmaf(qb, dx[j], 2.f * qc * dy[j]), ag[GY]);
+                    T[j] = comp ? Tn : T[j];
+                    alive[j] = alive[j] && !stop;
+                    anyc |= comp;
+                }
+                const bool hit = __ballot(anyc) != 0ull;
+                if (!any_alive()) more = false;  // every pixel of the wave is done
                 if (hit) {
                     filled[g] = true;
                     ids[g] = __builtin_amdgcn_readlane(rid, src);
@@ -700,8 +546,7 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_bwd(Consts k, const fl
                                                              const float *__restrict__ rgba,
                                                              const float *__restrict__ dl, float *__restrict__ grec) {
     if (starts[n_tiles] == 0xFFFFFFFFu) return;
-    if constexpr (PX == 1) bwd_tile_wave(k, rec, starts, sorted, rgba, dl, grec, blockIdx.x);
-    else bwd_tile<PX>(k, rec, starts, sorted, rgba, dl, grec, blockIdx.x);
+    bwd_tile_wave<PX>(k, rec, starts, sorted, rgba, dl, grec, blockIdx.x);
 }
 
 template <int PX>
@@ -713,8 +558,7 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_bwd_persistent(
     const uint32_t n_items = queue[1];
     uint32_t item;
     while (next_item(queue, n_items, item)) {
-        if constexpr (PX == 1) bwd_tile_wave(k, rec, starts, sorted, rgba, dl, grec, queue[2 + item]);
-        else bwd_tile<PX>(k, rec, starts, sorted, rgba, dl, grec, queue[2 + item]);
+        bwd_tile_wave<PX>(k, rec, starts, sorted, rgba, dl, grec, queue[2 + item]);
     }
 }
 
