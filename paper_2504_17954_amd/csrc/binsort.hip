@@ -58,14 +58,23 @@ int seg_rows(const ivrgs_batch &b) { return (b.max_job_count + kSeg - 1) / kSeg;
 
 // AND and OR of the depth keys of each job's visible records (rng[j] and
 // rng[n_jobs + j], preset to ~0 and 0).  Culled records carry the key ~0.
+constexpr int kRangeBlocks = 64;  // workgroups per job for the key range
+
+__global__ void k_rng_init(uint32_t *__restrict__ rng, int n_jobs) {
+    for (int i = threadIdx.x; i < 2 * n_jobs; i += blockDim.x) rng[i] = i < n_jobs ? 0xFFFFFFFFu : 0u;
+}
+
+// Grid-stride over the job's records; the four waves combine in LDS so each
+// workgroup adds one AND and one OR (at most kRangeBlocks same-address
+// atomics per job: they serialise in L2).
 __global__ __launch_bounds__(kSegThreads) void k_dkey_range(ivrgs_batch b, const uint32_t *__restrict__ depth,
                                                             uint32_t *__restrict__ rng) {
+    __shared__ uint32_t sa[kSegThreads / 64], so[kSegThreads / 64];
     const ivrgs_job job = b.jobs[blockIdx.y];
-    const int64_t base = (int64_t)blockIdx.x * kSeg;
-    if (base >= job.gauss_count) return;
     uint32_t a = 0xFFFFFFFFu, o = 0u;
-    for (int i = threadIdx.x; i < kSeg && base + i < job.gauss_count; i += kSegThreads) {
-        const uint32_t z = depth[(int64_t)job.rec_begin + base + i];
+    for (int64_t i = (int64_t)blockIdx.x * kSegThreads + threadIdx.x; i < job.gauss_count;
+         i += (int64_t)gridDim.x * kSegThreads) {
+        const uint32_t z = depth[(int64_t)job.rec_begin + i];
         if (z != 0xFFFFFFFFu) {
             a &= z;
             o |= z;
@@ -77,8 +86,17 @@ __global__ __launch_bounds__(kSegThreads) void k_dkey_range(ivrgs_batch b, const
         o |= __shfl_xor(o, d, 64);
     }
     if ((threadIdx.x & 63) == 0) {
-        atomicAnd(&rng[blockIdx.y], a);
-        atomicOr(&rng[b.n_jobs + blockIdx.y], o);
+        sa[threadIdx.x >> 6] = a;
+        so[threadIdx.x >> 6] = o;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kSegThreads / 64; ++w) {
+            a &= sa[w];
+            o |= so[w];
+        }
+        if (a != 0xFFFFFFFFu) atomicAnd(&rng[blockIdx.y], a);
+        if (o != 0u) atomicOr(&rng[b.n_jobs + blockIdx.y], o);
     }
 }
 
@@ -273,6 +291,7 @@ struct ExpandLds {
     uint32_t off[64];       // exclusive prefix of rect areas
     uint32_t org[64];       // rect origin, x0 | y0 << 16
     uint32_t wid[64];       // rect width in tiles
+    float iwid[64];         // 1 / wid
     uint32_t rid[64];       // record index
     int32_t mark[64];       // record starting at each position of the current item window, or -1
 };
@@ -307,6 +326,7 @@ __device__ __forceinline__ void for_each_pair(const ivrgs_job &job, int begin, i
                 L.h1[lane] = make_float4(h.qc, h.i2qa, h.i2qc, h.tol);
                 L.org[lane] = rc.x;
                 L.wid[lane] = (uint32_t)(x1 - x0);
+                L.iwid[lane] = __builtin_amdgcn_rcpf((float)(x1 - x0));
                 L.rid[lane] = (uint32_t)r;
             }
         }
@@ -334,7 +354,14 @@ __device__ __forceinline__ void for_each_pair(const ivrgs_job &job, int begin, i
             if (idx < total) {
                 const uint32_t t = idx - L.off[j];
                 const uint32_t w = L.wid[j];
-                const uint32_t dy = t / w, dx = t - dy * w;
+                // t / w from the reciprocal, corrected to the exact value:
+                // t is below the tiles of one job (at most 2^16, as the
+                // per-tile LDS counters require), where the estimate is
+                // within one of the quotient
+                int q = (int)((float)t * L.iwid[j]);
+                q -= (int)((uint32_t)q * w > t);
+                q += (int)((uint32_t)(q + 1) * w <= t);
+                const uint32_t dy = (uint32_t)q, dx = t - dy * w;
                 const uint32_t o = L.org[j];
                 const int x = (int)((o & 0xFFFFu) + dx), y = (int)((o >> 16) + dy);
                 const float4 a = L.h0[j], c = L.h1[j];
@@ -648,9 +675,9 @@ hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *r
     uint32_t *tot = w.hist + (size_t)b.n_jobs * 256 * n_seg;
     if (n_seg > 0) {
         TimedScope ts(TK_SORT, s);
-        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, w.rng, (int64_t)b.n_jobs, 0xFFFFFFFFu);
-        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, w.rng + b.n_jobs, (int64_t)b.n_jobs, 0u);
-        hipLaunchKernelGGL(k_dkey_range, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, depth, w.rng);
+        hipLaunchKernelGGL(k_rng_init, dim3(1), dim3(256), 0, s, w.rng, b.n_jobs);
+        hipLaunchKernelGGL(k_dkey_range, dim3(n_seg < kRangeBlocks ? n_seg : kRangeBlocks, b.n_jobs),
+                           dim3(kSegThreads), 0, s, b, depth, w.rng);
         for (int pass = 0; pass < 4; ++pass) {
             const int shift = 8 * pass;
             hipLaunchKernelGGL(k_dsort_hist, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, depth, w.key[0],
