@@ -276,17 +276,22 @@ ivrgs_status ivrgs_light_bwd(const ivrgs_batch *batch, const ivrgs_params *param
                              const ivrgs_projected *proj, float *out_light_grad,
                              const void *workspace, size_t workspace_bytes, void *stream);
 
-/* Kernel timing (benchmark instrumentation).  While enabled, every kernel
- * the library launches is bracketed by a pair of HIP events recorded on its
- * launch stream; ivrgs_timing_read() waits for those events and returns, per
- * kernel kind, the summed milliseconds and the number of launches since the
- * last enable.  Kinds: 0 project, 1 tile counts (per-chunk counts, column
- * and tile scans, work queue), 2 scatter, 3 depth order, 4 render_fwd,
- * 5 render_bwd, 6 project_bwd, 7 compose, 8 fills, 9 cull, 10 edit and
- * light gradients and the exploration step.  Process-wide state; not for
- * concurrent callers. */
+/* Kernel timing (benchmark instrumentation).  ivrgs_timing_enable(kinds)
+ * selects the kernel kinds to time (bit k for kind k, IVRGS_TIMING_ALL for
+ * every kind, 0 to stop) and clears the sums.  Every launch of a selected
+ * kind is then bracketed by a pair of HIP events recorded on its launch
+ * stream (two event records per launch: timing every kind slows a short
+ * step measurably, so time only what is needed).  ivrgs_timing_read()
+ * waits for those events and returns, per kernel kind, the summed
+ * milliseconds and the number of launches since the last enable.  Kinds:
+ * 0 project, 1 tile counts (per-chunk counts, column and tile scans, work
+ * queue), 2 scatter, 3 depth order, 4 render_fwd, 5 render_bwd,
+ * 6 project_bwd, 7 compose, 8 fills, 9 cull, 10 edit and light gradients
+ * and the exploration step.  Process-wide state; not for concurrent
+ * callers. */
 #define IVRGS_TIMING_KINDS 11
-void ivrgs_timing_enable(int32_t on);
+#define IVRGS_TIMING_ALL 0x7FFu
+void ivrgs_timing_enable(uint32_t kinds);
 int32_t ivrgs_timing_read(double *ms, int64_t *launches);
 
 /* Learned culler (device weights): an MLP 16 -> 64 -> 64 -> 1 with ReLU on

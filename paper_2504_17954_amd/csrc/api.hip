@@ -10,7 +10,7 @@ namespace ivrgs {
 // --------------------------------------------------------------- timing
 namespace {
 struct Timing {
-    bool on = false;
+    uint32_t mask = 0;  // bit k: kind k is timed
     std::vector<hipEvent_t> pool;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
     std::vector<std::pair<hipEvent_t, int>> open;  // begun, not yet ended
@@ -34,7 +34,7 @@ hipEvent_t take_event() {
 
 void timing_begin(int kind, hipStream_t s) {
     std::lock_guard<std::mutex> lock(g_timing_mu);
-    if (!g_timing.on) return;
+    if (!((g_timing.mask >> kind) & 1u)) return;
     hipEvent_t e = take_event();
     if (!e) return;
     hipEventRecord(e, s);
@@ -43,7 +43,7 @@ void timing_begin(int kind, hipStream_t s) {
 
 void timing_end(int kind, hipStream_t s) {
     std::lock_guard<std::mutex> lock(g_timing_mu);
-    if (!g_timing.on) return;
+    if (!((g_timing.mask >> kind) & 1u)) return;
     for (size_t i = g_timing.open.size(); i-- > 0;) {
         if (g_timing.open[i].second != kind) continue;
         hipEvent_t b = g_timing.open[i].first;
@@ -397,7 +397,7 @@ ivrgs_status ivrgs_render_bwd(const ivrgs_batch *batch, const ivrgs_params *para
     return hip_status(e);
 }
 
-void ivrgs_timing_enable(int32_t on) {
+void ivrgs_timing_enable(uint32_t kinds) {
     std::lock_guard<std::mutex> lock(g_timing_mu);
     for (auto &p : g_timing.pending) {
         hipEventSynchronize(p.second.second);
@@ -411,7 +411,7 @@ void ivrgs_timing_enable(int32_t on) {
         g_timing.ms[k] = 0.0;
         g_timing.n[k] = 0;
     }
-    g_timing.on = on != 0;
+    g_timing.mask = kinds & ((1u << TK_KINDS) - 1u);
 }
 
 int32_t ivrgs_timing_read(double *ms, int64_t *launches) {

@@ -133,7 +133,7 @@ def load(path: str = LIB_PATH):
     lib.ivrgs_explore_state_words.restype = C.c_int64
     lib.ivrgs_explore_step.argtypes = [P, P, C.c_int32, P, P, P, P]
     lib.ivrgs_explore_step.restype = C.c_int
-    lib.ivrgs_timing_enable.argtypes = [C.c_int32]
+    lib.ivrgs_timing_enable.argtypes = [C.c_uint32]
     lib.ivrgs_timing_enable.restype = None
     lib.ivrgs_timing_read.argtypes = [P, P]
     lib.ivrgs_timing_read.restype = C.c_int32
@@ -215,8 +215,23 @@ def ivrgs_struct_size(which: int) -> int:
     return int(load().ivrgs_struct_size(which))
 
 
-def ivrgs_timing_enable(on: bool):
-    load().ivrgs_timing_enable(1 if on else 0)
+TIMING_ALL = (1 << len(TIMING_KINDS)) - 1
+
+
+def ivrgs_timing_enable(kinds=True):
+    """Time the listed kernel kinds (names or a bit mask; True = all, False =
+    off) and clear the sums."""
+    if kinds is True:
+        mask = TIMING_ALL
+    elif kinds is False or kinds is None:
+        mask = 0
+    elif isinstance(kinds, int):
+        mask = kinds
+    else:
+        mask = 0
+        for k in kinds:
+            mask |= 1 << TIMING_KINDS.index(k)
+    load().ivrgs_timing_enable(mask)
 
 
 def ivrgs_timing_read() -> dict:
