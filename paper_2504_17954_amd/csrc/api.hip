@@ -1,4 +1,5 @@
 // C ABI: host-side validation, workspace layout and launch sequencing.
+#include <algorithm>
 #include <mutex>
 #include <utility>
 #include <vector>
@@ -223,10 +224,16 @@ ivrgs_status compose_common(const ivrgs_gaussians *models, int32_t n_models, con
     if (total != out->n) return IVRGS_E_SHAPE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     int64_t off = 0;
-    for (int m = 0; m < n_models; ++m) {
-        hipError_t e = launch_compose(models[m], off, m, host_edits ? host_edits + m : nullptr, dev_edits, *out, s);
+    for (int m0 = 0; m0 < n_models; m0 += kComposeModels) {
+        const int cnt = std::min(kComposeModels, n_models - m0);
+        int64_t offs[kComposeModels];
+        for (int j = 0; j < cnt; ++j) {
+            offs[j] = off;
+            off += models[m0 + j].n;
+        }
+        hipError_t e = launch_compose(models + m0, offs, m0, cnt, host_edits ? host_edits + m0 : nullptr, dev_edits,
+                                      *out, s);
         if (e != hipSuccess) return IVRGS_E_HIP;
-        off += models[m].n;
     }
     return IVRGS_OK;
 }
@@ -385,15 +392,19 @@ ivrgs_status ivrgs_render_bwd(const ivrgs_batch *batch, const ivrgs_params *para
                                   ? reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + L.queue)
                                   : nullptr,
                               params->persist_per_cu, s);
+    // One job over the whole set (its range lies in [0, n) and has n
+    // records) writes every Gaussian's gradient, zeros included; otherwise
+    // the planes are cleared first and, when several jobs may share a
+    // Gaussian, accumulated with atomics.
     const int64_t n = grads->n;
+    const bool dense = batch->n_jobs == 1 && !batch->gauss_index && batch->n_records == n;
+    const bool shared = batch->n_jobs > 1;
     float *planes[7] = {grads->mean, grads->log_scale, grads->quat, grads->opacity,
                         grads->normal, grads->color, grads->shade};
     const int dims[7] = {3, 3, 4, 1, 3, 3, 4};
-    for (int p = 0; p < 7 && e == hipSuccess; ++p)
+    for (int p = 0; p < 7 && e == hipSuccess && !dense; ++p)
         e = launch_fill_u32(reinterpret_cast<uint32_t *>(planes[p]), dims[p] * n, 0u, s);
-    // a Gaussian that several jobs share accumulates with atomics
-    const bool shared = batch->n_jobs > 1;
-    if (e == hipSuccess) e = launch_project_bwd(*batch, k, proj->rect, grec, *grads, shared, s);
+    if (e == hipSuccess) e = launch_project_bwd(*batch, k, proj->rect, grec, *grads, shared, dense, s);
     return hip_status(e);
 }
 

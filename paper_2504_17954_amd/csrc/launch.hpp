@@ -32,10 +32,14 @@ size_t col_part_words(const ivrgs_batch &b, const Consts &k, int chunk);
 hipError_t launch_project(const ivrgs_batch &b, const Consts &k, float *rec, uint32_t *rect, uint32_t *depth,
                           hipStream_t s);
 hipError_t launch_project_bwd(const ivrgs_batch &b, const Consts &k, const uint32_t *rect, const float *grec,
-                              const ivrgs_gaussians_mut &out, bool atomic, hipStream_t s);
-// host_e != nullptr: edit values from the host row; else from dev_table[model].
-hipError_t launch_compose(const ivrgs_gaussians &src, int64_t offset, int32_t model, const ivrgs_model_edit *host_e,
-                          const ivrgs_model_edit *dev_table, const ivrgs_gaussians_mut &out, hipStream_t s);
+                              const ivrgs_gaussians_mut &out, bool atomic, bool dense, hipStream_t s);
+// Models model0 .. model0 + count - 1 (count <= kComposeModels) in one
+// launch: src[j] goes to out[offset[j] ...).  host_e != nullptr: edit values
+// from the host rows host_e[j]; else from dev_table[model0 + j].
+constexpr int kComposeModels = 8;
+hipError_t launch_compose(const ivrgs_gaussians *src, const int64_t *offset, int32_t model0, int32_t count,
+                          const ivrgs_model_edit *host_e, const ivrgs_model_edit *dev_table,
+                          const ivrgs_gaussians_mut &out, hipStream_t s);
 struct ExploreOpts {
     float lr, beta1, beta2, eps;
     uint32_t learn;

@@ -346,22 +346,49 @@ __device__ __forceinline__ void shade_bwd(const GIn &a, const Fwd &f, const floa
 // ----------------------------------------------------------------------------
 // Backward: record gradients (dL/d mx, my, qa, qb, qc, o, r, g, b) -> the 21
 // parameter gradients, by the chain rule through the forward above.
-template <bool kAtomic>
+// kDense (one job over every Gaussian, no index list): each Gaussian is
+// written exactly once, zeros included, so the output needs no clearing.
+template <bool kAtomic, bool kDense>
 __global__ __launch_bounds__(256) void k_project_bwd(ivrgs_batch b, Consts k, const uint2 *__restrict__ rect,
                                                      const float *__restrict__ grec, ivrgs_gaussians_mut out) {
+    static_assert(!(kAtomic && kDense), "dense output is written, not accumulated");
     const ivrgs_job job = b.jobs[blockIdx.y];
     const int local = blockIdx.x * blockDim.x + threadIdx.x;
     if (local >= job.gauss_count) return;
     const int64_t r = (int64_t)job.rec_begin + local;
+    auto zero = [&]() {
+        if constexpr (kDense) {
+            const int64_t gi = (int64_t)job.gauss_begin + local, n = out.n;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                out.mean[c * n + gi] = 0.f;
+                out.log_scale[c * n + gi] = 0.f;
+                out.normal[c * n + gi] = 0.f;
+                out.color[c * n + gi] = 0.f;
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                out.quat[c * n + gi] = 0.f;
+                out.shade[c * n + gi] = 0.f;
+            }
+            out.opacity[gi] = 0.f;
+        }
+    };
     const uint2 rc = rect[r];
-    if (rc.x == 0u && rc.y == 0u) return;  // culled
+    if (rc.x == 0u && rc.y == 0u) {  // culled
+        zero();
+        return;
+    }
     float gr[kGradRec];
 #pragma unroll
     for (int i = 0; i < kGradRec; ++i) gr[i] = grec[r * kGradStride + i];
     bool any = false;
 #pragma unroll
     for (int i = 0; i < kGradRec; ++i) any |= gr[i] != 0.f;
-    if (!any) return;
+    if (!any) {
+        zero();
+        return;
+    }
 
     const int64_t gi = job_gaussian(job, b.gauss_index, local);
     const Cam cam = load_cam(&b.cameras[job.camera]);
@@ -516,47 +543,95 @@ __global__ __launch_bounds__(256) void k_project_bwd(ivrgs_batch b, Consts k, co
 }
 
 // ----------------------------------------------------------------------------
-// Composition: one launch per basic model, writing its slice of the output.
+// Composition: one launch covers up to kComposeModels basic models; a thread
+// writes 4 consecutive Gaussians of one model, as float4 loads and stores
+// where the model's source planes and its output slice are 16-byte aligned.
 struct ComposeArgs {
-    ivrgs_gaussians src;
-    int64_t offset;   // first output index
-    int32_t model;
-    float palette[3], oscale, kscale[4], kbias[4];
+    ivrgs_gaussians src[kComposeModels];
+    int64_t offset[kComposeModels];  // first output index of each model
+    int64_t quad[kComposeModels + 1];  // first thread of each model (4 Gaussians per thread)
+    int32_t model0;                  // model number of src[0]
+    int32_t count;
+    float edit[kComposeModels][12];  // palette 3, opacity scale, shade scale 4, shade bias 4 (host rows)
 };
 
-// table != nullptr: the edit values come from the device row table[a.model]
-// (the same for every thread; the values in `a` are unused).
+__device__ __forceinline__ bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0u; }
+
+// table != nullptr: the edit values come from the device rows table[model]
+// (the same for every thread of the model); else from the host rows in `a`.
 __global__ __launch_bounds__(256) void k_compose(ComposeArgs a, const ivrgs_model_edit *__restrict__ table,
                                                  ivrgs_gaussians_mut out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n = a.src.n;
-    if (i >= n) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.quad[a.count]) return;
+    int j = 0;
+    while (j + 1 < a.count && t >= a.quad[j + 1]) ++j;
+    const ivrgs_gaussians &src = a.src[j];
+    const int64_t n = src.n, N = out.n, i0 = 4 * (t - a.quad[j]), o0 = a.offset[j] + i0;
+    const int model = a.model0 + j;
+    float e[12];
     if (table) {
-        const ivrgs_model_edit &e = table[a.model];
+        const ivrgs_model_edit &r = table[model];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) a.palette[c] = e.palette[c];
-        a.oscale = e.opacity_scale;
+        for (int c = 0; c < 3; ++c) e[c] = r.palette[c];
+        e[3] = r.opacity_scale;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            a.kscale[c] = e.shade_scale[c];
-            a.kbias[c] = e.shade_bias[c];
+            e[4 + c] = r.shade_scale[c];
+            e[8 + c] = r.shade_bias[c];
         }
-    }
-    const int64_t N = out.n, o = a.offset + i;
+    } else {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        out.mean[c * N + o] = a.src.mean[c * n + i];
-        out.log_scale[c * N + o] = a.src.log_scale[c * n + i];
-        out.normal[c * N + o] = a.src.normal[c * n + i];
-        out.color[c * N + o] = a.palette[c] + a.src.color[c * n + i];
+        for (int c = 0; c < 12; ++c) e[c] = a.edit[j][c];
     }
+    // the whole quad in range, the model's planes (n % 4 == 0) and its output
+    // slice (N % 4 == 0, offset % 4 == 0) on 16-byte boundaries
+    const bool vec = i0 + 4 <= n && (n & 3) == 0 && (N & 3) == 0 && (a.offset[j] & 3) == 0 &&
+                     aligned16(src.mean) && aligned16(src.log_scale) && aligned16(src.quat) &&
+                     aligned16(src.opacity) && aligned16(src.normal) && aligned16(src.color) &&
+                     aligned16(src.shade) && aligned16(out.mean) && aligned16(out.log_scale) &&
+                     aligned16(out.quat) && aligned16(out.opacity) && aligned16(out.normal) &&
+                     aligned16(out.color) && aligned16(out.shade) && aligned16(out.model_id);
+    if (vec) {
+        auto ld = [](const float *p) { return *reinterpret_cast<const float4 *>(p); };
+        auto st = [](float *p, float4 v) { *reinterpret_cast<float4 *>(p) = v; };
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        out.quat[c * N + o] = a.src.quat[c * n + i];
-        out.shade[c * N + o] = fmaf(a.kscale[c], a.src.shade[c * n + i], a.kbias[c]);
+        for (int c = 0; c < 3; ++c) {
+            st(out.mean + c * N + o0, ld(src.mean + c * n + i0));
+            st(out.log_scale + c * N + o0, ld(src.log_scale + c * n + i0));
+            st(out.normal + c * N + o0, ld(src.normal + c * n + i0));
+            const float4 v = ld(src.color + c * n + i0);
+            st(out.color + c * N + o0, make_float4(e[c] + v.x, e[c] + v.y, e[c] + v.z, e[c] + v.w));
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            st(out.quat + c * N + o0, ld(src.quat + c * n + i0));
+            const float4 v = ld(src.shade + c * n + i0);
+            const float ks = e[4 + c], kb = e[8 + c];
+            st(out.shade + c * N + o0, make_float4(fmaf(ks, v.x, kb), fmaf(ks, v.y, kb), fmaf(ks, v.z, kb),
+                                                   fmaf(ks, v.w, kb)));
+        }
+        const float4 v = ld(src.opacity + i0);
+        st(out.opacity + o0, make_float4(e[3] * v.x, e[3] * v.y, e[3] * v.z, e[3] * v.w));
+        *reinterpret_cast<int4 *>(out.model_id + o0) = make_int4(model, model, model, model);
+        return;
     }
-    out.opacity[o] = a.oscale * a.src.opacity[i];
-    out.model_id[o] = a.model;
+    for (int64_t i = i0; i < i0 + 4 && i < n; ++i) {
+        const int64_t o = a.offset[j] + i;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            out.mean[c * N + o] = src.mean[c * n + i];
+            out.log_scale[c * N + o] = src.log_scale[c * n + i];
+            out.normal[c * N + o] = src.normal[c * n + i];
+            out.color[c * N + o] = e[c] + src.color[c * n + i];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            out.quat[c * N + o] = src.quat[c * n + i];
+            out.shade[c * N + o] = fmaf(e[4 + c], src.shade[c * n + i], e[8 + c]);
+        }
+        out.opacity[o] = e[3] * src.opacity[i];
+        out.model_id[o] = model;
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -735,34 +810,44 @@ hipError_t launch_project(const ivrgs_batch &b, const Consts &k, float *rec, uin
 }
 
 hipError_t launch_project_bwd(const ivrgs_batch &b, const Consts &k, const uint32_t *rect, const float *grec,
-                              const ivrgs_gaussians_mut &out, bool atomic, hipStream_t s) {
+                              const ivrgs_gaussians_mut &out, bool atomic, bool dense, hipStream_t s) {
     if (b.n_jobs == 0 || b.max_job_count == 0) return hipSuccess;
     dim3 grid((b.max_job_count + 255) / 256, b.n_jobs);
     const uint2 *rc = reinterpret_cast<const uint2 *>(rect);
     TimedScope ts(TK_PROJECT_BWD, s);
     if (atomic)
-        hipLaunchKernelGGL(k_project_bwd<true>, grid, dim3(256), 0, s, b, k, rc, grec, out);
+        hipLaunchKernelGGL((k_project_bwd<true, false>), grid, dim3(256), 0, s, b, k, rc, grec, out);
+    else if (dense)
+        hipLaunchKernelGGL((k_project_bwd<false, true>), grid, dim3(256), 0, s, b, k, rc, grec, out);
     else
-        hipLaunchKernelGGL(k_project_bwd<false>, grid, dim3(256), 0, s, b, k, rc, grec, out);
+        hipLaunchKernelGGL((k_project_bwd<false, false>), grid, dim3(256), 0, s, b, k, rc, grec, out);
     return hipGetLastError();
 }
 
-hipError_t launch_compose(const ivrgs_gaussians &src, int64_t offset, int32_t model, const ivrgs_model_edit *host_e,
-                          const ivrgs_model_edit *dev_table, const ivrgs_gaussians_mut &out, hipStream_t s) {
-    if (src.n == 0) return hipSuccess;
+hipError_t launch_compose(const ivrgs_gaussians *src, const int64_t *offset, int32_t model0, int32_t count,
+                          const ivrgs_model_edit *host_e, const ivrgs_model_edit *dev_table,
+                          const ivrgs_gaussians_mut &out, hipStream_t s) {
+    if (count <= 0 || count > kComposeModels) return hipErrorInvalidValue;
     ComposeArgs a = {};
-    a.src = src;
-    a.offset = offset;
-    a.model = model;
-    if (host_e) {
-        for (int c = 0; c < 3; ++c) a.palette[c] = host_e->palette[c];
-        a.oscale = host_e->opacity_scale;
-        for (int c = 0; c < 4; ++c) {
-            a.kscale[c] = host_e->shade_scale[c];
-            a.kbias[c] = host_e->shade_bias[c];
+    a.model0 = model0;
+    a.count = count;
+    a.quad[0] = 0;
+    for (int j = 0; j < count; ++j) {
+        a.src[j] = src[j];
+        a.offset[j] = offset[j];
+        a.quad[j + 1] = a.quad[j] + (src[j].n + 3) / 4;
+        if (host_e) {
+            const ivrgs_model_edit &r = host_e[j];
+            for (int c = 0; c < 3; ++c) a.edit[j][c] = r.palette[c];
+            a.edit[j][3] = r.opacity_scale;
+            for (int c = 0; c < 4; ++c) {
+                a.edit[j][4 + c] = r.shade_scale[c];
+                a.edit[j][8 + c] = r.shade_bias[c];
+            }
         }
     }
-    dim3 grid((unsigned)((src.n + 255) / 256));
+    if (a.quad[count] == 0) return hipSuccess;
+    dim3 grid((unsigned)((a.quad[count] + 255) / 256));
     TimedScope ts(TK_COMPOSE, s);
     hipLaunchKernelGGL(k_compose, grid, dim3(256), 0, s, a, host_e ? nullptr : dev_table, out);
     return hipGetLastError();

@@ -325,6 +325,34 @@ def test_render_bwd_c1(dev, px):
     check_grads(g, g_ref, f"c1 bwd px={px}", exclude=grad_exclusions(planes, cam, prm))
 
 
+def test_backward_overwrites_stale_gradients(dev):
+    """One job over the whole set: the backward writes every Gaussian's
+    gradient itself (no clearing pass), so buffers holding NaN come back
+    equal to the oracle, with exact zeros for Gaussians it culls."""
+    planes, cam, prm = c1_setup(seed_offset=3)
+    planes = {k: v.copy() for k, v in planes.items()}
+    planes["mean"][:, :50] = np.array([[0.0], [-10.0], [0.0]], np.float32)  # behind the camera: culled
+    ref = O.render(planes, cam, prm)
+    dl = upstream(ref, 2003, ref["rgba"].shape)
+    g_ref, _ = O.backward(planes, cam, prm, dl)
+    rnd = R.Renderer(R.Settings(128, 128))
+    pd = to_dev(planes, dev)
+    cams, jobs = R.camera_table([cam]), R.Jobs.single(10_000)
+    rgba = rnd.forward(pd, cams, jobs, edits_t=R.default_edits(dev))
+    stale = {k: torch.full((d, 10_000), float("nan"), device=dev) for k, d in R.PLANE_DIMS.items()}
+    say("backward into NaN-filled gradient buffers, one job")
+    g = rnd.backward(pd, cams, jobs, rgba, torch.from_numpy(dl[None].astype(np.float32)).to(dev),
+                     edits_t=R.default_edits(dev), grads=stale)
+    g = {k: v.cpu().numpy() for k, v in g.items()}
+    for k in R.PLANES:
+        assert np.isfinite(g[k]).all(), k
+    culled = rnd.rect[:10_000].cpu().numpy().any(1) == 0
+    assert culled[:50].all()
+    for k in R.PLANES:
+        assert np.all(g[k][:, culled] == 0.0), k
+    check_grads(g, g_ref, "stale buffers", exclude=grad_exclusions(planes, cam, prm))
+
+
 def test_autograd_function(dev):
     """loss.backward() through rasterize() equals the oracle gradient of the
     same L1 loss; the backward recomputes the bins when the renderer was
