@@ -60,6 +60,38 @@ __device__ __forceinline__ uint32_t wave_mask(const TileGeom &tg, float4 r0, flo
     return m;
 }
 
+// Issue priority of a wave from the length of its tile's list.  All waves
+// of a view start together, most finish within a few microseconds, and the
+// view ends with the few tiles whose walks are longest; raising their
+// priority lets them run at nearly the speed of a wave alone on its SIMD
+// while the short walks fill the remaining issue slots.
+__device__ __forceinline__ void walk_priority(uint32_t list_len) {
+    if (list_len >= 2048u) __builtin_amdgcn_s_setprio(3);
+    else if (list_len >= 1024u) __builtin_amdgcn_s_setprio(2);
+    else if (list_len >= 512u) __builtin_amdgcn_s_setprio(1);
+    else __builtin_amdgcn_s_setprio(0);  // a persistent wave's next tile may be shorter
+}
+
+// Bounding box, within the wave's 8x8 quadrant at (sx, sy), of the pixels
+// whose lanes are set in `alive` (lane l owns pixel (l % 8, l / 8)); `alive`
+// must be nonzero.  Scalar bit operations only.  A record that cannot reach
+// this box cannot reach a pixel still compositing, and a pixel that has
+// terminated ignores every later record, so testing the records of each step
+// of the walk against this box instead of the whole quadrant changes no
+// result while the walks of the last pixels of a quadrant shrink.
+struct PixBox {
+    int x0, y0, w, h;
+};
+__device__ __forceinline__ PixBox alive_box(uint64_t alive, int sx, int sy) {
+    uint64_t c = alive | (alive >> 32);
+    c |= c >> 16;
+    c |= c >> 8;
+    const uint32_t cols = (uint32_t)c & 0xFFu;
+    const int xa = __builtin_ctz(cols), xb = 31 - __builtin_clz(cols);
+    const int ya = __builtin_ctzll(alive) >> 3, yb = (63 - __builtin_clzll(alive)) >> 3;
+    return {sx + xa, sy + ya, xb - xa + 1, yb - ya + 1};
+}
+
 __device__ __forceinline__ float wave_max_to_lane63(float v) {
     v = fmaxf(v, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false)));
     v = fmaxf(v, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, false)));
@@ -193,8 +225,8 @@ __device__ __forceinline__ void fwd_tile(const Consts &k, const float4 *__restri
 // and tests it against the quadrant (the conservative ellipse-box test of the
 // binning), a ballot gives the records that can reach it, and the wave visits
 // only those, in list order, broadcasting each record's fields from its
-// lane into scalar registers.  The next 64 records are loaded while the
-// current ones are composited.  No LDS and no workgroup barrier: a wave
+// lane into scalar registers.  The next 64 records are gathered, and the ids
+// of the 64 after them loaded, while the current ones are composited.  No LDS and no workgroup barrier: a wave
 // stops as soon as its own 64 pixels are done.
 template <bool kMaxw, bool kCount>
 __device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__restrict__ rec,
@@ -203,6 +235,7 @@ __device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__r
                                               float *__restrict__ maxw, int64_t *__restrict__ status, int64_t tile) {
     const TileGeom tg = tile_geom(k, tile);
     const uint32_t start = starts[tile], end = starts[tile + 1];
+    walk_priority(end - start);
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int sx = tg.tx * kTile + 8 * (wave & 1), sy = tg.ty * kTile + 8 * (wave >> 1);
@@ -213,84 +246,95 @@ __device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__r
     uint32_t stop_at = end;  // list position of this pixel's terminating record
     uint32_t composited = 0;
 
+    // Two-stage software pipeline over steps of 64 records: while one step
+    // is composited, the records of the next are gathered with ids loaded a
+    // step earlier, and the ids of the step after are loaded, so neither the
+    // id load nor the gather that depends on it is waited for in the walk.
     float4 n0, n1, n2;
-    uint32_t nid = 0;
-    auto fetch = [&](uint32_t base) {
-        const uint32_t idx = base + lane;
-        if (idx < end) {
-            nid = sorted[idx];
+    uint32_t nid = 0, pid = 0;  // ids of the next step's records / of the step after
+    auto load_ids = [&](uint32_t base) {
+        if (base + lane < end) pid = sorted[base + lane];
+    };
+    auto load_recs = [&](uint32_t base) {
+        if (base + lane < end) {
+            nid = pid;
             n0 = rec[3 * (size_t)nid];
             n1 = rec[3 * (size_t)nid + 1];
             n2 = rec[3 * (size_t)nid + 2];
         }
     };
-    if (start < end) fetch(start);
+    if (start < end) {
+        load_ids(start);
+        load_recs(start);
+        if (start + 64 < end) load_ids(start + 64);
+    }
     for (uint32_t base = start; base < end; base += 64) {
-        if (__ballot(alive) == 0ull) break;
+        const uint64_t live = __ballot(alive);
+        if (live == 0ull) break;
+        const PixBox bx = alive_box(live, sx, sy);
         const float4 r0 = n0, r1 = n1, r2 = n2;
         const uint32_t rid = nid;
         bool touch = false;
-        if (base + lane < end) touch = box_hit(make_hit_test(r0, r1, r2), sx, sy, 8, 8);
-        if (base + 64 < end) fetch(base + 64);
+        if (base + lane < end) touch = box_hit(make_hit_test(r0, r1, r2), bx.x0, bx.y0, bx.w, bx.h);
+        if (base + 64 < end) load_recs(base + 64);
+        if (base + 128 < end) load_ids(base + 128);
         uint64_t m = __ballot(touch);
-        // Composites the record held by lane `src` whose exponent p2 (and its
-        // power G) are already known; same arithmetic as every other path.
-        auto composite = [&](int src, float p2, float G) {
-            const float cut = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r2.z), src));
-            // below the cutoff alpha < alpha_min is certain
-            const bool pass = alive && p2 >= cut;
-            if (__ballot(pass) == 0ull) return;  // wave-uniform
-            const float o = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r1.y), src));
-            const float cr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r1.z), src));
-            const float cg = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r1.w), src));
-            const float cb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r2.x), src));
-            const float al = fminf(k.alpha_max, o * G);
-            const float Tn = T * (1.f - al);
-            const bool use = pass && al >= k.alpha_min;
-            const bool stop = use && Tn < k.T_min;
-            const bool comp = use && !stop;
-            const float w = comp ? al * T : 0.f;
-            C0 = fmaf(w, cr, C0);
-            C1 = fmaf(w, cg, C1);
-            C2 = fmaf(w, cb, C2);
-            T = comp ? Tn : T;
-            if (kCount) {
-                composited += comp ? 1u : 0u;
-                if (stop) stop_at = base + (uint32_t)src;
-            }
-            alive = alive && !stop;
-            if (kMaxw) {
-                if (__ballot(w > 0.f)) {
-                    const float wm = wave_max_to_lane63(w);
-                    const uint32_t id = __builtin_amdgcn_readlane(rid, src);
-                    if (lane == 63) atomicMax(reinterpret_cast<int *>(&maxw[id]), __float_as_int(wm));
-                }
-            }
-        };
-        auto exponent = [&](int src) {
-            const float mx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r0.x), src));
-            const float my = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r0.y), src));
-            const float qa = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r0.z), src));
-            const float qb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r0.w), src));
-            const float qc = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r1.x), src));
-            return splat_exponent(qa, qb, qc, px - mx, py - my);
-        };
-        // two records per step: their exponents and powers are independent
-        // of the compositing order, so they are computed together and the
-        // two dependent compositing steps follow in list order
+        // Records are visited in groups of kGroupFwd.  Phase 1 computes, with
+        // no branch, everything that does not depend on the compositing
+        // order (fields broadcast from the record's lane, exponent, cutoff
+        // test, power, alpha); the records are independent, so their
+        // instructions interleave.  Phase 2 is the front-to-back chain in
+        // list order, a few instructions per record.  The arithmetic of each
+        // record is the same as on every other path.
+        constexpr int kGroupFwd = 4;
+        auto bc = [&](float v, int src) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src)); };
         while (m) {
-            const int sa = (int)__builtin_ctzll(m);
-            m &= m - 1;
-            if (m) {
-                const int sb = (int)__builtin_ctzll(m);
+            int src[kGroupFwd];
+            bool valid[kGroupFwd];
+#pragma unroll
+            for (int g = 0; g < kGroupFwd; ++g) {
+                valid[g] = m != 0ull;  // wave-uniform
+                src[g] = valid[g] ? (int)__builtin_ctzll(m) : 0;
                 m &= m - 1;
-                const float pa = exponent(sa), pb = exponent(sb);
-                const float Ga = fast_exp2(pa), Gb = fast_exp2(pb);
-                composite(sa, pa, Ga);
-                composite(sb, pb, Gb);
-            } else {
-                const float pa = exponent(sa);
-                composite(sa, pa, fast_exp2(pa));
+            }
+            float al[kGroupFwd], cr[kGroupFwd], cg[kGroupFwd], cb[kGroupFwd];
+            bool pass[kGroupFwd];
+#pragma unroll
+            for (int g = 0; g < kGroupFwd; ++g) {
+                const int sg = src[g];
+                const float p2 = splat_exponent(bc(r0.z, sg), bc(r0.w, sg), bc(r1.x, sg), px - bc(r0.x, sg),
+                                                py - bc(r0.y, sg));
+                // below the cutoff alpha < alpha_min is certain
+                pass[g] = valid[g] && p2 >= bc(r2.z, sg);
+                al[g] = fminf(k.alpha_max, bc(r1.y, sg) * fast_exp2(p2));
+                cr[g] = bc(r1.z, sg);
+                cg[g] = bc(r1.w, sg);
+                cb[g] = bc(r2.x, sg);
+            }
+#pragma unroll
+            for (int g = 0; g < kGroupFwd; ++g) {
+                const float Tn = T * (1.f - al[g]);
+                // alive as it stands after the records before this one
+                const bool use = alive && pass[g] && al[g] >= k.alpha_min;
+                const bool stop = use && Tn < k.T_min;
+                const bool comp = use && !stop;
+                const float w = comp ? al[g] * T : 0.f;
+                C0 = fmaf(w, cr[g], C0);
+                C1 = fmaf(w, cg[g], C1);
+                C2 = fmaf(w, cb[g], C2);
+                T = comp ? Tn : T;
+                if (kCount) {
+                    composited += comp ? 1u : 0u;
+                    if (stop) stop_at = base + (uint32_t)src[g];
+                }
+                alive = alive && !stop;
+                if (kMaxw) {
+                    if (__ballot(w > 0.f)) {
+                        const float wm = wave_max_to_lane63(w);
+                        const uint32_t id = __builtin_amdgcn_readlane(rid, src[g]);
+                        if (lane == 63) atomicMax(reinterpret_cast<int *>(&maxw[id]), __float_as_int(wm));
+                    }
+                }
             }
             if (__ballot(alive) == 0ull) break;
         }
@@ -369,6 +413,7 @@ __device__ __forceinline__ void bwd_tile_wave(const Consts &k, const float4 *__r
                                               const float *__restrict__ dl, float *__restrict__ grec, int64_t tile) {
     const TileGeom tg = tile_geom(k, tile);
     const uint32_t start = starts[tile], end = starts[tile + 1];
+    walk_priority(end - start);
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // the wave's region: with one pixel per lane the 8x8 quadrant w of the
@@ -415,20 +460,27 @@ __device__ __forceinline__ void bwd_tile_wave(const Consts &k, const float4 *__r
     const bool my_slot = ((lane & 1) == 0) && my_m < kGroup * kGradRec;
     const int my_g = my_m / kGradRec, my_v = my_m % kGradRec;
 
-    // records of the current step (r*, rid) and of the next one (n*, nid)
+    // records of the current step (r*, rid) and of the next one (n*, nid),
+    // ids of the step after (pid): the two-stage pipeline of fwd_tile_wave
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0, n0 = r0, n1 = r0, n2 = r0;
-    uint32_t rid = 0, nid = 0;
+    uint32_t rid = 0, nid = 0, pid = 0;
     uint32_t nbase = start;  // list position of the records held in n*
-    auto fetch = [&]() {
-        const uint32_t idx = nbase + lane;
-        if (idx < end) {
-            nid = sorted[idx];
+    auto load_ids = [&](uint32_t base) {
+        if (base + lane < end) pid = sorted[base + lane];
+    };
+    auto load_recs = [&](uint32_t base) {
+        if (base + lane < end) {
+            nid = pid;
             n0 = rec[3 * (size_t)nid];
             n1 = rec[3 * (size_t)nid + 1];
             n2 = rec[3 * (size_t)nid + 2];
         }
     };
-    if (start < end) fetch();
+    if (start < end) {
+        load_ids(start);
+        load_recs(start);
+        if (start + 64 < end) load_ids(start + 64);
+    }
     uint64_t m = 0;
     // the next record that can reach the region (its lane in r*), moving on to
     // the next 64 records when the current ones are used up; false at the end
@@ -439,9 +491,16 @@ __device__ __forceinline__ void bwd_tile_wave(const Consts &k, const float4 *__r
             r1 = n1;
             r2 = n2;
             rid = nid;
-            const bool touch = nbase + lane < end && box_hit(make_hit_test(r0, r1, r2), sx, sy, RW, RH);
+            PixBox bx = {sx, sy, RW, RH};
+            if constexpr (PX == 1) {
+                const uint64_t live = __ballot(alive[0]);
+                if (live != 0ull) bx = alive_box(live, sx, sy);
+            }
+            const bool touch =
+                nbase + lane < end && box_hit(make_hit_test(r0, r1, r2), bx.x0, bx.y0, bx.w, bx.h);
             nbase += 64;
-            if (nbase < end) fetch();
+            if (nbase < end) load_recs(nbase);
+            if (nbase + 64 < end) load_ids(nbase + 64);
             m = __ballot(touch);
         }
         src = (int)__builtin_ctzll(m);
