@@ -18,7 +18,11 @@ constexpr float kLn2 = 0.6931471805599453f;
 
 // Record word indices.
 enum { RX = 0, RY, RQA, RQB, RQC, RO, RCR, RCG, RCB, RZ, RCUT, RPAD };
-// Record-gradient planes ([9][n_records]).
+// Record-gradient rows (kGradStride floats per record).  With d = pixel
+// centre - screen mean and D = dL/do' * o' G summed over the record's
+// composited pixels: GX, GY = sum D dx, sum D dy; GQA, GQB, GQC = sum D dx^2,
+// D dx dy, D dy^2 (moments; the conic and ln 2 are applied once per record
+// by the projection backward); GO = dL/do'; GCR..GCB = dL/d(rgb).
 enum { GX = 0, GY, GQA, GQB, GQC, GO, GCR, GCG, GCB };
 
 // Compositing constants passed by value to kernels.

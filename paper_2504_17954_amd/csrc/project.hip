@@ -418,10 +418,14 @@ __global__ __launch_bounds__(256) void k_project_bwd(ivrgs_batch b, Consts k, co
         for (int i = 0; i < 3; ++i) g_n[i] = (g_nu[i] - f.nu[i] * nd) / f.nlen;
     }
 
-    // ---- conic: (qa, qb, qc) = -log2(e) (Q00/2, Q01, Q11/2), Q = inv(Sigma')
-    const float gQ00 = -0.5f * kLog2e * gr[GQA];
-    const float gQ01 = -kLog2e * gr[GQB];
-    const float gQ11 = -0.5f * kLog2e * gr[GQC];
+    // ---- conic: the exponent is -(Q00 dx^2 + 2 Q01 dx dy + Q11 dy^2) / 2
+    // (base e), so from the moments D dx^2, D dx dy, D dy^2:
+    const float gQ00 = -0.5f * gr[GQA];
+    const float gQ01 = -gr[GQB];
+    const float gQ11 = -0.5f * gr[GQC];
+    // and the screen mean (d = pixel - mean): dL/dm = Q (sum D d)
+    const float gmx = f.Q00 * gr[GX] + f.Q01 * gr[GY];
+    const float gmy = f.Q01 * gr[GX] + f.Q11 * gr[GY];
     // dL/dSigma' (full symmetric) = -Q G Q, G = [[gQ00, gQ01/2], [gQ01/2, gQ11]]
     const float G01 = 0.5f * gQ01;
     const float A00 = f.Q00 * gQ00 + f.Q01 * G01, A01 = f.Q00 * G01 + f.Q01 * gQ11;
@@ -464,11 +468,11 @@ __global__ __launch_bounds__(256) void k_project_bwd(ivrgs_batch b, Consts k, co
                               gT[r2 * 3 + 2] * cam.R[kk * 3 + 2];
     const float iz = 1.f / f.t[2], iz2 = iz * iz, iz3 = iz2 * iz;
     float gt[3];
-    gt[0] = gJ[2] * (-cam.fx * iz2) + gr[GX] * cam.fx * iz;
-    gt[1] = gJ[5] * (-cam.fy * iz2) + gr[GY] * cam.fy * iz;
+    gt[0] = gJ[2] * (-cam.fx * iz2) + gmx * cam.fx * iz;
+    gt[1] = gJ[5] * (-cam.fy * iz2) + gmy * cam.fy * iz;
     gt[2] = gJ[0] * (-cam.fx * iz2) + gJ[2] * (2.f * cam.fx * f.t[0] * iz3) + gJ[4] * (-cam.fy * iz2) +
-            gJ[5] * (2.f * cam.fy * f.t[1] * iz3) - gr[GX] * cam.fx * f.t[0] * iz2 -
-            gr[GY] * cam.fy * f.t[1] * iz2;
+            gJ[5] * (2.f * cam.fy * f.t[1] * iz3) - gmx * cam.fx * f.t[0] * iz2 -
+            gmy * cam.fy * f.t[1] * iz2;
 #pragma unroll
     for (int i = 0; i < 3; ++i) g_mu[i] += cam.R[0 * 3 + i] * gt[0] + cam.R[1 * 3 + i] * gt[1] + cam.R[2 * 3 + i] * gt[2];
 

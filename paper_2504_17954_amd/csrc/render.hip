@@ -570,12 +570,13 @@ __device__ __forceinline__ void bwd_tile_wave(const Consts &k, const float4 *__r
                     ag[GCG] = fmaf(w, g1[j], ag[GCG]);
                     ag[GCB] = fmaf(w, g2[j], ag[GCB]);
                     ag[GO] = fmaf(dLdo, G, ag[GO]);
-                    const float dp = dLdo * raw * kLn2;
+                    // moments of dL/dG G about the mean (see GX .. GQC)
+                    const float dp = dLdo * raw;
                     ag[GQA] = fmaf(dp, dx[j] * dx[j], ag[GQA]);
                     ag[GQB] = fmaf(dp, dx[j] * dy[j], ag[GQB]);
                     ag[GQC] = fmaf(dp, dy[j] * dy[j], ag[GQC]);
-                    ag[GX] = fmaf(-dp, fmaf(2.f * qa, dx[j], qb * dy[j]), ag[GX]);
-                    ag[GY] = fmaf(-dp, fmaf(qb, dx[j], 2.f * qc * dy[j]), ag[GY]);
+                    ag[GX] = fmaf(dp, dx[j], ag[GX]);
+                    ag[GY] = fmaf(dp, dy[j], ag[GY]);
                     T[j] = comp ? Tn : T[j];
                     alive[j] = alive[j] && !stop;
                     anyc |= comp;
