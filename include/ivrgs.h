@@ -179,9 +179,13 @@ typedef struct {
 /* Bytes of workspace needed by ivrgs_bin_sort, ivrgs_render_fwd and
  * ivrgs_render_bwd for this batch: the depth order (two words per record,
  * twice), its digit histograms, the per-chunk tile counts, the record
- * gradients (9 floats per record) and the work queue.  capacity (>= 0) is the
- * pair capacity of the bins; the workspace does not depend on it.  Returns 0
- * for invalid arguments. */
+ * gradients (9 floats per record), the work queue and, with one pixel per
+ * lane and no work queue, per-pixel checkpoints at up to 15 cuts of every
+ * tile's list (60 KiB per tile, used while they take at most 256 MiB): the
+ * backward walks each segment of a long list in its own workgroup from the
+ * state the forward stored at the cut.  capacity (>= 0) is the pair capacity
+ * of the bins; the workspace does not depend on it.  Returns 0 for invalid
+ * arguments. */
 size_t ivrgs_workspace_size(const ivrgs_batch *batch, const ivrgs_params *params,
                             int64_t capacity);
 
@@ -233,7 +237,10 @@ ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params
 /* Front-to-back alpha compositing (Eq. 2): per pixel C = sum T_i alpha_i c_i,
  * T_i = prod_{j<i} (1 - alpha_j).  out_rgba: [n_jobs][4][H][W].  out_maxw:
  * [n_records] or NULL; if given it must be zeroed by the caller and receives,
- * per record, the largest T*alpha over its composited pixels (culling labels). */
+ * per record, the largest T*alpha over its composited pixels (culling labels).
+ * The workspace is required when the batch uses list checkpoints (see
+ * ivrgs_workspace_size) or the persistent launch; the checkpoints it stores
+ * there are what a following ivrgs_render_bwd reads. */
 ivrgs_status ivrgs_render_fwd(const ivrgs_batch *batch, const ivrgs_params *params,
                               const ivrgs_projected *proj, const ivrgs_bins *bins,
                               float *out_rgba, float *out_maxw,
@@ -243,7 +250,10 @@ ivrgs_status ivrgs_render_fwd(const ivrgs_batch *batch, const ivrgs_params *para
  * compositing front to back from out_rgba (nothing per pixel is stored by the
  * forward) and returns dL/d(parameters) for upstream dL/dRGBA (dl_drgba, same
  * layout as out_rgba).  grads: planes of length batch->g.n (model_id unused);
- * the callee zeroes them.  Gaussians shared by several jobs accumulate. */
+ * the callee zeroes them.  Gaussians shared by several jobs accumulate.
+ * Must follow the ivrgs_render_fwd that produced out_rgba with the same
+ * batch, params, bins and workspace (it reads the list checkpoints that call
+ * stored). */
 ivrgs_status ivrgs_render_bwd(const ivrgs_batch *batch, const ivrgs_params *params,
                               const ivrgs_projected *proj, const ivrgs_bins *bins,
                               const float *out_rgba, const float *dl_drgba,

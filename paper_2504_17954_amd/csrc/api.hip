@@ -143,8 +143,22 @@ ivrgs_status check_batch(const ivrgs_batch *b) {
 
 // Workspace regions.
 struct Layout {
-    size_t key0, val0, key1, val1, hist, rng, counts, part, grec, queue, total;
+    size_t key0, val0, key1, val1, hist, rng, counts, part, grec, queue, ckpt, ckpt_bytes, total;
 };
+
+int pick_px(int requested, int fallback) { return requested == 0 ? fallback : requested; }
+
+// Checkpoints for cutting long tile lists in the backward: (kSplitMax - 1)
+// cuts x 256 pixels x 16 B per tile, with one pixel per lane in both render
+// kernels and no work queue, while that stays within kCkptBudget (one view or
+// a few); otherwise every list is walked whole.
+constexpr size_t kCkptBudget = size_t(256) << 20;
+
+size_t ckpt_bytes(const ivrgs_batch &b, const ivrgs_params &p, const Consts &k) {
+    if (pick_px(p.fwd_px, 1) != 1 || pick_px(p.bwd_px, 1) != 1 || (p.flags & IVRGS_FLAG_PERSISTENT)) return 0;
+    const size_t bytes = (size_t)b.n_jobs * k.tiles_per_job * (kSplitMax - 1) * kCkptPix * sizeof(float) * 4;
+    return bytes <= kCkptBudget ? bytes : 0;
+}
 
 // Records per binning chunk: a multiple of 64 (one wave walks a chunk).
 // Records per binning chunk: the caller's choice rounded up to a multiple of
@@ -186,13 +200,14 @@ Layout layout(const ivrgs_batch &b, const ivrgs_params &p) {
     off += align_up(sizeof(float) * kGradStride * (size_t)b.n_records);
     L.queue = off;
     off += align_up(sizeof(uint32_t) * (size_t)(2 + (int64_t)b.n_jobs * k.tiles_per_job));
+    L.ckpt = off;
+    L.ckpt_bytes = ckpt_bytes(b, p, k);
+    off += align_up(L.ckpt_bytes);
     L.total = off;
     return L;
 }
 
 ivrgs_status hip_status(hipError_t e) { return e == hipSuccess ? IVRGS_OK : IVRGS_E_HIP; }
-
-int pick_px(int requested, int fallback) { return requested == 0 ? fallback : requested; }
 
 }  // namespace
 }  // namespace ivrgs
@@ -360,14 +375,17 @@ ivrgs_status ivrgs_render_fwd(const ivrgs_batch *batch, const ivrgs_params *para
     const int64_t n_tiles = (int64_t)batch->n_jobs * k.tiles_per_job;
     const bool count = (params->flags & IVRGS_FLAG_COUNT_EVAL) != 0;
     uint32_t *queue = nullptr;
-    if (params->flags & IVRGS_FLAG_PERSISTENT) {
-        const Layout L = layout(*batch, *params);
+    float *ckpt = nullptr;
+    const Layout L = layout(*batch, *params);
+    if ((params->flags & IVRGS_FLAG_PERSISTENT) || L.ckpt_bytes) {
         if (!workspace || workspace_bytes < L.total) return IVRGS_E_CAPACITY;
-        queue = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + L.queue);
+        char *ws = static_cast<char *>(workspace);
+        if (params->flags & IVRGS_FLAG_PERSISTENT) queue = reinterpret_cast<uint32_t *>(ws + L.queue);
+        if (L.ckpt_bytes) ckpt = reinterpret_cast<float *>(ws + L.ckpt);
     }
     return hip_status(launch_render_fwd(k, pick_px(params->fwd_px, 1), n_tiles, proj->rec, bins->tile_start,
                                         bins->sorted, out_rgba, out_maxw, bins->status, count, queue,
-                                        params->persist_per_cu, reinterpret_cast<hipStream_t>(stream)));
+                                        params->persist_per_cu, ckpt, reinterpret_cast<hipStream_t>(stream)));
 }
 
 ivrgs_status ivrgs_render_bwd(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
@@ -391,7 +409,10 @@ ivrgs_status ivrgs_render_bwd(const ivrgs_batch *batch, const ivrgs_params *para
                               (params->flags & IVRGS_FLAG_PERSISTENT)
                                   ? reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + L.queue)
                                   : nullptr,
-                              params->persist_per_cu, s);
+                              params->persist_per_cu,
+                              L.ckpt_bytes ? reinterpret_cast<const float *>(static_cast<char *>(workspace) + L.ckpt)
+                                           : nullptr,
+                              s);
     // One job over the whole set (its range lies in [0, n) and has n
     // records) writes every Gaussian's gradient, zeros included; otherwise
     // the planes are cleared first and, when several jobs may share a

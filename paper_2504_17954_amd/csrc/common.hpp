@@ -13,6 +13,26 @@ constexpr int kTilePix = kTile * kTile;
 constexpr int kRecWords = 12;         // floats per projected record
 constexpr int kGradRec = 9;           // record-gradient components
 constexpr int kGradStride = 9;        // floats between the gradient rows of consecutive records
+
+// Long tile lists are cut for the backward: a list of more than kSplitMin
+// records becomes up to kSplitMax segments of equal length (a multiple of 64
+// records, the step of the walks), each walked by its own workgroup from a
+// per-pixel checkpoint (T, C) that the forward stores at the cut.
+constexpr int kSplitMax = 16;
+constexpr uint32_t kSplitMin = 128;
+constexpr int kCkptPix = 256;  // checkpoint floats4 per (tile, cut): one per pixel
+
+__host__ __device__ __forceinline__ void split_of(uint32_t len, int &nseg, uint32_t &seg_len) {
+    if (len <= kSplitMin) {
+        nseg = 1;
+        seg_len = len;
+        return;
+    }
+    uint32_t n = (len + kSplitMin - 1) / kSplitMin;
+    if (n > (uint32_t)kSplitMax) n = kSplitMax;
+    seg_len = (len + 64u * n - 1) / (64u * n) * 64u;
+    nseg = (int)((len + seg_len - 1) / seg_len);  // every segment nonempty
+}
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
 

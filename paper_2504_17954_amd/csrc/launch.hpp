@@ -56,12 +56,16 @@ hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *r
                            int cus, hipStream_t s);
 size_t bin_static_lds_bytes();
 hipError_t set_bin_lds_limit(size_t bytes);
+// ckpt: per-(tile, cut) per-pixel checkpoints [n_tiles][kSplitMax - 1][256]
+// float4, or nullptr: the forward writes them and the backward then walks
+// each segment of a long list in its own workgroup (one pixel per lane and
+// no work queue only; otherwise ignored).
 hipError_t launch_render_fwd(const Consts &k, int px, int64_t n_tiles, const float *rec, const uint32_t *starts,
                              const uint32_t *sorted, float *out, float *maxw, int64_t *status, bool count,
-                             uint32_t *queue, int per_cu, hipStream_t s);
+                             uint32_t *queue, int per_cu, float *ckpt, hipStream_t s);
 hipError_t launch_render_bwd(const Consts &k, int px, int64_t n_tiles, const float *rec, const uint32_t *starts,
                              const uint32_t *sorted, const float *rgba, const float *dl, float *grec,
-                             uint32_t *queue, int per_cu, hipStream_t s);
+                             uint32_t *queue, int per_cu, const float *ckpt, hipStream_t s);
 hipError_t launch_cull(const ivrgs_gaussians &g, const ivrgs_camera *cams, int camera, const ivrgs_culler &mlp,
                        int32_t *out_index, ivrgs_job *jobs, int job, float *logits, uint8_t *keep,
                        uint32_t *counts, hipStream_t s);

@@ -228,11 +228,16 @@ __device__ __forceinline__ void fwd_tile(const Consts &k, const float4 *__restri
 // lane into scalar registers.  The next 64 records are gathered, and the ids
 // of the 64 after them loaded, while the current ones are composited.  No LDS and no workgroup barrier: a wave
 // stops as soon as its own 64 pixels are done.
+//
+// ckpt != nullptr: at every cut of the tile's list (split_of) the wave stores
+// each pixel's state before the cut, (T, C) with T = -1 for a pixel that has
+// already terminated, for the backward's segments.
 template <bool kMaxw, bool kCount>
 __device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__restrict__ rec,
                                               const uint32_t *__restrict__ starts,
                                               const uint32_t *__restrict__ sorted, float *__restrict__ out,
-                                              float *__restrict__ maxw, int64_t *__restrict__ status, int64_t tile) {
+                                              float *__restrict__ maxw, int64_t *__restrict__ status, int64_t tile,
+                                              float4 *__restrict__ ckpt) {
     const TileGeom tg = tile_geom(k, tile);
     const uint32_t start = starts[tile], end = starts[tile + 1];
     walk_priority(end - start);
@@ -268,7 +273,15 @@ __device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__r
         load_recs(start);
         if (start + 64 < end) load_ids(start + 64);
     }
+    int nseg = 1, next_cut = 1;
+    uint32_t seg_len = end - start;
+    if (ckpt) split_of(end - start, nseg, seg_len);
+    auto store_cut = [&](int cut, bool live_px) {
+        ckpt[((size_t)tile * (kSplitMax - 1) + (cut - 1)) * kCkptPix + wave * 64 + lane] =
+            make_float4(live_px ? T : -1.f, C0, C1, C2);
+    };
     for (uint32_t base = start; base < end; base += 64) {
+        if (next_cut < nseg && base - start == (uint32_t)next_cut * seg_len) store_cut(next_cut++, alive);
         const uint64_t live = __ballot(alive);
         if (live == 0ull) break;
         const PixBox bx = alive_box(live, sx, sy);
@@ -339,6 +352,7 @@ __device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__r
             if (__ballot(alive) == 0ull) break;
         }
     }
+    while (next_cut < nseg) store_cut(next_cut++, false);  // the walk ended before these cuts
     if (x < k.width && y < k.height) {
         const size_t plane = (size_t)k.width * k.height;
         float *img = out + (size_t)tg.job * 4 * plane;
@@ -363,9 +377,9 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_fwd(Consts k, const fl
                                                              const uint32_t *__restrict__ starts,
                                                              const uint32_t *__restrict__ sorted, int64_t n_tiles,
                                                              float *__restrict__ out, float *__restrict__ maxw,
-                                                             int64_t *__restrict__ status) {
+                                                             int64_t *__restrict__ status, float4 *__restrict__ ckpt) {
     if (starts[n_tiles] == 0xFFFFFFFFu) return;
-    if constexpr (PX == 1) fwd_tile_wave<kMaxw, kCount>(k, rec, starts, sorted, out, maxw, status, blockIdx.x);
+    if constexpr (PX == 1) fwd_tile_wave<kMaxw, kCount>(k, rec, starts, sorted, out, maxw, status, blockIdx.x, ckpt);
     else fwd_tile<PX, kMaxw, kCount>(k, rec, starts, sorted, out, maxw, status, blockIdx.x);
 }
 
@@ -389,7 +403,8 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_fwd_persistent(
     const uint32_t n_items = queue[1];
     uint32_t item;
     while (next_item(queue, n_items, item)) {
-        if constexpr (PX == 1) fwd_tile_wave<kMaxw, kCount>(k, rec, starts, sorted, out, maxw, status, queue[2 + item]);
+        if constexpr (PX == 1)
+            fwd_tile_wave<kMaxw, kCount>(k, rec, starts, sorted, out, maxw, status, queue[2 + item], nullptr);
         else fwd_tile<PX, kMaxw, kCount>(k, rec, starts, sorted, out, maxw, status, queue[2 + item]);
     }
 }
@@ -406,13 +421,28 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_fwd_persistent(
 // its tile.  Records that composite somewhere in the region fill the three
 // slots of one reduce-scatter; their ids are kept in scalar registers for
 // the atomics.
+//
+// ckpt != nullptr (one pixel per lane): the workgroup walks segment `seg` of
+// the tile's list (split_of), starting from the forward's checkpoint at its
+// cut: T exactly as the forward had it, and the colour prefix as g . C.
 template <int PX>
 __device__ __forceinline__ void bwd_tile_wave(const Consts &k, const float4 *__restrict__ rec,
                                               const uint32_t *__restrict__ starts,
                                               const uint32_t *__restrict__ sorted, const float *__restrict__ rgba,
-                                              const float *__restrict__ dl, float *__restrict__ grec, int64_t tile) {
+                                              const float *__restrict__ dl, float *__restrict__ grec, int64_t tile,
+                                              int seg, const float4 *__restrict__ ckpt) {
     const TileGeom tg = tile_geom(k, tile);
-    const uint32_t start = starts[tile], end = starts[tile + 1];
+    uint32_t start = starts[tile], end = starts[tile + 1];
+    if (PX == 1 && ckpt) {
+        int nseg;
+        uint32_t seg_len;
+        split_of(end - start, nseg, seg_len);
+        if (seg >= nseg) return;  // the whole workgroup
+        start += (uint32_t)seg * seg_len;
+        end = min(end, start + seg_len);
+    } else if (seg > 0) {
+        return;
+    }
     walk_priority(end - start);
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -447,6 +477,15 @@ __device__ __forceinline__ void bwd_tile_wave(const Consts &k, const float4 *__r
             go[j] = fmaf(g2[j], img[2 * plane + o], fmaf(g1[j], img[plane + o], g0[j] * img[o]));
             gATf[j] = gA * Tf;
             alive[j] = (g0[j] != 0.f) | (g1[j] != 0.f) | (g2[j] != 0.f) | (gA != 0.f);
+        }
+        if (PX == 1 && ckpt && seg > 0) {
+            const float4 c = ckpt[((size_t)tile * (kSplitMax - 1) + (seg - 1)) * kCkptPix + wave * 64 + lane];
+            if (c.x < 0.f) {
+                alive[j] = false;  // terminated before the cut
+            } else {
+                T[j] = c.x;
+                gP[j] = fmaf(g2[j], c.w, fmaf(g1[j], c.z, g0[j] * c.y));
+            }
         }
     }
     auto any_alive = [&]() {
@@ -604,9 +643,10 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_bwd(Consts k, const fl
                                                              const uint32_t *__restrict__ starts,
                                                              const uint32_t *__restrict__ sorted, int64_t n_tiles,
                                                              const float *__restrict__ rgba,
-                                                             const float *__restrict__ dl, float *__restrict__ grec) {
+                                                             const float *__restrict__ dl, float *__restrict__ grec,
+                                                             const float4 *__restrict__ ckpt) {
     if (starts[n_tiles] == 0xFFFFFFFFu) return;
-    bwd_tile_wave<PX>(k, rec, starts, sorted, rgba, dl, grec, blockIdx.x);
+    bwd_tile_wave<PX>(k, rec, starts, sorted, rgba, dl, grec, blockIdx.x, blockIdx.y, ckpt);
 }
 
 template <int PX>
@@ -618,7 +658,7 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_bwd_persistent(
     const uint32_t n_items = queue[1];
     uint32_t item;
     while (next_item(queue, n_items, item)) {
-        bwd_tile_wave<PX>(k, rec, starts, sorted, rgba, dl, grec, queue[2 + item]);
+        bwd_tile_wave<PX>(k, rec, starts, sorted, rgba, dl, grec, queue[2 + item], 0, nullptr);
     }
 }
 
@@ -626,7 +666,7 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_bwd_persistent(
 template <int PX>
 static void fwd_variant(bool maxw, bool count, dim3 grid, hipStream_t s, const Consts &k, const float4 *rec,
                         const uint32_t *starts, const uint32_t *sorted, int64_t n_tiles, float *out, float *mw,
-                        int64_t *status, uint32_t *queue) {
+                        int64_t *status, uint32_t *queue, float4 *ckpt) {
     constexpr int NT = kTilePix / PX;
     if (queue) {
 #define IVRGS_FWD_P(M, C)                                                                                          \
@@ -640,7 +680,8 @@ static void fwd_variant(bool maxw, bool count, dim3 grid, hipStream_t s, const C
         return;
     }
 #define IVRGS_FWD(M, C) \
-    hipLaunchKernelGGL((k_render_fwd<PX, M, C>), grid, dim3(NT), 0, s, k, rec, starts, sorted, n_tiles, out, mw, status)
+    hipLaunchKernelGGL((k_render_fwd<PX, M, C>), grid, dim3(NT), 0, s, k, rec, starts, sorted, n_tiles, out, mw, status, \
+                       ckpt)
     if (maxw && count) IVRGS_FWD(true, true);
     else if (maxw) IVRGS_FWD(true, false);
     else if (count) IVRGS_FWD(false, true);
@@ -684,7 +725,8 @@ static dim3 persistent_grid_fwd(bool maxw, bool count, int per_cu) {
 
 hipError_t launch_render_fwd(const Consts &k, int px, int64_t n_tiles, const float *rec, const uint32_t *starts,
                              const uint32_t *sorted, float *out, float *maxw, int64_t *status, bool count,
-                             uint32_t *queue, int per_cu, hipStream_t s) {
+                             uint32_t *queue, int per_cu, float *ckpt, hipStream_t s) {
+    float4 *ck = px == 1 && !queue ? reinterpret_cast<float4 *>(ckpt) : nullptr;
     if (n_tiles == 0) return hipSuccess;
     const float4 *r4 = reinterpret_cast<const float4 *>(rec);
     const bool mw = maxw != nullptr;
@@ -694,9 +736,9 @@ hipError_t launch_render_fwd(const Consts &k, int px, int64_t n_tiles, const flo
     }
     TimedScope ts(TK_FWD, s);
     switch (px) {
-    case 1: fwd_variant<1>(mw, count, queue ? persistent_grid_fwd<1>(mw, count, per_cu) : dim3((unsigned)n_tiles), s, k, r4, starts, sorted, n_tiles, out, maxw, status, queue); break;
-    case 2: fwd_variant<2>(mw, count, queue ? persistent_grid_fwd<2>(mw, count, per_cu) : dim3((unsigned)n_tiles), s, k, r4, starts, sorted, n_tiles, out, maxw, status, queue); break;
-    default: fwd_variant<4>(mw, count, queue ? persistent_grid_fwd<4>(mw, count, per_cu) : dim3((unsigned)n_tiles), s, k, r4, starts, sorted, n_tiles, out, maxw, status, queue); break;
+    case 1: fwd_variant<1>(mw, count, queue ? persistent_grid_fwd<1>(mw, count, per_cu) : dim3((unsigned)n_tiles), s, k, r4, starts, sorted, n_tiles, out, maxw, status, queue, ck); break;
+    case 2: fwd_variant<2>(mw, count, queue ? persistent_grid_fwd<2>(mw, count, per_cu) : dim3((unsigned)n_tiles), s, k, r4, starts, sorted, n_tiles, out, maxw, status, queue, nullptr); break;
+    default: fwd_variant<4>(mw, count, queue ? persistent_grid_fwd<4>(mw, count, per_cu) : dim3((unsigned)n_tiles), s, k, r4, starts, sorted, n_tiles, out, maxw, status, queue, nullptr); break;
     }
     return hipGetLastError();
 }
@@ -704,7 +746,7 @@ hipError_t launch_render_fwd(const Consts &k, int px, int64_t n_tiles, const flo
 template <int PX>
 static void bwd_variant(hipStream_t s, const Consts &k, const float4 *rec, const uint32_t *starts,
                         const uint32_t *sorted, int64_t n_tiles, const float *rgba, const float *dl, float *grec,
-                        uint32_t *queue, int per_cu) {
+                        uint32_t *queue, int per_cu, const float4 *ckpt) {
     constexpr int NT = kTilePix / PX;
     if (queue) {
         static int occ = 0;  // queried once
@@ -713,14 +755,16 @@ static void bwd_variant(hipStream_t s, const Consts &k, const float4 *rec, const
         hipLaunchKernelGGL(k_render_bwd_persistent<PX>, dim3((unsigned)(nb * cu_count())), dim3(NT), 0, s, k, rec,
                            starts, sorted, n_tiles, rgba, dl, grec, queue);
     } else {
-        hipLaunchKernelGGL(k_render_bwd<PX>, dim3((unsigned)n_tiles), dim3(NT), 0, s, k, rec, starts, sorted, n_tiles,
-                           rgba, dl, grec);
+        // one workgroup per (tile, segment of its list)
+        hipLaunchKernelGGL(k_render_bwd<PX>, dim3((unsigned)n_tiles, ckpt ? kSplitMax : 1), dim3(NT), 0, s, k, rec,
+                           starts, sorted, n_tiles, rgba, dl, grec, ckpt);
     }
 }
 
 hipError_t launch_render_bwd(const Consts &k, int px, int64_t n_tiles, const float *rec, const uint32_t *starts,
                              const uint32_t *sorted, const float *rgba, const float *dl, float *grec,
-                             uint32_t *queue, int per_cu, hipStream_t s) {
+                             uint32_t *queue, int per_cu, const float *ckpt, hipStream_t s) {
+    const float4 *ck = px == 1 && !queue ? reinterpret_cast<const float4 *>(ckpt) : nullptr;
     if (n_tiles == 0) return hipSuccess;
     const float4 *r4 = reinterpret_cast<const float4 *>(rec);
     if (queue) {
@@ -729,9 +773,9 @@ hipError_t launch_render_bwd(const Consts &k, int px, int64_t n_tiles, const flo
     }
     TimedScope ts(TK_BWD, s);
     switch (px) {
-    case 1: bwd_variant<1>(s, k, r4, starts, sorted, n_tiles, rgba, dl, grec, queue, per_cu); break;
-    case 2: bwd_variant<2>(s, k, r4, starts, sorted, n_tiles, rgba, dl, grec, queue, per_cu); break;
-    default: bwd_variant<4>(s, k, r4, starts, sorted, n_tiles, rgba, dl, grec, queue, per_cu); break;
+    case 1: bwd_variant<1>(s, k, r4, starts, sorted, n_tiles, rgba, dl, grec, queue, per_cu, ck); break;
+    case 2: bwd_variant<2>(s, k, r4, starts, sorted, n_tiles, rgba, dl, grec, queue, per_cu, nullptr); break;
+    default: bwd_variant<4>(s, k, r4, starts, sorted, n_tiles, rgba, dl, grec, queue, per_cu, nullptr); break;
     }
     return hipGetLastError();
 }

@@ -270,7 +270,13 @@ class Renderer:
                  gauss_index=None, rebin: bool = False, grads=None):
         batch = self.make_batch(planes, model_id, edits_t, cams_t, jobs, gauss_index)
         if rebin:
+            # recompute what the backward reads besides the image: the
+            # records, the bins and the list checkpoints of the forward (its
+            # image comes out bit-identical and is discarded)
             proj, bins = self.project_and_bin(batch)
+            scratch = torch.empty_like(rgba)
+            N.ivrgs_render_fwd(batch, self.settings.params(), proj, bins, scratch.data_ptr(), None,
+                               self.ws.data_ptr(), self.ws.numel(), _stream())
         else:
             self._ensure(batch)
             proj, bins = self._structs(batch)

@@ -56,6 +56,36 @@ def test_persistent_backward(dev):
                 exclude=grad_exclusions(planes, cam, prm))
 
 
+def test_split_backward_matches_whole_walks(dev):
+    """Long tile lists are cut and their segments walked from the forward's
+    checkpoints (one pixel per lane); the persistent launch walks every list
+    whole.  Both equal the oracle gradient, and each other to rounding."""
+    m = I.small_scene(30_000, 811, log_scale_mu=-3.4)
+    planes = I.plain_planes(m)
+    cam = I.look_at((0.2, -3.0, 0.6), width=96, height=96)
+    prm = O.Params(96, 96)
+    ref = O.render(planes, cam, prm)
+    dl = O.l1_loss_grad(ref["rgba"], np.random.default_rng(12).uniform(0, 1, ref["rgba"].shape))
+    dl[:, ref["flags"] != 0] = 0.0
+    g_ref, _ = O.backward(planes, cam, prm, dl)
+    pd = to_dev(planes, dev)
+    cams, jobs = R.camera_table([cam]), R.Jobs.single(m.n)
+    out = {}
+    for name, flags in (("split", 0), ("whole", N.FLAG_PERSISTENT)):
+        rnd = R.Renderer(R.Settings(96, 96, flags=flags))
+        rgba = rnd.forward(pd, cams, jobs, edits_t=R.default_edits(dev))
+        lens = np.diff(rnd.tile_start[:37].cpu().numpy().astype(np.int64))
+        g = rnd.backward(pd, cams, jobs, rgba, torch.from_numpy(dl[None].astype(np.float32)).to(dev),
+                         edits_t=R.default_edits(dev))
+        out[name] = {k: v.cpu().numpy() for k, v in g.items()}
+        say(f"{name}: longest tile list {lens.max()} (cut above 128, into up to 16 segments)")
+        assert lens.max() > 16 * 128  # the longest lists take every cut
+        check_grads(out[name], g_ref, f"{name} bwd", exclude=grad_exclusions(planes, cam, prm))
+    for k in R.PLANES:
+        a, b = out["split"][k], out["whole"][k]
+        assert np.all(np.abs(a - b) <= 1e-4 * np.abs(b) + 1e-6 * np.abs(b).max()), k
+
+
 def batched_setup(W=64, H=48, n_views=3):
     sizes = (300, 800, 1500)
     models = [I.small_scene(n, 700 + i, log_scale_mu=-3.0) for i, n in enumerate(sizes)]
