@@ -160,7 +160,6 @@ size_t ckpt_bytes(const ivrgs_batch &b, const ivrgs_params &p, const Consts &k) 
     return bytes <= kCkptBudget ? bytes : 0;
 }
 
-// Records per binning chunk: a multiple of 64 (one wave walks a chunk).
 // Records per binning chunk: the caller's choice rounded up to a multiple of
 // 64 (one wave walks a chunk), or by default the largest power of two up to
 // kDefaultChunk that still gives about kChunkTarget chunks over the batch, so

@@ -37,14 +37,23 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Active lanes whose value v (bits < nbits) equals this lane's.
+// Active lanes whose value v (bits < nbits <= kMaxBits) equals this lane's.
+// Per bit: the lane's bit sign-extended to a full word x (0 or ~0) gives
+// the ballot of set bits b, and the lanes that agree with this lane are
+// ~b ^ x (b where the bit is set, ~b where it is clear); nbits is uniform.
+template <int kMaxBits>
 __device__ __forceinline__ uint64_t match_bits(uint32_t v, int nbits, uint64_t active) {
-    uint64_t m = active;
-    for (int bit = 0; bit < nbits; ++bit) {
-        const uint64_t bb = __ballot((v >> bit) & 1u);
-        m &= ((v >> bit) & 1u) ? bb : ~bb;
+    uint32_t lo = (uint32_t)active, hi = (uint32_t)(active >> 32);
+#pragma unroll
+    for (int bit = 0; bit < kMaxBits; ++bit) {
+        if (bit < nbits) {
+            const uint32_t x = (uint32_t)__builtin_amdgcn_sbfe((int)v, bit, 1);
+            const uint64_t bb = __ballot(x != 0u);
+            lo &= ~(uint32_t)bb ^ x;
+            hi &= ~(uint32_t)(bb >> 32) ^ x;
+        }
     }
-    return m;
+    return (uint64_t)hi << 32 | lo;
 }
 
 // ---------------------------------------------------------------------------
@@ -262,7 +271,7 @@ __global__ __launch_bounds__(kSegThreads) void k_dsort_scatter(ivrgs_batch b, co
         if (w0 + u * 64 < n) {  // wave-uniform
             const bool act = w0 + u * 64 + lane < n;
             const uint32_t dg = (kk[u] >> shift) & 255u;
-            const uint64_t m = match_bits(dg, 8, __ballot(act));
+            const uint64_t m = match_bits<8>(dg, 8, __ballot(act));
             const uint32_t rank = lanes_below(m);
             const uint32_t pos = wh[wave][dg] + rank;
             if (act) {
@@ -430,13 +439,27 @@ __global__ __launch_bounds__(256) void k_col_sum(ivrgs_batch b, Consts k, const 
     part[((int64_t)blockIdx.z * n_part + blockIdx.y) * k.tiles_per_job + t] = sum;
 }
 
+constexpr int kPartUnroll = 16;
+
 __global__ __launch_bounds__(256) void k_col_part_scan(ivrgs_batch b, Consts k, uint32_t *__restrict__ part,
                                                        int n_part, uint32_t *__restrict__ tile_counts) {
     const int t = blockIdx.x * 256 + threadIdx.x;
     if (t >= k.tiles_per_job) return;
     uint32_t *p = part + (int64_t)blockIdx.y * n_part * k.tiles_per_job + t;
     uint32_t run = 0;
-    for (int i = 0; i < n_part; ++i) {
+    int i = 0;
+    // loads issued kPartUnroll at a time: one memory round trip per batch
+    for (; i + kPartUnroll <= n_part; i += kPartUnroll) {
+        uint32_t v[kPartUnroll];
+#pragma unroll
+        for (int u = 0; u < kPartUnroll; ++u) v[u] = p[(int64_t)(i + u) * k.tiles_per_job];
+#pragma unroll
+        for (int u = 0; u < kPartUnroll; ++u) {
+            p[(int64_t)(i + u) * k.tiles_per_job] = run;
+            run += v[u];
+        }
+    }
+    for (; i < n_part; ++i) {
         const uint32_t v = p[(int64_t)i * k.tiles_per_job];
         p[(int64_t)i * k.tiles_per_job] = run;
         run += v;
@@ -531,7 +554,7 @@ __global__ __launch_bounds__(NW * 64) void k_scatter(ivrgs_batch b, Consts k, co
     if (begin >= job.gauss_count) return;
     const int end = min(begin + chunk, job.gauss_count);
     const int tpj = k.tiles_per_job, tx_n = k.tiles_x;
-    const int tile_bits = 32 - __clz(max(tpj - 1, 1));
+    const int tile_bits = __builtin_amdgcn_readfirstlane(32 - __clz(max(tpj - 1, 1)));
     const int wave = threadIdx.x >> 6;
     const uint32_t *order = depth_order(rng, b.n_jobs, blockIdx.y, val0, val1);
     const float4 *rec4 = reinterpret_cast<const float4 *>(rec);
@@ -572,7 +595,7 @@ __global__ __launch_bounds__(NW * 64) void k_scatter(ivrgs_batch b, Consts k, co
     __syncthreads();
     for_each_pair(job, qb, qe, 64, order, rec4, rect, L[wave], [&](uint32_t r, int x, int y) {
         const uint32_t t = (uint32_t)(y * tx_n + x);
-        const uint64_t m = match_bits(t, tile_bits, __ballot(true));
+        const uint64_t m = match_bits<16>(t, tile_bits, __ballot(true));
         const uint32_t rank = lanes_below(m);
         const uint32_t at = c[t];
         sorted[at + rank] = r;
