@@ -67,28 +67,34 @@ int seg_rows(const ivrgs_batch &b) { return (b.max_job_count + kSeg - 1) / kSeg;
 
 // AND and OR of the depth keys of each job's visible records (rng[j] and
 // rng[n_jobs + j], preset to ~0 and 0).  Culled records carry the key ~0.
-constexpr int kRangeBlocks = 64;  // workgroups per job for the key range
-
 __global__ void k_rng_init(uint32_t *__restrict__ rng, int n_jobs) {
     for (int i = threadIdx.x; i < 2 * n_jobs; i += blockDim.x) rng[i] = i < n_jobs ? 0xFFFFFFFFu : 0u;
 }
 
-// Grid-stride over the job's records; the four waves combine in LDS so each
-// workgroup adds one AND and one OR (at most kRangeBlocks same-address
-// atomics per job: they serialise in L2).
+// One workgroup per segment of kSeg keys, kSegItems loads per thread issued
+// together; the four waves combine in LDS so each workgroup adds one AND and
+// one OR (same-address atomics serialise in L2: one pair per segment).
 __global__ __launch_bounds__(kSegThreads) void k_dkey_range(ivrgs_batch b, const uint32_t *__restrict__ depth,
                                                             uint32_t *__restrict__ rng) {
     __shared__ uint32_t sa[kSegThreads / 64], so[kSegThreads / 64];
     const ivrgs_job job = b.jobs[blockIdx.y];
+    const int64_t base = (int64_t)blockIdx.x * kSeg;
+    if (base >= job.gauss_count) return;
+    const int n = (int)min((int64_t)kSeg, job.gauss_count - base);
+    const uint32_t *z = depth + job.rec_begin + base;
     uint32_t a = 0xFFFFFFFFu, o = 0u;
-    for (int64_t i = (int64_t)blockIdx.x * kSegThreads + threadIdx.x; i < job.gauss_count;
-         i += (int64_t)gridDim.x * kSegThreads) {
-        const uint32_t z = depth[(int64_t)job.rec_begin + i];
-        if (z != 0xFFFFFFFFu) {
-            a &= z;
-            o |= z;
-        }
+    uint32_t v[kSegItems];
+#pragma unroll
+    for (int u = 0; u < kSegItems; ++u) {
+        const int i = u * kSegThreads + threadIdx.x;
+        v[u] = i < n ? z[i] : 0xFFFFFFFFu;
     }
+#pragma unroll
+    for (int u = 0; u < kSegItems; ++u)
+        if (v[u] != 0xFFFFFFFFu) {
+            a &= v[u];
+            o |= v[u];
+        }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
         a &= __shfl_xor(a, d, 64);
@@ -146,7 +152,15 @@ __global__ __launch_bounds__(kSegThreads) void k_dsort_hist(ivrgs_batch b, const
     const int before = passes_before(rng, b.n_jobs, blockIdx.y, shift);
     const uint32_t *k = (before == 0 ? depth : ((before - 1) & 1 ? key1 : key0)) + job.rec_begin + base;
     const int n = (int)min((int64_t)kSeg, job.gauss_count - base);
-    for (int i = threadIdx.x; i < n; i += kSegThreads) atomicAdd(&h[(k[i] >> shift) & 255u], 1u);
+    uint32_t v[kSegItems];
+#pragma unroll
+    for (int u = 0; u < kSegItems; ++u) {
+        const int i = u * kSegThreads + threadIdx.x;
+        v[u] = i < n ? k[i] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kSegItems; ++u)
+        if (u * kSegThreads + (int)threadIdx.x < n) atomicAdd(&h[(v[u] >> shift) & 255u], 1u);
     __syncthreads();
     hist[((int64_t)blockIdx.y * 256 + threadIdx.x) * n_seg + blockIdx.x] = h[threadIdx.x];
 }
@@ -306,6 +320,31 @@ struct ExpandLds {
 };
 constexpr int kBinWaves = 4;  // waves per binning workgroup (sharing one chunk)
 
+// Inclusive prefix maximum over the lanes of a wave, for values >= -1 (a lane
+// with no source in a step takes -1): DPP shifts within each row of 16,
+// then row_bcast15 / row_bcast31 carry the row maxima into the later rows.
+__device__ __forceinline__ int wave_prefix_max(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xF, 0xF, false));  // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xF, 0xF, false));  // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xF, 0xF, false));  // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xF, 0xF, false));  // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xA, 0xF, false));  // row_bcast15 -> rows 1, 3
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xC, 0xF, false));  // row_bcast31 -> rows 2, 3
+    return v;
+}
+
+// Inclusive prefix sum over the lanes of a wave, with the same DPP steps.
+__device__ __forceinline__ uint32_t wave_prefix_sum(uint32_t u) {
+    int v = (int)u;
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);
+    return (uint32_t)v;
+}
+
 // Orders a wave's LDS writes before its other lanes' reads.
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -339,12 +378,7 @@ __device__ __forceinline__ void for_each_pair(const ivrgs_job &job, int begin, i
                 L.rid[lane] = (uint32_t)r;
             }
         }
-        uint32_t incl = n;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t o = __shfl_up(incl, d, 64);
-            if (lane >= d) incl += o;
-        }
+        const uint32_t incl = wave_prefix_sum(n);
         const uint32_t my_off = incl - n;
         L.off[lane] = my_off;
         const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
@@ -354,28 +388,31 @@ __device__ __forceinline__ void for_each_pair(const ivrgs_job &job, int begin, i
             wave_lds_sync();
             if (n != 0u && my_off >= base && my_off < base + 64u) L.mark[my_off - base] = lane;
             wave_lds_sync();
-            const int m = L.mark[lane];
-            const uint64_t starts = __ballot(m >= 0);
-            const uint64_t upto = starts & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
-            const int j = upto ? __shfl(m, 63 - __clzll(upto), 64) : carry;
+            // marks rise with the position, so the last one at or before
+            // this item is the prefix maximum
+            const int pm = wave_prefix_max(L.mark[lane]);
+            const int j = pm >= 0 ? pm : carry;
             carry = __builtin_amdgcn_readlane(j, 63);
             const uint32_t idx = base + lane;
             if (idx < total) {
-                const uint32_t t = idx - L.off[j];
-                const uint32_t w = L.wid[j];
+                // every field of the item's record in one LDS round trip
+                const uint32_t offj = L.off[j], w = L.wid[j], o = L.org[j], rid = L.rid[j];
+                const float iw = L.iwid[j];
+                const float4 a = L.h0[j], c = L.h1[j];
+                asm volatile("" ::"v"(offj), "v"(w), "v"(o), "v"(rid), "v"(iw), "v"(a.x), "v"(a.y), "v"(a.z),
+                             "v"(a.w), "v"(c.x), "v"(c.y), "v"(c.z), "v"(c.w));
+                const uint32_t t = idx - offj;
                 // t / w from the reciprocal, corrected to the exact value:
                 // t is below the tiles of one job (at most 2^16, as the
                 // per-tile LDS counters require), where the estimate is
                 // within one of the quotient
-                int q = (int)((float)t * L.iwid[j]);
+                int q = (int)((float)t * iw);
                 q -= (int)((uint32_t)q * w > t);
                 q += (int)((uint32_t)(q + 1) * w <= t);
                 const uint32_t dy = (uint32_t)q, dx = t - dy * w;
-                const uint32_t o = L.org[j];
                 const int x = (int)((o & 0xFFFFu) + dx), y = (int)((o >> 16) + dy);
-                const float4 a = L.h0[j], c = L.h1[j];
                 const HitTest h = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
-                if (box_hit(h, x * kTile, y * kTile, kTile, kTile)) f(L.rid[j], x, y);
+                if (box_hit(h, x * kTile, y * kTile, kTile, kTile)) f(rid, x, y);
             }
         }
         wave_lds_sync();  // every lane is done with the tables before they are rewritten
@@ -595,9 +632,9 @@ __global__ __launch_bounds__(NW * 64) void k_scatter(ivrgs_batch b, Consts k, co
     __syncthreads();
     for_each_pair(job, qb, qe, 64, order, rec4, rect, L[wave], [&](uint32_t r, int x, int y) {
         const uint32_t t = (uint32_t)(y * tx_n + x);
+        const uint32_t at = c[t];  // read ahead of the match, which hides its latency
         const uint64_t m = match_bits<16>(t, tile_bits, __ballot(true));
         const uint32_t rank = lanes_below(m);
-        const uint32_t at = c[t];
         sorted[at + rank] = r;
         if (rank == 0) c[t] = at + (uint32_t)__popcll(m);
     });
@@ -699,8 +736,7 @@ hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *r
     if (n_seg > 0) {
         TimedScope ts(TK_SORT, s);
         hipLaunchKernelGGL(k_rng_init, dim3(1), dim3(256), 0, s, w.rng, b.n_jobs);
-        hipLaunchKernelGGL(k_dkey_range, dim3(n_seg < kRangeBlocks ? n_seg : kRangeBlocks, b.n_jobs),
-                           dim3(kSegThreads), 0, s, b, depth, w.rng);
+        hipLaunchKernelGGL(k_dkey_range, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, depth, w.rng);
         for (int pass = 0; pass < 4; ++pass) {
             const int shift = 8 * pass;
             hipLaunchKernelGGL(k_dsort_hist, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, depth, w.key[0],
