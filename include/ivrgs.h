@@ -297,10 +297,10 @@ ivrgs_status ivrgs_light_bwd(const ivrgs_batch *batch, const ivrgs_params *param
  * 0 project, 1 tile counts (per-chunk counts, column and tile scans, work
  * queue), 2 scatter, 3 depth order, 4 render_fwd, 5 render_bwd,
  * 6 project_bwd, 7 compose, 8 fills, 9 cull, 10 edit and light gradients
- * and the exploration step.  Process-wide state; not for concurrent
- * callers. */
-#define IVRGS_TIMING_KINDS 11
-#define IVRGS_TIMING_ALL 0x7FFu
+ * and the exploration step, 11 VQ (k-means, assignment, quantised compose).
+ * Process-wide state; not for concurrent callers. */
+#define IVRGS_TIMING_KINDS 12
+#define IVRGS_TIMING_ALL 0xFFFu
 void ivrgs_timing_enable(uint32_t kinds);
 int32_t ivrgs_timing_read(double *ms, int64_t *launches);
 
@@ -378,9 +378,72 @@ ivrgs_status ivrgs_explore_step(const float *edit_grad, const float *light_grad,
                                 const ivrgs_explore_opts *opts, float *state, ivrgs_model_edit *edits,
                                 void *stream);
 
+/* ---- Vector quantisation (Sec. 4.4) ------------------------------------
+ * k-means gives one codebook per attribute over all the Gaussians of a basic
+ * model; a vector attribute shares one scalar codebook, with one index per
+ * component; mean and normal stay exact.  The attributes (Sec. 4.3) are
+ * log-scale, rotation, opacity, offset colour delta-c, and the shading terms
+ * k_a, k_d, k_s, beta: eight codebooks.  Codebook size k is 1..256 (one byte
+ * per index).  The paper gives no sizes or schedule; the readings here:
+ * initial centroids at the centres of k equal cells of [min, max] of the
+ * finite values (lo + (j + 1/2) * ((hi - lo) / k), FP32); each Lloyd
+ * iteration assigns every value to its nearest centroid (|x - c| in FP32,
+ * the lowest index on ties), moves each non-empty cluster's centroid to the
+ * FP64 mean of its values rounded to FP32 (an empty cluster keeps its
+ * centroid) and sorts the codebook ascending; the indices are the assignment
+ * to the final codebook.  Non-finite values take index 0 and move no
+ * centroid. */
+
+/* A quantised basic model.  Index planes, component-major [15][n] uint8:
+ * log_scale 0-2, quat 3-6, opacity 7, delta-c 8-10, k_a 11, k_d 12, k_s 13,
+ * beta 14; codebooks [8][k] FP32: log_scale, quat, opacity, delta-c, k_a,
+ * k_d, k_s, beta (index plane p reads codebook 0,0,0,1,1,1,1,2,3,3,3,4,5,6,7).
+ * An index >= k reads entry k - 1.  All pointers device. */
+typedef struct {
+    int64_t n;
+    const float *mean;      /* [3][n], exact */
+    const float *normal;    /* [3][n], exact */
+    const uint8_t *index;   /* [15][n] */
+    const float *codebook;  /* [8][k] */
+    int32_t k;              /* 1..256 */
+} ivrgs_vq_model;
+
+/* Workspace bytes of ivrgs_vq_fit for n values and codebook size k (per
+ * workgroup FP64 sums and counts of every centroid, and value ranges). */
+size_t ivrgs_vq_workspace_size(int64_t n, int32_t k);
+
+/* k-means codebook of one attribute (values: device [n] FP32, all the
+ * components of the attribute back to back) with `iters` Lloyd iterations
+ * (>= 0) from the cell-centre initialisation, then the index of every value
+ * against the final codebook.  Outputs: codebook (device [k], ascending)
+ * and index (device [n] uint8).  workspace: device, at least
+ * ivrgs_vq_workspace_size(n, k) bytes.  n = 0 writes an all-zero codebook.
+ * Returns IVRGS_E_INVALID for k outside 1..256, iters < 0 or a null pointer
+ * (values and index may be null when n = 0), IVRGS_E_CAPACITY for a short
+ * workspace. */
+ivrgs_status ivrgs_vq_fit(const float *values, int64_t n, int32_t k, int32_t iters, float *codebook,
+                          uint8_t *index, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Nearest-centroid index of each value (the assignment step of the fit):
+ * argmin_j |x - c_j| in FP32, the lowest index on ties, 0 for non-finite
+ * values.  Any codebook order is accepted (an ascending one takes a binary
+ * search, any other a full scan).  values: device [n]; codebook: device
+ * [k], k in 1..256; index: device [n] uint8. */
+ivrgs_status ivrgs_vq_assign(const float *values, int64_t n, const float *codebook, int32_t k,
+                             uint8_t *index, void *stream);
+
+/* Composition and editing of quantised models (Sec. 4.5: each model is
+ * decompressed from its indices and codebooks and appended): the same
+ * output and edits as ivrgs_compose, with every quantised attribute read
+ * through its codebook inside the kernel.  models: HOST array of n_models
+ * structs; edits: HOST array of n_models rows; out->n must equal the sum of
+ * models[m].n. */
+ivrgs_status ivrgs_vq_compose(const ivrgs_vq_model *models, int32_t n_models, const ivrgs_model_edit *edits,
+                              ivrgs_gaussians_mut *out, void *stream);
+
 /* sizeof of the ABI structs, for binding checks: which = 0 gaussians,
  * 1 camera, 2 model_edit, 3 job, 4 batch, 5 params, 6 projected, 7 bins,
- * 8 culler, 9 explore_opts. */
+ * 8 culler, 9 explore_opts, 10 vq_model. */
 int32_t ivrgs_struct_size(int32_t which);
 
 /* Human-readable name of a status code. */

@@ -265,6 +265,55 @@ ivrgs_status ivrgs_compose_dev(const ivrgs_gaussians *models, int32_t n_models, 
     return compose_common(models, n_models, nullptr, edits, out, stream);
 }
 
+size_t ivrgs_vq_workspace_size(int64_t n, int32_t k) {
+    if (n < 0 || k < 1 || k > 256) return 0;
+    return vq_workspace_bytes(n, k);
+}
+
+ivrgs_status ivrgs_vq_fit(const float *values, int64_t n, int32_t k, int32_t iters, float *codebook,
+                          uint8_t *index, void *workspace, size_t workspace_bytes, void *stream) {
+    if (n < 0 || k < 1 || k > 256 || iters < 0 || !codebook || !workspace) return IVRGS_E_INVALID;
+    if (n > 0 && (!values || !index)) return IVRGS_E_INVALID;
+    if (workspace_bytes < vq_workspace_bytes(n, k)) return IVRGS_E_CAPACITY;
+    return hip_status(launch_vq_fit(values, n, k, iters, codebook, index, workspace,
+                                    reinterpret_cast<hipStream_t>(stream)));
+}
+
+ivrgs_status ivrgs_vq_assign(const float *values, int64_t n, const float *codebook, int32_t k, uint8_t *index,
+                             void *stream) {
+    if (n < 0 || k < 1 || k > 256 || !codebook) return IVRGS_E_INVALID;
+    if (n > 0 && (!values || !index)) return IVRGS_E_INVALID;
+    return hip_status(launch_vq_assign(values, n, codebook, k, index, reinterpret_cast<hipStream_t>(stream)));
+}
+
+ivrgs_status ivrgs_vq_compose(const ivrgs_vq_model *models, int32_t n_models, const ivrgs_model_edit *edits,
+                              ivrgs_gaussians_mut *out, void *stream) {
+    if (!models || !edits || !out || n_models <= 0) return IVRGS_E_INVALID;
+    if (!valid_gauss_mut(*out) || (out->n > 0 && !out->model_id)) return IVRGS_E_INVALID;
+    int64_t total = 0;
+    for (int m = 0; m < n_models; ++m) {
+        const ivrgs_vq_model &q = models[m];
+        if (q.n < 0) return IVRGS_E_INVALID;
+        if (q.n > 0 && (!q.mean || !q.normal || !q.index || !q.codebook || q.k < 1 || q.k > 256))
+            return IVRGS_E_INVALID;
+        total += q.n;
+    }
+    if (total != out->n) return IVRGS_E_SHAPE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int64_t off = 0;
+    for (int m0 = 0; m0 < n_models; m0 += kComposeModels) {
+        const int cnt = std::min(kComposeModels, n_models - m0);
+        int64_t offs[kComposeModels];
+        for (int j = 0; j < cnt; ++j) {
+            offs[j] = off;
+            off += models[m0 + j].n;
+        }
+        const hipError_t e = launch_vq_compose(models + m0, offs, m0, cnt, edits + m0, *out, s);
+        if (e != hipSuccess) return IVRGS_E_HIP;
+    }
+    return IVRGS_OK;
+}
+
 int64_t ivrgs_explore_state_words(int32_t n_models) {
     if (n_models <= 0) return 0;
     return 3 * (4 * (int64_t)n_models + 10) + 1;
@@ -494,6 +543,7 @@ int32_t ivrgs_struct_size(int32_t which) {
     case 7: return (int32_t)sizeof(ivrgs_bins);
     case 8: return (int32_t)sizeof(ivrgs_culler);
     case 9: return (int32_t)sizeof(ivrgs_explore_opts);
+    case 10: return (int32_t)sizeof(ivrgs_vq_model);
     default: return -1;
     }
 }

@@ -7,7 +7,7 @@ namespace ivrgs {
 
 // Kernel-timing hooks (no-ops unless timing is enabled).
 enum TimingKind { TK_PROJECT = 0, TK_COUNT, TK_SCATTER, TK_SORT, TK_FWD, TK_BWD, TK_PROJECT_BWD,
-                  TK_COMPOSE, TK_FILL, TK_CULL, TK_EDIT_BWD, TK_KINDS };
+                  TK_COMPOSE, TK_FILL, TK_CULL, TK_EDIT_BWD, TK_VQ, TK_KINDS };
 void timing_begin(int kind, hipStream_t s);
 void timing_end(int kind, hipStream_t s);
 
@@ -70,6 +70,16 @@ hipError_t launch_cull(const ivrgs_gaussians &g, const ivrgs_camera *cams, int c
                        int32_t *out_index, ivrgs_job *jobs, int job, float *logits, uint8_t *keep,
                        uint32_t *counts, hipStream_t s);
 size_t cull_workspace_bytes(int64_t n);
+// Vector quantisation: k-means fit of one attribute, assignment against a
+// codebook, and the composition of quantised models (count <= kComposeModels
+// models in one launch, edits: the host rows of those models).
+size_t vq_workspace_bytes(int64_t n, int k);
+hipError_t launch_vq_fit(const float *values, int64_t n, int k, int iters, float *codebook, uint8_t *index,
+                         void *workspace, hipStream_t s);
+hipError_t launch_vq_assign(const float *values, int64_t n, const float *codebook, int k, uint8_t *index,
+                            hipStream_t s);
+hipError_t launch_vq_compose(const ivrgs_vq_model *src, const int64_t *offset, int32_t model0, int32_t count,
+                             const ivrgs_model_edit *edits, const ivrgs_gaussians_mut &out, hipStream_t s);
 hipError_t launch_work_queue(const uint32_t *starts, int64_t n_tiles, uint32_t *queue, hipStream_t s);
 
 }  // namespace ivrgs

@@ -1,0 +1,376 @@
+// Vector quantisation of editable Gaussians (Sec. 4.4): scalar k-means
+// codebooks per attribute, and the composition of quantised models with the
+// codebook reads fused into the compose kernel (Sec. 4.5).
+//
+// The fit is memory-bound over the attribute's values: each Lloyd iteration
+// streams them once, assigns each by binary search over the codebook held
+// in LDS, and accumulates per-centroid FP64 sums and counts in LDS; one
+// small workgroup then folds the per-workgroup partials in a fixed order,
+// forms the means and re-sorts the codebook.
+#include <algorithm>
+
+#include "launch.hpp"
+
+namespace ivrgs {
+
+namespace {
+
+constexpr int kVqThreads = 256;
+constexpr int kVqItems = 16;                    // values per thread per tile
+constexpr int kVqTile = kVqThreads * kVqItems;  // values per tile
+constexpr int kVqMaxGroups = 1024;              // workgroups of the streaming kernels
+constexpr int kVqMaxK = 256;
+constexpr int kUpdateThreads = 1024;            // 4 threads per centroid in the update
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+int vq_groups(int64_t n) {
+    const int64_t tiles = (n + kVqTile - 1) / kVqTile;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kVqMaxGroups));
+}
+
+struct VqWork {
+    double *sum;     // [groups][k]
+    uint32_t *cnt;   // [groups][k]
+    float *range;    // [groups][2]: min, max of the finite values
+};
+
+VqWork vq_work(void *ws, int64_t n, int k) {
+    const int g = vq_groups(n);
+    char *p = static_cast<char *>(ws);
+    VqWork w;
+    w.sum = reinterpret_cast<double *>(p);
+    p += align256(sizeof(double) * (size_t)g * k);
+    w.cnt = reinterpret_cast<uint32_t *>(p);
+    p += align256(sizeof(uint32_t) * (size_t)g * k);
+    w.range = reinterpret_cast<float *>(p);
+    return w;
+}
+
+// Nearest centroid of a finite x in an ascending codebook c[0, k): the
+// index that a scan for the least |x - c_j| (FP32 difference, the lowest
+// index on ties) returns.  Rounding is monotonic, so left of x the
+// difference x - c_j only grows as j falls and right of x c_j - x only grows
+// as j rises: the candidates are the last centroid at or below x, moved down
+// over centroids whose difference rounds to the same value, and the first
+// centroid above x.
+__device__ __forceinline__ int nearest_sorted(float x, const float *c, int k) {
+    int lo = 0, hi = k;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (c[mid] <= x) lo = mid + 1;
+        else hi = mid;
+    }
+    const int q = lo;  // first centroid above x (k if none)
+    if (q == 0) return 0;
+    int p = q - 1;
+    const float dl = x - c[p];
+    while (p > 0 && x - c[p - 1] == dl) --p;
+    if (q == k) return p;
+    return dl <= c[q] - x ? p : q;
+}
+
+__device__ __forceinline__ int nearest_scan(float x, const float *c, int k) {
+    int best = 0;
+    float bd = fabsf(x - c[0]);
+    for (int j = 1; j < k; ++j) {
+        const float d = fabsf(x - c[j]);
+        if (d < bd) {
+            bd = d;
+            best = j;
+        }
+    }
+    return best;
+}
+
+__device__ __forceinline__ bool is_finite32(float x) { return (__float_as_uint(x) & 0x7F800000u) != 0x7F800000u; }
+
+// Per workgroup: min and max of the finite values of its tiles.
+__global__ __launch_bounds__(kVqThreads) void k_vq_range(const float *__restrict__ v, int64_t n,
+                                                         float *__restrict__ part) {
+    __shared__ float slo[kVqThreads / 64], shi[kVqThreads / 64];
+    float lo = __builtin_inff(), hi = -__builtin_inff();
+    for (int64_t t0 = (int64_t)blockIdx.x * kVqTile; t0 < n; t0 += (int64_t)gridDim.x * kVqTile) {
+        float x[kVqItems];
+#pragma unroll
+        for (int u = 0; u < kVqItems; ++u) {
+            const int64_t i = t0 + u * kVqThreads + threadIdx.x;
+            x[u] = i < n ? v[i] : __builtin_nanf("");
+        }
+#pragma unroll
+        for (int u = 0; u < kVqItems; ++u)
+            if (is_finite32(x[u])) {
+                lo = fminf(lo, x[u]);
+                hi = fmaxf(hi, x[u]);
+            }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        lo = fminf(lo, __shfl_xor(lo, d, 64));
+        hi = fmaxf(hi, __shfl_xor(hi, d, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        slo[threadIdx.x >> 6] = lo;
+        shi[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kVqThreads / 64; ++w) {
+            lo = fminf(lo, slo[w]);
+            hi = fmaxf(hi, shi[w]);
+        }
+        part[2 * blockIdx.x] = lo;
+        part[2 * blockIdx.x + 1] = hi;
+    }
+}
+
+// One workgroup: the range over the `groups` partials, then centroid j at
+// lo + (j + 1/2) * ((hi - lo) / k); all zero without a finite value.
+__global__ __launch_bounds__(kVqThreads) void k_vq_init(const float *__restrict__ part, int groups, int k,
+                                                        float *__restrict__ cb) {
+    __shared__ float slo[kVqThreads / 64], shi[kVqThreads / 64];
+    float lo = __builtin_inff(), hi = -__builtin_inff();
+    for (int g = threadIdx.x; g < groups; g += kVqThreads) {
+        lo = fminf(lo, part[2 * g]);
+        hi = fmaxf(hi, part[2 * g + 1]);
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        lo = fminf(lo, __shfl_xor(lo, d, 64));
+        hi = fmaxf(hi, __shfl_xor(hi, d, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        slo[threadIdx.x >> 6] = lo;
+        shi[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    lo = fminf(fminf(slo[0], slo[1]), fminf(slo[2], slo[3]));
+    hi = fmaxf(fmaxf(shi[0], shi[1]), fmaxf(shi[2], shi[3]));
+    const bool any = lo <= hi;
+    const float w = (hi - lo) / (float)k;
+    for (int j = threadIdx.x; j < k; j += kVqThreads) cb[j] = any ? lo + ((float)j + 0.5f) * w : 0.f;
+}
+
+// Assignment and accumulation of one Lloyd iteration: per workgroup, the
+// FP64 sum and the count of the finite values nearest each centroid (the
+// codebook is ascending throughout the fit).
+__global__ __launch_bounds__(kVqThreads) void k_vq_lloyd(const float *__restrict__ v, int64_t n,
+                                                         const float *__restrict__ cb, int k,
+                                                         double *__restrict__ psum, uint32_t *__restrict__ pcnt) {
+    __shared__ float c[kVqMaxK];
+    __shared__ double sum[kVqMaxK];
+    __shared__ uint32_t cnt[kVqMaxK];
+    for (int j = threadIdx.x; j < k; j += kVqThreads) {
+        c[j] = cb[j];
+        sum[j] = 0.0;
+        cnt[j] = 0u;
+    }
+    __syncthreads();
+    for (int64_t t0 = (int64_t)blockIdx.x * kVqTile; t0 < n; t0 += (int64_t)gridDim.x * kVqTile) {
+        float x[kVqItems];
+#pragma unroll
+        for (int u = 0; u < kVqItems; ++u) {
+            const int64_t i = t0 + u * kVqThreads + threadIdx.x;
+            x[u] = i < n ? v[i] : __builtin_nanf("");
+        }
+#pragma unroll
+        for (int u = 0; u < kVqItems; ++u)
+            if (is_finite32(x[u])) {
+                const int j = nearest_sorted(x[u], c, k);
+                atomicAdd(&sum[j], (double)x[u]);
+                atomicAdd(&cnt[j], 1u);
+            }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < k; j += kVqThreads) {
+        psum[(size_t)blockIdx.x * k + j] = sum[j];
+        pcnt[(size_t)blockIdx.x * k + j] = cnt[j];
+    }
+}
+
+// One workgroup of kUpdateThreads: thread (quarter q, centroid j) adds the
+// partials of workgroups q, q + 4, ... in order; the quarters combine in a
+// fixed order; each non-empty centroid becomes its mean, rounded to FP32;
+// then a bitonic sort of the padded codebook in LDS.
+__global__ __launch_bounds__(kUpdateThreads) void k_vq_update(const double *__restrict__ psum,
+                                                              const uint32_t *__restrict__ pcnt, int groups,
+                                                              int k, float *__restrict__ cb) {
+    __shared__ double qs[4][kVqMaxK];
+    __shared__ uint32_t qc[4][kVqMaxK];
+    __shared__ float key[kVqMaxK];
+    const int j = threadIdx.x & (kVqMaxK - 1), q = threadIdx.x / kVqMaxK;
+    double s = 0.0;
+    uint32_t cn = 0u;
+    if (j < k) {
+#pragma unroll 8
+        for (int g = q; g < groups; g += 4) {
+            s += psum[(size_t)g * k + j];
+            cn += pcnt[(size_t)g * k + j];
+        }
+    }
+    qs[q][j] = s;
+    qc[q][j] = cn;
+    __syncthreads();
+    if (q == 0) {
+        float v = __builtin_inff();  // padding sorts last
+        if (j < k) {
+            const double S = (qs[0][j] + qs[1][j]) + (qs[2][j] + qs[3][j]);
+            const uint32_t C = (qc[0][j] + qc[1][j]) + (qc[2][j] + qc[3][j]);
+            v = C ? (float)(S / (double)C) : cb[j];
+        }
+        key[j] = v;
+    }
+    for (int size = 2; size <= kVqMaxK; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            const int t = threadIdx.x;
+            if (t < kVqMaxK / 2) {
+                const int i = 2 * stride * (t / stride) + (t % stride), l = i + stride;
+                const bool up = (i & size) == 0;
+                const float a = key[i], b = key[l];
+                if ((a > b) == up) {
+                    key[i] = b;
+                    key[l] = a;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < k) cb[threadIdx.x] = key[threadIdx.x];
+}
+
+// Index of every value: binary search when the codebook is ascending, a
+// full scan otherwise (both give the least FP32 |x - c_j|, lowest index on
+// ties); 0 for non-finite values.
+__global__ __launch_bounds__(kVqThreads) void k_vq_assign(const float *__restrict__ v, int64_t n,
+                                                          const float *__restrict__ cb, int k,
+                                                          uint8_t *__restrict__ index) {
+    __shared__ float c[kVqMaxK];
+    __shared__ int unsorted;
+    if (threadIdx.x == 0) unsorted = 0;
+    for (int j = threadIdx.x; j < k; j += kVqThreads) c[j] = cb[j];
+    __syncthreads();
+    for (int j = threadIdx.x; j + 1 < k; j += kVqThreads)
+        if (!(c[j] <= c[j + 1])) unsorted = 1;
+    __syncthreads();
+    const bool sorted = unsorted == 0;
+    for (int64_t t0 = (int64_t)blockIdx.x * kVqTile; t0 < n; t0 += (int64_t)gridDim.x * kVqTile) {
+        float x[kVqItems];
+#pragma unroll
+        for (int u = 0; u < kVqItems; ++u) {
+            const int64_t i = t0 + u * kVqThreads + threadIdx.x;
+            x[u] = i < n ? v[i] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < kVqItems; ++u) {
+            const int64_t i = t0 + u * kVqThreads + threadIdx.x;
+            if (i < n) {
+                const int j = !is_finite32(x[u]) ? 0 : sorted ? nearest_sorted(x[u], c, k) : nearest_scan(x[u], c, k);
+                index[i] = (uint8_t)j;
+            }
+        }
+    }
+}
+
+struct VqComposeArgs {
+    ivrgs_vq_model src[kComposeModels];
+    int64_t offset[kComposeModels];     // first output index of each model
+    int64_t first[kComposeModels + 1];  // first thread of each model (one Gaussian per thread)
+    int32_t model0;                     // model number of src[0]
+    int32_t count;
+    float edit[kComposeModels][12];     // palette 3, opacity scale, shade scale 4, shade bias 4
+};
+
+// Decode and compose: mean and normal copied, every other attribute read
+// through its codebook (index clamped to k - 1), then the edits of
+// ivrgs_compose.  Planes stay coalesced across the wave; the codebooks (at
+// most 8 KiB per model) are gathered through the vector cache.
+__global__ __launch_bounds__(256) void k_vq_compose(VqComposeArgs a, ivrgs_gaussians_mut out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.first[a.count]) return;
+    int j = 0;
+    while (j + 1 < a.count && t >= a.first[j + 1]) ++j;
+    const ivrgs_vq_model &m = a.src[j];
+    const int64_t n = m.n, N = out.n, i = t - a.first[j], o = a.offset[j] + i;
+    const int kk = m.k, last = kk - 1;
+    const float *e = a.edit[j];
+    auto dec = [&](int book, int plane) {
+        const int idx = min((int)m.index[plane * n + i], last);
+        return m.codebook[book * kk + idx];
+    };
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        out.mean[c * N + o] = m.mean[c * n + i];
+        out.normal[c * N + o] = m.normal[c * n + i];
+        out.log_scale[c * N + o] = dec(0, c);
+        out.color[c * N + o] = e[c] + dec(3, 8 + c);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        out.quat[c * N + o] = dec(1, 3 + c);
+        out.shade[c * N + o] = fmaf(e[4 + c], dec(4 + c, 11 + c), e[8 + c]);
+    }
+    out.opacity[o] = e[3] * dec(2, 7);
+    out.model_id[o] = a.model0 + j;
+}
+
+}  // namespace
+
+size_t vq_workspace_bytes(int64_t n, int k) {
+    const int g = vq_groups(n);
+    return align256(sizeof(double) * (size_t)g * k) + align256(sizeof(uint32_t) * (size_t)g * k) +
+           align256(sizeof(float) * 2 * (size_t)g);
+}
+
+hipError_t launch_vq_fit(const float *values, int64_t n, int k, int iters, float *codebook, uint8_t *index,
+                         void *workspace, hipStream_t s) {
+    TimedScope ts(TK_VQ, s);
+    const VqWork w = vq_work(workspace, n, k);
+    const int g = vq_groups(n);
+    if (n > 0) hipLaunchKernelGGL(k_vq_range, dim3(g), dim3(kVqThreads), 0, s, values, n, w.range);
+    hipLaunchKernelGGL(k_vq_init, dim3(1), dim3(kVqThreads), 0, s, w.range, n > 0 ? g : 0, k, codebook);
+    if (n > 0) {
+        for (int it = 0; it < iters; ++it) {
+            hipLaunchKernelGGL(k_vq_lloyd, dim3(g), dim3(kVqThreads), 0, s, values, n, codebook, k, w.sum, w.cnt);
+            hipLaunchKernelGGL(k_vq_update, dim3(1), dim3(kUpdateThreads), 0, s, w.sum, w.cnt, g, k, codebook);
+        }
+        hipLaunchKernelGGL(k_vq_assign, dim3(g), dim3(kVqThreads), 0, s, values, n, codebook, k, index);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_vq_assign(const float *values, int64_t n, const float *codebook, int k, uint8_t *index,
+                            hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    TimedScope ts(TK_VQ, s);
+    hipLaunchKernelGGL(k_vq_assign, dim3(vq_groups(n)), dim3(kVqThreads), 0, s, values, n, codebook, k, index);
+    return hipGetLastError();
+}
+
+hipError_t launch_vq_compose(const ivrgs_vq_model *src, const int64_t *offset, int32_t model0, int32_t count,
+                             const ivrgs_model_edit *edits, const ivrgs_gaussians_mut &out, hipStream_t s) {
+    VqComposeArgs a = {};
+    a.model0 = model0;
+    a.count = count;
+    int64_t total = 0;
+    for (int j = 0; j < count; ++j) {
+        a.src[j] = src[j];
+        a.offset[j] = offset[j];
+        a.first[j] = total;
+        total += src[j].n;
+        const ivrgs_model_edit &r = edits[j];
+        for (int c = 0; c < 3; ++c) a.edit[j][c] = r.palette[c];
+        a.edit[j][3] = r.opacity_scale;
+        for (int c = 0; c < 4; ++c) {
+            a.edit[j][4 + c] = r.shade_scale[c];
+            a.edit[j][8 + c] = r.shade_bias[c];
+        }
+    }
+    a.first[count] = total;
+    if (total == 0) return hipSuccess;
+    TimedScope ts(TK_VQ, s);
+    hipLaunchKernelGGL(k_vq_compose, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a, out);
+    return hipGetLastError();
+}
+
+}  // namespace ivrgs

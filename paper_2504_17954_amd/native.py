@@ -22,9 +22,10 @@ EXPORTS = ("ivrgs_workspace_size", "ivrgs_tiles_per_job", "ivrgs_compose", "ivrg
            "ivrgs_bin_sort", "ivrgs_render_fwd", "ivrgs_render_bwd", "ivrgs_struct_size",
            "ivrgs_status_string", "ivrgs_timing_enable", "ivrgs_timing_read",
            "ivrgs_cull_workspace_size", "ivrgs_cull", "ivrgs_compose_bwd", "ivrgs_light_bwd",
-           "ivrgs_compose_dev", "ivrgs_explore_state_words", "ivrgs_explore_step")
+           "ivrgs_compose_dev", "ivrgs_explore_state_words", "ivrgs_explore_step",
+           "ivrgs_vq_workspace_size", "ivrgs_vq_fit", "ivrgs_vq_assign", "ivrgs_vq_compose")
 TIMING_KINDS = ("project", "tile_count", "scatter", "depth_sort", "render_fwd", "render_bwd",
-                "project_bwd", "compose", "fill", "cull", "edit_bwd")
+                "project_bwd", "compose", "fill", "cull", "edit_bwd", "vq")
 
 
 class ivrgs_gaussians(C.Structure):
@@ -83,8 +84,13 @@ class ivrgs_explore_opts(C.Structure):
                 ("learn", C.c_uint32)]
 
 
+class ivrgs_vq_model(C.Structure):
+    _fields_ = [("n", C.c_int64), ("mean", C.c_void_p), ("normal", C.c_void_p), ("index", C.c_void_p),
+                ("codebook", C.c_void_p), ("k", C.c_int32)]
+
+
 STRUCTS = (ivrgs_gaussians, ivrgs_camera, ivrgs_model_edit, ivrgs_job, ivrgs_batch,
-           ivrgs_params, ivrgs_projected, ivrgs_bins, ivrgs_culler, ivrgs_explore_opts)
+           ivrgs_params, ivrgs_projected, ivrgs_bins, ivrgs_culler, ivrgs_explore_opts, ivrgs_vq_model)
 
 _lib = None
 
@@ -133,6 +139,14 @@ def load(path: str = LIB_PATH):
     lib.ivrgs_explore_state_words.restype = C.c_int64
     lib.ivrgs_explore_step.argtypes = [P, P, C.c_int32, P, P, P, P]
     lib.ivrgs_explore_step.restype = C.c_int
+    lib.ivrgs_vq_workspace_size.argtypes = [C.c_int64, C.c_int32]
+    lib.ivrgs_vq_workspace_size.restype = C.c_size_t
+    lib.ivrgs_vq_fit.argtypes = [P, C.c_int64, C.c_int32, C.c_int32, P, P, P, C.c_size_t, P]
+    lib.ivrgs_vq_fit.restype = C.c_int
+    lib.ivrgs_vq_assign.argtypes = [P, C.c_int64, P, C.c_int32, P, P]
+    lib.ivrgs_vq_assign.restype = C.c_int
+    lib.ivrgs_vq_compose.argtypes = [P, C.c_int32, P, P, P]
+    lib.ivrgs_vq_compose.restype = C.c_int
     lib.ivrgs_timing_enable.argtypes = [C.c_uint32]
     lib.ivrgs_timing_enable.restype = None
     lib.ivrgs_timing_read.argtypes = [P, P]
@@ -190,6 +204,26 @@ def ivrgs_explore_state_words(n_models: int) -> int:
 def ivrgs_explore_step(edit_grad_ptr, light_grad_ptr, n_models: int, opts, state_ptr, edits_ptr, stream):
     check(load().ivrgs_explore_step(edit_grad_ptr, light_grad_ptr, n_models, ref(opts), state_ptr, edits_ptr,
                                     stream), "ivrgs_explore_step")
+
+
+def ivrgs_vq_workspace_size(n: int, k: int) -> int:
+    return int(load().ivrgs_vq_workspace_size(C.c_int64(n), k))
+
+
+def ivrgs_vq_fit(values_ptr, n: int, k: int, iters: int, codebook_ptr, index_ptr, ws_ptr, ws_bytes, stream):
+    check(load().ivrgs_vq_fit(values_ptr, C.c_int64(n), k, iters, codebook_ptr, index_ptr, ws_ptr, ws_bytes,
+                              stream), "ivrgs_vq_fit")
+
+
+def ivrgs_vq_assign(values_ptr, n: int, codebook_ptr, k: int, index_ptr, stream):
+    check(load().ivrgs_vq_assign(values_ptr, C.c_int64(n), codebook_ptr, k, index_ptr, stream), "ivrgs_vq_assign")
+
+
+def ivrgs_vq_compose(models, n_models: int, edits, out, stream):
+    arr_m = (ivrgs_vq_model * n_models)(*models)
+    arr_e = (ivrgs_model_edit * n_models)(*edits)
+    check(load().ivrgs_vq_compose(C.cast(arr_m, C.c_void_p), n_models, C.cast(arr_e, C.c_void_p), ref(out),
+                                  stream), "ivrgs_vq_compose")
 
 
 def ivrgs_project(batch, params, proj, stream):

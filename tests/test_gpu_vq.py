@@ -1,0 +1,170 @@
+"""GPU parity of vector quantisation (Sec. 4.4) and the composition of
+quantised models (Sec. 4.5) against the oracle, through the C ABI.
+
+The bar: indices bit-exact (both sides decide the nearest centroid from FP32
+differences, the lowest index on ties); codebooks bit-exact (each centroid
+is an FP64 mean rounded to FP32 on both sides; the summation orders differ,
+which moves an FP64 sum by far less than half an FP32 unit, so the rounded
+means agree unless one lies within about 1e-16 relative of an FP32 rounding
+boundary); composed planes bit-exact except the shading terms, where the
+kernel's single-rounding fma and the oracle's FP64 evaluation rounded to FP32
+may differ by one unit in the last place.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle import vq as OV
+from paper_2504_17954_amd import inputs as I
+from paper_2504_17954_amd import native as N
+from paper_2504_17954_amd import raster as R
+from paper_2504_17954_amd import vq as V
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available()
+    return torch.device("cuda:0")
+
+
+def to_dev(planes, dev):
+    return {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in planes.items()}
+
+
+def mixture(n, seed):
+    rng = np.random.default_rng(seed)
+    a = rng.normal(0.0, 1.0, n)
+    b = rng.exponential(3.0, n) - 2.0
+    return np.where(rng.random(n) < 0.6, a, b).astype(np.float32)
+
+
+@pytest.mark.parametrize("n,k,kind", [(1, 1, "sorted"), (65, 2, "sorted"), (4096 * 3 + 17, 17, "sorted"),
+                                      (100003, 256, "sorted"), (5000, 256, "dups"), (5000, 33, "unsorted"),
+                                      (0, 4, "sorted")])
+def test_assign_matches_oracle(dev, n, k, kind):
+    rng = np.random.default_rng(n + k)
+    c = rng.normal(size=k).astype(np.float32)
+    if kind == "sorted":
+        c = np.sort(c)
+    elif kind == "dups":
+        c = np.sort(np.round(c * 4) / 4).astype(np.float32)  # many repeated entries
+    x = mixture(n, 7 + n)
+    if n > 10:
+        # exact midpoints (ties) and non-finite values
+        m = (c[: min(k - 1, 8)] + c[1: min(k, 9)]) / 2
+        x[: m.size] = m
+        x[-3:] = [np.nan, np.inf, -np.inf]
+    say(f"vq assign n={n} k={k} {kind}")
+    got = V.assign(torch.from_numpy(x).to(dev), torch.from_numpy(c).to(dev)).cpu().numpy()
+    np.testing.assert_array_equal(got, OV.assign(x, c))
+
+
+@pytest.mark.parametrize("n,k,iters", [(5, 1, 3), (1000, 7, 5), (100003, 256, 6), (4096, 256, 0), (0, 16, 3)])
+def test_fit_matches_oracle(dev, n, k, iters):
+    x = mixture(n, 100 + n)
+    if n > 20:
+        x[5] = np.nan
+        x[9] = -np.inf
+    say(f"vq fit n={n} k={k} iters={iters}")
+    cb, idx = V.fit(torch.from_numpy(x).to(dev), k, iters)
+    cb, idx = cb.cpu().numpy(), idx.cpu().numpy()
+    rc, ri = OV.fit(x, k, iters)
+    np.testing.assert_array_equal(cb, rc)
+    np.testing.assert_array_equal(idx, ri)
+    assert np.all(np.diff(cb) >= 0)
+
+
+def test_fit_degenerate_inputs(dev):
+    for x in (np.full(777, 1.5, np.float32), np.array([np.nan, np.inf], np.float32),
+              np.array([-0.0, 0.0, -0.0], np.float32)):
+        say(f"vq fit degenerate {x[:3]}")
+        cb, idx = V.fit(torch.from_numpy(x).to(dev), 8, 4)
+        rc, ri = OV.fit(x, 8, 4)
+        np.testing.assert_array_equal(cb.cpu().numpy(), rc)
+        np.testing.assert_array_equal(idx.cpu().numpy(), ri)
+
+
+def test_fit_full_size_attribute(dev):
+    """One attribute of a 250K-Gaussian model (opacity, and the four-component
+    rotation), k = 256, against the oracle at full size."""
+    m = I.isosurface_model(250_000, I.SEED_SCENE + 2, 0.0)
+    for name in ("opacity", "quat"):
+        x = np.ascontiguousarray(m.planes[name], np.float32).ravel()
+        say(f"vq fit full size {name}: {x.size} values")
+        cb, idx = V.fit(torch.from_numpy(x).to(dev), 256, 3)
+        rc, ri = OV.fit(x, 256, 3)
+        np.testing.assert_array_equal(cb.cpu().numpy(), rc)
+        np.testing.assert_array_equal(idx.cpu().numpy().ravel(), ri)
+
+
+def test_quantize_and_compose_match_oracle(dev):
+    ms = [I.small_scene(n, 60 + j) for j, n in enumerate((1500, 1, 2300))]
+    edits = I.c3_edits(ms, 9)
+    rows = np.stack([e.row() if hasattr(e, "row") else np.asarray(e, np.float32) for e in edits])
+    say("vq quantize + compose, 3 models")
+    qs = [V.quantize(to_dev(m.planes, dev), k=64, iters=4) for m in ms]
+    oq = [OV.quantize(m.planes, 64, 4) for m in ms]
+    for q, o in zip(qs, oq):
+        np.testing.assert_array_equal(q.codebook.cpu().numpy(), o["codebook"])
+        np.testing.assert_array_equal(q.index.cpu().numpy(), o["index"])
+    planes, mid = V.compose(qs, edits, dev)
+    ref, ref_mid = O.compose([OV.decode(o) for o in oq], rows)
+    for k in R.PLANES:
+        got = planes[k].cpu().numpy()
+        if k == "shade":
+            np.testing.assert_array_max_ulp(got, ref[k], maxulp=1)
+        else:
+            np.testing.assert_array_equal(got, ref[k], err_msg=k)
+    np.testing.assert_array_equal(mid.cpu().numpy(), ref_mid)
+    # decode inside compose == compose of the decoded planes on the device
+    dec = [to_dev(OV.decode(o), dev) for o in oq]
+    p2, mid2 = R.compose(dec, edits, dev)
+    for k in R.PLANES:
+        assert torch.equal(planes[k], p2[k]), k
+    assert torch.equal(mid, mid2)
+
+
+def test_compose_many_models_and_index_clamp(dev):
+    """More models than one launch holds, and out-of-range indices read the
+    last codebook entry."""
+    ms = [I.small_scene(100 + 37 * j, 300 + j) for j in range(11)]
+    edits = I.c3_edits(ms, 4)
+    rows = np.stack([e.row() if hasattr(e, "row") else np.asarray(e, np.float32) for e in edits])
+    oq = [OV.quantize(m.planes, 8, 2) for m in ms]
+    oq[3]["index"][:, ::7] = 200  # >= k = 8: reads entry 7
+    qs = [V.QuantizedModel(*(torch.from_numpy(np.ascontiguousarray(o[f])).to(dev)
+                             for f in ("mean", "normal", "index", "codebook"))) for o in oq]
+    planes, mid = V.compose(qs, edits, dev)
+    clamped = [dict(o, index=np.minimum(o["index"], 7)) for o in oq]
+    ref, ref_mid = O.compose([OV.decode(o) for o in clamped], rows)
+    for k in R.PLANES:
+        if k == "shade":
+            np.testing.assert_array_max_ulp(planes[k].cpu().numpy(), ref[k], maxulp=1)
+        else:
+            np.testing.assert_array_equal(planes[k].cpu().numpy(), ref[k], err_msg=k)
+    np.testing.assert_array_equal(mid.cpu().numpy(), ref_mid)
+
+
+def test_invalid_arguments(dev):
+    x = torch.zeros(10, device=dev)
+    cb = torch.zeros(300, device=dev)
+    idx = torch.zeros(10, dtype=torch.uint8, device=dev)
+    ws = torch.zeros(N.ivrgs_vq_workspace_size(10, 256), dtype=torch.uint8, device=dev)
+    lib = N.load()
+    s = R._stream()
+    assert lib.ivrgs_vq_fit(x.data_ptr(), 10, 0, 1, cb.data_ptr(), idx.data_ptr(), ws.data_ptr(), ws.numel(), s) == N.E_INVALID
+    assert lib.ivrgs_vq_fit(x.data_ptr(), 10, 257, 1, cb.data_ptr(), idx.data_ptr(), ws.data_ptr(), ws.numel(), s) == N.E_INVALID
+    assert lib.ivrgs_vq_fit(x.data_ptr(), 10, 8, -1, cb.data_ptr(), idx.data_ptr(), ws.data_ptr(), ws.numel(), s) == N.E_INVALID
+    assert lib.ivrgs_vq_fit(x.data_ptr(), 10, 256, 1, cb.data_ptr(), idx.data_ptr(), ws.data_ptr(), 16, s) == N.E_CAPACITY
+    assert lib.ivrgs_vq_assign(x.data_ptr(), 10, cb.data_ptr(), 0, idx.data_ptr(), s) == N.E_INVALID
+    assert N.ivrgs_vq_workspace_size(10, 0) == 0
