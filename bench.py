@@ -101,6 +101,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-culler", action="store_true")
     ap.add_argument("--no-explore", action="store_true")
+    ap.add_argument("--no-vq", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB five times (counter calibration)")
@@ -311,6 +312,8 @@ def main():
             result["secondary"]["culler"] = secondary_culler(dev)
         if not args.no_explore:
             result["secondary"]["inverse_exploration"] = secondary_explore(dev)
+        if not args.no_vq:
+            result["secondary"]["vq"] = secondary_vq(dev)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(models, edits, cams, W, H, views[0], args.cpu_seconds)
@@ -356,6 +359,68 @@ def secondary_fwd(dev):
     log(f"composed forward: {dt / nv * 1e3:.3f} ms/view, {mpix:.1f} Mpix/s")
     return {"fwd_mpix_s": round(mpix, 2), "fwd_ms_per_view": round(dt / nv * 1e3, 4),
             "workload": f"compose-{len(w.models)}x{w.models[0].n}-{w.width}px-{nv}views-fwd"}
+
+
+VQ_BYTES = 3 * 4 + 3 * 4 + 15       # stored per quantised Gaussian: exact mean and normal, 15 one-byte indices
+OUT_BYTES = 21 * 4 + 4              # written per composed Gaussian: 21 FP32 attributes and the model id
+FLOAT_BYTES = 21 * 4                # read per Gaussian by the float compose
+
+
+def secondary_vq(dev, k=256, iters=10, reps=20):
+    """Vector quantisation (Sec. 4.4) of the four 250k-Gaussian shells of the
+    main workload (eight codebooks per model, k = 256, 10 Lloyd iterations),
+    then compose of the quantised models with the decode fused, against the
+    float compose; the forward render of one view from both composed sets
+    gives the PSNR cost of quantisation."""
+    import torch
+    from paper_2504_17954_amd import inputs as I
+    from paper_2504_17954_amd import native as N
+    from paper_2504_17954_amd import raster as R
+    from paper_2504_17954_amd import vq as V
+    models, edits = h2_scene(1_000_000, 4)
+    mdev = [{kk: torch.from_numpy(v).to(dev) for kk, v in m.planes.items()} for m in models]
+    n = sum(m.n for m in models)
+    for m in mdev[:1]:
+        V.quantize(m, k, iters)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    qs = [V.quantize(m, k, iters) for m in mdev]
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t0
+    for _ in range(3):
+        V.compose(qs, edits, dev)
+        R.compose(mdev, edits, dev)
+    torch.cuda.synchronize()
+    N.ivrgs_timing_enable(["vq", "compose"])
+    for _ in range(reps):
+        planes_q, mid_q = V.compose(qs, edits, dev)
+        planes_f, mid_f = R.compose(mdev, edits, dev)
+    t = N.ivrgs_timing_read()
+    N.ivrgs_timing_enable(0)
+    ms_q = t["vq"][0] / max(t["vq"][1], 1)
+    ms_f = t["compose"][0] / max(t["compose"][1], 1)
+    gbs_q = n * (VQ_BYTES + OUT_BYTES) / (ms_q * 1e-3) / 1e9
+    gbs_f = n * (FLOAT_BYTES + OUT_BYTES) / (ms_f * 1e-3) / 1e9
+    cams = I.cameras_at(I.fibonacci_sphere(100), 800, 800)
+    cams_t = R.camera_table(cams, dev)
+    edits_t = R.edit_table(edits, dev)
+    rnd = R.Renderer(R.Settings(800, 800), capacity=1 << 24, check="sync")
+    job = R.Jobs.single(n, camera=3)
+    a = rnd.forward(planes_f, cams_t, job, model_id=mid_f, edits_t=edits_t).clone()
+    b = rnd.forward(planes_q, cams_t, job, model_id=mid_q, edits_t=edits_t)
+    mse = float(((a[:, :3] - b[:, :3]) ** 2).mean())
+    psnr = 10 * np.log10(1.0 / max(mse, 1e-20))
+    stored_q = sum(q.nbytes() for q in qs)
+    stored_f = n * FLOAT_BYTES
+    log(f"vq: quantise 4x250k in {t_fit * 1e3:.1f} ms; compose quantised {ms_q:.4f} ms ({gbs_q:.0f} GB/s) "
+        f"vs float {ms_f:.4f} ms ({gbs_f:.0f} GB/s); {stored_f / stored_q:.2f}x smaller; PSNR {psnr:.1f} dB")
+    return {"quantize_ms": round(t_fit * 1e3, 3), "compose_vq_ms": round(ms_q, 4), "compose_float_ms": round(ms_f, 4),
+            "compose_vq_roofline": {"bound": "hbm", "achieved": round(gbs_q, 1), "peak": 8000.0, "unit": "GB/s",
+                                    "frac": round(gbs_q / 8000.0, 4),
+                                    "bytes_per_gaussian": VQ_BYTES + OUT_BYTES},
+            "compose_float_gbs": round(gbs_f, 1), "compression": round(stored_f / stored_q, 3),
+            "psnr_quantised_vs_float_db": round(psnr, 2),
+            "workload": f"vq-4x250k-k{k}-iters{iters}-compose-800px-view3"}
 
 
 EXPLORE_N = 1_484_642  # composed primitives of the paper's largest-timed exploration example

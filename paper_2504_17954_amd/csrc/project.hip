@@ -597,7 +597,11 @@ __global__ __launch_bounds__(256) void k_compose(ComposeArgs a, const ivrgs_mode
                      aligned16(out.color) && aligned16(out.shade) && aligned16(out.model_id);
     if (vec) {
         auto ld = [](const float *p) { return *reinterpret_cast<const float4 *>(p); };
-        auto st = [](float *p, float4 v) { *reinterpret_cast<float4 *>(p) = v; };
+        // streaming stores: the composed planes are not read again by this kernel
+        auto st = [](float *p, float4 v) {
+            typedef float f4v __attribute__((ext_vector_type(4)));
+            __builtin_nontemporal_store(f4v{v.x, v.y, v.z, v.w}, reinterpret_cast<f4v *>(p));
+        };
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             st(out.mean + c * N + o0, ld(src.mean + c * n + i0));
@@ -616,7 +620,8 @@ __global__ __launch_bounds__(256) void k_compose(ComposeArgs a, const ivrgs_mode
         }
         const float4 v = ld(src.opacity + i0);
         st(out.opacity + o0, make_float4(e[3] * v.x, e[3] * v.y, e[3] * v.z, e[3] * v.w));
-        *reinterpret_cast<int4 *>(out.model_id + o0) = make_int4(model, model, model, model);
+        typedef int i4v __attribute__((ext_vector_type(4)));
+        __builtin_nontemporal_store(i4v{model, model, model, model}, reinterpret_cast<i4v *>(out.model_id + o0));
         return;
     }
     for (int64_t i = i0; i < i0 + 4 && i < n; ++i) {

@@ -272,46 +272,113 @@ __global__ __launch_bounds__(kVqThreads) void k_vq_assign(const float *__restric
     }
 }
 
+constexpr int kVqBooks = 8;
+
 struct VqComposeArgs {
     ivrgs_vq_model src[kComposeModels];
-    int64_t offset[kComposeModels];     // first output index of each model
-    int64_t first[kComposeModels + 1];  // first thread of each model (one Gaussian per thread)
-    int32_t model0;                     // model number of src[0]
+    int64_t offset[kComposeModels];    // first output index of each model
+    int64_t quad[kComposeModels + 1];  // first thread of each model (4 Gaussians per thread)
+    int32_t model0;                    // model number of src[0]
     int32_t count;
-    float edit[kComposeModels][12];     // palette 3, opacity scale, shade scale 4, shade bias 4
+    float edit[kComposeModels][12];    // palette 3, opacity scale, shade scale 4, shade bias 4
 };
 
-// Decode and compose: mean and normal copied, every other attribute read
-// through its codebook (index clamped to k - 1), then the edits of
-// ivrgs_compose.  Planes stay coalesced across the wave; the codebooks (at
-// most 8 KiB per model) are gathered through the vector cache.
+__device__ __forceinline__ bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+
+// Decode and compose, four Gaussians per thread: mean and normal copied,
+// every other attribute read through its codebook (index clamped to k - 1),
+// then the edits of ivrgs_compose.  A workgroup inside one model stages that
+// model's codebooks (at most 8 KiB) in LDS; one that straddles models reads
+// them from global memory.  Planes move as float4 and the indices as four
+// bytes when the model's slices are aligned.
 __global__ __launch_bounds__(256) void k_vq_compose(VqComposeArgs a, ivrgs_gaussians_mut out) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.first[a.count]) return;
-    int j = 0;
-    while (j + 1 < a.count && t >= a.first[j + 1]) ++j;
+    __shared__ float book[kVqBooks * kVqMaxK];
+    auto model_of = [&](int64_t t) {
+        int j = 0;
+        while (j + 1 < a.count && t >= a.quad[j + 1]) ++j;
+        return j;
+    };
+    const int64_t nq = a.quad[a.count];
+    const int64_t q0 = (int64_t)blockIdx.x * blockDim.x, q1 = min(q0 + (int64_t)blockDim.x, nq) - 1;
+    const int jb = model_of(q0);
+    const bool staged = jb == model_of(q1);
+    if (staged) {
+        const ivrgs_vq_model &m = a.src[jb];
+        for (int e = threadIdx.x; e < kVqBooks * m.k; e += blockDim.x) book[e] = m.codebook[e];
+    }
+    __syncthreads();
+    const int64_t t = q0 + threadIdx.x;
+    if (t >= nq) return;
+    const int j = model_of(t);
     const ivrgs_vq_model &m = a.src[j];
-    const int64_t n = m.n, N = out.n, i = t - a.first[j], o = a.offset[j] + i;
+    const int64_t n = m.n, N = out.n, i0 = 4 * (t - a.quad[j]), o0 = a.offset[j] + i0;
     const int kk = m.k, last = kk - 1;
     const float *e = a.edit[j];
-    auto dec = [&](int book, int plane) {
-        const int idx = min((int)m.index[plane * n + i], last);
-        return m.codebook[book * kk + idx];
+    // the body is instantiated once per codebook location, so that each keeps
+    // its address space (LDS reads, or global loads)
+    auto body = [&](auto look) {
+        const bool vec = i0 + 4 <= n && (n & 3) == 0 && (N & 3) == 0 && (a.offset[j] & 3) == 0 &&
+                         aligned(m.mean, 16) && aligned(m.normal, 16) && aligned(m.index, 4) && aligned(out.mean, 16) &&
+                         aligned(out.log_scale, 16) && aligned(out.quat, 16) && aligned(out.opacity, 16) &&
+                         aligned(out.normal, 16) && aligned(out.color, 16) && aligned(out.shade, 16) &&
+                         aligned(out.model_id, 16);
+        if (vec) {
+            auto ld = [](const float *p) { return *reinterpret_cast<const float4 *>(p); };
+            // streaming stores: the composed planes are not read again by this kernel
+            auto st = [](float *p, float4 v) {
+                typedef float f4v __attribute__((ext_vector_type(4)));
+                __builtin_nontemporal_store(f4v{v.x, v.y, v.z, v.w}, reinterpret_cast<f4v *>(p));
+            };
+            auto idx4 = [&](int plane) { return *reinterpret_cast<const uint32_t *>(m.index + plane * n + i0); };
+            // the four Gaussians' entries of codebook bk, then f applied to each
+            auto dec4 = [&](int bk, int plane, auto f) {
+                const uint32_t w = idx4(plane);
+                return make_float4(f(look(bk, w & 255u)), f(look(bk, (w >> 8) & 255u)), f(look(bk, (w >> 16) & 255u)),
+                                   f(look(bk, w >> 24)));
+            };
+            auto id = [](float v) { return v; };
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                st(out.mean + c * N + o0, ld(m.mean + c * n + i0));
+                st(out.normal + c * N + o0, ld(m.normal + c * n + i0));
+                st(out.log_scale + c * N + o0, dec4(0, c, id));
+                const float pc = e[c];
+                st(out.color + c * N + o0, dec4(3, 8 + c, [pc](float v) { return pc + v; }));
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                st(out.quat + c * N + o0, dec4(1, 3 + c, id));
+                const float ks = e[4 + c], kb = e[8 + c];
+                st(out.shade + c * N + o0, dec4(4 + c, 11 + c, [ks, kb](float v) { return fmaf(ks, v, kb); }));
+            }
+            const float so = e[3];
+            st(out.opacity + o0, dec4(2, 7, [so](float v) { return so * v; }));
+            const int model = a.model0 + j;
+            typedef int i4v __attribute__((ext_vector_type(4)));
+            __builtin_nontemporal_store(i4v{model, model, model, model}, reinterpret_cast<i4v *>(out.model_id + o0));
+            return;
+        }
+        for (int64_t i = i0; i < i0 + 4 && i < n; ++i) {
+            const int64_t o = a.offset[j] + i;
+            auto dec = [&](int bk, int plane) { return look(bk, m.index[plane * n + i]); };
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                out.mean[c * N + o] = m.mean[c * n + i];
+                out.normal[c * N + o] = m.normal[c * n + i];
+                out.log_scale[c * N + o] = dec(0, c);
+                out.color[c * N + o] = e[c] + dec(3, 8 + c);
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                out.quat[c * N + o] = dec(1, 3 + c);
+                out.shade[c * N + o] = fmaf(e[4 + c], dec(4 + c, 11 + c), e[8 + c]);
+            }
+            out.opacity[o] = e[3] * dec(2, 7);
+            out.model_id[o] = a.model0 + j;
+        }
     };
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        out.mean[c * N + o] = m.mean[c * n + i];
-        out.normal[c * N + o] = m.normal[c * n + i];
-        out.log_scale[c * N + o] = dec(0, c);
-        out.color[c * N + o] = e[c] + dec(3, 8 + c);
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        out.quat[c * N + o] = dec(1, 3 + c);
-        out.shade[c * N + o] = fmaf(e[4 + c], dec(4 + c, 11 + c), e[8 + c]);
-    }
-    out.opacity[o] = e[3] * dec(2, 7);
-    out.model_id[o] = a.model0 + j;
+    if (staged) body([&](int bk, uint32_t idx) { return book[bk * kk + min((int)idx, last)]; });
+    else body([&](int bk, uint32_t idx) { return m.codebook[bk * kk + min((int)idx, last)]; });
 }
 
 }  // namespace
@@ -352,12 +419,12 @@ hipError_t launch_vq_compose(const ivrgs_vq_model *src, const int64_t *offset, i
     VqComposeArgs a = {};
     a.model0 = model0;
     a.count = count;
-    int64_t total = 0;
+    int64_t quads = 0;
     for (int j = 0; j < count; ++j) {
         a.src[j] = src[j];
         a.offset[j] = offset[j];
-        a.first[j] = total;
-        total += src[j].n;
+        a.quad[j] = quads;
+        quads += (src[j].n + 3) / 4;
         const ivrgs_model_edit &r = edits[j];
         for (int c = 0; c < 3; ++c) a.edit[j][c] = r.palette[c];
         a.edit[j][3] = r.opacity_scale;
@@ -366,10 +433,10 @@ hipError_t launch_vq_compose(const ivrgs_vq_model *src, const int64_t *offset, i
             a.edit[j][8 + c] = r.shade_bias[c];
         }
     }
-    a.first[count] = total;
-    if (total == 0) return hipSuccess;
+    a.quad[count] = quads;
+    if (quads == 0) return hipSuccess;
     TimedScope ts(TK_VQ, s);
-    hipLaunchKernelGGL(k_vq_compose, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a, out);
+    hipLaunchKernelGGL(k_vq_compose, dim3((unsigned)((quads + 255) / 256)), dim3(256), 0, s, a, out);
     return hipGetLastError();
 }
 
