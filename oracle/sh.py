@@ -12,8 +12,8 @@ coefficients as in the original 3DGS.  Readings (the same on the GPU side):
   - the real basis built from the complex harmonics with the Condon-Shortley
     phase: Y_l^0; sqrt(2) Re Y_l^m for m > 0; sqrt(2) Im Y_l^|m| for m < 0;
     ordered by l, then m = -l .. l;
-  - the direction d = (mean - C) / |mean - C| from the camera centre C
-    (d = 0 when the mean sits on the centre);
+  - the direction d = (mean - C) / |mean - C| from the camera centre C,
+    held in FP32 like the camera row (d = 0 when the mean sits on it);
   - colour_c = max(sum_k Y_k(d) f_kc + 1/2, 0).
 Below, each basis function is written out as a polynomial in (x, y, z) = d,
 with its normalisation from the square roots; the tests pin them to SciPy's
@@ -62,11 +62,13 @@ def basis(d, degree: int):
 
 
 def camera_centre(cam) -> np.ndarray:
-    """C = -R^T t for x_cam = R x_world + t."""
+    """C = -R^T t for x_cam = R x_world + t, evaluated in FP64 from the FP32
+    camera row and held in FP32 (returned as float64), like the camera row
+    itself: a mean stored at the centre then has d = 0 on both sides."""
     row = cam.row() if hasattr(cam, "row") else np.asarray(cam, np.float32)
     R = np.asarray(row[:9], np.float64).reshape(3, 3)
     t = np.asarray(row[9:12], np.float64)
-    return -R.T @ t
+    return (-R.T @ t).astype(np.float32).astype(np.float64)
 
 
 def _colour(sh, mean, centre, degree):
