@@ -297,10 +297,11 @@ ivrgs_status ivrgs_light_bwd(const ivrgs_batch *batch, const ivrgs_params *param
  * 0 project, 1 tile counts (per-chunk counts, column and tile scans, work
  * queue), 2 scatter, 3 depth order, 4 render_fwd, 5 render_bwd,
  * 6 project_bwd, 7 compose, 8 fills, 9 cull, 10 edit and light gradients
- * and the exploration step, 11 VQ (k-means, assignment, quantised compose).
- * Process-wide state; not for concurrent callers. */
-#define IVRGS_TIMING_KINDS 12
-#define IVRGS_TIMING_ALL 0xFFFu
+ * and the exploration step, 11 VQ (k-means, assignment, quantised compose),
+ * 12 SH colour and its backward.  Process-wide state; not for concurrent
+ * callers. */
+#define IVRGS_TIMING_KINDS 13
+#define IVRGS_TIMING_ALL 0x1FFFu
 void ivrgs_timing_enable(uint32_t kinds);
 int32_t ivrgs_timing_read(double *ms, int64_t *launches);
 
@@ -440,6 +441,35 @@ ivrgs_status ivrgs_vq_assign(const float *values, int64_t n, const float *codebo
  * models[m].n. */
 ivrgs_status ivrgs_vq_compose(const ivrgs_vq_model *models, int32_t n_models, const ivrgs_model_edit *edits,
                               ivrgs_gaussians_mut *out, void *stream);
+
+/* ---- SH colour (base 3DGS, Sec. 3 and Sec. 4.2) ---------------------------
+ * The base model's view-dependent colour is parameterised by spherical-
+ * harmonic coefficients, as in the original 3DGS; the paper gives no degree
+ * or convention.  Readings: degree L in 0..3, K = (L + 1)^2 coefficients per
+ * channel; the real basis from the complex harmonics with the Condon-Shortley
+ * phase (Y_l^0; sqrt(2) Re Y_l^m for m > 0; sqrt(2) Im Y_l^|m| for m < 0),
+ * ordered by band l, then m = -l .. l; the direction d = (mean - C) / |mean -
+ * C| from the camera centre C = -R^T t (d = 0 for a mean on the centre);
+ * colour_c = max(sum_k Y_k(d) sh[k][c] + 1/2, 0) (a NaN passes through).
+ * The result is a colour plane for the rest of the path: with shading terms
+ * (k_a, k_d, k_s) = (1, 0, 0) projection passes it through unchanged. */
+
+/* sh: device [K][3][n] (coefficient-major planes); mean: device [3][n];
+ * camera: HOST struct; color: device [3][n], written.  Returns
+ * IVRGS_E_INVALID for a degree outside 0..3, a negative n or a null pointer
+ * (none is read when n = 0). */
+ivrgs_status ivrgs_sh_color(const float *sh, int32_t degree, const float *mean, int64_t n,
+                            const ivrgs_camera *camera, float *color, void *stream);
+
+/* Backward of ivrgs_sh_color for dL/dcolour (device [3][n]): grad_sh
+ * (device [K][3][n]) is written with Y_k(d) g_c, where g_c = dL/dcolour_c
+ * unless the colour is clamped (raw colour <= 0: g_c = 0); when grad_mean
+ * (device [3][n]) is not NULL, the mean's gradient through the direction
+ * (tangent to the sphere of directions, over |mean - C|) is ADDED into it,
+ * so it can follow the projection backward's mean gradient. */
+ivrgs_status ivrgs_sh_color_bwd(const float *sh, int32_t degree, const float *mean, int64_t n,
+                                const ivrgs_camera *camera, const float *grad_color, float *grad_sh,
+                                float *grad_mean, void *stream);
 
 /* sizeof of the ABI structs, for binding checks: which = 0 gaussians,
  * 1 camera, 2 model_edit, 3 job, 4 batch, 5 params, 6 projected, 7 bins,

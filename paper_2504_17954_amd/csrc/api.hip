@@ -314,6 +314,24 @@ ivrgs_status ivrgs_vq_compose(const ivrgs_vq_model *models, int32_t n_models, co
     return IVRGS_OK;
 }
 
+ivrgs_status ivrgs_sh_color(const float *sh, int32_t degree, const float *mean, int64_t n,
+                            const ivrgs_camera *camera, float *color, void *stream) {
+    if (degree < 0 || degree > 3 || n < 0 || !camera) return IVRGS_E_INVALID;
+    if (n > 0 && (!sh || !mean || !color)) return IVRGS_E_INVALID;
+    if ((n + 255) / 256 > (int64_t)UINT32_MAX) return IVRGS_E_SHAPE;
+    return hip_status(launch_sh_color(sh, degree, mean, n, *camera, color, reinterpret_cast<hipStream_t>(stream)));
+}
+
+ivrgs_status ivrgs_sh_color_bwd(const float *sh, int32_t degree, const float *mean, int64_t n,
+                                const ivrgs_camera *camera, const float *grad_color, float *grad_sh,
+                                float *grad_mean, void *stream) {
+    if (degree < 0 || degree > 3 || n < 0 || !camera) return IVRGS_E_INVALID;
+    if (n > 0 && (!sh || !mean || !grad_color || !grad_sh)) return IVRGS_E_INVALID;
+    if ((n + 255) / 256 > (int64_t)UINT32_MAX) return IVRGS_E_SHAPE;
+    return hip_status(launch_sh_color_bwd(sh, degree, mean, n, *camera, grad_color, grad_sh, grad_mean,
+                                          reinterpret_cast<hipStream_t>(stream)));
+}
+
 int64_t ivrgs_explore_state_words(int32_t n_models) {
     if (n_models <= 0) return 0;
     return 3 * (4 * (int64_t)n_models + 10) + 1;

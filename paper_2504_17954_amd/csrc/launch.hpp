@@ -7,7 +7,7 @@ namespace ivrgs {
 
 // Kernel-timing hooks (no-ops unless timing is enabled).
 enum TimingKind { TK_PROJECT = 0, TK_COUNT, TK_SCATTER, TK_SORT, TK_FWD, TK_BWD, TK_PROJECT_BWD,
-                  TK_COMPOSE, TK_FILL, TK_CULL, TK_EDIT_BWD, TK_VQ, TK_KINDS };
+                  TK_COMPOSE, TK_FILL, TK_CULL, TK_EDIT_BWD, TK_VQ, TK_SH, TK_KINDS };
 void timing_begin(int kind, hipStream_t s);
 void timing_end(int kind, hipStream_t s);
 
@@ -80,6 +80,11 @@ hipError_t launch_vq_assign(const float *values, int64_t n, const float *codeboo
                             hipStream_t s);
 hipError_t launch_vq_compose(const ivrgs_vq_model *src, const int64_t *offset, int32_t model0, int32_t count,
                              const ivrgs_model_edit *edits, const ivrgs_gaussians_mut &out, hipStream_t s);
+// SH colour of base 3DGS and its backward (degree 0..3).
+hipError_t launch_sh_color(const float *sh, int degree, const float *mean, int64_t n, const ivrgs_camera &cam,
+                           float *color, hipStream_t s);
+hipError_t launch_sh_color_bwd(const float *sh, int degree, const float *mean, int64_t n, const ivrgs_camera &cam,
+                               const float *grad_color, float *grad_sh, float *grad_mean, hipStream_t s);
 hipError_t launch_work_queue(const uint32_t *starts, int64_t n_tiles, uint32_t *queue, hipStream_t s);
 
 }  // namespace ivrgs

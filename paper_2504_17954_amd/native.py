@@ -23,9 +23,10 @@ EXPORTS = ("ivrgs_workspace_size", "ivrgs_tiles_per_job", "ivrgs_compose", "ivrg
            "ivrgs_status_string", "ivrgs_timing_enable", "ivrgs_timing_read",
            "ivrgs_cull_workspace_size", "ivrgs_cull", "ivrgs_compose_bwd", "ivrgs_light_bwd",
            "ivrgs_compose_dev", "ivrgs_explore_state_words", "ivrgs_explore_step",
-           "ivrgs_vq_workspace_size", "ivrgs_vq_fit", "ivrgs_vq_assign", "ivrgs_vq_compose")
+           "ivrgs_vq_workspace_size", "ivrgs_vq_fit", "ivrgs_vq_assign", "ivrgs_vq_compose",
+           "ivrgs_sh_color", "ivrgs_sh_color_bwd")
 TIMING_KINDS = ("project", "tile_count", "scatter", "depth_sort", "render_fwd", "render_bwd",
-                "project_bwd", "compose", "fill", "cull", "edit_bwd", "vq")
+                "project_bwd", "compose", "fill", "cull", "edit_bwd", "vq", "sh")
 
 
 class ivrgs_gaussians(C.Structure):
@@ -147,6 +148,10 @@ def load(path: str = LIB_PATH):
     lib.ivrgs_vq_assign.restype = C.c_int
     lib.ivrgs_vq_compose.argtypes = [P, C.c_int32, P, P, P]
     lib.ivrgs_vq_compose.restype = C.c_int
+    lib.ivrgs_sh_color.argtypes = [P, C.c_int32, P, C.c_int64, P, P, P]
+    lib.ivrgs_sh_color.restype = C.c_int
+    lib.ivrgs_sh_color_bwd.argtypes = [P, C.c_int32, P, C.c_int64, P, P, P, P, P]
+    lib.ivrgs_sh_color_bwd.restype = C.c_int
     lib.ivrgs_timing_enable.argtypes = [C.c_uint32]
     lib.ivrgs_timing_enable.restype = None
     lib.ivrgs_timing_read.argtypes = [P, P]
@@ -224,6 +229,17 @@ def ivrgs_vq_compose(models, n_models: int, edits, out, stream):
     arr_e = (ivrgs_model_edit * n_models)(*edits)
     check(load().ivrgs_vq_compose(C.cast(arr_m, C.c_void_p), n_models, C.cast(arr_e, C.c_void_p), ref(out),
                                   stream), "ivrgs_vq_compose")
+
+
+def ivrgs_sh_color(sh_ptr, degree: int, mean_ptr, n: int, camera, color_ptr, stream):
+    check(load().ivrgs_sh_color(sh_ptr, degree, mean_ptr, C.c_int64(n), ref(camera), color_ptr, stream),
+          "ivrgs_sh_color")
+
+
+def ivrgs_sh_color_bwd(sh_ptr, degree: int, mean_ptr, n: int, camera, grad_color_ptr, grad_sh_ptr, grad_mean_ptr,
+                       stream):
+    check(load().ivrgs_sh_color_bwd(sh_ptr, degree, mean_ptr, C.c_int64(n), ref(camera), grad_color_ptr,
+                                    grad_sh_ptr, grad_mean_ptr, stream), "ivrgs_sh_color_bwd")
 
 
 def ivrgs_project(batch, params, proj, stream):
