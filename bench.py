@@ -102,6 +102,7 @@ def parse():
     ap.add_argument("--no-culler", action="store_true")
     ap.add_argument("--no-explore", action="store_true")
     ap.add_argument("--no-vq", action="store_true")
+    ap.add_argument("--no-sh", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB five times (counter calibration)")
@@ -314,6 +315,8 @@ def main():
             result["secondary"]["inverse_exploration"] = secondary_explore(dev)
         if not args.no_vq:
             result["secondary"]["vq"] = secondary_vq(dev)
+        if not args.no_sh:
+            result["secondary"]["base_3dgs_sh"] = secondary_sh(dev)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(models, edits, cams, W, H, views[0], args.cpu_seconds)
@@ -421,6 +424,82 @@ def secondary_vq(dev, k=256, iters=10, reps=20):
             "compose_float_gbs": round(gbs_f, 1), "compression": round(stored_f / stored_q, 3),
             "psnr_quantised_vs_float_db": round(psnr, 2),
             "workload": f"vq-4x250k-k{k}-iters{iters}-compose-800px-view3"}
+
+
+SH_FWD_BYTES = 48 * 4 + 12 + 12            # per Gaussian: coefficients and mean read, colour written
+SH_BWD_BYTES = 48 * 4 + 12 + 12 + 48 * 4 + 24  # + dL/dcolour read, dL/dsh written, dL/dmean read and written
+
+
+def secondary_sh(dev, steps=20, warmup=3):
+    """Base 3DGS (Sec. 4.2), degree-3 SH colour on the 1M Gaussians of the
+    main workload: the SH colour and backward kernels on their own, and a
+    training step (SH colour -> rasterize -> L1 -> backward through both) at
+    800x800, one view per step cycling the 100 cameras."""
+    import torch
+    from paper_2504_17954_amd import inputs as I
+    from paper_2504_17954_amd import native as N
+    from paper_2504_17954_amd import raster as R
+    from paper_2504_17954_amd import sh as SH
+    models, edits = h2_scene(1_000_000, 4)
+    mdev = [{kk: torch.from_numpy(v).to(dev) for kk, v in m.planes.items()} for m in models]
+    planes, _ = R.compose(mdev, edits, dev)
+    n = planes["mean"].shape[1]
+    planes["shade"] = SH.base_shade(n, dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(I.SEED_SCENE + 91)
+    sh = (torch.randn((48, n), generator=g, device=dev) * 0.15).contiguous()
+    sh[0:3] = (torch.rand((3, n), generator=g, device=dev) - 0.5) / 0.28209479177387814
+    cams = I.cameras_at(I.fibonacci_sphere(100), 800, 800)
+    cams_t = R.camera_table(cams, dev)
+    gc = torch.rand((3, n), generator=g, device=dev) - 0.5
+    gm = torch.zeros((3, n), device=dev)
+    for _ in range(3):
+        SH.color(sh, planes["mean"], cams[0], 3)
+        SH.color_bwd(sh, planes["mean"], cams[0], 3, gc, gm)
+    N.ivrgs_timing_enable(["sh"])
+    for v in range(10):
+        SH.color(sh, planes["mean"], cams[v], 3)
+    t_f = N.ivrgs_timing_read()["sh"]
+    N.ivrgs_timing_enable(["sh"])
+    for v in range(10):
+        SH.color_bwd(sh, planes["mean"], cams[v], 3, gc, gm)
+    t_b = N.ivrgs_timing_read()["sh"]
+    N.ivrgs_timing_enable(0)
+    ms_f, ms_b = t_f[0] / t_f[1], t_b[0] / t_b[1]
+    gbs_f = n * SH_FWD_BYTES / (ms_f * 1e-3) / 1e9
+    gbs_b = n * SH_BWD_BYTES / (ms_b * 1e-3) / 1e9
+    rnd = R.Renderer(R.Settings(800, 800), capacity=1 << 24, check="sync")
+    jobs = R.Jobs.single(n)
+    mean = planes["mean"].clone().requires_grad_(True)
+    shp = sh.clone().requires_grad_(True)
+    tg = torch.Generator(device=dev)
+    tg.manual_seed(I.SEED_TARGET + 91)
+    targets = [torch.rand((4, 800, 800), generator=tg, device=dev) for _ in range(4)]
+
+    def step(v):
+        pl = dict(planes, mean=mean, color=SH.SHColor.apply(shp, mean, cams[v % 100], 3))
+        out = R.rasterize(pl, cams_t[v % 100:v % 100 + 1], jobs, rnd)[0]
+        loss = (out - targets[v % 4]).abs().mean()
+        mean.grad = shp.grad = None
+        loss.backward()
+
+    for v in range(warmup):
+        step(v)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for v in range(steps):
+        step(v)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    log(f"base 3DGS SH: colour {ms_f:.4f} ms ({gbs_f:.0f} GB/s), backward {ms_b:.4f} ms ({gbs_b:.0f} GB/s); "
+        f"training step {dt * 1e3:.3f} ms ({1 / dt:.1f} it/s)")
+    return {"sh_color_ms": round(ms_f, 4), "sh_color_bwd_ms": round(ms_b, 4),
+            "sh_color_roofline": {"bound": "hbm", "achieved": round(gbs_f, 1), "peak": 8000.0, "unit": "GB/s",
+                                  "frac": round(gbs_f / 8000.0, 4), "bytes_per_gaussian": SH_FWD_BYTES},
+            "sh_color_bwd_roofline": {"bound": "hbm", "achieved": round(gbs_b, 1), "peak": 8000.0, "unit": "GB/s",
+                                      "frac": round(gbs_b / 8000.0, 4), "bytes_per_gaussian": SH_BWD_BYTES},
+            "train_step_ms": round(dt * 1e3, 4), "train_iters_per_s": round(1 / dt, 2),
+            "workload": "base3dgs-sh3-1000000-800px-fwd+bwd"}
 
 
 EXPLORE_N = 1_484_642  # composed primitives of the paper's largest-timed exploration example
