@@ -47,10 +47,15 @@ def depth_keys(mean32: np.ndarray, cam_row: np.ndarray) -> np.ndarray:
 
 
 def render(planes_t: dict, cam_row, params: Params, model_id=None, edit_rows=None,
-           planes_np: dict | None = None):
+           planes_np: dict | None = None, attr_t=None):
     """planes_t: dict of float64 tensors [d, n] (may require grad).
     Returns rgba [4, H, W] (float64 tensor), the kept-Gaussian order and a
-    decision signature (changes iff the set of composited pairs changes)."""
+    decision signature (changes iff the set of composited pairs changes).
+    With attr_t (float64 [A, n]): also the auxiliary maps [1 + A, H, W]
+    composited with the same weights T_i alpha_i (Eq. 5 for depth and normal,
+    and the offset-colour and shading maps of Sec. 4.3): channel 0 the
+    camera-space depth of each Gaussian, then the A attributes; no
+    background term."""
     cam_row = np.asarray(cam_row, np.float32)
     n = planes_t["mean"].shape[1]
     mean = planes_t["mean"].T
@@ -116,6 +121,7 @@ def render(planes_t: dict, cam_row, params: Params, model_id=None, edit_rows=Non
     T = torch.ones(P, dtype=torch.float64)
     Cc = torch.zeros(3, P, dtype=torch.float64)
     A = torch.zeros(P, dtype=torch.float64)
+    aux = None if attr_t is None else torch.zeros(1 + attr_t.shape[0], P, dtype=torch.float64)
     alive = torch.ones(P, dtype=torch.bool)
     sig = 0
     pix_id = torch.arange(1, P + 1, dtype=torch.int64)
@@ -135,9 +141,14 @@ def render(planes_t: dict, cam_row, params: Params, model_id=None, edit_rows=Non
         w = torch.where(comp, T * alpha, torch.zeros_like(T))
         Cc = Cc + w[None] * rgb[:, i:i + 1]
         A = A + w
+        if aux is not None:
+            vals = torch.cat([tz[i:i + 1], attr_t[:, i]])
+            aux = aux + w[None] * vals[:, None]
         T = torch.where(comp, Tn, T)
     bg = torch.tensor(params.bg, dtype=torch.float64)[:, None]
     out = torch.cat([Cc + T[None] * bg, A[None]], 0).reshape(4, H, Wd)
+    if aux is not None:
+        return out, order, sig, aux.reshape(-1, H, Wd)
     return out, order, sig
 
 
