@@ -298,10 +298,10 @@ ivrgs_status ivrgs_light_bwd(const ivrgs_batch *batch, const ivrgs_params *param
  * queue), 2 scatter, 3 depth order, 4 render_fwd, 5 render_bwd,
  * 6 project_bwd, 7 compose, 8 fills, 9 cull, 10 edit and light gradients
  * and the exploration step, 11 VQ (k-means, assignment, quantised compose),
- * 12 SH colour and its backward.  Process-wide state; not for concurrent
- * callers. */
-#define IVRGS_TIMING_KINDS 13
-#define IVRGS_TIMING_ALL 0x1FFFu
+ * 12 SH colour and its backward, 13 auxiliary maps and their backward.
+ * Process-wide state; not for concurrent callers. */
+#define IVRGS_TIMING_KINDS 14
+#define IVRGS_TIMING_ALL 0x3FFFu
 void ivrgs_timing_enable(uint32_t kinds);
 int32_t ivrgs_timing_read(double *ms, int64_t *launches);
 
@@ -441,6 +441,36 @@ ivrgs_status ivrgs_vq_assign(const float *values, int64_t n, const float *codebo
  * models[m].n. */
 ivrgs_status ivrgs_vq_compose(const ivrgs_vq_model *models, int32_t n_models, const ivrgs_model_edit *edits,
                               ivrgs_gaussians_mut *out, void *stream);
+
+/* ---- Auxiliary maps (Eq. 5; Sec. 4.3) --------------------------------------
+ * The training losses of the basic models read, besides the image, maps
+ * composited with the image's weights T_i alpha_i: the depth and normal maps
+ * of Eq. 5 (normal consistency) and the offset-colour and shading-term maps
+ * of Sec. 4.3 (sparsity and bilateral smoothness).  Channel 0 is the
+ * camera-space depth of each record (its depth key, row 3 of R applied to
+ * the mean plus t); channels 1 .. n_attr composite caller attribute planes
+ * attr[c][g] (0 <= n_attr <= 15; for example the unit normal, delta-c, k_a,
+ * k_d, k_s, beta).  No background term.  Both calls follow ivrgs_bin_sort
+ * of the same batch and params (the composited pairs are exactly the
+ * image's). */
+
+/* attr: device [n_attr][batch->g.n]; out_aux: device
+ * [n_jobs][1 + n_attr][H][W], written. */
+ivrgs_status ivrgs_render_aux_fwd(const ivrgs_batch *batch, const ivrgs_params *params,
+                                  const ivrgs_projected *proj, const ivrgs_bins *bins, const float *attr,
+                                  int32_t n_attr, float *out_aux, void *stream);
+
+/* Backward for dL/d(maps) grad_aux (same layout as the maps; aux: the
+ * forward's maps).  ADDS into grad_attr (device [n_attr][g.n]) the attribute
+ * gradients and into grads the geometry gradients: through alpha (mean,
+ * log_scale, quat, opacity, by the projection backward, accumulated) and
+ * through the depth (mean).  The caller clears both first.  workspace: the
+ * render workspace of this batch (its record-gradient rows are reused). */
+ivrgs_status ivrgs_render_aux_bwd(const ivrgs_batch *batch, const ivrgs_params *params,
+                                  const ivrgs_projected *proj, const ivrgs_bins *bins, const float *attr,
+                                  int32_t n_attr, const float *aux, const float *grad_aux, float *grad_attr,
+                                  ivrgs_gaussians_mut *grads, void *workspace, size_t workspace_bytes,
+                                  void *stream);
 
 /* ---- SH colour (base 3DGS, Sec. 3 and Sec. 4.2) ---------------------------
  * The base model's view-dependent colour is parameterised by spherical-

@@ -1,0 +1,76 @@
+"""Auxiliary maps for the training losses (Eq. 5 depth and normal maps; the
+offset-colour and shading-term maps of Sec. 4.3): argument marshalling
+around ivrgs_render_aux_fwd / ivrgs_render_aux_bwd and an autograd Function.
+The compositing and its backward run in the HIP kernels."""
+from __future__ import annotations
+
+import torch
+
+from . import native as N
+from .raster import PLANES, PLANE_DIMS, Jobs, Renderer, _stream, default_edits
+
+
+class _AuxFn(torch.autograd.Function):
+    """Forward: project, bin and composite the maps.  Backward: attribute
+    gradients and geometry gradients (through alpha and the depth)."""
+
+    @staticmethod
+    def forward(ctx, renderer, cams_t, jobs, model_id, edits_t, gauss_index, attr, *planes):
+        pl = dict(zip(PLANES, planes))
+        batch = renderer.make_batch(pl, model_id, edits_t, cams_t, jobs, gauss_index)
+        proj, bins = renderer.project_and_bin(batch)
+        s = renderer.settings
+        A = int(attr.shape[0])
+        aux = torch.empty((jobs.n_jobs, 1 + A, s.height, s.width), dtype=torch.float32, device=renderer.device)
+        N.ivrgs_render_aux_fwd(batch, s.params(), proj, bins, attr.data_ptr() if A else None, A, aux.data_ptr(),
+                               _stream())
+        ctx.renderer, ctx.jobs, ctx.generation = renderer, jobs, renderer.generation
+        ctx.has_mid, ctx.has_idx = model_id is not None, gauss_index is not None
+        ctx.save_for_backward(cams_t, model_id if model_id is not None else torch.empty(0), edits_t,
+                              gauss_index if gauss_index is not None else torch.empty(0), attr, aux, *planes)
+        return aux
+
+    @staticmethod
+    def backward(ctx, grad_aux):
+        saved = ctx.saved_tensors
+        cams_t, mid, edits_t, idx, attr, aux = saved[:6]
+        planes = dict(zip(PLANES, saved[6:]))
+        r = ctx.renderer
+        batch = r.make_batch(planes, mid if ctx.has_mid else None, edits_t, cams_t, ctx.jobs,
+                             idx if ctx.has_idx else None)
+        if r.generation != ctx.generation:  # the renderer's buffers were reused: bin again
+            proj, bins = r.project_and_bin(batch)
+        else:
+            proj, bins = r._structs(batch)
+        n = int(planes["mean"].shape[1])
+        grads = {k: torch.zeros((d, n), dtype=torch.float32, device=r.device) for k, d in PLANE_DIMS.items()}
+        gattr = torch.zeros_like(attr)
+        A = int(attr.shape[0])
+        g = N.ivrgs_gaussians(n, *[grads[k].data_ptr() for k in PLANES], None)
+        N.ivrgs_render_aux_bwd(batch, r.settings.params(), proj, bins, attr.data_ptr() if A else None, A,
+                               aux.data_ptr(), grad_aux.contiguous().data_ptr(), gattr.data_ptr() if A else None, g,
+                               r.ws.data_ptr(), r.ws.numel(), _stream())
+        return (None, None, None, None, None, None, gattr, *[grads[k] for k in PLANES])
+
+
+def render_aux(planes: dict, attr: torch.Tensor, cams_t, jobs: Jobs, renderer: Renderer, model_id=None,
+               edits_t=None, gauss_index=None) -> torch.Tensor:
+    """Differentiable maps [n_jobs, 1 + A, H, W]: channel 0 the camera-space
+    depth, then the A attribute planes attr [A, n] (float32, contiguous),
+    each composited with the image's weights T_i alpha_i."""
+    if attr.dtype != torch.float32 or attr.dim() != 2 or not attr.is_contiguous() or not attr.is_cuda:
+        raise ValueError("attr: expected contiguous float32 [A, n] on the device")
+    if attr.shape[0] > 15:
+        raise ValueError("at most 15 attribute planes")
+    if edits_t is None:
+        edits_t = default_edits(renderer.device)
+    return _AuxFn.apply(renderer, cams_t, jobs, model_id, edits_t, gauss_index, attr, *[planes[k] for k in PLANES])
+
+
+def editable_attributes(planes: dict) -> torch.Tensor:
+    """The attributes of the editable-Gaussian training losses, [10, n]: the
+    unit normal (3), delta-c (3, the colour plane of a basic model), k_a,
+    k_d, k_s, beta — differentiable in the planes."""
+    nrm = planes["normal"]
+    nrm = nrm / nrm.norm(dim=0, keepdim=True).clamp_min(1e-12)
+    return torch.cat([nrm, planes["color"], planes["shade"]]).contiguous()

@@ -314,6 +314,46 @@ ivrgs_status ivrgs_vq_compose(const ivrgs_vq_model *models, int32_t n_models, co
     return IVRGS_OK;
 }
 
+ivrgs_status ivrgs_render_aux_fwd(const ivrgs_batch *batch, const ivrgs_params *params,
+                                  const ivrgs_projected *proj, const ivrgs_bins *bins, const float *attr,
+                                  int32_t n_attr, float *out_aux, void *stream) {
+    ivrgs_status st = check_batch(batch);
+    if (st != IVRGS_OK) return st;
+    if ((st = check_params(params)) != IVRGS_OK) return st;
+    if (!proj || !bins || !bins->tile_start || !out_aux || n_attr < 0 || n_attr > kAuxMax) return IVRGS_E_INVALID;
+    if (n_attr > 0 && !attr) return IVRGS_E_INVALID;
+    const Consts k = make_consts(*params);
+    const int64_t n_tiles = (int64_t)batch->n_jobs * k.tiles_per_job;
+    return hip_status(launch_aux_fwd(*batch, k, n_tiles, proj->rec, bins->tile_start, bins->sorted, attr, n_attr,
+                                     out_aux, reinterpret_cast<hipStream_t>(stream)));
+}
+
+ivrgs_status ivrgs_render_aux_bwd(const ivrgs_batch *batch, const ivrgs_params *params,
+                                  const ivrgs_projected *proj, const ivrgs_bins *bins, const float *attr,
+                                  int32_t n_attr, const float *aux, const float *grad_aux, float *grad_attr,
+                                  ivrgs_gaussians_mut *grads, void *workspace, size_t workspace_bytes,
+                                  void *stream) {
+    ivrgs_status st = check_batch(batch);
+    if (st != IVRGS_OK) return st;
+    if ((st = check_params(params)) != IVRGS_OK) return st;
+    if (!proj || !bins || !bins->tile_start || !aux || !grad_aux || !grads || n_attr < 0 || n_attr > kAuxMax)
+        return IVRGS_E_INVALID;
+    if (n_attr > 0 && (!attr || !grad_attr)) return IVRGS_E_INVALID;
+    if (!valid_gauss_mut(*grads) || grads->n != batch->g.n) return IVRGS_E_SHAPE;
+    const Consts k = make_consts(*params);
+    const Layout L = layout(*batch, *params);
+    if (!workspace || workspace_bytes < L.total) return IVRGS_E_CAPACITY;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    float *grec = reinterpret_cast<float *>(static_cast<char *>(workspace) + L.grec);
+    const int64_t n_tiles = (int64_t)batch->n_jobs * k.tiles_per_job;
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(grec), kGradStride * batch->n_records, 0u, s);
+    if (e == hipSuccess)
+        e = launch_aux_bwd(*batch, k, n_tiles, proj->rec, bins->tile_start, bins->sorted, attr, n_attr, aux, grad_aux,
+                           grec, grad_attr, grads->mean, s);
+    if (e == hipSuccess) e = launch_project_bwd(*batch, k, proj->rect, grec, *grads, true, false, s);
+    return hip_status(e);
+}
+
 ivrgs_status ivrgs_sh_color(const float *sh, int32_t degree, const float *mean, int64_t n,
                             const ivrgs_camera *camera, float *color, void *stream) {
     if (degree < 0 || degree > 3 || n < 0 || !camera) return IVRGS_E_INVALID;

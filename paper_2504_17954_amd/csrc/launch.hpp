@@ -7,7 +7,7 @@ namespace ivrgs {
 
 // Kernel-timing hooks (no-ops unless timing is enabled).
 enum TimingKind { TK_PROJECT = 0, TK_COUNT, TK_SCATTER, TK_SORT, TK_FWD, TK_BWD, TK_PROJECT_BWD,
-                  TK_COMPOSE, TK_FILL, TK_CULL, TK_EDIT_BWD, TK_VQ, TK_SH, TK_KINDS };
+                  TK_COMPOSE, TK_FILL, TK_CULL, TK_EDIT_BWD, TK_VQ, TK_SH, TK_AUX, TK_KINDS };
 void timing_begin(int kind, hipStream_t s);
 void timing_end(int kind, hipStream_t s);
 
@@ -85,6 +85,17 @@ hipError_t launch_sh_color(const float *sh, int degree, const float *mean, int64
                            float *color, hipStream_t s);
 hipError_t launch_sh_color_bwd(const float *sh, int degree, const float *mean, int64_t n, const ivrgs_camera &cam,
                                const float *grad_color, float *grad_sh, float *grad_mean, hipStream_t s);
+// Auxiliary maps: depth plus up to kAuxMax attribute planes composited with
+// the image's weights, and their backward (record gradients for the
+// projection backward, attribute and depth-to-mean gradients added).
+constexpr int kAuxMax = 15;
+hipError_t launch_aux_fwd(const ivrgs_batch &b, const Consts &k, int64_t n_tiles, const float *rec,
+                          const uint32_t *starts, const uint32_t *sorted, const float *attr, int n_attr, float *aux,
+                          hipStream_t s);
+hipError_t launch_aux_bwd(const ivrgs_batch &b, const Consts &k, int64_t n_tiles, const float *rec,
+                          const uint32_t *starts, const uint32_t *sorted, const float *attr, int n_attr,
+                          const float *aux, const float *grad_aux, float *grec, float *grad_attr, float *grad_mean,
+                          hipStream_t s);
 hipError_t launch_work_queue(const uint32_t *starts, int64_t n_tiles, uint32_t *queue, hipStream_t s);
 
 }  // namespace ivrgs

@@ -1,0 +1,107 @@
+"""Training losses of the basic models, in torch on the maps the kernels
+render (the image, and the auxiliary maps of `aux.render_aux`):
+
+  - photometric: (1 - lam) L1 + lam (1 - SSIM) on the colour and alpha
+    channels (Sec. 4.2), lam = 0.2;
+  - normal consistency ||N - N~|| between the rendered normal map and the
+    pseudo-normal of the rendered depth under local planarity (Eq. 5, Eq. 6);
+  - sparsity: L1 of the rendered offset-colour map (Sec. 4.3);
+  - bilateral smoothness |grad K| exp(-|grad c_gt|) of the shading-term maps
+    (Eq. 7);
+  - opacity L1 over the Gaussians (Sec. 4.3).
+
+Readings where the paper is silent: SSIM after Wang et al. (2004), an 11x11
+Gaussian window of sigma 1.5, C1 = 0.01^2, C2 = 0.03^2, averaged over the
+windows that lie inside the image; depth and normal maps are divided by the
+alpha map before use (pixels with alpha <= 0.5 are left out); the
+pseudo-normal is the cross product of the central differences of the
+back-projected points, turned to face the camera and taken to world space;
+image gradients are forward differences, |grad c_gt| the mean over colour
+channels of their absolute values.
+"""
+from __future__ import annotations
+
+import torch
+import torch.nn.functional as F
+
+
+def _gauss_window(size: int, sigma: float, dtype, device):
+    x = torch.arange(size, dtype=dtype, device=device) - (size - 1) / 2
+    g = torch.exp(-(x * x) / (2 * sigma * sigma))
+    return g / g.sum()
+
+
+def ssim(x: torch.Tensor, y: torch.Tensor, window: int = 11, sigma: float = 1.5) -> torch.Tensor:
+    """Mean SSIM of two images [C, H, W] with values in [0, 1]."""
+    c = x.shape[0]
+    g = _gauss_window(window, sigma, x.dtype, x.device)
+    wx = g.view(1, 1, 1, window).expand(c, 1, 1, window)
+    wy = g.view(1, 1, window, 1).expand(c, 1, window, 1)
+
+    def blur(t):
+        return F.conv2d(F.conv2d(t[None], wx, groups=c), wy, groups=c)[0]  # 'valid' windows only
+
+    mx, my = blur(x), blur(y)
+    sxx = blur(x * x) - mx * mx
+    syy = blur(y * y) - my * my
+    sxy = blur(x * y) - mx * my
+    c1, c2 = 0.01 ** 2, 0.03 ** 2
+    s = ((2 * mx * my + c1) * (2 * sxy + c2)) / ((mx * mx + my * my + c1) * (sxx + syy + c2))
+    return s.mean()
+
+
+def photometric(rgba: torch.Tensor, target: torch.Tensor, lam: float = 0.2) -> torch.Tensor:
+    """(1 - lam) mean |rgba - target| + lam (1 - SSIM), colour and alpha."""
+    return (1 - lam) * (rgba - target).abs().mean() + lam * (1 - ssim(rgba, target))
+
+
+def pseudo_normal(depth: torch.Tensor, alpha: torch.Tensor, cam) -> tuple[torch.Tensor, torch.Tensor]:
+    """World-space unit normals [3, H, W] of the alpha-normalised depth map
+    under local planarity, and the mask of pixels where they are defined."""
+    H, W = depth.shape
+    dev, dt = depth.device, depth.dtype
+    ok = alpha > 0.5
+    d = torch.where(ok, depth / alpha.clamp_min(1e-6), torch.zeros_like(depth))
+    ys, xs = torch.meshgrid(torch.arange(H, dtype=dt, device=dev) + 0.5,
+                            torch.arange(W, dtype=dt, device=dev) + 0.5, indexing="ij")
+    P = torch.stack([(xs - cam.cx) / cam.fx * d, (ys - cam.cy) / cam.fy * d, d])  # camera space
+    dx = torch.zeros_like(P)
+    dy = torch.zeros_like(P)
+    dx[:, :, 1:-1] = (P[:, :, 2:] - P[:, :, :-2]) / 2
+    dy[:, 1:-1, :] = (P[:, 2:, :] - P[:, :-2, :]) / 2
+    n = torch.cross(dx, dy, dim=0)
+    n = n / n.norm(dim=0, keepdim=True).clamp_min(1e-12)
+    n = torch.where((n * P).sum(0, keepdim=True) > 0, -n, n)  # face the camera
+    valid = ok.clone()
+    valid[:, [0, -1]] = False
+    valid[[0, -1], :] = False
+    valid &= ok.roll(1, 0) & ok.roll(-1, 0) & ok.roll(1, 1) & ok.roll(-1, 1)
+    R = torch.as_tensor(cam.R, dtype=dt, device=dev)
+    return torch.einsum("ji,jhw->ihw", R, n), valid  # R^T n: camera to world
+
+
+def normal_consistency(normal_map: torch.Tensor, depth: torch.Tensor, alpha: torch.Tensor, cam) -> torch.Tensor:
+    """Mean over valid pixels of || N / |N| - N~ ||_2 (Eq. 6)."""
+    pn, valid = pseudo_normal(depth.detach(), alpha.detach(), cam)
+    nn_ = normal_map / normal_map.norm(dim=0, keepdim=True).clamp_min(1e-12)
+    diff = (nn_ - pn).norm(dim=0)
+    return diff[valid].mean() if valid.any() else normal_map.sum() * 0
+
+
+def sparsity(delta_c_map: torch.Tensor) -> torch.Tensor:
+    """L1 of the rendered offset-colour map."""
+    return delta_c_map.abs().mean()
+
+
+def bilateral_smoothness(k_maps: torch.Tensor, gt_rgb: torch.Tensor) -> torch.Tensor:
+    """Mean over maps and pixels of |grad K| exp(-|grad c_gt|) (Eq. 7),
+    forward differences in x and y."""
+    gx = (k_maps[:, :, 1:] - k_maps[:, :, :-1]).abs()
+    gy = (k_maps[:, 1:, :] - k_maps[:, :-1, :]).abs()
+    wx = torch.exp(-(gt_rgb[:, :, 1:] - gt_rgb[:, :, :-1]).abs().mean(0))
+    wy = torch.exp(-(gt_rgb[:, 1:, :] - gt_rgb[:, :-1, :]).abs().mean(0))
+    return (gx * wx).mean() + (gy * wy).mean()
+
+
+def opacity_l1(opacity: torch.Tensor) -> torch.Tensor:
+    return opacity.abs().mean()

@@ -24,9 +24,9 @@ EXPORTS = ("ivrgs_workspace_size", "ivrgs_tiles_per_job", "ivrgs_compose", "ivrg
            "ivrgs_cull_workspace_size", "ivrgs_cull", "ivrgs_compose_bwd", "ivrgs_light_bwd",
            "ivrgs_compose_dev", "ivrgs_explore_state_words", "ivrgs_explore_step",
            "ivrgs_vq_workspace_size", "ivrgs_vq_fit", "ivrgs_vq_assign", "ivrgs_vq_compose",
-           "ivrgs_sh_color", "ivrgs_sh_color_bwd")
+           "ivrgs_sh_color", "ivrgs_sh_color_bwd", "ivrgs_render_aux_fwd", "ivrgs_render_aux_bwd")
 TIMING_KINDS = ("project", "tile_count", "scatter", "depth_sort", "render_fwd", "render_bwd",
-                "project_bwd", "compose", "fill", "cull", "edit_bwd", "vq", "sh")
+                "project_bwd", "compose", "fill", "cull", "edit_bwd", "vq", "sh", "aux")
 
 
 class ivrgs_gaussians(C.Structure):
@@ -152,6 +152,10 @@ def load(path: str = LIB_PATH):
     lib.ivrgs_sh_color.restype = C.c_int
     lib.ivrgs_sh_color_bwd.argtypes = [P, C.c_int32, P, C.c_int64, P, P, P, P, P]
     lib.ivrgs_sh_color_bwd.restype = C.c_int
+    lib.ivrgs_render_aux_fwd.argtypes = [P, P, P, P, P, C.c_int32, P, P]
+    lib.ivrgs_render_aux_fwd.restype = C.c_int
+    lib.ivrgs_render_aux_bwd.argtypes = [P, P, P, P, P, C.c_int32, P, P, P, P, P, C.c_size_t, P]
+    lib.ivrgs_render_aux_bwd.restype = C.c_int
     lib.ivrgs_timing_enable.argtypes = [C.c_uint32]
     lib.ivrgs_timing_enable.restype = None
     lib.ivrgs_timing_read.argtypes = [P, P]
@@ -240,6 +244,18 @@ def ivrgs_sh_color_bwd(sh_ptr, degree: int, mean_ptr, n: int, camera, grad_color
                        stream):
     check(load().ivrgs_sh_color_bwd(sh_ptr, degree, mean_ptr, C.c_int64(n), ref(camera), grad_color_ptr,
                                     grad_sh_ptr, grad_mean_ptr, stream), "ivrgs_sh_color_bwd")
+
+
+def ivrgs_render_aux_fwd(batch, params, proj, bins, attr_ptr, n_attr: int, aux_ptr, stream):
+    check(load().ivrgs_render_aux_fwd(ref(batch), ref(params), ref(proj), ref(bins), attr_ptr, n_attr, aux_ptr,
+                                      stream), "ivrgs_render_aux_fwd")
+
+
+def ivrgs_render_aux_bwd(batch, params, proj, bins, attr_ptr, n_attr: int, aux_ptr, grad_aux_ptr, grad_attr_ptr,
+                         grads, ws_ptr, ws_bytes, stream):
+    check(load().ivrgs_render_aux_bwd(ref(batch), ref(params), ref(proj), ref(bins), attr_ptr, n_attr, aux_ptr,
+                                      grad_aux_ptr, grad_attr_ptr, ref(grads), ws_ptr, ws_bytes, stream),
+          "ivrgs_render_aux_bwd")
 
 
 def ivrgs_project(batch, params, proj, stream):

@@ -1,0 +1,116 @@
+"""GPU parity of the auxiliary maps (Eq. 5 depth and normal maps; offset-
+colour and shading maps of Sec. 4.3) and their backward, through the C ABI,
+against the dense FP64 oracle and its autograd; and, at full size, the
+property that compositing each Gaussian's colour as an attribute gives the
+image itself.
+
+Tolerances: maps within 1e-4 of the channel's largest attribute magnitude
+(1e-4 of colour in [0, 1], scaled for depth); gradients within 1e-3 relative
+plus 1e-5 of the largest magnitude; pixels with an ambiguous decision in the
+C oracle are left out of the maps and carry no upstream gradient.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle import dense as D
+from paper_2504_17954_amd import aux as AX
+from paper_2504_17954_amd import inputs as I
+from paper_2504_17954_amd import raster as R
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available()
+    return torch.device("cuda:0")
+
+
+def check_grad(a, b, what):
+    tol = 1e-3 * np.abs(b) + 1e-5 * np.abs(b).max() + 1e-30
+    bad = np.abs(a - b) > tol
+    say(f"  {what}: max|g| {np.abs(b).max():.3e}, outside {bad.sum()} / {b.size}, "
+        f"worst {(np.abs(a - b) / tol).max():.3f}")
+    assert not bad.any(), np.argwhere(bad)[:5]
+
+
+def attributes(planes):
+    n = planes["normal"]
+    return np.concatenate([n / np.linalg.norm(n, axis=0, keepdims=True), planes["color"],
+                           planes["shade"]]).astype(np.float32)
+
+
+def small(n, seed, width=40, height=32):
+    m = I.small_scene(n, seed, log_scale_mu=-2.6)
+    planes = I.plain_planes(m)
+    cam = I.look_at((0.3, -3.6, 0.9), width=width, height=height)
+    return planes, cam, O.Params(width, height)
+
+
+@pytest.mark.parametrize("n,seed", [(150, 41), (400, 42)])
+def test_aux_forward_and_backward_match_dense_oracle(dev, n, seed):
+    planes, cam, prm = small(n, seed)
+    attr = attributes(planes)
+    say(f"aux maps, {n} Gaussians, 10 attributes")
+    flags = O.render(planes, cam, prm)["flags"]
+    ok = flags == 0
+    pt = D.to_tensors(planes, requires_grad=True)
+    at = torch.tensor(attr.astype(np.float64), requires_grad=True)
+    _, _, _, ref = D.render(pt, cam.row(), prm, attr_t=at)
+    G = np.random.default_rng(seed).normal(size=ref.shape) * ok[None]
+    (ref * torch.from_numpy(G)).sum().backward()
+
+    pd = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev).requires_grad_(True) for k, v in planes.items()}
+    ad = torch.from_numpy(attr).to(dev).requires_grad_(True)
+    rnd = R.Renderer(R.Settings(prm.width, prm.height))
+    out = AX.render_aux(pd, ad, R.camera_table([cam]), R.Jobs.single(n), rnd)[0]
+    got = out.detach().cpu().numpy()
+    refn = ref.detach().numpy()
+    scale = np.concatenate([[np.abs(refn[0]).max()], np.abs(attr).max(axis=1)])  # depth, then attributes
+    err = np.abs(got - refn)[:, ok].max(axis=1)
+    say(f"  map errors {np.array2string(err, precision=2)}")
+    assert np.all(err <= 1e-4 * np.maximum(scale, 1.0))
+    (out * torch.from_numpy(G.astype(np.float32)).to(dev)).sum().backward()
+    check_grad(ad.grad.cpu().numpy(), at.grad.numpy(), "d/dattr")
+    for k in ("mean", "log_scale", "quat", "opacity"):
+        check_grad(pd[k].grad.cpu().numpy(), pt[k].grad.numpy(), f"d/d{k}")
+
+
+def test_colour_attribute_gives_the_image_at_full_size(dev):
+    """300k Gaussians at 800x800 (the single-model configuration): with the
+    shading passing the colour through, the colour maps equal the image."""
+    m = I.isosurface_model(300_000, I.SEED_SCENE + 2, 0.0)
+    planes = I.plain_planes(m)
+    n = m.n
+    planes["shade"] = np.tile(np.array([[1.0], [0.0], [0.0], [1.0]], np.float32), (1, n))
+    cam = I.cameras_at(I.fibonacci_sphere(100), 800, 800)[7]
+    pd = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in planes.items()}
+    rnd = R.Renderer(R.Settings(800, 800), capacity=1 << 24, check="sync")
+    cams = R.camera_table([cam])
+    say("aux colour maps vs the image, 300k Gaussians, 800x800")
+    img = rnd.forward(pd, cams, R.Jobs.single(n), edits_t=R.default_edits(dev))[0]
+    ones = torch.ones((1, n), device=dev)
+    attr = torch.cat([pd["color"], ones]).contiguous()
+    aux = AX.render_aux(pd, attr, cams, R.Jobs.single(n), rnd)[0]
+    d = (aux[1:4] - img[:3]).abs().max().item()
+    da = (aux[4] - img[3]).abs().max().item()
+    say(f"  colour max diff {d:.3e}, alpha max diff {da:.3e}")
+    assert d <= 1e-5 and da <= 1e-5
+    assert float(aux[0].max()) > 0.0
+
+
+def test_invalid_attribute_count(dev):
+    planes, cam, prm = small(20, 43)
+    pd = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in planes.items()}
+    with pytest.raises(ValueError):
+        AX.render_aux(pd, torch.zeros((16, 20), device=dev), R.camera_table([cam]), R.Jobs.single(20),
+                      R.Renderer(R.Settings(prm.width, prm.height)))

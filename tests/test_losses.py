@@ -1,0 +1,70 @@
+"""The training losses (Sec. 4.2, 4.3; Eq. 6, 7) against brute force and
+closed forms, on the CPU."""
+import numpy as np
+import torch
+
+from paper_2504_17954_amd import inputs as I
+from paper_2504_17954_amd import losses as L
+
+
+def test_ssim_of_an_image_with_itself_is_one():
+    x = torch.rand((4, 20, 24), dtype=torch.float64, generator=torch.Generator().manual_seed(1))
+    assert abs(L.ssim(x, x).item() - 1.0) < 1e-12
+
+
+def test_ssim_matches_brute_force_windows():
+    rng = np.random.default_rng(2)
+    x = rng.uniform(0, 1, (2, 16, 18))
+    y = np.clip(x + rng.normal(0, 0.1, x.shape), 0, 1)
+    g = np.exp(-((np.arange(11) - 5.0) ** 2) / (2 * 1.5 ** 2))
+    w = np.outer(g, g) / np.outer(g, g).sum()
+    vals = []
+    for c in range(2):
+        for i in range(16 - 10):
+            for j in range(18 - 10):
+                a, b = x[c, i:i + 11, j:j + 11], y[c, i:i + 11, j:j + 11]
+                ma, mb = (w * a).sum(), (w * b).sum()
+                va, vb = (w * a * a).sum() - ma * ma, (w * b * b).sum() - mb * mb
+                cab = (w * a * b).sum() - ma * mb
+                vals.append(((2 * ma * mb + 1e-4) * (2 * cab + 9e-4)) / ((ma * ma + mb * mb + 1e-4) * (va + vb + 9e-4)))
+    got = L.ssim(torch.from_numpy(x), torch.from_numpy(y)).item()
+    assert abs(got - np.mean(vals)) < 1e-12
+
+
+def test_pseudo_normal_of_a_plane_is_its_normal():
+    cam = I.look_at((0.4, -3.0, 1.0), width=48, height=40)
+    n_c = np.array([0.2, -0.3, -1.0])
+    n_c /= np.linalg.norm(n_c)  # facing the camera (negative z in camera space)
+    c = -2.5  # plane n . P = c in camera space
+    ys, xs = np.meshgrid(np.arange(40) + 0.5, np.arange(48) + 0.5, indexing="ij")
+    rays = np.stack([(xs - cam.cx) / cam.fx, (ys - cam.cy) / cam.fy, np.ones_like(xs)])
+    depth = c / np.einsum("i,ihw->hw", n_c, rays)
+    alpha = np.full_like(depth, 0.9)
+    pn, valid = L.pseudo_normal(torch.from_numpy(depth * alpha), torch.from_numpy(alpha), cam)
+    want = np.asarray(cam.R, np.float64).T @ n_c  # world space
+    got = pn.numpy()[:, valid.numpy()]
+    assert valid.sum() == 38 * 46
+    np.testing.assert_allclose(got, np.repeat(want[:, None], got.shape[1], 1), atol=1e-9)
+
+
+def test_normal_consistency_is_zero_on_agreeing_maps():
+    cam = I.look_at((0.0, -3.0, 0.0), width=24, height=24)
+    depth = torch.full((24, 24), 2.0, dtype=torch.float64)
+    alpha = torch.ones((24, 24), dtype=torch.float64)
+    pn, _ = L.pseudo_normal(depth, alpha, cam)
+    assert L.normal_consistency(pn * 0.7, depth, alpha, cam).item() < 1e-12
+
+
+def test_bilateral_smoothness_and_sparsity_closed_forms():
+    k = torch.zeros((4, 10, 12), dtype=torch.float64)
+    gt = torch.rand((3, 10, 12), dtype=torch.float64, generator=torch.Generator().manual_seed(3))
+    assert L.bilateral_smoothness(k, gt).item() == 0.0
+    k[0] = torch.arange(12, dtype=torch.float64)[None, :] * 0.5  # slope 0.5 along x
+    flat = torch.zeros_like(gt)
+    # only the x differences of one map of four: mean 0.5 over a quarter of the entries
+    assert abs(L.bilateral_smoothness(k, flat).item() - 0.5 / 4) < 1e-12
+    edge = flat.clone()
+    edge[:, :, 6:] = 1.0  # a unit step in every channel between columns 5 and 6
+    want = 0.5 * (10 * 10 + 10 * np.exp(-1.0)) / (4 * 10 * 11)
+    assert abs(L.bilateral_smoothness(k, edge).item() - want) < 1e-12
+    assert abs(L.sparsity(torch.tensor([[-1.0, 2.0], [0.5, -0.5]])).item() - 1.0) < 1e-12
