@@ -103,6 +103,7 @@ def parse():
     ap.add_argument("--no-explore", action="store_true")
     ap.add_argument("--no-vq", action="store_true")
     ap.add_argument("--no-sh", action="store_true")
+    ap.add_argument("--no-editable", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB five times (counter calibration)")
@@ -317,6 +318,8 @@ def main():
             result["secondary"]["vq"] = secondary_vq(dev)
         if not args.no_sh:
             result["secondary"]["base_3dgs_sh"] = secondary_sh(dev)
+        if not args.no_editable:
+            result["secondary"]["editable_training"] = secondary_editable(dev)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(models, edits, cams, W, H, views[0], args.cpu_seconds)
@@ -500,6 +503,56 @@ def secondary_sh(dev, steps=20, warmup=3):
                                       "frac": round(gbs_b / 8000.0, 4), "bytes_per_gaussian": SH_BWD_BYTES},
             "train_step_ms": round(dt * 1e3, 4), "train_iters_per_s": round(1 / dt, 2),
             "workload": "base3dgs-sh3-1000000-800px-fwd+bwd"}
+
+
+def secondary_editable(dev, steps=20, warmup=3):
+    """Editable-Gaussian training step of one basic model (Sec. 4.3): 300k
+    Gaussians, 800x800, one view per step: the image and the eleven
+    auxiliary maps (depth, unit normal, delta-c, k_a, k_d, k_s, beta), the
+    full loss (L1 + SSIM, normal consistency, opacity L1, sparsity,
+    bilateral smoothness) and the backward through both renders."""
+    import torch
+    from paper_2504_17954_amd import aux as AX
+    from paper_2504_17954_amd import inputs as I
+    from paper_2504_17954_amd import losses as LS
+    from paper_2504_17954_amd import native as N
+    from paper_2504_17954_amd import raster as R
+    m = I.isosurface_model(300_000, I.SEED_SCENE + 2, 0.0)
+    planes = {k: torch.from_numpy(v).to(dev).requires_grad_(True) for k, v in I.plain_planes(m).items()}
+    n = m.n
+    cams = I.cameras_at(I.fibonacci_sphere(100), 800, 800)
+    cams_t = R.camera_table(cams, dev)
+    tg = torch.Generator(device=dev)
+    tg.manual_seed(I.SEED_TARGET + 93)
+    targets = [torch.rand((4, 800, 800), generator=tg, device=dev) for _ in range(4)]
+    rnd = R.Renderer(R.Settings(800, 800), capacity=1 << 24, check="sync")
+    jobs = R.Jobs.single(n)
+
+    def step(v):
+        rgba = R.rasterize(planes, cams_t[v % 100:v % 100 + 1], jobs, rnd)[0]
+        maps = AX.render_aux(planes, AX.editable_attributes(planes), cams_t[v % 100:v % 100 + 1], jobs, rnd)[0]
+        loss = LS.editable_loss(rgba, targets[v % 4], maps, planes["opacity"], cams[v % 100])
+        for t in planes.values():
+            t.grad = None
+        loss.backward()
+        return loss
+
+    for v in range(warmup):
+        step(v)
+    torch.cuda.synchronize()
+    N.ivrgs_timing_enable(["aux"])
+    t0 = time.perf_counter()
+    for v in range(steps):
+        loss = step(v)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    t_aux = N.ivrgs_timing_read()["aux"]
+    N.ivrgs_timing_enable(0)
+    log(f"editable training step (300k, 800x800, image + 11 maps + full loss): {dt * 1e3:.3f} ms "
+        f"({1 / dt:.1f} it/s); aux kernels {t_aux[0] / steps:.3f} ms per step; loss {float(loss):.4f}")
+    return {"train_step_ms": round(dt * 1e3, 4), "train_iters_per_s": round(1 / dt, 2),
+            "aux_kernels_ms_per_step": round(t_aux[0] / steps, 4),
+            "workload": "editable-300000-800px-image+11maps-fullloss-fwd+bwd"}
 
 
 EXPLORE_N = 1_484_642  # composed primitives of the paper's largest-timed exploration example

@@ -10,6 +10,10 @@ render (the image, and the auxiliary maps of `aux.render_aux`):
     (Eq. 7);
   - opacity L1 over the Gaussians (Sec. 4.3).
 
+Weights (appendix): L1 and SSIM combine as 0.8 and 0.2, the opacity L1 is
+scaled by 0.1, and the normal consistency and the other regularisers by
+0.01.  The editable stage adds its regularisers to the base stage's loss.
+
 Readings where the paper is silent: SSIM after Wang et al. (2004), an 11x11
 Gaussian window of sigma 1.5, C1 = 0.01^2, C2 = 0.03^2, averaged over the
 windows that lie inside the image; depth and normal maps are divided by the
@@ -105,3 +109,22 @@ def bilateral_smoothness(k_maps: torch.Tensor, gt_rgb: torch.Tensor) -> torch.Te
 
 def opacity_l1(opacity: torch.Tensor) -> torch.Tensor:
     return opacity.abs().mean()
+
+
+W_OPACITY = 0.1  # the L1 regulariser of the editable stage
+W_REG = 0.01     # normal consistency and the other regularisers
+
+
+def base_loss(rgba, target, depth, normal_map, cam) -> torch.Tensor:
+    """Base-3DGS stage: photometric + 0.01 normal consistency (maps of one
+    view: rgba [4, H, W], depth [H, W], normal_map [3, H, W])."""
+    return photometric(rgba, target) + W_REG * normal_consistency(normal_map, depth, rgba[3], cam)
+
+
+def editable_loss(rgba, target, maps, opacity, cam) -> torch.Tensor:
+    """Editable stage: the base loss plus 0.1 opacity L1 and 0.01 (offset-
+    colour sparsity + bilateral smoothness of the four shading maps).  maps
+    [11, H, W] from aux.render_aux with aux.editable_attributes: depth, unit
+    normal (3), delta-c (3), k_a, k_d, k_s, beta."""
+    return (base_loss(rgba, target, maps[0], maps[1:4], cam) + W_OPACITY * opacity_l1(opacity)
+            + W_REG * (sparsity(maps[4:7]) + bilateral_smoothness(maps[7:11], target[:3])))
