@@ -19,6 +19,7 @@ and the CPU oracle timed on a bounded sample of the same step.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -79,6 +80,15 @@ def measured_traffic(kernel: str):
     except (OSError, ValueError, KeyError):
         pass
     return None
+
+
+def settle():
+    """Collect, then freeze the surviving objects out of the cyclic garbage
+    collector: a full collection over the setup's objects (a few hundred
+    thousand; tens of milliseconds) would otherwise land inside a timed loop
+    as a host pause that has nothing to do with the GPU work."""
+    gc.collect()
+    gc.freeze()
 
 
 def log(*a):
@@ -190,6 +200,7 @@ def main():
             composed[k].grad = None
         return loss
 
+    settle()
     for i in range(args.warmup):
         step(i % args.views)
     torch.cuda.synchronize()
@@ -351,6 +362,7 @@ def secondary_fwd(dev):
         mx = max(mx, rnd.pairs())
     rnd.grow(int(mx * 1.1) + 4096)
     rnd.check = "defer"
+    settle()
     for v in range(5):
         rnd.forward(planes, cams_t, jobs[v], model_id=mid, edits_t=edits_t, out=out)
     torch.cuda.synchronize()
@@ -389,6 +401,7 @@ def secondary_vq(dev, k=256, iters=10, reps=20):
     for m in mdev[:1]:
         V.quantize(m, k, iters)  # warm-up
     torch.cuda.synchronize()
+    settle()
     t0 = time.perf_counter()
     qs = [V.quantize(m, k, iters) for m in mdev]
     torch.cuda.synchronize()
@@ -454,18 +467,18 @@ def secondary_sh(dev, steps=20, warmup=3):
     sh[0:3] = (torch.rand((3, n), generator=g, device=dev) - 0.5) / 0.28209479177387814
     cams = I.cameras_at(I.fibonacci_sphere(100), 800, 800)
     cams_t = R.camera_table(cams, dev)
-    gc = torch.rand((3, n), generator=g, device=dev) - 0.5
+    gcol = torch.rand((3, n), generator=g, device=dev) - 0.5
     gm = torch.zeros((3, n), device=dev)
     for _ in range(3):
         SH.color(sh, planes["mean"], cams[0], 3)
-        SH.color_bwd(sh, planes["mean"], cams[0], 3, gc, gm)
+        SH.color_bwd(sh, planes["mean"], cams[0], 3, gcol, gm)
     N.ivrgs_timing_enable(["sh"])
     for v in range(10):
         SH.color(sh, planes["mean"], cams[v], 3)
     t_f = N.ivrgs_timing_read()["sh"]
     N.ivrgs_timing_enable(["sh"])
     for v in range(10):
-        SH.color_bwd(sh, planes["mean"], cams[v], 3, gc, gm)
+        SH.color_bwd(sh, planes["mean"], cams[v], 3, gcol, gm)
     t_b = N.ivrgs_timing_read()["sh"]
     N.ivrgs_timing_enable(0)
     ms_f, ms_b = t_f[0] / t_f[1], t_b[0] / t_b[1]
@@ -486,6 +499,7 @@ def secondary_sh(dev, steps=20, warmup=3):
         mean.grad = shp.grad = None
         loss.backward()
 
+    settle()
     for v in range(warmup):
         step(v)
     torch.cuda.synchronize()
@@ -537,6 +551,7 @@ def secondary_editable(dev, steps=20, warmup=3):
         loss.backward()
         return loss
 
+    settle()
     for v in range(warmup):
         step(v)
     torch.cuda.synchronize()
@@ -592,6 +607,7 @@ def secondary_explore(dev, iters=100, warmup=5):
     target = ref.rgba.clone()
     del ref
     ex = E.Explorer(mdev, base, start, cam, target, R.Settings(W, W), lr=0.01)
+    settle()
     for _ in range(warmup):
         ex.step()
     torch.cuda.synchronize()
@@ -646,6 +662,7 @@ def secondary_batched(dev):
     best, times = A.tune(make, w.width, w.height, jobs.n_jobs, jobs.n_records, reps=3, use_cache=False)
     step.renderer.settings = A.apply(base, best)
     log(f"autotune (ms per candidate): {times} -> {best}")
+    settle()
     for _ in range(2):
         step.step()
     torch.cuda.synchronize()
