@@ -18,6 +18,7 @@ namespace {
 
 constexpr int kAuxChunk = 256;        // records staged per pass
 constexpr int kAuxAcc = 7 + kAuxMax;  // per-record sums of the backward: GO, GX, GY, GQA..GQC, depth, attributes
+static_assert(kAuxAcc <= 32, "one reduce-scatter of 32 values per record");
 
 struct AuxStage {
     float4 s0[kAuxChunk];  // mean x, mean y, qa, qb
@@ -25,6 +26,7 @@ struct AuxStage {
     float sa[kAuxMax][kAuxChunk];
     int64_t gid[kAuxChunk];
     uint32_t rid[kAuxChunk];
+    uint32_t wmask[kAuxChunk];  // bit w: the record can reach wave w's 16x4 strip of the tile
     int any_alive;
 };
 
@@ -32,13 +34,22 @@ struct AuxStage {
 // record, attributes from the record's Gaussian.
 __device__ __forceinline__ void stage(AuxStage &S, const ivrgs_batch &b, const ivrgs_job &job,
                                       const float4 *__restrict__ rec, const uint32_t *__restrict__ sorted,
-                                      uint32_t base, uint32_t end, const float *__restrict__ attr, int n_attr) {
+                                      uint32_t base, uint32_t end, const float *__restrict__ attr, int n_attr,
+                                      int tx0, int ty0) {
     const uint32_t e = base + threadIdx.x;
     if (e < end) {
         const uint32_t r = sorted[e];
         const float4 r0 = rec[3 * (size_t)r], r1 = rec[3 * (size_t)r + 1], r2 = rec[3 * (size_t)r + 2];
         S.s0[threadIdx.x] = r0;
         S.s1[threadIdx.x] = make_float4(r1.x, r1.y, r2.y, r2.z);
+        // the binning's conservative ellipse-box test, per wave strip: a wave
+        // skips a record that cannot reach any of its pixels
+        const HitTest h = make_hit_test(r0, r1, r2);
+        uint32_t m = 0;
+#pragma unroll
+        for (int w = 0; w < kTilePix / 64; ++w)
+            m |= box_hit(h, tx0, ty0 + w * (64 / kTile), kTile, 64 / kTile) ? 1u << w : 0u;
+        S.wmask[threadIdx.x] = m;
         const int64_t g = job_gaussian(job, b.gauss_index, (int)((int64_t)r - job.rec_begin));
         S.gid[threadIdx.x] = g;
         S.rid[threadIdx.x] = r;
@@ -84,8 +95,10 @@ __global__ __launch_bounds__(kTilePix) void k_aux_fwd(ivrgs_batch b, Consts k, c
     const int64_t tile = blockIdx.x;
     const int ji = (int)(tile / k.tiles_per_job), lt = (int)(tile % k.tiles_per_job);
     const ivrgs_job job = b.jobs[ji];
-    const int x = (lt % k.tiles_x) * kTile + (threadIdx.x & (kTile - 1));
-    const int y = (lt / k.tiles_x) * kTile + threadIdx.x / kTile;
+    const int tx0 = (lt % k.tiles_x) * kTile, ty0 = (lt / k.tiles_x) * kTile;
+    const int x = tx0 + (threadIdx.x & (kTile - 1));
+    const int y = ty0 + threadIdx.x / kTile;
+    const uint32_t wave_bit = 1u << (threadIdx.x >> 6);
     const bool inside = x < k.width && y < k.height;
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
     float T = 1.f, acc[1 + kAuxMax];
@@ -96,13 +109,15 @@ __global__ __launch_bounds__(kTilePix) void k_aux_fwd(ivrgs_batch b, Consts k, c
     for (uint32_t base = beg; base < end; base += kAuxChunk) {
         __syncthreads();  // the previous pass is consumed
         if (threadIdx.x == 0) S.any_alive = 0;
-        stage(S, b, job, rec, sorted, base, end, attr, n_attr);
+        stage(S, b, job, rec, sorted, base, end, attr, n_attr, tx0, ty0);
         __syncthreads();
         if (alive) S.any_alive = 1;
         __syncthreads();
         if (!S.any_alive) break;  // every pixel of the tile is done
         const int cnt = (int)min((uint32_t)kAuxChunk, end - base);
         for (int i = 0; i < cnt; ++i) {
+            if (__ballot(alive) == 0ull) break;  // this wave's pixels are done (it still meets the barriers)
+            if (!(S.wmask[i] & wave_bit)) continue;  // wave-uniform: cannot reach this wave's pixels
             const Step s = step(k, S.s0[i], S.s1[i], px, py, T, alive);
             if (s.comp) {
                 acc[0] = fmaf(s.w, S.s1[i].z, acc[0]);
@@ -125,8 +140,8 @@ __global__ __launch_bounds__(kTilePix) void k_aux_fwd(ivrgs_batch b, Consts k, c
 // composited pair, with ga = g . (depth, attributes) of the record and the
 // prefix P = sum of w ga over the pairs up to this one, dL/dalpha =
 // T ga - (g . A - P) / (1 - alpha) (the maps carry no background); then the
-// same record-gradient moments as the image backward.  The wave sums each
-// value into LDS per record; the workgroup then adds the record's sums into
+// same record-gradient moments as the image backward.  The wave reduces all
+// of a record's values in one reduce-scatter and adds them into LDS; the workgroup then adds the record's sums into
 // the record gradients (for the projection backward), the attribute
 // gradients and, for the depth, the mean gradient (depth = row 3 of R
 // applied to the mean, plus t).
@@ -143,8 +158,10 @@ __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, c
     const int64_t tile = blockIdx.x;
     const int ji = (int)(tile / k.tiles_per_job), lt = (int)(tile % k.tiles_per_job);
     const ivrgs_job job = b.jobs[ji];
-    const int x = (lt % k.tiles_x) * kTile + (threadIdx.x & (kTile - 1));
-    const int y = (lt / k.tiles_x) * kTile + threadIdx.x / kTile;
+    const int tx0 = (lt % k.tiles_x) * kTile, ty0 = (lt / k.tiles_x) * kTile;
+    const int x = tx0 + (threadIdx.x & (kTile - 1));
+    const int y = ty0 + threadIdx.x / kTile;
+    const uint32_t wave_bit = 1u << (threadIdx.x >> 6);
     const bool inside = x < k.width && y < k.height;
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
     const int nv = 1 + n_attr;
@@ -168,7 +185,7 @@ __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, c
     for (uint32_t base = beg; base < end; base += kAuxChunk) {
         __syncthreads();
         if (threadIdx.x == 0) S.any_alive = 0;
-        stage(S, b, job, rec, sorted, base, end, attr, n_attr);
+        stage(S, b, job, rec, sorted, base, end, attr, n_attr, tx0, ty0);
         for (int v = 0; v < kAuxAcc; ++v) acc[threadIdx.x][v] = 0.f;
         __syncthreads();
         if (alive) S.any_alive = 1;
@@ -176,6 +193,8 @@ __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, c
         if (!S.any_alive) break;
         const int cnt = (int)min((uint32_t)kAuxChunk, end - base);
         for (int i = 0; i < cnt; ++i) {
+            if (__ballot(alive) == 0ull) break;  // this wave's pixels are done (it still meets the barriers)
+            if (!(S.wmask[i] & wave_bit)) continue;  // wave-uniform: cannot reach this wave's pixels
             const float T0 = T;  // transmittance in front of this record
             const Step s = step(k, S.s0[i], S.s1[i], px, py, T, alive);
             if (__ballot(s.comp) == 0ull) continue;  // wave-uniform: nothing to add
@@ -196,12 +215,14 @@ __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, c
             vals[5] = dp * s.dy * s.dy;  // GQC
 #pragma unroll
             for (int c = 0; c < 1 + kAuxMax; ++c) vals[6 + c] = s.w * g[c];  // depth, then attributes
+            // one reduce-scatter for all the values: lanes 2m, 2m + 1 hold the
+            // wave total of value m
+            float v32[32];
 #pragma unroll
-            for (int v = 0; v < kAuxAcc; ++v)
-                if (v < 6 + nv) {
-                    const float t = wave_sum_to_lane63(vals[v]);
-                    if (lane == 63 && t != 0.f) atomicAdd(&acc[i][v], t);
-                }
+            for (int v = 0; v < 32; ++v) v32[v] = v < kAuxAcc ? vals[v] : 0.f;
+            const float tot = reduce_scatter32(v32);
+            const int m = lane >> 1;
+            if ((lane & 1) == 0 && m < 6 + nv && tot != 0.f) atomicAdd(&acc[i][m], tot);
         }
         __syncthreads();
         if ((int)threadIdx.x < cnt) {
