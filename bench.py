@@ -148,8 +148,8 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
-              "multi-GPU path to measure.", file=sys.stderr)
+        print(f"bench.py measures one GPU (asked for --gpus {args.gpus}): the library has no multi-GPU "
+              "path; how the path would shard is described with the design notes.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2504_17954_amd import inputs as I
