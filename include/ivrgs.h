@@ -178,7 +178,8 @@ typedef struct {
 
 /* Bytes of workspace needed by ivrgs_bin_sort, ivrgs_render_fwd and
  * ivrgs_render_bwd for this batch: the depth order (two words per record,
- * twice), its digit histograms, the per-chunk tile counts, the record
+ * twice), its digit histograms, the per-chunk tile counts, the records'
+ * binning fields in depth order (32 bytes per record), the record
  * gradients (9 floats per record), the work queue and, with one pixel per
  * lane and no work queue, per-pixel checkpoints at up to 15 cuts of every
  * tile's list (60 KiB per tile, used while they take at most 256 MiB): the

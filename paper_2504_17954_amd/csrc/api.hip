@@ -143,7 +143,7 @@ ivrgs_status check_batch(const ivrgs_batch *b) {
 
 // Workspace regions.
 struct Layout {
-    size_t key0, val0, key1, val1, hist, rng, counts, part, grec, queue, ckpt, ckpt_bytes, total;
+    size_t key0, val0, key1, val1, hist, rng, counts, part, pay, grec, queue, ckpt, ckpt_bytes, total;
 };
 
 int pick_px(int requested, int fallback) { return requested == 0 ? fallback : requested; }
@@ -195,6 +195,8 @@ Layout layout(const ivrgs_batch &b, const ivrgs_params &p) {
     off += align_up(sizeof(uint32_t) * (size_t)b.n_jobs * chunk_rows(b, chunk_of(p, b)) * k.tiles_per_job);
     L.part = off;
     off += align_up(sizeof(uint32_t) * col_part_words(b, k, chunk_of(p, b)));
+    L.pay = off;
+    off += align_up(2 * sizeof(uint4) * (size_t)b.n_records);
     L.grec = off;
     off += align_up(sizeof(float) * kGradStride * (size_t)b.n_records);
     L.queue = off;
@@ -461,6 +463,7 @@ ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params
     w.rng = reinterpret_cast<uint32_t *>(ws + L.rng);
     w.counts = reinterpret_cast<uint32_t *>(ws + L.counts);
     w.part = reinterpret_cast<uint32_t *>(ws + L.part);
+    w.pay = reinterpret_cast<uint4 *>(ws + L.pay);
     const int chunk = chunk_of(*params, *batch);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e = launch_bin_sort(*batch, k, proj->rec, proj->rect, proj->depth, *bins, w, chunk, dl.bin_lds, dl.cus, s);

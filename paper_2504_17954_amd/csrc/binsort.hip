@@ -354,22 +354,48 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Groups of 64 records start at begin, begin + stride, ... (stride 64: the
 // whole range in order; stride 64 * waves: the waves of a workgroup share it).
-template <typename F>
+// In depth order (order != nullptr) the records' binning fields are
+// gathered once, by the counting pass, which also stores them in depth order
+// (kPayWrite: 32 bytes per record, its rect and the fields of the ellipse-box
+// test), so the scatter reads them coalesced beside the ids (kPayRead).
+enum { kPayNone = 0, kPayWrite = 1, kPayRead = 2 };
+
+template <int kPay, typename F>
 __device__ __forceinline__ void for_each_pair(const ivrgs_job &job, int begin, int end, int stride,
-                                              const uint32_t *order, const float4 *rec4, const uint2 *rect,
-                                              ExpandLds &L, F &&f) {
+                                              const uint32_t *order, uint4 *pay, const float4 *rec4,
+                                              const uint2 *rect, ExpandLds &L, F &&f) {
     const int lane = threadIdx.x & 63;
     for (int g0 = begin; g0 < end; g0 += stride) {
         const int l = g0 + lane;
         uint32_t n = 0;
         if (l < end) {
-            const int64_t r = order ? (int64_t)order[(int64_t)job.rec_begin + l] : (int64_t)job.rec_begin + l;
-            const uint2 rc = rect[r];
+            const int64_t at = (int64_t)job.rec_begin + l;
+            const int64_t r = order ? (int64_t)order[at] : at;
+            uint2 rc;
+            float4 r0, r1, r2;
+            if (kPay == kPayRead && order) {
+                const uint4 pa = pay[2 * at], pb = pay[2 * at + 1];
+                rc = make_uint2(pa.x, pa.y);
+                r0 = make_float4(__uint_as_float(pa.z), __uint_as_float(pa.w), __uint_as_float(pb.x),
+                                 __uint_as_float(pb.y));
+                r1 = make_float4(__uint_as_float(pb.z), 0.f, 0.f, 0.f);
+                r2 = make_float4(0.f, 0.f, __uint_as_float(pb.w), 0.f);
+            } else {
+                rc = rect[r];
+                r0 = rec4[3 * r];
+                r1 = rec4[3 * r + 1];
+                r2 = rec4[3 * r + 2];
+                if (kPay == kPayWrite && order) {
+                    pay[2 * at] = make_uint4(rc.x, rc.y, __float_as_uint(r0.x), __float_as_uint(r0.y));
+                    pay[2 * at + 1] = make_uint4(__float_as_uint(r0.z), __float_as_uint(r0.w), __float_as_uint(r1.x),
+                                                 __float_as_uint(r2.z));
+                }
+            }
             if (rc.x | rc.y) {
                 int x0, y0, x1, y1;
                 unpack_rect(rc, x0, y0, x1, y1);
                 n = (uint32_t)((x1 - x0) * (y1 - y0));
-                const HitTest h = make_hit_test(rec4[3 * r], rec4[3 * r + 1], rec4[3 * r + 2]);
+                const HitTest h = make_hit_test(r0, r1, r2);
                 L.h0[lane] = make_float4(h.mx, h.my, h.qa, h.qb);
                 L.h1[lane] = make_float4(h.qc, h.i2qa, h.i2qc, h.tol);
                 L.org[lane] = rc.x;
@@ -427,6 +453,7 @@ __global__ __launch_bounds__(kBinWaves * 64) void k_chunk_count(ivrgs_batch b, C
                                                                 const uint32_t *__restrict__ val0,
                                                                 const uint32_t *__restrict__ val1,
                                                                 const uint32_t *__restrict__ rng,
+                                                                uint4 *__restrict__ pay,
                                                                 uint32_t *__restrict__ counts, int chunk,
                                                                 int n_chunks) {
     extern __shared__ uint32_t cnt[];  // [tiles]
@@ -440,7 +467,7 @@ __global__ __launch_bounds__(kBinWaves * 64) void k_chunk_count(ivrgs_batch b, C
     for (int t = threadIdx.x; t < tpj; t += kBinWaves * 64) cnt[t] = 0;
     __syncthreads();
     const uint32_t *order = depth_order(rng, b.n_jobs, blockIdx.y, val0, val1);
-    for_each_pair(job, begin + wave * 64, end, kBinWaves * 64, order, reinterpret_cast<const float4 *>(rec), rect,
+    for_each_pair<kPayWrite>(job, begin + wave * 64, end, kBinWaves * 64, order, pay, reinterpret_cast<const float4 *>(rec), rect,
                   L[wave], [&](uint32_t, int x, int y) { atomicAdd(&cnt[y * tx_n + x], 1u); });
     __syncthreads();
     uint32_t *row = counts + ((int64_t)blockIdx.y * n_chunks + blockIdx.x) * tpj;
@@ -573,6 +600,7 @@ __global__ __launch_bounds__(NW * 64) void k_scatter(ivrgs_batch b, Consts k, co
                                                      const uint32_t *__restrict__ val0,
                                                      const uint32_t *__restrict__ val1,
                                                      const uint32_t *__restrict__ rng,
+                                                     uint4 *__restrict__ pay,
                                                      const uint32_t *__restrict__ counts,
                                                      uint32_t *__restrict__ sorted, int chunk, int n_chunks,
                                                      const uint32_t *__restrict__ starts, int64_t n_tiles,
@@ -604,7 +632,7 @@ __global__ __launch_bounds__(NW * 64) void k_scatter(ivrgs_batch b, Consts k, co
         qe = min(qb + part, end);
         for (int t = threadIdx.x; t < NW * tpj; t += NW * 64) cur[t] = 0;
         __syncthreads();
-        for_each_pair(job, qb, qe, 64, order, rec4, rect, L[wave],
+        for_each_pair<kPayRead>(job, qb, qe, 64, order, pay, rec4, rect, L[wave],
                       [&](uint32_t, int x, int y) { atomicAdd(&c[y * tx_n + x], 1u); });
         __syncthreads();
         const uint32_t *row = counts + ((int64_t)blockIdx.y * n_chunks + blockIdx.x) * tpj;
@@ -630,7 +658,7 @@ __global__ __launch_bounds__(NW * 64) void k_scatter(ivrgs_batch b, Consts k, co
         }
     }
     __syncthreads();
-    for_each_pair(job, qb, qe, 64, order, rec4, rect, L[wave], [&](uint32_t r, int x, int y) {
+    for_each_pair<kPayRead>(job, qb, qe, 64, order, pay, rec4, rect, L[wave], [&](uint32_t r, int x, int y) {
         const uint32_t t = (uint32_t)(y * tx_n + x);
         const uint32_t at = c[t];  // read ahead of the match, which hides its latency
         const uint64_t m = match_bits<16>(t, tile_bits, __ballot(true));
@@ -717,12 +745,12 @@ static void launch_scatter(const ivrgs_batch &b, const Consts &k, const float *r
     const int64_t whole_bound = (int64_t)(n_chunks + NW - 1) / NW * b.n_jobs;
     if (NW > 1)
         hipLaunchKernelGGL((k_scatter<NW, true>), dim3((unsigned)n_chunks, (unsigned)b.n_jobs), dim3(NW * 64), lds, s,
-                           b, k, rec, rect2, w.val[0], w.val[1], w.rng, w.counts, bins.sorted, chunk, n_chunks,
-                           bins.tile_start, n_tiles, whole_min);
+                           b, k, rec, rect2, w.val[0], w.val[1], w.rng, w.pay, w.counts, bins.sorted, chunk,
+                           n_chunks, bins.tile_start, n_tiles, whole_min);
     if (NW == 1 || whole_bound >= whole_min)
         hipLaunchKernelGGL((k_scatter<NW, false>), dim3((unsigned)((n_chunks + NW - 1) / NW), (unsigned)b.n_jobs),
-                           dim3(NW * 64), lds, s, b, k, rec, rect2, w.val[0], w.val[1], w.rng, w.counts, bins.sorted,
-                           chunk, n_chunks, bins.tile_start, n_tiles, whole_min);
+                           dim3(NW * 64), lds, s, b, k, rec, rect2, w.val[0], w.val[1], w.rng, w.pay, w.counts,
+                           bins.sorted, chunk, n_chunks, bins.tile_start, n_tiles, whole_min);
 }
 
 hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *rec, const uint32_t *rect,
@@ -752,7 +780,7 @@ hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *r
         if (n_chunks > 0) {
             hipLaunchKernelGGL(k_chunk_count, dim3((unsigned)n_chunks, (unsigned)b.n_jobs), dim3(kBinWaves * 64),
                                sizeof(uint32_t) * (size_t)k.tiles_per_job, s, b, k, rec, rect2, w.val[0], w.val[1],
-                               w.rng, w.counts, chunk, n_chunks);
+                               w.rng, w.pay, w.counts, chunk, n_chunks);
             const int seg = col_segment(n_chunks), n_part = (n_chunks + seg - 1) / seg;
             const unsigned tg = (unsigned)((k.tiles_per_job + 255) / 256);
             hipLaunchKernelGGL(k_col_sum, dim3(tg, (unsigned)n_part, (unsigned)b.n_jobs), dim3(256), 0, s, b, k,

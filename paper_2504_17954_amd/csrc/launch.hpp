@@ -24,6 +24,7 @@ struct BinWork {
     uint32_t *rng;              // 2 * n_jobs
     uint32_t *counts;           // [job][chunk][tile]
     uint32_t *part;             // col_part_words: per-segment column sums
+    uint4 *pay;                 // 2 per record: binning fields in depth order
 };
 int chunk_rows(const ivrgs_batch &b, int chunk);
 size_t depth_sort_hist_words(const ivrgs_batch &b);
