@@ -85,46 +85,79 @@ __device__ __forceinline__ Step step(const Consts &k, float4 a, float4 c, float 
     return s;
 }
 
+// Forward: each wave owns an 8x8 quadrant of the tile and walks the list on
+// its own (no LDS, no barrier), 64 records per step: lane l holds record
+// base + l in registers (ids loaded two steps ahead, records and attributes
+// one step ahead, so the walk does not wait on the gathers), the
+// ellipse-box test against the quadrant picks the records to visit, and a
+// visited record's fields are broadcast from its lane.
 __global__ __launch_bounds__(kTilePix) void k_aux_fwd(ivrgs_batch b, Consts k, const float4 *__restrict__ rec,
                                                       const uint32_t *__restrict__ starts,
                                                       const uint32_t *__restrict__ sorted, int64_t n_tiles,
                                                       const float *__restrict__ attr, int n_attr,
                                                       float *__restrict__ aux) {
     if (starts[n_tiles] == 0xFFFFFFFFu) return;  // pair capacity exceeded: nothing is rendered
-    __shared__ AuxStage S;
     const int64_t tile = blockIdx.x;
     const int ji = (int)(tile / k.tiles_per_job), lt = (int)(tile % k.tiles_per_job);
     const ivrgs_job job = b.jobs[ji];
-    const int tx0 = (lt % k.tiles_x) * kTile, ty0 = (lt / k.tiles_x) * kTile;
-    const int x = tx0 + (threadIdx.x & (kTile - 1));
-    const int y = ty0 + threadIdx.x / kTile;
-    const uint32_t wave_bit = 1u << (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int sx = (lt % k.tiles_x) * kTile + 8 * (wave & 1), sy = (lt / k.tiles_x) * kTile + 8 * (wave >> 1);
+    const int x = sx + (lane & 7), y = sy + (lane >> 3);
     const bool inside = x < k.width && y < k.height;
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
     float T = 1.f, acc[1 + kAuxMax];
 #pragma unroll
     for (int c = 0; c < 1 + kAuxMax; ++c) acc[c] = 0.f;
     bool alive = inside;
-    const uint32_t beg = starts[tile], end = starts[tile + 1];
-    for (uint32_t base = beg; base < end; base += kAuxChunk) {
-        __syncthreads();  // the previous pass is consumed
-        if (threadIdx.x == 0) S.any_alive = 0;
-        stage(S, b, job, rec, sorted, base, end, attr, n_attr, tx0, ty0);
-        __syncthreads();
-        if (alive) S.any_alive = 1;
-        __syncthreads();
-        if (!S.any_alive) break;  // every pixel of the tile is done
-        const int cnt = (int)min((uint32_t)kAuxChunk, end - base);
-        for (int i = 0; i < cnt; ++i) {
-            if (__ballot(alive) == 0ull) break;  // this wave's pixels are done (it still meets the barriers)
-            if (!(S.wmask[i] & wave_bit)) continue;  // wave-uniform: cannot reach this wave's pixels
-            const Step s = step(k, S.s0[i], S.s1[i], px, py, T, alive);
-            if (s.comp) {
-                acc[0] = fmaf(s.w, S.s1[i].z, acc[0]);
+    const uint32_t start = starts[tile], end = starts[tile + 1];
+
+    float4 n0, n1, n2;
+    float na[kAuxMax];
+    uint32_t pid = 0;
+    auto load_ids = [&](uint32_t base) {
+        if (lane < (int)(end - base)) pid = sorted[base + lane];
+    };
+    auto load_recs = [&](uint32_t base) {
+        if (lane < (int)(end - base)) {
+            n0 = rec[3 * (size_t)pid];
+            n1 = rec[3 * (size_t)pid + 1];
+            n2 = rec[3 * (size_t)pid + 2];
+            const int64_t g = job_gaussian(job, b.gauss_index, (int)((int64_t)pid - job.rec_begin));
+#pragma unroll
+            for (int c = 0; c < kAuxMax; ++c)
+                if (c < n_attr) na[c] = attr[(int64_t)c * b.g.n + g];
+        }
+    };
+    auto bc = [](float v, int src) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src)); };
+    if (start < end) {
+        load_ids(start);
+        load_recs(start);
+        if (end - start > 64) load_ids(start + 64);
+    }
+    for (uint32_t base = start; base < end; base += 64) {
+        if (__ballot(alive) == 0ull) break;  // every pixel of the quadrant is done
+        const float4 r0 = n0, r1 = n1, r2 = n2;
+        float a[kAuxMax];
+#pragma unroll
+        for (int c = 0; c < kAuxMax; ++c) a[c] = na[c];
+        const bool touch = lane < (int)(end - base) && box_hit(make_hit_test(r0, r1, r2), sx, sy, 8, 8);
+        if (end - base > 64) load_recs(base + 64);
+        if (end - base > 128) load_ids(base + 128);
+        uint64_t m = __ballot(touch);
+        while (m) {
+            const int src = __builtin_ctzll(m);  // records in list order
+            m &= m - 1;
+            const float4 fa = make_float4(bc(r0.x, src), bc(r0.y, src), bc(r0.z, src), bc(r0.w, src));
+            const float4 fc = make_float4(bc(r1.x, src), bc(r1.y, src), bc(r2.y, src), bc(r2.z, src));
+            const Step s = step(k, fa, fc, px, py, T, alive);
+            if (__ballot(s.comp) != 0ull) {  // wave-uniform
+                acc[0] = fmaf(s.w, fc.z, acc[0]);
 #pragma unroll
                 for (int c = 0; c < kAuxMax; ++c)
-                    if (c < n_attr) acc[1 + c] = fmaf(s.w, S.sa[c][i], acc[1 + c]);
+                    if (c < n_attr) acc[1 + c] = fmaf(s.w, bc(a[c], src), acc[1 + c]);
             }
+            if (__ballot(alive) == 0ull) break;
         }
     }
     if (!inside) return;
