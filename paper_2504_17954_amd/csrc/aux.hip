@@ -225,37 +225,57 @@ __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, c
         __syncthreads();
         if (!S.any_alive) break;
         const int cnt = (int)min((uint32_t)kAuxChunk, end - base);
-        for (int i = 0; i < cnt; ++i) {
+        auto bc = [](float v, int src) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src)); };
+        // 64 staged records at a time into registers (lane l: record
+        // sub * 64 + l), one LDS round trip; the records reaching this wave's
+        // strip are then visited in order with their fields broadcast
+        for (int sub = 0; sub * 64 < cnt; ++sub) {
             if (__ballot(alive) == 0ull) break;  // this wave's pixels are done (it still meets the barriers)
-            if (!(S.wmask[i] & wave_bit)) continue;  // wave-uniform: cannot reach this wave's pixels
-            const float T0 = T;  // transmittance in front of this record
-            const Step s = step(k, S.s0[i], S.s1[i], px, py, T, alive);
-            if (__ballot(s.comp) == 0ull) continue;  // wave-uniform: nothing to add
-            float ga = g[0] * S.s1[i].z;
+            const int li = sub * 64 + lane;
+            const bool have = li < cnt;
+            const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 q0 = have ? S.s0[li] : z4, q1 = have ? S.s1[li] : z4;
+            float qa[kAuxMax];
 #pragma unroll
-            for (int c = 0; c < kAuxMax; ++c)
-                if (c < n_attr) ga = fmaf(g[1 + c], S.sa[c][i], ga);
-            gP = fmaf(s.w, ga, gP);
-            const float dA = s.comp ? T0 * ga - (gA - gP) / (1.f - s.al) : 0.f;
-            const float dLdo = s.raw <= k.alpha_max ? dA : 0.f;  // no gradient through alpha where the cap is active
-            const float dp = dLdo * s.raw;
-            float vals[kAuxAcc];
-            vals[0] = dLdo * s.G;        // GO
-            vals[1] = dp * s.dx;         // GX
-            vals[2] = dp * s.dy;         // GY
-            vals[3] = dp * s.dx * s.dx;  // GQA
-            vals[4] = dp * s.dx * s.dy;  // GQB
-            vals[5] = dp * s.dy * s.dy;  // GQC
+            for (int c = 0; c < kAuxMax; ++c) qa[c] = have && c < n_attr ? S.sa[c][li] : 0.f;
+            uint64_t visit = __ballot(have && (S.wmask[have ? li : 0] & wave_bit));
+            while (visit) {
+                const int src = __builtin_ctzll(visit);  // list order
+                visit &= visit - 1;
+                const int i = sub * 64 + src;  // position in the staged chunk
+                const float4 fa = make_float4(bc(q0.x, src), bc(q0.y, src), bc(q0.z, src), bc(q0.w, src));
+                const float4 fc = make_float4(bc(q1.x, src), bc(q1.y, src), bc(q1.z, src), bc(q1.w, src));
+                const float T0 = T;  // transmittance in front of this record
+                const Step s = step(k, fa, fc, px, py, T, alive);
+                if (__ballot(s.comp) != 0ull) {  // wave-uniform: something to add
+                    float ga = g[0] * fc.z;
 #pragma unroll
-            for (int c = 0; c < 1 + kAuxMax; ++c) vals[6 + c] = s.w * g[c];  // depth, then attributes
-            // one reduce-scatter for all the values: lanes 2m, 2m + 1 hold the
-            // wave total of value m
-            float v32[32];
+                    for (int c = 0; c < kAuxMax; ++c)
+                        if (c < n_attr) ga = fmaf(g[1 + c], bc(qa[c], src), ga);
+                    gP = fmaf(s.w, ga, gP);
+                    const float dA = s.comp ? T0 * ga - (gA - gP) / (1.f - s.al) : 0.f;
+                    const float dLdo = s.raw <= k.alpha_max ? dA : 0.f;  // no gradient through alpha where capped
+                    const float dp = dLdo * s.raw;
+                    float vals[kAuxAcc];
+                    vals[0] = dLdo * s.G;        // GO
+                    vals[1] = dp * s.dx;         // GX
+                    vals[2] = dp * s.dy;         // GY
+                    vals[3] = dp * s.dx * s.dx;  // GQA
+                    vals[4] = dp * s.dx * s.dy;  // GQB
+                    vals[5] = dp * s.dy * s.dy;  // GQC
 #pragma unroll
-            for (int v = 0; v < 32; ++v) v32[v] = v < kAuxAcc ? vals[v] : 0.f;
-            const float tot = reduce_scatter32(v32);
-            const int m = lane >> 1;
-            if ((lane & 1) == 0 && m < 6 + nv && tot != 0.f) atomicAdd(&acc[i][m], tot);
+                    for (int c = 0; c < 1 + kAuxMax; ++c) vals[6 + c] = s.w * g[c];  // depth, then attributes
+                    // one reduce-scatter for all the values: lanes 2v, 2v + 1
+                    // hold the wave total of value v
+                    float v32[32];
+#pragma unroll
+                    for (int v = 0; v < 32; ++v) v32[v] = v < kAuxAcc ? vals[v] : 0.f;
+                    const float tot = reduce_scatter32(v32);
+                    const int vi = lane >> 1;
+                    if ((lane & 1) == 0 && vi < 6 + nv && tot != 0.f) atomicAdd(&acc[i][vi], tot);
+                }
+                if (__ballot(alive) == 0ull) break;
+            }
         }
         __syncthreads();
         if ((int)threadIdx.x < cnt) {
