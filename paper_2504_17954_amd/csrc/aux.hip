@@ -3,13 +3,14 @@
 // Sec. 4.3 that the training regularisers read; and their backward, to the
 // attributes and, through alpha and the depth, to the geometry.
 //
-// One workgroup per 16x16 tile, one pixel per thread.  The tile's list is
-// staged through LDS 256 records at a time (record fields and the
-// attributes of their Gaussians), and every thread walks the staged records
-// in order with the forward's arithmetic, so the composited pairs are
-// exactly those of the image.  These maps belong to the training step of
-// the basic models, off the composed-scene hot path: the kernels favour a
-// direct structure over the render kernels' wave-level scheduling.
+// One workgroup per 16x16 tile, one pixel per thread, every pixel walking
+// its tile's list in order with the image forward's arithmetic, so the
+// composited pairs are exactly those of the image.  The forward runs each
+// wave on its own over its 8x8 quadrant with the records in registers.  The
+// backward stages the list through LDS 256 records at a time, so that the
+// four waves can sum each record's gradients in LDS before one set of global
+// atomics per workgroup; each wave takes the staged records 64 at a time
+// into registers.
 #include "launch.hpp"
 
 namespace ivrgs {
