@@ -114,3 +114,44 @@ def test_invalid_attribute_count(dev):
     with pytest.raises(ValueError):
         AX.render_aux(pd, torch.zeros((16, 20), device=dev), R.camera_table([cam]), R.Jobs.single(20),
                       R.Renderer(R.Settings(prm.width, prm.height)))
+
+
+def test_aux_two_jobs_with_overlapping_ranges(dev):
+    """Two jobs in one batch (two cameras, overlapping Gaussian ranges): the
+    maps of each job against the oracle of its camera and range, and the
+    gradients, accumulated over the jobs, against the summed autograd."""
+    n = 300
+    planes, cam0, prm = small(n, 44)
+    cam1 = I.look_at((-2.0, -3.0, 1.5), width=prm.width, height=prm.height)
+    attr = attributes(planes)
+    ranges = [(cam0, 0, n), (cam1, 80, n - 80)]
+    pt = D.to_tensors(planes, requires_grad=True)
+    at = torch.tensor(attr.astype(np.float64), requires_grad=True)
+    refs, Gs, oks = [], [], []
+    total = 0
+    for j, (cam, b0, cnt) in enumerate(ranges):
+        sub = {k: v[:, b0:b0 + cnt] for k, v in pt.items()}
+        sub_np = {k: np.ascontiguousarray(v[:, b0:b0 + cnt]) for k, v in planes.items()}
+        ok = O.render(sub_np, cam, prm)["flags"] == 0
+        _, _, _, ref = D.render(sub, cam.row(), prm, attr_t=at[:, b0:b0 + cnt])
+        G = np.random.default_rng(50 + j).normal(size=ref.shape) * ok[None]
+        total = total + (ref * torch.from_numpy(G)).sum()
+        refs.append(ref.detach().numpy())
+        Gs.append(G)
+        oks.append(ok)
+    total.backward()
+    say("aux maps, two jobs over overlapping ranges")
+    pd = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev).requires_grad_(True) for k, v in planes.items()}
+    ad = torch.from_numpy(attr).to(dev).requires_grad_(True)
+    jobs = R.Jobs.ranges([0, 1], [r[1] for r in ranges], [r[2] for r in ranges])
+    out = AX.render_aux(pd, ad, R.camera_table([cam0, cam1]), jobs, R.Renderer(R.Settings(prm.width, prm.height)))
+    for j in range(2):
+        got = out[j].detach().cpu().numpy()
+        scale = np.maximum(np.concatenate([[np.abs(refs[j][0]).max()], np.abs(attr).max(axis=1)]), 1.0)
+        err = np.abs(got - refs[j])[:, oks[j]].max(axis=1)
+        assert np.all(err <= 1e-4 * scale), (j, err)
+    G = torch.from_numpy(np.stack(Gs).astype(np.float32)).to(dev)
+    (out * G).sum().backward()
+    check_grad(ad.grad.cpu().numpy(), at.grad.numpy(), "d/dattr, two jobs")
+    for k in ("mean", "log_scale", "quat", "opacity"):
+        check_grad(pd[k].grad.cpu().numpy(), pt[k].grad.numpy(), f"d/d{k}, two jobs")
