@@ -507,6 +507,14 @@ ivrgs_status ivrgs_sh_color_bwd(const float *sh, int32_t degree, const float *me
  * 8 culler, 9 explore_opts, 10 vq_model. */
 int32_t ivrgs_struct_size(int32_t which);
 
+/* Device-side errors: waits for `stream`, then reads the device status word
+ * the last ivrgs_bin_sort on these bins wrote (bins->status[1]: a mask of
+ * IVRGS_DEV_E_* bits, 0 when none) into *device_error, and the pairs that
+ * sort required (bins->status[0]) into *pairs_required when not NULL.  The
+ * other entry points return host-side validation only and never wait. */
+ivrgs_status ivrgs_get_error(const ivrgs_bins *bins, void *stream, int64_t *device_error,
+                             int64_t *pairs_required);
+
 /* Human-readable name of a status code. */
 const char *ivrgs_status_string(ivrgs_status s);
 

@@ -609,6 +609,17 @@ int32_t ivrgs_struct_size(int32_t which) {
     }
 }
 
+ivrgs_status ivrgs_get_error(const ivrgs_bins *bins, void *stream, int64_t *device_error,
+                             int64_t *pairs_required) {
+    if (!bins || !bins->status || !device_error) return IVRGS_E_INVALID;
+    if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return IVRGS_E_HIP;
+    int64_t st[2] = {0, 0};
+    if (hipMemcpy(st, bins->status, sizeof st, hipMemcpyDeviceToHost) != hipSuccess) return IVRGS_E_HIP;
+    *device_error = st[1];
+    if (pairs_required) *pairs_required = st[0];
+    return IVRGS_OK;
+}
+
 const char *ivrgs_status_string(ivrgs_status s) {
     switch (s) {
     case IVRGS_OK: return "ok";

@@ -24,7 +24,8 @@ EXPORTS = ("ivrgs_workspace_size", "ivrgs_tiles_per_job", "ivrgs_compose", "ivrg
            "ivrgs_cull_workspace_size", "ivrgs_cull", "ivrgs_compose_bwd", "ivrgs_light_bwd",
            "ivrgs_compose_dev", "ivrgs_explore_state_words", "ivrgs_explore_step",
            "ivrgs_vq_workspace_size", "ivrgs_vq_fit", "ivrgs_vq_assign", "ivrgs_vq_compose",
-           "ivrgs_sh_color", "ivrgs_sh_color_bwd", "ivrgs_render_aux_fwd", "ivrgs_render_aux_bwd")
+           "ivrgs_sh_color", "ivrgs_sh_color_bwd", "ivrgs_render_aux_fwd", "ivrgs_render_aux_bwd",
+           "ivrgs_get_error")
 TIMING_KINDS = ("project", "tile_count", "scatter", "depth_sort", "render_fwd", "render_bwd",
                 "project_bwd", "compose", "fill", "cull", "edit_bwd", "vq", "sh", "aux")
 
@@ -156,6 +157,8 @@ def load(path: str = LIB_PATH):
     lib.ivrgs_render_aux_fwd.restype = C.c_int
     lib.ivrgs_render_aux_bwd.argtypes = [P, P, P, P, P, C.c_int32, P, P, P, P, P, C.c_size_t, P]
     lib.ivrgs_render_aux_bwd.restype = C.c_int
+    lib.ivrgs_get_error.argtypes = [P, P, P, P]
+    lib.ivrgs_get_error.restype = C.c_int
     lib.ivrgs_timing_enable.argtypes = [C.c_uint32]
     lib.ivrgs_timing_enable.restype = None
     lib.ivrgs_timing_read.argtypes = [P, P]
@@ -256,6 +259,15 @@ def ivrgs_render_aux_bwd(batch, params, proj, bins, attr_ptr, n_attr: int, aux_p
     check(load().ivrgs_render_aux_bwd(ref(batch), ref(params), ref(proj), ref(bins), attr_ptr, n_attr, aux_ptr,
                                       grad_aux_ptr, grad_attr_ptr, ref(grads), ws_ptr, ws_bytes, stream),
           "ivrgs_render_aux_bwd")
+
+
+def ivrgs_get_error(bins, stream) -> tuple[int, int]:
+    """(device error bits, pairs required) of the last bin sort on these bins
+    (waits for the stream)."""
+    err, need = C.c_int64(0), C.c_int64(0)
+    check(load().ivrgs_get_error(ref(bins), stream, C.cast(C.byref(err), C.c_void_p),
+                                 C.cast(C.byref(need), C.c_void_p)), "ivrgs_get_error")
+    return int(err.value), int(need.value)
 
 
 def ivrgs_project(batch, params, proj, stream):

@@ -305,11 +305,15 @@ class Renderer:
         return out
 
     def verify(self):
-        """Raise if the last binning overflowed the pair capacity (syncs)."""
-        st = self.status.cpu()
-        if int(st[1]) & N.DEV_E_CAPACITY:
-            raise N.IvrgsError(f"pair capacity {self.capacity} exceeded: {int(st[0])} pairs needed")
-        return int(st[0])
+        """Raise if the last binning overflowed the pair capacity (waits for
+        the stream); else return the pairs it required."""
+        bins = N.ivrgs_bins(self.tile_start.data_ptr(), _ptr(self.sorted), self.capacity, self.status.data_ptr())
+        err, need = N.ivrgs_get_error(bins, _stream())
+        if err & N.DEV_E_CAPACITY:
+            raise N.IvrgsError(f"pair capacity {self.capacity} exceeded: {need} pairs needed")
+        if err:
+            raise N.IvrgsError(f"device error bits {err:#x}")
+        return need
 
     def pairs(self) -> int:
         return int(self.status[0].item())

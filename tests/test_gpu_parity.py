@@ -282,12 +282,16 @@ def test_capacity_overflow_regrows(dev):
     rgba = rnd.forward(to_dev(planes, dev), R.camera_table([cam]), R.Jobs.single(10_000),
                        edits_t=R.default_edits(dev))[0].cpu().numpy()
     assert rnd.capacity > 1000
+    assert N.ivrgs_get_error(rnd._structs(None)[1], R._stream()) == (0, rnd.pairs())
+    assert 1000 < rnd.verify() <= rnd.capacity
     ref = O.render(planes, cam, prm)
     check_image(rgba, ref, "after capacity regrow")
     # deferred mode reports the overflow instead of fixing it
     rnd2 = R.Renderer(R.Settings(128, 128), capacity=1000, check="defer")
     rnd2.forward(to_dev(planes, dev), R.camera_table([cam]), R.Jobs.single(10_000),
                  edits_t=R.default_edits(dev))
+    err, need = N.ivrgs_get_error(rnd2._structs(None)[1], R._stream())
+    assert err == N.DEV_E_CAPACITY and need == rnd.pairs()
     with pytest.raises(N.IvrgsError):
         rnd2.verify()
 
