@@ -56,6 +56,31 @@ __device__ __forceinline__ uint64_t match_bits(uint32_t v, int nbits, uint64_t a
     return (uint64_t)hi << 32 | lo;
 }
 
+// Inclusive prefix maximum over the lanes of a wave, for values >= -1 (a lane
+// with no source in a step takes -1): DPP shifts within each row of 16,
+// then row_bcast15 / row_bcast31 carry the row maxima into the later rows.
+__device__ __forceinline__ int wave_prefix_max(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xF, 0xF, false));  // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xF, 0xF, false));  // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xF, 0xF, false));  // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xF, 0xF, false));  // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xA, 0xF, false));  // row_bcast15 -> rows 1, 3
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xC, 0xF, false));  // row_bcast31 -> rows 2, 3
+    return v;
+}
+
+// Inclusive prefix sum over the lanes of a wave, with the same DPP steps.
+__device__ __forceinline__ uint32_t wave_prefix_sum(uint32_t u) {
+    int v = (int)u;
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);
+    return (uint32_t)v;
+}
+
 // ---------------------------------------------------------------------------
 // Depth order.
 constexpr int kSegThreads = 256;
@@ -188,7 +213,9 @@ __device__ uint64_t block_exclusive_scan_1024(uint64_t v, uint64_t *tmp /* >= 16
 
 // Per (job, digit), one wave: exclusive scan of the digit's counts over the
 // job's segments (contiguous, in place) and the digit's total into
-// tot[job][digit].
+// tot[job][digit].  The counts of up to kColBlock x 64 segments are loaded
+// before any is scanned, so a column pays one load latency per block.
+constexpr int kColBlock = 16;
 __global__ __launch_bounds__(256) void k_dsort_colscan(ivrgs_batch b, const uint32_t *__restrict__ rng, int shift,
                                                        uint32_t *__restrict__ hist, uint32_t *__restrict__ tot,
                                                        int n_seg) {
@@ -199,17 +226,21 @@ __global__ __launch_bounds__(256) void k_dsort_colscan(ivrgs_batch b, const uint
     if (rows == 0 || !digit_varies(rng, b.n_jobs, blockIdx.y, shift)) return;
     uint32_t *col = hist + ((int64_t)blockIdx.y * 256 + d) * n_seg;
     uint32_t carry = 0;
-    for (int base = 0; base < rows; base += 64) {
-        const int c = base + lane;
-        const uint32_t v = c < rows ? col[c] : 0u;
-        uint32_t incl = v;
+    for (int base = 0; base < rows; base += 64 * kColBlock) {
+        uint32_t v[kColBlock];
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t u = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += u;
+        for (int u = 0; u < kColBlock; ++u) {
+            const int c = base + u * 64 + lane;
+            v[u] = c < rows ? col[c] : 0u;
         }
-        if (c < rows) col[c] = carry + incl - v;
-        carry += __shfl(incl, 63, 64);
+#pragma unroll
+        for (int u = 0; u < kColBlock; ++u) {
+            if (base + u * 64 >= rows) break;  // wave-uniform
+            const uint32_t incl = wave_prefix_sum(v[u]);
+            const int c = base + u * 64 + lane;
+            if (c < rows) col[c] = carry + incl - v[u];
+            carry += __builtin_amdgcn_readlane(incl, 63);
+        }
     }
     if (lane == 0) tot[(int64_t)blockIdx.y * 256 + d] = carry;
 }
@@ -319,31 +350,6 @@ struct ExpandLds {
     int32_t mark[64];       // record starting at each position of the current item window, or -1
 };
 constexpr int kBinWaves = 4;  // waves per binning workgroup (sharing one chunk)
-
-// Inclusive prefix maximum over the lanes of a wave, for values >= -1 (a lane
-// with no source in a step takes -1): DPP shifts within each row of 16,
-// then row_bcast15 / row_bcast31 carry the row maxima into the later rows.
-__device__ __forceinline__ int wave_prefix_max(int v) {
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xF, 0xF, false));  // row_shr:1
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xF, 0xF, false));  // row_shr:2
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xF, 0xF, false));  // row_shr:4
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xF, 0xF, false));  // row_shr:8
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xA, 0xF, false));  // row_bcast15 -> rows 1, 3
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xC, 0xF, false));  // row_bcast31 -> rows 2, 3
-    return v;
-}
-
-// Inclusive prefix sum over the lanes of a wave, with the same DPP steps.
-__device__ __forceinline__ uint32_t wave_prefix_sum(uint32_t u) {
-    int v = (int)u;
-    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);
-    return (uint32_t)v;
-}
 
 // Orders a wave's LDS writes before its other lanes' reads.
 __device__ __forceinline__ void wave_lds_sync() {
