@@ -473,6 +473,28 @@ ivrgs_status ivrgs_render_aux_bwd(const ivrgs_batch *batch, const ivrgs_params *
                                   ivrgs_gaussians_mut *grads, void *workspace, size_t workspace_bytes,
                                   void *stream);
 
+/* ---- SSIM term of the photometric loss (Sec. 4.2; appendix weights) -------
+ * Structural similarity of an image x against a target y, both device
+ * [channels][height][width] float32, contiguous: per channel, every valid
+ * 11x11 window (its top-left corner in [0, height - 10) x [0, width - 10))
+ * with Gaussian weights of sigma 1.5 normalised to 1, and the constants
+ * C1 = 0.01^2, C2 = 0.03^2 (values in [0, 1]); the result is the mean over
+ * windows and channels.  height and width must be at least 11
+ * (IVRGS_E_SHAPE otherwise).  The forward stores per-window partial
+ * derivatives in the workspace, which the backward reads: keep the
+ * workspace unchanged between the two calls.  Deterministic. */
+size_t ivrgs_ssim_workspace_size(int32_t channels, int32_t height, int32_t width);
+
+/* out_mean: device float, the mean SSIM. */
+ivrgs_status ivrgs_ssim_fwd(const float *x, const float *y, int32_t channels, int32_t height, int32_t width,
+                            float *out_mean, void *workspace, size_t workspace_bytes, void *stream);
+
+/* grad_mean: device float, dL/d(mean SSIM); grad_x: device, the layout of x,
+ * overwritten with dL/dx.  The target gets no gradient. */
+ivrgs_status ivrgs_ssim_bwd(const float *x, const float *y, int32_t channels, int32_t height, int32_t width,
+                            const float *grad_mean, float *grad_x, const void *workspace, size_t workspace_bytes,
+                            void *stream);
+
 /* ---- SH colour (base 3DGS, Sec. 3 and Sec. 4.2) ---------------------------
  * The base model's view-dependent colour is parameterised by spherical-
  * harmonic coefficients, as in the original 3DGS; the paper gives no degree

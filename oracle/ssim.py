@@ -65,4 +65,4 @@ def ssim_and_grad(x: np.ndarray, y: np.ndarray) -> tuple[float, np.ndarray]:
     xt = torch.tensor(np.asarray(x, np.float64), requires_grad=True)
     s = ssim_map(xt, torch.as_tensor(np.asarray(y, np.float64))).mean()
     s.backward()
-    return float(s), xt.grad.numpy()
+    return float(s.detach()), xt.grad.numpy()

@@ -374,6 +374,34 @@ ivrgs_status ivrgs_sh_color_bwd(const float *sh, int32_t degree, const float *me
                                           reinterpret_cast<hipStream_t>(stream)));
 }
 
+static bool ssim_shape_ok(int32_t c, int32_t h, int32_t w) {
+    return c >= 1 && h >= kSsimWindow && w >= kSsimWindow && c <= 65535 && (int64_t)h * w <= (int64_t)1 << 31;
+}
+
+size_t ivrgs_ssim_workspace_size(int32_t channels, int32_t height, int32_t width) {
+    if (!ssim_shape_ok(channels, height, width)) return 0;
+    return sizeof(float) * ssim_workspace_floats(channels, height, width);
+}
+
+ivrgs_status ivrgs_ssim_fwd(const float *x, const float *y, int32_t channels, int32_t height, int32_t width,
+                            float *out_mean, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!x || !y || !out_mean || !workspace) return IVRGS_E_INVALID;
+    if (!ssim_shape_ok(channels, height, width)) return IVRGS_E_SHAPE;
+    if (workspace_bytes < ivrgs_ssim_workspace_size(channels, height, width)) return IVRGS_E_CAPACITY;
+    return hip_status(launch_ssim_fwd(x, y, channels, height, width, out_mean, static_cast<float *>(workspace),
+                                      reinterpret_cast<hipStream_t>(stream)));
+}
+
+ivrgs_status ivrgs_ssim_bwd(const float *x, const float *y, int32_t channels, int32_t height, int32_t width,
+                            const float *grad_mean, float *grad_x, const void *workspace, size_t workspace_bytes,
+                            void *stream) {
+    if (!x || !y || !grad_mean || !grad_x || !workspace) return IVRGS_E_INVALID;
+    if (!ssim_shape_ok(channels, height, width)) return IVRGS_E_SHAPE;
+    if (workspace_bytes < ivrgs_ssim_workspace_size(channels, height, width)) return IVRGS_E_CAPACITY;
+    return hip_status(launch_ssim_bwd(x, y, channels, height, width, grad_mean, grad_x,
+                                      static_cast<const float *>(workspace), reinterpret_cast<hipStream_t>(stream)));
+}
+
 int64_t ivrgs_explore_state_words(int32_t n_models) {
     if (n_models <= 0) return 0;
     return 3 * (4 * (int64_t)n_models + 10) + 1;

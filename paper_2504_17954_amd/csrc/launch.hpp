@@ -97,6 +97,19 @@ hipError_t launch_aux_bwd(const ivrgs_batch &b, const Consts &k, int64_t n_tiles
                           const uint32_t *starts, const uint32_t *sorted, const float *attr, int n_attr,
                           const float *aux, const float *grad_aux, float *grec, float *grad_attr, float *grad_mean,
                           hipStream_t s);
+
+// SSIM of an image against its target over valid 11x11 Gaussian windows
+// (sigma 1.5), and its gradient with respect to the image.
+constexpr int kSsimWindow = 11;
+struct SsimTaps {
+    float w[kSsimWindow];
+};
+SsimTaps ssim_taps();
+size_t ssim_workspace_floats(int channels, int H, int W);
+hipError_t launch_ssim_fwd(const float *x, const float *y, int channels, int H, int W, float *out, float *ws,
+                           hipStream_t s);
+hipError_t launch_ssim_bwd(const float *x, const float *y, int channels, int H, int W, const float *grad_mean,
+                           float *grad_x, const float *ws, hipStream_t s);
 hipError_t launch_work_queue(const uint32_t *starts, int64_t n_tiles, uint32_t *queue, hipStream_t s);
 
 }  // namespace ivrgs

@@ -1,0 +1,229 @@
+// Structural similarity of a rendered image against its target, the second
+// term of the photometric loss (Sec. 4.2; weights in the appendix), and its
+// gradient with respect to the rendered image.
+//
+// Per channel, every valid 11x11 window p (top-left corner, Ho x Wo of them)
+// carries Gaussian-weighted moments mx, my, Exx, Eyy, Exy (weights
+// g[i] g[j], sigma 1.5, normalised).  With sxx = Exx - mx^2 and likewise
+//   S(p) = (2 mx my + C1)(2 sxy + C2) / ((mx^2 + my^2 + C1)(sxx + syy + C2)),
+// and the loss term is the mean of S over windows and channels.  Writing
+// N1, N2, D1, D2 for the four factors, the partial derivatives of S(p) are
+//   dS/dmx  = (2 my (N2 - N1)) / (D1 D2) + 2 mx S (1/D2 - 1/D1)   (= A),
+//   dS/dExx = -S / D2                                              (= B),
+//   dS/dExy = 2 N1 / (D1 D2)                                       (= C),
+// so the gradient at pixel q is the transposed window sum
+//   dmean/dx_q = (sum_p w(q - p) [A(p) + 2 x_q B(p) + y_q C(p)]) / (channels Ho Wo).
+// No factor divides by N1 or N2, which may vanish.
+//
+// Both kernels are separable stencils over 16x16 output tiles: the 26x26
+// input region (the tile plus the window's 10-pixel halo) is staged in LDS,
+// a horizontal 11-tap pass writes 26 x 16 row sums to LDS, and each thread
+// finishes one output with the vertical pass.  The forward keeps A, B, C per
+// window in the workspace for the backward and one partial sum of S per
+// workgroup; a single workgroup adds the partials in a fixed order (FP64),
+// so the result does not depend on scheduling.  Bound: HBM (the image and
+// target read once, 12 B per window written, read back once).
+#include <cmath>
+
+#include "launch.hpp"
+
+namespace ivrgs {
+
+namespace {
+
+constexpr int kSsimTile = 16;
+constexpr int kWin = kSsimWindow;          // 11
+constexpr int kReg = kSsimTile + kWin - 1;     // 26: tile plus halo
+constexpr float kC1 = 0.01f * 0.01f, kC2 = 0.03f * 0.03f;
+
+__global__ __launch_bounds__(256) void k_ssim_fwd(const float *__restrict__ x, const float *__restrict__ y, int H,
+                                                  int W, SsimTaps taps, float *__restrict__ abc,
+                                                  float *__restrict__ partial) {
+    __shared__ float sx[kReg][kReg + 1], sy[kReg][kReg + 1];
+    __shared__ float hs[5][kReg][kSsimTile];
+    __shared__ float wsum[4];
+    const int Ho = H - kWin + 1, Wo = W - kWin + 1;
+    const int ox0 = blockIdx.x * kSsimTile, oy0 = blockIdx.y * kSsimTile, c = blockIdx.z;
+    const int64_t plane = (int64_t)H * W;
+    const float *xc = x + c * plane, *yc = y + c * plane;
+    const int t = threadIdx.x;
+    for (int i = t; i < kReg * kReg; i += 256) {
+        const int r = i / kReg, q = i - r * kReg;
+        const int gy = oy0 + r, gx = ox0 + q;
+        const bool ok = gy < H && gx < W;
+        sx[r][q] = ok ? xc[(int64_t)gy * W + gx] : 0.0f;
+        sy[r][q] = ok ? yc[(int64_t)gy * W + gx] : 0.0f;
+    }
+    __syncthreads();
+    for (int i = t; i < kReg * kSsimTile; i += 256) {
+        const int r = i / kSsimTile, q = i - r * kSsimTile;
+        float a = 0, b = 0, aa = 0, bb = 0, ab = 0;
+#pragma unroll
+        for (int k = 0; k < kWin; ++k) {
+            const float u = sx[r][q + k], v = sy[r][q + k], g = taps.w[k];
+            a = fmaf(g, u, a);
+            b = fmaf(g, v, b);
+            aa = fmaf(g, u * u, aa);
+            bb = fmaf(g, v * v, bb);
+            ab = fmaf(g, u * v, ab);
+        }
+        hs[0][r][q] = a;
+        hs[1][r][q] = b;
+        hs[2][r][q] = aa;
+        hs[3][r][q] = bb;
+        hs[4][r][q] = ab;
+    }
+    __syncthreads();
+    const int ty = t / kSsimTile, tx = t - ty * kSsimTile;
+    const int oy = oy0 + ty, ox = ox0 + tx;
+    float m[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < kWin; ++k) {
+        const float g = taps.w[k];
+#pragma unroll
+        for (int s = 0; s < 5; ++s) m[s] = fmaf(g, hs[s][ty + k][tx], m[s]);
+    }
+    float S = 0.0f;
+    if (oy < Ho && ox < Wo) {
+        const float mx = m[0], my = m[1];
+        const float sxx = m[2] - mx * mx, syy = m[3] - my * my, sxy = m[4] - mx * my;
+        const float N1 = 2.0f * mx * my + kC1, N2 = 2.0f * sxy + kC2;
+        const float D1 = mx * mx + my * my + kC1, D2 = sxx + syy + kC2;
+        const float D = D1 * D2;
+        S = N1 * N2 / D;
+        const float A = 2.0f * my * (N2 - N1) / D + 2.0f * mx * S * (1.0f / D2 - 1.0f / D1);
+        const float B = -S / D2;
+        const float C = 2.0f * N1 / D;
+        const int64_t wp = (int64_t)Ho * Wo, at = (int64_t)oy * Wo + ox;
+        float *o = abc + (int64_t)c * 3 * wp;
+        o[at] = A;
+        o[wp + at] = B;
+        o[2 * wp + at] = C;
+    }
+    // workgroup sum of S, lanes then waves in a fixed order
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) S += __shfl_xor(S, d, 64);
+    if ((t & 63) == 0) wsum[t >> 6] = S;
+    __syncthreads();
+    if (t == 0)
+        partial[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] =
+            ((wsum[0] + wsum[1]) + (wsum[2] + wsum[3]));
+}
+
+// One workgroup: the partials in a fixed order (FP64), divided by the
+// number of windows.
+__global__ __launch_bounds__(256) void k_ssim_reduce(const float *__restrict__ partial, int64_t n, double inv,
+                                                     float *__restrict__ out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) s += (double)partial[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = (float)(red[0] * inv);
+}
+
+// Pixel tile [qy0, qy0 + 16) x [qx0, qx0 + 16): the windows that cover it
+// have corners in [q0 - 10, q0 + 15]; corners outside [0, Ho) x [0, Wo)
+// contribute zero.  The taps are symmetric (g[k] = g[10 - k]), so the
+// transposed sum over corners p = q - k with weight g[k] is the same
+// forward 11-tap sum over the staged region.
+__global__ __launch_bounds__(256) void k_ssim_bwd(const float *__restrict__ x, const float *__restrict__ y, int H,
+                                                  int W, SsimTaps taps, const float *__restrict__ abc,
+                                                  const float *__restrict__ grad_mean, double inv,
+                                                  float *__restrict__ grad_x) {
+    __shared__ float sa[3][kReg][kReg + 1];
+    __shared__ float hs[3][kReg][kSsimTile];
+    const int Ho = H - kWin + 1, Wo = W - kWin + 1;
+    const int qx0 = blockIdx.x * kSsimTile, qy0 = blockIdx.y * kSsimTile, c = blockIdx.z;
+    const int64_t wp = (int64_t)Ho * Wo;
+    const float *ac = abc + (int64_t)c * 3 * wp;
+    const int t = threadIdx.x;
+    for (int i = t; i < kReg * kReg; i += 256) {
+        const int r = i / kReg, q = i - r * kReg;
+        const int py = qy0 - (kWin - 1) + r, px = qx0 - (kWin - 1) + q;
+        const bool ok = py >= 0 && py < Ho && px >= 0 && px < Wo;
+        const int64_t at = (int64_t)py * Wo + px;
+        sa[0][r][q] = ok ? ac[at] : 0.0f;
+        sa[1][r][q] = ok ? ac[wp + at] : 0.0f;
+        sa[2][r][q] = ok ? ac[2 * wp + at] : 0.0f;
+    }
+    __syncthreads();
+    for (int i = t; i < kReg * kSsimTile; i += 256) {
+        const int r = i / kSsimTile, q = i - r * kSsimTile;
+        float s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+        for (int k = 0; k < kWin; ++k) {
+            const float g = taps.w[k];
+            s0 = fmaf(g, sa[0][r][q + k], s0);
+            s1 = fmaf(g, sa[1][r][q + k], s1);
+            s2 = fmaf(g, sa[2][r][q + k], s2);
+        }
+        hs[0][r][q] = s0;
+        hs[1][r][q] = s1;
+        hs[2][r][q] = s2;
+    }
+    __syncthreads();
+    const int ty = t / kSsimTile, tx = t - ty * kSsimTile;
+    const int qy = qy0 + ty, qx = qx0 + tx;
+    if (qy >= H || qx >= W) return;
+    float bA = 0, bB = 0, bC = 0;
+#pragma unroll
+    for (int k = 0; k < kWin; ++k) {
+        const float g = taps.w[k];
+        bA = fmaf(g, hs[0][ty + k][tx], bA);
+        bB = fmaf(g, hs[1][ty + k][tx], bB);
+        bC = fmaf(g, hs[2][ty + k][tx], bC);
+    }
+    const int64_t at = (int64_t)c * H * W + (int64_t)qy * W + qx;
+    const float xq = x[at], yq = y[at];
+    const float scale = (float)((double)grad_mean[0] * inv);
+    grad_x[at] = scale * (bA + 2.0f * xq * bB + yq * bC);
+}
+
+}  // namespace
+
+SsimTaps ssim_taps() {
+    // g[k] = exp(-(k - 5)^2 / (2 * 1.5^2)), normalised in FP64, then rounded
+    SsimTaps t;
+    double g[kWin], s = 0.0;
+    for (int k = 0; k < kWin; ++k) {
+        const double d = k - (kWin - 1) / 2;
+        g[k] = std::exp(-d * d / (2.0 * 1.5 * 1.5));
+        s += g[k];
+    }
+    for (int k = 0; k < kWin; ++k) t.w[k] = (float)(g[k] / s);
+    return t;
+}
+
+size_t ssim_workspace_floats(int channels, int H, int W) {
+    const int64_t Ho = H - kWin + 1, Wo = W - kWin + 1;
+    const int64_t blocks = (int64_t)channels * ((Ho + kSsimTile - 1) / kSsimTile) * ((Wo + kSsimTile - 1) / kSsimTile);
+    return (size_t)(3 * channels * Ho * Wo + blocks);
+}
+
+hipError_t launch_ssim_fwd(const float *x, const float *y, int channels, int H, int W, float *out, float *ws,
+                           hipStream_t s) {
+    const int Ho = H - kWin + 1, Wo = W - kWin + 1;
+    const dim3 grid((Wo + kSsimTile - 1) / kSsimTile, (Ho + kSsimTile - 1) / kSsimTile, channels);
+    float *abc = ws, *partial = ws + (size_t)3 * channels * Ho * Wo;
+    hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, s, x, y, H, W, ssim_taps(), abc, partial);
+    const int64_t n = (int64_t)grid.x * grid.y * grid.z;
+    hipLaunchKernelGGL(k_ssim_reduce, dim3(1), dim3(256), 0, s, partial, n,
+                       1.0 / ((double)channels * Ho * Wo), out);
+    return hipGetLastError();
+}
+
+hipError_t launch_ssim_bwd(const float *x, const float *y, int channels, int H, int W, const float *grad_mean,
+                           float *grad_x, const float *ws, hipStream_t s) {
+    const int Ho = H - kWin + 1, Wo = W - kWin + 1;
+    const dim3 grid((W + kSsimTile - 1) / kSsimTile, (H + kSsimTile - 1) / kSsimTile, channels);
+    hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, s, x, y, H, W, ssim_taps(), ws, grad_mean,
+                       1.0 / ((double)channels * Ho * Wo), grad_x);
+    return hipGetLastError();
+}
+
+}  // namespace ivrgs

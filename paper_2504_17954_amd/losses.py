@@ -16,7 +16,9 @@ scaled by 0.1, and the normal consistency and the other regularisers by
 
 Readings where the paper is silent: SSIM after Wang et al. (2004), an 11x11
 Gaussian window of sigma 1.5, C1 = 0.01^2, C2 = 0.03^2, averaged over the
-windows that lie inside the image; depth and normal maps are divided by the
+windows that lie inside the image (on the device: the HIP kernels behind
+ivrgs_ssim_fwd / ivrgs_ssim_bwd, the target taken as a constant; the torch
+form below serves CPU tensors); depth and normal maps are divided by the
 alpha map before use (pixels with alpha <= 0.5 are left out); the
 pseudo-normal is the cross product of the central differences of the
 back-projected points, turned to face the camera and taken to world space;
@@ -28,6 +30,8 @@ from __future__ import annotations
 import torch
 import torch.nn.functional as F
 
+from . import native as N
+
 
 def _gauss_window(size: int, sigma: float, dtype, device):
     x = torch.arange(size, dtype=dtype, device=device) - (size - 1) / 2
@@ -35,8 +39,46 @@ def _gauss_window(size: int, sigma: float, dtype, device):
     return g / g.sum()
 
 
+class _SsimFn(torch.autograd.Function):
+    """Mean SSIM of a device image against a constant target: argument
+    marshalling around the HIP kernels (the forward keeps per-window partial
+    derivatives in its workspace for the backward)."""
+
+    @staticmethod
+    def forward(ctx, x, y):
+        from .raster import _stream
+        c, h, w = (int(v) for v in x.shape)
+        nbytes = N.ivrgs_ssim_workspace_size(c, h, w)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+        out = torch.empty((), dtype=torch.float32, device=x.device)
+        N.ivrgs_ssim_fwd(x.data_ptr(), y.data_ptr(), c, h, w, out.data_ptr(), ws.data_ptr(), nbytes, _stream())
+        ctx.save_for_backward(x, y, ws)
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        from .raster import _stream
+        x, y, ws = ctx.saved_tensors
+        c, h, w = (int(v) for v in x.shape)
+        gx = torch.empty_like(x)
+        g = g.to(torch.float32).contiguous()
+        N.ivrgs_ssim_bwd(x.data_ptr(), y.data_ptr(), c, h, w, g.data_ptr(), gx.data_ptr(), ws.data_ptr(),
+                         ws.numel(), _stream())
+        return gx, None
+
+
 def ssim(x: torch.Tensor, y: torch.Tensor, window: int = 11, sigma: float = 1.5) -> torch.Tensor:
-    """Mean SSIM of two images [C, H, W] with values in [0, 1]."""
+    """Mean SSIM of two images [C, H, W] with values in [0, 1].  Device
+    tensors go through the HIP kernels (float32, 11x11 window of sigma 1.5;
+    no gradient to the target)."""
+    if x.is_cuda:
+        if window != 11 or sigma != 1.5:
+            raise ValueError("the device SSIM takes the 11x11 window of sigma 1.5")
+        if x.dim() != 3 or y.shape != x.shape or x.dtype != torch.float32 or y.dtype != torch.float32:
+            raise ValueError("ssim: expected float32 [C, H, W] image and target of one shape")
+        if x.shape[1] < 11 or x.shape[2] < 11:
+            raise ValueError("ssim: height and width must be at least 11")
+        return _SsimFn.apply(x.contiguous(), y.detach().contiguous())
     c = x.shape[0]
     g = _gauss_window(window, sigma, x.dtype, x.device)
     wx = g.view(1, 1, 1, window).expand(c, 1, 1, window)

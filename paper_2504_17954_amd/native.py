@@ -25,7 +25,7 @@ EXPORTS = ("ivrgs_workspace_size", "ivrgs_tiles_per_job", "ivrgs_compose", "ivrg
            "ivrgs_compose_dev", "ivrgs_explore_state_words", "ivrgs_explore_step",
            "ivrgs_vq_workspace_size", "ivrgs_vq_fit", "ivrgs_vq_assign", "ivrgs_vq_compose",
            "ivrgs_sh_color", "ivrgs_sh_color_bwd", "ivrgs_render_aux_fwd", "ivrgs_render_aux_bwd",
-           "ivrgs_get_error")
+           "ivrgs_get_error", "ivrgs_ssim_workspace_size", "ivrgs_ssim_fwd", "ivrgs_ssim_bwd")
 TIMING_KINDS = ("project", "tile_count", "scatter", "depth_sort", "render_fwd", "render_bwd",
                 "project_bwd", "compose", "fill", "cull", "edit_bwd", "vq", "sh", "aux")
 
@@ -157,6 +157,13 @@ def load(path: str = LIB_PATH):
     lib.ivrgs_render_aux_fwd.restype = C.c_int
     lib.ivrgs_render_aux_bwd.argtypes = [P, P, P, P, P, C.c_int32, P, P, P, P, P, C.c_size_t, P]
     lib.ivrgs_render_aux_bwd.restype = C.c_int
+    I32 = C.c_int32
+    lib.ivrgs_ssim_workspace_size.argtypes = [I32, I32, I32]
+    lib.ivrgs_ssim_workspace_size.restype = C.c_size_t
+    lib.ivrgs_ssim_fwd.argtypes = [P, P, I32, I32, I32, P, P, C.c_size_t, P]
+    lib.ivrgs_ssim_fwd.restype = C.c_int
+    lib.ivrgs_ssim_bwd.argtypes = [P, P, I32, I32, I32, P, P, P, C.c_size_t, P]
+    lib.ivrgs_ssim_bwd.restype = C.c_int
     lib.ivrgs_get_error.argtypes = [P, P, P, P]
     lib.ivrgs_get_error.restype = C.c_int
     lib.ivrgs_timing_enable.argtypes = [C.c_uint32]
@@ -268,6 +275,21 @@ def ivrgs_get_error(bins, stream) -> tuple[int, int]:
     check(load().ivrgs_get_error(ref(bins), stream, C.cast(C.byref(err), C.c_void_p),
                                  C.cast(C.byref(need), C.c_void_p)), "ivrgs_get_error")
     return int(err.value), int(need.value)
+
+
+def ivrgs_ssim_workspace_size(channels: int, height: int, width: int) -> int:
+    return int(load().ivrgs_ssim_workspace_size(channels, height, width))
+
+
+def ivrgs_ssim_fwd(x_ptr, y_ptr, channels: int, height: int, width: int, out_ptr, ws_ptr, ws_bytes, stream):
+    check(load().ivrgs_ssim_fwd(x_ptr, y_ptr, channels, height, width, out_ptr, ws_ptr, ws_bytes, stream),
+          "ivrgs_ssim_fwd")
+
+
+def ivrgs_ssim_bwd(x_ptr, y_ptr, channels: int, height: int, width: int, grad_mean_ptr, grad_x_ptr, ws_ptr,
+                   ws_bytes, stream):
+    check(load().ivrgs_ssim_bwd(x_ptr, y_ptr, channels, height, width, grad_mean_ptr, grad_x_ptr, ws_ptr,
+                                ws_bytes, stream), "ivrgs_ssim_bwd")
 
 
 def ivrgs_project(batch, params, proj, stream):

@@ -1,0 +1,100 @@
+"""GPU parity of the SSIM term of the photometric loss (Sec. 4.2) through
+ivrgs_ssim_fwd / ivrgs_ssim_bwd against the FP64 oracle: the mean within
+1e-5, the gradient within 1e-3 relative plus 1e-5 of its largest magnitude;
+several 16x16 tiles with ragged edges, the single-window image, and the full
+800x800 RGBA of the training step."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ssim as OS
+from paper_2504_17954_amd import losses as L
+from paper_2504_17954_amd import native as N
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available()
+    return torch.device("cuda:0")
+
+
+def pair(shape, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0, 1, shape)
+    y = np.clip(0.7 * x + 0.3 * rng.uniform(0, 1, shape) + rng.normal(0, 0.05, shape), 0, 1)
+    return x.astype(np.float32), y.astype(np.float32)
+
+
+def run(x, y, dev):
+    xd = torch.from_numpy(x).to(dev).requires_grad_(True)
+    yd = torch.from_numpy(y).to(dev)
+    v = L.ssim(xd, yd)
+    v.backward()
+    return float(v.detach()), xd.grad.cpu().numpy()
+
+
+@pytest.mark.parametrize("shape,seed", [((3, 11, 11), 1), ((4, 40, 52), 2), ((1, 27, 100), 3), ((4, 100, 130), 4)])
+def test_ssim_matches_oracle(dev, shape, seed):
+    x, y = pair(shape, seed)
+    say(f"ssim {shape}")
+    want, gwant = OS.ssim_and_grad(x.astype(np.float64), y.astype(np.float64))
+    got, g = run(x, y, dev)
+    assert abs(got - want) <= 1e-5, (got, want)
+    tol = 1e-3 * np.abs(gwant) + 1e-5 * np.abs(gwant).max()
+    bad = np.abs(g - gwant) > tol
+    say(f"  mean {got:.7f} vs {want:.7f}; gradient outside {bad.sum()} / {g.size}, "
+        f"worst {(np.abs(g - gwant) / tol).max():.3f}")
+    assert not bad.any()
+
+
+def test_ssim_full_size_rgba(dev):
+    """The 800x800 RGBA of a training view: mean and gradient at every pixel."""
+    x, y = pair((4, 800, 800), 5)
+    say("ssim 4x800x800")
+    want, gwant = OS.ssim_and_grad(x.astype(np.float64), y.astype(np.float64))
+    got, g = run(x, y, dev)
+    assert abs(got - want) <= 1e-5, (got, want)
+    tol = 1e-3 * np.abs(gwant) + 1e-5 * np.abs(gwant).max()
+    bad = np.abs(g - gwant) > tol
+    say(f"  mean {got:.7f} vs {want:.7f}; gradient outside {bad.sum()} / {g.size}")
+    assert not bad.any()
+
+
+def test_ssim_identity_is_exactly_one(dev):
+    x, _ = pair((4, 64, 80), 6)
+    xd = torch.from_numpy(x).to(dev)
+    assert float(L.ssim(xd, xd.clone())) == 1.0
+
+
+def test_ssim_twice_on_one_workspace_is_deterministic(dev):
+    x, y = pair((4, 90, 70), 7)
+    a, ga = run(x, y, dev)
+    b, gb = run(x, y, dev)
+    assert a == b and np.array_equal(ga, gb)
+
+
+def test_ssim_shape_errors(dev):
+    x = torch.zeros((2, 10, 40), device=dev)
+    with pytest.raises(ValueError):
+        L.ssim(x, x)
+    # the C ABI itself: too small an image, too small a workspace, null pointers
+    assert N.ivrgs_ssim_workspace_size(2, 10, 40) == 0
+    ws = torch.empty(16, dtype=torch.uint8, device=dev)
+    out = torch.empty((), device=dev)
+    with pytest.raises(N.IvrgsError):
+        N.ivrgs_ssim_fwd(x.data_ptr(), x.data_ptr(), 2, 10, 40, out.data_ptr(), ws.data_ptr(), 16, None)
+    y = torch.zeros((2, 20, 40), device=dev)
+    with pytest.raises(N.IvrgsError):
+        N.ivrgs_ssim_fwd(y.data_ptr(), y.data_ptr(), 2, 20, 40, out.data_ptr(), ws.data_ptr(), 16, None)
+    with pytest.raises(N.IvrgsError):
+        N.ivrgs_ssim_fwd(None, y.data_ptr(), 2, 20, 40, out.data_ptr(), ws.data_ptr(), 16, None)
+    torch.cuda.synchronize()
