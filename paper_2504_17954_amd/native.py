@@ -109,6 +109,11 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise IvrgsError(f"{path} is missing: build it with "
                          f"`python -m paper_2504_17954_amd.build` (no CPU fallback exists)")
+    # torch ships its own HIP runtime under the soname the library links
+    # against; loading torch first makes the loader reuse that runtime, so
+    # the library and torch's allocations share one.  Loaded the other way
+    # round, the system runtime sits under torch and launches fail.
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     P = C.c_void_p
     lib.ivrgs_workspace_size.argtypes = [P, P, C.c_int64]
