@@ -66,15 +66,26 @@ __global__ __launch_bounds__(kCullBlock) void k_cull_mlp(ivrgs_gaussians g, cons
 #pragma unroll
     for (int i = 0; i < 3; ++i) cpos[i] = -(cm.R[i] * cm.t[0] + cm.R[3 + i] * cm.t[1] + cm.R[6 + i] * cm.t[2]);
 
+    // biases and output weights staged once (global reads inside the loop
+    // could not be hoisted past the stores below)
+    __shared__ float sb1[kHidden], sb2[kHidden], sw3[kHidden];
     __shared__ uint32_t wave_cnt[4];
+    if (threadIdx.x < kHidden) {
+        sb1[threadIdx.x] = mlp.b1[threadIdx.x];
+        sb2[threadIdx.x] = mlp.b2[threadIdx.x];
+        sw3[threadIdx.x] = mlp.w3[threadIdx.x];
+    }
     uint32_t kept_by_wave = 0;
     const int64_t n = g.n;
-#pragma unroll 1
+    // the features of the wave's four groups of 16 Gaussians, all loads
+    // issued before the first product
+    float fe[4][4];
+#pragma unroll
     for (int grp = 0; grp < 4; ++grp) {
         const int64_t gi = (int64_t)blockIdx.x * kCullBlock + wave * 64 + grp * 16 + col;
-        const bool valid = gi < n;
-        float f[4] = {0.f, 0.f, 0.f, 0.f};
-        if (valid) {
+        float *f = fe[grp];
+        f[0] = f[1] = f[2] = f[3] = 0.f;
+        if (gi < n) {
             const float mx = g.mean[gi], my = g.mean[n + gi], mz = g.mean[2 * n + gi];
             const float vx = cpos[0] - mx, vy = cpos[1] - my, vz = cpos[2] - mz;
             const float inv = 1.f / sqrtf(vx * vx + vy * vy + vz * vz);
@@ -86,6 +97,15 @@ __global__ __launch_bounds__(kCullBlock) void k_cull_mlp(ivrgs_gaussians g, cons
                 f[0] = vy * inv; f[1] = vz * inv;
             }
         }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int grp = 0; grp < 4; ++grp) {
+        const int64_t gi = (int64_t)blockIdx.x * kCullBlock + wave * 64 + grp * 16 + col;
+        const bool valid = gi < n;
+        float f[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) f[i] = fe[grp][i];
         const bf16x4 x = pack4(f[0], f[1], f[2], f[3]);
         bf16x4 h1[4];
 #pragma unroll
@@ -94,7 +114,7 @@ __global__ __launch_bounds__(kCullBlock) void k_cull_mlp(ivrgs_gaussians g, cons
             acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[t], x, acc, 0, 0, 0);
             float h[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) h[i] = fmaxf(acc[i] + mlp.b1[16 * t + 4 * kg + i], 0.f);
+            for (int i = 0; i < 4; ++i) h[i] = fmaxf(acc[i] + sb1[16 * t + 4 * kg + i], 0.f);
             h1[t] = pack4(h[0], h[1], h[2], h[3]);
         }
         float part = 0.f;
@@ -106,7 +126,7 @@ __global__ __launch_bounds__(kCullBlock) void k_cull_mlp(ivrgs_gaussians g, cons
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int h = 16 * u + 4 * kg + i;
-                part = fmaf(mlp.w3[h], fmaxf(acc[i] + mlp.b2[h], 0.f), part);
+                part = fmaf(sw3[h], fmaxf(acc[i] + sb2[h], 0.f), part);
             }
         }
         // lanes col, col + 16, col + 32, col + 48 hold partial sums of one Gaussian
