@@ -541,10 +541,12 @@ def secondary_editable(dev, steps=20, warmup=3):
     targets = [torch.rand((4, 800, 800), generator=tg, device=dev) for _ in range(4)]
     rnd = R.Renderer(R.Settings(800, 800), capacity=1 << 24, check="sync")
     jobs = R.Jobs.single(n)
+    edits = R.default_edits(dev)  # one table for both renders, so the maps reuse the image's bins
 
     def step(v):
-        rgba = R.rasterize(planes, cams_t[v % 100:v % 100 + 1], jobs, rnd)[0]
-        maps = AX.render_aux(planes, AX.editable_attributes(planes), cams_t[v % 100:v % 100 + 1], jobs, rnd)[0]
+        rgba = R.rasterize(planes, cams_t[v % 100:v % 100 + 1], jobs, rnd, edits_t=edits)[0]
+        maps = AX.render_aux(planes, AX.editable_attributes(planes), cams_t[v % 100:v % 100 + 1], jobs, rnd,
+                             edits_t=edits)[0]
         loss = LS.editable_loss(rgba, targets[v % 4], maps, planes["opacity"], cams[v % 100])
         for t in planes.values():
             t.grad = None

@@ -18,7 +18,7 @@ class _AuxFn(torch.autograd.Function):
     def forward(ctx, renderer, cams_t, jobs, model_id, edits_t, gauss_index, attr, *planes):
         pl = dict(zip(PLANES, planes))
         batch = renderer.make_batch(pl, model_id, edits_t, cams_t, jobs, gauss_index)
-        proj, bins = renderer.project_and_bin(batch)
+        proj, bins = renderer.bins_for(batch)  # the image's bins when it was rendered from the same inputs
         s = renderer.settings
         A = int(attr.shape[0])
         aux = torch.empty((jobs.n_jobs, 1 + A, s.height, s.width), dtype=torch.float32, device=renderer.device)

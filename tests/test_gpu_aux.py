@@ -155,3 +155,42 @@ def test_aux_two_jobs_with_overlapping_ranges(dev):
     check_grad(ad.grad.cpu().numpy(), at.grad.numpy(), "d/dattr, two jobs")
     for k in ("mean", "log_scale", "quat", "opacity"):
         check_grad(pd[k].grad.cpu().numpy(), pt[k].grad.numpy(), f"d/d{k}, two jobs")
+
+
+def test_maps_reuse_the_image_bins(dev):
+    """Maps rendered from the same inputs as the image reuse its bins (no new
+    binning, so the image's backward needs none either): images and maps
+    equal those of two renderers that each bin for themselves, gradients
+    equal up to the order of the atomic sums; an in-place change of a plane
+    makes the next maps bin again."""
+    n = 400
+    planes, cam, prm = small(n, 45)
+    attr = attributes(planes)
+    cams, jobs, edits = R.camera_table([cam]), R.Jobs.single(n), R.default_edits(dev)
+    G = torch.from_numpy(np.random.default_rng(9).normal(size=(1, 11, prm.height, prm.width))
+                         .astype(np.float32)).to(dev)
+
+    def run(shared):
+        pd = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev).requires_grad_(True) for k, v in planes.items()}
+        ad = torch.from_numpy(attr).to(dev).requires_grad_(True)
+        r1 = R.Renderer(R.Settings(prm.width, prm.height))
+        r2 = r1 if shared else R.Renderer(R.Settings(prm.width, prm.height))
+        rgba = R.rasterize(pd, cams, jobs, r1, edits_t=edits)
+        gen = r1.generation
+        maps = AX.render_aux(pd, ad, cams, jobs, r2, edits_t=edits)
+        if shared:
+            assert r1.generation == gen, "the maps binned again"
+        (rgba.abs().sum() + (maps * G).sum()).backward()
+        if shared:
+            with torch.no_grad():
+                pd["opacity"].mul_(0.5)
+            AX.render_aux(pd, ad, cams, jobs, r1, edits_t=edits)
+            assert r1.generation == gen + 1, "a changed plane must be binned again"
+        return rgba.detach(), maps.detach(), {k: v.grad.cpu().numpy() for k, v in pd.items()}, ad.grad.cpu().numpy()
+
+    say("maps reusing the image's bins")
+    a, b = run(True), run(False)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    for k in a[2]:
+        np.testing.assert_allclose(a[2][k], b[2][k], rtol=1e-5, atol=1e-6 * max(np.abs(b[2][k]).max(), 1e-30))
+    np.testing.assert_allclose(a[3], b[3], rtol=1e-5, atol=1e-6 * np.abs(b[3]).max())
