@@ -31,6 +31,7 @@ import torch
 import torch.nn.functional as F
 
 from . import native as N
+from .raster import _stream
 
 
 def _gauss_window(size: int, sigma: float, dtype, device):
@@ -46,7 +47,6 @@ class _SsimFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, x, y):
-        from .raster import _stream
         c, h, w = (int(v) for v in x.shape)
         nbytes = N.ivrgs_ssim_workspace_size(c, h, w)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
@@ -57,7 +57,6 @@ class _SsimFn(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        from .raster import _stream
         x, y, ws = ctx.saved_tensors
         c, h, w = (int(v) for v in x.shape)
         gx = torch.empty_like(x)
