@@ -73,3 +73,28 @@ def test_host_validation(lib):
     assert N.ivrgs_workspace_size(b, p, 10 ** 6) == ws
     assert N.ivrgs_workspace_size(b, p, -1) == 0
     assert lib.ivrgs_status_string(N.E_CAPACITY).decode().startswith("workspace")
+
+
+def test_host_validation_of_ssim_and_error_query(lib):
+    """The SSIM entry points and the device-error query check their
+    arguments on the host: no device pointer is touched."""
+    # workspace: 3 floats per valid window and channel plus one partial per 16x16 tile of windows
+    assert N.ivrgs_ssim_workspace_size(4, 800, 800) == 4 * (3 * 4 * 790 * 790 + 4 * 50 * 50)
+    assert N.ivrgs_ssim_workspace_size(1, 11, 11) == 4 * (3 + 1)
+    for c, h, w in [(0, 32, 32), (2, 10, 40), (2, 40, 10), (-1, 20, 20)]:
+        assert N.ivrgs_ssim_workspace_size(c, h, w) == 0
+    P = C.c_void_p
+    fake = P(256)  # non-null placeholder, never dereferenced
+    assert lib.ivrgs_ssim_fwd(None, fake, 1, 20, 20, fake, fake, 1 << 20, None) == N.E_INVALID
+    assert lib.ivrgs_ssim_fwd(fake, fake, 1, 20, 20, fake, None, 1 << 20, None) == N.E_INVALID
+    assert lib.ivrgs_ssim_fwd(fake, fake, 1, 10, 20, fake, fake, 1 << 20, None) == N.E_SHAPE
+    assert lib.ivrgs_ssim_fwd(fake, fake, 1, 20, 20, fake, fake, 16, None) == N.E_CAPACITY
+    assert lib.ivrgs_ssim_bwd(fake, fake, 1, 20, 20, None, fake, fake, 1 << 20, None) == N.E_INVALID
+    assert lib.ivrgs_ssim_bwd(fake, fake, 1, 20, 5, fake, fake, fake, 1 << 20, None) == N.E_SHAPE
+    assert lib.ivrgs_ssim_bwd(fake, fake, 1, 20, 20, fake, fake, fake, 16, None) == N.E_CAPACITY
+    out = C.c_int64(0)
+    assert lib.ivrgs_get_error(None, None, C.cast(C.byref(out), P), None) == N.E_INVALID
+    bins = N.ivrgs_bins(0, 0, 0, 0)  # no status word
+    assert lib.ivrgs_get_error(N.ref(bins), None, C.cast(C.byref(out), P), None) == N.E_INVALID
+    bins = N.ivrgs_bins(0, 0, 0, 256)
+    assert lib.ivrgs_get_error(N.ref(bins), None, None, None) == N.E_INVALID
