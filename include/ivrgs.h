@@ -426,6 +426,28 @@ size_t ivrgs_vq_workspace_size(int64_t n, int32_t k);
 ivrgs_status ivrgs_vq_fit(const float *values, int64_t n, int32_t k, int32_t iters, float *codebook,
                           uint8_t *index, void *workspace, size_t workspace_bytes, void *stream);
 
+/* One attribute of ivrgs_vq_fit_batch: values device [n] FP32, outputs
+ * codebook device [k] and index device [n] uint8, as for ivrgs_vq_fit. */
+typedef struct {
+    const float *values;
+    int64_t n;
+    float *codebook;
+    uint8_t *index;
+} ivrgs_vq_book;
+
+/* Workspace bytes of ivrgs_vq_fit_batch: the sum over the books of
+ * ivrgs_vq_workspace_size(n, k). */
+size_t ivrgs_vq_fit_batch_workspace_size(const ivrgs_vq_book *books, int32_t count, int32_t k);
+
+/* ivrgs_vq_fit of `count` attributes (books: host array) with one codebook
+ * size k and iteration count: each result equals that of ivrgs_vq_fit on
+ * the attribute alone, bit for bit.  Up to 8 attributes share each launch
+ * (the eight codebooks of a model in one), so a fit costs 2 iters + 3
+ * launches per 8 attributes instead of per attribute.  Errors as for
+ * ivrgs_vq_fit, checked for every book before any launch. */
+ivrgs_status ivrgs_vq_fit_batch(const ivrgs_vq_book *books, int32_t count, int32_t k, int32_t iters,
+                                void *workspace, size_t workspace_bytes, void *stream);
+
 /* Nearest-centroid index of each value (the assignment step of the fit):
  * argmin_j |x - c_j| in FP32, the lowest index on ties, 0 for non-finite
  * values.  Any codebook order is accepted (an ascending one takes a binary

@@ -281,6 +281,26 @@ ivrgs_status ivrgs_vq_fit(const float *values, int64_t n, int32_t k, int32_t ite
                                     reinterpret_cast<hipStream_t>(stream)));
 }
 
+size_t ivrgs_vq_fit_batch_workspace_size(const ivrgs_vq_book *books, int32_t count, int32_t k) {
+    if (!books || count < 0 || k < 1 || k > 256) return 0;
+    for (int i = 0; i < count; ++i)
+        if (books[i].n < 0) return 0;
+    return vq_batch_workspace_bytes(books, count, k);
+}
+
+ivrgs_status ivrgs_vq_fit_batch(const ivrgs_vq_book *books, int32_t count, int32_t k, int32_t iters,
+                                void *workspace, size_t workspace_bytes, void *stream) {
+    if (count < 0 || k < 1 || k > 256 || iters < 0 || (count > 0 && (!books || !workspace))) return IVRGS_E_INVALID;
+    for (int i = 0; i < count; ++i) {
+        const ivrgs_vq_book &b = books[i];
+        if (b.n < 0 || !b.codebook) return IVRGS_E_INVALID;
+        if (b.n > 0 && (!b.values || !b.index)) return IVRGS_E_INVALID;
+    }
+    if (count == 0) return IVRGS_OK;
+    if (workspace_bytes < vq_batch_workspace_bytes(books, count, k)) return IVRGS_E_CAPACITY;
+    return hip_status(launch_vq_fit_batch(books, count, k, iters, workspace, reinterpret_cast<hipStream_t>(stream)));
+}
+
 ivrgs_status ivrgs_vq_assign(const float *values, int64_t n, const float *codebook, int32_t k, uint8_t *index,
                              void *stream) {
     if (n < 0 || k < 1 || k > 256 || !codebook) return IVRGS_E_INVALID;
@@ -633,6 +653,7 @@ int32_t ivrgs_struct_size(int32_t which) {
     case 8: return (int32_t)sizeof(ivrgs_culler);
     case 9: return (int32_t)sizeof(ivrgs_explore_opts);
     case 10: return (int32_t)sizeof(ivrgs_vq_model);
+    case 11: return (int32_t)sizeof(ivrgs_vq_book);
     default: return -1;
     }
 }

@@ -75,6 +75,9 @@ size_t cull_workspace_bytes(int64_t n);
 // codebook, and the composition of quantised models (count <= kComposeModels
 // models in one launch, edits: the host rows of those models).
 size_t vq_workspace_bytes(int64_t n, int k);
+size_t vq_batch_workspace_bytes(const ivrgs_vq_book *books, int count, int k);
+hipError_t launch_vq_fit_batch(const ivrgs_vq_book *books, int count, int k, int iters, void *workspace,
+                               hipStream_t s);
 hipError_t launch_vq_fit(const float *values, int64_t n, int k, int iters, float *codebook, uint8_t *index,
                          void *workspace, hipStream_t s);
 hipError_t launch_vq_assign(const float *values, int64_t n, const float *codebook, int k, uint8_t *index,

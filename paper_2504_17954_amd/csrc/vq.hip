@@ -85,12 +85,36 @@ __device__ __forceinline__ int nearest_scan(float x, const float *c, int k) {
 
 __device__ __forceinline__ bool is_finite32(float x) { return (__float_as_uint(x) & 0x7F800000u) != 0x7F800000u; }
 
+// The fits of one launch: codebook blockIdx.y takes its values, outputs and
+// workspace rows from its entry, and its streaming kernels run on `groups`
+// workgroups (a workgroup past them returns), so one codebook alone or
+// several side by side decompose their values identically.
+constexpr int kVqFitBatch = 8;
+struct VqBook {
+    const float *v;
+    int64_t n;
+    float *cb;
+    uint8_t *index;
+    double *psum;    // [groups][k]
+    uint32_t *pcnt;  // [groups][k]
+    float *part;     // [groups][2]
+    int groups;
+};
+struct VqBooks {
+    VqBook b[kVqFitBatch];
+};
+
 // Per workgroup: min and max of the finite values of its tiles.
-__global__ __launch_bounds__(kVqThreads) void k_vq_range(const float *__restrict__ v, int64_t n,
-                                                         float *__restrict__ part) {
+__global__ __launch_bounds__(kVqThreads) void k_vq_range(VqBooks books) {
+    const VqBook &bk = books.b[blockIdx.y];
+    const int bid = blockIdx.x, nb = bk.groups;
+    if (bid >= nb) return;
+    const float *__restrict__ v = bk.v;
+    const int64_t n = bk.n;
+    float *__restrict__ part = bk.part;
     __shared__ float slo[kVqThreads / 64], shi[kVqThreads / 64];
     float lo = __builtin_inff(), hi = -__builtin_inff();
-    for (int64_t t0 = (int64_t)blockIdx.x * kVqTile; t0 < n; t0 += (int64_t)gridDim.x * kVqTile) {
+    for (int64_t t0 = (int64_t)bid * kVqTile; t0 < n; t0 += (int64_t)nb * kVqTile) {
         float x[kVqItems];
 #pragma unroll
         for (int u = 0; u < kVqItems; ++u) {
@@ -119,15 +143,18 @@ __global__ __launch_bounds__(kVqThreads) void k_vq_range(const float *__restrict
             lo = fminf(lo, slo[w]);
             hi = fmaxf(hi, shi[w]);
         }
-        part[2 * blockIdx.x] = lo;
-        part[2 * blockIdx.x + 1] = hi;
+        part[2 * bid] = lo;
+        part[2 * bid + 1] = hi;
     }
 }
 
 // One workgroup: the range over the `groups` partials, then centroid j at
 // lo + (j + 1/2) * ((hi - lo) / k); all zero without a finite value.
-__global__ __launch_bounds__(kVqThreads) void k_vq_init(const float *__restrict__ part, int groups, int k,
-                                                        float *__restrict__ cb) {
+__global__ __launch_bounds__(kVqThreads) void k_vq_init(VqBooks books, int k) {
+    const VqBook &bk = books.b[blockIdx.y];
+    const float *__restrict__ part = bk.part;
+    const int groups = bk.n > 0 ? bk.groups : 0;
+    float *__restrict__ cb = bk.cb;
     __shared__ float slo[kVqThreads / 64], shi[kVqThreads / 64];
     float lo = __builtin_inff(), hi = -__builtin_inff();
     for (int g = threadIdx.x; g < groups; g += kVqThreads) {
@@ -154,9 +181,15 @@ __global__ __launch_bounds__(kVqThreads) void k_vq_init(const float *__restrict_
 // Assignment and accumulation of one Lloyd iteration: per workgroup, the
 // FP64 sum and the count of the finite values nearest each centroid (the
 // codebook is ascending throughout the fit).
-__global__ __launch_bounds__(kVqThreads) void k_vq_lloyd(const float *__restrict__ v, int64_t n,
-                                                         const float *__restrict__ cb, int k,
-                                                         double *__restrict__ psum, uint32_t *__restrict__ pcnt) {
+__global__ __launch_bounds__(kVqThreads) void k_vq_lloyd(VqBooks books, int k) {
+    const VqBook &bk = books.b[blockIdx.y];
+    const int bid = blockIdx.x, nb = bk.groups;
+    if (bid >= nb) return;
+    const float *__restrict__ v = bk.v;
+    const int64_t n = bk.n;
+    const float *__restrict__ cb = bk.cb;
+    double *__restrict__ psum = bk.psum;
+    uint32_t *__restrict__ pcnt = bk.pcnt;
     __shared__ float c[kVqMaxK];
     __shared__ double sum[kVqMaxK];
     __shared__ uint32_t cnt[kVqMaxK];
@@ -166,7 +199,7 @@ __global__ __launch_bounds__(kVqThreads) void k_vq_lloyd(const float *__restrict
         cnt[j] = 0u;
     }
     __syncthreads();
-    for (int64_t t0 = (int64_t)blockIdx.x * kVqTile; t0 < n; t0 += (int64_t)gridDim.x * kVqTile) {
+    for (int64_t t0 = (int64_t)bid * kVqTile; t0 < n; t0 += (int64_t)nb * kVqTile) {
         float x[kVqItems];
 #pragma unroll
         for (int u = 0; u < kVqItems; ++u) {
@@ -183,8 +216,8 @@ __global__ __launch_bounds__(kVqThreads) void k_vq_lloyd(const float *__restrict
     }
     __syncthreads();
     for (int j = threadIdx.x; j < k; j += kVqThreads) {
-        psum[(size_t)blockIdx.x * k + j] = sum[j];
-        pcnt[(size_t)blockIdx.x * k + j] = cnt[j];
+        psum[(size_t)bid * k + j] = sum[j];
+        pcnt[(size_t)bid * k + j] = cnt[j];
     }
 }
 
@@ -192,9 +225,12 @@ __global__ __launch_bounds__(kVqThreads) void k_vq_lloyd(const float *__restrict
 // partials of workgroups q, q + 4, ... in order; the quarters combine in a
 // fixed order; each non-empty centroid becomes its mean, rounded to FP32;
 // then a bitonic sort of the padded codebook in LDS.
-__global__ __launch_bounds__(kUpdateThreads) void k_vq_update(const double *__restrict__ psum,
-                                                              const uint32_t *__restrict__ pcnt, int groups,
-                                                              int k, float *__restrict__ cb) {
+__global__ __launch_bounds__(kUpdateThreads) void k_vq_update(VqBooks books, int k) {
+    const VqBook &bk = books.b[blockIdx.y];
+    const double *__restrict__ psum = bk.psum;
+    const uint32_t *__restrict__ pcnt = bk.pcnt;
+    const int groups = bk.groups;
+    float *__restrict__ cb = bk.cb;
     __shared__ double qs[4][kVqMaxK];
     __shared__ uint32_t qc[4][kVqMaxK];
     __shared__ float key[kVqMaxK];
@@ -242,9 +278,8 @@ __global__ __launch_bounds__(kUpdateThreads) void k_vq_update(const double *__re
 // Index of every value: binary search when the codebook is ascending, a
 // full scan otherwise (both give the least FP32 |x - c_j|, lowest index on
 // ties); 0 for non-finite values.
-__global__ __launch_bounds__(kVqThreads) void k_vq_assign(const float *__restrict__ v, int64_t n,
-                                                          const float *__restrict__ cb, int k,
-                                                          uint8_t *__restrict__ index) {
+__device__ __forceinline__ void vq_assign_body(const float *__restrict__ v, int64_t n, const float *__restrict__ cb,
+                                               int k, uint8_t *__restrict__ index, int bid, int nb) {
     __shared__ float c[kVqMaxK];
     __shared__ int unsorted;
     if (threadIdx.x == 0) unsorted = 0;
@@ -254,7 +289,7 @@ __global__ __launch_bounds__(kVqThreads) void k_vq_assign(const float *__restric
         if (!(c[j] <= c[j + 1])) unsorted = 1;
     __syncthreads();
     const bool sorted = unsorted == 0;
-    for (int64_t t0 = (int64_t)blockIdx.x * kVqTile; t0 < n; t0 += (int64_t)gridDim.x * kVqTile) {
+    for (int64_t t0 = (int64_t)bid * kVqTile; t0 < n; t0 += (int64_t)nb * kVqTile) {
         float x[kVqItems];
 #pragma unroll
         for (int u = 0; u < kVqItems; ++u) {
@@ -270,6 +305,18 @@ __global__ __launch_bounds__(kVqThreads) void k_vq_assign(const float *__restric
             }
         }
     }
+}
+
+__global__ __launch_bounds__(kVqThreads) void k_vq_assign(const float *__restrict__ v, int64_t n,
+                                                          const float *__restrict__ cb, int k,
+                                                          uint8_t *__restrict__ index) {
+    vq_assign_body(v, n, cb, k, index, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(kVqThreads) void k_vq_assign_books(VqBooks books, int k) {
+    const VqBook &bk = books.b[blockIdx.y];
+    if ((int)blockIdx.x >= bk.groups) return;
+    vq_assign_body(bk.v, bk.n, bk.cb, k, bk.index, blockIdx.x, bk.groups);
 }
 
 constexpr int kVqBooks = 8;
@@ -389,21 +436,60 @@ size_t vq_workspace_bytes(int64_t n, int k) {
            align256(sizeof(float) * 2 * (size_t)g);
 }
 
+static VqBook vq_book(const float *values, int64_t n, float *codebook, uint8_t *index, void *workspace, int k) {
+    const VqWork w = vq_work(workspace, n, k);
+    return VqBook{values, n, codebook, index, w.sum, w.cnt, w.range, vq_groups(n)};
+}
+
+// Up to kVqFitBatch fits side by side: one launch per step for all of them.
+static hipError_t launch_vq_books(const VqBooks &bs, int count, int k, int iters, bool any_values, hipStream_t s) {
+    int g = 1;
+    for (int i = 0; i < count; ++i) g = std::max(g, bs.b[i].groups);
+    const dim3 grid(g, count);
+    if (any_values) hipLaunchKernelGGL(k_vq_range, grid, dim3(kVqThreads), 0, s, bs);
+    hipLaunchKernelGGL(k_vq_init, dim3(1, count), dim3(kVqThreads), 0, s, bs, k);
+    if (any_values) {
+        for (int it = 0; it < iters; ++it) {
+            hipLaunchKernelGGL(k_vq_lloyd, grid, dim3(kVqThreads), 0, s, bs, k);
+            hipLaunchKernelGGL(k_vq_update, dim3(1, count), dim3(kUpdateThreads), 0, s, bs, k);
+        }
+        hipLaunchKernelGGL(k_vq_assign_books, grid, dim3(kVqThreads), 0, s, bs, k);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_vq_fit(const float *values, int64_t n, int k, int iters, float *codebook, uint8_t *index,
                          void *workspace, hipStream_t s) {
     TimedScope ts(TK_VQ, s);
-    const VqWork w = vq_work(workspace, n, k);
-    const int g = vq_groups(n);
-    if (n > 0) hipLaunchKernelGGL(k_vq_range, dim3(g), dim3(kVqThreads), 0, s, values, n, w.range);
-    hipLaunchKernelGGL(k_vq_init, dim3(1), dim3(kVqThreads), 0, s, w.range, n > 0 ? g : 0, k, codebook);
-    if (n > 0) {
-        for (int it = 0; it < iters; ++it) {
-            hipLaunchKernelGGL(k_vq_lloyd, dim3(g), dim3(kVqThreads), 0, s, values, n, codebook, k, w.sum, w.cnt);
-            hipLaunchKernelGGL(k_vq_update, dim3(1), dim3(kUpdateThreads), 0, s, w.sum, w.cnt, g, k, codebook);
+    VqBooks bs = {};
+    bs.b[0] = vq_book(values, n, codebook, index, workspace, k);
+    return launch_vq_books(bs, 1, k, iters, n > 0, s);
+}
+
+size_t vq_batch_workspace_bytes(const ivrgs_vq_book *books, int count, int k) {
+    size_t b = 0;
+    for (int i = 0; i < count; ++i) b += vq_workspace_bytes(books[i].n, k);
+    return b;
+}
+
+hipError_t launch_vq_fit_batch(const ivrgs_vq_book *books, int count, int k, int iters, void *workspace,
+                               hipStream_t s) {
+    TimedScope ts(TK_VQ, s);
+    char *ws = static_cast<char *>(workspace);
+    for (int c0 = 0; c0 < count; c0 += kVqFitBatch) {
+        const int m = std::min(kVqFitBatch, count - c0);
+        VqBooks bs = {};
+        bool any = false;
+        for (int i = 0; i < m; ++i) {
+            const ivrgs_vq_book &src = books[c0 + i];
+            bs.b[i] = vq_book(src.values, src.n, src.codebook, src.index, ws, k);
+            ws += vq_workspace_bytes(src.n, k);
+            any = any || src.n > 0;
         }
-        hipLaunchKernelGGL(k_vq_assign, dim3(g), dim3(kVqThreads), 0, s, values, n, codebook, k, index);
+        const hipError_t e = launch_vq_books(bs, m, k, iters, any, s);
+        if (e != hipSuccess) return e;
     }
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 hipError_t launch_vq_assign(const float *values, int64_t n, const float *codebook, int k, uint8_t *index,

@@ -25,7 +25,8 @@ EXPORTS = ("ivrgs_workspace_size", "ivrgs_tiles_per_job", "ivrgs_compose", "ivrg
            "ivrgs_compose_dev", "ivrgs_explore_state_words", "ivrgs_explore_step",
            "ivrgs_vq_workspace_size", "ivrgs_vq_fit", "ivrgs_vq_assign", "ivrgs_vq_compose",
            "ivrgs_sh_color", "ivrgs_sh_color_bwd", "ivrgs_render_aux_fwd", "ivrgs_render_aux_bwd",
-           "ivrgs_get_error", "ivrgs_ssim_workspace_size", "ivrgs_ssim_fwd", "ivrgs_ssim_bwd")
+           "ivrgs_get_error", "ivrgs_ssim_workspace_size", "ivrgs_ssim_fwd", "ivrgs_ssim_bwd",
+           "ivrgs_vq_fit_batch_workspace_size", "ivrgs_vq_fit_batch")
 TIMING_KINDS = ("project", "tile_count", "scatter", "depth_sort", "render_fwd", "render_bwd",
                 "project_bwd", "compose", "fill", "cull", "edit_bwd", "vq", "sh", "aux")
 
@@ -91,8 +92,13 @@ class ivrgs_vq_model(C.Structure):
                 ("codebook", C.c_void_p), ("k", C.c_int32)]
 
 
+class ivrgs_vq_book(C.Structure):
+    _fields_ = [("values", C.c_void_p), ("n", C.c_int64), ("codebook", C.c_void_p), ("index", C.c_void_p)]
+
+
 STRUCTS = (ivrgs_gaussians, ivrgs_camera, ivrgs_model_edit, ivrgs_job, ivrgs_batch,
-           ivrgs_params, ivrgs_projected, ivrgs_bins, ivrgs_culler, ivrgs_explore_opts, ivrgs_vq_model)
+           ivrgs_params, ivrgs_projected, ivrgs_bins, ivrgs_culler, ivrgs_explore_opts, ivrgs_vq_model,
+           ivrgs_vq_book)
 
 _lib = None
 
@@ -150,6 +156,10 @@ def load(path: str = LIB_PATH):
     lib.ivrgs_vq_workspace_size.restype = C.c_size_t
     lib.ivrgs_vq_fit.argtypes = [P, C.c_int64, C.c_int32, C.c_int32, P, P, P, C.c_size_t, P]
     lib.ivrgs_vq_fit.restype = C.c_int
+    lib.ivrgs_vq_fit_batch_workspace_size.argtypes = [P, C.c_int32, C.c_int32]
+    lib.ivrgs_vq_fit_batch_workspace_size.restype = C.c_size_t
+    lib.ivrgs_vq_fit_batch.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, C.c_size_t, P]
+    lib.ivrgs_vq_fit_batch.restype = C.c_int
     lib.ivrgs_vq_assign.argtypes = [P, C.c_int64, P, C.c_int32, P, P]
     lib.ivrgs_vq_assign.restype = C.c_int
     lib.ivrgs_vq_compose.argtypes = [P, C.c_int32, P, P, P]
@@ -232,6 +242,21 @@ def ivrgs_explore_step(edit_grad_ptr, light_grad_ptr, n_models: int, opts, state
 
 def ivrgs_vq_workspace_size(n: int, k: int) -> int:
     return int(load().ivrgs_vq_workspace_size(C.c_int64(n), k))
+
+
+def _book_array(books):
+    arr = (ivrgs_vq_book * max(len(books), 1))(*books)
+    return arr, C.cast(arr, C.c_void_p)
+
+
+def ivrgs_vq_fit_batch_workspace_size(books, k: int) -> int:
+    arr, ptr = _book_array(books)
+    return int(load().ivrgs_vq_fit_batch_workspace_size(ptr, len(books), k))
+
+
+def ivrgs_vq_fit_batch(books, k: int, iters: int, ws_ptr, ws_bytes, stream):
+    arr, ptr = _book_array(books)
+    check(load().ivrgs_vq_fit_batch(ptr, len(books), k, iters, ws_ptr, ws_bytes, stream), "ivrgs_vq_fit_batch")
 
 
 def ivrgs_vq_fit(values_ptr, n: int, k: int, iters: int, codebook_ptr, index_ptr, ws_ptr, ws_bytes, stream):

@@ -45,6 +45,26 @@ def fit(values: torch.Tensor, k: int = 256, iters: int = 10, workspace: torch.Te
     return cb, idx.view(values.shape)
 
 
+def fit_batch(values: list, k: int = 256, iters: int = 10):
+    """`fit` of several attributes at once (one launch per step for up to
+    eight of them); each result equals `fit` of that attribute alone."""
+    for t in values:
+        _dev_f32("values", t)
+    if not values:
+        return []
+    dev = values[0].device
+    out = [(torch.empty(k, dtype=torch.float32, device=dev), torch.empty(t.numel(), dtype=torch.uint8, device=dev))
+           for t in values]
+    books = [N.ivrgs_vq_book(t.data_ptr() if t.numel() else None, t.numel(), cb.data_ptr(),
+                             idx.data_ptr() if t.numel() else None) for t, (cb, idx) in zip(values, out)]
+    need = N.ivrgs_vq_fit_batch_workspace_size(books, k)
+    if need == 0:
+        raise ValueError(f"codebook size {k} outside 1..256")
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    N.ivrgs_vq_fit_batch(books, k, iters, ws.data_ptr(), ws.numel(), _stream())
+    return [(cb, idx.view(t.shape)) for t, (cb, idx) in zip(values, out)]
+
+
 def assign(values: torch.Tensor, codebook: torch.Tensor) -> torch.Tensor:
     """uint8 index of the nearest codebook entry of every value."""
     _dev_f32("values", values)
@@ -84,20 +104,21 @@ class QuantizedModel:
 
 def quantize(planes: dict, k: int = 256, iters: int = 10) -> QuantizedModel:
     """Quantise one basic model: one k-means fit per codebook over all the
-    components that share it."""
+    components that share it, the eight fits side by side."""
     n = int(planes["mean"].shape[1])
     dev = planes["mean"].device
     rows = torch.cat([planes[name].reshape(d, n) for name, d in INDEX_PLANES]).contiguous()
     books = torch.empty((N_BOOKS, k), dtype=torch.float32, device=dev)
     index = torch.empty((15, n), dtype=torch.uint8, device=dev)
-    ws = torch.empty(N.ivrgs_vq_workspace_size(4 * n, k), dtype=torch.uint8, device=dev)
-    p = 0
+    spans, p = [], 0
     for b in range(N_BOOKS):
         cnt = PLANE_BOOK.count(b)  # the planes of one book are adjacent
-        cb, idx = fit(rows[p:p + cnt], k, iters, ws)
+        spans.append((p, cnt))
+        p += cnt
+    fits = fit_batch([rows[p:p + cnt] for p, cnt in spans], k, iters)
+    for b, ((p, cnt), (cb, idx)) in enumerate(zip(spans, fits)):
         books[b] = cb
         index[p:p + cnt] = idx
-        p += cnt
     return QuantizedModel(planes["mean"].contiguous(), planes["normal"].contiguous(), index, books)
 
 

@@ -168,3 +168,19 @@ def test_invalid_arguments(dev):
     assert lib.ivrgs_vq_fit(x.data_ptr(), 10, 256, 1, cb.data_ptr(), idx.data_ptr(), ws.data_ptr(), 16, s) == N.E_CAPACITY
     assert lib.ivrgs_vq_assign(x.data_ptr(), 10, cb.data_ptr(), 0, idx.data_ptr(), s) == N.E_INVALID
     assert N.ivrgs_vq_workspace_size(10, 0) == 0
+
+
+def test_fit_batch_equals_fits_one_by_one(dev):
+    """Eleven attributes in one call (two launches: eight, then three) of
+    ragged sizes, an empty one among them: every codebook and index equals
+    the fit of that attribute alone, bit for bit."""
+    rng = np.random.default_rng(77)
+    sizes = [0, 1, 100, 4097, 65_537, 100_003, 5000, 3, 250_000, 77, 12_345]
+    vals = [torch.from_numpy((rng.normal(size=s) * (1 + i)).astype(np.float32)).to(dev) for i, s in enumerate(sizes)]
+    for k in (7, 256):
+        print(f"fit_batch of {len(vals)} attributes, k = {k}", flush=True)
+        got = V.fit_batch(vals, k, 6)
+        for s, v, (cb, idx) in zip(sizes, vals, got):
+            cb1, idx1 = V.fit(v, k, 6)
+            assert torch.equal(cb, cb1), (s, k)
+            assert torch.equal(idx, idx1), (s, k)
