@@ -73,8 +73,9 @@ def ssim(x: torch.Tensor, y: torch.Tensor, window: int = 11, sigma: float = 1.5)
     if x.is_cuda:
         if window != 11 or sigma != 1.5:
             raise ValueError("the device SSIM takes the 11x11 window of sigma 1.5")
-        if x.dim() != 3 or y.shape != x.shape or x.dtype != torch.float32 or y.dtype != torch.float32:
-            raise ValueError("ssim: expected float32 [C, H, W] image and target of one shape")
+        if x.dim() != 3 or y.shape != x.shape or x.dtype != torch.float32 or y.dtype != torch.float32 \
+                or y.device != x.device:
+            raise ValueError("ssim: expected float32 [C, H, W] image and target of one shape and device")
         if x.shape[1] < 11 or x.shape[2] < 11:
             raise ValueError("ssim: height and width must be at least 11")
         return _SsimFn.apply(x.contiguous(), y.detach().contiguous())

@@ -53,6 +53,8 @@ def fit_batch(values: list, k: int = 256, iters: int = 10):
     if not values:
         return []
     dev = values[0].device
+    if any(t.device != dev for t in values):
+        raise ValueError("fit_batch: all values on one device")
     out = [(torch.empty(k, dtype=torch.float32, device=dev), torch.empty(t.numel(), dtype=torch.uint8, device=dev))
            for t in values]
     books = [N.ivrgs_vq_book(t.data_ptr() if t.numel() else None, t.numel(), cb.data_ptr(),
