@@ -362,6 +362,21 @@ def secondary_fwd(dev):
         mx = max(mx, rnd.pairs())
     rnd.grow(int(mx * 1.1) + 4096)
     rnd.check = "defer"
+    # launch shape (results do not depend on it): pixels per lane and
+    # records per binning chunk, timed on the first views
+    from paper_2504_17954_amd import autotune as A
+    base = rnd.settings
+    cands = [c for c in A.CANDIDATES if not c["persistent"] and c["bwd_px"] == 1]
+
+    def make(cfg):
+        def run():
+            rnd.settings = A.apply(base, cfg)
+            for v in range(4):
+                rnd.forward(planes, cams_t, jobs[v], model_id=mid, edits_t=edits_t, out=out)
+        return run
+    best, times = A.tune(make, w.width, w.height, 1, n, candidates=cands, reps=3, use_cache=False)
+    rnd.settings = A.apply(base, best)
+    log(f"composed forward autotune (ms per candidate): {times} -> {best}")
     settle()
     for v in range(5):
         rnd.forward(planes, cams_t, jobs[v], model_id=mid, edits_t=edits_t, out=out)
@@ -376,7 +391,8 @@ def secondary_fwd(dev):
     mpix = nv * w.width * w.height / dt / 1e6
     log(f"composed forward: {dt / nv * 1e3:.3f} ms/view, {mpix:.1f} Mpix/s")
     return {"fwd_mpix_s": round(mpix, 2), "fwd_ms_per_view": round(dt / nv * 1e3, 4),
-            "workload": f"compose-{len(w.models)}x{w.models[0].n}-{w.width}px-{nv}views-fwd"}
+            "workload": f"compose-{len(w.models)}x{w.models[0].n}-{w.width}px-{nv}views-fwd",
+            "launch_shape": {k: best[k] for k in ("fwd_px", "sort_chunk")}}
 
 
 VQ_BYTES = 3 * 4 + 3 * 4 + 15       # stored per quantised Gaussian: exact mean and normal, 15 one-byte indices
