@@ -153,11 +153,17 @@ typedef struct {
  *   rect[r]     tile rectangle [x0, x1) x [y0, y1) packed as
  *               (x0 | y0 << 16, x1 | y1 << 16); (0, 0) if culled
  *   depth[r]    the depth key's FP32 bits (positive, finite) of a visible
- *               record, 0xFFFFFFFF if culled; ivrgs_bin_sort orders by it */
+ *               record, 0xFFFFFFFF if culled; ivrgs_bin_sort orders by it
+ *   nonfinite   NULL, or one device int64 to which ivrgs_project adds the
+ *               number of records it culls because a Gaussian parameter, or
+ *               a projected value of a Gaussian with a positive-definite
+ *               screen covariance, is NaN or infinite (such a Gaussian is
+ *               culled and counted, never propagated); the caller clears it */
 typedef struct {
     float *rec;
     uint32_t *rect;
     uint32_t *depth;
+    int64_t *nonfinite;
 } ivrgs_projected;
 
 /* Tile bins (device, caller-allocated):
@@ -165,10 +171,16 @@ typedef struct {
  *                                   the last entry is the pair total
  *   sorted[capacity]                record ids, each tile front to back by
  *                                   (depth key, record id)
- *   status[4]                       [0] pairs required, [1] IVRGS_DEV_E_* bits,
+ *   status[8]                       written by the library:
+ *                                   [0] pairs required and [1] IVRGS_DEV_E_*
+ *                                   bits of the last ivrgs_bin_sort,
  *                                   [2] evaluated and [3] composited pixel-
- *                                   Gaussian pairs (IVRGS_FLAG_COUNT_EVAL);
- *                                   written by the library */
+ *                                   Gaussian pairs (IVRGS_FLAG_COUNT_EVAL),
+ *                                   [4] the OR of [1] and [5] the largest [0]
+ *                                   over every bin sort since the last
+ *                                   ivrgs_get_error, which clears them (the
+ *                                   caller zeroes [4] and [5] once when it
+ *                                   allocates the word), [6], [7] reserved */
 typedef struct {
     uint32_t *tile_start;
     uint32_t *sorted;
@@ -517,6 +529,18 @@ ivrgs_status ivrgs_ssim_bwd(const float *x, const float *y, int32_t channels, in
                             const float *grad_mean, float *grad_x, const void *workspace, size_t workspace_bytes,
                             void *stream);
 
+/* Gradient of the photometric loss L = (1 - lam) mean|x - y| + lam (1 - SSIM)
+ * with respect to x (Sec. 4.2 names the L1 + D-SSIM combination, the
+ * appendix weights it 0.8 / 0.2; inverse exploration, Sec. 4.6, fits its
+ * parameters with the same combination).  mean|x - y| is over all
+ * channels x height x width values, with sign(0) = 0; SSIM as above.
+ * Needs the workspace of an ivrgs_ssim_fwd call on the same x and y, left
+ * unchanged since.  lam in [0, 1] (IVRGS_E_INVALID otherwise); grad_x:
+ * device, the layout of x, overwritten.  One launch; deterministic. */
+ivrgs_status ivrgs_photometric_grad(const float *x, const float *y, int32_t channels, int32_t height,
+                                    int32_t width, float lam, float *grad_x, const void *workspace,
+                                    size_t workspace_bytes, void *stream);
+
 /* ---- SH colour (base 3DGS, Sec. 3 and Sec. 4.2) ---------------------------
  * The base model's view-dependent colour is parameterised by spherical-
  * harmonic coefficients, as in the original 3DGS; the paper gives no degree
@@ -551,10 +575,13 @@ ivrgs_status ivrgs_sh_color_bwd(const float *sh, int32_t degree, const float *me
  * 8 culler, 9 explore_opts, 10 vq_model. */
 int32_t ivrgs_struct_size(int32_t which);
 
-/* Device-side errors: waits for `stream`, then reads the device status word
- * the last ivrgs_bin_sort on these bins wrote (bins->status[1]: a mask of
- * IVRGS_DEV_E_* bits, 0 when none) into *device_error, and the pairs that
- * sort required (bins->status[0]) into *pairs_required when not NULL.  The
+/* Device-side errors: waits for `stream`, then reads the device status
+ * words of every ivrgs_bin_sort on these bins since the previous call: the
+ * OR of their IVRGS_DEV_E_* bits (bins->status[4] | status[1]; 0 when none)
+ * into *device_error, and the largest pair count any of them required
+ * (max of status[5] and status[0]) into *pairs_required when not NULL; then
+ * clears status[4] and status[5], so a caller that runs many iterations
+ * without reading the pair count back checks them all with one call.  The
  * other entry points return host-side validation only and never wait. */
 ivrgs_status ivrgs_get_error(const ivrgs_bins *bins, void *stream, int64_t *device_error,
                              int64_t *pairs_required);

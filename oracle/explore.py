@@ -10,8 +10,11 @@ reference image by learning a small set of transformation parameters:
     lambda (4), b (4) applied as lambda * (k_a, k_d, k_s, beta) + b to every
     model, and one orbital light direction given by a polar angle t and an
     azimuth p, d = (sin t cos p, sin t sin p, cos t) in world space.
-The optimiser is Adam (Kingma and Ba, 2015, Algorithm 1); the loss here is
-the L1 term of the paper's L1 + SSIM objective, mean |RGBA - target|.
+The optimiser is Adam (Kingma and Ba, 2015, Algorithm 1).  The objective is
+the paper's combination of L1 and SSIM (Sec. 4.6), with the weights the
+appendix gives the photometric loss: (1 - lam) mean |RGBA - target| +
+lam (1 - SSIM(RGBA, target)), lam = 0.2, over the colour and alpha channels
+(SSIM from `oracle.ssim`, the target held fixed).
 
 Parameter vector layout (K models, n = 4K + 10):
   [palette K*3 | s_o K | lambda 4 | b 4 | t | p]
@@ -21,7 +24,9 @@ from __future__ import annotations
 import numpy as np
 
 from . import backward, compose, compose_bwd, light_grad, render
+from . import ssim as S
 
+SSIM_WEIGHT = 0.2  # lam: the appendix weights L1 and SSIM 0.8 and 0.2
 LEARN_PALETTE, LEARN_OPACITY, LEARN_MAGNITUDE, LEARN_LIGHT = 1, 2, 4, 8
 LEARN_ALL = 15
 
@@ -93,13 +98,26 @@ def assemble(eg, lg, theta):
     return g
 
 
-def loss_and_grad(models_planes, base_rows, theta, cam, prm, target):
-    """L1 loss mean |RGBA - target| under theta, its gradient with respect to
-    theta, and the render."""
+def photometric(rgba, target, lam=SSIM_WEIGHT):
+    """(1 - lam) mean |rgba - target| + lam (1 - SSIM(rgba, target)) and its
+    gradient with respect to rgba (sign(0) = 0; the target gets none)."""
+    rgba = np.asarray(rgba, np.float64)
+    target = np.asarray(target, np.float64)
+    l1 = float(np.abs(rgba - target).mean())
+    dl = (1.0 - lam) * np.sign(rgba - target) / rgba.size
+    loss = (1.0 - lam) * l1
+    if lam != 0.0:
+        s, ds = S.ssim_and_grad(rgba, target)
+        loss += lam * (1.0 - s)
+        dl = dl - lam * ds
+    return loss, dl
+
+
+def loss_and_grad(models_planes, base_rows, theta, cam, prm, target, lam=SSIM_WEIGHT):
+    """Photometric loss (L1 + SSIM, `photometric`) under theta, its gradient
+    with respect to theta, and the render."""
     out = render_params(models_planes, base_rows, theta, cam, prm)
-    rgba = out["rgba"]
-    loss = float(np.abs(rgba - target).mean())
-    dl = np.sign(rgba - target) / rgba.size
+    loss, dl = photometric(out["rgba"], target, lam)
     return loss, param_grad(models_planes, base_rows, theta, cam, prm, dl), out
 
 
@@ -132,7 +150,7 @@ def adam_update(theta, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, mask=No
 
 
 def explore(models_planes, base_rows, theta0, cam, prm, target, iters, lr=0.01, beta1=0.9,
-            beta2=0.999, eps=1e-8, learn=LEARN_ALL):
+            beta2=0.999, eps=1e-8, learn=LEARN_ALL, lam=SSIM_WEIGHT):
     """Run `iters` Adam steps from theta0.  Returns (thetas [iters + 1, n],
     losses [iters]) where losses[i] is the loss at thetas[i]."""
     K = len(models_planes)
@@ -142,7 +160,7 @@ def explore(models_planes, base_rows, theta0, cam, prm, target, iters, lr=0.01, 
     v = np.zeros_like(theta)
     thetas, losses = [theta.copy()], []
     for it in range(1, iters + 1):
-        loss, g, _ = loss_and_grad(models_planes, base_rows, theta, cam, prm, target)
+        loss, g, _ = loss_and_grad(models_planes, base_rows, theta, cam, prm, target, lam)
         losses.append(loss)
         theta, m, v = adam_update(theta, g, m, v, it, lr, beta1, beta2, eps, mask)
         thetas.append(theta.copy())

@@ -422,6 +422,18 @@ ivrgs_status ivrgs_ssim_bwd(const float *x, const float *y, int32_t channels, in
                                       static_cast<const float *>(workspace), reinterpret_cast<hipStream_t>(stream)));
 }
 
+ivrgs_status ivrgs_photometric_grad(const float *x, const float *y, int32_t channels, int32_t height,
+                                    int32_t width, float lam, float *grad_x, const void *workspace,
+                                    size_t workspace_bytes, void *stream) {
+    if (!x || !y || !grad_x || !workspace) return IVRGS_E_INVALID;
+    if (!(lam >= 0.0f && lam <= 1.0f)) return IVRGS_E_INVALID;
+    if (!ssim_shape_ok(channels, height, width)) return IVRGS_E_SHAPE;
+    if (workspace_bytes < ivrgs_ssim_workspace_size(channels, height, width)) return IVRGS_E_CAPACITY;
+    return hip_status(launch_photometric_grad(x, y, channels, height, width, lam, grad_x,
+                                              static_cast<const float *>(workspace),
+                                              reinterpret_cast<hipStream_t>(stream)));
+}
+
 int64_t ivrgs_explore_state_words(int32_t n_models) {
     if (n_models <= 0) return 0;
     return 3 * (4 * (int64_t)n_models + 10) + 1;
@@ -484,7 +496,8 @@ ivrgs_status ivrgs_project(const ivrgs_batch *batch, const ivrgs_params *params,
     if ((st = check_params(params)) != IVRGS_OK) return st;
     if (!out || (batch->n_records > 0 && (!out->rec || !out->rect || !out->depth))) return IVRGS_E_INVALID;
     const Consts k = make_consts(*params);
-    return hip_status(launch_project(*batch, k, out->rec, out->rect, out->depth, reinterpret_cast<hipStream_t>(stream)));
+    return hip_status(launch_project(*batch, k, out->rec, out->rect, out->depth, out->nonfinite,
+                                     reinterpret_cast<hipStream_t>(stream)));
 }
 
 ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
@@ -662,10 +675,12 @@ ivrgs_status ivrgs_get_error(const ivrgs_bins *bins, void *stream, int64_t *devi
                              int64_t *pairs_required) {
     if (!bins || !bins->status || !device_error) return IVRGS_E_INVALID;
     if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return IVRGS_E_HIP;
-    int64_t st[2] = {0, 0};
+    int64_t st[6] = {0, 0, 0, 0, 0, 0};
     if (hipMemcpy(st, bins->status, sizeof st, hipMemcpyDeviceToHost) != hipSuccess) return IVRGS_E_HIP;
-    *device_error = st[1];
-    if (pairs_required) *pairs_required = st[0];
+    *device_error = st[1] | st[4];
+    if (pairs_required) *pairs_required = st[0] > st[5] ? st[0] : st[5];
+    const int64_t zero[2] = {0, 0};
+    if (hipMemcpy(bins->status + 4, zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess) return IVRGS_E_HIP;
     return IVRGS_OK;
 }
 

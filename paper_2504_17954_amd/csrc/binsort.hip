@@ -584,10 +584,15 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t *__restrict__ star
     if (threadIdx.x == 0) {
         const bool over = total > (uint64_t)capacity || total > 0xFFFFFFF0ull;
         starts[n_tiles] = over ? 0xFFFFFFFFu : (uint32_t)total;
+        const int64_t bits = over ? (int64_t)IVRGS_DEV_E_CAPACITY : 0;
         status[0] = (int64_t)total;
-        status[1] = over ? (int64_t)IVRGS_DEV_E_CAPACITY : 0;
+        status[1] = bits;
         status[2] = 0;
         status[3] = 0;
+        // sticky until ivrgs_get_error reads them: the bits of every sort
+        // since, and the largest requirement
+        status[4] |= bits;
+        status[5] = max(status[5], (int64_t)total);
     }
 }
 

@@ -31,7 +31,7 @@ size_t depth_sort_hist_words(const ivrgs_batch &b);
 size_t col_part_words(const ivrgs_batch &b, const Consts &k, int chunk);
 
 hipError_t launch_project(const ivrgs_batch &b, const Consts &k, float *rec, uint32_t *rect, uint32_t *depth,
-                          hipStream_t s);
+                          int64_t *nonfinite, hipStream_t s);
 hipError_t launch_project_bwd(const ivrgs_batch &b, const Consts &k, const uint32_t *rect, const float *grec,
                               const ivrgs_gaussians_mut &out, bool atomic, bool dense, hipStream_t s);
 // Models model0 .. model0 + count - 1 (count <= kComposeModels) in one
@@ -113,6 +113,8 @@ hipError_t launch_ssim_fwd(const float *x, const float *y, int channels, int H, 
                            hipStream_t s);
 hipError_t launch_ssim_bwd(const float *x, const float *y, int channels, int H, int W, const float *grad_mean,
                            float *grad_x, const float *ws, hipStream_t s);
+hipError_t launch_photometric_grad(const float *x, const float *y, int channels, int H, int W, float lam,
+                                   float *grad_x, const float *ws, hipStream_t s);
 hipError_t launch_work_queue(const uint32_t *starts, int64_t n_tiles, uint32_t *queue, hipStream_t s);
 
 }  // namespace ivrgs

@@ -236,7 +236,8 @@ __device__ __forceinline__ void camera_center(const Cam &c, float p[3]) {
 
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_project(ivrgs_batch b, Consts k, float4 *__restrict__ rec,
-                                                 uint2 *__restrict__ rect, uint32_t *__restrict__ depth) {
+                                                 uint2 *__restrict__ rect, uint32_t *__restrict__ depth,
+                                                 unsigned long long *__restrict__ nonfinite) {
     const ivrgs_job job = b.jobs[blockIdx.y];
     const int local = blockIdx.x * blockDim.x + threadIdx.x;
     if (local >= job.gauss_count) return;
@@ -249,7 +250,9 @@ __global__ __launch_bounds__(256) void k_project(ivrgs_batch b, Consts k, float4
     const ivrgs_model_edit e = b.edits[m];
 
     const float z32 = depth_key(cam, a.mu[0], a.mu[1], a.mu[2]);
-    bool valid = all_finite(a) && z32 > k.z_near && a.o >= k.alpha_min;
+    const bool finite_in = all_finite(a);
+    bool bad = !finite_in;  // culled for a value that is not finite
+    bool valid = finite_in && z32 > k.z_near && a.o >= k.alpha_min;
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
     uint2 rc = make_uint2(0u, 0u);
     if (valid) {
@@ -257,9 +260,10 @@ __global__ __launch_bounds__(256) void k_project(ivrgs_batch b, Consts k, float4
         camera_center(cam, cpos);
         Fwd f;
         forward_gaussian(a, cam, cpos, e, k.lowpass, f);
-        valid = f.det > 0.f && isfinite(f.Q00) && isfinite(f.Q01) && isfinite(f.Q11) &&
-                isfinite(f.mx) && isfinite(f.my) && isfinite(f.rgb[0]) && isfinite(f.rgb[1]) &&
-                isfinite(f.rgb[2]);
+        const bool finite_out = isfinite(f.Q00) && isfinite(f.Q01) && isfinite(f.Q11) && isfinite(f.mx) &&
+                                isfinite(f.my) && isfinite(f.rgb[0]) && isfinite(f.rgb[1]) && isfinite(f.rgb[2]);
+        bad = f.det > 0.f && !finite_out;
+        valid = f.det > 0.f && finite_out;
         if (valid) {
             // conservative footprint of {alpha >= alpha_min}: the ellipse
             // d^T Q d <= 2 ln(o / alpha_min) has half-widths k sqrt(a), k sqrt(c)
@@ -291,6 +295,10 @@ __global__ __launch_bounds__(256) void k_project(ivrgs_batch b, Consts k, float4
     rec[3 * r + 2] = r2;
     rect[r] = rc;
     depth[r] = (rc.x | rc.y) ? __float_as_uint(z32) : 0xFFFFFFFFu;
+    if (nonfinite) {
+        const uint64_t nb = __ballot(bad);
+        if (nb && lane_id() == (int)__builtin_ctzll(nb)) atomicAdd(nonfinite, (unsigned long long)__popcll(nb));
+    }
 }
 
 // Shading backward (Eq. 3): from the record's colour gradient gr[GCR..GCB],
@@ -809,12 +817,12 @@ __global__ __launch_bounds__(256) void k_explore_step(const float *__restrict__ 
 // ----------------------------------------------------------------------------
 // host launchers
 hipError_t launch_project(const ivrgs_batch &b, const Consts &k, float *rec, uint32_t *rect, uint32_t *depth,
-                          hipStream_t s) {
+                          int64_t *nonfinite, hipStream_t s) {
     if (b.n_jobs == 0 || b.max_job_count == 0) return hipSuccess;
     dim3 grid((b.max_job_count + 255) / 256, b.n_jobs);
     TimedScope ts(TK_PROJECT, s);
     hipLaunchKernelGGL(k_project, grid, dim3(256), 0, s, b, k, reinterpret_cast<float4 *>(rec),
-                       reinterpret_cast<uint2 *>(rect), depth);
+                       reinterpret_cast<uint2 *>(rect), depth, reinterpret_cast<unsigned long long *>(nonfinite));
     return hipGetLastError();
 }
 

@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void k_ssim_reduce(const float *__restrict__ p
 __global__ __launch_bounds__(256) void k_ssim_bwd(const float *__restrict__ x, const float *__restrict__ y, int H,
                                                   int W, SsimTaps taps, const float *__restrict__ abc,
                                                   const float *__restrict__ grad_mean, double inv,
-                                                  float *__restrict__ grad_x) {
+                                                  float ssim_w, float l1_w, float *__restrict__ grad_x) {
     __shared__ float sa[3][kReg][kReg + 1];
     __shared__ float hs[3][kReg][kSsimTile];
     const int Ho = H - kWin + 1, Wo = W - kWin + 1;
@@ -180,8 +180,12 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float *__restrict__ x, c
     }
     const int64_t at = (int64_t)c * H * W + (int64_t)qy * W + qx;
     const float xq = x[at], yq = y[at];
-    const float scale = (float)((double)grad_mean[0] * inv);
-    grad_x[at] = scale * (bA + 2.0f * xq * bB + yq * bC);
+    // dL/d(mean SSIM) from the device (ivrgs_ssim_bwd) or the host weight
+    const float scale = (float)((grad_mean ? (double)grad_mean[0] : (double)ssim_w) * inv);
+    float gq = scale * (bA + 2.0f * xq * bB + yq * bC);
+    // the L1 term: l1_w sign(x - y), with sign(0) = 0
+    if (l1_w != 0.0f) gq = fmaf(l1_w, (float)((xq > yq) - (xq < yq)), gq);
+    grad_x[at] = gq;
 }
 
 }  // namespace
@@ -222,7 +226,19 @@ hipError_t launch_ssim_bwd(const float *x, const float *y, int channels, int H, 
     const int Ho = H - kWin + 1, Wo = W - kWin + 1;
     const dim3 grid((W + kSsimTile - 1) / kSsimTile, (H + kSsimTile - 1) / kSsimTile, channels);
     hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, s, x, y, H, W, ssim_taps(), ws, grad_mean,
-                       1.0 / ((double)channels * Ho * Wo), grad_x);
+                       1.0 / ((double)channels * Ho * Wo), 0.0f, 0.0f, grad_x);
+    return hipGetLastError();
+}
+
+hipError_t launch_photometric_grad(const float *x, const float *y, int channels, int H, int W, float lam,
+                                   float *grad_x, const float *ws, hipStream_t s) {
+    const int Ho = H - kWin + 1, Wo = W - kWin + 1;
+    const dim3 grid((W + kSsimTile - 1) / kSsimTile, (H + kSsimTile - 1) / kSsimTile, channels);
+    // L = (1 - lam) mean |x - y| + lam (1 - mean SSIM): the SSIM mean enters
+    // with weight -lam, each |x - y| with (1 - lam) / (channels H W)
+    const float l1_w = (float)((1.0 - (double)lam) / ((double)channels * H * W));
+    hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, s, x, y, H, W, ssim_taps(), ws, nullptr,
+                       1.0 / ((double)channels * Ho * Wo), -lam, l1_w, grad_x);
     return hipGetLastError();
 }
 

@@ -16,9 +16,9 @@ scaled by 0.1, and the normal consistency and the other regularisers by
 
 Readings where the paper is silent: SSIM after Wang et al. (2004), an 11x11
 Gaussian window of sigma 1.5, C1 = 0.01^2, C2 = 0.03^2, averaged over the
-windows that lie inside the image (on the device: the HIP kernels behind
-ivrgs_ssim_fwd / ivrgs_ssim_bwd, the target taken as a constant; the torch
-form below serves CPU tensors); depth and normal maps are divided by the
+windows that lie inside the image (the HIP kernels behind ivrgs_ssim_fwd /
+ivrgs_ssim_bwd / ivrgs_photometric_grad, the target taken as a constant);
+depth and normal maps are divided by the
 alpha map before use (pixels with alpha <= 0.5 are left out); the
 pseudo-normal is the cross product of the central differences of the
 back-projected points, turned to face the camera and taken to world space;
@@ -28,16 +28,9 @@ channels of their absolute values.
 from __future__ import annotations
 
 import torch
-import torch.nn.functional as F
 
 from . import native as N
 from .raster import _stream
-
-
-def _gauss_window(size: int, sigma: float, dtype, device):
-    x = torch.arange(size, dtype=dtype, device=device) - (size - 1) / 2
-    g = torch.exp(-(x * x) / (2 * sigma * sigma))
-    return g / g.sum()
 
 
 class _SsimFn(torch.autograd.Function):
@@ -66,39 +59,55 @@ class _SsimFn(torch.autograd.Function):
         return gx, None
 
 
-def ssim(x: torch.Tensor, y: torch.Tensor, window: int = 11, sigma: float = 1.5) -> torch.Tensor:
-    """Mean SSIM of two images [C, H, W] with values in [0, 1].  Device
-    tensors go through the HIP kernels (float32, 11x11 window of sigma 1.5;
-    no gradient to the target)."""
-    if x.is_cuda:
-        if window != 11 or sigma != 1.5:
-            raise ValueError("the device SSIM takes the 11x11 window of sigma 1.5")
-        if x.dim() != 3 or y.shape != x.shape or x.dtype != torch.float32 or y.dtype != torch.float32 \
-                or y.device != x.device:
-            raise ValueError("ssim: expected float32 [C, H, W] image and target of one shape and device")
-        if x.shape[1] < 11 or x.shape[2] < 11:
-            raise ValueError("ssim: height and width must be at least 11")
-        return _SsimFn.apply(x.contiguous(), y.detach().contiguous())
-    c = x.shape[0]
-    g = _gauss_window(window, sigma, x.dtype, x.device)
-    wx = g.view(1, 1, 1, window).expand(c, 1, 1, window)
-    wy = g.view(1, 1, window, 1).expand(c, 1, window, 1)
+def _check_pair(x, y):
+    if not (x.is_cuda and y.is_cuda):
+        raise ValueError("expected device tensors (the kernels run on the GPU; the CPU reference is "
+                         "the oracle's, not part of this package)")
+    if x.dim() != 3 or y.shape != x.shape or x.dtype != torch.float32 or y.dtype != torch.float32 \
+            or y.device != x.device:
+        raise ValueError("expected float32 [C, H, W] image and target of one shape and device")
+    if x.shape[1] < 11 or x.shape[2] < 11:
+        raise ValueError("height and width must be at least 11")
 
-    def blur(t):
-        return F.conv2d(F.conv2d(t[None], wx, groups=c), wy, groups=c)[0]  # 'valid' windows only
 
-    mx, my = blur(x), blur(y)
-    sxx = blur(x * x) - mx * mx
-    syy = blur(y * y) - my * my
-    sxy = blur(x * y) - mx * my
-    c1, c2 = 0.01 ** 2, 0.03 ** 2
-    s = ((2 * mx * my + c1) * (2 * sxy + c2)) / ((mx * mx + my * my + c1) * (sxx + syy + c2))
-    return s.mean()
+def ssim(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+    """Mean SSIM of two device images [C, H, W] with values in [0, 1],
+    through the HIP kernels (float32, 11x11 window of sigma 1.5; no gradient
+    to the target)."""
+    _check_pair(x, y)
+    return _SsimFn.apply(x.contiguous(), y.detach().contiguous())
+
+
+class _PhotometricFn(torch.autograd.Function):
+    """(1 - lam) mean |x - y| + lam (1 - SSIM(x, y)); the backward is one
+    launch of ivrgs_photometric_grad over the SSIM forward's workspace."""
+
+    @staticmethod
+    def forward(ctx, x, y, lam):
+        c, h, w = (int(v) for v in x.shape)
+        nbytes = N.ivrgs_ssim_workspace_size(c, h, w)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+        s = torch.empty((), dtype=torch.float32, device=x.device)
+        N.ivrgs_ssim_fwd(x.data_ptr(), y.data_ptr(), c, h, w, s.data_ptr(), ws.data_ptr(), nbytes, _stream())
+        ctx.save_for_backward(x, y, ws)
+        ctx.lam = lam
+        return (1 - lam) * (x - y).abs().mean() + lam * (1 - s)
+
+    @staticmethod
+    def backward(ctx, g):
+        x, y, ws = ctx.saved_tensors
+        c, h, w = (int(v) for v in x.shape)
+        gx = torch.empty_like(x)
+        N.ivrgs_photometric_grad(x.data_ptr(), y.data_ptr(), c, h, w, ctx.lam, gx.data_ptr(), ws.data_ptr(),
+                                 ws.numel(), _stream())
+        return gx * g, None, None
 
 
 def photometric(rgba: torch.Tensor, target: torch.Tensor, lam: float = 0.2) -> torch.Tensor:
-    """(1 - lam) mean |rgba - target| + lam (1 - SSIM), colour and alpha."""
-    return (1 - lam) * (rgba - target).abs().mean() + lam * (1 - ssim(rgba, target))
+    """(1 - lam) mean |rgba - target| + lam (1 - SSIM), colour and alpha
+    (device tensors; no gradient to the target)."""
+    _check_pair(rgba, target)
+    return _PhotometricFn.apply(rgba.contiguous(), target.detach().contiguous(), float(lam))
 
 
 def pseudo_normal(depth: torch.Tensor, alpha: torch.Tensor, cam) -> tuple[torch.Tensor, torch.Tensor]:

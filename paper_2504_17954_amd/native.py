@@ -26,7 +26,7 @@ EXPORTS = ("ivrgs_workspace_size", "ivrgs_tiles_per_job", "ivrgs_compose", "ivrg
            "ivrgs_vq_workspace_size", "ivrgs_vq_fit", "ivrgs_vq_assign", "ivrgs_vq_compose",
            "ivrgs_sh_color", "ivrgs_sh_color_bwd", "ivrgs_render_aux_fwd", "ivrgs_render_aux_bwd",
            "ivrgs_get_error", "ivrgs_ssim_workspace_size", "ivrgs_ssim_fwd", "ivrgs_ssim_bwd",
-           "ivrgs_vq_fit_batch_workspace_size", "ivrgs_vq_fit_batch")
+           "ivrgs_vq_fit_batch_workspace_size", "ivrgs_vq_fit_batch", "ivrgs_photometric_grad")
 TIMING_KINDS = ("project", "tile_count", "scatter", "depth_sort", "render_fwd", "render_bwd",
                 "project_bwd", "compose", "fill", "cull", "edit_bwd", "vq", "sh", "aux")
 
@@ -69,7 +69,7 @@ class ivrgs_params(C.Structure):
 
 
 class ivrgs_projected(C.Structure):
-    _fields_ = [("rec", C.c_void_p), ("rect", C.c_void_p), ("depth", C.c_void_p)]
+    _fields_ = [("rec", C.c_void_p), ("rect", C.c_void_p), ("depth", C.c_void_p), ("nonfinite", C.c_void_p)]
 
 
 class ivrgs_bins(C.Structure):
@@ -179,6 +179,8 @@ def load(path: str = LIB_PATH):
     lib.ivrgs_ssim_fwd.restype = C.c_int
     lib.ivrgs_ssim_bwd.argtypes = [P, P, I32, I32, I32, P, P, P, C.c_size_t, P]
     lib.ivrgs_ssim_bwd.restype = C.c_int
+    lib.ivrgs_photometric_grad.argtypes = [P, P, I32, I32, I32, C.c_float, P, P, C.c_size_t, P]
+    lib.ivrgs_photometric_grad.restype = C.c_int
     lib.ivrgs_get_error.argtypes = [P, P, P, P]
     lib.ivrgs_get_error.restype = C.c_int
     lib.ivrgs_timing_enable.argtypes = [C.c_uint32]
@@ -299,8 +301,9 @@ def ivrgs_render_aux_bwd(batch, params, proj, bins, attr_ptr, n_attr: int, aux_p
 
 
 def ivrgs_get_error(bins, stream) -> tuple[int, int]:
-    """(device error bits, pairs required) of the last bin sort on these bins
-    (waits for the stream)."""
+    """(device error bits, pairs required) over every bin sort on these bins
+    since the previous call: the OR of their bits and the largest count;
+    clears the sticky words (waits for the stream)."""
     err, need = C.c_int64(0), C.c_int64(0)
     check(load().ivrgs_get_error(ref(bins), stream, C.cast(C.byref(err), C.c_void_p),
                                  C.cast(C.byref(need), C.c_void_p)), "ivrgs_get_error")
@@ -320,6 +323,12 @@ def ivrgs_ssim_bwd(x_ptr, y_ptr, channels: int, height: int, width: int, grad_me
                    ws_bytes, stream):
     check(load().ivrgs_ssim_bwd(x_ptr, y_ptr, channels, height, width, grad_mean_ptr, grad_x_ptr, ws_ptr,
                                 ws_bytes, stream), "ivrgs_ssim_bwd")
+
+
+def ivrgs_photometric_grad(x_ptr, y_ptr, channels: int, height: int, width: int, lam: float, grad_x_ptr,
+                           ws_ptr, ws_bytes, stream):
+    check(load().ivrgs_photometric_grad(x_ptr, y_ptr, channels, height, width, lam, grad_x_ptr, ws_ptr,
+                                        ws_bytes, stream), "ivrgs_photometric_grad")
 
 
 def ivrgs_project(batch, params, proj, stream):

@@ -160,6 +160,7 @@ class Renderer:
         self.n_records = -1
         self.n_jobs = -1
         self.rec = self.rect = self.depth = self.tile_start = self.sorted = self.status = self.ws = None
+        self.nonfinite = None
         self.generation = 0
         self._key = None
         self._bin_fp = None  # inputs of the binning the buffers hold
@@ -185,7 +186,8 @@ class Renderer:
             self._bin_fp = None
             self.sorted = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev)
         if self.status is None:
-            self.status = torch.zeros(4, dtype=torch.int64, device=dev)
+            self.status = torch.zeros(8, dtype=torch.int64, device=dev)
+            self.nonfinite = torch.zeros(1, dtype=torch.int64, device=dev)
         need = N.ivrgs_workspace_size(batch, p, self.capacity)
         if need == 0:
             raise ValueError("ivrgs_workspace_size rejected the batch")
@@ -222,7 +224,8 @@ class Renderer:
         return self.project_and_bin(batch)
 
     def _structs(self, batch):
-        proj = N.ivrgs_projected(self.rec.data_ptr(), self.rect.data_ptr(), self.depth.data_ptr())
+        proj = N.ivrgs_projected(self.rec.data_ptr(), self.rect.data_ptr(), self.depth.data_ptr(),
+                                 self.nonfinite.data_ptr())
         bins = N.ivrgs_bins(self.tile_start.data_ptr(), self.sorted.data_ptr(), self.capacity,
                             self.status.data_ptr())
         return proj, bins
@@ -276,6 +279,8 @@ class Renderer:
                 self.grow(int(int(st[0]) * 1.25) + 1024)
                 self._ensure(batch)
                 proj, bins = self._structs(batch)
+                # the overflow is handled: drop it from the sticky words
+                self.status[4:6].zero_()
                 N.ivrgs_bin_sort(batch, p, proj, bins, self.ws.data_ptr(), self.ws.numel(), s)
         self.generation += 1
         self._bin_fp = self._fingerprint(batch)
@@ -334,8 +339,9 @@ class Renderer:
         return out
 
     def verify(self):
-        """Raise if the last binning overflowed the pair capacity (waits for
-        the stream); else return the pairs it required."""
+        """Raise if a binning since the last check overflowed the pair
+        capacity (waits for the stream); else return the largest pair count
+        they required."""
         bins = N.ivrgs_bins(self.tile_start.data_ptr(), _ptr(self.sorted), self.capacity, self.status.data_ptr())
         err, need = N.ivrgs_get_error(bins, _stream())
         if err & N.DEV_E_CAPACITY:
@@ -346,6 +352,15 @@ class Renderer:
 
     def pairs(self) -> int:
         return int(self.status[0].item())
+
+    def nonfinite_count(self) -> int:
+        """Gaussian-views culled for a NaN or infinite value since the
+        renderer was created (or since `clear_nonfinite`).  Waits."""
+        return 0 if self.nonfinite is None else int(self.nonfinite.item())
+
+    def clear_nonfinite(self):
+        if self.nonfinite is not None:
+            self.nonfinite.zero_()
 
 
 class _RasterFn(torch.autograd.Function):

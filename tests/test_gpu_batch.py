@@ -184,6 +184,35 @@ def bf16_round(x):
     return r.astype(np.uint32).view(np.float32)
 
 
+def bf16_ulp(x):
+    a = np.abs(np.asarray(x, np.float32)).astype(np.float64)
+    e = np.floor(np.log2(np.maximum(a, 1e-30)))
+    return np.where(a > 0, 2.0 ** (e - 7), 2.0 ** -133)
+
+
+def mlp_logit_bound(x16, W1, b1, W2, b2, w3, b3):
+    """FP64 reference logits of the BF16 MLP and, per Gaussian, the largest
+    difference an FP32 evaluation in any summation order may show: one bf16
+    ulp on each first-layer activation whose FP32 sum (17 terms) lies within
+    its accumulation error of a bf16 rounding boundary, times that
+    activation's largest effect on the logit, plus the FP32 accumulation
+    error of the second layer and the output (gamma_n = n 2^-24 times the
+    sums of magnitudes)."""
+    W1, W2 = W1.astype(np.float64), W2.astype(np.float64)
+    b1, b2, w3 = (np.asarray(v, np.float64) for v in (b1, b2, w3))
+    v1 = x16.astype(np.float64) @ W1.T + b1
+    e1 = 17 * 2.0 ** -24 * (np.abs(x16) @ np.abs(W1).T + np.abs(b1))
+    lo = bf16_round(np.maximum(v1 - e1, 0))
+    hi = bf16_round(np.maximum(v1 + e1, 0))
+    h1 = bf16_round(np.maximum(v1, 0)).astype(np.float64)
+    reach = np.abs(W2).T @ np.abs(w3)
+    amb = ((lo != hi) * np.maximum(bf16_ulp(lo), bf16_ulp(hi)) * reach[None, :]).sum(1)
+    h2 = np.maximum(h1 @ W2.T + b2, 0)
+    g = 66 * 2.0 ** -24
+    acc = g * ((np.abs(h1) @ np.abs(W2).T + np.abs(b2)) @ np.abs(w3)) + g * (np.abs(h2) @ np.abs(w3) + abs(b3))
+    return h2 @ w3 + b3, amb + acc
+
+
 def random_culler(dev, seed=0, threshold=0.0):
     from paper_2504_17954_amd import cull as CU
     torch.manual_seed(seed)
@@ -194,9 +223,10 @@ def random_culler(dev, seed=0, threshold=0.0):
 
 
 def test_cull_mlp_matches_reference(dev):
-    """The BF16 matrix-core MLP equals the same network evaluated in numpy
-    with BF16-rounded weights, inputs and first-layer activations and FP32
-    accumulation (exercises the MFMA operand layouts)."""
+    """The BF16 matrix-core MLP equals the same network evaluated in FP64
+    with BF16-rounded weights, inputs and first-layer activations, every
+    logit within the bound of an FP32 evaluation (exercises the MFMA operand
+    layouts)."""
     from paper_2504_17954_amd import cull as CU
     m = I.small_scene(5000, 801, log_scale_mu=-3.0)
     planes = I.plain_planes(m)
@@ -218,13 +248,12 @@ def test_cull_mlp_matches_reference(dev):
     w2 = w.w2.cpu().numpy().astype(np.int32).astype(np.uint32) << 16
     W1 = (w1 & 0xFFFF0000).astype(np.uint32).view(np.float32)
     W2 = (w2 & 0xFFFF0000).astype(np.uint32).view(np.float32)
-    h1 = bf16_round(np.maximum(x16.astype(np.float64) @ W1.T + w.b1.cpu().numpy(), 0).astype(np.float32))
-    h2 = np.maximum(h1.astype(np.float64) @ W2.T + w.b2.cpu().numpy(), 0)
-    ref = h2 @ w.w3.cpu().numpy() + w.b3
+    ref, bound = mlp_logit_bound(x16, W1, w.b1.cpu().numpy(), W2, w.b2.cpu().numpy(), w.w3.cpu().numpy(),
+                                 float(w.b3))
     err = np.abs(got - ref)
-    say(f"cull mlp: max err {err.max():.3e}, max |logit| {np.abs(ref).max():.3e}")
-    # bf16 rounding of h1 can differ by one ulp when FP32 sums round differently
-    assert np.quantile(err, 0.999) <= 2e-3 * (1 + np.abs(ref).max())
+    say(f"cull mlp: max err {err.max():.3e}, max |logit| {np.abs(ref).max():.3e}, "
+        f"worst err / bound {(err / bound).max():.3f}")
+    assert np.all(err <= bound), np.argsort(-(err / bound))[:5]
     assert jobs.device[0, 2].item() == 5000
 
 

@@ -274,6 +274,36 @@ def test_nonfinite_gaussians_are_culled(dev):
     rgba = rnd.forward(to_dev(bad, dev), R.camera_table([cam]), R.Jobs.single(bad["mean"].shape[1]),
                        edits_t=R.default_edits(dev))[0].cpu().numpy()
     check_image(rgba, ref, "non-finite culled")
+    # culled and counted: three Gaussians, once per projection
+    assert rnd.nonfinite_count() == 3
+    rnd.forward(to_dev(bad, dev), R.camera_table([cam, cam]), R.Jobs.views(bad["mean"].shape[1], [0, 1]),
+                edits_t=R.default_edits(dev))
+    assert rnd.nonfinite_count() == 3 + 6
+    rnd.clear_nonfinite()
+    rnd.forward(to_dev(planes, dev), R.camera_table([cam]), R.Jobs.single(planes["mean"].shape[1]),
+                edits_t=R.default_edits(dev))
+    assert rnd.nonfinite_count() == 0
+
+
+def test_capacity_error_is_sticky_until_read(dev):
+    """With the deferred check, an overflow in an earlier binning stays
+    reported (with the largest requirement) after later binnings fit, until
+    ivrgs_get_error reads and clears it."""
+    planes, cam, prm = c1_setup()
+    small = {k: v[:, :200].copy() for k, v in planes.items()}
+    rnd = R.Renderer(R.Settings(128, 128), capacity=2000, check="defer")
+    cams = R.camera_table([cam])
+    rnd.forward(to_dev(planes, dev), cams, R.Jobs.single(10_000), edits_t=R.default_edits(dev))
+    big = int(rnd.status[0].item())
+    assert big > 2000
+    rnd.forward(to_dev(small, dev), cams, R.Jobs.single(200), edits_t=R.default_edits(dev))
+    small_pairs = int(rnd.status[0].item())
+    assert small_pairs <= 2000 and int(rnd.status[1].item()) == 0
+    bins = rnd._structs(None)[1]
+    assert N.ivrgs_get_error(bins, R._stream()) == (N.DEV_E_CAPACITY, big)
+    # read and cleared: now only the last (fitting) binning counts
+    assert N.ivrgs_get_error(bins, R._stream()) == (0, small_pairs)
+    assert rnd.verify() == small_pairs
 
 
 def test_capacity_overflow_regrows(dev):
@@ -327,6 +357,63 @@ def test_render_bwd_c1(dev, px):
                      edits_t=R.default_edits(dev))
     g = {k: v.cpu().numpy() for k, v in g.items()}
     check_grads(g, g_ref, f"c1 bwd px={px}", exclude=grad_exclusions(planes, cam, prm))
+
+
+BG = (0.3, 0.7, 0.15)
+
+
+@pytest.mark.parametrize("px", [1, 2, 4])
+def test_render_bwd_background(dev, px):
+    """A coloured background puts T_final * bg into every alpha gradient (the
+    colour behind each Gaussian includes it): C1 against the oracle at 1, 2
+    and 4 pixels per lane."""
+    w = I.c1(0)
+    planes = I.plain_planes(w.models[0])
+    cam = I.look_at((0.0, -4.0, 0.0), width=128, height=128)
+    prm = O.Params(128, 128, bg=BG)
+    say(f"render_bwd with background {BG}, bwd_px={px}")
+    ref = O.render(planes, cam, prm)
+    dl = upstream(ref, 2011, ref["rgba"].shape)
+    g_ref, _ = O.backward(planes, cam, prm, dl)
+    rnd = R.Renderer(R.Settings(128, 128, bg=BG, bwd_px=px))
+    pd = to_dev(planes, dev)
+    cams, jobs = R.camera_table([cam]), R.Jobs.single(10_000)
+    rgba = rnd.forward(pd, cams, jobs, edits_t=R.default_edits(dev))
+    check_image(rgba[0].cpu().numpy(), ref, f"c1 fwd bg px={px}")
+    g = rnd.backward(pd, cams, jobs, rgba, torch.from_numpy(dl[None].astype(np.float32)).to(dev),
+                     edits_t=R.default_edits(dev))
+    g = {k: v.cpu().numpy() for k, v in g.items()}
+    check_grads(g, g_ref, f"c1 bwd bg px={px}", exclude=grad_exclusions(planes, cam, prm))
+
+
+def test_render_bwd_background_segmented(dev):
+    """Tile lists far longer than 128 records are cut into segments, and each
+    segment's backward starts from the forward's checkpoint of (T, C): with a
+    coloured background the colour behind a Gaussian must still include
+    T_final * bg in every segment.  A dense cluster of 6000 Gaussians in a
+    64x64 image gives lists of thousands of records."""
+    m = I.small_scene(6000, 811, log_scale_mu=-3.3)
+    m.planes["mean"] *= np.float32(0.8)
+    planes = I.plain_planes(m)
+    W = H = 64
+    cam = I.look_at((0.2, -4.0, 0.3), width=W, height=H)
+    prm = O.Params(W, H, bg=BG)
+    ref = O.render(planes, cam, prm)
+    dl = upstream(ref, 2012, ref["rgba"].shape)
+    g_ref, _ = O.backward(planes, cam, prm, dl)
+    rnd = R.Renderer(R.Settings(W, H, bg=BG))
+    pd = to_dev(planes, dev)
+    cams, jobs = R.camera_table([cam]), R.Jobs.single(m.n)
+    rgba = rnd.forward(pd, cams, jobs, edits_t=R.default_edits(dev))
+    starts = rnd.tile_start[:N.ivrgs_tiles_per_job(rnd.settings.params()) + 1].cpu().numpy()
+    lens = np.diff(starts.astype(np.int64))
+    say(f"segmented backward with background: longest list {lens.max()}, lists > 128: {(lens > 128).sum()}")
+    assert lens.max() > 1024 and (lens > 128).sum() >= 12
+    check_image(rgba[0].cpu().numpy(), ref, "cluster fwd bg")
+    g = rnd.backward(pd, cams, jobs, rgba, torch.from_numpy(dl[None].astype(np.float32)).to(dev),
+                     edits_t=R.default_edits(dev))
+    g = {k: v.cpu().numpy() for k, v in g.items()}
+    check_grads(g, g_ref, "cluster bwd bg", exclude=grad_exclusions(planes, cam, prm))
 
 
 def test_backward_overwrites_stale_gradients(dev):
@@ -483,6 +570,39 @@ def test_c2_fullsize_sampled(dev, c2_planes, view):
     # untouched Gaussians get exactly zero
     for k in R.PLANES:
         assert np.all(g[k][:, ~touched] == 0), k
+
+
+@pytest.fixture(scope="module")
+def c3_scene():
+    w = I.c3()
+    rows = np.stack([e.row() for e in w.edits])
+    pl, mid = O.compose([m.planes for m in w.models], rows)
+    return w, rows, pl, mid
+
+
+@pytest.mark.parametrize("view", [0, 31])
+def test_c3_fullsize_sampled(dev, c3_scene, view):
+    """The composed forward in the launch configuration the benchmark times:
+    8 nested-shell models of 150k Gaussians (1.2M) with per-model transfer-
+    function and lighting edits (opacity scale up to 2, recolour, orbital
+    lights, intensity), composed on the device, 1024x1024, 256 records per
+    binning chunk; 3000 sampled pixels against the oracle's render of its
+    own composition."""
+    w, rows, pl, mid = c3_scene
+    cam = w.cameras[view]
+    W = H = 1024
+    prm = O.Params(W, H)
+    say(f"c3 full size, view {view}: compose + forward, 3000 sampled pixels")
+    out, mid_d = R.compose([to_dev(m.planes, dev) for m in w.models], w.edits)
+    assert np.array_equal(mid_d.cpu().numpy(), mid)
+    rnd = R.Renderer(R.Settings(W, H, fwd_px=1, sort_chunk=256))
+    rgba = rnd.forward(out, R.camera_table([cam]), R.Jobs.single(mid.size), model_id=mid_d,
+                       edits_t=R.edit_table(w.edits, dev))
+    img = rgba[0].cpu().numpy()
+    say(f"c3 view {view}: {rnd.pairs()} pairs")
+    pix = sample_pixels(W, H, 3000, 500 + view)
+    ref = O.render(pl, cam, prm, model_id=mid, edits=rows, pix=pix)
+    check_image(img[:, pix[:, 1], pix[:, 0]].T, ref, f"c3 view {view} sampled")
 
 
 @pytest.mark.parametrize("n", [511, 512, 513, 4095, 4096, 4097, 8193])

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 import torch
 
+from oracle import explore as OX
 from oracle import ssim as OS
 from paper_2504_17954_amd import losses as L
 from paper_2504_17954_amd import native as N
@@ -97,4 +98,54 @@ def test_ssim_shape_errors(dev):
         N.ivrgs_ssim_fwd(y.data_ptr(), y.data_ptr(), 2, 20, 40, out.data_ptr(), ws.data_ptr(), 16, None)
     with pytest.raises(N.IvrgsError):
         N.ivrgs_ssim_fwd(None, y.data_ptr(), 2, 20, 40, out.data_ptr(), ws.data_ptr(), 16, None)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("shape,seed,lam", [((3, 11, 11), 11, 0.2), ((4, 40, 52), 12, 0.2),
+                                            ((4, 100, 130), 13, 0.0), ((2, 27, 100), 14, 1.0),
+                                            ((4, 800, 800), 15, 0.2)])
+def test_photometric_grad_matches_oracle(dev, shape, seed, lam):
+    """ivrgs_photometric_grad: the gradient of (1 - lam) mean|x - y| +
+    lam (1 - SSIM) against the oracle's (the exploration objective, and the
+    photometric term of training), through the C ABI; the autograd Function
+    of the losses gives the same gradient and the loss value."""
+    x, y = pair(shape, seed)
+    y[:, :3, :5] = x[:, :3, :5]  # exact ties: sign(0) = 0 on both sides
+    say(f"photometric grad {shape} lam={lam}")
+    want, gwant = OX.photometric(x.astype(np.float64), y.astype(np.float64), lam)
+    c, h, w = shape
+    xd, yd = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+    nbytes = N.ivrgs_ssim_workspace_size(c, h, w)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    s = torch.empty((), device=dev)
+    g = torch.full_like(xd, float("nan"))
+    N.ivrgs_ssim_fwd(xd.data_ptr(), yd.data_ptr(), c, h, w, s.data_ptr(), ws.data_ptr(), nbytes, None)
+    N.ivrgs_photometric_grad(xd.data_ptr(), yd.data_ptr(), c, h, w, lam, g.data_ptr(), ws.data_ptr(), nbytes,
+                             None)
+    g = g.cpu().numpy()
+    tol = 1e-3 * np.abs(gwant) + 1e-5 * np.abs(gwant).max()
+    bad = np.abs(g - gwant) > tol
+    say(f"  gradient outside {bad.sum()} / {g.size}, worst {(np.abs(g - gwant) / tol).max():.3f}")
+    assert not bad.any()
+    xr = xd.clone().requires_grad_(True)
+    loss = L.photometric(xr, yd, lam)
+    loss.backward()
+    assert abs(float(loss.detach()) - want) <= 1e-5 * max(1.0, abs(want))
+    assert torch.equal(xr.grad.cpu(), torch.from_numpy(g))
+
+
+def test_photometric_grad_argument_errors(dev):
+    x = torch.zeros((4, 20, 20), device=dev)
+    nbytes = N.ivrgs_ssim_workspace_size(4, 20, 20)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    for lam in (-0.1, 1.5, float("nan")):
+        with pytest.raises(N.IvrgsError):
+            N.ivrgs_photometric_grad(x.data_ptr(), x.data_ptr(), 4, 20, 20, lam, x.data_ptr(), ws.data_ptr(),
+                                     nbytes, None)
+    with pytest.raises(N.IvrgsError):
+        N.ivrgs_photometric_grad(x.data_ptr(), x.data_ptr(), 4, 20, 20, 0.2, x.data_ptr(), ws.data_ptr(), 16,
+                                 None)
+    with pytest.raises(N.IvrgsError):
+        N.ivrgs_photometric_grad(x.data_ptr(), x.data_ptr(), 4, 20, 9, 0.2, x.data_ptr(), ws.data_ptr(),
+                                 nbytes, None)
     torch.cuda.synchronize()

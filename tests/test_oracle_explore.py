@@ -4,6 +4,7 @@ lambda, b and light angles) against central finite differences of the whole
 FP64 pipeline, Adam against its closed forms and a step computed by hand,
 the light-angle convention, and recovery of known parameters.  CPU only."""
 import numpy as np
+import pytest
 
 import oracle as O
 from oracle import explore as X
@@ -46,6 +47,54 @@ def test_param_gradient_matches_finite_differences():
         assert abs(g[j] - ref) <= 2e-3 * abs(ref) + 1e-4 * np.abs(g).max(), (j, g[j], ref)
     K = len(planes)
     assert np.abs(g[4 * K + 8:]).min() > 0.0  # the angles do move the image
+
+
+@pytest.mark.parametrize("lam", [0.2, 1.0])
+def test_photometric_objective_gradient_matches_finite_differences(lam):
+    """The exploration objective (1 - lam) mean|RGBA - t| + lam (1 - SSIM)
+    (Sec. 4.6; lam = 0.2 from the appendix, and the SSIM term alone):
+    its theta gradient against central differences of the loss value of the
+    whole FP64 pipeline.  A target with values away from the render keeps
+    every |.| away from its kink within a step."""
+    planes, base, theta, cam = scene(seed=13)
+    prm = O.Params(32, 32, alpha_min=1e-9, T_min=1e-12, alpha_max=0.999999)
+    rng = np.random.default_rng(5)
+    img = X.render_params(planes, base, theta, cam, prm)["rgba"]
+    # unclipped: every |RGBA - t| >= 0.05 (a clip to [0, 1] would put targets
+    # at 0 beside pixels whose colour, c_v may be negative, is near 0)
+    target = img + rng.choice([-1.0, 1.0], img.shape) * rng.uniform(0.05, 0.3, img.shape)
+    loss0, g, _ = X.loss_and_grad(planes, base, theta, cam, prm, target, lam)
+
+    def loss(th):
+        return X.photometric(X.render_params(planes, base, th, cam, prm)["rgba"], target, lam)[0]
+
+    assert loss(theta) == pytest.approx(loss0, rel=1e-14)
+    # fourth-order central differences: SSIM's small constants make it
+    # strongly curved, and the composed planes are FP32, so h cannot shrink
+    for j in range(theta.size):
+        f = {}
+        for k in (-2, -1, 1, 2):
+            th = theta.copy()
+            th[j] += k * H
+            f[k] = loss(th)
+        ref = (-f[2] + 8 * f[1] - 8 * f[-1] + f[-2]) / (12 * H)
+        assert abs(g[j] - ref) <= 2e-3 * abs(ref) + 1e-4 * np.abs(g).max(), (j, g[j], ref)
+
+
+def test_photometric_closed_forms():
+    """An image against itself: zero L1 and SSIM 1, so the loss is 0 and only
+    the SSIM gradient (zero at the optimum) remains; a constant offset d
+    against a constant target: L1 = |d|, and the L1 part of the gradient is
+    (1 - lam) sign(d) / n."""
+    rng = np.random.default_rng(2)
+    x = rng.uniform(0.2, 0.8, (4, 24, 24))
+    loss, dl = X.photometric(x, x, 0.2)
+    assert loss == pytest.approx(0.0, abs=1e-14)
+    np.testing.assert_allclose(dl, 0.0, atol=1e-14)
+    y = np.full((4, 24, 24), 0.3)
+    loss, dl = X.photometric(y + 0.1, y, 0.0)
+    assert loss == pytest.approx(0.1, rel=1e-12)
+    np.testing.assert_allclose(dl, 1.0 / y.size, rtol=1e-12)
 
 
 def test_headlight_only_gives_no_angle_gradient():
@@ -105,8 +154,8 @@ def test_adam_mask_freezes_groups():
 
 def test_explore_recovers_known_parameters():
     """Target = render under known parameters; from a perturbed start, Adam
-    at the paper's learning rate lowers the L1 loss and moves the palette and
-    opacity scales toward the known values."""
+    at the paper's learning rate lowers the L1 + SSIM loss and moves the
+    palette and opacity scales toward the known values."""
     planes, base, truth, cam = scene(seed=21, n=60)
     prm = O.Params(32, 32)
     target = X.render_params(planes, base, truth, cam, prm)["rgba"]

@@ -248,6 +248,52 @@ def test_two_gaussian_order():
         np.testing.assert_allclose(out[3], red + blue, atol=1e-12)
 
 
+def test_two_gaussian_gradient_with_background():
+    """Eq. 2 with two terms and a background b: RGB = a1 c1 + (1 - a1) a2 c2 +
+    (1 - a1)(1 - a2) b and A = 1 - (1 - a1)(1 - a2).  Differentiating by hand:
+    dRGB/da1 = c1 - a2 c2 - (1 - a2) b, dRGB/da2 = (1 - a1)(c2 - b),
+    dA/da1 = 1 - a2, dA/da2 = 1 - a1; and da/do = G below the cap, 0 where a
+    pixel skips the Gaussian.  Dropping the background term of the backward,
+    or its sign, fails this pin."""
+    W = H = 40
+    cam = cam_minus_y(W, H)
+    bg = (0.25, 0.6, 0.9)
+    prm = O.Params(W, H, bg=bg)
+    s1, s2 = np.log([0.05, 0.04, 0.05]), np.log([0.07, 0.03, 0.06])
+    g1 = one_gaussian((0, -0.2, 0), s1, opacity=0.7, color=(1.0, 0.2, 0.1), shade=(1, 0, 0, 1))
+    g2 = one_gaussian((0, 0.3, 0), s2, opacity=0.6, color=(0.1, 0.3, 1.0), shade=(1, 0, 0, 1))
+    g = stack(g1, g2)
+    xs, ys = pixel_grid(W, H)
+    f = float(cam.fx)
+    sc = np.exp(g["log_scale"].astype(np.float64))
+    z = 4.0 + g["mean"][1].astype(np.float64)
+    o = g["opacity"][0].astype(np.float64)
+    c = g["color"].astype(np.float64)
+    G, a = [], []
+    for i in range(2):
+        vx = (f * sc[0, i] / z[i]) ** 2 + 0.3
+        vy = (f * sc[2, i] / z[i]) ** 2 + 0.3
+        Gi = np.exp(-0.5 * ((xs - W / 2) ** 2 / vx + (ys - H / 2) ** 2 / vy))
+        ai = np.minimum(0.99, o[i] * Gi)
+        G.append(np.where(ai >= 1 / 255, Gi, 0.0))
+        a.append(np.where(ai >= 1 / 255, ai, 0.0))
+    b = np.asarray(bg)[:, None, None]
+    u = np.random.default_rng(4).normal(size=(4, H, W))
+    dc1 = c[:, 0, None, None] - a[1] * c[:, 1, None, None] - (1 - a[1]) * b
+    dc2 = (1 - a[0]) * (c[:, 1, None, None] - b)
+    d1 = (u[:3] * dc1).sum(0) + u[3] * (1 - a[1])
+    d2 = (u[:3] * dc2).sum(0) + u[3] * (1 - a[0])
+    expect = np.array([(d1 * G[0]).sum(), (d2 * G[1]).sum()])
+    got, grad_rec = O.backward(g, cam, prm, u)
+    np.testing.assert_allclose(got["opacity"][0], expect, rtol=1e-11)
+    np.testing.assert_allclose(grad_rec[:, 5], expect, rtol=1e-11)
+    # the same image with a black background differs exactly by the b terms
+    got0, _ = O.backward(g, cam, O.Params(W, H), u)
+    diff = np.array([(-(1 - a[1]) * (u[:3] * b).sum(0) * G[0]).sum(),
+                     (-(1 - a[0]) * (u[:3] * b).sum(0) * G[1]).sum()])
+    np.testing.assert_allclose(got["opacity"][0] - got0["opacity"][0], diff, rtol=1e-9)
+
+
 # ------------------------------------------------------------ P3: invariant
 def test_weights_plus_transmittance_is_one():
     """Telescoping Eq. 2: sum_i T_i alpha_i + T_final = 1.  With every colour
@@ -292,15 +338,19 @@ def test_pixel_subset_matches_full_image():
 
 
 # ------------------------------------------------------- P5: gradients
-def fd_scene():
+BACKGROUNDS = [(0.0, 0.0, 0.0), (0.3, 0.7, 0.15)]
+
+
+def fd_scene(bg=(0.0, 0.0, 0.0)):
     """64 Gaussians, 32x32 (Gaussians span about 1-3 px), a seed with no
     decision near a threshold."""
     m = I.small_scene(64, 7, log_scale_mu=-2.0, log_scale_sigma=0.3)
-    return I.plain_planes(m), I.look_at((0.3, -4, 0.5), width=32, height=32), O.Params(32, 32)
+    return I.plain_planes(m), I.look_at((0.3, -4, 0.5), width=32, height=32), O.Params(32, 32, bg=bg)
 
 
-def test_backward_matches_autograd():
-    pl, cam, prm = fd_scene()
+@pytest.mark.parametrize("bg", BACKGROUNDS)
+def test_backward_matches_autograd(bg):
+    pl, cam, prm = fd_scene(bg)
     u = np.random.default_rng(1).normal(size=(4, 32, 32))
     g, _ = O.backward(pl, cam, prm, u)
     t = D.to_tensors(pl, True)
@@ -311,11 +361,13 @@ def test_backward_matches_autograd():
         np.testing.assert_allclose(g[k], ref, rtol=1e-9, atol=1e-11 * np.abs(ref).max())
 
 
-def test_backward_matches_finite_differences():
+@pytest.mark.parametrize("bg", BACKGROUNDS)
+def test_backward_matches_finite_differences(bg):
     """FP64 central differences, h = 1e-6 max(1, |theta|), of L = sum(u * RGBA)
     on the dense forward; parameters whose +-h changes a compositing decision
-    are excluded (counted, must be few)."""
-    pl, cam, prm = fd_scene()
+    are excluded (counted, must be few).  A coloured background puts the
+    T_final * bg term of Eq. 2's image into every alpha derivative."""
+    pl, cam, prm = fd_scene(bg)
     u = np.random.default_rng(2).normal(size=(4, 32, 32))
     g, _ = O.backward(pl, cam, prm, u)
     base = {k: np.asarray(v, np.float64) for k, v in pl.items()}
