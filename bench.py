@@ -376,7 +376,7 @@ def secondary_fwd(dev):
     out = torch.empty((1, 4, w.height, w.width), dtype=torch.float32, device=dev)
     mx = 0
     for v in range(len(w.cameras)):
-        rnd.forward(planes, cams_t, jobs[v], model_id=mid, edits_t=edits_t, out=out)
+        rnd.forward(planes, cams_t, jobs[v], model_id=mid, edits_t=edits_t, out=out, fwd_only=True)
         mx = max(mx, rnd.pairs())
     rnd.grow(int(mx * 1.1) + 4096)
     rnd.check = "defer"
@@ -390,18 +390,18 @@ def secondary_fwd(dev):
         def run():
             rnd.settings = A.apply(base, cfg)
             for v in range(4):
-                rnd.forward(planes, cams_t, jobs[v], model_id=mid, edits_t=edits_t, out=out)
+                rnd.forward(planes, cams_t, jobs[v], model_id=mid, edits_t=edits_t, out=out, fwd_only=True)
         return run
     best, times = A.tune(make, w.width, w.height, 1, n, candidates=cands, reps=3, use_cache=False)
     rnd.settings = A.apply(base, best)
     log(f"composed forward autotune (ms per candidate): {times} -> {best}")
     settle()
     for v in range(5):
-        rnd.forward(planes, cams_t, jobs[v], model_id=mid, edits_t=edits_t, out=out)
+        rnd.forward(planes, cams_t, jobs[v], model_id=mid, edits_t=edits_t, out=out, fwd_only=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for v in range(len(w.cameras)):
-        rnd.forward(planes, cams_t, jobs[v], model_id=mid, edits_t=edits_t, out=out)
+        rnd.forward(planes, cams_t, jobs[v], model_id=mid, edits_t=edits_t, out=out, fwd_only=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     rnd.verify()
@@ -459,8 +459,8 @@ def secondary_vq(dev, k=256, iters=10, reps=20):
     edits_t = R.edit_table(edits, dev)
     rnd = R.Renderer(R.Settings(800, 800), capacity=1 << 24, check="sync")
     job = R.Jobs.single(n, camera=3)
-    a = rnd.forward(planes_f, cams_t, job, model_id=mid_f, edits_t=edits_t).clone()
-    b = rnd.forward(planes_q, cams_t, job, model_id=mid_q, edits_t=edits_t)
+    a = rnd.forward(planes_f, cams_t, job, model_id=mid_f, edits_t=edits_t, fwd_only=True).clone()
+    b = rnd.forward(planes_q, cams_t, job, model_id=mid_q, edits_t=edits_t, fwd_only=True)
     mse = float(((a[:, :3] - b[:, :3]) ** 2).mean())
     psnr = 10 * np.log10(1.0 / max(mse, 1e-20))
     stored_q = sum(q.nbytes() for q in qs)
@@ -760,7 +760,7 @@ def secondary_culler(dev):
     views = list(range(len(test_c)))
     jobs_p = [R.Jobs.single(n, camera=v) for v in views]
     jobs_c = [R.Jobs.single(n, camera=v) for v in views]
-    ref = [plain.forward(planes, te_t, jobs_p[v], edits_t=edits).clone() for v in views]
+    ref = [plain.forward(planes, te_t, jobs_p[v], edits_t=edits, fwd_only=True).clone() for v in views]
     got = [culler.render(culled, planes, te_t, jobs_c[v], v).clone() for v in views]
     q = [min(CU.psnr(a[0], b[0]), 120.0) for a, b in zip(got, ref)]  # identical images: capped
     kept = float(np.mean([int(j.device[0, 2].item()) for j in jobs_c])) / n
@@ -805,7 +805,7 @@ def secondary_culler(dev):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / 1e3 / len(views)
 
-    render_plain = lambda v: plain.forward(planes, te_t, jobs_p[v], edits_t=edits, out=out)
+    render_plain = lambda v: plain.forward(planes, te_t, jobs_p[v], edits_t=edits, out=out, fwd_only=True)
     render_cull = lambda v: culler.render(culled, planes, te_t, jobs_c[v], v, out=out)
     e_plain, e_cull = timed(render_plain), timed(render_cull)
     t_plain, t_cull = graphed(render_plain), graphed(render_cull)

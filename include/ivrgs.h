@@ -50,6 +50,10 @@ typedef enum {
 #define IVRGS_FLAG_PERSISTENT 1u  /* render kernels use the persistent (job, tile) queue */
 #define IVRGS_FLAG_COUNT_EVAL 2u  /* render_fwd counts evaluated (pixel, Gaussian) pairs into
                                      status[2] and composited ones into status[3] */
+#define IVRGS_FLAG_FWD_ONLY 4u    /* nothing will differentiate the render: render_fwd stores no
+                                     list checkpoints and needs no workspace (unless
+                                     IVRGS_FLAG_PERSISTENT), and a render_bwd with the same flag
+                                     walks every tile list whole */
 
 /* Editable Gaussians (Sec. 4.3), device SoA planes of length n each:
  *   mean[3][n]       mu
@@ -193,9 +197,9 @@ typedef struct {
  * twice), its digit histograms, the per-chunk tile counts, the records'
  * binning fields in depth order (32 bytes per record), the record
  * gradients (9 floats per record), the work queue and, with one pixel per
- * lane and no work queue, per-pixel checkpoints at up to 15 cuts of every
- * tile's list (60 KiB per tile, used while they take at most 256 MiB): the
- * backward walks each segment of a long list in its own workgroup from the
+ * lane, no work queue and no IVRGS_FLAG_FWD_ONLY, per-pixel checkpoints at
+ * up to 15 cuts of every tile's list (60 KiB per tile, used while they take
+ * at most 256 MiB): the backward walks each segment of a long list in its own workgroup from the
  * state the forward stored at the cut.  capacity (>= 0) is the pair capacity
  * of the bins; the workspace does not depend on it.  Returns 0 for invalid
  * arguments. */
@@ -541,6 +545,57 @@ ivrgs_status ivrgs_photometric_grad(const float *x, const float *y, int32_t chan
                                     int32_t width, float lam, float *grad_x, const void *workspace,
                                     size_t workspace_bytes, void *stream);
 
+/* ---- Training regularisers on the rendered maps (Eq. 5-7, Sec. 4.3) -------
+ * The editable stage's regularisers of one view (the appendix weights them
+ * 0.01 each, the opacity L1 0.1):
+ *   [0] normal consistency (Eq. 6): mean over valid pixels of
+ *       || N / max(|N|, 1e-12) - N~ ||_2, N the composited normal map and N~
+ *       the pseudo-normal of the depth map under local planarity (Eq. 5; held
+ *       fixed, no gradient through it);
+ *   [1] sparsity of the offset colour (Sec. 4.3): mean |delta-c map|;
+ *   [2] bilateral smoothness (Eq. 7): mean over the four shading-term maps and
+ *       pixels of |K(x+1) - K(x)| exp(-mean_c |c(x+1) - c(x)|) plus the same
+ *       in y, each averaged over its own (H (W-1) or (H-1) W) differences,
+ *       c the target colour;
+ *   [3] opacity L1 (Sec. 4.3): mean |o| over the Gaussians.
+ * The pseudo-normal: at pixels with alpha > 0.5, d = depth / alpha;
+ * P = d ((x + 1/2 - cx) / fx, (y + 1/2 - cy) / fy, 1) in camera space; N~ =
+ * the normalised cross product of the central differences of P in x and y,
+ * negated if N~ . P > 0 (it faces the camera), then R^T N~ (world space).  A
+ * pixel is valid when it and its four neighbours have alpha > 0.5 and it is
+ * not on the border.  |x| has the derivative sign(x) (0 at 0).  A NULL map
+ * drops its term (0); with no valid pixel term [0] is 0. */
+typedef struct {
+    const float *depth;    /* [H][W] alpha-weighted depth map (channel 0 of the aux maps) */
+    const float *alpha;    /* [H][W] alpha map (channel 3 of the image) */
+    const float *normal;   /* [3][H][W] composited normal map, or NULL */
+    const float *delta_c;  /* [3][H][W] offset-colour map, or NULL */
+    const float *shade;    /* [4][H][W] k_a, k_d, k_s, beta maps, or NULL */
+    const float *target;   /* [3][H][W] target colour; required with shade */
+    const float *opacity;  /* [n_gauss] opacities, or NULL */
+    int64_t n_gauss;
+    int32_t height, width; /* each at least 3 */
+} ivrgs_reg_maps;
+
+/* Bytes of workspace ivrgs_reg_fwd needs (0 for invalid maps). */
+size_t ivrgs_reg_workspace_size(const ivrgs_reg_maps *maps);
+
+/* out_terms: device float[5], written: the four terms above and, in [4], the
+ * number of valid pixels.  out_pseudo_normal: device [3][H][W] or NULL,
+ * written with N~ (0 at invalid pixels).  camera: HOST struct.  The sums are
+ * reduced in a fixed order (deterministic).  Two launches. */
+ivrgs_status ivrgs_reg_fwd(const ivrgs_reg_maps *maps, const ivrgs_camera *camera, float *out_terms,
+                           float *out_pseudo_normal, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Gradients of sum_k grad_terms[k] * term_k (grad_terms: device float[4];
+ * terms: the out_terms of the forward on the same maps) with respect to the
+ * normal map, the offset-colour map, the shading maps and the opacities;
+ * each output (device, the layout of its input, or NULL to skip) is
+ * overwritten.  The depth, alpha and target get no gradient.  One launch. */
+ivrgs_status ivrgs_reg_bwd(const ivrgs_reg_maps *maps, const ivrgs_camera *camera, const float *terms,
+                           const float *grad_terms, float *grad_normal, float *grad_delta_c, float *grad_shade,
+                           float *grad_opacity, void *stream);
+
 /* ---- SH colour (base 3DGS, Sec. 3 and Sec. 4.2) ---------------------------
  * The base model's view-dependent colour is parameterised by spherical-
  * harmonic coefficients, as in the original 3DGS; the paper gives no degree
@@ -572,7 +627,8 @@ ivrgs_status ivrgs_sh_color_bwd(const float *sh, int32_t degree, const float *me
 
 /* sizeof of the ABI structs, for binding checks: which = 0 gaussians,
  * 1 camera, 2 model_edit, 3 job, 4 batch, 5 params, 6 projected, 7 bins,
- * 8 culler, 9 explore_opts, 10 vq_model. */
+ * 8 culler, 9 explore_opts, 10 vq_model, 11 vq_book, 12 reg_maps; -1 for
+ * any other value. */
 int32_t ivrgs_struct_size(int32_t which);
 
 /* Device-side errors: waits for `stream`, then reads the device status

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libivrgs.so")
-SOURCES = ["project.hip", "binsort.hip", "render.hip", "cull.hip", "vq.hip", "sh.hip", "aux.hip", "ssim.hip", "api.hip"]
+SOURCES = ["project.hip", "binsort.hip", "render.hip", "cull.hip", "vq.hip", "sh.hip", "aux.hip", "ssim.hip", "reg.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -127,7 +127,8 @@ ivrgs_status check_params(const ivrgs_params *p) {
     for (int px : {p->fwd_px, p->bwd_px})
         if (px != 0 && px != 1 && px != 2 && px != 4) return IVRGS_E_UNSUPPORTED;
     if (p->sort_chunk < 0 || p->persist_per_cu < 0) return IVRGS_E_INVALID;
-    if ((p->flags & ~(IVRGS_FLAG_PERSISTENT | IVRGS_FLAG_COUNT_EVAL)) != 0u) return IVRGS_E_UNSUPPORTED;
+    if ((p->flags & ~(IVRGS_FLAG_PERSISTENT | IVRGS_FLAG_COUNT_EVAL | IVRGS_FLAG_FWD_ONLY)) != 0u)
+        return IVRGS_E_UNSUPPORTED;
     return IVRGS_OK;
 }
 
@@ -155,7 +156,8 @@ int pick_px(int requested, int fallback) { return requested == 0 ? fallback : re
 constexpr size_t kCkptBudget = size_t(256) << 20;
 
 size_t ckpt_bytes(const ivrgs_batch &b, const ivrgs_params &p, const Consts &k) {
-    if (pick_px(p.fwd_px, 1) != 1 || pick_px(p.bwd_px, 1) != 1 || (p.flags & IVRGS_FLAG_PERSISTENT)) return 0;
+    if (pick_px(p.fwd_px, 1) != 1 || pick_px(p.bwd_px, 1) != 1) return 0;
+    if (p.flags & (IVRGS_FLAG_PERSISTENT | IVRGS_FLAG_FWD_ONLY)) return 0;
     const size_t bytes = (size_t)b.n_jobs * k.tiles_per_job * (kSplitMax - 1) * kCkptPix * sizeof(float) * 4;
     return bytes <= kCkptBudget ? bytes : 0;
 }
@@ -500,8 +502,11 @@ ivrgs_status ivrgs_project(const ivrgs_batch *batch, const ivrgs_params *params,
                                      reinterpret_cast<hipStream_t>(stream)));
 }
 
-ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
-                            ivrgs_bins *bins, void *workspace, size_t workspace_bytes, void *stream) {
+namespace {
+// Host validation shared by both binning entry points; fills the layout and
+// the device limits on success.
+ivrgs_status bin_sort_check(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
+                            const ivrgs_bins *bins, Layout &L, DeviceLimits &dl) {
     ivrgs_status st = check_batch(batch);
     if (st != IVRGS_OK) return st;
     if ((st = check_params(params)) != IVRGS_OK) return st;
@@ -509,12 +514,17 @@ ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params
     if (bins->capacity > 0 && !bins->sorted) return IVRGS_E_INVALID;
     if (batch->n_records > 0 && (!proj->rec || !proj->rect || !proj->depth)) return IVRGS_E_INVALID;
     const Consts k = make_consts(*params);
-    DeviceLimits dl;
     if (device_limits(dl) != hipSuccess) return IVRGS_E_HIP;
     if (sizeof(uint32_t) * (size_t)k.tiles_per_job > dl.bin_lds) return IVRGS_E_SHAPE;
-    const Layout L = layout(*batch, *params);
-    if (!workspace || workspace_bytes < L.total) return IVRGS_E_CAPACITY;
-    char *ws = static_cast<char *>(workspace);
+    L = layout(*batch, *params);
+    return IVRGS_OK;
+}
+
+// The binning launches over a workspace `ws` laid out by L (the regions
+// before L.grec; the work queue too with IVRGS_FLAG_PERSISTENT).
+ivrgs_status bin_sort_run(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
+                          ivrgs_bins *bins, const Layout &L, const DeviceLimits &dl, char *ws, void *stream) {
+    const Consts k = make_consts(*params);
     BinWork w;
     w.key[0] = reinterpret_cast<uint32_t *>(ws + L.key0);
     w.val[0] = reinterpret_cast<uint32_t *>(ws + L.val0);
@@ -532,6 +542,18 @@ ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params
         e = launch_work_queue(bins->tile_start, (int64_t)batch->n_jobs * k.tiles_per_job,
                               reinterpret_cast<uint32_t *>(ws + L.queue), s);
     return hip_status(e);
+}
+
+}  // namespace
+
+ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
+                            ivrgs_bins *bins, void *workspace, size_t workspace_bytes, void *stream) {
+    Layout L;
+    DeviceLimits dl;
+    const ivrgs_status st = bin_sort_check(batch, params, proj, bins, L, dl);
+    if (st != IVRGS_OK) return st;
+    if (!workspace || workspace_bytes < L.total) return IVRGS_E_CAPACITY;
+    return bin_sort_run(batch, params, proj, bins, L, dl, static_cast<char *>(workspace), stream);
 }
 
 ivrgs_status ivrgs_render_fwd(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
@@ -653,6 +675,48 @@ ivrgs_status ivrgs_cull(const ivrgs_gaussians *g, const ivrgs_camera *cameras, i
                                   reinterpret_cast<hipStream_t>(stream)));
 }
 
+namespace {
+// Host validation of the regulariser maps: sizes, and the inputs each
+// present term needs.
+ivrgs_status check_reg_maps(const ivrgs_reg_maps *m) {
+    if (!m) return IVRGS_E_INVALID;
+    if (m->height < 3 || m->width < 3 || m->n_gauss < 0) return IVRGS_E_SHAPE;
+    if (m->normal && (!m->depth || !m->alpha)) return IVRGS_E_INVALID;
+    if (m->shade && !m->target) return IVRGS_E_INVALID;
+    if ((int64_t)m->height * m->width > ((int64_t)1 << 31)) return IVRGS_E_SHAPE;
+    return IVRGS_OK;
+}
+}  // namespace
+
+size_t ivrgs_reg_workspace_size(const ivrgs_reg_maps *maps) {
+    if (check_reg_maps(maps) != IVRGS_OK) return 0;
+    return reg_workspace_bytes(*maps);
+}
+
+ivrgs_status ivrgs_reg_fwd(const ivrgs_reg_maps *maps, const ivrgs_camera *camera, float *out_terms,
+                           float *out_pseudo_normal, void *workspace, size_t workspace_bytes, void *stream) {
+    const ivrgs_status st = check_reg_maps(maps);
+    if (st != IVRGS_OK) return st;
+    if (!camera || !out_terms || !workspace) return IVRGS_E_INVALID;
+    if (out_pseudo_normal && (!maps->depth || !maps->alpha)) return IVRGS_E_INVALID;
+    if (workspace_bytes < reg_workspace_bytes(*maps)) return IVRGS_E_CAPACITY;
+    return hip_status(launch_reg_fwd(*maps, *camera, out_terms, out_pseudo_normal, workspace,
+                                     reinterpret_cast<hipStream_t>(stream)));
+}
+
+ivrgs_status ivrgs_reg_bwd(const ivrgs_reg_maps *maps, const ivrgs_camera *camera, const float *terms,
+                           const float *grad_terms, float *grad_normal, float *grad_delta_c, float *grad_shade,
+                           float *grad_opacity, void *stream) {
+    const ivrgs_status st = check_reg_maps(maps);
+    if (st != IVRGS_OK) return st;
+    if (!camera || !terms || !grad_terms) return IVRGS_E_INVALID;
+    if ((grad_normal && !maps->normal) || (grad_delta_c && !maps->delta_c) || (grad_shade && !maps->shade) ||
+        (grad_opacity && !maps->opacity))
+        return IVRGS_E_INVALID;
+    return hip_status(launch_reg_bwd(*maps, *camera, terms, grad_terms, grad_normal, grad_delta_c, grad_shade,
+                                     grad_opacity, reinterpret_cast<hipStream_t>(stream)));
+}
+
 int32_t ivrgs_struct_size(int32_t which) {
     switch (which) {
     case 0: return (int32_t)sizeof(ivrgs_gaussians);
@@ -667,6 +731,7 @@ int32_t ivrgs_struct_size(int32_t which) {
     case 9: return (int32_t)sizeof(ivrgs_explore_opts);
     case 10: return (int32_t)sizeof(ivrgs_vq_model);
     case 11: return (int32_t)sizeof(ivrgs_vq_book);
+    case 12: return (int32_t)sizeof(ivrgs_reg_maps);
     default: return -1;
     }
 }

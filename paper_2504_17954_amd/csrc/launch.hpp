@@ -115,6 +115,13 @@ hipError_t launch_ssim_bwd(const float *x, const float *y, int channels, int H, 
                            float *grad_x, const float *ws, hipStream_t s);
 hipError_t launch_photometric_grad(const float *x, const float *y, int channels, int H, int W, float lam,
                                    float *grad_x, const float *ws, hipStream_t s);
+// Training regularisers on the rendered maps of one view (normal
+// consistency, offset-colour sparsity, bilateral smoothness, opacity L1).
+size_t reg_workspace_bytes(const ivrgs_reg_maps &m);
+hipError_t launch_reg_fwd(const ivrgs_reg_maps &m, const ivrgs_camera &cam, float *terms, float *pseudo, void *ws,
+                          hipStream_t s);
+hipError_t launch_reg_bwd(const ivrgs_reg_maps &m, const ivrgs_camera &cam, const float *terms, const float *gterm,
+                          float *g_normal, float *g_dc, float *g_shade, float *g_op, hipStream_t s);
 hipError_t launch_work_queue(const uint32_t *starts, int64_t n_tiles, uint32_t *queue, hipStream_t s);
 
 }  // namespace ivrgs

@@ -51,7 +51,7 @@ def collect_labels(planes: dict, cams_t: torch.Tensor, width: int, height: int,
     with torch.no_grad():
         for v in range(cams_t.shape[0]):
             _, maxw = rnd.forward(planes, cams_t, R.Jobs.single(n, camera=v), edits_t=R.default_edits(cams_t.device),
-                                  want_maxw=True)
+                                  want_maxw=True, fwd_only=True)
             out[v] = (maxw[:n] >= VISIBLE).to(torch.uint8)
     return out
 
@@ -164,7 +164,7 @@ class Culler:
         host count is n (an upper bound) and whose device count the cull writes."""
         self.run(planes, cams_t, jobs, camera)
         return renderer.forward(planes, cams_t, jobs, edits_t=R.default_edits(cams_t.device),
-                                gauss_index=self.index, out=out)
+                                gauss_index=self.index, out=out, fwd_only=True)
 
 
 def calibrate_threshold(culler: Culler, planes: dict, cams_t: torch.Tensor, labels: torch.Tensor,

@@ -335,3 +335,24 @@ def random_target(n_views: int, height: int, width: int, seed: int) -> np.ndarra
     """Random RGBA target image U(0,1), layout [views, 4, H, W]."""
     rng = np.random.default_rng(seed)
     return rng.uniform(0.0, 1.0, size=(n_views, 4, height, width)).astype(np.float32)
+
+
+def view_maps(height: int, width: int, seed: int, n_gauss: int = 257) -> dict:
+    """Seeded float32 maps of one view for the training regularisers: the
+    alpha-weighted depth of a smooth bumpy surface (depth 2.7-3.5), an alpha
+    map near 0.95 with a hole that drops below 0.5, normals N(0, 1) per
+    component, offset colours U(-0.5, 0.5), shading terms and a target colour
+    U(0, 1), and opacities U(-0.2, 1.5) (negative values reach the L1's
+    sign)."""
+    rng = np.random.default_rng(seed)
+    ys, xs = np.meshgrid(np.arange(height) + 0.5, np.arange(width) + 0.5, indexing="ij")
+    u, v = xs / width, ys / height
+    d = 3.0 + 0.3 * np.sin(5 * u + 1.0) * np.cos(4 * v) + 0.2 * u * v
+    alpha = np.clip(0.95 - 0.9 * np.exp(-((u - 0.6) ** 2 + (v - 0.4) ** 2) / 0.01), 0.0, 1.0)
+    f = np.float32
+    return {"depth": (d * alpha).astype(f), "alpha": alpha.astype(f),
+            "normal": rng.normal(size=(3, height, width)).astype(f),
+            "delta_c": rng.uniform(-0.5, 0.5, (3, height, width)).astype(f),
+            "shade": rng.uniform(0, 1, (4, height, width)).astype(f),
+            "target": rng.uniform(0, 1, (3, height, width)).astype(f),
+            "opacity": rng.uniform(-0.2, 1.5, n_gauss).astype(f)}

@@ -1,14 +1,15 @@
-"""Training losses of the basic models, in torch on the maps the kernels
-render (the image, and the auxiliary maps of `aux.render_aux`):
+"""Training losses of the basic models on the maps the kernels render (the
+image, and the auxiliary maps of `aux.render_aux`), as autograd Functions
+around the HIP kernels (argument marshalling only):
 
   - photometric: (1 - lam) L1 + lam (1 - SSIM) on the colour and alpha
-    channels (Sec. 4.2), lam = 0.2;
-  - normal consistency ||N - N~|| between the rendered normal map and the
-    pseudo-normal of the rendered depth under local planarity (Eq. 5, Eq. 6);
-  - sparsity: L1 of the rendered offset-colour map (Sec. 4.3);
-  - bilateral smoothness |grad K| exp(-|grad c_gt|) of the shading-term maps
-    (Eq. 7);
-  - opacity L1 over the Gaussians (Sec. 4.3).
+    channels (Sec. 4.2), lam = 0.2 (ivrgs_ssim_fwd, ivrgs_photometric_grad);
+  - the regularisers of one view in one pass (ivrgs_reg_fwd / ivrgs_reg_bwd):
+    normal consistency ||N - N~|| between the rendered normal map and the
+    pseudo-normal of the rendered depth under local planarity (Eq. 5, Eq. 6),
+    sparsity of the offset-colour map (Sec. 4.3), bilateral smoothness
+    |grad K| exp(-|grad c_gt|) of the shading-term maps (Eq. 7), opacity L1
+    over the Gaussians (Sec. 4.3).
 
 Weights (appendix): L1 and SSIM combine as 0.8 and 0.2, the opacity L1 is
 scaled by 0.1, and the normal consistency and the other regularisers by
@@ -16,17 +17,16 @@ scaled by 0.1, and the normal consistency and the other regularisers by
 
 Readings where the paper is silent: SSIM after Wang et al. (2004), an 11x11
 Gaussian window of sigma 1.5, C1 = 0.01^2, C2 = 0.03^2, averaged over the
-windows that lie inside the image (the HIP kernels behind ivrgs_ssim_fwd /
-ivrgs_ssim_bwd / ivrgs_photometric_grad, the target taken as a constant);
-depth and normal maps are divided by the
-alpha map before use (pixels with alpha <= 0.5 are left out); the
-pseudo-normal is the cross product of the central differences of the
-back-projected points, turned to face the camera and taken to world space;
-image gradients are forward differences, |grad c_gt| the mean over colour
-channels of their absolute values.
+windows that lie inside the image, the target taken as a constant; depth
+maps are divided by the alpha map before use (pixels with alpha <= 0.5 and
+their neighbours are left out); the pseudo-normal is the cross product of
+the central differences of the back-projected points, turned to face the
+camera and taken to world space; image gradients are forward differences,
+|grad c_gt| the mean over colour channels of their absolute values.
 """
 from __future__ import annotations
 
+import numpy as np
 import torch
 
 from . import native as N
@@ -110,56 +110,86 @@ def photometric(rgba: torch.Tensor, target: torch.Tensor, lam: float = 0.2) -> t
     return _PhotometricFn.apply(rgba.contiguous(), target.detach().contiguous(), float(lam))
 
 
-def pseudo_normal(depth: torch.Tensor, alpha: torch.Tensor, cam) -> tuple[torch.Tensor, torch.Tensor]:
-    """World-space unit normals [3, H, W] of the alpha-normalised depth map
-    under local planarity, and the mask of pixels where they are defined."""
-    H, W = depth.shape
-    dev, dt = depth.device, depth.dtype
-    ok = alpha > 0.5
-    d = torch.where(ok, depth / alpha.clamp_min(1e-6), torch.zeros_like(depth))
-    ys, xs = torch.meshgrid(torch.arange(H, dtype=dt, device=dev) + 0.5,
-                            torch.arange(W, dtype=dt, device=dev) + 0.5, indexing="ij")
-    P = torch.stack([(xs - cam.cx) / cam.fx * d, (ys - cam.cy) / cam.fy * d, d])  # camera space
-    dx = torch.zeros_like(P)
-    dy = torch.zeros_like(P)
-    dx[:, :, 1:-1] = (P[:, :, 2:] - P[:, :, :-2]) / 2
-    dy[:, 1:-1, :] = (P[:, 2:, :] - P[:, :-2, :]) / 2
-    n = torch.cross(dx, dy, dim=0)
-    n = n / n.norm(dim=0, keepdim=True).clamp_min(1e-12)
-    n = torch.where((n * P).sum(0, keepdim=True) > 0, -n, n)  # face the camera
-    valid = ok.clone()
-    valid[:, [0, -1]] = False
-    valid[[0, -1], :] = False
-    valid &= ok.roll(1, 0) & ok.roll(-1, 0) & ok.roll(1, 1) & ok.roll(-1, 1)
-    R = torch.as_tensor(cam.R, dtype=dt, device=dev)
-    return torch.einsum("ji,jhw->ihw", R, n), valid  # R^T n: camera to world
+def camera_struct(cam) -> N.ivrgs_camera:
+    """The ABI camera of an object with .row() (16 float32 words) or a row."""
+    row = cam.row() if hasattr(cam, "row") else np.asarray(cam, np.float32)
+    return N.ivrgs_camera.from_buffer_copy(np.ascontiguousarray(row, np.float32).tobytes())
 
 
-def normal_consistency(normal_map: torch.Tensor, depth: torch.Tensor, alpha: torch.Tensor, cam) -> torch.Tensor:
-    """Mean over valid pixels of || N / |N| - N~ ||_2 (Eq. 6)."""
-    pn, valid = pseudo_normal(depth.detach(), alpha.detach(), cam)
-    nn_ = normal_map / normal_map.norm(dim=0, keepdim=True).clamp_min(1e-12)
-    diff = (nn_ - pn).norm(dim=0)
-    return diff[valid].mean() if valid.any() else normal_map.sum() * 0
+def _reg_maps(depth, alpha, normal, delta_c, shade, target, opacity) -> N.ivrgs_reg_maps:
+    H, W = (int(v) for v in alpha.shape)
+    m = N.ivrgs_reg_maps()
+    for name, t, shape in (("depth", depth, (H, W)), ("alpha", alpha, (H, W)), ("normal", normal, (3, H, W)),
+                           ("delta_c", delta_c, (3, H, W)), ("shade", shade, (4, H, W)),
+                           ("target", target, (3, H, W))):
+        if t is None:
+            continue
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and tuple(t.shape) == shape
+                and t.device == alpha.device):
+            raise ValueError(f"{name}: expected a contiguous float32 device tensor of shape {shape}")
+        setattr(m, name, t.data_ptr())
+    if opacity is not None:
+        if not (opacity.is_cuda and opacity.dtype == torch.float32 and opacity.is_contiguous()):
+            raise ValueError("opacity: expected a contiguous float32 device tensor")
+        m.opacity, m.n_gauss = opacity.data_ptr(), opacity.numel()
+    m.height, m.width = H, W
+    return m
 
 
-def sparsity(delta_c_map: torch.Tensor) -> torch.Tensor:
-    """L1 of the rendered offset-colour map."""
-    return delta_c_map.abs().mean()
+class _RegFn(torch.autograd.Function):
+    """The four regulariser terms of one view through ivrgs_reg_fwd /
+    ivrgs_reg_bwd (argument marshalling only); no gradient to the depth,
+    the alpha map or the target."""
+
+    @staticmethod
+    def forward(ctx, cam, depth, alpha, normal, delta_c, shade, target, opacity):
+        m = _reg_maps(depth, alpha, normal, delta_c, shade, target, opacity)
+        c = camera_struct(cam)
+        ws = torch.empty(max(N.ivrgs_reg_workspace_size(m), 1), dtype=torch.uint8, device=alpha.device)
+        terms = torch.empty(5, dtype=torch.float32, device=alpha.device)
+        N.ivrgs_reg_fwd(m, c, terms.data_ptr(), None, ws.data_ptr(), ws.numel(), _stream())
+        ctx.cam = cam
+        ctx.save_for_backward(depth, alpha, normal, delta_c, shade, target, opacity, terms)
+        return terms[:4]
+
+    @staticmethod
+    def backward(ctx, g):
+        depth, alpha, normal, delta_c, shade, target, opacity, terms = ctx.saved_tensors
+        m = _reg_maps(depth, alpha, normal, delta_c, shade, target, opacity)
+        g = g.to(torch.float32).contiguous()
+        outs = [None if t is None or not need else torch.empty_like(t)
+                for t, need in zip((normal, delta_c, shade, opacity), ctx.needs_input_grad[3:5] +
+                                   ctx.needs_input_grad[5:6] + ctx.needs_input_grad[7:8])]
+        N.ivrgs_reg_bwd(m, camera_struct(ctx.cam), terms.data_ptr(), g.data_ptr(),
+                        *[None if o is None else o.data_ptr() for o in outs], _stream())
+        gn, gd, gs, go = outs
+        return None, None, None, gn, gd, gs, None, go
 
 
-def bilateral_smoothness(k_maps: torch.Tensor, gt_rgb: torch.Tensor) -> torch.Tensor:
-    """Mean over maps and pixels of |grad K| exp(-|grad c_gt|) (Eq. 7),
-    forward differences in x and y."""
-    gx = (k_maps[:, :, 1:] - k_maps[:, :, :-1]).abs()
-    gy = (k_maps[:, 1:, :] - k_maps[:, :-1, :]).abs()
-    wx = torch.exp(-(gt_rgb[:, :, 1:] - gt_rgb[:, :, :-1]).abs().mean(0))
-    wy = torch.exp(-(gt_rgb[:, 1:, :] - gt_rgb[:, :-1, :]).abs().mean(0))
-    return (gx * wx).mean() + (gy * wy).mean()
+def regularisers(depth, alpha, cam, normal=None, delta_c=None, shade=None, target=None,
+                 opacity=None) -> torch.Tensor:
+    """[normal consistency (Eq. 6), offset-colour sparsity, bilateral
+    smoothness (Eq. 7), opacity L1] of one view's maps (device float32:
+    depth, alpha [H, W]; normal [3, H, W]; delta_c [3, H, W]; shade
+    [4, H, W] with the target colour [3, H, W]; opacity [n]); a term whose
+    input is None is 0.  Differentiable in the normal, offset-colour and
+    shading maps and the opacities."""
+    if opacity is not None:
+        opacity = opacity.reshape(-1)
+    return _RegFn.apply(cam, depth.contiguous(), alpha.contiguous(), normal, delta_c, shade,
+                        None if target is None else target.detach().contiguous(), opacity)
 
 
-def opacity_l1(opacity: torch.Tensor) -> torch.Tensor:
-    return opacity.abs().mean()
+def pseudo_normal(depth: torch.Tensor, alpha: torch.Tensor, cam) -> tuple[torch.Tensor, int]:
+    """World-space pseudo-normal map N~ [3, H, W] of the alpha-normalised
+    depth (0 where undefined) and the number of pixels where it is defined,
+    from the kernel of ivrgs_reg_fwd (waits for the count)."""
+    m = _reg_maps(depth.contiguous(), alpha.contiguous(), None, None, None, None, None)
+    ws = torch.empty(max(N.ivrgs_reg_workspace_size(m), 1), dtype=torch.uint8, device=alpha.device)
+    terms = torch.empty(5, dtype=torch.float32, device=alpha.device)
+    pn = torch.empty((3,) + tuple(alpha.shape), dtype=torch.float32, device=alpha.device)
+    N.ivrgs_reg_fwd(m, camera_struct(cam), terms.data_ptr(), pn.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+    return pn, int(terms[4].item())
 
 
 W_OPACITY = 0.1  # the L1 regulariser of the editable stage
@@ -169,7 +199,8 @@ W_REG = 0.01     # normal consistency and the other regularisers
 def base_loss(rgba, target, depth, normal_map, cam) -> torch.Tensor:
     """Base-3DGS stage: photometric + 0.01 normal consistency (maps of one
     view: rgba [4, H, W], depth [H, W], normal_map [3, H, W])."""
-    return photometric(rgba, target) + W_REG * normal_consistency(normal_map, depth, rgba[3], cam)
+    t = regularisers(depth, rgba[3], cam, normal=normal_map)
+    return photometric(rgba, target) + W_REG * t[0]
 
 
 def editable_loss(rgba, target, maps, opacity, cam) -> torch.Tensor:
@@ -177,5 +208,7 @@ def editable_loss(rgba, target, maps, opacity, cam) -> torch.Tensor:
     colour sparsity + bilateral smoothness of the four shading maps).  maps
     [11, H, W] from aux.render_aux with aux.editable_attributes: depth, unit
     normal (3), delta-c (3), k_a, k_d, k_s, beta."""
-    return (base_loss(rgba, target, maps[0], maps[1:4], cam) + W_OPACITY * opacity_l1(opacity)
-            + W_REG * (sparsity(maps[4:7]) + bilateral_smoothness(maps[7:11], target[:3])))
+    t = regularisers(maps[0], rgba[3], cam, normal=maps[1:4], delta_c=maps[4:7], shade=maps[7:11],
+                     target=target[:3], opacity=opacity)
+    w = torch.tensor([W_REG, W_REG, W_REG, W_OPACITY], dtype=torch.float32, device=t.device)
+    return photometric(rgba, target) + (t * w).sum()

@@ -18,6 +18,7 @@ OK, E_INVALID, E_SHAPE, E_CAPACITY, E_HIP, E_UNSUPPORTED = range(6)
 DEV_E_CAPACITY = 1
 FLAG_PERSISTENT = 1
 FLAG_COUNT_EVAL = 2
+FLAG_FWD_ONLY = 4
 EXPORTS = ("ivrgs_workspace_size", "ivrgs_tiles_per_job", "ivrgs_compose", "ivrgs_project",
            "ivrgs_bin_sort", "ivrgs_render_fwd", "ivrgs_render_bwd", "ivrgs_struct_size",
            "ivrgs_status_string", "ivrgs_timing_enable", "ivrgs_timing_read",
@@ -26,7 +27,8 @@ EXPORTS = ("ivrgs_workspace_size", "ivrgs_tiles_per_job", "ivrgs_compose", "ivrg
            "ivrgs_vq_workspace_size", "ivrgs_vq_fit", "ivrgs_vq_assign", "ivrgs_vq_compose",
            "ivrgs_sh_color", "ivrgs_sh_color_bwd", "ivrgs_render_aux_fwd", "ivrgs_render_aux_bwd",
            "ivrgs_get_error", "ivrgs_ssim_workspace_size", "ivrgs_ssim_fwd", "ivrgs_ssim_bwd",
-           "ivrgs_vq_fit_batch_workspace_size", "ivrgs_vq_fit_batch", "ivrgs_photometric_grad")
+           "ivrgs_vq_fit_batch_workspace_size", "ivrgs_vq_fit_batch", "ivrgs_photometric_grad",
+           "ivrgs_reg_workspace_size", "ivrgs_reg_fwd", "ivrgs_reg_bwd")
 TIMING_KINDS = ("project", "tile_count", "scatter", "depth_sort", "render_fwd", "render_bwd",
                 "project_bwd", "compose", "fill", "cull", "edit_bwd", "vq", "sh", "aux")
 
@@ -96,9 +98,15 @@ class ivrgs_vq_book(C.Structure):
     _fields_ = [("values", C.c_void_p), ("n", C.c_int64), ("codebook", C.c_void_p), ("index", C.c_void_p)]
 
 
+class ivrgs_reg_maps(C.Structure):
+    _fields_ = [("depth", C.c_void_p), ("alpha", C.c_void_p), ("normal", C.c_void_p), ("delta_c", C.c_void_p),
+                ("shade", C.c_void_p), ("target", C.c_void_p), ("opacity", C.c_void_p), ("n_gauss", C.c_int64),
+                ("height", C.c_int32), ("width", C.c_int32)]
+
+
 STRUCTS = (ivrgs_gaussians, ivrgs_camera, ivrgs_model_edit, ivrgs_job, ivrgs_batch,
            ivrgs_params, ivrgs_projected, ivrgs_bins, ivrgs_culler, ivrgs_explore_opts, ivrgs_vq_model,
-           ivrgs_vq_book)
+           ivrgs_vq_book, ivrgs_reg_maps)
 
 _lib = None
 
@@ -181,6 +189,12 @@ def load(path: str = LIB_PATH):
     lib.ivrgs_ssim_bwd.restype = C.c_int
     lib.ivrgs_photometric_grad.argtypes = [P, P, I32, I32, I32, C.c_float, P, P, C.c_size_t, P]
     lib.ivrgs_photometric_grad.restype = C.c_int
+    lib.ivrgs_reg_workspace_size.argtypes = [P]
+    lib.ivrgs_reg_workspace_size.restype = C.c_size_t
+    lib.ivrgs_reg_fwd.argtypes = [P, P, P, P, P, C.c_size_t, P]
+    lib.ivrgs_reg_fwd.restype = C.c_int
+    lib.ivrgs_reg_bwd.argtypes = [P, P, P, P, P, P, P, P, P]
+    lib.ivrgs_reg_bwd.restype = C.c_int
     lib.ivrgs_get_error.argtypes = [P, P, P, P]
     lib.ivrgs_get_error.restype = C.c_int
     lib.ivrgs_timing_enable.argtypes = [C.c_uint32]
@@ -329,6 +343,20 @@ def ivrgs_photometric_grad(x_ptr, y_ptr, channels: int, height: int, width: int,
                            ws_ptr, ws_bytes, stream):
     check(load().ivrgs_photometric_grad(x_ptr, y_ptr, channels, height, width, lam, grad_x_ptr, ws_ptr,
                                         ws_bytes, stream), "ivrgs_photometric_grad")
+
+
+def ivrgs_reg_workspace_size(maps) -> int:
+    return int(load().ivrgs_reg_workspace_size(ref(maps)))
+
+
+def ivrgs_reg_fwd(maps, camera, terms_ptr, pseudo_ptr, ws_ptr, ws_bytes, stream):
+    check(load().ivrgs_reg_fwd(ref(maps), ref(camera), terms_ptr, pseudo_ptr, ws_ptr, ws_bytes, stream),
+          "ivrgs_reg_fwd")
+
+
+def ivrgs_reg_bwd(maps, camera, terms_ptr, grad_terms_ptr, g_normal_ptr, g_dc_ptr, g_shade_ptr, g_op_ptr, stream):
+    check(load().ivrgs_reg_bwd(ref(maps), ref(camera), terms_ptr, grad_terms_ptr, g_normal_ptr, g_dc_ptr,
+                               g_shade_ptr, g_op_ptr, stream), "ivrgs_reg_bwd")
 
 
 def ivrgs_project(batch, params, proj, stream):

@@ -164,6 +164,7 @@ class Renderer:
         self.generation = 0
         self._key = None
         self._bin_fp = None  # inputs of the binning the buffers hold
+        self._ckpt_generation = None  # binning whose list checkpoints the workspace holds
 
     # -- buffers ----------------------------------------------------------
     def _ensure(self, batch: N.ivrgs_batch):
@@ -193,6 +194,7 @@ class Renderer:
             raise ValueError("ivrgs_workspace_size rejected the batch")
         if self.ws is None or self.ws.numel() < need:
             self._bin_fp = None
+            self._ckpt_generation = None
             self.ws = torch.empty(need, dtype=torch.uint8, device=dev)
 
     def grow(self, capacity: int):
@@ -287,7 +289,10 @@ class Renderer:
         return proj, bins
 
     def forward(self, planes, cams_t, jobs: Jobs, model_id=None, edits_t=None, gauss_index=None,
-                want_maxw: bool = False, out=None):
+                want_maxw: bool = False, out=None, fwd_only: bool = False):
+        """Render the batch.  fwd_only=True (a render nothing will
+        differentiate) stores no list checkpoints for the backward; a later
+        backward() of such a render recomputes them."""
         batch = self.make_batch(planes, model_id, edits_t, cams_t, jobs, gauss_index)
         proj, bins = self.project_and_bin(batch)
         s = self.settings
@@ -295,8 +300,12 @@ class Renderer:
             (jobs.n_jobs, 4, s.height, s.width), dtype=torch.float32, device=self.device)
         maxw = torch.zeros(max(jobs.n_records, 1), dtype=torch.float32, device=self.device) \
             if want_maxw else None
-        N.ivrgs_render_fwd(batch, s.params(), proj, bins, rgba.data_ptr(), _ptr(maxw),
+        p = s.params()
+        if fwd_only:
+            p.flags |= N.FLAG_FWD_ONLY
+        N.ivrgs_render_fwd(batch, p, proj, bins, rgba.data_ptr(), _ptr(maxw),
                            self.ws.data_ptr(), self.ws.numel(), _stream())
+        self._ckpt_generation = None if fwd_only else self.generation
         self._key = (id(batch), self.generation)
         return (rgba, maxw) if want_maxw else rgba
 
@@ -308,12 +317,14 @@ class Renderer:
             # records, the bins and the list checkpoints of the forward (its
             # image comes out bit-identical and is discarded)
             proj, bins = self.project_and_bin(batch)
-            scratch = torch.empty_like(rgba)
-            N.ivrgs_render_fwd(batch, self.settings.params(), proj, bins, scratch.data_ptr(), None,
-                               self.ws.data_ptr(), self.ws.numel(), _stream())
         else:
             self._ensure(batch)
             proj, bins = self._structs(batch)
+        if rebin or self._ckpt_generation != self.generation:
+            scratch = torch.empty_like(rgba)
+            N.ivrgs_render_fwd(batch, self.settings.params(), proj, bins, scratch.data_ptr(), None,
+                               self.ws.data_ptr(), self.ws.numel(), _stream())
+            self._ckpt_generation = self.generation
         n = batch.g.n
         if grads is None:
             grads = {k: torch.empty((d, n), dtype=torch.float32, device=self.device)

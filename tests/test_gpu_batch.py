@@ -190,23 +190,28 @@ def bf16_ulp(x):
     return np.where(a > 0, 2.0 ** (e - 7), 2.0 ** -133)
 
 
-def mlp_logit_bound(x16, W1, b1, W2, b2, w3, b3):
+def mlp_logit_bound(x16, W1, b1, W2, b2, w3, b3, x_amb=None):
     """FP64 reference logits of the BF16 MLP and, per Gaussian, the largest
     difference an FP32 evaluation in any summation order may show: one bf16
     ulp on each first-layer activation whose FP32 sum (17 terms) lies within
     its accumulation error of a bf16 rounding boundary, times that
     activation's largest effect on the logit, plus the FP32 accumulation
     error of the second layer and the output (gamma_n = n 2^-24 times the
-    sums of magnitudes)."""
+    sums of magnitudes).  x_amb [n, 16] (optional): per input feature, the
+    size of a bf16 rounding the kernel may take the other way (a feature it
+    computes in FP32 that lies within a few FP32 ulps of a bf16 midpoint),
+    propagated through the first layer."""
     W1, W2 = W1.astype(np.float64), W2.astype(np.float64)
     b1, b2, w3 = (np.asarray(v, np.float64) for v in (b1, b2, w3))
     v1 = x16.astype(np.float64) @ W1.T + b1
-    e1 = 17 * 2.0 ** -24 * (np.abs(x16) @ np.abs(W1).T + np.abs(b1))
+    e_in = 0.0 if x_amb is None else x_amb @ np.abs(W1).T
+    e1 = 17 * 2.0 ** -24 * (np.abs(x16) @ np.abs(W1).T + np.abs(b1)) + e_in
     lo = bf16_round(np.maximum(v1 - e1, 0))
     hi = bf16_round(np.maximum(v1 + e1, 0))
     h1 = bf16_round(np.maximum(v1, 0)).astype(np.float64)
     reach = np.abs(W2).T @ np.abs(w3)
     amb = ((lo != hi) * np.maximum(bf16_ulp(lo), bf16_ulp(hi)) * reach[None, :]).sum(1)
+    amb = amb + (np.asarray(e_in) * reach[None, :]).sum(1) if x_amb is not None else amb
     h2 = np.maximum(h1 @ W2.T + b2, 0)
     g = 66 * 2.0 ** -24
     acc = g * ((np.abs(h1) @ np.abs(W2).T + np.abs(b2)) @ np.abs(w3)) + g * (np.abs(h2) @ np.abs(w3) + abs(b3))
@@ -238,18 +243,33 @@ def test_cull_mlp_matches_reference(dev):
     jobs = R.Jobs.single(5000)
     cu.run(pd, cams_t, jobs, 0, want_logits=True)
     got = cu.logits.cpu().numpy()
-    c = cam.center
-    d = c[None, :] - planes["mean"].T.astype(np.float64)
-    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    # the unit direction to the camera is computed by the kernel in FP32 and
+    # then rounded to bf16: the reference takes that rounding in the same
+    # precision, with the kernel's operation order (camera centre -R^T t,
+    # difference, squared length, reciprocal square root, product)
+    f32 = np.float32
+    Rm, tv = cam.R.astype(f32), cam.t.astype(f32)
+    cpos = np.array([-(Rm[0, i] * tv[0] + Rm[1, i] * tv[1] + Rm[2, i] * tv[2]) for i in range(3)], f32)
+    v = cpos[:, None] - planes["mean"].astype(f32)
+    inv = f32(1) / np.sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2])
+    d = (v * inv).T.astype(f32)
     x = np.concatenate([planes["mean"].T, planes["log_scale"].T, planes["opacity"].T, d], 1)
     x16 = np.zeros((5000, 16), np.float32)
     x16[:, :10] = bf16_round(x)
+    # a direction component within 4 FP32 ulps of a bf16 midpoint may round
+    # the other way in the kernel (its square root and division need not be
+    # correctly rounded): one bf16 ulp of input there
+    mid = (bf16_round(d) + np.float32(0.5) * bf16_ulp(d).astype(np.float32) * np.sign(d - bf16_round(d)))
+    near = np.abs(d.astype(np.float64) - mid) <= 4 * np.spacing(np.abs(d)).astype(np.float64)
+    x_amb = np.zeros((5000, 16))
+    x_amb[:, 7:10] = near * bf16_ulp(d)
     w1 = w.w1.cpu().numpy().astype(np.int32).astype(np.uint32) << 16
     w2 = w.w2.cpu().numpy().astype(np.int32).astype(np.uint32) << 16
     W1 = (w1 & 0xFFFF0000).astype(np.uint32).view(np.float32)
     W2 = (w2 & 0xFFFF0000).astype(np.uint32).view(np.float32)
     ref, bound = mlp_logit_bound(x16, W1, w.b1.cpu().numpy(), W2, w.b2.cpu().numpy(), w.w3.cpu().numpy(),
-                                 float(w.b3))
+                                 float(w.b3), x_amb)
+    say(f"cull mlp: {int(near.any(1).sum())} Gaussians with a direction component at a bf16 midpoint")
     err = np.abs(got - ref)
     say(f"cull mlp: max err {err.max():.3e}, max |logit| {np.abs(ref).max():.3e}, "
         f"worst err / bound {(err / bound).max():.3f}")

@@ -510,3 +510,74 @@ def test_maxw_labels_bound_removal_error():
         sub = {k: v[:, keep] for k, v in pl.items()}
         img2 = O.render(sub, cam, prm)["rgba"]
         assert np.abs(img - img2).max() <= 2 * maxw[i] * cmax + 1e-12
+
+
+def _fp32_alpha(planes, cam, lowpass, mx, my, px, py, idx):
+    """alpha of Gaussians idx at pixel centres (px, py), evaluated in FP32
+    with numpy (every operation rounded to float32, no fused multiply-add),
+    written independently of the oracle: Sigma = R diag(s^2) R^T, the camera
+    rotation, the EWA Jacobian, the 2x2 inverse by its adjugate.  The screen
+    mean (mx, my) is the oracle's rounded once to FP32, as a compensated
+    evaluation delivers it."""
+    f = np.float32
+    mean = planes["mean"][:, idx].astype(f)
+    s = np.exp(planes["log_scale"][:, idx].astype(f)).astype(f)
+    q = planes["quat"][:, idx].astype(f)
+    w, x, y, z = q / np.sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3])
+    one, two = f(1), f(2)
+    rot = np.array([[one - two * (y * y + z * z), two * (x * y - w * z), two * (x * z + w * y)],
+                    [two * (x * y + w * z), one - two * (x * x + z * z), two * (y * z - w * x)],
+                    [two * (x * z - w * y), two * (y * z + w * x), one - two * (x * x + y * y)]], dtype=f)
+    m = rot * s[None]
+
+    def mul(a, b, n_i, n_j, n_k):  # elementwise-batched small matrix product
+        return np.array([[sum(a[i][k] * b[k][j] for k in range(n_k)) for j in range(n_j)]
+                         for i in range(n_i)], dtype=f)
+
+    sig = mul(m, [[m[j][i] for j in range(3)] for i in range(3)], 3, 3, 3)
+    Wc = cam.R.astype(f)
+    t = [Wc[r, 0] * mean[0] + Wc[r, 1] * mean[1] + Wc[r, 2] * mean[2] + cam.t.astype(f)[r] for r in range(3)]
+    Wb = [[np.full(idx.shape, Wc[i, j], f) for j in range(3)] for i in range(3)]
+    cov = mul(mul(Wb, sig, 3, 3, 3), [[Wb[j][i] for j in range(3)] for i in range(3)], 3, 3, 3)
+    iz = one / t[2]
+    zero = np.zeros(idx.shape, f)
+    J = [[f(cam.fx) * iz, zero, -f(cam.fx) * t[0] * iz * iz], [zero, f(cam.fy) * iz, -f(cam.fy) * t[1] * iz * iz]]
+    s2 = mul(mul(J, cov, 2, 3, 3), [[J[j][i] for j in range(2)] for i in range(3)], 2, 2, 3)
+    a, b, c = s2[0, 0] + f(lowpass), s2[0, 1], s2[1, 1] + f(lowpass)
+    det = a * c - b * b
+    dx, dy = px.astype(f) - mx.astype(f), py.astype(f) - my.astype(f)
+    power = f(-0.5) * ((c / det) * dx * dx + two * (-b / det) * dx * dy + (a / det) * dy * dy)
+    return planes["opacity"][0, idx].astype(f) * np.exp(power).astype(f)
+
+
+@pytest.mark.parametrize("log_mu,sigma,width,lowpass", [(-4.0, 0.5, 128, 0.3), (-4.0, 0.5, 128, 0.0),
+                                                         (-2.5, 1.0, 128, 0.3), (-3.0, 1.0, 800, 0.3)])
+def test_fp32_error_model_covers_an_fp32_evaluation(log_mu, sigma, width, lowpass):
+    """The oracle's bound on the FP32 error of ln alpha (its ambiguity test,
+    2e-6 + (3e-7 kappa + 2e-6) |power| + |Q d|_1 dm) holds for an independent
+    FP32 evaluation of alpha at pixels across each Gaussian's footprint,
+    including very elongated ones (kappa up to ~2.5e4)."""
+    m = I.small_scene(4000, 11, log_scale_mu=log_mu, log_scale_sigma=sigma)
+    planes = I.plain_planes(m)
+    cam = I.look_at((0.3, -4.0, 1.0), width=width, height=width)
+    prm = O.Params(width, width)
+    prm.lowpass = lowpass
+    p = O.project(planes, cam, prm)
+    F = {k: i for i, k in enumerate(O.P_FIELDS)}
+    idx = np.where((p[:, F["valid"]] > 0) & (p[:, F["o"]] >= prm.alpha_min))[0]
+    assert idx.size > 1000
+    rng = np.random.default_rng(3)
+    worst = 0.0
+    for _ in range(8):
+        px = np.floor(p[idx, F["mx"]] + rng.uniform(-1, 1, idx.size) * p[idx, F["extx"]]) + 0.5
+        py = np.floor(p[idx, F["my"]] + rng.uniform(-1, 1, idx.size) * p[idx, F["exty"]]) + 0.5
+        a32 = _fp32_alpha(planes, cam, lowpass, p[idx, F["mx"]], p[idx, F["my"]], px, py, idx).astype(np.float64)
+        dx, dy = px - p[idx, F["mx"]], py - p[idx, F["my"]]
+        q00, q01, q11 = p[idx, F["q00"]], p[idx, F["q01"]], p[idx, F["q11"]]
+        power = -0.5 * (q00 * dx * dx + 2 * q01 * dx * dy + q11 * dy * dy)
+        a64 = p[idx, F["o"]] * np.exp(power)
+        bound = 2e-6 + (3e-7 * p[idx, F["kappa"]] + 2e-6) * np.abs(power) + \
+            (np.abs(q00 * dx + q01 * dy) + np.abs(q01 * dx + q11 * dy)) * p[idx, F["dm"]]
+        ok = (a64 > 1e-30) & (a32 > 0)  # FP32 underflow far out in the tail is no decision
+        worst = max(worst, float((np.abs(np.log(a32[ok]) - np.log(a64[ok])) / bound[ok]).max()))
+    assert worst <= 1.0, worst
