@@ -251,6 +251,30 @@ ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params
                             const ivrgs_projected *proj, ivrgs_bins *bins,
                             void *workspace, size_t workspace_bytes, void *stream);
 
+/* Size of the device scratch array behind ivrgs_bin_sort_noalloc (64 MiB).
+ * Every device that loads the library holds one until the process ends. */
+#define IVRGS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* ivrgs_bin_sort for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same result (tile_start, sorted, status), with the
+ * binning scratch in a static device array of IVRGS_NOALLOC_SCRATCH_BYTES
+ * instead of a caller workspace.  The caller still passes the projection
+ * and the bins.  The call allocates nothing; its first call on a device
+ * looks up that device's array (do it once outside graph capture).
+ * The scratch takes 16 bytes per record for the depth order, 32 per record
+ * for the binning fields, plus the digit histograms and the per-chunk tile
+ * counts (4 bytes per tile per chunk of params->sort_chunk records);
+ * IVRGS_E_CAPACITY if that exceeds IVRGS_NOALLOC_SCRATCH_BYTES (nothing is
+ * launched), IVRGS_E_UNSUPPORTED with IVRGS_FLAG_PERSISTENT (the render
+ * calls read that launch's work queue from their own workspace).  A render
+ * that follows needs no workspace from this call: with
+ * IVRGS_FLAG_FWD_ONLY, ivrgs_render_fwd takes none at all.  All calls on
+ * one device share the array, which keeps the last call's contents; calls
+ * that overlap on one device (concurrent streams or threads) race. */
+ivrgs_status ivrgs_bin_sort_noalloc(const ivrgs_batch *batch, const ivrgs_params *params,
+                                    const ivrgs_projected *proj, ivrgs_bins *bins, void *stream);
+
 /* Front-to-back alpha compositing (Eq. 2): per pixel C = sum T_i alpha_i c_i,
  * T_i = prod_{j<i} (1 - alpha_j).  out_rgba: [n_jobs][4][H][W].  out_maxw:
  * [n_records] or NULL; if given it must be zeroed by the caller and receives,

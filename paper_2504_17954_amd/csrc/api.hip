@@ -556,6 +556,61 @@ ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params
     return bin_sort_run(batch, params, proj, bins, L, dl, static_cast<char *>(workspace), stream);
 }
 
+}  // extern "C"
+
+// ------------------------------------------------ binning without allocation
+namespace ivrgs {
+namespace {
+// Scratch of ivrgs_bin_sort_noalloc: the binning regions of the workspace
+// layout (depth order, digit histograms, per-chunk tile counts and the
+// records' binning fields in depth order).  Every device that loads the
+// library holds its own copy until the process ends, and every call on a
+// device shares it.  In host code `scratch` only stands in for the array:
+// kernels get the device address that hipGetSymbolAddress returns.
+static __device__ __align__(256) unsigned char scratch[IVRGS_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+char *g_scratch[64];  // device address of `scratch`, per device
+
+// The current device's address of `scratch`, looked up on the first call on
+// that device (with it current) and kept.
+hipError_t scratch_address(char **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch[dev] = static_cast<char *>(ptr);
+    }
+    *out = g_scratch[dev];
+    return hipSuccess;
+}
+}  // namespace
+}  // namespace ivrgs
+
+extern "C" {
+
+ivrgs_status ivrgs_bin_sort_noalloc(const ivrgs_batch *batch, const ivrgs_params *params,
+                                    const ivrgs_projected *proj, ivrgs_bins *bins, void *stream) {
+    Layout L;
+    DeviceLimits dl;
+    const ivrgs_status st = bin_sort_check(batch, params, proj, bins, L, dl);
+    if (st != IVRGS_OK) return st;
+    // the work queue of a persistent launch lives in the render calls' workspace
+    if (params->flags & IVRGS_FLAG_PERSISTENT) return IVRGS_E_UNSUPPORTED;
+    // the binning regions come first in the layout and end where the record
+    // gradients begin
+    if (L.grec > (size_t)IVRGS_NOALLOC_SCRATCH_BYTES) return IVRGS_E_CAPACITY;
+    char *ws = nullptr;
+    if (scratch_address(&ws) != hipSuccess) return IVRGS_E_HIP;
+    return bin_sort_run(batch, params, proj, bins, L, dl, ws, stream);
+}
+
 ivrgs_status ivrgs_render_fwd(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
                               const ivrgs_bins *bins, float *out_rgba, float *out_maxw, void *workspace,
                               size_t workspace_bytes, void *stream) {

@@ -28,7 +28,8 @@ EXPORTS = ("ivrgs_workspace_size", "ivrgs_tiles_per_job", "ivrgs_compose", "ivrg
            "ivrgs_sh_color", "ivrgs_sh_color_bwd", "ivrgs_render_aux_fwd", "ivrgs_render_aux_bwd",
            "ivrgs_get_error", "ivrgs_ssim_workspace_size", "ivrgs_ssim_fwd", "ivrgs_ssim_bwd",
            "ivrgs_vq_fit_batch_workspace_size", "ivrgs_vq_fit_batch", "ivrgs_photometric_grad",
-           "ivrgs_reg_workspace_size", "ivrgs_reg_fwd", "ivrgs_reg_bwd")
+           "ivrgs_reg_workspace_size", "ivrgs_reg_fwd", "ivrgs_reg_bwd", "ivrgs_bin_sort_noalloc")
+NOALLOC_SCRATCH_BYTES = 64 << 20
 TIMING_KINDS = ("project", "tile_count", "scatter", "depth_sort", "render_fwd", "render_bwd",
                 "project_bwd", "compose", "fill", "cull", "edit_bwd", "vq", "sh", "aux")
 
@@ -137,6 +138,8 @@ def load(path: str = LIB_PATH):
     lib.ivrgs_compose.argtypes = [P, C.c_int32, P, P, P]
     lib.ivrgs_project.argtypes = [P, P, P, P]
     lib.ivrgs_bin_sort.argtypes = [P, P, P, P, P, C.c_size_t, P]
+    lib.ivrgs_bin_sort_noalloc.argtypes = [P, P, P, P, P]
+    lib.ivrgs_bin_sort_noalloc.restype = C.c_int
     lib.ivrgs_render_fwd.argtypes = [P, P, P, P, P, P, P, C.c_size_t, P]
     lib.ivrgs_render_bwd.argtypes = [P, P, P, P, P, P, P, P, C.c_size_t, P]
     for f in ("ivrgs_compose", "ivrgs_project", "ivrgs_bin_sort", "ivrgs_render_fwd",
@@ -366,6 +369,11 @@ def ivrgs_project(batch, params, proj, stream):
 def ivrgs_bin_sort(batch, params, proj, bins, ws_ptr, ws_bytes, stream):
     check(load().ivrgs_bin_sort(ref(batch), ref(params), ref(proj), ref(bins), ws_ptr, ws_bytes,
                                 stream), "ivrgs_bin_sort")
+
+
+def ivrgs_bin_sort_noalloc(batch, params, proj, bins, stream):
+    check(load().ivrgs_bin_sort_noalloc(ref(batch), ref(params), ref(proj), ref(bins), stream),
+          "ivrgs_bin_sort_noalloc")
 
 
 def ivrgs_render_fwd(batch, params, proj, bins, rgba_ptr, maxw_ptr, ws_ptr, ws_bytes, stream):
