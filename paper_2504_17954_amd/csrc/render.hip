@@ -219,6 +219,37 @@ __device__ __forceinline__ void fwd_tile(const Consts &k, const float4 *__restri
     }
 }
 
+// Per-wave LDS of the one-pixel-per-lane walks: the records of one step of
+// 64 that can reach the wave's pixels, compacted in list order, three float4
+// each: (x, y, qa, qb), (qc, cutoff, opacity, r), (g, b, id, lane of the
+// record in its step).
+struct WaveSlots {
+    float4 f[64][3];
+};
+
+// Orders this wave's LDS stores before its later loads (and the loads before
+// later stores): the lanes of one wave exchange records through LDS.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Compacts the records of lanes with `touch` (ballot m) into the wave's
+// slots, in lane order; returns their number.
+__device__ __forceinline__ int compact_records(WaveSlots &slots, uint64_t m, bool touch, float4 r0, float4 r1,
+                                               float4 r2, uint32_t rid, int lane) {
+    wave_lds_sync();  // the previous step's reads are done
+    if (touch) {
+        const int slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        slots.f[slot][0] = r0;
+        slots.f[slot][1] = make_float4(r1.x, r2.z, r1.y, r1.z);
+        slots.f[slot][2] = make_float4(r1.w, r2.x, __uint_as_float(rid), __int_as_float(lane));
+    }
+    wave_lds_sync();
+    return __builtin_popcountll(m);
+}
+
 // Forward of one tile with one pixel per lane, each wave on its own.  Wave
 // w owns the 8x8 quadrant (w % 2, w / 2) of the tile and walks the tile's
 // list 64 records at a time: every lane gathers one record into registers
@@ -237,7 +268,7 @@ __device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__r
                                               const uint32_t *__restrict__ starts,
                                               const uint32_t *__restrict__ sorted, float *__restrict__ out,
                                               float *__restrict__ maxw, int64_t *__restrict__ status, int64_t tile,
-                                              float4 *__restrict__ ckpt) {
+                                              float4 *__restrict__ ckpt, WaveSlots &slots) {
     const TileGeom tg = tile_geom(k, tile);
     const uint32_t start = starts[tile], end = starts[tile + 1];
     walk_priority(end - start);
@@ -291,46 +322,41 @@ __device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__r
         if (base + lane < end) touch = box_hit(make_hit_test(r0, r1, r2), bx.x0, bx.y0, bx.w, bx.h);
         if (base + 64 < end) load_recs(base + 64);
         if (base + 128 < end) load_ids(base + 128);
-        uint64_t m = __ballot(touch);
+        const uint64_t m = __ballot(touch);
+        if (m == 0ull) continue;
+        const int cnt = compact_records(slots, m, touch, r0, r1, r2, rid, lane);
         // Records are visited in groups of kGroupFwd.  Phase 1 computes, with
         // no branch, everything that does not depend on the compositing
-        // order (fields broadcast from the record's lane, exponent, cutoff
-        // test, power, alpha); the records are independent, so their
-        // instructions interleave.  Phase 2 is the front-to-back chain in
-        // list order, a few instructions per record.  The arithmetic of each
-        // record is the same as on every other path.
+        // order (fields read from LDS at one address for the whole wave,
+        // exponent, cutoff test, power, alpha); the records are independent,
+        // so their instructions interleave.  Phase 2 is the front-to-back
+        // chain in list order, a few instructions per record.  The
+        // arithmetic of each record is the same as on every other path.
         constexpr int kGroupFwd = 4;
-        auto bc = [&](float v, int src) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src)); };
-        while (m) {
-            int src[kGroupFwd];
-            bool valid[kGroupFwd];
-#pragma unroll
-            for (int g = 0; g < kGroupFwd; ++g) {
-                valid[g] = m != 0ull;  // wave-uniform
-                src[g] = valid[g] ? (int)__builtin_ctzll(m) : 0;
-                m &= m - 1;
-            }
+        for (int sl = 0; sl < cnt; sl += kGroupFwd) {
             float al[kGroupFwd], cr[kGroupFwd], cg[kGroupFwd], cb[kGroupFwd];
             bool pass[kGroupFwd];
+            int src[kGroupFwd];
 #pragma unroll
             for (int g = 0; g < kGroupFwd; ++g) {
-                const int sg = src[g];
-                const float p2 = splat_exponent(bc(r0.z, sg), bc(r0.w, sg), bc(r1.x, sg), px - bc(r0.x, sg),
-                                                py - bc(r0.y, sg));
+                const bool valid = sl + g < cnt;  // wave-uniform
+                src[g] = valid ? sl + g : sl;
+                const float4 a = slots.f[src[g]][0], b = slots.f[src[g]][1], c = slots.f[src[g]][2];
+                const float p2 = splat_exponent(a.z, a.w, b.x, px - a.x, py - a.y);
                 // below the cutoff alpha < alpha_min is certain
-                pass[g] = valid[g] && p2 >= bc(r2.z, sg);
-                al[g] = fminf(k.alpha_max, bc(r1.y, sg) * fast_exp2(p2));
-                cr[g] = bc(r1.z, sg);
-                cg[g] = bc(r1.w, sg);
-                cb[g] = bc(r2.x, sg);
+                pass[g] = valid & (p2 >= b.y);
+                al[g] = fminf(k.alpha_max, b.z * fast_exp2(p2));
+                cr[g] = b.w;
+                cg[g] = c.x;
+                cb[g] = c.y;
             }
 #pragma unroll
             for (int g = 0; g < kGroupFwd; ++g) {
                 const float Tn = T * (1.f - al[g]);
                 // alive as it stands after the records before this one
-                const bool use = alive && pass[g] && al[g] >= k.alpha_min;
-                const bool stop = use && Tn < k.T_min;
-                const bool comp = use && !stop;
+                const bool use = alive & pass[g] & (al[g] >= k.alpha_min);
+                const bool stop = use & (Tn < k.T_min);
+                const bool comp = use & !stop;
                 const float w = comp ? al[g] * T : 0.f;
                 C0 = fmaf(w, cr[g], C0);
                 C1 = fmaf(w, cg[g], C1);
@@ -338,13 +364,13 @@ __device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__r
                 T = comp ? Tn : T;
                 if (kCount) {
                     composited += comp ? 1u : 0u;
-                    if (stop) stop_at = base + (uint32_t)src[g];
+                    if (stop) stop_at = base + (uint32_t)__float_as_int(slots.f[src[g]][2].w);
                 }
-                alive = alive && !stop;
+                alive = alive & !stop;
                 if (kMaxw) {
                     if (__ballot(w > 0.f)) {
                         const float wm = wave_max_to_lane63(w);
-                        const uint32_t id = __builtin_amdgcn_readlane(rid, src[g]);
+                        const uint32_t id = __float_as_uint(slots.f[src[g]][2].z);
                         if (lane == 63) atomicMax(reinterpret_cast<int *>(&maxw[id]), __float_as_int(wm));
                     }
                 }
@@ -379,7 +405,11 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_fwd(Consts k, const fl
                                                              float *__restrict__ out, float *__restrict__ maxw,
                                                              int64_t *__restrict__ status, float4 *__restrict__ ckpt) {
     if (starts[n_tiles] == 0xFFFFFFFFu) return;
-    if constexpr (PX == 1) fwd_tile_wave<kMaxw, kCount>(k, rec, starts, sorted, out, maxw, status, blockIdx.x, ckpt);
+    if constexpr (PX == 1) {
+        __shared__ WaveSlots slots[kTilePix / 64];
+        fwd_tile_wave<kMaxw, kCount>(k, rec, starts, sorted, out, maxw, status, blockIdx.x, ckpt,
+                                     slots[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
+    }
     else fwd_tile<PX, kMaxw, kCount>(k, rec, starts, sorted, out, maxw, status, blockIdx.x);
 }
 
@@ -403,9 +433,13 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_fwd_persistent(
     const uint32_t n_items = queue[1];
     uint32_t item;
     while (next_item(queue, n_items, item)) {
-        if constexpr (PX == 1)
-            fwd_tile_wave<kMaxw, kCount>(k, rec, starts, sorted, out, maxw, status, queue[2 + item], nullptr);
-        else fwd_tile<PX, kMaxw, kCount>(k, rec, starts, sorted, out, maxw, status, queue[2 + item]);
+        if constexpr (PX == 1) {
+            __shared__ WaveSlots slots[kTilePix / 64];
+            fwd_tile_wave<kMaxw, kCount>(k, rec, starts, sorted, out, maxw, status, queue[2 + item], nullptr,
+                                         slots[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
+        } else {
+            fwd_tile<PX, kMaxw, kCount>(k, rec, starts, sorted, out, maxw, status, queue[2 + item]);
+        }
     }
 }
 
@@ -638,6 +672,193 @@ __device__ __forceinline__ void bwd_tile_wave(const Consts &k, const float4 *__r
     }
 }
 
+// Backward of one tile with one pixel per lane, each wave on its own 8x8
+// quadrant (the walk of fwd_tile_wave: 64 records gathered per step into
+// registers and tested against the box of the quadrant's live pixels).  The
+// records of a step that can reach the box are compacted, in list order,
+// into the wave's LDS slots; one pass over them keeps those whose exponent
+// passes the cutoff at a live pixel (a bit mask); the rest are visited in
+// groups of three.  Each record's fields are read from LDS with one address
+// for the whole wave (a broadcast).  A group first computes, without
+// branches, everything that does not depend on the compositing order (offset,
+// exponent, power, alpha, 1 / (1 - alpha), g . colour) for its three records,
+// then runs the front-to-back chain and writes each record's nine per-pixel
+// gradient terms into its slots of one reduce-scatter; records that
+// composite somewhere get one atomic per value.
+//
+// ckpt != nullptr: the workgroup walks segment `seg` of the tile's list
+// (split_of), starting from the forward's checkpoint at its cut: T exactly as
+// the forward had it, and the colour prefix as g . C.
+__device__ __forceinline__ void bwd_tile_quad(const Consts &k, const float4 *__restrict__ rec,
+                                              const uint32_t *__restrict__ starts,
+                                              const uint32_t *__restrict__ sorted, const float *__restrict__ rgba,
+                                              const float *__restrict__ dl, float *__restrict__ grec, int64_t tile,
+                                              int seg, const float4 *__restrict__ ckpt, WaveSlots &slots) {
+    const TileGeom tg = tile_geom(k, tile);
+    uint32_t start = starts[tile], end = starts[tile + 1];
+    if (ckpt) {
+        int nseg;
+        uint32_t seg_len;
+        split_of(end - start, nseg, seg_len);
+        if (seg >= nseg) return;  // the whole workgroup
+        start += (uint32_t)seg * seg_len;
+        end = min(end, start + seg_len);
+    } else if (seg > 0) {
+        return;
+    }
+    walk_priority(end - start);
+    const int lane = lane_id();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int sx = tg.tx * kTile + 8 * (wave & 1), sy = tg.ty * kTile + 8 * (wave >> 1);
+    const int x = sx + (lane & 7), y = sy + (lane >> 3);
+    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+    const size_t plane = (size_t)k.width * k.height;
+    // per pixel: upstream colour gradient g, g . out, gA T_final and the
+    // running g . P_i of the composited prefix
+    float T = 1.f, gP = 0.f, go = 0.f, gATf = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
+    bool alive = x < k.width && y < k.height;
+    if (alive) {
+        const float *img = rgba + (size_t)tg.job * 4 * plane;
+        const float *gimg = dl + (size_t)tg.job * 4 * plane;
+        const size_t o = (size_t)y * k.width + x;
+        const float Tf = 1.f - img[3 * plane + o];
+        g0 = gimg[o];
+        g1 = gimg[plane + o];
+        g2 = gimg[2 * plane + o];
+        const float gA = gimg[3 * plane + o];
+        go = fmaf(g2, img[2 * plane + o], fmaf(g1, img[plane + o], g0 * img[o]));
+        gATf = gA * Tf;
+        alive = (g0 != 0.f) | (g1 != 0.f) | (g2 != 0.f) | (gA != 0.f);
+    }
+    if (ckpt && seg > 0) {
+        const float4 c = ckpt[((size_t)tile * (kSplitMax - 1) + (seg - 1)) * kCkptPix + wave * 64 + lane];
+        if (c.x < 0.f) {
+            alive = false;  // terminated before the cut
+        } else {
+            T = c.x;
+            gP = fmaf(g2, c.w, fmaf(g1, c.z, g0 * c.y));
+        }
+    }
+    constexpr int kGroup = 3;
+    const int my_m = lane >> 1;
+    const bool my_slot = ((lane & 1) == 0) && my_m < kGroup * kGradRec;
+    const int my_g = my_m < kGroup * kGradRec ? my_m / kGradRec : 0, my_v = my_m % kGradRec;
+    float acc[32];
+#pragma unroll
+    for (int q = kGroup * kGradRec; q < 32; ++q) acc[q] = 0.f;  // never written
+
+    // the two-stage gather pipeline of fwd_tile_wave
+    float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0, n2 = n0;
+    uint32_t nid = 0, pid = 0;
+    auto load_ids = [&](uint32_t base) {
+        if (base + lane < end) pid = sorted[base + lane];
+    };
+    auto load_recs = [&](uint32_t base) {
+        if (base + lane < end) {
+            nid = pid;
+            n0 = rec[3 * (size_t)nid];
+            n1 = rec[3 * (size_t)nid + 1];
+            n2 = rec[3 * (size_t)nid + 2];
+        }
+    };
+    if (start < end) {
+        load_ids(start);
+        load_recs(start);
+        if (start + 64 < end) load_ids(start + 64);
+    }
+    for (uint32_t base = start; base < end; base += 64) {
+        const uint64_t live = __ballot(alive);
+        if (live == 0ull) break;
+        const PixBox bx = alive_box(live, sx, sy);
+        const float4 r0 = n0, r1 = n1, r2 = n2;
+        const uint32_t rid = nid;
+        const bool touch = base + lane < end && box_hit(make_hit_test(r0, r1, r2), bx.x0, bx.y0, bx.w, bx.h);
+        if (base + 64 < end) load_recs(base + 64);
+        if (base + 128 < end) load_ids(base + 128);
+        const uint64_t m = __ballot(touch);
+        if (m == 0ull) continue;
+        const int cnt = compact_records(slots, m, touch, r0, r1, r2, rid, lane);
+        // the records whose exponent passes the cutoff at a live pixel
+        uint64_t pm = 0;
+        for (int sl = 0; sl < cnt; ++sl) {
+            const float4 a = slots.f[sl][0], b = slots.f[sl][1];
+            const float p2 = splat_exponent(a.z, a.w, b.x, px - a.x, py - a.y);
+            if (__ballot(alive & (p2 >= b.y))) pm |= 1ull << sl;
+        }
+        while (pm) {
+            int src[kGroup];
+            bool valid[kGroup];
+#pragma unroll
+            for (int g = 0; g < kGroup; ++g) {
+                valid[g] = pm != 0ull;  // wave-uniform
+                src[g] = valid[g] ? (int)__builtin_ctzll(pm) : src[0];
+                pm &= pm - 1;
+            }
+            // order-free part of the three records
+            float dx[kGroup], dy[kGroup], G[kGroup], raw[kGroup], al[kGroup], om[kGroup], inv[kGroup], gc[kGroup];
+            bool pass[kGroup];
+#pragma unroll
+            for (int g = 0; g < kGroup; ++g) {
+                const float4 a = slots.f[src[g]][0], b = slots.f[src[g]][1], c = slots.f[src[g]][2];
+                dx[g] = px - a.x;
+                dy[g] = py - a.y;
+                const float p2 = splat_exponent(a.z, a.w, b.x, dx[g], dy[g]);
+                // below the cutoff alpha < alpha_min is certain
+                pass[g] = valid[g] & (p2 >= b.y);
+                G[g] = fast_exp2(p2);
+                raw[g] = b.z * G[g];
+                al[g] = fminf(k.alpha_max, raw[g]);
+                om[g] = 1.f - al[g];
+                inv[g] = __builtin_amdgcn_rcpf(om[g]);
+                gc[g] = fmaf(g2, c.y, fmaf(g1, c.x, g0 * b.w));
+            }
+            // the front-to-back chain, the arithmetic of the forward
+            bool hit[kGroup];
+#pragma unroll
+            for (int g = 0; g < kGroup; ++g) {
+                // bitwise logic: no short-circuit branches in the chain
+                const float Tn = T * om[g];
+                const bool use = alive & pass[g] & (al[g] >= k.alpha_min);
+                const bool stop = use & (Tn < k.T_min);
+                const bool comp = use & !stop;
+                const float w = comp ? al[g] * T : 0.f;
+                gP = fmaf(w, gc[g], gP);
+                // g . (colour behind this Gaussian, background included)
+                const float gb = go - gP;
+                const float dLda = fmaf(-(gb - gATf), inv[g], T * gc[g]);
+                // no gradient through alpha where the cap is active
+                const float dLdo = comp & (raw[g] <= k.alpha_max) ? dLda : 0.f;
+                const float dp = dLdo * raw[g];
+                float *ag = acc + g * kGradRec;
+                ag[GCR] = w * g0;
+                ag[GCG] = w * g1;
+                ag[GCB] = w * g2;
+                ag[GO] = dLdo * G[g];
+                // moments of dL/dG G about the mean (see GX .. GQC)
+                const float dpx = dp * dx[g], dpy = dp * dy[g];
+                ag[GX] = dpx;
+                ag[GY] = dpy;
+                ag[GQA] = dpx * dx[g];
+                ag[GQB] = dpx * dy[g];
+                ag[GQC] = dpy * dy[g];
+                T = comp ? Tn : T;
+                alive = alive & !stop;
+                hit[g] = __ballot(comp) != 0ull;
+            }
+            if (hit[0] | hit[1] | hit[2]) {
+                const float tot = reduce_scatter32(acc);
+                const bool ok = my_g == 0 ? hit[0] : (my_g == 1 ? hit[1] : hit[2]);
+                const int sg = my_g == 0 ? src[0] : (my_g == 1 ? src[1] : src[2]);
+                if (my_slot && ok && tot != 0.f) {
+                    const uint32_t id = __float_as_uint(slots.f[sg][2].z);
+                    atomicAdd(&grec[(size_t)id * kGradStride + my_v], tot);
+                }
+            }
+            if (__ballot(alive) == 0ull) break;  // every pixel of the wave is done
+        }
+    }
+}
+
 template <int PX>
 __global__ __launch_bounds__(kTilePix / PX) void k_render_bwd(Consts k, const float4 *__restrict__ rec,
                                                              const uint32_t *__restrict__ starts,
@@ -646,7 +867,13 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_bwd(Consts k, const fl
                                                              const float *__restrict__ dl, float *__restrict__ grec,
                                                              const float4 *__restrict__ ckpt) {
     if (starts[n_tiles] == 0xFFFFFFFFu) return;
-    bwd_tile_wave<PX>(k, rec, starts, sorted, rgba, dl, grec, blockIdx.x, blockIdx.y, ckpt);
+    if constexpr (PX == 1) {
+        __shared__ WaveSlots slots[kTilePix / 64];
+        bwd_tile_quad(k, rec, starts, sorted, rgba, dl, grec, blockIdx.x, blockIdx.y, ckpt,
+                      slots[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
+    } else {
+        bwd_tile_wave<PX>(k, rec, starts, sorted, rgba, dl, grec, blockIdx.x, blockIdx.y, ckpt);
+    }
 }
 
 template <int PX>
@@ -658,7 +885,13 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_bwd_persistent(
     const uint32_t n_items = queue[1];
     uint32_t item;
     while (next_item(queue, n_items, item)) {
-        bwd_tile_wave<PX>(k, rec, starts, sorted, rgba, dl, grec, queue[2 + item], 0, nullptr);
+        if constexpr (PX == 1) {
+            __shared__ WaveSlots slots[kTilePix / 64];
+            bwd_tile_quad(k, rec, starts, sorted, rgba, dl, grec, queue[2 + item], 0, nullptr,
+                          slots[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
+        } else {
+            bwd_tile_wave<PX>(k, rec, starts, sorted, rgba, dl, grec, queue[2 + item], 0, nullptr);
+        }
     }
 }
 
