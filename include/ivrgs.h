@@ -54,6 +54,16 @@ typedef enum {
                                      list checkpoints and needs no workspace (unless
                                      IVRGS_FLAG_PERSISTENT), and a render_bwd with the same flag
                                      walks every tile list whole */
+#define IVRGS_FLAG_DETERMINISTIC_BWD 8u
+                                  /* render_bwd's gradients are the same bit for bit on every
+                                     run: the per-record sums of all waves are added as 64-bit
+                                     integers (order-free) at a power-of-two scale that a first
+                                     walk over the same lists sets from the largest per-wave sum
+                                     of each value kind (its 2^-40 is the quantum), so the
+                                     backward walks the lists twice; jobs that share Gaussians
+                                     add their gradients in job order (one projection-backward
+                                     launch per job; a job lists a Gaussian at most once).  The
+                                     workspace grows by 72 bytes per record and 36 per tile. */
 
 /* Editable Gaussians (Sec. 4.3), device SoA planes of length n each:
  *   mean[3][n]       mu

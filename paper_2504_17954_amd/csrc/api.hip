@@ -127,7 +127,8 @@ ivrgs_status check_params(const ivrgs_params *p) {
     for (int px : {p->fwd_px, p->bwd_px})
         if (px != 0 && px != 1 && px != 2 && px != 4) return IVRGS_E_UNSUPPORTED;
     if (p->sort_chunk < 0 || p->persist_per_cu < 0) return IVRGS_E_INVALID;
-    if ((p->flags & ~(IVRGS_FLAG_PERSISTENT | IVRGS_FLAG_COUNT_EVAL | IVRGS_FLAG_FWD_ONLY)) != 0u)
+    if ((p->flags & ~(IVRGS_FLAG_PERSISTENT | IVRGS_FLAG_COUNT_EVAL | IVRGS_FLAG_FWD_ONLY |
+                      IVRGS_FLAG_DETERMINISTIC_BWD)) != 0u)
         return IVRGS_E_UNSUPPORTED;
     return IVRGS_OK;
 }
@@ -144,7 +145,7 @@ ivrgs_status check_batch(const ivrgs_batch *b) {
 
 // Workspace regions.
 struct Layout {
-    size_t key0, val0, key1, val1, hist, rng, counts, part, pay, grec, queue, ckpt, ckpt_bytes, total;
+    size_t key0, val0, key1, val1, hist, rng, counts, part, pay, grec, queue, ckpt, ckpt_bytes, det, total;
 };
 
 int pick_px(int requested, int fallback) { return requested == 0 ? fallback : requested; }
@@ -206,6 +207,13 @@ Layout layout(const ivrgs_batch &b, const ivrgs_params &p) {
     L.ckpt = off;
     L.ckpt_bytes = ckpt_bytes(b, p, k);
     off += align_up(L.ckpt_bytes);
+    // deterministic backward: 64-bit sums per record value, the largest sum
+    // per (tile, value kind) and the scales
+    L.det = off;
+    if (p.flags & IVRGS_FLAG_DETERMINISTIC_BWD)
+        off += align_up(sizeof(uint64_t) * kGradStride * (size_t)b.n_records) +
+               align_up(sizeof(uint32_t) * kGradRec * (size_t)b.n_jobs * k.tiles_per_job) +
+               align_up(sizeof(float) * 2 * kGradRec);
     L.total = off;
     return L;
 }
@@ -649,7 +657,19 @@ ivrgs_status ivrgs_render_bwd(const ivrgs_batch *batch, const ivrgs_params *para
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     float *grec = reinterpret_cast<float *>(static_cast<char *>(workspace) + L.grec);
     const int64_t n_tiles = (int64_t)batch->n_jobs * k.tiles_per_job;
-    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(grec), kGradStride * batch->n_records, 0u, s);
+    const bool det = (params->flags & IVRGS_FLAG_DETERMINISTIC_BWD) != 0;
+    DetWork dw;
+    if (det) {
+        char *d = static_cast<char *>(workspace) + L.det;
+        dw.gfix = reinterpret_cast<unsigned long long *>(d);
+        d += align_up(sizeof(uint64_t) * kGradStride * (size_t)batch->n_records);
+        dw.probe = reinterpret_cast<uint32_t *>(d);
+        d += align_up(sizeof(uint32_t) * kGradRec * (size_t)n_tiles);
+        dw.scale = reinterpret_cast<float *>(d);
+    }
+    // the deterministic walk writes every record gradient itself
+    hipError_t e = det ? hipSuccess
+                       : launch_fill_u32(reinterpret_cast<uint32_t *>(grec), kGradStride * batch->n_records, 0u, s);
     if (e == hipSuccess)
         e = launch_render_bwd(k, pick_px(params->bwd_px, 1), n_tiles, proj->rec, bins->tile_start, bins->sorted,
                               out_rgba, dl_drgba, grec,
@@ -659,7 +679,7 @@ ivrgs_status ivrgs_render_bwd(const ivrgs_batch *batch, const ivrgs_params *para
                               params->persist_per_cu,
                               L.ckpt_bytes ? reinterpret_cast<const float *>(static_cast<char *>(workspace) + L.ckpt)
                                            : nullptr,
-                              s);
+                              det ? &dw : nullptr, batch->n_records, s);
     // One job over the whole set (its range lies in [0, n) and has n
     // records) writes every Gaussian's gradient, zeros included; otherwise
     // the planes are cleared first and, when several jobs may share a
@@ -672,7 +692,7 @@ ivrgs_status ivrgs_render_bwd(const ivrgs_batch *batch, const ivrgs_params *para
     const int dims[7] = {3, 3, 4, 1, 3, 3, 4};
     for (int p = 0; p < 7 && e == hipSuccess && !dense; ++p)
         e = launch_fill_u32(reinterpret_cast<uint32_t *>(planes[p]), dims[p] * n, 0u, s);
-    if (e == hipSuccess) e = launch_project_bwd(*batch, k, proj->rect, grec, *grads, shared, dense, s);
+    if (e == hipSuccess) e = launch_project_bwd(*batch, k, proj->rect, grec, *grads, shared, dense, s, det);
     return hip_status(e);
 }
 

@@ -32,8 +32,12 @@ size_t col_part_words(const ivrgs_batch &b, const Consts &k, int chunk);
 
 hipError_t launch_project(const ivrgs_batch &b, const Consts &k, float *rec, uint32_t *rect, uint32_t *depth,
                           int64_t *nonfinite, hipStream_t s);
+// atomic: several jobs may share a Gaussian; job_order: then add the jobs'
+// gradients one launch per job, in job order, instead of with atomics (the
+// sums are then reproducible bit for bit).
 hipError_t launch_project_bwd(const ivrgs_batch &b, const Consts &k, const uint32_t *rect, const float *grec,
-                              const ivrgs_gaussians_mut &out, bool atomic, bool dense, hipStream_t s);
+                              const ivrgs_gaussians_mut &out, bool atomic, bool dense, hipStream_t s,
+                              bool job_order = false);
 // Models model0 .. model0 + count - 1 (count <= kComposeModels) in one
 // launch: src[j] goes to out[offset[j] ...).  host_e != nullptr: edit values
 // from the host rows host_e[j]; else from dev_table[model0 + j].
@@ -64,9 +68,20 @@ hipError_t set_bin_lds_limit(size_t bytes);
 hipError_t launch_render_fwd(const Consts &k, int px, int64_t n_tiles, const float *rec, const uint32_t *starts,
                              const uint32_t *sorted, float *out, float *maxw, int64_t *status, bool count,
                              uint32_t *queue, int per_cu, float *ckpt, hipStream_t s);
+// Buffers of the deterministic backward (IVRGS_FLAG_DETERMINISTIC_BWD):
+// probe [n_tiles][kGradRec] words, scale 2 * kGradRec floats, gfix
+// [n_records][kGradStride] 64-bit integer sums.
+struct DetWork {
+    uint32_t *probe;
+    float *scale;
+    unsigned long long *gfix;
+};
+// det == nullptr: record gradients accumulated with float atomics; else
+// bit-reproducible (two walks, 64-bit integer sums; see render.hip).
 hipError_t launch_render_bwd(const Consts &k, int px, int64_t n_tiles, const float *rec, const uint32_t *starts,
                              const uint32_t *sorted, const float *rgba, const float *dl, float *grec,
-                             uint32_t *queue, int per_cu, const float *ckpt, hipStream_t s);
+                             uint32_t *queue, int per_cu, const float *ckpt, const DetWork *det,
+                             int64_t n_records, hipStream_t s);
 hipError_t launch_cull(const ivrgs_gaussians &g, const ivrgs_camera *cams, int camera, const ivrgs_culler &mlp,
                        int32_t *out_index, ivrgs_job *jobs, int job, float *logits, uint8_t *keep,
                        uint32_t *counts, hipStream_t s);

@@ -356,10 +356,15 @@ __device__ __forceinline__ void shade_bwd(const GIn &a, const Fwd &f, const floa
 // parameter gradients, by the chain rule through the forward above.
 // kDense (one job over every Gaussian, no index list): each Gaussian is
 // written exactly once, zeros included, so the output needs no clearing.
-template <bool kAtomic, bool kDense>
+// kOut: how a Gaussian's gradient reaches `out`: stored (kOutStore), added
+// with float atomics (kOutAtomic: several jobs of one launch may share it) or
+// added without atomics (kOutAccum: one launch per job, in job order, so the
+// sums do not depend on the order of the atomics).
+enum { kOutStore = 0, kOutAtomic = 1, kOutAccum = 2 };
+template <int kOut, bool kDense>
 __global__ __launch_bounds__(256) void k_project_bwd(ivrgs_batch b, Consts k, const uint2 *__restrict__ rect,
                                                      const float *__restrict__ grec, ivrgs_gaussians_mut out) {
-    static_assert(!(kAtomic && kDense), "dense output is written, not accumulated");
+    static_assert(!(kOut != kOutStore && kDense), "dense output is written, not accumulated");
     const ivrgs_job job = b.jobs[blockIdx.y];
     const int local = blockIdx.x * blockDim.x + threadIdx.x;
     if (local >= job.gauss_count) return;
@@ -523,7 +528,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(ivrgs_batch b, Consts k, co
     }
 
     const int64_t n = out.n;
-    if (kAtomic) {
+    if (kOut == kOutAtomic) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             atomicAdd(&out.mean[c * n + gi], g_mu[c]);
@@ -537,6 +542,20 @@ __global__ __launch_bounds__(256) void k_project_bwd(ivrgs_batch b, Consts k, co
             atomicAdd(&out.shade[c * n + gi], g_k[c]);
         }
         atomicAdd(&out.opacity[gi], g_o);
+    } else if (kOut == kOutAccum) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            out.mean[c * n + gi] += g_mu[c];
+            out.log_scale[c * n + gi] += g_ls[c];
+            out.normal[c * n + gi] += g_n[c];
+            out.color[c * n + gi] += g_c[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            out.quat[c * n + gi] += g_q[c];
+            out.shade[c * n + gi] += g_k[c];
+        }
+        out.opacity[gi] += g_o;
     } else {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -827,17 +846,29 @@ hipError_t launch_project(const ivrgs_batch &b, const Consts &k, float *rec, uin
 }
 
 hipError_t launch_project_bwd(const ivrgs_batch &b, const Consts &k, const uint32_t *rect, const float *grec,
-                              const ivrgs_gaussians_mut &out, bool atomic, bool dense, hipStream_t s) {
+                              const ivrgs_gaussians_mut &out, bool atomic, bool dense, hipStream_t s,
+                              bool job_order) {
     if (b.n_jobs == 0 || b.max_job_count == 0) return hipSuccess;
     dim3 grid((b.max_job_count + 255) / 256, b.n_jobs);
     const uint2 *rc = reinterpret_cast<const uint2 *>(rect);
     TimedScope ts(TK_PROJECT_BWD, s);
-    if (atomic)
-        hipLaunchKernelGGL((k_project_bwd<true, false>), grid, dim3(256), 0, s, b, k, rc, grec, out);
-    else if (dense)
-        hipLaunchKernelGGL((k_project_bwd<false, true>), grid, dim3(256), 0, s, b, k, rc, grec, out);
-    else
-        hipLaunchKernelGGL((k_project_bwd<false, false>), grid, dim3(256), 0, s, b, k, rc, grec, out);
+    if (atomic && job_order) {
+        // one launch per job, in job order, each adding its Gaussians'
+        // gradients (a job lists a Gaussian at most once)
+        for (int j = 0; j < b.n_jobs; ++j) {
+            ivrgs_batch bj = b;
+            bj.jobs = b.jobs + j;
+            bj.n_jobs = 1;
+            hipLaunchKernelGGL((k_project_bwd<kOutAccum, false>), dim3(grid.x, 1), dim3(256), 0, s, bj, k, rc, grec,
+                               out);
+        }
+    } else if (atomic) {
+        hipLaunchKernelGGL((k_project_bwd<kOutAtomic, false>), grid, dim3(256), 0, s, b, k, rc, grec, out);
+    } else if (dense) {
+        hipLaunchKernelGGL((k_project_bwd<kOutStore, true>), grid, dim3(256), 0, s, b, k, rc, grec, out);
+    } else {
+        hipLaunchKernelGGL((k_project_bwd<kOutStore, false>), grid, dim3(256), 0, s, b, k, rc, grec, out);
+    }
     return hipGetLastError();
 }
 

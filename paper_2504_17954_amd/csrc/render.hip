@@ -21,6 +21,8 @@
 // gradients of three Gaussians are summed over the wave with one
 // reduce-scatter and added to the records' gradients with one atomic per
 // value.
+#include <algorithm>
+
 #include "launch.hpp"
 
 namespace ivrgs {
@@ -444,6 +446,46 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_fwd_persistent(
 }
 
 // ----------------------------------------------------------------------------
+// Where a backward walk puts each record's per-wave sums (one value kind per
+// lane, my_v).  kSinkFloat: float atomics into grec.  The deterministic mode
+// runs the walk twice: kSinkProbe keeps the largest |sum| of each value kind
+// over the tile (a lane-local running maximum, then one atomicMax of its FP32
+// bits per lane into probe[tile][9]); kSinkFixed adds each sum to gfix as a
+// 64-bit integer, sum * scale[v] rounded, where the power of two scale[v] puts
+// the largest |sum| below 2^40.  The integer sums do not depend on the order
+// in which waves add them.
+enum { kSinkFloat = 0, kSinkProbe = 1, kSinkFixed = 2 };
+struct GradSink {
+    float *grec;
+    uint32_t *probe;
+    unsigned long long *gfix;
+    const float *scale;
+};
+
+template <int kMode>
+struct SinkLane {
+    float scale = 0.f, vmax = 0.f;
+    __device__ __forceinline__ void init(const GradSink &s, int my_v) {
+        if (kMode == kSinkFixed) scale = s.scale[my_v];
+    }
+    // tot: the wave's sum of value my_v for record id
+    __device__ __forceinline__ void add(const GradSink &s, uint32_t id, int my_v, float tot) {
+        if constexpr (kMode == kSinkFloat) {
+            atomicAdd(&s.grec[(size_t)id * kGradStride + my_v], tot);
+        } else if constexpr (kMode == kSinkProbe) {
+            vmax = fmaxf(vmax, fabsf(tot));
+        } else {
+            const long long q = (long long)rintf(tot * scale);
+            atomicAdd(&s.gfix[(size_t)id * kGradStride + my_v], (unsigned long long)q);
+        }
+    }
+    __device__ __forceinline__ void flush(const GradSink &s, int64_t tile, int my_v, bool my_slot) {
+        if (kMode == kSinkProbe && my_slot && vmax > 0.f)
+            atomicMax(&s.probe[tile * kGradRec + my_v], __float_as_uint(vmax));
+    }
+};
+
+// ----------------------------------------------------------------------------
 // Backward of one tile, each wave on its own region (the walk of
 // fwd_tile_wave: 64 records gathered per step into registers, a ballot of the
 // records that can reach the region, fields broadcast from the record's
@@ -459,11 +501,11 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_fwd_persistent(
 // ckpt != nullptr (one pixel per lane): the workgroup walks segment `seg` of
 // the tile's list (split_of), starting from the forward's checkpoint at its
 // cut: T exactly as the forward had it, and the colour prefix as g . C.
-template <int PX>
+template <int PX, int kMode>
 __device__ __forceinline__ void bwd_tile_wave(const Consts &k, const float4 *__restrict__ rec,
                                               const uint32_t *__restrict__ starts,
                                               const uint32_t *__restrict__ sorted, const float *__restrict__ rgba,
-                                              const float *__restrict__ dl, float *__restrict__ grec, int64_t tile,
+                                              const float *__restrict__ dl, const GradSink &sink, int64_t tile,
                                               int seg, const float4 *__restrict__ ckpt) {
     const TileGeom tg = tile_geom(k, tile);
     uint32_t start = starts[tile], end = starts[tile + 1];
@@ -532,6 +574,8 @@ __device__ __forceinline__ void bwd_tile_wave(const Consts &k, const float4 *__r
     const int my_m = lane >> 1;
     const bool my_slot = ((lane & 1) == 0) && my_m < kGroup * kGradRec;
     const int my_g = my_m / kGradRec, my_v = my_m % kGradRec;
+    SinkLane<kMode> out;
+    out.init(sink, my_v);
 
     // records of the current step (r*, rid) and of the next one (n*, nid),
     // ids of the step after (pid): the two-stage pipeline of fwd_tile_wave
@@ -667,9 +711,10 @@ __device__ __forceinline__ void bwd_tile_wave(const Consts &k, const float4 *__r
             const float tot = reduce_scatter32(acc);
             const bool ok = my_g == 0 ? filled[0] : (my_g == 1 ? filled[1] : filled[2]);
             const uint32_t id = my_g == 0 ? ids[0] : (my_g == 1 ? ids[1] : ids[2]);
-            if (my_slot && ok && tot != 0.f) atomicAdd(&grec[(size_t)id * kGradStride + my_v], tot);
+            if (my_slot && ok && tot != 0.f) out.add(sink, id, my_v, tot);
         }
     }
+    out.flush(sink, tile, my_v, my_slot);
 }
 
 // Backward of one tile with one pixel per lane, each wave on its own 8x8
@@ -689,10 +734,11 @@ __device__ __forceinline__ void bwd_tile_wave(const Consts &k, const float4 *__r
 // ckpt != nullptr: the workgroup walks segment `seg` of the tile's list
 // (split_of), starting from the forward's checkpoint at its cut: T exactly as
 // the forward had it, and the colour prefix as g . C.
+template <int kMode>
 __device__ __forceinline__ void bwd_tile_quad(const Consts &k, const float4 *__restrict__ rec,
                                               const uint32_t *__restrict__ starts,
                                               const uint32_t *__restrict__ sorted, const float *__restrict__ rgba,
-                                              const float *__restrict__ dl, float *__restrict__ grec, int64_t tile,
+                                              const float *__restrict__ dl, const GradSink &sink, int64_t tile,
                                               int seg, const float4 *__restrict__ ckpt, WaveSlots &slots) {
     const TileGeom tg = tile_geom(k, tile);
     uint32_t start = starts[tile], end = starts[tile + 1];
@@ -743,6 +789,8 @@ __device__ __forceinline__ void bwd_tile_quad(const Consts &k, const float4 *__r
     const int my_m = lane >> 1;
     const bool my_slot = ((lane & 1) == 0) && my_m < kGroup * kGradRec;
     const int my_g = my_m < kGroup * kGradRec ? my_m / kGradRec : 0, my_v = my_m % kGradRec;
+    SinkLane<kMode> out;
+    out.init(sink, my_v);
     float acc[32];
 #pragma unroll
     for (int q = kGroup * kGradRec; q < 32; ++q) acc[q] = 0.f;  // never written
@@ -850,48 +898,80 @@ __device__ __forceinline__ void bwd_tile_quad(const Consts &k, const float4 *__r
                 const bool ok = my_g == 0 ? hit[0] : (my_g == 1 ? hit[1] : hit[2]);
                 const int sg = my_g == 0 ? src[0] : (my_g == 1 ? src[1] : src[2]);
                 if (my_slot && ok && tot != 0.f) {
-                    const uint32_t id = __float_as_uint(slots.f[sg][2].z);
-                    atomicAdd(&grec[(size_t)id * kGradStride + my_v], tot);
+                    const uint32_t id = kMode == kSinkProbe ? 0u : __float_as_uint(slots.f[sg][2].z);
+                    out.add(sink, id, my_v, tot);
                 }
             }
             if (__ballot(alive) == 0ull) break;  // every pixel of the wave is done
         }
     }
+    out.flush(sink, tile, my_v, my_slot);
 }
 
-template <int PX>
+template <int PX, int kMode>
 __global__ __launch_bounds__(kTilePix / PX) void k_render_bwd(Consts k, const float4 *__restrict__ rec,
                                                              const uint32_t *__restrict__ starts,
                                                              const uint32_t *__restrict__ sorted, int64_t n_tiles,
                                                              const float *__restrict__ rgba,
-                                                             const float *__restrict__ dl, float *__restrict__ grec,
+                                                             const float *__restrict__ dl, GradSink sink,
                                                              const float4 *__restrict__ ckpt) {
     if (starts[n_tiles] == 0xFFFFFFFFu) return;
     if constexpr (PX == 1) {
         __shared__ WaveSlots slots[kTilePix / 64];
-        bwd_tile_quad(k, rec, starts, sorted, rgba, dl, grec, blockIdx.x, blockIdx.y, ckpt,
-                      slots[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
+        bwd_tile_quad<kMode>(k, rec, starts, sorted, rgba, dl, sink, blockIdx.x, blockIdx.y, ckpt,
+                             slots[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
     } else {
-        bwd_tile_wave<PX>(k, rec, starts, sorted, rgba, dl, grec, blockIdx.x, blockIdx.y, ckpt);
+        bwd_tile_wave<PX, kMode>(k, rec, starts, sorted, rgba, dl, sink, blockIdx.x, blockIdx.y, ckpt);
     }
 }
 
-template <int PX>
+template <int PX, int kMode>
 __global__ __launch_bounds__(kTilePix / PX) void k_render_bwd_persistent(
     Consts k, const float4 *__restrict__ rec, const uint32_t *__restrict__ starts,
     const uint32_t *__restrict__ sorted, int64_t n_tiles, const float *__restrict__ rgba,
-    const float *__restrict__ dl, float *__restrict__ grec, uint32_t *__restrict__ queue) {
+    const float *__restrict__ dl, GradSink sink, uint32_t *__restrict__ queue) {
     if (starts[n_tiles] == 0xFFFFFFFFu) return;
     const uint32_t n_items = queue[1];
     uint32_t item;
     while (next_item(queue, n_items, item)) {
         if constexpr (PX == 1) {
             __shared__ WaveSlots slots[kTilePix / 64];
-            bwd_tile_quad(k, rec, starts, sorted, rgba, dl, grec, queue[2 + item], 0, nullptr,
-                          slots[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
+            bwd_tile_quad<kMode>(k, rec, starts, sorted, rgba, dl, sink, queue[2 + item], 0, nullptr,
+                                 slots[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
         } else {
-            bwd_tile_wave<PX>(k, rec, starts, sorted, rgba, dl, grec, queue[2 + item], 0, nullptr);
+            bwd_tile_wave<PX, kMode>(k, rec, starts, sorted, rgba, dl, sink, queue[2 + item], 0, nullptr);
         }
+    }
+}
+
+// Deterministic mode, between the two walks: scale[v] = 2^(40 - e) with
+// 2^(e-1) <= max over tiles of probe[tile][v] < 2^e (1 if nothing was
+// added), and its inverse.  One workgroup of kGradRec * 64 threads.
+__global__ __launch_bounds__(kGradRec * 64) void k_det_scale(const uint32_t *__restrict__ probe, int64_t n_tiles,
+                                                             float *__restrict__ scale) {
+    const int v = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t m = 0;
+    for (int64_t t = lane; t < n_tiles; t += 64) m = max(m, probe[t * kGradRec + v]);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d, 64));
+    if (lane == 0) {
+        int e = 0;
+        if (m != 0u) {
+            frexpf(__uint_as_float(m), &e);
+            e = max(e, -80);
+        }
+        scale[v] = m ? ldexpf(1.f, 40 - e) : 1.f;
+        scale[kGradRec + v] = m ? ldexpf(1.f, e - 40) : 1.f;
+    }
+}
+
+// Deterministic mode, after the second walk: the FP32 record gradients from
+// their integer sums.
+__global__ void k_det_finish(const unsigned long long *__restrict__ gfix, const float *__restrict__ scale,
+                             int64_t n, float *__restrict__ grec) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int v = (int)(i % kGradRec);
+        grec[i] = (float)((double)(long long)gfix[i] * (double)scale[kGradRec + v]);
     }
 }
 
@@ -976,40 +1056,69 @@ hipError_t launch_render_fwd(const Consts &k, int px, int64_t n_tiles, const flo
     return hipGetLastError();
 }
 
-template <int PX>
+template <int PX, int kMode>
 static void bwd_variant(hipStream_t s, const Consts &k, const float4 *rec, const uint32_t *starts,
-                        const uint32_t *sorted, int64_t n_tiles, const float *rgba, const float *dl, float *grec,
-                        uint32_t *queue, int per_cu, const float4 *ckpt) {
+                        const uint32_t *sorted, int64_t n_tiles, const float *rgba, const float *dl,
+                        const GradSink &sink, uint32_t *queue, int per_cu, const float4 *ckpt) {
     constexpr int NT = kTilePix / PX;
     if (queue) {
         static int occ = 0;  // queried once
-        if (occ == 0) occ = resident_blocks(k_render_bwd_persistent<PX>, NT);
+        if (occ == 0) occ = resident_blocks(k_render_bwd_persistent<PX, kMode>, NT);
         const int nb = per_cu > 0 ? per_cu : occ;
-        hipLaunchKernelGGL(k_render_bwd_persistent<PX>, dim3((unsigned)(nb * cu_count())), dim3(NT), 0, s, k, rec,
-                           starts, sorted, n_tiles, rgba, dl, grec, queue);
+        hipLaunchKernelGGL((k_render_bwd_persistent<PX, kMode>), dim3((unsigned)(nb * cu_count())), dim3(NT), 0, s,
+                           k, rec, starts, sorted, n_tiles, rgba, dl, sink, queue);
     } else {
         // one workgroup per (tile, segment of its list)
-        hipLaunchKernelGGL(k_render_bwd<PX>, dim3((unsigned)n_tiles, ckpt ? kSplitMax : 1), dim3(NT), 0, s, k, rec,
-                           starts, sorted, n_tiles, rgba, dl, grec, ckpt);
+        hipLaunchKernelGGL((k_render_bwd<PX, kMode>), dim3((unsigned)n_tiles, ckpt ? kSplitMax : 1), dim3(NT), 0, s,
+                           k, rec, starts, sorted, n_tiles, rgba, dl, sink, ckpt);
     }
 }
 
-hipError_t launch_render_bwd(const Consts &k, int px, int64_t n_tiles, const float *rec, const uint32_t *starts,
-                             const uint32_t *sorted, const float *rgba, const float *dl, float *grec,
-                             uint32_t *queue, int per_cu, const float *ckpt, hipStream_t s) {
-    const float4 *ck = px == 1 && !queue ? reinterpret_cast<const float4 *>(ckpt) : nullptr;
-    if (n_tiles == 0) return hipSuccess;
-    const float4 *r4 = reinterpret_cast<const float4 *>(rec);
+template <int kMode>
+static hipError_t bwd_walk(const Consts &k, int px, int64_t n_tiles, const float4 *r4, const uint32_t *starts,
+                           const uint32_t *sorted, const float *rgba, const float *dl, const GradSink &sink,
+                           uint32_t *queue, int per_cu, const float4 *ck, hipStream_t s) {
     if (queue) {
-        hipError_t e = launch_fill_u32(queue, 1, 0u, s);
+        hipError_t e = launch_fill_u32(queue, 1, 0u, s);  // reset the work counter
         if (e != hipSuccess) return e;
     }
     TimedScope ts(TK_BWD, s);
     switch (px) {
-    case 1: bwd_variant<1>(s, k, r4, starts, sorted, n_tiles, rgba, dl, grec, queue, per_cu, ck); break;
-    case 2: bwd_variant<2>(s, k, r4, starts, sorted, n_tiles, rgba, dl, grec, queue, per_cu, nullptr); break;
-    default: bwd_variant<4>(s, k, r4, starts, sorted, n_tiles, rgba, dl, grec, queue, per_cu, nullptr); break;
+    case 1: bwd_variant<1, kMode>(s, k, r4, starts, sorted, n_tiles, rgba, dl, sink, queue, per_cu, ck); break;
+    case 2: bwd_variant<2, kMode>(s, k, r4, starts, sorted, n_tiles, rgba, dl, sink, queue, per_cu, nullptr); break;
+    default: bwd_variant<4, kMode>(s, k, r4, starts, sorted, n_tiles, rgba, dl, sink, queue, per_cu, nullptr); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_render_bwd(const Consts &k, int px, int64_t n_tiles, const float *rec, const uint32_t *starts,
+                             const uint32_t *sorted, const float *rgba, const float *dl, float *grec,
+                             uint32_t *queue, int per_cu, const float *ckpt, const DetWork *det,
+                             int64_t n_records, hipStream_t s) {
+    const float4 *ck = px == 1 && !queue ? reinterpret_cast<const float4 *>(ckpt) : nullptr;
+    if (n_tiles == 0) return hipSuccess;
+    const float4 *r4 = reinterpret_cast<const float4 *>(rec);
+    GradSink sink = {grec, nullptr, nullptr, nullptr};
+    if (!det) return bwd_walk<kSinkFloat>(k, px, n_tiles, r4, starts, sorted, rgba, dl, sink, queue, per_cu, ck, s);
+    // deterministic: the largest |sum| per value kind, its scale, then the
+    // integer sums and their FP32 values
+    sink.probe = det->probe;
+    sink.gfix = det->gfix;
+    sink.scale = det->scale;
+    hipError_t e = launch_fill_u32(det->probe, n_tiles * kGradRec, 0u, s);
+    if (e == hipSuccess)
+        e = bwd_walk<kSinkProbe>(k, px, n_tiles, r4, starts, sorted, rgba, dl, sink, queue, per_cu, ck, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_det_scale, dim3(1), dim3(kGradRec * 64), 0, s, det->probe, n_tiles, det->scale);
+    e = hipGetLastError();
+    if (e == hipSuccess)
+        e = launch_fill_u32(reinterpret_cast<uint32_t *>(det->gfix), 2 * kGradStride * n_records, 0u, s);
+    if (e == hipSuccess)
+        e = bwd_walk<kSinkFixed>(k, px, n_tiles, r4, starts, sorted, rgba, dl, sink, queue, per_cu, ck, s);
+    if (e != hipSuccess) return e;
+    const int64_t nv = kGradStride * n_records;
+    const unsigned blocks = (unsigned)std::min<int64_t>((nv + 255) / 256, 65535);
+    if (nv > 0) hipLaunchKernelGGL(k_det_finish, dim3(blocks), dim3(256), 0, s, det->gfix, det->scale, nv, grec);
     return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@ DEV_E_CAPACITY = 1
 FLAG_PERSISTENT = 1
 FLAG_COUNT_EVAL = 2
 FLAG_FWD_ONLY = 4
+FLAG_DETERMINISTIC_BWD = 8
 EXPORTS = ("ivrgs_workspace_size", "ivrgs_tiles_per_job", "ivrgs_compose", "ivrgs_project",
            "ivrgs_bin_sort", "ivrgs_render_fwd", "ivrgs_render_bwd", "ivrgs_struct_size",
            "ivrgs_status_string", "ivrgs_timing_enable", "ivrgs_timing_read",
