@@ -3,106 +3,113 @@
 // Sec. 4.3 that the training regularisers read; and their backward, to the
 // attributes and, through alpha and the depth, to the geometry.
 //
-// One workgroup per 16x16 tile, one pixel per thread, every pixel walking
-// its tile's list in order with the image forward's arithmetic, so the
-// composited pairs are exactly those of the image.  The forward runs each
-// wave on its own over its 8x8 quadrant with the records in registers.  The
-// backward stages the list through LDS 256 records at a time, so that the
-// four waves can sum each record's gradients in LDS before one set of global
-// atomics per workgroup; each wave takes the staged records 64 at a time
-// into registers.
+// One workgroup per 16x16 tile; each wave walks the tile's list on its own
+// over its 8x8 quadrant, one pixel per lane, with the image forward's
+// arithmetic, so the composited pairs are exactly those of the image.  A
+// step gathers 64 records (and their attributes) into registers, one step
+// ahead of its use; the records whose ellipse reaches the box of the
+// quadrant's live pixels are compacted, in list order, into the wave's LDS
+// slots, and each is read from there at one address for the whole wave.  No
+// workgroup barrier: a wave stops when its own pixels are done.  The
+// backward sums each composited record's values over the wave with one
+// reduce-scatter and adds them with one atomic per value.
 #include "launch.hpp"
 
 namespace ivrgs {
 
 namespace {
 
-constexpr int kAuxChunk = 256;        // records staged per pass
 constexpr int kAuxAcc = 7 + kAuxMax;  // per-record sums of the backward: GO, GX, GY, GQA..GQC, depth, attributes
 static_assert(kAuxAcc <= 32, "one reduce-scatter of 32 values per record");
 
-struct AuxStage {
-    float4 s0[kAuxChunk];  // mean x, mean y, qa, qb
-    float4 s1[kAuxChunk];  // qc, opacity, depth, cutoff
-    float sa[kAuxMax][kAuxChunk];
-    int64_t gid[kAuxChunk];
-    uint32_t rid[kAuxChunk];
-    uint32_t wmask[kAuxChunk];  // bit w: the record can reach wave w's 16x4 strip of the tile
-    int any_alive;
+// Per-wave LDS: the compacted records of one step.
+struct AuxSlots {
+    float4 f0[64];            // mean x, mean y, qa, qb
+    float4 f1[64];            // qc, opacity, depth, cutoff
+    float sa[kAuxMax][64];    // attributes
+    uint32_t rid[64], gid[64];
 };
 
-// Stage records [base, base + cnt) of the list: fields from the projected
-// record, attributes from the record's Gaussian.
-__device__ __forceinline__ void stage(AuxStage &S, const ivrgs_batch &b, const ivrgs_job &job,
-                                      const float4 *__restrict__ rec, const uint32_t *__restrict__ sorted,
-                                      uint32_t base, uint32_t end, const float *__restrict__ attr, int n_attr,
-                                      int tx0, int ty0) {
-    const uint32_t e = base + threadIdx.x;
-    if (e < end) {
-        const uint32_t r = sorted[e];
-        const float4 r0 = rec[3 * (size_t)r], r1 = rec[3 * (size_t)r + 1], r2 = rec[3 * (size_t)r + 2];
-        S.s0[threadIdx.x] = r0;
-        S.s1[threadIdx.x] = make_float4(r1.x, r1.y, r2.y, r2.z);
-        // the binning's conservative ellipse-box test, per wave strip: a wave
-        // skips a record that cannot reach any of its pixels
-        const HitTest h = make_hit_test(r0, r1, r2);
-        uint32_t m = 0;
+// The quadrant walk's per-wave state: pixel, gather pipeline (ids two steps
+// ahead, records and attributes one step ahead).
+struct AuxWalk {
+    const ivrgs_batch &b;
+    const ivrgs_job &job;
+    const float4 *rec;
+    const uint32_t *sorted;
+    const float *attr;
+    int n_attr, lane;
+    uint32_t end;
+    float4 n0, n1, n2;
+    float na[kAuxMax];
+    uint32_t nid, pid;
+
+    __device__ __forceinline__ AuxWalk(const ivrgs_batch &b_, const ivrgs_job &j_, const float4 *r_,
+                                       const uint32_t *s_, const float *a_, int na_, int lane_, uint32_t end_)
+        : b(b_), job(j_), rec(r_), sorted(s_), attr(a_), n_attr(na_), lane(lane_), end(end_), nid(0), pid(0) {
+        n0 = n1 = n2 = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-        for (int w = 0; w < kTilePix / 64; ++w)
-            m |= box_hit(h, tx0, ty0 + w * (64 / kTile), kTile, 64 / kTile) ? 1u << w : 0u;
-        S.wmask[threadIdx.x] = m;
-        const int64_t g = job_gaussian(job, b.gauss_index, (int)((int64_t)r - job.rec_begin));
-        S.gid[threadIdx.x] = g;
-        S.rid[threadIdx.x] = r;
-#pragma unroll
-        for (int c = 0; c < kAuxMax; ++c)
-            if (c < n_attr) S.sa[c][threadIdx.x] = attr[(int64_t)c * b.g.n + g];
+        for (int c = 0; c < kAuxMax; ++c) na[c] = 0.f;
     }
-}
-
-// One pixel's step over a staged record, the forward's decisions exactly.
-struct Step {
-    float dx, dy, G, raw, al, w;
-    bool comp;
+    __device__ __forceinline__ void load_ids(uint32_t base) {
+        if (base + lane < end) pid = sorted[base + lane];
+    }
+    __device__ __forceinline__ void load_recs(uint32_t base) {
+        if (base + lane < end) {
+            nid = pid;
+            n0 = rec[3 * (size_t)nid];
+            n1 = rec[3 * (size_t)nid + 1];
+            n2 = rec[3 * (size_t)nid + 2];
+            const int64_t g = job_gaussian(job, b.gauss_index, (int)((int64_t)nid - job.rec_begin));
+#pragma unroll
+            for (int c = 0; c < kAuxMax; ++c)
+                if (c < n_attr) na[c] = attr[(int64_t)c * b.g.n + g];
+        }
+    }
+    // Takes the gathered records of the step at base, issues the next
+    // gathers and compacts the records that reach the pixel box into the
+    // slots; returns their number.
+    __device__ __forceinline__ int step(uint32_t base, const PixBox &bx, AuxSlots &S) {
+        const float4 r0 = n0, r1 = n1, r2 = n2;
+        const uint32_t rid = nid;
+        float a[kAuxMax];
+#pragma unroll
+        for (int c = 0; c < kAuxMax; ++c) a[c] = na[c];
+        const bool touch = base + lane < end && box_hit(make_hit_test(r0, r1, r2), bx.x0, bx.y0, bx.w, bx.h);
+        if (base + 64 < end) load_recs(base + 64);
+        if (base + 128 < end) load_ids(base + 128);
+        const uint64_t m = __ballot(touch);
+        if (m == 0ull) return 0;
+        wave_lds_sync();  // the previous step's reads are done
+        if (touch) {
+            const int slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            S.f0[slot] = r0;
+            S.f1[slot] = make_float4(r1.x, r1.y, r2.y, r2.z);
+#pragma unroll
+            for (int c = 0; c < kAuxMax; ++c)
+                if (c < n_attr) S.sa[c][slot] = a[c];
+            S.rid[slot] = rid;
+            S.gid[slot] = (uint32_t)job_gaussian(job, b.gauss_index, (int)((int64_t)rid - job.rec_begin));
+        }
+        wave_lds_sync();
+        return __builtin_popcountll(m);
+    }
 };
 
-__device__ __forceinline__ Step step(const Consts &k, float4 a, float4 c, float px, float py, float &T,
-                                     bool &alive) {
-    Step s;
-    s.dx = px - a.x;
-    s.dy = py - a.y;
-    const float p2 = splat_exponent(a.z, a.w, c.x, s.dx, s.dy);
-    const bool pass = alive && p2 >= c.w;  // below the cutoff alpha < alpha_min is certain
-    s.G = fast_exp2(p2);
-    s.raw = c.y * s.G;
-    s.al = fminf(k.alpha_max, s.raw);
-    const float Tn = T * (1.f - s.al);
-    const bool use = pass && s.al >= k.alpha_min;
-    const bool stop = use && Tn < k.T_min;
-    s.comp = use && !stop;
-    s.w = s.comp ? s.al * T : 0.f;
-    T = s.comp ? Tn : T;
-    alive = alive && !stop;
-    return s;
-}
-
-// Forward: each wave owns an 8x8 quadrant of the tile and walks the list on
-// its own (no LDS, no barrier), 64 records per step: lane l holds record
-// base + l in registers (ids loaded two steps ahead, records and attributes
-// one step ahead, so the walk does not wait on the gathers), the
-// ellipse-box test against the quadrant picks the records to visit, and a
-// visited record's fields are broadcast from its lane.
+// Forward: maps = sum over composited records of w * (depth, attributes).
 __global__ __launch_bounds__(kTilePix) void k_aux_fwd(ivrgs_batch b, Consts k, const float4 *__restrict__ rec,
                                                       const uint32_t *__restrict__ starts,
                                                       const uint32_t *__restrict__ sorted, int64_t n_tiles,
                                                       const float *__restrict__ attr, int n_attr,
                                                       float *__restrict__ aux) {
     if (starts[n_tiles] == 0xFFFFFFFFu) return;  // pair capacity exceeded: nothing is rendered
+    __shared__ AuxSlots slots[kTilePix / 64];
     const int64_t tile = blockIdx.x;
     const int ji = (int)(tile / k.tiles_per_job), lt = (int)(tile % k.tiles_per_job);
     const ivrgs_job job = b.jobs[ji];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    AuxSlots &S = slots[wave];
     const int sx = (lt % k.tiles_x) * kTile + 8 * (wave & 1), sy = (lt / k.tiles_x) * kTile + 8 * (wave >> 1);
     const int x = sx + (lane & 7), y = sy + (lane >> 3);
     const bool inside = x < k.width && y < k.height;
@@ -112,51 +119,34 @@ __global__ __launch_bounds__(kTilePix) void k_aux_fwd(ivrgs_batch b, Consts k, c
     for (int c = 0; c < 1 + kAuxMax; ++c) acc[c] = 0.f;
     bool alive = inside;
     const uint32_t start = starts[tile], end = starts[tile + 1];
-
-    float4 n0, n1, n2;
-    float na[kAuxMax];
-    uint32_t pid = 0;
-    auto load_ids = [&](uint32_t base) {
-        if (lane < (int)(end - base)) pid = sorted[base + lane];
-    };
-    auto load_recs = [&](uint32_t base) {
-        if (lane < (int)(end - base)) {
-            n0 = rec[3 * (size_t)pid];
-            n1 = rec[3 * (size_t)pid + 1];
-            n2 = rec[3 * (size_t)pid + 2];
-            const int64_t g = job_gaussian(job, b.gauss_index, (int)((int64_t)pid - job.rec_begin));
-#pragma unroll
-            for (int c = 0; c < kAuxMax; ++c)
-                if (c < n_attr) na[c] = attr[(int64_t)c * b.g.n + g];
-        }
-    };
-    auto bc = [](float v, int src) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src)); };
+    AuxWalk W(b, job, rec, sorted, attr, n_attr, lane, end);
     if (start < end) {
-        load_ids(start);
-        load_recs(start);
-        if (end - start > 64) load_ids(start + 64);
+        W.load_ids(start);
+        W.load_recs(start);
+        if (start + 64 < end) W.load_ids(start + 64);
     }
     for (uint32_t base = start; base < end; base += 64) {
-        if (__ballot(alive) == 0ull) break;  // every pixel of the quadrant is done
-        const float4 r0 = n0, r1 = n1, r2 = n2;
-        float a[kAuxMax];
-#pragma unroll
-        for (int c = 0; c < kAuxMax; ++c) a[c] = na[c];
-        const bool touch = lane < (int)(end - base) && box_hit(make_hit_test(r0, r1, r2), sx, sy, 8, 8);
-        if (end - base > 64) load_recs(base + 64);
-        if (end - base > 128) load_ids(base + 128);
-        uint64_t m = __ballot(touch);
-        while (m) {
-            const int src = __builtin_ctzll(m);  // records in list order
-            m &= m - 1;
-            const float4 fa = make_float4(bc(r0.x, src), bc(r0.y, src), bc(r0.z, src), bc(r0.w, src));
-            const float4 fc = make_float4(bc(r1.x, src), bc(r1.y, src), bc(r2.y, src), bc(r2.z, src));
-            const Step s = step(k, fa, fc, px, py, T, alive);
-            if (__ballot(s.comp) != 0ull) {  // wave-uniform
-                acc[0] = fmaf(s.w, fc.z, acc[0]);
+        const uint64_t live = __ballot(alive);
+        if (live == 0ull) break;  // every pixel of the quadrant is done
+        const int cnt = W.step(base, alive_box(live, sx, sy), S);
+        for (int sl = 0; sl < cnt; ++sl) {
+            const float4 fa = S.f0[sl], fc = S.f1[sl];
+            const float dx = px - fa.x, dy = py - fa.y;
+            const float p2 = splat_exponent(fa.z, fa.w, fc.x, dx, dy);
+            const bool pass = alive & (p2 >= fc.w);  // below the cutoff alpha < alpha_min is certain
+            const float al = fminf(k.alpha_max, fc.y * fast_exp2(p2));
+            const float Tn = T * (1.f - al);
+            const bool use = pass & (al >= k.alpha_min);
+            const bool stop = use & (Tn < k.T_min);
+            const bool comp = use & !stop;
+            const float w = comp ? al * T : 0.f;
+            T = comp ? Tn : T;
+            alive = alive & !stop;
+            if (__ballot(comp) != 0ull) {  // wave-uniform
+                acc[0] = fmaf(w, fc.z, acc[0]);
 #pragma unroll
                 for (int c = 0; c < kAuxMax; ++c)
-                    if (c < n_attr) acc[1 + c] = fmaf(s.w, bc(a[c], src), acc[1 + c]);
+                    if (c < n_attr) acc[1 + c] = fmaf(w, S.sa[c][sl], acc[1 + c]);
             }
             if (__ballot(alive) == 0ull) break;
         }
@@ -175,10 +165,10 @@ __global__ __launch_bounds__(kTilePix) void k_aux_fwd(ivrgs_batch b, Consts k, c
 // prefix P = sum of w ga over the pairs up to this one, dL/dalpha =
 // T ga - (g . A - P) / (1 - alpha) (the maps carry no background); then the
 // same record-gradient moments as the image backward.  The wave reduces all
-// of a record's values in one reduce-scatter and adds them into LDS; the workgroup then adds the record's sums into
-// the record gradients (for the projection backward), the attribute
-// gradients and, for the depth, the mean gradient (depth = row 3 of R
-// applied to the mean, plus t).
+// of a record's values in one reduce-scatter; lanes 2v add value v to the
+// record gradients (for the projection backward), the attribute gradients
+// or, for the depth, the mean gradient (depth = row 3 of R applied to the
+// mean, plus t).
 __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, const float4 *__restrict__ rec,
                                                       const uint32_t *__restrict__ starts,
                                                       const uint32_t *__restrict__ sorted, int64_t n_tiles,
@@ -187,15 +177,15 @@ __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, c
                                                       float *__restrict__ grec, float *__restrict__ gattr,
                                                       float *__restrict__ gmean) {
     if (starts[n_tiles] == 0xFFFFFFFFu) return;
-    __shared__ AuxStage S;
-    __shared__ float acc[kAuxChunk][kAuxAcc];
+    __shared__ AuxSlots slots[kTilePix / 64];
     const int64_t tile = blockIdx.x;
     const int ji = (int)(tile / k.tiles_per_job), lt = (int)(tile % k.tiles_per_job);
     const ivrgs_job job = b.jobs[ji];
-    const int tx0 = (lt % k.tiles_x) * kTile, ty0 = (lt / k.tiles_x) * kTile;
-    const int x = tx0 + (threadIdx.x & (kTile - 1));
-    const int y = ty0 + threadIdx.x / kTile;
-    const uint32_t wave_bit = 1u << (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    AuxSlots &S = slots[wave];
+    const int sx = (lt % k.tiles_x) * kTile + 8 * (wave & 1), sy = (lt / k.tiles_x) * kTile + 8 * (wave >> 1);
+    const int x = sx + (lane & 7), y = sy + (lane >> 3);
     const bool inside = x < k.width && y < k.height;
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
     const int nv = 1 + n_attr;
@@ -211,92 +201,82 @@ __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, c
             gA = fmaf(g[c], on ? aux[o + c * plane] : 0.f, gA);
         }
     }
+    bool any_g = false;
+#pragma unroll
+    for (int c = 0; c < 1 + kAuxMax; ++c) any_g |= g[c] != 0.f;
     const ivrgs_camera &cam = b.cameras[job.camera];
     float T = 1.f, gP = 0.f;
-    bool alive = inside;
-    const uint32_t beg = starts[tile], end = starts[tile + 1];
-    const int lane = threadIdx.x & 63;
-    for (uint32_t base = beg; base < end; base += kAuxChunk) {
-        __syncthreads();
-        if (threadIdx.x == 0) S.any_alive = 0;
-        stage(S, b, job, rec, sorted, base, end, attr, n_attr, tx0, ty0);
-        for (int v = 0; v < kAuxAcc; ++v) acc[threadIdx.x][v] = 0.f;
-        __syncthreads();
-        if (alive) S.any_alive = 1;
-        __syncthreads();
-        if (!S.any_alive) break;
-        const int cnt = (int)min((uint32_t)kAuxChunk, end - base);
-        auto bc = [](float v, int src) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src)); };
-        // 64 staged records at a time into registers (lane l: record
-        // sub * 64 + l), one LDS round trip; the records reaching this wave's
-        // strip are then visited in order with their fields broadcast
-        for (int sub = 0; sub * 64 < cnt; ++sub) {
-            if (__ballot(alive) == 0ull) break;  // this wave's pixels are done (it still meets the barriers)
-            const int li = sub * 64 + lane;
-            const bool have = li < cnt;
-            const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-            const float4 q0 = have ? S.s0[li] : z4, q1 = have ? S.s1[li] : z4;
-            float qa[kAuxMax];
+    bool alive = inside & any_g;
+    const uint32_t start = starts[tile], end = starts[tile + 1];
+    const int vi = lane >> 1;
+    const bool my_slot = (lane & 1) == 0 && vi < 6 + nv;
+    AuxWalk W(b, job, rec, sorted, attr, n_attr, lane, end);
+    if (start < end) {
+        W.load_ids(start);
+        W.load_recs(start);
+        if (start + 64 < end) W.load_ids(start + 64);
+    }
+    for (uint32_t base = start; base < end; base += 64) {
+        const uint64_t live = __ballot(alive);
+        if (live == 0ull) break;
+        const int cnt = W.step(base, alive_box(live, sx, sy), S);
+        for (int sl = 0; sl < cnt; ++sl) {
+            const float4 fa = S.f0[sl], fc = S.f1[sl];
+            const float dx = px - fa.x, dy = py - fa.y;
+            const float p2 = splat_exponent(fa.z, fa.w, fc.x, dx, dy);
+            const bool pass = alive & (p2 >= fc.w);
+            if (__ballot(pass) == 0ull) continue;  // wave-uniform: no live pixel reaches the cutoff
+            const float G = fast_exp2(p2);
+            const float raw = fc.y * G;
+            const float al = fminf(k.alpha_max, raw);
+            const float T0 = T;  // transmittance in front of this record
+            const float Tn = T * (1.f - al);
+            const bool use = pass & (al >= k.alpha_min);
+            const bool stop = use & (Tn < k.T_min);
+            const bool comp = use & !stop;
+            const float w = comp ? al * T : 0.f;
+            T = comp ? Tn : T;
+            alive = alive & !stop;
+            if (__ballot(comp) != 0ull) {  // wave-uniform: something to add
+                float ga = g[0] * fc.z;
 #pragma unroll
-            for (int c = 0; c < kAuxMax; ++c) qa[c] = have && c < n_attr ? S.sa[c][li] : 0.f;
-            uint64_t visit = __ballot(have && (S.wmask[have ? li : 0] & wave_bit));
-            while (visit) {
-                const int src = __builtin_ctzll(visit);  // list order
-                visit &= visit - 1;
-                const int i = sub * 64 + src;  // position in the staged chunk
-                const float4 fa = make_float4(bc(q0.x, src), bc(q0.y, src), bc(q0.z, src), bc(q0.w, src));
-                const float4 fc = make_float4(bc(q1.x, src), bc(q1.y, src), bc(q1.z, src), bc(q1.w, src));
-                const float T0 = T;  // transmittance in front of this record
-                const Step s = step(k, fa, fc, px, py, T, alive);
-                if (__ballot(s.comp) != 0ull) {  // wave-uniform: something to add
-                    float ga = g[0] * fc.z;
+                for (int c = 0; c < kAuxMax; ++c)
+                    if (c < n_attr) ga = fmaf(g[1 + c], S.sa[c][sl], ga);
+                gP = fmaf(w, ga, gP);
+                const float dA = fmaf(-(gA - gP), __builtin_amdgcn_rcpf(1.f - al), T0 * ga);
+                // no gradient through alpha where the cap is active
+                const float dLdo = (comp & (raw <= k.alpha_max)) ? dA : 0.f;
+                const float dp = dLdo * raw;
+                float v32[32];
+                v32[0] = dLdo * G;  // GO
+                const float dpx = dp * dx, dpy = dp * dy;
+                v32[1] = dpx;       // GX
+                v32[2] = dpy;       // GY
+                v32[3] = dpx * dx;  // GQA
+                v32[4] = dpx * dy;  // GQB
+                v32[5] = dpy * dy;  // GQC
 #pragma unroll
-                    for (int c = 0; c < kAuxMax; ++c)
-                        if (c < n_attr) ga = fmaf(g[1 + c], bc(qa[c], src), ga);
-                    gP = fmaf(s.w, ga, gP);
-                    const float dA = s.comp ? T0 * ga - (gA - gP) / (1.f - s.al) : 0.f;
-                    const float dLdo = s.raw <= k.alpha_max ? dA : 0.f;  // no gradient through alpha where capped
-                    const float dp = dLdo * s.raw;
-                    float vals[kAuxAcc];
-                    vals[0] = dLdo * s.G;        // GO
-                    vals[1] = dp * s.dx;         // GX
-                    vals[2] = dp * s.dy;         // GY
-                    vals[3] = dp * s.dx * s.dx;  // GQA
-                    vals[4] = dp * s.dx * s.dy;  // GQB
-                    vals[5] = dp * s.dy * s.dy;  // GQC
+                for (int c = 0; c < 1 + kAuxMax; ++c) v32[6 + c] = c < nv ? w * g[c] : 0.f;  // depth, attributes
 #pragma unroll
-                    for (int c = 0; c < 1 + kAuxMax; ++c) vals[6 + c] = s.w * g[c];  // depth, then attributes
-                    // one reduce-scatter for all the values: lanes 2v, 2v + 1
-                    // hold the wave total of value v
-                    float v32[32];
-#pragma unroll
-                    for (int v = 0; v < 32; ++v) v32[v] = v < kAuxAcc ? vals[v] : 0.f;
-                    const float tot = reduce_scatter32(v32);
-                    const int vi = lane >> 1;
-                    if ((lane & 1) == 0 && vi < 6 + nv && tot != 0.f) atomicAdd(&acc[i][vi], tot);
+                for (int v = 7 + kAuxMax; v < 32; ++v) v32[v] = 0.f;
+                // lanes 2v, 2v + 1 hold the wave total of value v
+                const float tot = reduce_scatter32(v32);
+                if (my_slot && tot != 0.f) {
+                    const uint32_t r = S.rid[sl];
+                    const int64_t gi = S.gid[sl];
+                    if (vi < 6) {
+                        const int row = vi == 0 ? GO : (vi == 1 ? GX : (vi == 2 ? GY : GQA + (vi - 3)));
+                        atomicAdd(&grec[(size_t)r * kGradStride + row], tot);
+                    } else if (vi == 6) {
+                        atomicAdd(&gmean[gi], tot * cam.R[6]);
+                        atomicAdd(&gmean[b.g.n + gi], tot * cam.R[7]);
+                        atomicAdd(&gmean[2 * b.g.n + gi], tot * cam.R[8]);
+                    } else {
+                        atomicAdd(&gattr[(int64_t)(vi - 7) * b.g.n + gi], tot);
+                    }
                 }
-                if (__ballot(alive) == 0ull) break;
             }
-        }
-        __syncthreads();
-        if ((int)threadIdx.x < cnt) {
-            const float *a = acc[threadIdx.x];
-            const uint32_t r = S.rid[threadIdx.x];
-            const int64_t gi = S.gid[threadIdx.x];
-            float *gr = grec + (size_t)r * kGradStride;
-            if (a[0] != 0.f) atomicAdd(&gr[GO], a[0]);
-            if (a[1] != 0.f) atomicAdd(&gr[GX], a[1]);
-            if (a[2] != 0.f) atomicAdd(&gr[GY], a[2]);
-            if (a[3] != 0.f) atomicAdd(&gr[GQA], a[3]);
-            if (a[4] != 0.f) atomicAdd(&gr[GQB], a[4]);
-            if (a[5] != 0.f) atomicAdd(&gr[GQC], a[5]);
-            if (a[6] != 0.f) {
-                atomicAdd(&gmean[gi], a[6] * cam.R[6]);
-                atomicAdd(&gmean[b.g.n + gi], a[6] * cam.R[7]);
-                atomicAdd(&gmean[2 * b.g.n + gi], a[6] * cam.R[8]);
-            }
-            for (int c = 0; c < n_attr; ++c)
-                if (a[7 + c] != 0.f) atomicAdd(&gattr[(int64_t)c * b.g.n + gi], a[7 + c]);  // LDS row: indexable
+            if (__ballot(alive) == 0ull) break;
         }
     }
 }

@@ -351,13 +351,6 @@ struct ExpandLds {
 };
 constexpr int kBinWaves = 4;  // waves per binning workgroup (sharing one chunk)
 
-// Orders a wave's LDS writes before its other lanes' reads.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Groups of 64 records start at begin, begin + stride, ... (stride 64: the
 // whole range in order; stride 64 * waves: the waves of a workgroup share it).
 // In depth order (order != nullptr) the records' binning fields are

@@ -128,6 +128,34 @@ __device__ __forceinline__ bool box_hit(const HitTest &h, int px0, int py0, int 
     return fmaf(1.0e-6f, mag, best) >= h.tol;
 }
 
+// Bounding box, within the wave's 8x8 quadrant at (sx, sy), of the pixels
+// whose lanes are set in `alive` (lane l owns pixel (l % 8, l / 8)); `alive`
+// must be nonzero.  Scalar bit operations only.  A record that cannot reach
+// this box cannot reach a pixel still compositing, and a pixel that has
+// terminated ignores every later record, so testing the records of each step
+// of the walk against this box instead of the whole quadrant changes no
+// result while the walks of the last pixels of a quadrant shrink.
+struct PixBox {
+    int x0, y0, w, h;
+};
+__device__ __forceinline__ PixBox alive_box(uint64_t alive, int sx, int sy) {
+    uint64_t c = alive | (alive >> 32);
+    c |= c >> 16;
+    c |= c >> 8;
+    const uint32_t cols = (uint32_t)c & 0xFFu;
+    const int xa = __builtin_ctz(cols), xb = 31 - __builtin_clz(cols);
+    const int ya = __builtin_ctzll(alive) >> 3, yb = (63 - __builtin_clzll(alive)) >> 3;
+    return {sx + xa, sy + ya, xb - xa + 1, yb - ya + 1};
+}
+
+// Orders this wave's LDS stores before its later loads (and the loads before
+// later stores): the lanes of one wave exchange records through LDS.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
 // Sum over the 64 lanes of a wave; the total lands in lane 63.  DPP row

@@ -74,26 +74,6 @@ __device__ __forceinline__ void walk_priority(uint32_t list_len) {
     else __builtin_amdgcn_s_setprio(0);  // a persistent wave's next tile may be shorter
 }
 
-// Bounding box, within the wave's 8x8 quadrant at (sx, sy), of the pixels
-// whose lanes are set in `alive` (lane l owns pixel (l % 8, l / 8)); `alive`
-// must be nonzero.  Scalar bit operations only.  A record that cannot reach
-// this box cannot reach a pixel still compositing, and a pixel that has
-// terminated ignores every later record, so testing the records of each step
-// of the walk against this box instead of the whole quadrant changes no
-// result while the walks of the last pixels of a quadrant shrink.
-struct PixBox {
-    int x0, y0, w, h;
-};
-__device__ __forceinline__ PixBox alive_box(uint64_t alive, int sx, int sy) {
-    uint64_t c = alive | (alive >> 32);
-    c |= c >> 16;
-    c |= c >> 8;
-    const uint32_t cols = (uint32_t)c & 0xFFu;
-    const int xa = __builtin_ctz(cols), xb = 31 - __builtin_clz(cols);
-    const int ya = __builtin_ctzll(alive) >> 3, yb = (63 - __builtin_clzll(alive)) >> 3;
-    return {sx + xa, sy + ya, xb - xa + 1, yb - ya + 1};
-}
-
 __device__ __forceinline__ float wave_max_to_lane63(float v) {
     v = fmaxf(v, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false)));
     v = fmaxf(v, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, false)));
@@ -228,14 +208,6 @@ __device__ __forceinline__ void fwd_tile(const Consts &k, const float4 *__restri
 struct WaveSlots {
     float4 f[64][3];
 };
-
-// Orders this wave's LDS stores before its later loads (and the loads before
-// later stores): the lanes of one wave exchange records through LDS.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Compacts the records of lanes with `touch` (ballot m) into the wave's
 // slots, in lane order; returns their number.
@@ -875,7 +847,7 @@ __device__ __forceinline__ void bwd_tile_quad(const Consts &k, const float4 *__r
                 const float gb = go - gP;
                 const float dLda = fmaf(-(gb - gATf), inv[g], T * gc[g]);
                 // no gradient through alpha where the cap is active
-                const float dLdo = comp & (raw[g] <= k.alpha_max) ? dLda : 0.f;
+                const float dLdo = (comp & (raw[g] <= k.alpha_max)) ? dLda : 0.f;
                 const float dp = dLdo * raw[g];
                 float *ag = acc + g * kGradRec;
                 ag[GCR] = w * g0;
