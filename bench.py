@@ -580,6 +580,7 @@ def secondary_editable(dev, steps=20, warmup=3):
     def step(v):
         rgba = R.rasterize(planes, cams_t[v % 100:v % 100 + 1], jobs, rnd, edits_t=edits)[0]
         maps = AX.render_aux(planes, AX.editable_attributes(planes), cams_t[v % 100:v % 100 + 1], jobs, rnd,
+                             n_attr=AX.EDITABLE_ATTRS,
                              edits_t=edits)[0]
         loss = LS.editable_loss(rgba, targets[v % 4], maps, planes["opacity"], cams[v % 100])
         for t in planes.values():

@@ -521,20 +521,23 @@ ivrgs_status ivrgs_vq_compose(const ivrgs_vq_model *models, int32_t n_models, co
  * of Eq. 5 (normal consistency) and the offset-colour and shading-term maps
  * of Sec. 4.3 (sparsity and bilateral smoothness).  Channel 0 is the
  * camera-space depth of each record (its depth key, row 3 of R applied to
- * the mean plus t); channels 1 .. n_attr composite caller attribute planes
- * attr[c][g] (0 <= n_attr <= 15; for example the unit normal, delta-c, k_a,
- * k_d, k_s, beta).  No background term.  Both calls follow ivrgs_bin_sort
- * of the same batch and params (the composited pairs are exactly the
- * image's). */
+ * the mean plus t); channels 1 .. n_attr composite caller attributes
+ * (0 <= n_attr <= 15; for example the unit normal, delta-c, k_a, k_d, k_s,
+ * beta).  The attributes are per-Gaussian rows: attr[g * S + c] with the row
+ * stride S = n_attr rounded up to a multiple of 4 (the pad entries are not
+ * read), 16-byte aligned, so that a record's attributes load as whole
+ * vectors.  No background term.  Both calls follow ivrgs_bin_sort of the
+ * same batch and params (the composited pairs are exactly the image's). */
 
-/* attr: device [n_attr][batch->g.n]; out_aux: device
- * [n_jobs][1 + n_attr][H][W], written. */
+/* attr: device [batch->g.n][S]; out_aux: device [n_jobs][1 + n_attr][H][W],
+ * written.  IVRGS_E_INVALID if attr is not 16-byte aligned. */
 ivrgs_status ivrgs_render_aux_fwd(const ivrgs_batch *batch, const ivrgs_params *params,
                                   const ivrgs_projected *proj, const ivrgs_bins *bins, const float *attr,
                                   int32_t n_attr, float *out_aux, void *stream);
 
 /* Backward for dL/d(maps) grad_aux (same layout as the maps; aux: the
- * forward's maps).  ADDS into grad_attr (device [n_attr][g.n]) the attribute
+ * forward's maps).  ADDS into grad_attr (device [g.n][S], the rows of attr;
+ * the pad entries are left alone) the attribute
  * gradients and into grads the geometry gradients: through alpha (mean,
  * log_scale, quat, opacity, by the projection backward, accumulated) and
  * through the depth (mean).  The caller clears both first.  workspace: the

@@ -15,12 +15,12 @@ class _AuxFn(torch.autograd.Function):
     gradients and geometry gradients (through alpha and the depth)."""
 
     @staticmethod
-    def forward(ctx, renderer, cams_t, jobs, model_id, edits_t, gauss_index, attr, *planes):
+    def forward(ctx, renderer, cams_t, jobs, model_id, edits_t, gauss_index, n_attr, attr, *planes):
         pl = dict(zip(PLANES, planes))
         batch = renderer.make_batch(pl, model_id, edits_t, cams_t, jobs, gauss_index)
         proj, bins = renderer.bins_for(batch)  # the image's bins when it was rendered from the same inputs
         s = renderer.settings
-        A = int(attr.shape[0])
+        A = ctx.n_attr = int(n_attr)
         aux = torch.empty((jobs.n_jobs, 1 + A, s.height, s.width), dtype=torch.float32, device=renderer.device)
         N.ivrgs_render_aux_fwd(batch, s.params(), proj, bins, attr.data_ptr() if A else None, A, aux.data_ptr(),
                                _stream())
@@ -45,32 +45,42 @@ class _AuxFn(torch.autograd.Function):
         n = int(planes["mean"].shape[1])
         grads = {k: torch.zeros((d, n), dtype=torch.float32, device=r.device) for k, d in PLANE_DIMS.items()}
         gattr = torch.zeros_like(attr)
-        A = int(attr.shape[0])
+        A = ctx.n_attr
         g = N.ivrgs_gaussians(n, *[grads[k].data_ptr() for k in PLANES], None)
         N.ivrgs_render_aux_bwd(batch, r.settings.params(), proj, bins, attr.data_ptr() if A else None, A,
                                aux.data_ptr(), grad_aux.contiguous().data_ptr(), gattr.data_ptr() if A else None, g,
                                r.ws.data_ptr(), r.ws.numel(), _stream())
-        return (None, None, None, None, None, None, gattr, *[grads[k] for k in PLANES])
+        return (None, None, None, None, None, None, None, gattr, *[grads[k] for k in PLANES])
 
 
 def render_aux(planes: dict, attr: torch.Tensor, cams_t, jobs: Jobs, renderer: Renderer, model_id=None,
-               edits_t=None, gauss_index=None) -> torch.Tensor:
-    """Differentiable maps [n_jobs, 1 + A, H, W]: channel 0 the camera-space
-    depth, then the A attribute planes attr [A, n] (float32, contiguous),
-    each composited with the image's weights T_i alpha_i."""
+               edits_t=None, gauss_index=None, n_attr: int | None = None) -> torch.Tensor:
+    """Differentiable maps [n_jobs, 1 + n_attr, H, W]: channel 0 the
+    camera-space depth, then the first n_attr columns of the attribute rows
+    attr [n, S] (float32, contiguous, S a multiple of 4, 16-byte aligned;
+    n_attr defaults to S), each composited with the image's weights
+    T_i alpha_i."""
     if attr.dtype != torch.float32 or attr.dim() != 2 or not attr.is_contiguous() or not attr.is_cuda:
-        raise ValueError("attr: expected contiguous float32 [A, n] on the device")
-    if attr.shape[0] > 15:
-        raise ValueError("at most 15 attribute planes")
+        raise ValueError("attr: expected contiguous float32 rows [n, S] on the device")
+    S = int(attr.shape[1])
+    A = S if n_attr is None else int(n_attr)
+    if S % 4 or not 0 <= A <= 15 or S != (A + 3) // 4 * 4 or attr.data_ptr() % 16:
+        raise ValueError("attr: rows of n_attr <= 15 values padded to a multiple of 4, 16-byte aligned")
     if edits_t is None:
         edits_t = default_edits(renderer.device)
-    return _AuxFn.apply(renderer, cams_t, jobs, model_id, edits_t, gauss_index, attr, *[planes[k] for k in PLANES])
+    return _AuxFn.apply(renderer, cams_t, jobs, model_id, edits_t, gauss_index, A, attr,
+                        *[planes[k] for k in PLANES])
+
+
+EDITABLE_ATTRS = 10  # unit normal 3, delta-c 3, k_a, k_d, k_s, beta
 
 
 def editable_attributes(planes: dict) -> torch.Tensor:
-    """The attributes of the editable-Gaussian training losses, [10, n]: the
-    unit normal (3), delta-c (3, the colour plane of a basic model), k_a,
-    k_d, k_s, beta — differentiable in the planes."""
+    """The attribute rows of the editable-Gaussian training losses, [n, 12]
+    (EDITABLE_ATTRS values and two pad columns): the unit normal (3),
+    delta-c (3, the colour plane of a basic model), k_a, k_d, k_s, beta —
+    differentiable in the planes."""
     nrm = planes["normal"]
     nrm = nrm / nrm.norm(dim=0, keepdim=True).clamp_min(1e-12)
-    return torch.cat([nrm, planes["color"], planes["shade"]]).contiguous()
+    pad = torch.zeros((2, nrm.shape[1]), dtype=nrm.dtype, device=nrm.device)
+    return torch.cat([nrm, planes["color"], planes["shade"], pad]).t().contiguous()

@@ -353,7 +353,7 @@ ivrgs_status ivrgs_render_aux_fwd(const ivrgs_batch *batch, const ivrgs_params *
     if (st != IVRGS_OK) return st;
     if ((st = check_params(params)) != IVRGS_OK) return st;
     if (!proj || !bins || !bins->tile_start || !out_aux || n_attr < 0 || n_attr > kAuxMax) return IVRGS_E_INVALID;
-    if (n_attr > 0 && !attr) return IVRGS_E_INVALID;
+    if (n_attr > 0 && (!attr || (reinterpret_cast<uintptr_t>(attr) & 15u))) return IVRGS_E_INVALID;
     const Consts k = make_consts(*params);
     const int64_t n_tiles = (int64_t)batch->n_jobs * k.tiles_per_job;
     return hip_status(launch_aux_fwd(*batch, k, n_tiles, proj->rec, bins->tile_start, bins->sorted, attr, n_attr,
@@ -370,7 +370,7 @@ ivrgs_status ivrgs_render_aux_bwd(const ivrgs_batch *batch, const ivrgs_params *
     if ((st = check_params(params)) != IVRGS_OK) return st;
     if (!proj || !bins || !bins->tile_start || !aux || !grad_aux || !grads || n_attr < 0 || n_attr > kAuxMax)
         return IVRGS_E_INVALID;
-    if (n_attr > 0 && (!attr || !grad_attr)) return IVRGS_E_INVALID;
+    if (n_attr > 0 && (!attr || !grad_attr || (reinterpret_cast<uintptr_t>(attr) & 15u))) return IVRGS_E_INVALID;
     if (!valid_gauss_mut(*grads) || grads->n != batch->g.n) return IVRGS_E_SHAPE;
     const Consts k = make_consts(*params);
     const Layout L = layout(*batch, *params);

@@ -23,10 +23,15 @@ constexpr int kAuxAcc = 7 + kAuxMax;  // per-record sums of the backward: GO, GX
 static_assert(kAuxAcc <= 32, "one reduce-scatter of 32 values per record");
 
 // Per-wave LDS: the compacted records of one step.
+constexpr int kAuxQuads = (kAuxMax + 3) / 4;  // float4s per attribute row
+
+// Row stride of the attributes: n_attr rounded up to a multiple of 4.
+__host__ __device__ __forceinline__ int attr_stride(int n_attr) { return (n_attr + 3) & ~3; }
+
 struct AuxSlots {
-    float4 f0[64];            // mean x, mean y, qa, qb
-    float4 f1[64];            // qc, opacity, depth, cutoff
-    float sa[kAuxMax][64];    // attributes
+    float4 f0[64];             // mean x, mean y, qa, qb
+    float4 f1[64];             // qc, opacity, depth, cutoff
+    float4 sa[kAuxQuads][64];  // attribute row, four at a time
     uint32_t rid[64], gid[64];
 };
 
@@ -41,7 +46,7 @@ struct AuxWalk {
     int n_attr, lane;
     uint32_t end;
     float4 n0, n1, n2;
-    float na[kAuxMax];
+    float4 na[kAuxQuads];
     uint32_t nid, pid;
 
     __device__ __forceinline__ AuxWalk(const ivrgs_batch &b_, const ivrgs_job &j_, const float4 *r_,
@@ -49,7 +54,7 @@ struct AuxWalk {
         : b(b_), job(j_), rec(r_), sorted(s_), attr(a_), n_attr(na_), lane(lane_), end(end_), nid(0), pid(0) {
         n0 = n1 = n2 = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-        for (int c = 0; c < kAuxMax; ++c) na[c] = 0.f;
+        for (int q = 0; q < kAuxQuads; ++q) na[q] = n0;
     }
     __device__ __forceinline__ void load_ids(uint32_t base) {
         if (base + lane < end) pid = sorted[base + lane];
@@ -61,9 +66,11 @@ struct AuxWalk {
             n1 = rec[3 * (size_t)nid + 1];
             n2 = rec[3 * (size_t)nid + 2];
             const int64_t g = job_gaussian(job, b.gauss_index, (int)((int64_t)nid - job.rec_begin));
+            // the record's attribute row, whole vectors
+            const float4 *row = reinterpret_cast<const float4 *>(attr + g * attr_stride(n_attr));
 #pragma unroll
-            for (int c = 0; c < kAuxMax; ++c)
-                if (c < n_attr) na[c] = attr[(int64_t)c * b.g.n + g];
+            for (int q = 0; q < kAuxQuads; ++q)
+                if (4 * q < n_attr) na[q] = row[q];
         }
     }
     // Takes the gathered records of the step at base, issues the next
@@ -72,9 +79,9 @@ struct AuxWalk {
     __device__ __forceinline__ int step(uint32_t base, const PixBox &bx, AuxSlots &S) {
         const float4 r0 = n0, r1 = n1, r2 = n2;
         const uint32_t rid = nid;
-        float a[kAuxMax];
+        float4 a[kAuxQuads];
 #pragma unroll
-        for (int c = 0; c < kAuxMax; ++c) a[c] = na[c];
+        for (int q = 0; q < kAuxQuads; ++q) a[q] = na[q];
         const bool touch = base + lane < end && box_hit(make_hit_test(r0, r1, r2), bx.x0, bx.y0, bx.w, bx.h);
         if (base + 64 < end) load_recs(base + 64);
         if (base + 128 < end) load_ids(base + 128);
@@ -86,8 +93,8 @@ struct AuxWalk {
             S.f0[slot] = r0;
             S.f1[slot] = make_float4(r1.x, r1.y, r2.y, r2.z);
 #pragma unroll
-            for (int c = 0; c < kAuxMax; ++c)
-                if (c < n_attr) S.sa[c][slot] = a[c];
+            for (int q = 0; q < kAuxQuads; ++q)
+                if (4 * q < n_attr) S.sa[q][slot] = a[q];
             S.rid[slot] = rid;
             S.gid[slot] = (uint32_t)job_gaussian(job, b.gauss_index, (int)((int64_t)rid - job.rec_begin));
         }
@@ -129,24 +136,49 @@ __global__ __launch_bounds__(kTilePix) void k_aux_fwd(ivrgs_batch b, Consts k, c
         const uint64_t live = __ballot(alive);
         if (live == 0ull) break;  // every pixel of the quadrant is done
         const int cnt = W.step(base, alive_box(live, sx, sy), S);
-        for (int sl = 0; sl < cnt; ++sl) {
-            const float4 fa = S.f0[sl], fc = S.f1[sl];
-            const float dx = px - fa.x, dy = py - fa.y;
-            const float p2 = splat_exponent(fa.z, fa.w, fc.x, dx, dy);
-            const bool pass = alive & (p2 >= fc.w);  // below the cutoff alpha < alpha_min is certain
-            const float al = fminf(k.alpha_max, fc.y * fast_exp2(p2));
-            const float Tn = T * (1.f - al);
-            const bool use = pass & (al >= k.alpha_min);
-            const bool stop = use & (Tn < k.T_min);
-            const bool comp = use & !stop;
-            const float w = comp ? al * T : 0.f;
-            T = comp ? Tn : T;
-            alive = alive & !stop;
-            if (__ballot(comp) != 0ull) {  // wave-uniform
-                acc[0] = fmaf(w, fc.z, acc[0]);
+        // records in groups of four: the order-free part (exponent, power,
+        // alpha) of the four first, then the chain, then the sums of the
+        // group's weighted depth and attributes when a pixel composites
+        constexpr int kG = 4;
+        for (int sl = 0; sl < cnt; sl += kG) {
+            float al[kG], w[kG];
+            bool pass[kG];
+            int src[kG];
 #pragma unroll
-                for (int c = 0; c < kAuxMax; ++c)
-                    if (c < n_attr) acc[1 + c] = fmaf(w, S.sa[c][sl], acc[1 + c]);
+            for (int g = 0; g < kG; ++g) {
+                const bool valid = sl + g < cnt;  // wave-uniform
+                src[g] = valid ? sl + g : sl;
+                const float4 fa = S.f0[src[g]], fc = S.f1[src[g]];
+                const float p2 = splat_exponent(fa.z, fa.w, fc.x, px - fa.x, py - fa.y);
+                pass[g] = valid & (p2 >= fc.w);  // below the cutoff alpha < alpha_min is certain
+                al[g] = fminf(k.alpha_max, fc.y * fast_exp2(p2));
+            }
+            bool any = false;
+#pragma unroll
+            for (int g = 0; g < kG; ++g) {
+                const float Tn = T * (1.f - al[g]);
+                const bool use = alive & pass[g] & (al[g] >= k.alpha_min);
+                const bool stop = use & (Tn < k.T_min);
+                const bool comp = use & !stop;
+                w[g] = comp ? al[g] * T : 0.f;
+                T = comp ? Tn : T;
+                alive = alive & !stop;
+                any |= comp;
+            }
+            if (__ballot(any) != 0ull) {  // wave-uniform
+#pragma unroll
+                for (int g = 0; g < kG; ++g) {
+                    acc[0] = fmaf(w[g], S.f1[src[g]].z, acc[0]);
+#pragma unroll
+                    for (int q = 0; q < kAuxQuads; ++q) {
+                        if (4 * q >= n_attr) break;
+                        const float4 a4 = S.sa[q][src[g]];
+                        acc[1 + 4 * q] = fmaf(w[g], a4.x, acc[1 + 4 * q]);
+                        if (4 * q + 1 < kAuxMax) acc[2 + 4 * q] = fmaf(w[g], a4.y, acc[2 + 4 * q]);
+                        if (4 * q + 2 < kAuxMax) acc[3 + 4 * q] = fmaf(w[g], a4.z, acc[3 + 4 * q]);
+                        if (4 * q + 3 < kAuxMax) acc[4 + 4 * q] = fmaf(w[g], a4.w, acc[4 + 4 * q]);
+                    }
+                }
             }
             if (__ballot(alive) == 0ull) break;
         }
@@ -240,8 +272,14 @@ __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, c
             if (__ballot(comp) != 0ull) {  // wave-uniform: something to add
                 float ga = g[0] * fc.z;
 #pragma unroll
-                for (int c = 0; c < kAuxMax; ++c)
-                    if (c < n_attr) ga = fmaf(g[1 + c], S.sa[c][sl], ga);
+                for (int q = 0; q < kAuxQuads; ++q) {
+                    if (4 * q >= n_attr) break;
+                    const float4 a4 = S.sa[q][sl];
+                    ga = fmaf(g[1 + 4 * q], a4.x, ga);
+                    if (4 * q + 1 < kAuxMax) ga = fmaf(g[2 + 4 * q], a4.y, ga);
+                    if (4 * q + 2 < kAuxMax) ga = fmaf(g[3 + 4 * q], a4.z, ga);
+                    if (4 * q + 3 < kAuxMax) ga = fmaf(g[4 + 4 * q], a4.w, ga);
+                }
                 gP = fmaf(w, ga, gP);
                 const float dA = fmaf(-(gA - gP), __builtin_amdgcn_rcpf(1.f - al), T0 * ga);
                 // no gradient through alpha where the cap is active
@@ -272,7 +310,7 @@ __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, c
                         atomicAdd(&gmean[b.g.n + gi], tot * cam.R[7]);
                         atomicAdd(&gmean[2 * b.g.n + gi], tot * cam.R[8]);
                     } else {
-                        atomicAdd(&gattr[(int64_t)(vi - 7) * b.g.n + gi], tot);
+                        atomicAdd(&gattr[gi * attr_stride(n_attr) + (vi - 7)], tot);
                     }
                 }
             }

@@ -49,6 +49,15 @@ def attributes(planes):
                            planes["shade"]]).astype(np.float32)
 
 
+def device_rows(attr, dev):
+    """Attribute planes [A, n] as the device rows the kernels take: [n, S]
+    with S = A rounded up to a multiple of 4 (pad columns zero)."""
+    A, n = attr.shape
+    rows = np.zeros((n, (A + 3) // 4 * 4), np.float32)
+    rows[:, :A] = attr.T
+    return torch.from_numpy(rows).to(dev).requires_grad_(True)
+
+
 def small(n, seed, width=40, height=32):
     m = I.small_scene(n, seed, log_scale_mu=-2.6)
     planes = I.plain_planes(m)
@@ -70,9 +79,9 @@ def test_aux_forward_and_backward_match_dense_oracle(dev, n, seed):
     (ref * torch.from_numpy(G)).sum().backward()
 
     pd = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev).requires_grad_(True) for k, v in planes.items()}
-    ad = torch.from_numpy(attr).to(dev).requires_grad_(True)
+    ad = device_rows(attr, dev)
     rnd = R.Renderer(R.Settings(prm.width, prm.height))
-    out = AX.render_aux(pd, ad, R.camera_table([cam]), R.Jobs.single(n), rnd)[0]
+    out = AX.render_aux(pd, ad, R.camera_table([cam]), R.Jobs.single(n), rnd, n_attr=len(attr))[0]
     got = out.detach().cpu().numpy()
     refn = ref.detach().numpy()
     scale = np.concatenate([[np.abs(refn[0]).max()], np.abs(attr).max(axis=1)])  # depth, then attributes
@@ -80,7 +89,7 @@ def test_aux_forward_and_backward_match_dense_oracle(dev, n, seed):
     say(f"  map errors {np.array2string(err, precision=2)}")
     assert np.all(err <= 1e-4 * np.maximum(scale, 1.0))
     (out * torch.from_numpy(G.astype(np.float32)).to(dev)).sum().backward()
-    check_grad(ad.grad.cpu().numpy(), at.grad.numpy(), "d/dattr")
+    check_grad(ad.grad.cpu().numpy()[:, :len(attr)].T, at.grad.numpy(), "d/dattr")
     for k in ("mean", "log_scale", "quat", "opacity"):
         check_grad(pd[k].grad.cpu().numpy(), pt[k].grad.numpy(), f"d/d{k}")
 
@@ -99,7 +108,7 @@ def test_colour_attribute_gives_the_image_at_full_size(dev):
     say("aux colour maps vs the image, 300k Gaussians, 800x800")
     img = rnd.forward(pd, cams, R.Jobs.single(n), edits_t=R.default_edits(dev))[0]
     ones = torch.ones((1, n), device=dev)
-    attr = torch.cat([pd["color"], ones]).contiguous()
+    attr = torch.cat([pd["color"], ones]).t().contiguous()
     aux = AX.render_aux(pd, attr, cams, R.Jobs.single(n), rnd)[0]
     d = (aux[1:4] - img[:3]).abs().max().item()
     da = (aux[4] - img[3]).abs().max().item()
@@ -112,7 +121,10 @@ def test_invalid_attribute_count(dev):
     planes, cam, prm = small(20, 43)
     pd = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in planes.items()}
     with pytest.raises(ValueError):
-        AX.render_aux(pd, torch.zeros((16, 20), device=dev), R.camera_table([cam]), R.Jobs.single(20),
+        AX.render_aux(pd, torch.zeros((20, 16), device=dev), R.camera_table([cam]), R.Jobs.single(20),
+                      R.Renderer(R.Settings(prm.width, prm.height)))
+    with pytest.raises(ValueError):  # rows not padded to a multiple of 4
+        AX.render_aux(pd, torch.zeros((20, 10), device=dev), R.camera_table([cam]), R.Jobs.single(20),
                       R.Renderer(R.Settings(prm.width, prm.height)))
 
 
@@ -142,9 +154,10 @@ def test_aux_two_jobs_with_overlapping_ranges(dev):
     total.backward()
     say("aux maps, two jobs over overlapping ranges")
     pd = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev).requires_grad_(True) for k, v in planes.items()}
-    ad = torch.from_numpy(attr).to(dev).requires_grad_(True)
+    ad = device_rows(attr, dev)
     jobs = R.Jobs.ranges([0, 1], [r[1] for r in ranges], [r[2] for r in ranges])
-    out = AX.render_aux(pd, ad, R.camera_table([cam0, cam1]), jobs, R.Renderer(R.Settings(prm.width, prm.height)))
+    out = AX.render_aux(pd, ad, R.camera_table([cam0, cam1]), jobs, R.Renderer(R.Settings(prm.width, prm.height)),
+                        n_attr=len(attr))
     for j in range(2):
         got = out[j].detach().cpu().numpy()
         scale = np.maximum(np.concatenate([[np.abs(refs[j][0]).max()], np.abs(attr).max(axis=1)]), 1.0)
@@ -152,7 +165,7 @@ def test_aux_two_jobs_with_overlapping_ranges(dev):
         assert np.all(err <= 1e-4 * scale), (j, err)
     G = torch.from_numpy(np.stack(Gs).astype(np.float32)).to(dev)
     (out * G).sum().backward()
-    check_grad(ad.grad.cpu().numpy(), at.grad.numpy(), "d/dattr, two jobs")
+    check_grad(ad.grad.cpu().numpy()[:, :len(attr)].T, at.grad.numpy(), "d/dattr, two jobs")
     for k in ("mean", "log_scale", "quat", "opacity"):
         check_grad(pd[k].grad.cpu().numpy(), pt[k].grad.numpy(), f"d/d{k}, two jobs")
 
@@ -172,19 +185,19 @@ def test_maps_reuse_the_image_bins(dev):
 
     def run(shared):
         pd = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev).requires_grad_(True) for k, v in planes.items()}
-        ad = torch.from_numpy(attr).to(dev).requires_grad_(True)
+        ad = device_rows(attr, dev)
         r1 = R.Renderer(R.Settings(prm.width, prm.height))
         r2 = r1 if shared else R.Renderer(R.Settings(prm.width, prm.height))
         rgba = R.rasterize(pd, cams, jobs, r1, edits_t=edits)
         gen = r1.generation
-        maps = AX.render_aux(pd, ad, cams, jobs, r2, edits_t=edits)
+        maps = AX.render_aux(pd, ad, cams, jobs, r2, edits_t=edits, n_attr=len(attr))
         if shared:
             assert r1.generation == gen, "the maps binned again"
         (rgba.abs().sum() + (maps * G).sum()).backward()
         if shared:
             with torch.no_grad():
                 pd["opacity"].mul_(0.5)
-            AX.render_aux(pd, ad, cams, jobs, r1, edits_t=edits)
+            AX.render_aux(pd, ad, cams, jobs, r1, edits_t=edits, n_attr=len(attr))
             assert r1.generation == gen + 1, "a changed plane must be binned again"
         return rgba.detach(), maps.detach(), {k: v.grad.cpu().numpy() for k, v in pd.items()}, ad.grad.cpu().numpy()
 
