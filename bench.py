@@ -192,6 +192,28 @@ def main():
     rnd.check = "defer"
     for k in R.PLANES:
         composed[k].requires_grad_(True)
+    tuned = {"fwd_px": args.fwd_px, "bwd_px": args.bwd_px}
+    if not (args.fwd_px or args.bwd_px):
+        # launch shape (results do not depend on it): pixels per lane, records
+        # per binning chunk, persistent render kernels; each candidate timed
+        # on a few fwd+bwd steps of this workload
+        from paper_2504_17954_amd import autotune as A
+        base = rnd.settings
+
+        def make(cfg):
+            def run():
+                rnd.settings = A.apply(base, cfg)
+                for v in range(3):
+                    rgba = R.rasterize(composed, cams_t, jobs[v], rnd, model_id=mid, edits_t=edits_t)
+                    (rgba - targets[v]).abs().mean().backward()
+                for kk in R.PLANES:
+                    composed[kk].grad = None
+            return run
+        best, times = A.tune(make, W, H, 1, n, reps=3, use_cache=False)
+        rnd.settings = A.apply(base, best)
+        tuned = {"choice": best, "ms_per_3_steps": {A.describe(c): round(times[i], 3)
+                                                      for i, c in enumerate(A.CANDIDATES)}}
+        log(f"fwd+bwd autotune (ms per 3 steps): {tuned['ms_per_3_steps']} -> {best}")
 
     def step(v):
         with torch.no_grad():
@@ -239,7 +261,8 @@ def main():
 
     # --------------------------------------------- algorithmic counts per view
     counts = {"pairs": [], "evaluated": [], "composited": []}
-    cnt_settings = R.Settings(W, H, fwd_px=args.fwd_px, bwd_px=args.bwd_px, flags=N.FLAG_COUNT_EVAL)
+    cnt_settings = R.Settings(**{**rnd.settings.__dict__})
+    cnt_settings.flags = N.FLAG_COUNT_EVAL
     cnt = R.Renderer(cnt_settings, capacity=rnd.capacity, check="sync")
     with torch.no_grad():
         for v in sorted(set(views)):
@@ -327,7 +350,8 @@ def main():
                    "views": args.views, "views_per_step": 1,
                    "pairs_per_view": round(per_view["pairs"]),
                    "evaluated_per_view": round(per_view["evaluated"]),
-                   "composited_per_view": round(per_view["composited"])},
+                   "composited_per_view": round(per_view["composited"]),
+                   "launch_shape": tuned},
         "roofline": roofline,
         "step_roofline": step_roofline,
         "kernels_avg_ms": {k: round(a, 4) for k, (a, nl) in avg.items() if nl},

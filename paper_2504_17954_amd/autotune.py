@@ -30,6 +30,14 @@ CANDIDATES = [
 ]
 
 
+def describe(cfg: dict) -> str:
+    """Short name of a launch shape, e.g. 'fwd1 bwd2 chunk256 persistent8'."""
+    name = f"fwd{cfg['fwd_px']} bwd{cfg['bwd_px']} chunk{cfg['sort_chunk'] or 'auto'}"
+    if cfg["persistent"]:
+        name += f" persistent{cfg['persist_per_cu'] or 'occ'}"
+    return name
+
+
 def cache_path() -> str:
     return os.environ.get("IVRGS_AUTOTUNE_CACHE",
                           os.path.join(os.path.expanduser("~"), ".cache", "ivrgs_autotune.json"))
