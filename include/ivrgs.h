@@ -186,15 +186,21 @@ typedef struct {
  *   sorted[capacity]                record ids, each tile front to back by
  *                                   (depth key, record id)
  *   status[8]                       written by the library:
- *                                   [0] pairs required and [1] IVRGS_DEV_E_*
- *                                   bits of the last ivrgs_bin_sort,
+ *                                   [0] the pair capacity required (the pair
+ *                                   total, or, when the binning's block
+ *                                   entries did not fit the workspace sized
+ *                                   for the capacity, the capacity whose
+ *                                   workspace holds them) and [1]
+ *                                   IVRGS_DEV_E_* bits of the last
+ *                                   ivrgs_bin_sort,
  *                                   [2] evaluated and [3] composited pixel-
  *                                   Gaussian pairs (IVRGS_FLAG_COUNT_EVAL),
  *                                   [4] the OR of [1] and [5] the largest [0]
  *                                   over every bin sort since the last
  *                                   ivrgs_get_error, which clears them (the
  *                                   caller zeroes [4] and [5] once when it
- *                                   allocates the word), [6], [7] reserved */
+ *                                   allocates the word), [6] used by the
+ *                                   binning, [7] reserved */
 typedef struct {
     uint32_t *tile_start;
     uint32_t *sorted;
@@ -204,14 +210,16 @@ typedef struct {
 
 /* Bytes of workspace needed by ivrgs_bin_sort, ivrgs_render_fwd and
  * ivrgs_render_bwd for this batch: the depth order (two words per record,
- * twice), its digit histograms, the per-chunk tile counts, the records'
- * binning fields in depth order (32 bytes per record), the record
+ * twice), its digit histograms, the per-chunk block counts, the records'
+ * binning fields in depth order (32 bytes per record), the block entries
+ * (8 bytes each; capacity / 2, plus 2 per record and 256 per block of 4x4
+ * tiles, of them) with, per 256 entries, 68 bytes of tile counts, the record
  * gradients (9 floats per record), the work queue and, with one pixel per
  * lane, no work queue and no IVRGS_FLAG_FWD_ONLY, per-pixel checkpoints at
  * up to 15 cuts of every tile's list (60 KiB per tile, used while they take
  * at most 256 MiB): the backward walks each segment of a long list in its own workgroup from the
  * state the forward stored at the cut.  capacity (>= 0) is the pair capacity
- * of the bins; the workspace does not depend on it.  Returns 0 for invalid
+ * of the bins (the block entries grow with it).  Returns 0 for invalid
  * arguments. */
 size_t ivrgs_workspace_size(const ivrgs_batch *batch, const ivrgs_params *params,
                             int64_t capacity);
@@ -248,15 +256,19 @@ ivrgs_status ivrgs_project(const ivrgs_batch *batch, const ivrgs_params *params,
  * (a conservative test: the exponent's maximum over the tile's pixel box,
  * with margins for FP32 rounding), ordered by (depth key, record id).  The
  * records are put in depth order first and binned in that order, so the
- * lists need no sort of their own.  params->sort_chunk is the number of
- * records per binning chunk (rounded up to a multiple of 64; 0 picks a power
- * of two up to 512 that gives about 1024 chunks per batch); it does not
- * change the result.  Writes bins->tile_start, bins->sorted and
- * bins->status.  Returns IVRGS_E_SHAPE if a job has more tiles than the
- * per-tile counters that fit in one workgroup's LDS (about 37k tiles on a
- * 160 KiB device).  If the pair total exceeds bins->capacity, status[1] gets
- * IVRGS_DEV_E_CAPACITY, status[0] the required count, and the lists are not
- * written (render calls then leave their outputs untouched). */
+ * lists need no sort of their own: first into blocks of 4x4 tiles (an
+ * entry per overlapped block with the mask of its tiles the footprint
+ * reaches), then from each block's entries into its tiles' lists.
+ * params->sort_chunk is the number of records per binning chunk (rounded up
+ * to a multiple of 64; 0 picks a power of two up to 512 that gives about
+ * 1024 chunks per batch); it does not change the result.  Writes
+ * bins->tile_start, bins->sorted and bins->status.  Returns IVRGS_E_SHAPE
+ * if a job has more blocks than the binning's per-block LDS counters hold
+ * (about 4,700 blocks, 4,300 x 4,300 pixels, on a 160 KiB device).  If the
+ * pair total exceeds bins->capacity (or the block entries exceed the
+ * workspace sized for it), status[1] gets IVRGS_DEV_E_CAPACITY, status[0]
+ * the capacity required, and the lists are not written (render calls then
+ * leave their outputs untouched). */
 ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params,
                             const ivrgs_projected *proj, ivrgs_bins *bins,
                             void *workspace, size_t workspace_bytes, void *stream);
@@ -273,8 +285,10 @@ ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params
  * and the bins.  The call allocates nothing; its first call on a device
  * looks up that device's array (do it once outside graph capture).
  * The scratch takes 16 bytes per record for the depth order, 32 per record
- * for the binning fields, plus the digit histograms and the per-chunk tile
- * counts (4 bytes per tile per chunk of params->sort_chunk records);
+ * for the binning fields, the digit histograms, the per-chunk block counts
+ * (4 bytes per block of 4x4 tiles per chunk of params->sort_chunk records)
+ * and the block entries with their tile counts (about 8.3 bytes per entry;
+ * capacity / 2, plus 2 per record and 256 per block, of them);
  * IVRGS_E_CAPACITY if that exceeds IVRGS_NOALLOC_SCRATCH_BYTES (nothing is
  * launched), IVRGS_E_UNSUPPORTED with IVRGS_FLAG_PERSISTENT (the render
  * calls read that launch's work queue from their own workspace).  A render

@@ -145,8 +145,25 @@ ivrgs_status check_batch(const ivrgs_batch *b) {
 
 // Workspace regions.
 struct Layout {
-    size_t key0, val0, key1, val1, hist, rng, counts, part, pay, grec, queue, ckpt, ckpt_bytes, det, total;
+    size_t key0, val0, key1, val1, hist, rng, counts, part, pay, sb_len, sb_start, grec, queue, ckpt, ckpt_bytes,
+        det, tail, total;
+    int64_t ent_cap, max_parts;
 };
+
+// Block entries of the binning (8 bytes each): there are never more than
+// tile items (rect tiles), about a sixth of the pairs in practice; the
+// region holds capacity / 2 + 2 per record plus each block's padding to
+// whole parts, so a larger pair capacity also makes room for more entries.
+int64_t ent_capacity(const ivrgs_batch &b, int64_t capacity, int64_t n_blocks) {
+    return capacity / 2 + 2 * b.n_records + n_blocks * kBinPart + 64;
+}
+
+// The capacity-sized tail of the binning regions: the block entries, then
+// the block of each part and the per-part tile counts.
+size_t tail_bytes(int64_t ent_cap, int64_t max_parts) {
+    return align_up(sizeof(uint2) * (size_t)ent_cap) + align_up(sizeof(uint32_t) * (size_t)max_parts) +
+           align_up(sizeof(uint32_t) * 16 * (size_t)max_parts);
+}
 
 int pick_px(int requested, int fallback) { return requested == 0 ? fallback : requested; }
 
@@ -177,9 +194,10 @@ int chunk_of(const ivrgs_params &p, const ivrgs_batch &b) {
     return c;
 }
 
-Layout layout(const ivrgs_batch &b, const ivrgs_params &p) {
+Layout layout(const ivrgs_batch &b, const ivrgs_params &p, int64_t capacity = 0) {
     Layout L;
     const Consts k = make_consts(p);
+    const int n_sb = bin_blocks_per_job(k);
     const size_t rec_words = align_up(sizeof(uint32_t) * (size_t)b.n_records);
     size_t off = 0;
     L.key0 = off;
@@ -195,11 +213,15 @@ Layout layout(const ivrgs_batch &b, const ivrgs_params &p) {
     L.rng = off;
     off += align_up(sizeof(uint32_t) * 2 * (size_t)b.n_jobs);
     L.counts = off;
-    off += align_up(sizeof(uint32_t) * (size_t)b.n_jobs * chunk_rows(b, chunk_of(p, b)) * k.tiles_per_job);
+    off += align_up(sizeof(uint32_t) * (size_t)b.n_jobs * chunk_rows(b, chunk_of(p, b)) * n_sb);
     L.part = off;
-    off += align_up(sizeof(uint32_t) * col_part_words(b, k, chunk_of(p, b)));
+    off += align_up(sizeof(uint32_t) * col_part_words(b, n_sb, chunk_of(p, b)));
     L.pay = off;
     off += align_up(2 * sizeof(uint4) * (size_t)b.n_records);
+    L.sb_len = off;
+    off += align_up(sizeof(uint32_t) * ((size_t)b.n_jobs * n_sb + 1));
+    L.sb_start = off;
+    off += align_up(sizeof(uint32_t) * ((size_t)b.n_jobs * n_sb + 1));
     L.grec = off;
     off += align_up(sizeof(float) * kGradStride * (size_t)b.n_records);
     L.queue = off;
@@ -214,6 +236,11 @@ Layout layout(const ivrgs_batch &b, const ivrgs_params &p) {
         off += align_up(sizeof(uint64_t) * kGradStride * (size_t)b.n_records) +
                align_up(sizeof(uint32_t) * kGradRec * (size_t)b.n_jobs * k.tiles_per_job) +
                align_up(sizeof(float) * 2 * kGradRec);
+    // last, so that no other region moves with the capacity
+    L.ent_cap = ent_capacity(b, capacity, (int64_t)b.n_jobs * n_sb);
+    L.max_parts = bin_max_parts(L.ent_cap);
+    L.tail = off;
+    off += tail_bytes(L.ent_cap, L.max_parts);
     L.total = off;
     return L;
 }
@@ -229,7 +256,7 @@ extern "C" {
 
 size_t ivrgs_workspace_size(const ivrgs_batch *batch, const ivrgs_params *params, int64_t capacity) {
     if (check_batch(batch) != IVRGS_OK || check_params(params) != IVRGS_OK || capacity < 0) return 0;
-    return layout(*batch, *params).total;
+    return layout(*batch, *params, capacity).total;
 }
 
 int32_t ivrgs_tiles_per_job(const ivrgs_params *params) {
@@ -523,15 +550,17 @@ ivrgs_status bin_sort_check(const ivrgs_batch *batch, const ivrgs_params *params
     if (batch->n_records > 0 && (!proj->rec || !proj->rect || !proj->depth)) return IVRGS_E_INVALID;
     const Consts k = make_consts(*params);
     if (device_limits(dl) != hipSuccess) return IVRGS_E_HIP;
-    if (sizeof(uint32_t) * (size_t)k.tiles_per_job > dl.bin_lds) return IVRGS_E_SHAPE;
-    L = layout(*batch, *params);
+    if (bin_dyn_lds_bytes(k) > dl.bin_lds || bin_blocks_per_job(k) > 65535) return IVRGS_E_SHAPE;
+    L = layout(*batch, *params, bins->capacity);
     return IVRGS_OK;
 }
 
 // The binning launches over a workspace `ws` laid out by L (the regions
-// before L.grec; the work queue too with IVRGS_FLAG_PERSISTENT).
+// before L.grec; the work queue too with IVRGS_FLAG_PERSISTENT) and the
+// capacity-sized tail at `tail` (tail_bytes of L's sizes).
 ivrgs_status bin_sort_run(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
-                          ivrgs_bins *bins, const Layout &L, const DeviceLimits &dl, char *ws, void *stream) {
+                          ivrgs_bins *bins, const Layout &L, const DeviceLimits &dl, char *ws, char *tail,
+                          void *stream) {
     const Consts k = make_consts(*params);
     BinWork w;
     w.key[0] = reinterpret_cast<uint32_t *>(ws + L.key0);
@@ -543,6 +572,15 @@ ivrgs_status bin_sort_run(const ivrgs_batch *batch, const ivrgs_params *params, 
     w.counts = reinterpret_cast<uint32_t *>(ws + L.counts);
     w.part = reinterpret_cast<uint32_t *>(ws + L.part);
     w.pay = reinterpret_cast<uint4 *>(ws + L.pay);
+    w.sb_len = reinterpret_cast<uint32_t *>(ws + L.sb_len);
+    w.sb_start = reinterpret_cast<uint32_t *>(ws + L.sb_start);
+    w.ent = reinterpret_cast<uint2 *>(tail);
+    tail += align_up(sizeof(uint2) * (size_t)L.ent_cap);
+    w.part_sb = reinterpret_cast<uint32_t *>(tail);
+    tail += align_up(sizeof(uint32_t) * (size_t)L.max_parts);
+    w.pcnt = reinterpret_cast<uint32_t *>(tail);
+    w.ent_cap = L.ent_cap;
+    w.max_parts = L.max_parts;
     const int chunk = chunk_of(*params, *batch);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e = launch_bin_sort(*batch, k, proj->rec, proj->rect, proj->depth, *bins, w, chunk, dl.bin_lds, dl.cus, s);
@@ -561,7 +599,8 @@ ivrgs_status ivrgs_bin_sort(const ivrgs_batch *batch, const ivrgs_params *params
     const ivrgs_status st = bin_sort_check(batch, params, proj, bins, L, dl);
     if (st != IVRGS_OK) return st;
     if (!workspace || workspace_bytes < L.total) return IVRGS_E_CAPACITY;
-    return bin_sort_run(batch, params, proj, bins, L, dl, static_cast<char *>(workspace), stream);
+    char *ws = static_cast<char *>(workspace);
+    return bin_sort_run(batch, params, proj, bins, L, dl, ws, ws + L.tail, stream);
 }
 
 }  // extern "C"
@@ -612,11 +651,11 @@ ivrgs_status ivrgs_bin_sort_noalloc(const ivrgs_batch *batch, const ivrgs_params
     // the work queue of a persistent launch lives in the render calls' workspace
     if (params->flags & IVRGS_FLAG_PERSISTENT) return IVRGS_E_UNSUPPORTED;
     // the binning regions come first in the layout and end where the record
-    // gradients begin
-    if (L.grec > (size_t)IVRGS_NOALLOC_SCRATCH_BYTES) return IVRGS_E_CAPACITY;
+    // gradients begin; the capacity-sized tail follows them here
+    if (L.grec + tail_bytes(L.ent_cap, L.max_parts) > (size_t)IVRGS_NOALLOC_SCRATCH_BYTES) return IVRGS_E_CAPACITY;
     char *ws = nullptr;
     if (scratch_address(&ws) != hipSuccess) return IVRGS_E_HIP;
-    return bin_sort_run(batch, params, proj, bins, L, dl, ws, stream);
+    return bin_sort_run(batch, params, proj, bins, L, dl, ws, ws + L.grec, stream);
 }
 
 ivrgs_status ivrgs_render_fwd(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,

@@ -17,6 +17,8 @@
 //    different records, in depth order by lane, and are ranked by lane, so
 //    each tile's list comes out in (depth key, record id) order: no per-tile
 //    sort.
+#include <algorithm>
+
 #include "launch.hpp"
 
 namespace ivrgs {
@@ -329,148 +331,110 @@ __global__ __launch_bounds__(kSegThreads) void k_dsort_scatter(ivrgs_batch b, co
 }
 
 // ---------------------------------------------------------------------------
-// Binning over the depth order.
+// Binning over the depth order, in two levels.
 //
-// Visits every (record, tile) pair of the range [begin, end) of a job's depth
-// order whose tile the record's ellipse reaches, in depth order.  The work of
-// 64 consecutive records is spread evenly over the lanes: the lanes scan the
-// records' rect areas, then take the flattened (record, tile) items 64 at a
-// time (record-major, so in depth order).  Each record that starts inside
-// the current window of 64 items marks its first position in LDS; an item's
-// record is the last mark at or before it (a ballot finds its position), or
-// the record still running from the previous window.  f(record, tile x,
-// tile y) is called by the lanes of a hit, all lanes of one step together.
-struct ExpandLds {
-    float4 h0[64], h1[64];  // hit tests of the step's records
-    uint32_t off[64];       // exclusive prefix of rect areas
-    uint32_t org[64];       // rect origin, x0 | y0 << 16
-    uint32_t wid[64];       // rect width in tiles
-    float iwid[64];         // 1 / wid
-    uint32_t rid[64];       // record index
-    int32_t mark[64];       // record starting at each position of the current item window, or -1
-};
-constexpr int kBinWaves = 4;  // waves per binning workgroup (sharing one chunk)
+// Level 1 bins the records, in depth order, into blocks of 4x4 tiles (64x64
+// pixels): an entry per (record, block) that the record's tile rect
+// overlaps, with a 16-bit mask of the block's tiles that the record's
+// ellipse reaches (the ellipse-box test of each (record, tile) item).  Each
+// entry contains at least one tile of its record's rect, so there are never
+// more entries than rect tiles (about 1.8 per record at 1M Gaussians,
+// 800x800, against 11 tile items).  A counting pass per chunk of records
+// (block overlaps only, no ellipse tests), a column scan over chunks and a
+// scan over blocks give every (chunk, block) its place in the block's entry
+// list; the scatter then computes the masks (one ellipse-box test per tile
+// item, load-balanced over the wave) and appends the entries from per-block
+// cursors, so each block's list is in (depth key, record id) order.
+// Level 2 gives every tile one wave: it counts the entries of its block
+// that carry its bit (the tile totals, then one scan for the list starts),
+// and a second launch copies those entries' record ids in order into the
+// tile's list, which one wave writes contiguously.
+constexpr int kSbEdge = 4;  // tiles per block edge
+constexpr int kBinWaves = 4;  // waves per binning workgroup
 
-// Groups of 64 records start at begin, begin + stride, ... (stride 64: the
-// whole range in order; stride 64 * waves: the waves of a workgroup share it).
-// In depth order (order != nullptr) the records' binning fields are
-// gathered once, by the counting pass, which also stores them in depth order
-// (kPayWrite: 32 bytes per record, its rect and the fields of the ellipse-box
-// test), so the scatter reads them coalesced beside the ids (kPayRead).
+struct SbGeom {
+    int sbx, sby, n_sb;  // blocks per row, per column, per job
+};
+inline SbGeom sb_geom(const Consts &k) {
+    SbGeom g;
+    g.sbx = (k.tiles_x + kSbEdge - 1) / kSbEdge;
+    g.sby = (k.tiles_y + kSbEdge - 1) / kSbEdge;
+    g.n_sb = g.sbx * g.sby;
+    return g;
+}
+
+// Entry slots of one group of records in a scatter wave: at least every
+// block of a job, so that any single record fits.
+__host__ __device__ inline int sb_ent_cap(int n_sb) { return (n_sb > 256 ? n_sb + 63 : 256 + 63) / 64 * 64; }
+
+// A record's fields for binning: from the projection (gathered through the
+// depth order), or from the 32-byte copy the counting pass stored in depth
+// order.  In depth order (order != nullptr) the counting pass gathers them
+// once and stores them (kPayWrite: the rect and the fields of the
+// ellipse-box test), so the scatter reads them coalesced (kPayRead).
 enum { kPayNone = 0, kPayWrite = 1, kPayRead = 2 };
 
-template <int kPay, typename F>
-__device__ __forceinline__ void for_each_pair(const ivrgs_job &job, int begin, int end, int stride,
-                                              const uint32_t *order, uint4 *pay, const float4 *rec4,
-                                              const uint2 *rect, ExpandLds &L, F &&f) {
-    const int lane = threadIdx.x & 63;
-    for (int g0 = begin; g0 < end; g0 += stride) {
-        const int l = g0 + lane;
-        uint32_t n = 0;
-        if (l < end) {
-            const int64_t at = (int64_t)job.rec_begin + l;
-            const int64_t r = order ? (int64_t)order[at] : at;
-            uint2 rc;
-            float4 r0, r1, r2;
-            if (kPay == kPayRead && order) {
-                const uint4 pa = pay[2 * at], pb = pay[2 * at + 1];
-                rc = make_uint2(pa.x, pa.y);
-                r0 = make_float4(__uint_as_float(pa.z), __uint_as_float(pa.w), __uint_as_float(pb.x),
-                                 __uint_as_float(pb.y));
-                r1 = make_float4(__uint_as_float(pb.z), 0.f, 0.f, 0.f);
-                r2 = make_float4(0.f, 0.f, __uint_as_float(pb.w), 0.f);
-            } else {
-                rc = rect[r];
-                r0 = rec4[3 * r];
-                r1 = rec4[3 * r + 1];
-                r2 = rec4[3 * r + 2];
-                if (kPay == kPayWrite && order) {
-                    pay[2 * at] = make_uint4(rc.x, rc.y, __float_as_uint(r0.x), __float_as_uint(r0.y));
-                    pay[2 * at + 1] = make_uint4(__float_as_uint(r0.z), __float_as_uint(r0.w), __float_as_uint(r1.x),
-                                                 __float_as_uint(r2.z));
-                }
-            }
-            if (rc.x | rc.y) {
-                int x0, y0, x1, y1;
-                unpack_rect(rc, x0, y0, x1, y1);
-                n = (uint32_t)((x1 - x0) * (y1 - y0));
-                const HitTest h = make_hit_test(r0, r1, r2);
-                L.h0[lane] = make_float4(h.mx, h.my, h.qa, h.qb);
-                L.h1[lane] = make_float4(h.qc, h.i2qa, h.i2qc, h.tol);
-                L.org[lane] = rc.x;
-                L.wid[lane] = (uint32_t)(x1 - x0);
-                L.iwid[lane] = __builtin_amdgcn_rcpf((float)(x1 - x0));
-                L.rid[lane] = (uint32_t)r;
-            }
+template <int kPay>
+__device__ __forceinline__ void load_bin_record(const ivrgs_job &job, int l, const uint32_t *order, uint4 *pay,
+                                                const float4 *rec4, const uint2 *rect, uint32_t &r, uint2 &rc,
+                                                float4 &r0, float4 &r1, float4 &r2) {
+    const int64_t at = (int64_t)job.rec_begin + l;
+    r = order ? order[at] : (uint32_t)at;
+    if (kPay == kPayRead && order) {
+        const uint4 pa = pay[2 * at], pb = pay[2 * at + 1];
+        rc = make_uint2(pa.x, pa.y);
+        r0 = make_float4(__uint_as_float(pa.z), __uint_as_float(pa.w), __uint_as_float(pb.x), __uint_as_float(pb.y));
+        r1 = make_float4(__uint_as_float(pb.z), 0.f, 0.f, 0.f);
+        r2 = make_float4(0.f, 0.f, __uint_as_float(pb.w), 0.f);
+    } else {
+        rc = rect[r];
+        r0 = rec4[3 * (size_t)r];
+        r1 = rec4[3 * (size_t)r + 1];
+        r2 = rec4[3 * (size_t)r + 2];
+        if (kPay == kPayWrite && order) {
+            pay[2 * at] = make_uint4(rc.x, rc.y, __float_as_uint(r0.x), __float_as_uint(r0.y));
+            pay[2 * at + 1] = make_uint4(__float_as_uint(r0.z), __float_as_uint(r0.w), __float_as_uint(r1.x),
+                                         __float_as_uint(r2.z));
         }
-        const uint32_t incl = wave_prefix_sum(n);
-        const uint32_t my_off = incl - n;
-        L.off[lane] = my_off;
-        const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
-        int carry = 0;  // record covering the first item of the window
-        for (uint32_t base = 0; base < total; base += 64) {
-            L.mark[lane] = -1;
-            wave_lds_sync();
-            if (n != 0u && my_off >= base && my_off < base + 64u) L.mark[my_off - base] = lane;
-            wave_lds_sync();
-            // marks rise with the position, so the last one at or before
-            // this item is the prefix maximum
-            const int pm = wave_prefix_max(L.mark[lane]);
-            const int j = pm >= 0 ? pm : carry;
-            carry = __builtin_amdgcn_readlane(j, 63);
-            const uint32_t idx = base + lane;
-            if (idx < total) {
-                // every field of the item's record in one LDS round trip
-                const uint32_t offj = L.off[j], w = L.wid[j], o = L.org[j], rid = L.rid[j];
-                const float iw = L.iwid[j];
-                const float4 a = L.h0[j], c = L.h1[j];
-                asm volatile("" ::"v"(offj), "v"(w), "v"(o), "v"(rid), "v"(iw), "v"(a.x), "v"(a.y), "v"(a.z),
-                             "v"(a.w), "v"(c.x), "v"(c.y), "v"(c.z), "v"(c.w));
-                const uint32_t t = idx - offj;
-                // t / w from the reciprocal, corrected to the exact value:
-                // t is below the tiles of one job (at most 2^16, as the
-                // per-tile LDS counters require), where the estimate is
-                // within one of the quotient
-                int q = (int)((float)t * iw);
-                q -= (int)((uint32_t)q * w > t);
-                q += (int)((uint32_t)(q + 1) * w <= t);
-                const uint32_t dy = (uint32_t)q, dx = t - dy * w;
-                const int x = (int)((o & 0xFFFFu) + dx), y = (int)((o >> 16) + dy);
-                const HitTest h = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
-                if (box_hit(h, x * kTile, y * kTile, kTile, kTile)) f(rid, x, y);
-            }
-        }
-        wave_lds_sync();  // every lane is done with the tables before they are rewritten
     }
 }
 
-// Pairs per tile from each (job, chunk), into counts[job][chunk][tile].  The
-// four waves of a workgroup share the chunk (the order of counting does not
-// matter) and one set of LDS counters.
-__global__ __launch_bounds__(kBinWaves * 64) void k_chunk_count(ivrgs_batch b, Consts k, const float *__restrict__ rec,
-                                                                const uint2 *__restrict__ rect,
-                                                                const uint32_t *__restrict__ val0,
-                                                                const uint32_t *__restrict__ val1,
-                                                                const uint32_t *__restrict__ rng,
-                                                                uint4 *__restrict__ pay,
-                                                                uint32_t *__restrict__ counts, int chunk,
-                                                                int n_chunks) {
-    extern __shared__ uint32_t cnt[];  // [tiles]
-    __shared__ ExpandLds L[kBinWaves];
+// Level-1 counting: block overlaps per (job, chunk), into
+// counts[job][chunk][block]; one record per thread, the workgroup's
+// counters in LDS.
+__global__ __launch_bounds__(kBinWaves * 64) void k_sb_count(ivrgs_batch b, SbGeom sg, const float *__restrict__ rec,
+                                                             const uint2 *__restrict__ rect,
+                                                             const uint32_t *__restrict__ val0,
+                                                             const uint32_t *__restrict__ val1,
+                                                             const uint32_t *__restrict__ rng,
+                                                             uint4 *__restrict__ pay,
+                                                             uint32_t *__restrict__ counts, int chunk,
+                                                             int n_chunks) {
+    extern __shared__ uint32_t cnt[];  // [n_sb]
     const ivrgs_job job = b.jobs[blockIdx.y];
     const int begin = blockIdx.x * chunk;
     if (begin >= job.gauss_count) return;
     const int end = min(begin + chunk, job.gauss_count);
-    const int tpj = k.tiles_per_job, tx_n = k.tiles_x;
-    const int wave = threadIdx.x >> 6;
-    for (int t = threadIdx.x; t < tpj; t += kBinWaves * 64) cnt[t] = 0;
+    for (int t = threadIdx.x; t < sg.n_sb; t += kBinWaves * 64) cnt[t] = 0;
     __syncthreads();
     const uint32_t *order = depth_order(rng, b.n_jobs, blockIdx.y, val0, val1);
-    for_each_pair<kPayWrite>(job, begin + wave * 64, end, kBinWaves * 64, order, pay, reinterpret_cast<const float4 *>(rec), rect,
-                  L[wave], [&](uint32_t, int x, int y) { atomicAdd(&cnt[y * tx_n + x], 1u); });
+    const float4 *rec4 = reinterpret_cast<const float4 *>(rec);
+    for (int l = begin + (int)threadIdx.x; l < end; l += kBinWaves * 64) {
+        uint32_t r;
+        uint2 rc;
+        float4 r0, r1, r2;
+        load_bin_record<kPayWrite>(job, l, order, pay, rec4, rect, r, rc, r0, r1, r2);
+        if (rc.x | rc.y) {
+            int x0, y0, x1, y1;
+            unpack_rect(rc, x0, y0, x1, y1);
+            const int bx0 = x0 / kSbEdge, bx1 = (x1 - 1) / kSbEdge, by0 = y0 / kSbEdge, by1 = (y1 - 1) / kSbEdge;
+            for (int by = by0; by <= by1; ++by)
+                for (int bx = bx0; bx <= bx1; ++bx) atomicAdd(&cnt[by * sg.sbx + bx], 1u);
+        }
+    }
     __syncthreads();
-    uint32_t *row = counts + ((int64_t)blockIdx.y * n_chunks + blockIdx.x) * tpj;
-    for (int t = threadIdx.x; t < tpj; t += kBinWaves * 64) row[t] = cnt[t];
+    uint32_t *row = counts + ((int64_t)blockIdx.y * n_chunks + blockIdx.x) * sg.n_sb;
+    for (int t = threadIdx.x; t < sg.n_sb; t += kBinWaves * 64) row[t] = cnt[t];
 }
 
 // Exclusive scan of every tile's counts down the chunks (a column of the
@@ -561,7 +525,8 @@ __global__ __launch_bounds__(256) void k_col_apply(ivrgs_batch b, Consts k, uint
 // Single workgroup: tile counts -> exclusive starts (in place) and the total,
 // checked against the capacity.
 __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t *__restrict__ starts, int64_t n_tiles,
-                                                     int64_t *__restrict__ status, int64_t capacity) {
+                                                     int64_t *__restrict__ status, int64_t capacity,
+                                                     const uint32_t *__restrict__ ent_total) {
     __shared__ uint64_t tmp[16];
     const int64_t per = (n_tiles + blockDim.x - 1) / blockDim.x;
     const int64_t lo = threadIdx.x * per, hi = min(lo + per, n_tiles);
@@ -575,9 +540,13 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t *__restrict__ star
         run += c;
     }
     if (threadIdx.x == 0) {
-        const bool over = total > (uint64_t)capacity || total > 0xFFFFFFF0ull;
+        // the block entries did not fit: no pair was counted, and status[6]
+        // holds the capacity whose workspace would hold them
+        const bool ent_over = ent_total && *ent_total == 0xFFFFFFFFu;
+        const bool over = ent_over || total > (uint64_t)capacity || total > 0xFFFFFFF0ull;
         starts[n_tiles] = over ? 0xFFFFFFFFu : (uint32_t)total;
         const int64_t bits = over ? (int64_t)IVRGS_DEV_E_CAPACITY : 0;
+        if (ent_over) total = (uint64_t)status[6];
         status[0] = (int64_t)total;
         status[1] = bits;
         status[2] = 0;
@@ -589,87 +558,329 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t *__restrict__ star
     }
 }
 
-// Appends each chunk's record ids in depth order.  Two shapes:
-//  - kSplit: one chunk per workgroup; wave w takes the w-th part of the chunk
-//    (whole groups of 64 records), first counts its own pairs per tile, and
-//    the waves' per-tile cursors start at the tile's list start plus the
-//    chunk's column prefix plus the counts of the earlier parts.  Four times
-//    the parallelism for an extra counting pass: for few chunks.
-//  - otherwise: NW consecutive chunks per workgroup, one per wave, each
-//    cursor at the tile's list start plus the chunk's column prefix.
-// Each wave appends its records in order.  No global atomics.
-template <int NW, bool kSplit>
-__global__ __launch_bounds__(NW * 64) void k_scatter(ivrgs_batch b, Consts k, const float *__restrict__ rec,
-                                                     const uint2 *__restrict__ rect,
-                                                     const uint32_t *__restrict__ val0,
-                                                     const uint32_t *__restrict__ val1,
-                                                     const uint32_t *__restrict__ rng,
-                                                     uint4 *__restrict__ pay,
-                                                     const uint32_t *__restrict__ counts,
-                                                     uint32_t *__restrict__ sorted, int chunk, int n_chunks,
-                                                     const uint32_t *__restrict__ starts, int64_t n_tiles,
-                                                     int whole_min) {
-    extern __shared__ uint32_t cur[];  // [NW][tiles]: counts, then cursors
-    __shared__ ExpandLds L[NW];
-    if (starts[n_tiles] == 0xFFFFFFFFu) return;  // capacity exceeded
+constexpr int kPart = kBinPart;
+
+// Exclusive scan over (job, block) of the blocks' entry totals len[] padded
+// to whole parts (one workgroup): start[], with the padded total in
+// start[n], checked against the entry capacity (beyond it start[n] =
+// 0xFFFFFFFF, the later binning kernels do nothing, and status[6] gets the
+// pair capacity whose workspace holds the entries: capacity / 2 + 2 per
+// record of them); and part_sb[g], the block of each part.
+__global__ __launch_bounds__(1024) void k_scan_sb(const uint32_t *__restrict__ len, uint32_t *__restrict__ start,
+                                                  uint32_t *__restrict__ part_sb, int64_t n, int64_t ent_cap,
+                                                  int64_t n_records, int64_t *__restrict__ status) {
+    __shared__ uint64_t tmp[16];
+    __shared__ int s_over;
+    const int64_t per = (n + blockDim.x - 1) / blockDim.x;
+    const int64_t lo = threadIdx.x * per, hi = min(lo + per, n);
+    auto padded = [](uint32_t c) { return (uint64_t)(c + kPart - 1) / kPart * kPart; };
+    uint64_t sum = 0;
+    for (int64_t i = lo; i < hi; ++i) sum += padded(len[i]);
+    uint64_t total;
+    uint64_t run = block_exclusive_scan_1024(sum, tmp, total);
+    const bool over = total > (uint64_t)ent_cap;
+    if (threadIdx.x == 0) {
+        start[n] = over ? 0xFFFFFFFFu : (uint32_t)total;
+        status[6] = over ? 2 * ((int64_t)total - 2 * n_records) + 1024 : 0;
+    }
+    for (int64_t i = lo; i < hi; ++i) {
+        const uint64_t c = padded(len[i]);
+        start[i] = (uint32_t)run;
+        if (!over)
+            for (uint64_t g = run / kPart; g < (run + c) / kPart; ++g) part_sb[g] = (uint32_t)i;
+        run += c;
+    }
+    (void)s_over;
+}
+
+// Per-wave LDS of the level-1 scatter: the records of one group (at most
+// 64, in depth order) and their item and entry offsets.
+struct SbLds {
+    float4 h0[64], h1[64];  // hit tests
+    uint32_t off[64];       // exclusive prefix of rect areas (tile items)
+    uint32_t org[64];       // rect origin, x0 | y0 << 16
+    uint32_t wid[64];       // rect width in tiles
+    float iwid[64];         // 1 / wid
+    uint32_t rid[64];       // record index
+    uint32_t eoff[64];      // exclusive prefix of block overlaps (entries)
+    uint32_t borg[64];      // first block, bx0 | by0 << 16
+    uint32_t bcol[64];      // blocks per row of the overlap
+    float ibcol[64];        // 1 / bcol
+    int32_t mark[64];       // record starting at each position of the current window, or -1
+};
+
+// q = t / w for t < 2^24, w >= 1, from the reciprocal iw = 1 / w corrected to
+// the exact quotient (the estimate is within one of it).
+__device__ __forceinline__ uint32_t div_small(uint32_t t, uint32_t w, float iw) {
+    int q = (int)((float)t * iw);
+    q -= (int)((uint32_t)q * w > t);
+    q += (int)((uint32_t)(q + 1) * w <= t);
+    return (uint32_t)q;
+}
+
+// Window over flattened items of the group: the record of each position
+// (the last record starting at or before it, by a prefix maximum of the
+// marks, or the one carried from the previous window).
+__device__ __forceinline__ int window_record(SbLds &L, const uint32_t *off, bool starts_here, uint32_t my_off,
+                                             uint32_t base, int lane, int &carry) {
+    L.mark[lane] = -1;
+    wave_lds_sync();
+    if (starts_here && my_off >= base && my_off < base + 64u) L.mark[my_off - base] = lane;
+    wave_lds_sync();
+    const int pm = wave_prefix_max(L.mark[lane]);
+    const int j = pm >= 0 ? pm : carry;
+    carry = __builtin_amdgcn_readlane(j, 63);
+    (void)off;
+    return j;
+}
+
+// Level-1 scatter: one chunk per wave.  Records are taken in groups of up to
+// 64 whose block overlaps fit the wave's entry slots; the group's tile items
+// are spread evenly over the lanes (64 at a time, record-major), each item's
+// ellipse-box test sets its tile's bit in the entry of (record, block) with
+// an LDS OR; then the entries, 64 at a time in (record, block) order, are
+// appended to their blocks' lists from the wave's cursors (lanes appending
+// to one block hold different records, ranked by lane).  Entries are
+// (record id, block | tile mask << 16).
+__global__ __launch_bounds__(kBinWaves * 64) void k_sb_scatter(ivrgs_batch b, SbGeom sg,
+                                                               const float *__restrict__ rec,
+                                                               const uint2 *__restrict__ rect,
+                                                               const uint32_t *__restrict__ val0,
+                                                               const uint32_t *__restrict__ val1,
+                                                               const uint32_t *__restrict__ rng,
+                                                               const uint4 *__restrict__ pay,
+                                                               const uint32_t *__restrict__ counts,
+                                                               const uint32_t *__restrict__ sb_start,
+                                                               uint2 *__restrict__ ent, int chunk, int n_chunks) {
+    extern __shared__ uint32_t dyn[];  // per wave: [n_sb] cursors, then [ent_cap] masks
+    __shared__ SbLds Ls[kBinWaves];
+    const int n_all = b.n_jobs * sg.n_sb;
+    if (sb_start[n_all] == 0xFFFFFFFFu) return;  // the entries do not fit
     const ivrgs_job job = b.jobs[blockIdx.y];
-    // Both shapes are launched; the job's record count on the device picks
-    // the one that works: whole chunks per wave once there are at least
-    // whole_min such workgroups over the batch (estimated from this job).
-    const int rows = (job.gauss_count + chunk - 1) / chunk;
-    const bool whole = NW == 1 || (int64_t)(rows + NW - 1) / NW * b.n_jobs >= whole_min;
-    if (whole == kSplit) return;
-    const int begin = blockIdx.x * (kSplit ? 1 : NW) * chunk;
-    if (begin >= job.gauss_count) return;
-    const int end = min(begin + chunk, job.gauss_count);
-    const int tpj = k.tiles_per_job, tx_n = k.tiles_x;
-    const int tile_bits = __builtin_amdgcn_readfirstlane(32 - __clz(max(tpj - 1, 1)));
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int ch = blockIdx.x * kBinWaves + wave;  // this wave's chunk
+    const int cap = sb_ent_cap(sg.n_sb);
+    uint32_t *cur = dyn + wave * (sg.n_sb + cap);
+    uint32_t *emask = cur + sg.n_sb;
+    SbLds &L = Ls[wave];
+    const int qb = min(ch * chunk, job.gauss_count), qe = min(qb + chunk, job.gauss_count);
+    if (qb >= qe) return;  // no barrier below: each wave works alone
+    {
+        const uint32_t *row = counts + ((int64_t)blockIdx.y * n_chunks + ch) * sg.n_sb;
+        const uint32_t *st = sb_start + (int64_t)blockIdx.y * sg.n_sb;
+        for (int t = lane; t < sg.n_sb; t += 64) cur[t] = st[t] + row[t];
+    }
     const uint32_t *order = depth_order(rng, b.n_jobs, blockIdx.y, val0, val1);
     const float4 *rec4 = reinterpret_cast<const float4 *>(rec);
-    uint32_t *c = cur + wave * tpj;
-    const uint32_t *st = starts + (int64_t)blockIdx.y * tpj;
-    int qb, qe;
-    if (kSplit) {
-        const int part = (chunk / 64 + NW - 1) / NW * 64;
-        qb = min(begin + wave * part, end);
-        qe = min(qb + part, end);
-        for (int t = threadIdx.x; t < NW * tpj; t += NW * 64) cur[t] = 0;
-        __syncthreads();
-        for_each_pair<kPayRead>(job, qb, qe, 64, order, pay, rec4, rect, L[wave],
-                      [&](uint32_t, int x, int y) { atomicAdd(&c[y * tx_n + x], 1u); });
-        __syncthreads();
-        const uint32_t *row = counts + ((int64_t)blockIdx.y * n_chunks + blockIdx.x) * tpj;
-        for (int t = threadIdx.x; t < tpj; t += NW * 64) {
-            uint32_t run = st[t] + row[t];
-#pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                const uint32_t n = cur[w * tpj + t];
-                cur[w * tpj + t] = run;
-                run += n;
+    const int sb_bits = __builtin_amdgcn_readfirstlane(32 - __clz(max(sg.n_sb - 1, 1)));
+    int g0 = qb;
+    while (g0 < qe) {
+        // the group's records and their item and entry counts
+        const int l = g0 + lane;
+        uint32_t n_it = 0, n_en = 0;
+        HitTest h = {};
+        int x0 = 0, y0 = 0, x1 = 0, y1 = 0, bx0 = 0, by0 = 0, bcols = 1;
+        uint32_t r = 0;
+        if (l < qe) {
+            uint2 rc;
+            float4 r0, r1, r2;
+            load_bin_record<kPayRead>(job, l, order, const_cast<uint4 *>(pay), rec4, rect, r, rc, r0, r1, r2);
+            if (rc.x | rc.y) {
+                unpack_rect(rc, x0, y0, x1, y1);
+                n_it = (uint32_t)((x1 - x0) * (y1 - y0));
+                bx0 = x0 / kSbEdge;
+                by0 = y0 / kSbEdge;
+                bcols = (x1 - 1) / kSbEdge - bx0 + 1;
+                n_en = (uint32_t)(bcols * ((y1 - 1) / kSbEdge - by0 + 1));
+                h = make_hit_test(r0, r1, r2);
             }
         }
-    } else {
-        const int ch = blockIdx.x * NW + wave;  // this wave's chunk
-        qb = min(ch * chunk, job.gauss_count);
-        qe = min(qb + chunk, job.gauss_count);
-        const uint32_t *row = counts + ((int64_t)blockIdx.y * n_chunks + blockIdx.x * NW) * tpj;
-        for (int t = threadIdx.x; t < tpj; t += NW * 64) {
-            const uint32_t s0 = st[t];
+        // the longest prefix of records whose entries fit the slots (the
+        // first always does: a record overlaps at most every block)
+        const uint32_t e_incl = wave_prefix_sum(n_en);
+        const bool take = l < qe && e_incl <= (uint32_t)cap;
+        const uint64_t tk = __ballot(take);
+        const int ng = __popcll(tk);
+        if (!take) n_it = n_en = 0;
+        const uint32_t e_off = e_incl - n_en;
+        const uint32_t n_ent = __builtin_amdgcn_readlane(e_incl, ng - 1);
+        const uint32_t i_incl = wave_prefix_sum(n_it);
+        const uint32_t i_off = i_incl - n_it;
+        const uint32_t n_items = __builtin_amdgcn_readlane(i_incl, 63);
+        wave_lds_sync();  // the previous group's tables are no longer read
+        L.h0[lane] = make_float4(h.mx, h.my, h.qa, h.qb);
+        L.h1[lane] = make_float4(h.qc, h.i2qa, h.i2qc, h.tol);
+        L.off[lane] = i_off;
+        L.org[lane] = (uint32_t)x0 | ((uint32_t)y0 << 16);
+        L.wid[lane] = (uint32_t)max(x1 - x0, 1);
+        L.iwid[lane] = __builtin_amdgcn_rcpf((float)max(x1 - x0, 1));
+        L.rid[lane] = r;
+        L.eoff[lane] = e_off;
+        L.borg[lane] = (uint32_t)bx0 | ((uint32_t)by0 << 16);
+        L.bcol[lane] = (uint32_t)bcols;
+        L.ibcol[lane] = __builtin_amdgcn_rcpf((float)bcols);
+        for (uint32_t e = lane; e < n_ent; e += 64) emask[e] = 0u;
+        wave_lds_sync();
+        // tile items: ellipse-box test, bit into the (record, block) entry
+        int carry = 0;
+        for (uint32_t base = 0; base < n_items; base += 64) {
+            const int j = window_record(L, L.off, n_it != 0u, i_off, base, lane, carry);
+            const uint32_t idx = base + lane;
+            if (idx < n_items) {
+                const uint32_t offj = L.off[j], w = L.wid[j], o = L.org[j];
+                const float iw = L.iwid[j];
+                const float4 a = L.h0[j], c = L.h1[j];
+                const uint32_t eoj = L.eoff[j], bo = L.borg[j], bc = L.bcol[j];
+                const uint32_t t = idx - offj;
+                const uint32_t dy = div_small(t, w, iw), dx = t - dy * w;
+                const int x = (int)((o & 0xFFFFu) + dx), y = (int)((o >> 16) + dy);
+                const HitTest hh = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
+                if (box_hit(hh, x * kTile, y * kTile, kTile, kTile)) {
+                    const uint32_t e = eoj + (uint32_t)(y / kSbEdge - (int)(bo >> 16)) * bc +
+                                       (uint32_t)(x / kSbEdge - (int)(bo & 0xFFFFu));
+                    atomicOr(&emask[e], 1u << ((y % kSbEdge) * kSbEdge + (x % kSbEdge)));
+                }
+            }
+        }
+        wave_lds_sync();
+        // entries, in (record, block) order, onto their blocks' lists
+        carry = 0;
+        for (uint32_t base = 0; base < n_ent; base += 64) {
+            const int j = window_record(L, L.eoff, n_en != 0u, e_off, base, lane, carry);
+            const uint32_t idx = base + lane;
+            const bool act = idx < n_ent;
+            uint32_t sb = 0, mask = 0, rid = 0;
+            if (act) {
+                const uint32_t k = idx - L.eoff[j], bc = L.bcol[j], bo = L.borg[j];
+                const uint32_t ry = div_small(k, bc, L.ibcol[j]), rx = k - ry * bc;
+                sb = ((bo >> 16) + ry) * (uint32_t)sg.sbx + (bo & 0xFFFFu) + rx;
+                mask = emask[idx];
+                rid = L.rid[j];
+            }
+            const uint32_t at = act ? cur[sb] : 0u;  // read ahead of the match
+            const uint64_t m = match_bits<16>(sb, sb_bits, __ballot(act));
+            const uint32_t rank = lanes_below(m);
+            if (act) {
+                ent[at + rank] = make_uint2(rid, sb | (mask << 16));
+                if (rank == 0) cur[sb] = at + (uint32_t)__popcll(m);
+            }
+            wave_lds_sync();  // cursor updates before the next window reads them
+        }
+        g0 += ng;
+    }
+}
+
+// The tile of bit `bit` of block `sbl` of a job, or -1 past the image.
+__device__ __forceinline__ int block_tile(const Consts &k, const SbGeom &sg, int sbl, int bit) {
+    const int tx = (sbl % sg.sbx) * kSbEdge + bit % kSbEdge, ty = (sbl / sg.sbx) * kSbEdge + bit / kSbEdge;
+    return tx < k.tiles_x && ty < k.tiles_y ? ty * k.tiles_x + tx : -1;
+}
+
+// Level 2a, one wave per part (grid-stride over the parts): the part's
+// entries per tile bit into pcnt[part][16].  Entries past the block's length
+// (the padding) are not read.
+__global__ __launch_bounds__(256) void k_part_count(int64_t n_all, const uint32_t *__restrict__ len,
+                                                    const uint32_t *__restrict__ start,
+                                                    const uint32_t *__restrict__ part_sb,
+                                                    const uint2 *__restrict__ ent, uint32_t *__restrict__ pcnt) {
+    const uint32_t tot = start[n_all];
+    if (tot == 0xFFFFFFFFu) return;
+    const int64_t n_parts = tot / kPart;
+    const int lane = threadIdx.x & 63;
+    for (int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); g < n_parts; g += (int64_t)gridDim.x * 4) {
+        const uint32_t sb = part_sb[g];
+        const uint32_t e1 = start[sb] + len[sb];
+        uint32_t mask[kPart / 64];
 #pragma unroll
-            for (int w = 0; w < NW; ++w)
-                if (blockIdx.x * NW + w < n_chunks) cur[w * tpj + t] = s0 + row[(int64_t)w * tpj + t];
+        for (int u = 0; u < kPart / 64; ++u) {
+            const uint32_t e = (uint32_t)g * kPart + u * 64 + lane;
+            mask[u] = e < e1 ? ent[e].y >> 16 : 0u;
+        }
+        uint32_t my = 0;  // lane b < 16: the count of bit b
+#pragma unroll
+        for (int bit = 0; bit < 16; ++bit) {
+            uint32_t c = 0;
+#pragma unroll
+            for (int u = 0; u < kPart / 64; ++u) c += (uint32_t)__popcll(__ballot((mask[u] >> bit) & 1u));
+            if (lane == bit) my = c;
+        }
+        if (lane < 16) pcnt[g * 16 + lane] = my;
+    }
+}
+
+// Level 2b, one wave per (job, block, tile bit): exclusive scan of the
+// bit's part counts over the block's parts (in place), and the total into
+// tile_count[job * tiles + tile].
+__global__ __launch_bounds__(256) void k_part_scan(Consts k, SbGeom sg, int64_t n_all,
+                                                   const uint32_t *__restrict__ len,
+                                                   const uint32_t *__restrict__ start,
+                                                   uint32_t *__restrict__ pcnt, uint32_t *__restrict__ tile_count) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= n_all * 16) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t sb = w >> 4;
+    const int bit = (int)(w & 15);
+    const int job = (int)(sb / sg.n_sb), sbl = (int)(sb % sg.n_sb);
+    const int tile = block_tile(k, sg, sbl, bit);
+    if (tile < 0) return;
+    uint32_t run = 0;
+    if (start[n_all] != 0xFFFFFFFFu) {
+        const int64_t g0 = start[sb] / kPart, g1 = g0 + (len[sb] + kPart - 1) / kPart;
+        for (int64_t g = g0; g < g1; g += 64) {
+            const int64_t gi = g + lane;
+            const uint32_t c = gi < g1 ? pcnt[gi * 16 + bit] : 0u;
+            const uint32_t incl = wave_prefix_sum(c);
+            if (gi < g1) pcnt[gi * 16 + bit] = run + incl - c;
+            run += __builtin_amdgcn_readlane(incl, 63);
         }
     }
-    __syncthreads();
-    for_each_pair<kPayRead>(job, qb, qe, 64, order, pay, rec4, rect, L[wave], [&](uint32_t r, int x, int y) {
-        const uint32_t t = (uint32_t)(y * tx_n + x);
-        const uint32_t at = c[t];  // read ahead of the match, which hides its latency
-        const uint64_t m = match_bits<16>(t, tile_bits, __ballot(true));
-        const uint32_t rank = lanes_below(m);
-        sorted[at + rank] = r;
-        if (rank == 0) c[t] = at + (uint32_t)__popcll(m);
-    });
+    if (lane == 0) tile_count[(int64_t)job * k.tiles_per_job + tile] = run;
+}
+
+// Level 2c, one wave per part (grid-stride): the record ids of the part's
+// entries, per tile bit in entry order, at the tile's start plus the part's
+// offset (ranked by lane within each step of 64).
+__global__ __launch_bounds__(256) void k_part_extract(Consts k, SbGeom sg, int64_t n_all,
+                                                      const uint32_t *__restrict__ len,
+                                                      const uint32_t *__restrict__ start,
+                                                      const uint32_t *__restrict__ part_sb,
+                                                      const uint2 *__restrict__ ent, const uint32_t *__restrict__ pcnt,
+                                                      const uint32_t *__restrict__ starts, int64_t n_tiles,
+                                                      uint32_t *__restrict__ sorted) {
+    if (starts[n_tiles] == 0xFFFFFFFFu) return;  // capacity exceeded
+    const uint32_t tot = start[n_all];
+    if (tot == 0xFFFFFFFFu) return;
+    const int64_t n_parts = tot / kPart;
+    const int lane = threadIdx.x & 63;
+    for (int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); g < n_parts; g += (int64_t)gridDim.x * 4) {
+        const uint32_t sb = part_sb[g];
+        const uint32_t e1 = start[sb] + len[sb];
+        const int job = (int)(sb / sg.n_sb), sbl = (int)(sb % sg.n_sb);
+        // lane b < 16: where bit b's ids of this part start
+        uint32_t my_pos = 0;
+        if (lane < 16) {
+            const int tile = block_tile(k, sg, sbl, lane);
+            if (tile >= 0) my_pos = starts[(int64_t)job * k.tiles_per_job + tile] + pcnt[g * 16 + lane];
+        }
+        uint2 v[kPart / 64];
+#pragma unroll
+        for (int u = 0; u < kPart / 64; ++u) {
+            const uint32_t e = (uint32_t)g * kPart + u * 64 + lane;
+            v[u] = e < e1 ? ent[e] : make_uint2(0u, 0u);
+        }
+#pragma unroll
+        for (int bit = 0; bit < 16; ++bit) {
+            uint32_t pos = __builtin_amdgcn_readlane(my_pos, bit);
+#pragma unroll
+            for (int u = 0; u < kPart / 64; ++u) {
+                const bool hit = (v[u].y >> (16 + bit)) & 1u;
+                const uint64_t m = __ballot(hit);
+                if (hit) sorted[pos + lanes_below(m)] = v[u].x;
+                pos += (uint32_t)__popcll(m);
+            }
+        }
+    }
 }
 
 // Work queue for the persistent render kernels: nonempty tiles ordered by
@@ -729,37 +940,19 @@ int col_segment(int n_chunks) {
     return by_count > 32 ? by_count : 32;
 }
 
-size_t col_part_words(const ivrgs_batch &b, const Consts &k, int chunk) {
+size_t col_part_words(const ivrgs_batch &b, int width, int chunk) {
     const int n_chunks = chunk_rows(b, chunk);
     const int seg = col_segment(n_chunks);
-    return (size_t)b.n_jobs * ((n_chunks + seg - 1) / seg) * (size_t)k.tiles_per_job;
+    return (size_t)b.n_jobs * ((n_chunks + seg - 1) / seg) * (size_t)width;
 }
 
 size_t depth_sort_hist_words(const ivrgs_batch &b) { return (size_t)b.n_jobs * 256 * ((size_t)seg_rows(b) + 1); }
 
-template <int NW>
-static void launch_scatter(const ivrgs_batch &b, const Consts &k, const float *rec, const uint2 *rect2,
-                           const ivrgs_bins &bins, const BinWork &w, int chunk, int n_chunks, int64_t n_tiles,
-                           int cus, hipStream_t s) {
-    const size_t lds = sizeof(uint32_t) * NW * (size_t)k.tiles_per_job;
-    // the shape is chosen on the device from the job's record count (a
-    // culled job may hold far fewer records than the host's bound), so both
-    // are launched unless even the bound is too small for whole chunks
-    const int whole_min = cus;
-    const int64_t whole_bound = (int64_t)(n_chunks + NW - 1) / NW * b.n_jobs;
-    if (NW > 1)
-        hipLaunchKernelGGL((k_scatter<NW, true>), dim3((unsigned)n_chunks, (unsigned)b.n_jobs), dim3(NW * 64), lds, s,
-                           b, k, rec, rect2, w.val[0], w.val[1], w.rng, w.pay, w.counts, bins.sorted, chunk,
-                           n_chunks, bins.tile_start, n_tiles, whole_min);
-    if (NW == 1 || whole_bound >= whole_min)
-        hipLaunchKernelGGL((k_scatter<NW, false>), dim3((unsigned)((n_chunks + NW - 1) / NW), (unsigned)b.n_jobs),
-                           dim3(NW * 64), lds, s, b, k, rec, rect2, w.val[0], w.val[1], w.rng, w.pay, w.counts,
-                           bins.sorted, chunk, n_chunks, bins.tile_start, n_tiles, whole_min);
-}
-
 hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *rec, const uint32_t *rect,
                            const uint32_t *depth, const ivrgs_bins &bins, const BinWork &w, int chunk,
                            size_t bin_lds, int cus, hipStream_t s) {
+    (void)bin_lds;
+    (void)cus;
     const int64_t n_tiles = (int64_t)b.n_jobs * k.tiles_per_job;
     const int n_chunks = chunk_rows(b, chunk);
     const int n_seg = seg_rows(b);
@@ -779,54 +972,77 @@ hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *r
                                w.val[0], w.key[1], w.val[1], w.rng, shift, w.hist, tot, n_seg);
         }
     }
+    const SbGeom sg = sb_geom(k);
+    const int64_t n_all = (int64_t)b.n_jobs * sg.n_sb;
     {
+        // level 1: block overlaps per chunk, their column scan (the
+        // per-chunk places and block totals) and the scan over blocks
         TimedScope ts(TK_COUNT, s);
         if (n_chunks > 0) {
-            hipLaunchKernelGGL(k_chunk_count, dim3((unsigned)n_chunks, (unsigned)b.n_jobs), dim3(kBinWaves * 64),
-                               sizeof(uint32_t) * (size_t)k.tiles_per_job, s, b, k, rec, rect2, w.val[0], w.val[1],
-                               w.rng, w.pay, w.counts, chunk, n_chunks);
+            hipLaunchKernelGGL(k_sb_count, dim3((unsigned)n_chunks, (unsigned)b.n_jobs), dim3(kBinWaves * 64),
+                               sizeof(uint32_t) * (size_t)sg.n_sb, s, b, sg, rec, rect2, w.val[0], w.val[1], w.rng,
+                               w.pay, w.counts, chunk, n_chunks);
+            Consts kb = k;  // the column scan over blocks instead of tiles
+            kb.tiles_per_job = sg.n_sb;
             const int seg = col_segment(n_chunks), n_part = (n_chunks + seg - 1) / seg;
-            const unsigned tg = (unsigned)((k.tiles_per_job + 255) / 256);
-            hipLaunchKernelGGL(k_col_sum, dim3(tg, (unsigned)n_part, (unsigned)b.n_jobs), dim3(256), 0, s, b, k,
+            const unsigned tg = (unsigned)((sg.n_sb + 255) / 256);
+            hipLaunchKernelGGL(k_col_sum, dim3(tg, (unsigned)n_part, (unsigned)b.n_jobs), dim3(256), 0, s, b, kb,
                                w.counts, chunk, n_chunks, seg, w.part, n_part);
-            hipLaunchKernelGGL(k_col_part_scan, dim3(tg, (unsigned)b.n_jobs), dim3(256), 0, s, b, k, w.part, n_part,
-                               bins.tile_start);
-            hipLaunchKernelGGL(k_col_apply, dim3(tg, (unsigned)n_part, (unsigned)b.n_jobs), dim3(256), 0, s, b, k,
+            hipLaunchKernelGGL(k_col_part_scan, dim3(tg, (unsigned)b.n_jobs), dim3(256), 0, s, b, kb, w.part, n_part,
+                               w.sb_len);
+            hipLaunchKernelGGL(k_col_apply, dim3(tg, (unsigned)n_part, (unsigned)b.n_jobs), dim3(256), 0, s, b, kb,
                                w.counts, chunk, n_chunks, seg, w.part, n_part);
-        } else if (n_tiles > 0) {
-            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, bins.tile_start, n_tiles, 0u);
+        } else {
+            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, w.sb_len, n_all, 0u);
         }
-        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, bins.tile_start, n_tiles, bins.status,
-                           bins.capacity);
+        hipLaunchKernelGGL(k_scan_sb, dim3(1), dim3(1024), 0, s, w.sb_len, w.sb_start, w.part_sb, n_all, w.ent_cap,
+                           b.n_records, bins.status);
     }
-    if (n_chunks == 0) return hipGetLastError();
-    // as many waves per chunk as the per-wave tile counters allow
-    TimedScope ts(TK_SCATTER, s);
-    const size_t per_wave = sizeof(uint32_t) * (size_t)k.tiles_per_job;
-    if (4 * per_wave <= bin_lds) launch_scatter<4>(b, k, rec, rect2, bins, w, chunk, n_chunks, n_tiles, cus, s);
-    else if (2 * per_wave <= bin_lds) launch_scatter<2>(b, k, rec, rect2, bins, w, chunk, n_chunks, n_tiles, cus, s);
-    else launch_scatter<1>(b, k, rec, rect2, bins, w, chunk, n_chunks, n_tiles, cus, s);
+    {
+        // the block entries, then level 2: the tiles' pair totals, their
+        // scan (list starts, checked against the capacity), the lists
+        TimedScope ts(TK_SCATTER, s);
+        if (n_chunks > 0) {
+            const size_t lds = sizeof(uint32_t) * kBinWaves * (size_t)(sg.n_sb + sb_ent_cap(sg.n_sb));
+            hipLaunchKernelGGL(k_sb_scatter,
+                               dim3((unsigned)((n_chunks + kBinWaves - 1) / kBinWaves), (unsigned)b.n_jobs),
+                               dim3(kBinWaves * 64), lds, s, b, sg, rec, rect2, w.val[0], w.val[1], w.rng, w.pay,
+                               w.counts, w.sb_start, w.ent, chunk, n_chunks);
+        }
+        const unsigned pgrid = (unsigned)std::min<int64_t>((w.max_parts + 3) / 4, 4096);
+        if (n_chunks > 0)
+            hipLaunchKernelGGL(k_part_count, dim3(pgrid), dim3(256), 0, s, n_all, w.sb_len, w.sb_start, w.part_sb,
+                               w.ent, w.pcnt);
+        if (n_tiles > 0)
+            hipLaunchKernelGGL(k_part_scan, dim3((unsigned)((n_all * 16 + 3) / 4)), dim3(256), 0, s, k, sg, n_all,
+                               w.sb_len, w.sb_start, w.pcnt, bins.tile_start);
+        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, bins.tile_start, n_tiles, bins.status,
+                           bins.capacity, w.sb_start + n_all);
+        if (n_chunks > 0 && n_tiles > 0)
+            hipLaunchKernelGGL(k_part_extract, dim3(pgrid), dim3(256), 0, s, k, sg, n_all, w.sb_len, w.sb_start,
+                               w.part_sb, w.ent, w.pcnt, bins.tile_start, n_tiles, bins.sorted);
+    }
     return hipGetLastError();
 }
 
-// Static LDS of the binning kernels (their per-tile counters are dynamic).
-size_t bin_static_lds_bytes() { return kBinWaves * sizeof(ExpandLds); }
+// Static LDS of the binning kernels (their block counters are dynamic).
+size_t bin_static_lds_bytes() { return kBinWaves * sizeof(SbLds); }
 
-template <int NW>
-static hipError_t set_scatter_lds(size_t bytes) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_scatter<NW, true>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_scatter<NW, false>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+// Dynamic LDS the binning needs for this job size (the scatter's per-wave
+// block cursors and entry slots).
+size_t bin_dyn_lds_bytes(const Consts &k) {
+    const SbGeom sg = sb_geom(k);
+    return sizeof(uint32_t) * kBinWaves * (size_t)(sg.n_sb + sb_ent_cap(sg.n_sb));
 }
 
+int bin_blocks_per_job(const Consts &k) { return sb_geom(k).n_sb; }
+
 hipError_t set_bin_lds_limit(size_t bytes) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_chunk_count),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_sb_count),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e == hipSuccess) e = set_scatter_lds<4>(bytes);
-    if (e == hipSuccess) e = set_scatter_lds<2>(bytes);
-    if (e == hipSuccess) e = set_scatter_lds<1>(bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_sb_scatter), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)bytes);
     return e;
 }
 

@@ -22,13 +22,27 @@ struct BinWork {
     uint32_t *key[2], *val[2];  // depth-order ping-pong, one word per record each
     uint32_t *hist;             // depth_sort_hist_words
     uint32_t *rng;              // 2 * n_jobs
-    uint32_t *counts;           // [job][chunk][tile]
+    uint32_t *counts;           // [job][chunk][block]: block overlaps per chunk
     uint32_t *part;             // col_part_words: per-segment column sums
     uint4 *pay;                 // 2 per record: binning fields in depth order
+    uint32_t *sb_len;           // n_jobs * blocks + 1: entries per block
+    uint32_t *sb_start;         // n_jobs * blocks + 1: start of each block's (padded) entry list
+    uint32_t *part_sb;          // max_parts: block of each part of kPart entries
+    uint32_t *pcnt;             // max_parts * 16: per part and tile bit, count then offset
+    uint2 *ent;                 // ent_cap block entries (record id, block | tile mask << 16)
+    int64_t ent_cap, max_parts;
 };
+// Level 2 of the binning works on parts of kBinPart entries of one block's
+// list (each list padded to whole parts): the parts an entry capacity holds.
+constexpr int kBinPart = 256;
+inline int64_t bin_max_parts(int64_t ent_cap) { return ent_cap / kBinPart + 1; }
 int chunk_rows(const ivrgs_batch &b, int chunk);
 size_t depth_sort_hist_words(const ivrgs_batch &b);
-size_t col_part_words(const ivrgs_batch &b, const Consts &k, int chunk);
+// Words of the column-scan partials over chunks for rows of `width` values.
+size_t col_part_words(const ivrgs_batch &b, int width, int chunk);
+// Blocks of 4x4 tiles per job, and the binning's dynamic LDS per workgroup.
+int bin_blocks_per_job(const Consts &k);
+size_t bin_dyn_lds_bytes(const Consts &k);
 
 hipError_t launch_project(const ivrgs_batch &b, const Consts &k, float *rec, uint32_t *rect, uint32_t *depth,
                           int64_t *nonfinite, hipStream_t s);

@@ -276,8 +276,13 @@ class Renderer:
         N.ivrgs_project(batch, p, proj, s)
         N.ivrgs_bin_sort(batch, p, proj, bins, self.ws.data_ptr(), self.ws.numel(), s)
         if self.check == "sync":
-            st = self.status[:2].cpu()
-            if int(st[1]) & N.DEV_E_CAPACITY:
+            # an overflow reports the capacity it needed; growing to it can
+            # reveal the next requirement (pairs once the binning's block
+            # entries fit), so a few rounds may be needed
+            for _ in range(4):
+                st = self.status[:2].cpu()
+                if not int(st[1]) & N.DEV_E_CAPACITY:
+                    break
                 self.grow(int(int(st[0]) * 1.25) + 1024)
                 self._ensure(batch)
                 proj, bins = self._structs(batch)

@@ -69,8 +69,12 @@ def test_host_validation(lib):
     ws = N.ivrgs_workspace_size(b, p, 1000)
     # two (key, id) arrays per record for the depth order, 9 gradient floats per record
     assert ws >= 4 * 4 * 20 + 9 * 4 * 20
-    # the pair capacity lives in the caller's bins, not in the workspace
-    assert N.ivrgs_workspace_size(b, p, 10 ** 6) == ws
+    # the block entries of the binning (8 bytes each, capacity / 2 of them
+    # besides a fixed part) and, per 256 of them, a part's block and 16 tile
+    # counts (68 bytes) grow with the pair capacity
+    big = N.ivrgs_workspace_size(b, p, 10 ** 6)
+    d_ent = (10 ** 6 - 1000) // 2
+    assert abs(big - ws - (8 * d_ent + 68 * d_ent / 256)) <= 1024
     assert N.ivrgs_workspace_size(b, p, -1) == 0
     assert lib.ivrgs_status_string(N.E_CAPACITY).decode().startswith("workspace")
 
