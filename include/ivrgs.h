@@ -311,7 +311,11 @@ ivrgs_status ivrgs_render_fwd(const ivrgs_batch *batch, const ivrgs_params *para
                               float *out_rgba, float *out_maxw,
                               void *workspace, size_t workspace_bytes, void *stream);
 
-/* Backward of ivrgs_project + ivrgs_render_fwd.  Recomputes the per-pixel
+/* Backward of ivrgs_project + ivrgs_render_fwd: the gradients of the
+ * compositing of Eq. 2 and of the splat projection (Sec. 3) that the
+ * gradient-based training of the base and editable Gaussians (Sec. 4.2, 4.3;
+ * appendix A, Adam on L1 + SSIM) and the inverse exploration (Sec. 4.6)
+ * descend.  Recomputes the per-pixel
  * compositing front to back from out_rgba (nothing per pixel is stored by the
  * forward) and returns dL/d(parameters) for upstream dL/dRGBA (dl_drgba, same
  * layout as out_rgba).  grads: planes of length batch->g.n (model_id unused);

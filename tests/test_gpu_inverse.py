@@ -6,7 +6,7 @@ the orbital light direction from the record gradients a backward leaves.
 Tolerances: a float32 sum of n terms against the FP64 sum, 3e-5 of the sum of
 the terms' magnitudes; sums of rendered gradients, the per-Gaussian gradient
 tolerance (1e-3 relative + 1e-5 of the largest) carried through the sum; the
-light direction, 2e-3 relative + 2e-4 of the largest component.
+light direction, 1e-3 relative + 1e-5 of the largest component.
 """
 import sys
 
