@@ -757,6 +757,8 @@ __device__ __forceinline__ void bwd_tile_quad(const Consts &k, const float4 *__r
             gP = fmaf(g2, c.w, fmaf(g1, c.z, g0 * c.y));
         }
     }
+    // g . (colour behind a Gaussian) - gA T_final is goA - gP
+    const float goA = go - gATf;
     constexpr int kGroup = 3;
     const int my_m = lane >> 1;
     const bool my_slot = ((lane & 1) == 0) && my_m < kGroup * kGradRec;
@@ -764,8 +766,6 @@ __device__ __forceinline__ void bwd_tile_quad(const Consts &k, const float4 *__r
     SinkLane<kMode> out;
     out.init(sink, my_v);
     float acc[32];
-#pragma unroll
-    for (int q = kGroup * kGradRec; q < 32; ++q) acc[q] = 0.f;  // never written
 
     // the two-stage gather pipeline of fwd_tile_wave
     float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0, n2 = n0;
@@ -798,13 +798,10 @@ __device__ __forceinline__ void bwd_tile_quad(const Consts &k, const float4 *__r
         const uint64_t m = __ballot(touch);
         if (m == 0ull) continue;
         const int cnt = compact_records(slots, m, touch, r0, r1, r2, rid, lane);
-        // the records whose exponent passes the cutoff at a live pixel
-        uint64_t pm = 0;
-        for (int sl = 0; sl < cnt; ++sl) {
-            const float4 a = slots.f[sl][0], b = slots.f[sl][1];
-            const float p2 = splat_exponent(a.z, a.w, b.x, px - a.x, py - a.y);
-            if (__ballot(alive & (p2 >= b.y))) pm |= 1ull << sl;
-        }
+        // every compacted record is visited: the cutoff test is part of its
+        // order-free work (a separate pass to drop the records that pass at no
+        // live pixel costs more than it saves)
+        uint64_t pm = cnt == 64 ? ~0ull : ((1ull << cnt) - 1ull);
         while (pm) {
             int src[kGroup];
             bool valid[kGroup];
@@ -814,40 +811,40 @@ __device__ __forceinline__ void bwd_tile_quad(const Consts &k, const float4 *__r
                 src[g] = valid[g] ? (int)__builtin_ctzll(pm) : src[0];
                 pm &= pm - 1;
             }
-            // order-free part of the three records
+            // order-free part of the three records: everything but T
             float dx[kGroup], dy[kGroup], G[kGroup], raw[kGroup], al[kGroup], om[kGroup], inv[kGroup], gc[kGroup];
-            bool pass[kGroup];
+            float idf[kGroup];
+            bool use[kGroup], free_a[kGroup];
 #pragma unroll
             for (int g = 0; g < kGroup; ++g) {
                 const float4 a = slots.f[src[g]][0], b = slots.f[src[g]][1], c = slots.f[src[g]][2];
                 dx[g] = px - a.x;
                 dy[g] = py - a.y;
                 const float p2 = splat_exponent(a.z, a.w, b.x, dx[g], dy[g]);
-                // below the cutoff alpha < alpha_min is certain
-                pass[g] = valid[g] & (p2 >= b.y);
                 G[g] = fast_exp2(p2);
                 raw[g] = b.z * G[g];
                 al[g] = fminf(k.alpha_max, raw[g]);
                 om[g] = 1.f - al[g];
                 inv[g] = __builtin_amdgcn_rcpf(om[g]);
                 gc[g] = fmaf(g2, c.y, fmaf(g1, c.x, g0 * b.w));
+                // below the cutoff alpha < alpha_min is certain
+                use[g] = valid[g] & (p2 >= b.y) & (al[g] >= k.alpha_min);
+                // no gradient through alpha where the cap is active
+                free_a[g] = raw[g] <= k.alpha_max;
+                idf[g] = c.z;
             }
             // the front-to-back chain, the arithmetic of the forward
-            bool hit[kGroup];
+            bool any = false;
 #pragma unroll
             for (int g = 0; g < kGroup; ++g) {
                 // bitwise logic: no short-circuit branches in the chain
                 const float Tn = T * om[g];
-                const bool use = alive & pass[g] & (al[g] >= k.alpha_min);
-                const bool stop = use & (Tn < k.T_min);
-                const bool comp = use & !stop;
+                const bool stop = alive & use[g] & (Tn < k.T_min);
+                const bool comp = alive & use[g] & !stop;
                 const float w = comp ? al[g] * T : 0.f;
                 gP = fmaf(w, gc[g], gP);
-                // g . (colour behind this Gaussian, background included)
-                const float gb = go - gP;
-                const float dLda = fmaf(-(gb - gATf), inv[g], T * gc[g]);
-                // no gradient through alpha where the cap is active
-                const float dLdo = (comp & (raw[g] <= k.alpha_max)) ? dLda : 0.f;
+                const float dLda = fmaf(gP - goA, inv[g], T * gc[g]);
+                const float dLdo = (comp & free_a[g]) ? dLda : 0.f;
                 const float dp = dLdo * raw[g];
                 float *ag = acc + g * kGradRec;
                 ag[GCR] = w * g0;
@@ -863,15 +860,21 @@ __device__ __forceinline__ void bwd_tile_quad(const Consts &k, const float4 *__r
                 ag[GQC] = dpy * dy[g];
                 T = comp ? Tn : T;
                 alive = alive & !stop;
-                hit[g] = __ballot(comp) != 0ull;
+                any = any | comp;
             }
-            if (hit[0] | hit[1] | hit[2]) {
+            // the five spare slots of the reduce-scatter carry values that
+            // are dead by now: their sums land on lanes that add nothing
+            acc[27] = dx[0];
+            acc[28] = dy[0];
+            acc[29] = dx[1];
+            acc[30] = dy[1];
+            acc[31] = dx[2];
+            if (__ballot(any) != 0ull) {
                 const float tot = reduce_scatter32(acc);
-                const bool ok = my_g == 0 ? hit[0] : (my_g == 1 ? hit[1] : hit[2]);
-                const int sg = my_g == 0 ? src[0] : (my_g == 1 ? src[1] : src[2]);
-                if (my_slot && ok && tot != 0.f) {
-                    const uint32_t id = kMode == kSinkProbe ? 0u : __float_as_uint(slots.f[sg][2].z);
-                    out.add(sink, id, my_v, tot);
+                // a record that composites nowhere has all sums exactly 0
+                if (my_slot && tot != 0.f) {
+                    const float id = my_g == 0 ? idf[0] : (my_g == 1 ? idf[1] : idf[2]);
+                    out.add(sink, kMode == kSinkProbe ? 0u : __float_as_uint(id), my_v, tot);
                 }
             }
             if (__ballot(alive) == 0ull) break;  // every pixel of the wave is done
