@@ -159,11 +159,14 @@ typedef struct {
 } ivrgs_params;
 
 /* Projected records (device, caller-allocated, n_records entries):
- *   rec[r][12]  x, y, qa, qb, qc, opacity, r, g, b, depth key, alpha cutoff, 0
- *               where the 2D Gaussian at offset d = p - (x, y) is
+ *   rec[r][16]  x, y, qa, qb, qc, opacity, r, g, b, depth key, alpha cutoff, 0,
+ *               rect (two words, as below, stored as their bits), 0, 0:
+ *               one 64-byte row (the array 64-byte aligned), where the 2D
+ *               Gaussian at offset d = p - (x, y) is
  *               2^(qa dx^2 + qb dx dy + qc dy^2)  (log2 units), alpha =
  *               min(alpha_max, opacity * that), and the depth key is the
- *               FP32 camera-space z of the mean
+ *               FP32 camera-space z of the mean; ivrgs_bin_sort takes each
+ *               record's rect from its row
  *   rect[r]     tile rectangle [x0, x1) x [y0, y1) packed as
  *               (x0 | y0 << 16, x1 | y1 << 16); (0, 0) if culled
  *   depth[r]    the depth key's FP32 bits (positive, finite) of a visible

@@ -22,6 +22,7 @@ CANDIDATES = [
     dict(DEFAULT),
     {**DEFAULT, "fwd_px": 2},
     {**DEFAULT, "bwd_px": 2},
+    {**DEFAULT, "sort_chunk": 128},
     {**DEFAULT, "sort_chunk": 256},
     {**DEFAULT, "sort_chunk": 512},
     {**DEFAULT, "persistent": True},

@@ -62,9 +62,9 @@ struct AuxWalk {
     __device__ __forceinline__ void load_recs(uint32_t base) {
         if (base + lane < end) {
             nid = pid;
-            n0 = rec[3 * (size_t)nid];
-            n1 = rec[3 * (size_t)nid + 1];
-            n2 = rec[3 * (size_t)nid + 2];
+            n0 = rec[kRecVec * (size_t)nid];
+            n1 = rec[kRecVec * (size_t)nid + 1];
+            n2 = rec[kRecVec * (size_t)nid + 2];
             const int64_t g = job_gaussian(job, b.gauss_index, (int)((int64_t)nid - job.rec_begin));
             // the record's attribute row, whole vectors
             const float4 *row = reinterpret_cast<const float4 *>(attr + g * attr_stride(n_attr));

@@ -367,16 +367,16 @@ inline SbGeom sb_geom(const Consts &k) {
 // block of a job, so that any single record fits.
 __host__ __device__ inline int sb_ent_cap(int n_sb) { return (n_sb > 256 ? n_sb + 63 : 256 + 63) / 64 * 64; }
 
-// A record's fields for binning: from the projection (gathered through the
-// depth order), or from the 32-byte copy the counting pass stored in depth
-// order.  In depth order (order != nullptr) the counting pass gathers them
+// A record's fields for binning: from its 64-byte row of the projection
+// (gathered through the depth order), or from the 32-byte copy the counting
+// pass stored in depth order.  In depth order (order != nullptr) the counting pass gathers them
 // once and stores them (kPayWrite: the rect and the fields of the
 // ellipse-box test), so the scatter reads them coalesced (kPayRead).
 enum { kPayNone = 0, kPayWrite = 1, kPayRead = 2 };
 
 template <int kPay>
 __device__ __forceinline__ void load_bin_record(const ivrgs_job &job, int l, const uint32_t *order, uint4 *pay,
-                                                const float4 *rec4, const uint2 *rect, uint32_t &r, uint2 &rc,
+                                                const float4 *rec4, uint32_t &r, uint2 &rc,
                                                 float4 &r0, float4 &r1, float4 &r2) {
     const int64_t at = (int64_t)job.rec_begin + l;
     r = order ? order[at] : (uint32_t)at;
@@ -387,10 +387,12 @@ __device__ __forceinline__ void load_bin_record(const ivrgs_job &job, int l, con
         r1 = make_float4(__uint_as_float(pb.z), 0.f, 0.f, 0.f);
         r2 = make_float4(0.f, 0.f, __uint_as_float(pb.w), 0.f);
     } else {
-        rc = rect[r];
-        r0 = rec4[3 * (size_t)r];
-        r1 = rec4[3 * (size_t)r + 1];
-        r2 = rec4[3 * (size_t)r + 2];
+        // one 64-byte row: the fields and, in its last float4, the rect
+        const float4 r3 = rec4[kRecVec * (size_t)r + 3];
+        rc = make_uint2(__float_as_uint(r3.x), __float_as_uint(r3.y));
+        r0 = rec4[kRecVec * (size_t)r];
+        r1 = rec4[kRecVec * (size_t)r + 1];
+        r2 = rec4[kRecVec * (size_t)r + 2];
         if (kPay == kPayWrite && order) {
             pay[2 * at] = make_uint4(rc.x, rc.y, __float_as_uint(r0.x), __float_as_uint(r0.y));
             pay[2 * at + 1] = make_uint4(__float_as_uint(r0.z), __float_as_uint(r0.w), __float_as_uint(r1.x),
@@ -403,7 +405,6 @@ __device__ __forceinline__ void load_bin_record(const ivrgs_job &job, int l, con
 // counts[job][chunk][block]; one record per thread, the workgroup's
 // counters in LDS.
 __global__ __launch_bounds__(kBinWaves * 64) void k_sb_count(ivrgs_batch b, SbGeom sg, const float *__restrict__ rec,
-                                                             const uint2 *__restrict__ rect,
                                                              const uint32_t *__restrict__ val0,
                                                              const uint32_t *__restrict__ val1,
                                                              const uint32_t *__restrict__ rng,
@@ -423,7 +424,7 @@ __global__ __launch_bounds__(kBinWaves * 64) void k_sb_count(ivrgs_batch b, SbGe
         uint32_t r;
         uint2 rc;
         float4 r0, r1, r2;
-        load_bin_record<kPayWrite>(job, l, order, pay, rec4, rect, r, rc, r0, r1, r2);
+        load_bin_record<kPayWrite>(job, l, order, pay, rec4, r, rc, r0, r1, r2);
         if (rc.x | rc.y) {
             int x0, y0, x1, y1;
             unpack_rect(rc, x0, y0, x1, y1);
@@ -570,27 +571,40 @@ __global__ __launch_bounds__(1024) void k_scan_sb(const uint32_t *__restrict__ l
                                                   uint32_t *__restrict__ part_sb, int64_t n, int64_t ent_cap,
                                                   int64_t n_records, int64_t *__restrict__ status) {
     __shared__ uint64_t tmp[16];
-    __shared__ int s_over;
+    __shared__ uint32_t first_part[1024];  // each thread's first part
     const int64_t per = (n + blockDim.x - 1) / blockDim.x;
     const int64_t lo = threadIdx.x * per, hi = min(lo + per, n);
     auto padded = [](uint32_t c) { return (uint64_t)(c + kPart - 1) / kPart * kPart; };
     uint64_t sum = 0;
     for (int64_t i = lo; i < hi; ++i) sum += padded(len[i]);
     uint64_t total;
-    uint64_t run = block_exclusive_scan_1024(sum, tmp, total);
+    const uint64_t run0 = block_exclusive_scan_1024(sum, tmp, total);
     const bool over = total > (uint64_t)ent_cap;
     if (threadIdx.x == 0) {
         start[n] = over ? 0xFFFFFFFFu : (uint32_t)total;
         status[6] = over ? 2 * ((int64_t)total - 2 * n_records) + 1024 : 0;
     }
+    uint64_t run = run0;
     for (int64_t i = lo; i < hi; ++i) {
-        const uint64_t c = padded(len[i]);
         start[i] = (uint32_t)run;
-        if (!over)
-            for (uint64_t g = run / kPart; g < (run + c) / kPart; ++g) part_sb[g] = (uint32_t)i;
-        run += c;
+        run += padded(len[i]);
     }
-    (void)s_over;
+    if (over) return;
+    // the block of each part, spread over the threads: the thread whose
+    // blocks hold the part (the last one whose first part is at or before
+    // it), then the block among that thread's
+    first_part[threadIdx.x] = (uint32_t)(run0 / kPart);
+    __syncthreads();
+    const uint32_t n_parts = (uint32_t)(total / kPart);
+    for (uint32_t g = threadIdx.x; g < n_parts; g += blockDim.x) {
+        int t = 0;
+        for (int step = 512; step > 0; step >>= 1)
+            if (t + step < (int)blockDim.x && first_part[t + step] <= g) t += step;
+        int64_t i = (int64_t)t * per;
+        uint32_t p = first_part[t];
+        while (p + padded(len[i]) / kPart <= g) p += (uint32_t)(padded(len[i++]) / kPart);
+        part_sb[g] = (uint32_t)i;
+    }
 }
 
 // Per-wave LDS of the level-1 scatter: the records of one group (at most
@@ -644,7 +658,6 @@ __device__ __forceinline__ int window_record(SbLds &L, const uint32_t *off, bool
 // (record id, block | tile mask << 16).
 __global__ __launch_bounds__(kBinWaves * 64) void k_sb_scatter(ivrgs_batch b, SbGeom sg,
                                                                const float *__restrict__ rec,
-                                                               const uint2 *__restrict__ rect,
                                                                const uint32_t *__restrict__ val0,
                                                                const uint32_t *__restrict__ val1,
                                                                const uint32_t *__restrict__ rng,
@@ -685,7 +698,7 @@ __global__ __launch_bounds__(kBinWaves * 64) void k_sb_scatter(ivrgs_batch b, Sb
         if (l < qe) {
             uint2 rc;
             float4 r0, r1, r2;
-            load_bin_record<kPayRead>(job, l, order, const_cast<uint4 *>(pay), rec4, rect, r, rc, r0, r1, r2);
+            load_bin_record<kPayRead>(job, l, order, const_cast<uint4 *>(pay), rec4, r, rc, r0, r1, r2);
             if (rc.x | rc.y) {
                 unpack_rect(rc, x0, y0, x1, y1);
                 n_it = (uint32_t)((x1 - x0) * (y1 - y0));
@@ -956,7 +969,7 @@ hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *r
     const int64_t n_tiles = (int64_t)b.n_jobs * k.tiles_per_job;
     const int n_chunks = chunk_rows(b, chunk);
     const int n_seg = seg_rows(b);
-    const uint2 *rect2 = reinterpret_cast<const uint2 *>(rect);
+    (void)rect;  // the binning reads each record's rect from its row in rec
     uint32_t *tot = w.hist + (size_t)b.n_jobs * 256 * n_seg;
     if (n_seg > 0) {
         TimedScope ts(TK_SORT, s);
@@ -980,7 +993,7 @@ hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *r
         TimedScope ts(TK_COUNT, s);
         if (n_chunks > 0) {
             hipLaunchKernelGGL(k_sb_count, dim3((unsigned)n_chunks, (unsigned)b.n_jobs), dim3(kBinWaves * 64),
-                               sizeof(uint32_t) * (size_t)sg.n_sb, s, b, sg, rec, rect2, w.val[0], w.val[1], w.rng,
+                               sizeof(uint32_t) * (size_t)sg.n_sb, s, b, sg, rec, w.val[0], w.val[1], w.rng,
                                w.pay, w.counts, chunk, n_chunks);
             Consts kb = k;  // the column scan over blocks instead of tiles
             kb.tiles_per_job = sg.n_sb;
@@ -1006,7 +1019,7 @@ hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *r
             const size_t lds = sizeof(uint32_t) * kBinWaves * (size_t)(sg.n_sb + sb_ent_cap(sg.n_sb));
             hipLaunchKernelGGL(k_sb_scatter,
                                dim3((unsigned)((n_chunks + kBinWaves - 1) / kBinWaves), (unsigned)b.n_jobs),
-                               dim3(kBinWaves * 64), lds, s, b, sg, rec, rect2, w.val[0], w.val[1], w.rng, w.pay,
+                               dim3(kBinWaves * 64), lds, s, b, sg, rec, w.val[0], w.val[1], w.rng, w.pay,
                                w.counts, w.sb_start, w.ent, chunk, n_chunks);
         }
         const unsigned pgrid = (unsigned)std::min<int64_t>((w.max_parts + 3) / 4, 4096);

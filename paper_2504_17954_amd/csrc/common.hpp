@@ -10,7 +10,8 @@ namespace ivrgs {
 
 constexpr int kTile = 16;             // tile edge in pixels
 constexpr int kTilePix = kTile * kTile;
-constexpr int kRecWords = 12;         // floats per projected record
+constexpr int kRecWords = 16;         // floats per projected record: one 64-byte row
+constexpr int kRecVec = kRecWords / 4;  // float4 per record
 constexpr int kGradRec = 9;           // record-gradient components
 constexpr int kGradStride = 9;        // floats between the gradient rows of consecutive records
 
@@ -37,7 +38,7 @@ constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
 
 // Record word indices.
-enum { RX = 0, RY, RQA, RQB, RQC, RO, RCR, RCG, RCB, RZ, RCUT, RPAD };
+enum { RX = 0, RY, RQA, RQB, RQC, RO, RCR, RCG, RCB, RZ, RCUT, RPAD, RRECT0, RRECT1, RPAD1, RPAD2 };
 // Record-gradient rows (kGradStride floats per record).  With d = pixel
 // centre - screen mean and D = dL/do' * o' G summed over the record's
 // composited pixels: GX, GY = sum D dx, sum D dy; GQA, GQB, GQC = sum D dx^2,

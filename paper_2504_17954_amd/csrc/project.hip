@@ -290,9 +290,12 @@ __global__ __launch_bounds__(256) void k_project(ivrgs_batch b, Consts k, float4
             }
         }
     }
-    rec[3 * r + 0] = r0;
-    rec[3 * r + 1] = r1;
-    rec[3 * r + 2] = r2;
+    rec[kRecVec * r + 0] = r0;
+    rec[kRecVec * r + 1] = r1;
+    rec[kRecVec * r + 2] = r2;
+    // the tile rectangle also in the row, so that the binning's gather of a
+    // record in depth order reads one 64-byte row
+    rec[kRecVec * r + 3] = make_float4(__uint_as_float(rc.x), __uint_as_float(rc.y), 0.f, 0.f);
     rect[r] = rc;
     depth[r] = (rc.x | rc.y) ? __float_as_uint(z32) : 0xFFFFFFFFu;
     if (nonfinite) {

@@ -121,7 +121,7 @@ __device__ __forceinline__ void fwd_tile(const Consts &k, const float4 *__restri
         const uint32_t idx = base + threadIdx.x;
         if (idx < end) {
             const uint32_t r = sorted[idx];
-            const float4 r0 = rec[3 * (size_t)r], r1 = rec[3 * (size_t)r + 1], r2 = rec[3 * (size_t)r + 2];
+            const float4 r0 = rec[kRecVec * (size_t)r], r1 = rec[kRecVec * (size_t)r + 1], r2 = rec[kRecVec * (size_t)r + 2];
             s0[threadIdx.x] = r0;
             s1[threadIdx.x] = r1;
             s2[threadIdx.x] = make_float2(r2.x, r2.z);
@@ -268,9 +268,9 @@ __device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__r
     auto load_recs = [&](uint32_t base) {
         if (base + lane < end) {
             nid = pid;
-            n0 = rec[3 * (size_t)nid];
-            n1 = rec[3 * (size_t)nid + 1];
-            n2 = rec[3 * (size_t)nid + 2];
+            n0 = rec[kRecVec * (size_t)nid];
+            n1 = rec[kRecVec * (size_t)nid + 1];
+            n2 = rec[kRecVec * (size_t)nid + 2];
         }
     };
     if (start < end) {
@@ -560,9 +560,9 @@ __device__ __forceinline__ void bwd_tile_wave(const Consts &k, const float4 *__r
     auto load_recs = [&](uint32_t base) {
         if (base + lane < end) {
             nid = pid;
-            n0 = rec[3 * (size_t)nid];
-            n1 = rec[3 * (size_t)nid + 1];
-            n2 = rec[3 * (size_t)nid + 2];
+            n0 = rec[kRecVec * (size_t)nid];
+            n1 = rec[kRecVec * (size_t)nid + 1];
+            n2 = rec[kRecVec * (size_t)nid + 2];
         }
     };
     if (start < end) {
@@ -776,9 +776,9 @@ __device__ __forceinline__ void bwd_tile_quad(const Consts &k, const float4 *__r
     auto load_recs = [&](uint32_t base) {
         if (base + lane < end) {
             nid = pid;
-            n0 = rec[3 * (size_t)nid];
-            n1 = rec[3 * (size_t)nid + 1];
-            n2 = rec[3 * (size_t)nid + 2];
+            n0 = rec[kRecVec * (size_t)nid];
+            n1 = rec[kRecVec * (size_t)nid + 1];
+            n2 = rec[kRecVec * (size_t)nid + 2];
         }
     };
     if (start < end) {

@@ -176,7 +176,7 @@ class Renderer:
         R, J = int(batch.n_records), int(batch.n_jobs)
         if self.rec is None or self.rec.shape[0] < max(R, 1):
             self._bin_fp = None
-            self.rec = torch.empty((max(R, 1), 12), dtype=torch.float32, device=dev)
+            self.rec = torch.empty((max(R, 1), 16), dtype=torch.float32, device=dev)
             self.rect = torch.empty((max(R, 1), 2), dtype=torch.int32, device=dev)
             self.depth = torch.empty(max(R, 1), dtype=torch.int32, device=dev)
         n_tiles = J * tiles

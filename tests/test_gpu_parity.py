@@ -81,6 +81,9 @@ def test_project_parity(dev):
     N.ivrgs_project(batch, R.Settings(128, 128).params(), proj, R._stream())
     rec = rnd.rec[:10_000].cpu().numpy()
     rect = rnd.rect[:10_000].cpu().numpy()
+    # the row carries the rect too, and zeros in its spare words
+    assert np.array_equal(rec[:, 12:14].view(np.uint32), rect.view(np.uint32))
+    assert np.all(rec[:, [11, 14, 15]] == 0.0)
     ref = O.project(planes, cam, prm)
     kept = (rect[:, 0] != 0) | (rect[:, 1] != 0)
     valid = ref[:, 0] != 0
@@ -125,10 +128,11 @@ def _bin_case(dev, width, height, rects, z, n_jobs=1, chunk=0):
     planes = {k: torch.zeros((d, per), dtype=torch.float32, device=dev) for k, d in R.PLANE_DIMS.items()}
     batch = rnd.make_batch(planes, None, R.default_edits(dev), R.camera_table([I.look_at((0, -4, 0))]), jobs)
     rnd._ensure(batch)
-    rec = np.zeros((n, 12), np.float32)
-    rec[:, 9] = z
-    rnd.rec[:n] = torch.from_numpy(rec).to(dev)
     packed = np.stack([rects[:, 0] | (rects[:, 1] << 16), rects[:, 2] | (rects[:, 3] << 16)], 1)
+    rec = np.zeros((n, 16), np.float32)
+    rec[:, 9] = z
+    rec[:, 12:14] = packed.astype(np.uint32).view(np.float32)  # the rect, also in the row
+    rnd.rec[:n] = torch.from_numpy(rec).to(dev)
     rnd.rect[:n] = torch.from_numpy(packed.astype(np.uint32).view(np.int32)).to(dev)
     culled = (rects[:, 0] == 0) & (rects[:, 1] == 0) & (rects[:, 2] == 0) & (rects[:, 3] == 0)
     dbits = np.where(culled, np.uint32(0xFFFFFFFF), z.astype(np.float32).view(np.uint32))
