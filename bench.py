@@ -156,6 +156,7 @@ def main():
         sys.exit(2)
     import torch
     from paper_2504_17954_amd import inputs as I
+    from paper_2504_17954_amd import losses as LS
     from paper_2504_17954_amd import native as N
     from paper_2504_17954_amd import raster as R
 
@@ -205,7 +206,7 @@ def main():
                 rnd.settings = A.apply(base, cfg)
                 for v in range(3):
                     rgba = R.rasterize(composed, cams_t, jobs[v], rnd, model_id=mid, edits_t=edits_t)
-                    (rgba - targets[v]).abs().mean().backward()
+                    LS.l1(rgba, targets[v]).backward()
                 for kk in R.PLANES:
                     composed[kk].grad = None
             return run
@@ -219,7 +220,7 @@ def main():
         with torch.no_grad():
             R.compose_into(mdev, edits, composed, mid)
         rgba = R.rasterize(composed, cams_t, jobs[v], rnd, model_id=mid, edits_t=edits_t)
-        loss = (rgba - targets[v]).abs().mean()
+        loss = LS.l1(rgba, targets[v])
         loss.backward()
         for k in R.PLANES:
             composed[k].grad = None
@@ -511,6 +512,7 @@ def secondary_sh(dev, steps=20, warmup=3):
     800x800, one view per step cycling the 100 cameras."""
     import torch
     from paper_2504_17954_amd import inputs as I
+    from paper_2504_17954_amd import losses as LS
     from paper_2504_17954_amd import native as N
     from paper_2504_17954_amd import raster as R
     from paper_2504_17954_amd import sh as SH
@@ -553,7 +555,7 @@ def secondary_sh(dev, steps=20, warmup=3):
     def step(v):
         pl = dict(planes, mean=mean, color=SH.SHColor.apply(shp, mean, cams[v % 100], 3))
         out = R.rasterize(pl, cams_t[v % 100:v % 100 + 1], jobs, rnd)[0]
-        loss = (out - targets[v % 4]).abs().mean()
+        loss = LS.l1(out, targets[v % 4])
         mean.grad = shp.grad = None
         loss.backward()
 

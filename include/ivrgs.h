@@ -591,6 +591,24 @@ ivrgs_status ivrgs_ssim_bwd(const float *x, const float *y, int32_t channels, in
                             const float *grad_mean, float *grad_x, const void *workspace, size_t workspace_bytes,
                             void *stream);
 
+/* The L1 term of the photometric loss (Sec. 4.2; the headline training step
+ * and the base stage weight it alone or with D-SSIM): mean |x - y| over n
+ * values (device float arrays; any layout, the same for both), FP32
+ * differences summed in FP64 per workgroup slice, the slices added in a
+ * fixed order (deterministic).  out_mean: one device float.  Workspace:
+ * ivrgs_l1_workspace_size(n) bytes of device memory (0 for n <= 0).
+ * IVRGS_E_SHAPE for n <= 0 or n > 2^40, IVRGS_E_CAPACITY for a small
+ * workspace. */
+size_t ivrgs_l1_workspace_size(int64_t n);
+ivrgs_status ivrgs_l1_fwd(const float *x, const float *y, int64_t n, float *out_mean, void *workspace,
+                          size_t workspace_bytes, void *stream);
+
+/* grad_x[i] = sign(x[i] - y[i]) * grad_mean / n (device; grad_mean one device
+ * float, dL/d(mean)); sign(0) = 0 and a NaN difference gives NaN.  One
+ * launch, no workspace. */
+ivrgs_status ivrgs_l1_bwd(const float *x, const float *y, int64_t n, const float *grad_mean, float *grad_x,
+                          void *stream);
+
 /* Gradient of the photometric loss L = (1 - lam) mean|x - y| + lam (1 - SSIM)
  * with respect to x (Sec. 4.2 names the L1 + D-SSIM combination, the
  * appendix weights it 0.8 / 0.2; inverse exploration, Sec. 4.6, fits its

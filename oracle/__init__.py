@@ -306,6 +306,13 @@ def compose_bwd(models_planes, edit_rows, grads):
     return out
 
 
+def l1_loss(x, y):
+    """The L1 term of the photometric loss (Sec. 4.2): mean |x - y| over all
+    entries, in FP64."""
+    d = np.asarray(x, np.float64) - np.asarray(y, np.float64)
+    return float(np.abs(d).sum() / d.size)
+
+
 def l1_loss_grad(rgba, target):
     """Gradient of mean |RGBA - target| over 4HW entries (sign(0) = 0)."""
     return np.sign(rgba - target) / rgba.size

@@ -4,8 +4,8 @@ a HIP graph.
 All jobs of a step go through one launch per kernel: projection over every
 (job, Gaussian), one binning/sort over every (job, tile), and persistent
 render kernels that take (job, tile) items longest-list-first from a device
-queue.  The step computes the L1 image gradient elementwise
-(sign(rgba - target) / numel, no reduction kernels), so it can be captured
+queue.  The step computes the L1 image gradient elementwise in one launch
+(sign(rgba - target) / numel, no reduction kernel), so it can be captured
 as a graph and replayed; gradients accumulate over jobs that share
 Gaussians (several views of one model).
 """
@@ -37,7 +37,10 @@ class BatchStep:
         n = planes["mean"].shape[1]
         self.grads = {k: torch.empty((d, n), dtype=torch.float32, device=dev) for k, d in R.PLANE_DIMS.items()}
         self.renderer = R.Renderer(settings, capacity=capacity or (1 << 24), check="sync")
-        self.scale = 1.0 / float(self.rgba.numel())
+        if tuple(targets.shape) != tuple(self.rgba.shape) or targets.dtype != torch.float32 \
+                or not targets.is_contiguous():
+            raise ValueError("targets: expected a contiguous float32 [n_jobs, 4, H, W] tensor")
+        self.one = torch.ones((), dtype=torch.float32, device=dev)  # dL/d(mean)
         self.graph = None
         # size every buffer (and the pair capacity) with one synchronising pass
         self.renderer.forward(self.planes, self.cams_t, self.jobs, self.model_id, self.edits_t, out=self.rgba)
@@ -48,9 +51,8 @@ class BatchStep:
         """Forward, L1 image gradient, backward; returns the gradient dict."""
         r = self.renderer
         r.forward(self.planes, self.cams_t, self.jobs, self.model_id, self.edits_t, out=self.rgba)
-        torch.sub(self.rgba, self.targets, out=self.dl)
-        torch.sign(self.dl, out=self.dl)
-        self.dl.mul_(self.scale)
+        N.ivrgs_l1_bwd(self.rgba.data_ptr(), self.targets.data_ptr(), self.rgba.numel(), self.one.data_ptr(),
+                       self.dl.data_ptr(), R._stream())
         r.backward(self.planes, self.cams_t, self.jobs, self.rgba, self.dl, self.model_id, self.edits_t,
                    grads=self.grads)
         return self.grads

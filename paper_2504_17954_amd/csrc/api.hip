@@ -471,6 +471,24 @@ ivrgs_status ivrgs_photometric_grad(const float *x, const float *y, int32_t chan
                                               reinterpret_cast<hipStream_t>(stream)));
 }
 
+size_t ivrgs_l1_workspace_size(int64_t n) { return n > 0 ? sizeof(double) * (size_t)l1_blocks(n) : 0; }
+
+ivrgs_status ivrgs_l1_fwd(const float *x, const float *y, int64_t n, float *out_mean, void *workspace,
+                          size_t workspace_bytes, void *stream) {
+    if (!x || !y || !out_mean || !workspace) return IVRGS_E_INVALID;
+    if (n <= 0 || n > ((int64_t)1 << 40)) return IVRGS_E_SHAPE;
+    if (workspace_bytes < ivrgs_l1_workspace_size(n)) return IVRGS_E_CAPACITY;
+    return hip_status(launch_l1_fwd(x, y, n, out_mean, static_cast<double *>(workspace),
+                                    reinterpret_cast<hipStream_t>(stream)));
+}
+
+ivrgs_status ivrgs_l1_bwd(const float *x, const float *y, int64_t n, const float *grad_mean, float *grad_x,
+                          void *stream) {
+    if (!x || !y || !grad_mean || !grad_x) return IVRGS_E_INVALID;
+    if (n <= 0 || (n + 255) / 256 > (int64_t)UINT32_MAX) return IVRGS_E_SHAPE;
+    return hip_status(launch_l1_bwd(x, y, n, grad_mean, grad_x, reinterpret_cast<hipStream_t>(stream)));
+}
+
 int64_t ivrgs_explore_state_words(int32_t n_models) {
     if (n_models <= 0) return 0;
     return 3 * (4 * (int64_t)n_models + 10) + 1;

@@ -142,6 +142,10 @@ hipError_t launch_ssim_fwd(const float *x, const float *y, int channels, int H, 
                            hipStream_t s);
 hipError_t launch_ssim_bwd(const float *x, const float *y, int channels, int H, int W, const float *grad_mean,
                            float *grad_x, const float *ws, hipStream_t s);
+int64_t l1_blocks(int64_t n);
+hipError_t launch_l1_fwd(const float *x, const float *y, int64_t n, float *out, double *partial, hipStream_t s);
+hipError_t launch_l1_bwd(const float *x, const float *y, int64_t n, const float *grad_mean, float *grad_x,
+                         hipStream_t s);
 hipError_t launch_photometric_grad(const float *x, const float *y, int channels, int H, int W, float lam,
                                    float *grad_x, const float *ws, hipStream_t s);
 // Training regularisers on the rendered maps of one view (normal

@@ -23,6 +23,7 @@
 // workgroup; a single workgroup adds the partials in a fixed order (FP64),
 // so the result does not depend on scheduling.  Bound: HBM (the image and
 // target read once, 12 B per window written, read back once).
+#include <algorithm>
 #include <cmath>
 
 #include "launch.hpp"
@@ -239,6 +240,92 @@ hipError_t launch_photometric_grad(const float *x, const float *y, int channels,
     const float l1_w = (float)((1.0 - (double)lam) / ((double)channels * H * W));
     hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, s, x, y, H, W, ssim_taps(), ws, nullptr,
                        1.0 / ((double)channels * Ho * Wo), -lam, l1_w, grad_x);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The L1 term of the photometric loss, mean |x - y| over n values, and its
+// gradient sign(x - y) g / n.  Forward: each workgroup sums |x - y| over a
+// fixed slice (the FP32 difference, accumulated in FP64) into one partial;
+// one workgroup adds the partials in a fixed order, so the result does not
+// depend on scheduling.  Both bound by HBM (x and y read once; the backward
+// writes the gradient once).
+constexpr int kL1MaxBlocks = 1024;
+constexpr int64_t kL1Quantum = 4 * 256;  // values per workgroup step (float4 per thread)
+
+int64_t l1_blocks(int64_t n) { return std::min<int64_t>(kL1MaxBlocks, (n + 4095) / 4096); }
+
+namespace {
+
+__device__ __forceinline__ double block_sum_256(double v, double *red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+// Workgroup b sums values [b per, min((b + 1) per, n)); per is a multiple of
+// kL1Quantum, so with 16-byte aligned x and y (vec) every float4 of a slice
+// is aligned and only the last slice has a scalar tail.
+__global__ __launch_bounds__(256) void k_l1_partial(const float *__restrict__ x, const float *__restrict__ y,
+                                                    int64_t n, int64_t per, bool vec, double *__restrict__ partial) {
+    __shared__ double red[256];
+    const int64_t b0 = (int64_t)blockIdx.x * per, b1 = min(b0 + per, n);
+    double s = 0.0;
+    int64_t tail = b0;
+    if (vec) {
+        const int64_t v1 = b0 + (b1 - b0) / 4 * 4;
+        const float4 *x4 = reinterpret_cast<const float4 *>(x), *y4 = reinterpret_cast<const float4 *>(y);
+        for (int64_t i = b0 / 4 + threadIdx.x; i < v1 / 4; i += 256) {
+            const float4 a = x4[i], c = y4[i];
+            s += (double)fabsf(a.x - c.x) + (double)fabsf(a.y - c.y) + (double)fabsf(a.z - c.z) +
+                 (double)fabsf(a.w - c.w);
+        }
+        tail = v1;
+    }
+    for (int64_t i = tail + threadIdx.x; i < b1; i += 256) s += (double)fabsf(x[i] - y[i]);
+    const double t = block_sum_256(s, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_l1_final(const double *__restrict__ partial, int64_t m, double inv_n,
+                                                  float *__restrict__ out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += 256) s += partial[i];
+    const double t = block_sum_256(s, red);
+    if (threadIdx.x == 0) out[0] = (float)(t * inv_n);
+}
+
+// d = x - y: g / n with the sign of d, 0 where d = 0, NaN where d is NaN.
+__global__ __launch_bounds__(256) void k_l1_bwd(const float *__restrict__ x, const float *__restrict__ y, int64_t n,
+                                                const float *__restrict__ grad_mean, double inv_n,
+                                                float *__restrict__ gx) {
+    const float g = (float)((double)grad_mean[0] * inv_n);
+    auto one = [g](float d) { return d > 0.f ? g : (d < 0.f ? -g : (d == 0.f ? 0.f : d)); };
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) gx[i] = one(x[i] - y[i]);
+}
+
+}  // namespace
+
+hipError_t launch_l1_fwd(const float *x, const float *y, int64_t n, float *out, double *partial, hipStream_t s) {
+    const int64_t m = l1_blocks(n);
+    const int64_t per = ((n + m - 1) / m + kL1Quantum - 1) / kL1Quantum * kL1Quantum;
+    const int64_t blocks = (n + per - 1) / per;
+    const bool vec = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) & 15u) == 0;
+    hipLaunchKernelGGL(k_l1_partial, dim3((unsigned)blocks), dim3(256), 0, s, x, y, n, per, vec, partial);
+    hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(256), 0, s, partial, blocks, 1.0 / (double)n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_l1_bwd(const float *x, const float *y, int64_t n, const float *grad_mean, float *grad_x,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_l1_bwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n, grad_mean,
+                       1.0 / (double)n, grad_x);
     return hipGetLastError();
 }
 

@@ -78,6 +78,40 @@ def ssim(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
     return _SsimFn.apply(x.contiguous(), y.detach().contiguous())
 
 
+class _L1Fn(torch.autograd.Function):
+    """mean |x - y| through ivrgs_l1_fwd / ivrgs_l1_bwd (no gradient to y)."""
+
+    @staticmethod
+    def forward(ctx, x, y):
+        n = x.numel()
+        ws = torch.empty(N.ivrgs_l1_workspace_size(n), dtype=torch.uint8, device=x.device)
+        out = torch.empty((), dtype=torch.float32, device=x.device)
+        N.ivrgs_l1_fwd(x.data_ptr(), y.data_ptr(), n, out.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+        ctx.save_for_backward(x, y)
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        x, y = ctx.saved_tensors
+        gx = torch.empty_like(x)
+        g = g.to(torch.float32).contiguous()
+        N.ivrgs_l1_bwd(x.data_ptr(), y.data_ptr(), x.numel(), g.data_ptr(), gx.data_ptr(), _stream())
+        return gx, None
+
+
+def l1(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+    """mean |x - y| of two float32 device tensors of one shape (the L1 term
+    of the photometric loss; no gradient to y), through the HIP kernels."""
+    if not (x.is_cuda and y.is_cuda):
+        raise ValueError("expected device tensors (the kernels run on the GPU; the CPU reference is "
+                         "the oracle's, not part of this package)")
+    if y.shape != x.shape or x.dtype != torch.float32 or y.dtype != torch.float32 or y.device != x.device:
+        raise ValueError("expected float32 tensors of one shape and device")
+    if x.numel() == 0:
+        raise ValueError("mean of an empty tensor")
+    return _L1Fn.apply(x.contiguous(), y.detach().contiguous())
+
+
 class _PhotometricFn(torch.autograd.Function):
     """(1 - lam) mean |x - y| + lam (1 - SSIM(x, y)); the backward is one
     launch of ivrgs_photometric_grad over the SSIM forward's workspace."""
@@ -91,7 +125,10 @@ class _PhotometricFn(torch.autograd.Function):
         N.ivrgs_ssim_fwd(x.data_ptr(), y.data_ptr(), c, h, w, s.data_ptr(), ws.data_ptr(), nbytes, _stream())
         ctx.save_for_backward(x, y, ws)
         ctx.lam = lam
-        return (1 - lam) * (x - y).abs().mean() + lam * (1 - s)
+        l1w = torch.empty(N.ivrgs_l1_workspace_size(x.numel()), dtype=torch.uint8, device=x.device)
+        m = torch.empty((), dtype=torch.float32, device=x.device)
+        N.ivrgs_l1_fwd(x.data_ptr(), y.data_ptr(), x.numel(), m.data_ptr(), l1w.data_ptr(), l1w.numel(), _stream())
+        return (1 - lam) * m + lam * (1 - s)
 
     @staticmethod
     def backward(ctx, g):

@@ -29,7 +29,8 @@ EXPORTS = ("ivrgs_workspace_size", "ivrgs_tiles_per_job", "ivrgs_compose", "ivrg
            "ivrgs_sh_color", "ivrgs_sh_color_bwd", "ivrgs_render_aux_fwd", "ivrgs_render_aux_bwd",
            "ivrgs_get_error", "ivrgs_ssim_workspace_size", "ivrgs_ssim_fwd", "ivrgs_ssim_bwd",
            "ivrgs_vq_fit_batch_workspace_size", "ivrgs_vq_fit_batch", "ivrgs_photometric_grad",
-           "ivrgs_reg_workspace_size", "ivrgs_reg_fwd", "ivrgs_reg_bwd", "ivrgs_bin_sort_noalloc")
+           "ivrgs_reg_workspace_size", "ivrgs_reg_fwd", "ivrgs_reg_bwd", "ivrgs_bin_sort_noalloc",
+           "ivrgs_l1_workspace_size", "ivrgs_l1_fwd", "ivrgs_l1_bwd")
 NOALLOC_SCRATCH_BYTES = 64 << 20
 TIMING_KINDS = ("project", "tile_count", "scatter", "depth_sort", "render_fwd", "render_bwd",
                 "project_bwd", "compose", "fill", "cull", "edit_bwd", "vq", "sh", "aux")
@@ -193,6 +194,12 @@ def load(path: str = LIB_PATH):
     lib.ivrgs_ssim_bwd.restype = C.c_int
     lib.ivrgs_photometric_grad.argtypes = [P, P, I32, I32, I32, C.c_float, P, P, C.c_size_t, P]
     lib.ivrgs_photometric_grad.restype = C.c_int
+    lib.ivrgs_l1_workspace_size.argtypes = [C.c_int64]
+    lib.ivrgs_l1_workspace_size.restype = C.c_size_t
+    lib.ivrgs_l1_fwd.argtypes = [P, P, C.c_int64, P, P, C.c_size_t, P]
+    lib.ivrgs_l1_fwd.restype = C.c_int
+    lib.ivrgs_l1_bwd.argtypes = [P, P, C.c_int64, P, P, P]
+    lib.ivrgs_l1_bwd.restype = C.c_int
     lib.ivrgs_reg_workspace_size.argtypes = [P]
     lib.ivrgs_reg_workspace_size.restype = C.c_size_t
     lib.ivrgs_reg_fwd.argtypes = [P, P, P, P, P, C.c_size_t, P]
@@ -347,6 +354,18 @@ def ivrgs_photometric_grad(x_ptr, y_ptr, channels: int, height: int, width: int,
                            ws_ptr, ws_bytes, stream):
     check(load().ivrgs_photometric_grad(x_ptr, y_ptr, channels, height, width, lam, grad_x_ptr, ws_ptr,
                                         ws_bytes, stream), "ivrgs_photometric_grad")
+
+
+def ivrgs_l1_workspace_size(n: int) -> int:
+    return int(load().ivrgs_l1_workspace_size(n))
+
+
+def ivrgs_l1_fwd(x_ptr, y_ptr, n: int, out_ptr, ws_ptr, ws_bytes, stream):
+    check(load().ivrgs_l1_fwd(x_ptr, y_ptr, n, out_ptr, ws_ptr, ws_bytes, stream), "ivrgs_l1_fwd")
+
+
+def ivrgs_l1_bwd(x_ptr, y_ptr, n: int, grad_mean_ptr, grad_x_ptr, stream):
+    check(load().ivrgs_l1_bwd(x_ptr, y_ptr, n, grad_mean_ptr, grad_x_ptr, stream), "ivrgs_l1_bwd")
 
 
 def ivrgs_reg_workspace_size(maps) -> int:

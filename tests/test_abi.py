@@ -80,7 +80,7 @@ def test_host_validation(lib):
 
 
 def test_host_validation_of_ssim_and_error_query(lib):
-    """The SSIM entry points and the device-error query check their
+    """The SSIM and L1 entry points and the device-error query check their
     arguments on the host: no device pointer is touched."""
     # workspace: 3 floats per valid window and channel plus one partial per 16x16 tile of windows
     assert N.ivrgs_ssim_workspace_size(4, 800, 800) == 4 * (3 * 4 * 790 * 790 + 4 * 50 * 50)
@@ -96,6 +96,17 @@ def test_host_validation_of_ssim_and_error_query(lib):
     assert lib.ivrgs_ssim_bwd(fake, fake, 1, 20, 20, None, fake, fake, 1 << 20, None) == N.E_INVALID
     assert lib.ivrgs_ssim_bwd(fake, fake, 1, 20, 5, fake, fake, fake, 1 << 20, None) == N.E_SHAPE
     assert lib.ivrgs_ssim_bwd(fake, fake, 1, 20, 20, fake, fake, fake, 16, None) == N.E_CAPACITY
+    # the L1 term: one FP64 partial per workgroup slice of at least 4096 values, at most 1024
+    assert N.ivrgs_l1_workspace_size(1) == 8
+    assert N.ivrgs_l1_workspace_size(4096 * 3 + 1) == 8 * 4
+    assert N.ivrgs_l1_workspace_size(10 ** 9) == 8 * 1024
+    assert N.ivrgs_l1_workspace_size(0) == 0 and N.ivrgs_l1_workspace_size(-5) == 0
+    assert lib.ivrgs_l1_fwd(None, fake, 10, fake, fake, 1 << 20, None) == N.E_INVALID
+    assert lib.ivrgs_l1_fwd(fake, fake, 10, None, fake, 1 << 20, None) == N.E_INVALID
+    assert lib.ivrgs_l1_fwd(fake, fake, 0, fake, fake, 1 << 20, None) == N.E_SHAPE
+    assert lib.ivrgs_l1_fwd(fake, fake, 10 ** 6, fake, fake, 8, None) == N.E_CAPACITY
+    assert lib.ivrgs_l1_bwd(fake, fake, 10, None, fake, None) == N.E_INVALID
+    assert lib.ivrgs_l1_bwd(fake, fake, -1, fake, fake, None) == N.E_SHAPE
     out = C.c_int64(0)
     assert lib.ivrgs_get_error(None, None, C.cast(C.byref(out), P), None) == N.E_INVALID
     bins = N.ivrgs_bins(0, 0, 0, 0)  # no status word

@@ -581,3 +581,25 @@ def test_fp32_error_model_covers_an_fp32_evaluation(log_mu, sigma, width, lowpas
         ok = (a64 > 1e-30) & (a32 > 0)  # FP32 underflow far out in the tail is no decision
         worst = max(worst, float((np.abs(np.log(a32[ok]) - np.log(a64[ok])) / bound[ok]).max()))
     assert worst <= 1.0, worst
+
+
+def test_l1_loss_closed_forms():
+    """The L1 term: |c| for a constant offset c, the mean of a hand-summed
+    pattern, 0 for equal inputs; its gradient is the central difference of
+    the loss away from ties, and 0 at a tie."""
+    rng = np.random.default_rng(5)
+    y = rng.uniform(0, 1, (4, 6, 5))
+    assert O.l1_loss(y - 0.25, y) == pytest.approx(0.25, rel=1e-12)
+    assert O.l1_loss(y, y) == 0.0
+    x = np.array([1.0, -2.0, 3.5, 0.0])
+    assert O.l1_loss(x, np.zeros(4)) == pytest.approx((1.0 + 2.0 + 3.5) / 4, rel=1e-15)
+    x = rng.uniform(0, 1, (2, 3, 4))
+    g = O.l1_loss_grad(x, y[:2, :3, :4])
+    h = 1e-7
+    for i in range(x.size):
+        e = np.zeros(x.size)
+        e[i] = h
+        e = e.reshape(x.shape)
+        fd = (O.l1_loss(x + e, y[:2, :3, :4]) - O.l1_loss(x - e, y[:2, :3, :4])) / (2 * h)
+        assert fd == pytest.approx(g.flat[i], rel=1e-6)
+    assert O.l1_loss_grad(np.ones(3), np.ones(3)).tolist() == [0.0, 0.0, 0.0]
