@@ -607,14 +607,78 @@ __global__ __launch_bounds__(1024) void k_scan_sb(const uint32_t *__restrict__ l
     }
 }
 
+// The tiles of one tile row that a record's footprint reaches, as one
+// interval.  The footprint E = {q(d) >= tol}, q(d) = qa dx^2 + qb dx dy +
+// qc dy^2 (negative definite, log2 units) and tol the cutoff with the box
+// test's margin, is convex, so the pixel centres of a row band
+// Y0 <= dy <= Y1 that it reaches span one interval [L, R] in dx: the
+// projection of E and the band onto x.  With det4 = 4 qa qc - qb^2 > 0 the
+// extreme points of E in x are (-Xe, yL) and (Xe, -yL), Xe^2 = 4 qc tol /
+// det4, yL = qb Xe / (2 qc); if the band holds yL then L = -Xe, else L is
+// the smaller root in x of q(x, y) = tol at the band edge nearest yL,
+// (sqrt(4 qa tol - det4 y^2) - qb y) / (2 qa), and R likewise.  The band
+// and the interval are widened by (1e-4 + 2e-7 kappa) of the footprint's
+// half-extent plus 0.05 pixel, kappa = 4 qa qc / det4 >= 1: several times
+// the FP32 error of these formulas, which grows with kappa through det4,
+// for the footprints they are used on (kappa below 1e5); any other record
+// (a degenerate or extremely elongated form) reaches its whole rect row.
+// The result is a superset of the tiles whose pixels can reach the cutoff,
+// which is all the lists need.
+struct RowIv {
+    float mx, my, xe, yl;         // mean, half-extent in x (+inf: whole rows), y of the leftmost point
+    float det4, a4, inv2qa, qb;   // 4 qa qc - qb^2, 4 qa tol, 1 / (2 qa), qb
+    float marg;                   // widening of the band and the interval
+};
+
+__device__ __forceinline__ RowIv make_row_iv(float4 r0, float qc, float cut) {
+    RowIv v;
+    v.mx = r0.x;
+    v.my = r0.y;
+    const float qa = r0.z, qb = r0.w;
+    const float tol = cut - 1.0e-3f * (1.f + fabsf(cut));
+    const float det4 = 4.f * qa * qc - qb * qb;
+    const float a4 = 4.f * qa * tol;
+    const float xe = sqrtf(4.f * qc * tol / det4), ye = sqrtf(a4 / det4);
+    const bool ok = qa < 0.f && qc < 0.f && tol < 0.f && det4 > 1.0e-5f * (4.f * qa * qc) && xe < 1.0e30f &&
+                    ye < 1.0e30f;
+    v.xe = ok ? xe : INFINITY;
+    v.yl = ok ? qb * xe / (2.f * qc) : 0.f;
+    v.det4 = ok ? det4 : 0.f;
+    v.a4 = ok ? a4 : INFINITY;
+    v.inv2qa = ok ? 0.5f / qa : -1.f;
+    v.qb = ok ? qb : 0.f;
+    const float kappa = 4.f * qa * qc / det4;  // >= 1; the FP32 error of det4 grows with it
+    v.marg = ok ? fmaf(fmaf(2.0e-7f, kappa, 1.0e-4f), fmaxf(xe, ye), 0.05f) : 0.f;
+    return v;
+}
+
+// Tiles [lo, hi] of tile row ty that the record reaches (lo > hi: none),
+// within the rect columns [x0, x1).
+__device__ __forceinline__ void row_tiles(const float4 a, const float4 c, float marg, int ty, int x0, int x1,
+                                          int &lo, int &hi) {
+    const float mx = a.x, my = a.y, xe = a.z, yl = a.w;
+    const float det4 = c.x, a4 = c.y, inv2qa = c.z, qb = c.w;
+    const float Y0 = (float)(ty * kTile) + 0.5f - my - marg, Y1 = Y0 + (float)(kTile - 1) + 2.f * marg;
+    const float ya = fminf(fmaxf(yl, Y0), Y1), yb = fminf(fmaxf(-yl, Y0), Y1);
+    const float da = fmaf(-det4 * ya, ya, a4), db = fmaf(-det4 * yb, yb, a4);
+    const float L = ya == yl ? -xe : (sqrtf(fmaxf(da, 0.f)) - qb * ya) * inv2qa;
+    const float R = yb == -yl ? xe : (-sqrtf(fmaxf(db, 0.f)) - qb * yb) * inv2qa;
+    const bool meets = (da >= 0.f) & (db >= 0.f);
+    // tile t holds the pixel centres [16 t + 0.5, 16 t + 15.5] - mx
+    const float flo = ceilf((L - marg + mx - (float)(kTile - 1) - 0.5f) * (1.f / kTile));
+    const float fhi = floorf((R + marg + mx - 0.5f) * (1.f / kTile));
+    lo = (int)fmaxf(flo, (float)x0);
+    hi = meets ? (int)fminf(fhi, (float)(x1 - 1)) : lo - 1;
+}
+
 // Per-wave LDS of the level-1 scatter: the records of one group (at most
-// 64, in depth order) and their item and entry offsets.
+// 64, in depth order) and their row-item and entry offsets.
 struct SbLds {
-    float4 h0[64], h1[64];  // hit tests
-    uint32_t off[64];       // exclusive prefix of rect areas (tile items)
+    float4 h0[64], h1[64];  // row intervals: (mx, my, Xe, yL), (det4, 4 qa tol, 1 / (2 qa), qb)
+    float marg[64];         // their widening
+    uint32_t off[64];       // exclusive prefix of rect heights (row items)
     uint32_t org[64];       // rect origin, x0 | y0 << 16
-    uint32_t wid[64];       // rect width in tiles
-    float iwid[64];         // 1 / wid
+    uint32_t xend[64];      // rect end column x1
     uint32_t rid[64];       // record index
     uint32_t eoff[64];      // exclusive prefix of block overlaps (entries)
     uint32_t borg[64];      // first block, bx0 | by0 << 16
@@ -649,10 +713,11 @@ __device__ __forceinline__ int window_record(SbLds &L, const uint32_t *off, bool
 }
 
 // Level-1 scatter: one chunk per wave.  Records are taken in groups of up to
-// 64 whose block overlaps fit the wave's entry slots; the group's tile items
-// are spread evenly over the lanes (64 at a time, record-major), each item's
-// ellipse-box test sets its tile's bit in the entry of (record, block) with
-// an LDS OR; then the entries, 64 at a time in (record, block) order, are
+// 64 whose block overlaps fit the wave's entry slots; the group's row items
+// (record, tile row of its rect) are spread evenly over the lanes (64 at a
+// time, record-major), each sets the bits of the row's reached tiles
+// (row_tiles) in the entries of (record, block) with LDS ORs; then the
+// entries, 64 at a time in (record, block) order, are
 // appended to their blocks' lists from the wave's cursors (lanes appending
 // to one block hold different records, ranked by lane).  Entries are
 // (record id, block | tile mask << 16).
@@ -692,7 +757,7 @@ __global__ __launch_bounds__(kBinWaves * 64) void k_sb_scatter(ivrgs_batch b, Sb
         // the group's records and their item and entry counts
         const int l = g0 + lane;
         uint32_t n_it = 0, n_en = 0;
-        HitTest h = {};
+        RowIv h = {};
         int x0 = 0, y0 = 0, x1 = 0, y1 = 0, bx0 = 0, by0 = 0, bcols = 1;
         uint32_t r = 0;
         if (l < qe) {
@@ -701,12 +766,12 @@ __global__ __launch_bounds__(kBinWaves * 64) void k_sb_scatter(ivrgs_batch b, Sb
             load_bin_record<kPayRead>(job, l, order, const_cast<uint4 *>(pay), rec4, r, rc, r0, r1, r2);
             if (rc.x | rc.y) {
                 unpack_rect(rc, x0, y0, x1, y1);
-                n_it = (uint32_t)((x1 - x0) * (y1 - y0));
+                n_it = (uint32_t)(y1 - y0);
                 bx0 = x0 / kSbEdge;
                 by0 = y0 / kSbEdge;
                 bcols = (x1 - 1) / kSbEdge - bx0 + 1;
                 n_en = (uint32_t)(bcols * ((y1 - 1) / kSbEdge - by0 + 1));
-                h = make_hit_test(r0, r1, r2);
+                h = make_row_iv(r0, r1.x, r2.z);
             }
         }
         // the longest prefix of records whose entries fit the slots (the
@@ -722,12 +787,12 @@ __global__ __launch_bounds__(kBinWaves * 64) void k_sb_scatter(ivrgs_batch b, Sb
         const uint32_t i_off = i_incl - n_it;
         const uint32_t n_items = __builtin_amdgcn_readlane(i_incl, 63);
         wave_lds_sync();  // the previous group's tables are no longer read
-        L.h0[lane] = make_float4(h.mx, h.my, h.qa, h.qb);
-        L.h1[lane] = make_float4(h.qc, h.i2qa, h.i2qc, h.tol);
+        L.h0[lane] = make_float4(h.mx, h.my, h.xe, h.yl);
+        L.h1[lane] = make_float4(h.det4, h.a4, h.inv2qa, h.qb);
+        L.marg[lane] = h.marg;
         L.off[lane] = i_off;
         L.org[lane] = (uint32_t)x0 | ((uint32_t)y0 << 16);
-        L.wid[lane] = (uint32_t)max(x1 - x0, 1);
-        L.iwid[lane] = __builtin_amdgcn_rcpf((float)max(x1 - x0, 1));
+        L.xend[lane] = (uint32_t)x1;
         L.rid[lane] = r;
         L.eoff[lane] = e_off;
         L.borg[lane] = (uint32_t)bx0 | ((uint32_t)by0 << 16);
@@ -735,24 +800,23 @@ __global__ __launch_bounds__(kBinWaves * 64) void k_sb_scatter(ivrgs_batch b, Sb
         L.ibcol[lane] = __builtin_amdgcn_rcpf((float)bcols);
         for (uint32_t e = lane; e < n_ent; e += 64) emask[e] = 0u;
         wave_lds_sync();
-        // tile items: ellipse-box test, bit into the (record, block) entry
+        // row items: the row's reached tiles, bits into the (record, block)
+        // entries they fall in
         int carry = 0;
         for (uint32_t base = 0; base < n_items; base += 64) {
             const int j = window_record(L, L.off, n_it != 0u, i_off, base, lane, carry);
             const uint32_t idx = base + lane;
             if (idx < n_items) {
-                const uint32_t offj = L.off[j], w = L.wid[j], o = L.org[j];
-                const float iw = L.iwid[j];
-                const float4 a = L.h0[j], c = L.h1[j];
+                const uint32_t o = L.org[j];
+                const int ty = (int)((o >> 16) + (idx - L.off[j]));
+                int lo, hi;
+                row_tiles(L.h0[j], L.h1[j], L.marg[j], ty, (int)(o & 0xFFFFu), (int)L.xend[j], lo, hi);
                 const uint32_t eoj = L.eoff[j], bo = L.borg[j], bc = L.bcol[j];
-                const uint32_t t = idx - offj;
-                const uint32_t dy = div_small(t, w, iw), dx = t - dy * w;
-                const int x = (int)((o & 0xFFFFu) + dx), y = (int)((o >> 16) + dy);
-                const HitTest hh = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
-                if (box_hit(hh, x * kTile, y * kTile, kTile, kTile)) {
-                    const uint32_t e = eoj + (uint32_t)(y / kSbEdge - (int)(bo >> 16)) * bc +
-                                       (uint32_t)(x / kSbEdge - (int)(bo & 0xFFFFu));
-                    atomicOr(&emask[e], 1u << ((y % kSbEdge) * kSbEdge + (x % kSbEdge)));
+                const uint32_t erow = eoj + (uint32_t)(ty / kSbEdge - (int)(bo >> 16)) * bc;
+                const int shift = (ty % kSbEdge) * kSbEdge;
+                for (int bx = lo / kSbEdge; bx <= hi / kSbEdge && lo <= hi; ++bx) {
+                    const int c0 = max(lo, bx * kSbEdge) - bx * kSbEdge, c1 = min(hi, bx * kSbEdge + 3) - bx * kSbEdge;
+                    atomicOr(&emask[erow + (uint32_t)(bx - (int)(bo & 0xFFFFu))], ((2u << c1) - (1u << c0)) << shift);
                 }
             }
         }
