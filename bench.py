@@ -19,6 +19,7 @@ and the CPU oracle timed on a bounded sample of the same step.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import gc
 import json
 import os
@@ -109,6 +110,8 @@ def parse():
     ap.add_argument("--views", type=int, default=100)
     ap.add_argument("--fwd-px", type=int, default=0)
     ap.add_argument("--bwd-px", type=int, default=0)
+    ap.add_argument("--sort-chunk", type=int, default=0,
+                    help="records per binning chunk with --fwd-px/--bwd-px (0: the library's choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -180,7 +183,7 @@ def main():
     g = torch.Generator(device=dev)
     g.manual_seed(I.SEED_TARGET + 2)
     targets = torch.rand((args.views, 1, 4, H, W), generator=g, device=dev)
-    settings = R.Settings(W, H, fwd_px=args.fwd_px, bwd_px=args.bwd_px)
+    settings = R.Settings(W, H, fwd_px=args.fwd_px, bwd_px=args.bwd_px, sort_chunk=args.sort_chunk)
     rnd = R.Renderer(settings, capacity=1 << 24, check="sync")
 
     # pair capacity from a pass over every view (sync mode grows it)
@@ -193,7 +196,7 @@ def main():
     rnd.check = "defer"
     for k in R.PLANES:
         composed[k].requires_grad_(True)
-    tuned = {"fwd_px": args.fwd_px, "bwd_px": args.bwd_px}
+    tuned = {"fwd_px": args.fwd_px, "bwd_px": args.bwd_px, "sort_chunk": args.sort_chunk}
     if not (args.fwd_px or args.bwd_px):
         # launch shape (results do not depend on it): pixels per lane, records
         # per binning chunk, persistent render kernels; each candidate timed
@@ -834,6 +837,19 @@ def secondary_culler(dev):
 
     render_plain = lambda v: plain.forward(planes, te_t, jobs_p[v], edits_t=edits, out=out, fwd_only=True)
     render_cull = lambda v: culler.render(culled, planes, te_t, jobs_c[v], v, out=out)
+    # records per binning chunk (a launch shape; results do not depend on
+    # it), chosen for each pipeline on its own eager renders
+    chunks = {}
+    for name, rnd_, fn in (("plain", plain, render_plain), ("culled", culled, render_cull)):
+        base = rnd_.settings
+        best = None
+        for c in (0, 64, 128, 256):
+            rnd_.settings = dataclasses.replace(base, sort_chunk=c)
+            t = timed(fn)
+            if best is None or t < best[1]:
+                best = (c, t)
+        rnd_.settings = dataclasses.replace(base, sort_chunk=best[0])
+        chunks[name] = best[0]
     e_plain, e_cull = timed(render_plain), timed(render_cull)
     t_plain, t_cull = graphed(render_plain), graphed(render_cull)
     plain.verify()
@@ -842,11 +858,12 @@ def secondary_culler(dev):
     last = views[-1]
     assert torch.equal(out, got[last]), "graph replay differs from the eager culled render"
     qmin = float(np.min(q))
+    log(f"culler: records per binning chunk {chunks}")
     log(f"culler: plain {t_plain * 1e3:.3f} ms, culled {t_cull * 1e3:.3f} ms per view (graphs); eager "
         f"{e_plain * 1e3:.3f} / {e_cull * 1e3:.3f} ms; kept {kept:.3f}, PSNR mean {np.mean(q):.2f} min {qmin:.2f}")
     return {"workload": f"cull-isosurface-{n}-{W}px-60views-fwd", "speedup": round(t_plain / t_cull, 3),
             "plain_ms": round(t_plain * 1e3, 4), "culled_ms": round(t_cull * 1e3, 4),
-            "timing": "per-view HIP graphs replayed back to back",
+            "timing": "per-view HIP graphs replayed back to back", "sort_chunk": chunks,
             "eager_plain_ms": round(e_plain * 1e3, 4), "eager_culled_ms": round(e_cull * 1e3, 4),
             "kept_fraction": round(kept, 4), "visible_fraction_train": round(labels.float().mean().item(), 4),
             "psnr_mean_db": round(float(np.mean(q)), 2), "psnr_min_db": round(qmin, 2),

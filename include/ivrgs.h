@@ -381,7 +381,8 @@ int32_t ivrgs_timing_read(double *ms, int64_t *launches);
  * the features (mean 3, log_scale 3, opacity 1, unit direction from the
  * Gaussian to the camera centre 3, then 6 zeros); any input normalisation is
  * folded into w1/b1.  w1 [64][16] and w2 [64][64] hold BF16 bit patterns
- * (row = output unit); b1, b2, w3 [64] and b3 are FP32.  A Gaussian is kept
+ * (row = output unit; both 8-byte aligned, IVRGS_E_INVALID otherwise); b1,
+ * b2, w3 [64] and b3 are FP32.  A Gaussian is kept
  * when its logit >= threshold. */
 typedef struct {
     const uint16_t *w1;

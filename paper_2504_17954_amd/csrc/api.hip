@@ -797,6 +797,7 @@ ivrgs_status ivrgs_cull(const ivrgs_gaussians *g, const ivrgs_camera *cameras, i
                         float *out_logit, void *workspace, size_t workspace_bytes, void *stream) {
     if (!g || !valid_gauss(*g) || !cameras || camera < 0 || !mlp || !jobs || job < 0) return IVRGS_E_INVALID;
     if (!mlp->w1 || !mlp->b1 || !mlp->w2 || !mlp->b2 || !mlp->w3) return IVRGS_E_INVALID;
+    if ((reinterpret_cast<uintptr_t>(mlp->w1) | reinterpret_cast<uintptr_t>(mlp->w2)) & 7u) return IVRGS_E_INVALID;
     if (g->n > 0 && !out_index) return IVRGS_E_INVALID;
     if (g->n >= (int64_t)0x7FFFFFFF) return IVRGS_E_SHAPE;
     const size_t need = cull_workspace_bytes(g->n);

@@ -86,11 +86,23 @@ __device__ __forceinline__ uint32_t wave_prefix_sum(uint32_t u) {
 // ---------------------------------------------------------------------------
 // Depth order.
 constexpr int kSegThreads = 256;
-constexpr int kSegItems = 16;                         // per thread
-constexpr int kSeg = kSegThreads * kSegItems;         // records per segment
-constexpr int kSegWaveItems = kSeg / (kSegThreads / 64);  // contiguous per wave
+// Keys per thread (kItems) of the depth sort's segments: 16, segments of
+// 4096 keys, for large jobs; 4, segments of 1024, for jobs of at most
+// kSmallSegJob records, where four times the workgroups hide more of each
+// one's load and LDS latency (at a million records the longer column scans
+// over the segments cost more than that gains).
+constexpr int64_t kSmallSegJob = int64_t(1) << 19;
+template <int kItems>
+struct Seg {
+    static constexpr int kSeg = kSegThreads * kItems;               // records per segment
+    static constexpr int kWaveItems = kSeg / (kSegThreads / 64);   // contiguous per wave
+};
+int seg_items(const ivrgs_batch &b) { return b.max_job_count <= kSmallSegJob ? 4 : 16; }
 
-int seg_rows(const ivrgs_batch &b) { return (b.max_job_count + kSeg - 1) / kSeg; }
+int seg_rows(const ivrgs_batch &b) {
+    const int seg = kSegThreads * seg_items(b);
+    return (b.max_job_count + seg - 1) / seg;
+}
 
 // AND and OR of the depth keys of each job's visible records (rng[j] and
 // rng[n_jobs + j], preset to ~0 and 0).  Culled records carry the key ~0.
@@ -98,26 +110,27 @@ __global__ void k_rng_init(uint32_t *__restrict__ rng, int n_jobs) {
     for (int i = threadIdx.x; i < 2 * n_jobs; i += blockDim.x) rng[i] = i < n_jobs ? 0xFFFFFFFFu : 0u;
 }
 
-// One workgroup per segment of kSeg keys, kSegItems loads per thread issued
+// One workgroup per segment of Seg<kItems>::kSeg keys, kItems loads per thread issued
 // together; the four waves combine in LDS so each workgroup adds one AND and
 // one OR (same-address atomics serialise in L2: one pair per segment).
+template <int kItems>
 __global__ __launch_bounds__(kSegThreads) void k_dkey_range(ivrgs_batch b, const uint32_t *__restrict__ depth,
                                                             uint32_t *__restrict__ rng) {
     __shared__ uint32_t sa[kSegThreads / 64], so[kSegThreads / 64];
     const ivrgs_job job = b.jobs[blockIdx.y];
-    const int64_t base = (int64_t)blockIdx.x * kSeg;
+    const int64_t base = (int64_t)blockIdx.x * Seg<kItems>::kSeg;
     if (base >= job.gauss_count) return;
-    const int n = (int)min((int64_t)kSeg, job.gauss_count - base);
+    const int n = (int)min((int64_t)Seg<kItems>::kSeg, job.gauss_count - base);
     const uint32_t *z = depth + job.rec_begin + base;
     uint32_t a = 0xFFFFFFFFu, o = 0u;
-    uint32_t v[kSegItems];
+    uint32_t v[kItems];
 #pragma unroll
-    for (int u = 0; u < kSegItems; ++u) {
+    for (int u = 0; u < kItems; ++u) {
         const int i = u * kSegThreads + threadIdx.x;
         v[u] = i < n ? z[i] : 0xFFFFFFFFu;
     }
 #pragma unroll
-    for (int u = 0; u < kSegItems; ++u)
+    for (int u = 0; u < kItems; ++u)
         if (v[u] != 0xFFFFFFFFu) {
             a &= v[u];
             o |= v[u];
@@ -165,6 +178,7 @@ __device__ __forceinline__ const uint32_t *depth_order(const uint32_t *rng, int 
 }
 
 // Per (job, segment): digit histogram into hist[job][digit][segment].
+template <int kItems>
 __global__ __launch_bounds__(kSegThreads) void k_dsort_hist(ivrgs_batch b, const uint32_t *__restrict__ depth,
                                                             const uint32_t *__restrict__ key0,
                                                             const uint32_t *__restrict__ key1,
@@ -172,21 +186,21 @@ __global__ __launch_bounds__(kSegThreads) void k_dsort_hist(ivrgs_batch b, const
                                                             uint32_t *__restrict__ hist, int n_seg) {
     __shared__ uint32_t h[256];
     const ivrgs_job job = b.jobs[blockIdx.y];
-    const int64_t base = (int64_t)blockIdx.x * kSeg;
+    const int64_t base = (int64_t)blockIdx.x * Seg<kItems>::kSeg;
     if (base >= job.gauss_count || !digit_varies(rng, b.n_jobs, blockIdx.y, shift)) return;
     h[threadIdx.x] = 0;
     __syncthreads();
     const int before = passes_before(rng, b.n_jobs, blockIdx.y, shift);
     const uint32_t *k = (before == 0 ? depth : ((before - 1) & 1 ? key1 : key0)) + job.rec_begin + base;
-    const int n = (int)min((int64_t)kSeg, job.gauss_count - base);
-    uint32_t v[kSegItems];
+    const int n = (int)min((int64_t)Seg<kItems>::kSeg, job.gauss_count - base);
+    uint32_t v[kItems];
 #pragma unroll
-    for (int u = 0; u < kSegItems; ++u) {
+    for (int u = 0; u < kItems; ++u) {
         const int i = u * kSegThreads + threadIdx.x;
         v[u] = i < n ? k[i] : 0u;
     }
 #pragma unroll
-    for (int u = 0; u < kSegItems; ++u)
+    for (int u = 0; u < kItems; ++u)
         if (u * kSegThreads + (int)threadIdx.x < n) atomicAdd(&h[(v[u] >> shift) & 255u], 1u);
     __syncthreads();
     hist[((int64_t)blockIdx.y * 256 + threadIdx.x) * n_seg + blockIdx.x] = h[threadIdx.x];
@@ -218,13 +232,14 @@ __device__ uint64_t block_exclusive_scan_1024(uint64_t v, uint64_t *tmp /* >= 16
 // tot[job][digit].  The counts of up to kColBlock x 64 segments are loaded
 // before any is scanned, so a column pays one load latency per block.
 constexpr int kColBlock = 16;
+template <int kItems>
 __global__ __launch_bounds__(256) void k_dsort_colscan(ivrgs_batch b, const uint32_t *__restrict__ rng, int shift,
                                                        uint32_t *__restrict__ hist, uint32_t *__restrict__ tot,
                                                        int n_seg) {
     const int d = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const ivrgs_job job = b.jobs[blockIdx.y];
-    const int rows = (job.gauss_count + kSeg - 1) / kSeg;
+    const int rows = (job.gauss_count + Seg<kItems>::kSeg - 1) / Seg<kItems>::kSeg;
     if (rows == 0 || !digit_varies(rng, b.n_jobs, blockIdx.y, shift)) return;
     uint32_t *col = hist + ((int64_t)blockIdx.y * 256 + d) * n_seg;
     uint32_t carry = 0;
@@ -248,10 +263,11 @@ __global__ __launch_bounds__(256) void k_dsort_colscan(ivrgs_batch b, const uint
 }
 
 // Per (job, segment): stable scatter of the segment's (key, id) pairs by
-// digit.  Wave w owns the contiguous part [w * kSegWaveItems, ...) of the
+// digit.  Wave w owns the contiguous part [w * Seg<kItems>::kWaveItems, ...) of the
 // segment and ranks equal digits by lane inside each step of 64, so the
 // order within a digit is the input order.  A digit that is constant over
 // the job leaves the pairs where they are (see passes_before).
+template <int kItems>
 __global__ __launch_bounds__(kSegThreads) void k_dsort_scatter(ivrgs_batch b, const uint32_t *__restrict__ depth,
                                                                uint32_t *__restrict__ key0,
                                                                uint32_t *__restrict__ val0,
@@ -263,9 +279,9 @@ __global__ __launch_bounds__(kSegThreads) void k_dsort_scatter(ivrgs_batch b, co
     __shared__ uint32_t wh[kSegThreads / 64][256];  // per wave: count, then start, per digit
     __shared__ uint32_t wsum[kSegThreads / 64];
     const ivrgs_job job = b.jobs[blockIdx.y];
-    const int64_t base = (int64_t)blockIdx.x * kSeg;
+    const int64_t base = (int64_t)blockIdx.x * Seg<kItems>::kSeg;
     if (base >= job.gauss_count) return;
-    const int n = (int)min((int64_t)kSeg, job.gauss_count - base);
+    const int n = (int)min((int64_t)Seg<kItems>::kSeg, job.gauss_count - base);
     const int64_t off = job.rec_begin + base;
     if (!digit_varies(rng, b.n_jobs, blockIdx.y, shift)) return;
     const int before = passes_before(rng, b.n_jobs, blockIdx.y, shift);
@@ -273,10 +289,10 @@ __global__ __launch_bounds__(kSegThreads) void k_dsort_scatter(ivrgs_batch b, co
     const uint32_t *sk = first ? depth : (to1 ? key0 : key1), *sv = to1 ? val0 : val1;
     uint32_t *dk = to1 ? key1 : key0, *dv = to1 ? val1 : val0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int w0 = wave * kSegWaveItems;
-    uint32_t kk[kSegItems], vv[kSegItems];
+    const int w0 = wave * Seg<kItems>::kWaveItems;
+    uint32_t kk[kItems], vv[kItems];
 #pragma unroll
-    for (int u = 0; u < kSegItems; ++u) {
+    for (int u = 0; u < kItems; ++u) {
         const int i = w0 + u * 64 + lane;
         kk[u] = i < n ? sk[off + i] : 0u;
         vv[u] = i < n ? (first ? (uint32_t)(off + i) : sv[off + i]) : 0u;
@@ -284,7 +300,7 @@ __global__ __launch_bounds__(kSegThreads) void k_dsort_scatter(ivrgs_batch b, co
     for (int d = lane; d < 256; d += 64) wh[wave][d] = 0;
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < kSegItems; ++u)
+    for (int u = 0; u < kItems; ++u)
         if (w0 + u * 64 + lane < n) atomicAdd(&wh[wave][(kk[u] >> shift) & 255u], 1u);
     __syncthreads();
     {
@@ -314,7 +330,7 @@ __global__ __launch_bounds__(kSegThreads) void k_dsort_scatter(ivrgs_batch b, co
     __syncthreads();
     uint32_t *dkj = dk + job.rec_begin, *dvj = dv + job.rec_begin;
 #pragma unroll
-    for (int u = 0; u < kSegItems; ++u) {
+    for (int u = 0; u < kItems; ++u) {
         if (w0 + u * 64 < n) {  // wave-uniform
             const bool act = w0 + u * 64 + lane < n;
             const uint32_t dg = (kk[u] >> shift) & 255u;
@@ -1025,6 +1041,23 @@ size_t col_part_words(const ivrgs_batch &b, int width, int chunk) {
 
 size_t depth_sort_hist_words(const ivrgs_batch &b) { return (size_t)b.n_jobs * 256 * ((size_t)seg_rows(b) + 1); }
 
+// Key range and the passes of the depth sort over varying digits (a pass
+// on a constant digit returns at once).
+template <int kItems>
+void launch_depth_sort(const ivrgs_batch &b, const uint32_t *depth, const BinWork &w, uint32_t *tot, int n_seg,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_dkey_range<kItems>, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, depth, w.rng);
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 8 * pass;
+        hipLaunchKernelGGL(k_dsort_hist<kItems>, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, depth, w.key[0],
+                           w.key[1], w.rng, shift, w.hist, n_seg);
+        hipLaunchKernelGGL(k_dsort_colscan<kItems>, dim3(64, b.n_jobs), dim3(256), 0, s, b, w.rng, shift, w.hist,
+                           tot, n_seg);
+        hipLaunchKernelGGL(k_dsort_scatter<kItems>, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, depth,
+                           w.key[0], w.val[0], w.key[1], w.val[1], w.rng, shift, w.hist, tot, n_seg);
+    }
+}
+
 hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *rec, const uint32_t *rect,
                            const uint32_t *depth, const ivrgs_bins &bins, const BinWork &w, int chunk,
                            size_t bin_lds, int cus, hipStream_t s) {
@@ -1038,16 +1071,10 @@ hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *r
     if (n_seg > 0) {
         TimedScope ts(TK_SORT, s);
         hipLaunchKernelGGL(k_rng_init, dim3(1), dim3(256), 0, s, w.rng, b.n_jobs);
-        hipLaunchKernelGGL(k_dkey_range, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, depth, w.rng);
-        for (int pass = 0; pass < 4; ++pass) {
-            const int shift = 8 * pass;
-            hipLaunchKernelGGL(k_dsort_hist, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, depth, w.key[0],
-                               w.key[1], w.rng, shift, w.hist, n_seg);
-            hipLaunchKernelGGL(k_dsort_colscan, dim3(64, b.n_jobs), dim3(256), 0, s, b, w.rng, shift, w.hist, tot,
-                               n_seg);
-            hipLaunchKernelGGL(k_dsort_scatter, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, depth, w.key[0],
-                               w.val[0], w.key[1], w.val[1], w.rng, shift, w.hist, tot, n_seg);
-        }
+        if (seg_items(b) == 4)
+            launch_depth_sort<4>(b, depth, w, tot, n_seg, s);
+        else
+            launch_depth_sort<16>(b, depth, w, tot, n_seg, s);
     }
     const SbGeom sg = sb_geom(k);
     const int64_t n_all = (int64_t)b.n_jobs * sg.n_sb;

@@ -37,12 +37,15 @@ __device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
     return v;
 }
 
+// Four consecutive BF16 weights in one 8-byte load (the weight arrays are
+// 8-byte aligned and every fragment starts at a multiple of 4 elements).
 __device__ __forceinline__ bf16x4 load4(const uint16_t *p) {
+    const uint2 u = *reinterpret_cast<const uint2 *>(p);
     bf16x4 v;
-    v[0] = (short)p[0];
-    v[1] = (short)p[1];
-    v[2] = (short)p[2];
-    v[3] = (short)p[3];
+    v[0] = (short)(u.x & 0xFFFFu);
+    v[1] = (short)(u.x >> 16);
+    v[2] = (short)(u.y & 0xFFFFu);
+    v[3] = (short)(u.y >> 16);
     return v;
 }
 
@@ -145,52 +148,39 @@ __global__ __launch_bounds__(kCullBlock) void k_cull_mlp(ivrgs_gaussians g, cons
     if (threadIdx.x == 0) block_count[blockIdx.x] = wave_cnt[0] + wave_cnt[1] + wave_cnt[2] + wave_cnt[3];
 }
 
-// Single workgroup: exclusive scan of the per-block counts (in place) and
-// the survivor total into the job table.
-__global__ __launch_bounds__(1024) void k_cull_scan(uint32_t *__restrict__ counts, int n_blocks,
-                                                    ivrgs_job *__restrict__ jobs, int job) {
-    __shared__ uint32_t tmp[16];
-    const int per = (n_blocks + blockDim.x - 1) / blockDim.x;
-    const int lo = threadIdx.x * per, hi = min(lo + per, n_blocks);
-    uint32_t sum = 0;
-    for (int i = lo; i < hi; ++i) sum += counts[i];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t incl = sum;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t o = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += o;
-    }
-    if (lane == 63) tmp[wave] = incl;
-    __syncthreads();
-    uint32_t off = 0, total = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-        if (w < wave) off += tmp[w];
-        total += tmp[w];
-    }
-    uint32_t run = off + incl - sum;
-    for (int i = lo; i < hi; ++i) {
-        const uint32_t c = counts[i];
-        counts[i] = run;
-        run += c;
-    }
-    if (threadIdx.x == 0) jobs[job].gauss_count = (int32_t)total;
-}
-
+// Ordered compaction: each workgroup sums the survivor counts of the blocks
+// before its own (at most a few thousand words, read by all its threads at
+// once) for its base; the last workgroup also writes the survivor total into
+// the job table.
 __global__ __launch_bounds__(kCullBlock) void k_cull_compact(const uint8_t *__restrict__ keep, int64_t n,
-                                                            const uint32_t *__restrict__ base,
+                                                            const uint32_t *__restrict__ counts, int n_blocks,
+                                                            ivrgs_job *__restrict__ jobs, int job,
                                                             int32_t *__restrict__ out_index) {
-    __shared__ uint32_t wave_off[4];
+    __shared__ uint32_t wave_before[4], wave_off[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t part = 0;
+    for (int i = threadIdx.x; i < (int)blockIdx.x; i += kCullBlock) part += counts[i];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) part += __shfl_xor(part, d, 64);
     const int64_t gi = (int64_t)blockIdx.x * kCullBlock + threadIdx.x;
     const bool k = gi < n && keep[gi];
     const uint64_t m = __ballot(k);
-    if (lane == 0) wave_off[wave] = (uint32_t)__popcll(m);
+    if (lane == 0) {
+        wave_before[wave] = part;
+        wave_off[wave] = (uint32_t)__popcll(m);
+    }
     __syncthreads();
-    uint32_t off = base[blockIdx.x];
+    const uint32_t before = wave_before[0] + wave_before[1] + wave_before[2] + wave_before[3];
+    if ((int)blockIdx.x == n_blocks - 1 && threadIdx.x == 0)
+        jobs[job].gauss_count = (int32_t)(before + wave_off[0] + wave_off[1] + wave_off[2] + wave_off[3]);
+    uint32_t off = before;
     for (int w = 0; w < wave; ++w) off += wave_off[w];
     const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
     if (k) out_index[off + below] = (int32_t)gi;
+}
+
+__global__ void k_cull_empty(ivrgs_job *__restrict__ jobs, int job) {
+    if (threadIdx.x == 0) jobs[job].gauss_count = 0;
 }
 
 hipError_t launch_cull(const ivrgs_gaussians &g, const ivrgs_camera *cams, int camera, const ivrgs_culler &mlp,
@@ -201,9 +191,11 @@ hipError_t launch_cull(const ivrgs_gaussians &g, const ivrgs_camera *cams, int c
     if (n_blocks > 0)
         hipLaunchKernelGGL(k_cull_mlp, dim3(n_blocks), dim3(kCullBlock), 0, s, g, cams, camera, mlp, keep, counts,
                            logits);
-    hipLaunchKernelGGL(k_cull_scan, dim3(1), dim3(1024), 0, s, counts, n_blocks, jobs, job);
     if (n_blocks > 0)
-        hipLaunchKernelGGL(k_cull_compact, dim3(n_blocks), dim3(kCullBlock), 0, s, keep, g.n, counts, out_index);
+        hipLaunchKernelGGL(k_cull_compact, dim3(n_blocks), dim3(kCullBlock), 0, s, keep, g.n, counts, n_blocks,
+                           jobs, job, out_index);
+    else
+        hipLaunchKernelGGL(k_cull_empty, dim3(1), dim3(64), 0, s, jobs, job);
     return hipGetLastError();
 }
 

@@ -113,3 +113,20 @@ def test_host_validation_of_ssim_and_error_query(lib):
     assert lib.ivrgs_get_error(N.ref(bins), None, C.cast(C.byref(out), P), None) == N.E_INVALID
     bins = N.ivrgs_bins(0, 0, 0, 256)
     assert lib.ivrgs_get_error(N.ref(bins), None, None, None) == N.E_INVALID
+
+
+def test_host_validation_of_cull(lib):
+    """ivrgs_cull rejects missing or misaligned weights on the host (the MLP
+    loads four BF16 weights at a time, 8-byte aligned)."""
+    P = C.c_void_p
+    g = N.ivrgs_gaussians(0, *([256] * (len(N.PLANES) + 1)))  # empty set, non-null planes never read
+    fake = P(256)  # non-null placeholder, never dereferenced: every call below fails its host checks
+    w = N.ivrgs_culler(256, 256, 256, 256, 256, 0.0, 0.0)
+    ws = N.ivrgs_cull_workspace_size(0)
+    for bad in ("w1", "w2"):
+        wb = N.ivrgs_culler.from_buffer_copy(w)
+        setattr(wb, bad, 258)  # 2-byte aligned only
+        assert lib.ivrgs_cull(N.ref(g), fake, 0, N.ref(wb), fake, fake, 0, None, fake, ws, None) == N.E_INVALID
+    wn = N.ivrgs_culler.from_buffer_copy(w)
+    wn.w3 = None
+    assert lib.ivrgs_cull(N.ref(g), fake, 0, N.ref(wn), fake, fake, 0, None, fake, ws, None) == N.E_INVALID

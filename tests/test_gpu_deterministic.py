@@ -46,9 +46,19 @@ def same_bits(a, b):
 
 
 def close(a, b, rel=1e-4):
+    """Agreement to rounding: 1e-4 relative, with a floor of 1e-5 of the
+    plane's largest entry (the absolute part of the oracle bar).  The
+    float-atomic path adds each record's per-wave sums in an order that
+    changes from run to run, and the projection backward combines them into
+    parameter gradients that can cancel to far below their terms, where that
+    rounding is a larger fraction of the entry."""
     for k in R.PLANES:
-        tol = rel * np.abs(b[k]) + 1e-6 * np.abs(b[k]).max() + 1e-30
-        bad = np.abs(a[k] - b[k]) > tol
+        tol = rel * np.abs(b[k]) + 1e-5 * np.abs(b[k]).max() + 1e-30
+        err = np.abs(a[k] - b[k])
+        bad = err > tol
+        if bad.any():
+            i = np.unravel_index(np.argmax(err / tol), err.shape)
+            say(f"  {k}: worst {i}: {a[k][i]:.6e} vs {b[k][i]:.6e} (max |b| {np.abs(b[k]).max():.3e})")
         assert not bad.any(), (k, int(bad.sum()))
 
 

@@ -609,10 +609,11 @@ def test_c3_fullsize_sampled(dev, c3_scene, view):
     check_image(img[:, pix[:, 1], pix[:, 0]].T, ref, f"c3 view {view} sampled")
 
 
-@pytest.mark.parametrize("n", [511, 512, 513, 4095, 4096, 4097, 8193])
+@pytest.mark.parametrize("n", [511, 512, 513, 1023, 1024, 1025, 4095, 4096, 4097, 8193, 600_001])
 def test_bin_sort_chunk_and_segment_boundaries(dev, n):
     """List lengths around the binning chunk (512 records), the wave step (64)
-    and the depth-sort segment (4096 records), all on one tile."""
+    and the depth-sort segment (1024 records up to 2^19 records per job,
+    4096 beyond: the last case), all on one tile."""
     say(f"bin_sort exact, {n} records on one tile")
     rng = np.random.default_rng(n)
     rects = np.tile(np.array([[0, 0, 1, 1]]), (n, 1))
