@@ -11,8 +11,9 @@
 // quadrant's live pixels are compacted, in list order, into the wave's LDS
 // slots, and each is read from there at one address for the whole wave.  No
 // workgroup barrier: a wave stops when its own pixels are done.  The
-// backward sums each composited record's values over the wave with one
-// reduce-scatter and adds them with one atomic per value.
+// backward visits the records a few at a time (their order-free work, then
+// the chain), sums the group's values over the wave with one reduce-scatter
+// and adds them with one atomic per value.
 #include "launch.hpp"
 
 namespace ivrgs {
@@ -20,7 +21,7 @@ namespace ivrgs {
 namespace {
 
 constexpr int kAuxAcc = 7 + kAuxMax;  // per-record sums of the backward: GO, GX, GY, GQA..GQC, depth, attributes
-static_assert(kAuxAcc <= 32, "one reduce-scatter of 32 values per record");
+static_assert(2 * kAuxAcc <= 64, "at least two records per reduce-scatter of 64 values");
 
 // Per-wave LDS: the compacted records of one step.
 constexpr int kAuxQuads = (kAuxMax + 3) / 4;  // float4s per attribute row
@@ -196,18 +197,27 @@ __global__ __launch_bounds__(kTilePix) void k_aux_fwd(ivrgs_batch b, Consts k, c
 // composited pair, with ga = g . (depth, attributes) of the record and the
 // prefix P = sum of w ga over the pairs up to this one, dL/dalpha =
 // T ga - (g . A - P) / (1 - alpha) (the maps carry no background); then the
-// same record-gradient moments as the image backward.  The wave reduces all
-// of a record's values in one reduce-scatter; lanes 2v add value v to the
-// record gradients (for the projection backward), the attribute gradients
-// or, for the depth, the mean gradient (depth = row 3 of R applied to the
-// mean, plus t).
+// same record-gradient moments as the image backward.  Records are visited
+// kG at a time (kN attributes: kG = min(4, 64 / (7 + kN)) records of 7 + kN
+// values fill one 64-value reduce-scatter): the order-free part (offset,
+// exponent, alpha, 1 / (1 - alpha), ga, the cutoff, alpha-min and cap tests)
+// of the group first, then the front-to-back chain, then one reduce-scatter
+// of the group's values; lane v adds value v % (7 + kN) of record v / (7 +
+// kN) to the record gradients (for the projection backward), the attribute
+// gradients or, for the depth, the mean gradient (depth = row 3 of R
+// applied to the mean, plus t).
+template <int kN>
 __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, const float4 *__restrict__ rec,
                                                       const uint32_t *__restrict__ starts,
                                                       const uint32_t *__restrict__ sorted, int64_t n_tiles,
-                                                      const float *__restrict__ attr, int n_attr,
+                                                      const float *__restrict__ attr,
                                                       const float *__restrict__ aux, const float *__restrict__ gaux,
                                                       float *__restrict__ grec, float *__restrict__ gattr,
                                                       float *__restrict__ gmean) {
+    constexpr int kNv = 1 + kN;                              // depth, attributes
+    constexpr int kVpr = 6 + kNv;                            // values per record
+    constexpr int kG = 64 / kVpr < 4 ? 64 / kVpr : 4;        // records per reduce-scatter
+    constexpr int kQ = (kN + 3) / 4;                         // float4s of an attribute row
     if (starts[n_tiles] == 0xFFFFFFFFu) return;
     __shared__ AuxSlots slots[kTilePix / 64];
     const int64_t tile = blockIdx.x;
@@ -220,29 +230,30 @@ __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, c
     const int x = sx + (lane & 7), y = sy + (lane >> 3);
     const bool inside = x < k.width && y < k.height;
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
-    const int nv = 1 + n_attr;
-    float g[1 + kAuxMax];
+    float g[kNv];
     float gA = 0.f;
     {
         const int64_t plane = (int64_t)k.width * k.height, pix = (int64_t)y * k.width + x;
-        const int64_t o = (int64_t)ji * nv * plane + pix;
+        const int64_t o = (int64_t)ji * kNv * plane + pix;
 #pragma unroll
-        for (int c = 0; c < 1 + kAuxMax; ++c) {
-            const bool on = inside && c < nv;
-            g[c] = on ? gaux[o + c * plane] : 0.f;
-            gA = fmaf(g[c], on ? aux[o + c * plane] : 0.f, gA);
+        for (int c = 0; c < kNv; ++c) {
+            g[c] = inside ? gaux[o + c * plane] : 0.f;
+            gA = fmaf(g[c], inside ? aux[o + c * plane] : 0.f, gA);
         }
     }
     bool any_g = false;
 #pragma unroll
-    for (int c = 0; c < 1 + kAuxMax; ++c) any_g |= g[c] != 0.f;
+    for (int c = 0; c < kNv; ++c) any_g |= g[c] != 0.f;
     const ivrgs_camera &cam = b.cameras[job.camera];
     float T = 1.f, gP = 0.f;
     bool alive = inside & any_g;
     const uint32_t start = starts[tile], end = starts[tile + 1];
-    const int vi = lane >> 1;
-    const bool my_slot = (lane & 1) == 0 && vi < 6 + nv;
-    AuxWalk W(b, job, rec, sorted, attr, n_attr, lane, end);
+    const bool my_slot = lane < kG * kVpr;
+    const int my_g = my_slot ? lane / kVpr : 0, my_v = lane % kVpr;
+    float acc[64];
+#pragma unroll
+    for (int q = kG * kVpr; q < 64; ++q) acc[q] = 0.f;  // never written
+    AuxWalk W(b, job, rec, sorted, attr, kN, lane, end);
     if (start < end) {
         W.load_ids(start);
         W.load_recs(start);
@@ -252,69 +263,93 @@ __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, c
         const uint64_t live = __ballot(alive);
         if (live == 0ull) break;
         const int cnt = W.step(base, alive_box(live, sx, sy), S);
-        for (int sl = 0; sl < cnt; ++sl) {
-            const float4 fa = S.f0[sl], fc = S.f1[sl];
-            const float dx = px - fa.x, dy = py - fa.y;
-            const float p2 = splat_exponent(fa.z, fa.w, fc.x, dx, dy);
-            const bool pass = alive & (p2 >= fc.w);
-            if (__ballot(pass) == 0ull) continue;  // wave-uniform: no live pixel reaches the cutoff
-            const float G = fast_exp2(p2);
-            const float raw = fc.y * G;
-            const float al = fminf(k.alpha_max, raw);
-            const float T0 = T;  // transmittance in front of this record
-            const float Tn = T * (1.f - al);
-            const bool use = pass & (al >= k.alpha_min);
-            const bool stop = use & (Tn < k.T_min);
-            const bool comp = use & !stop;
-            const float w = comp ? al * T : 0.f;
-            T = comp ? Tn : T;
-            alive = alive & !stop;
-            if (__ballot(comp) != 0ull) {  // wave-uniform: something to add
-                float ga = g[0] * fc.z;
+        uint64_t pm = cnt == 64 ? ~0ull : ((1ull << cnt) - 1ull);
+        while (pm) {
+            int src[kG];
+            bool valid[kG];
 #pragma unroll
-                for (int q = 0; q < kAuxQuads; ++q) {
-                    if (4 * q >= n_attr) break;
-                    const float4 a4 = S.sa[q][sl];
-                    ga = fmaf(g[1 + 4 * q], a4.x, ga);
-                    if (4 * q + 1 < kAuxMax) ga = fmaf(g[2 + 4 * q], a4.y, ga);
-                    if (4 * q + 2 < kAuxMax) ga = fmaf(g[3 + 4 * q], a4.z, ga);
-                    if (4 * q + 3 < kAuxMax) ga = fmaf(g[4 + 4 * q], a4.w, ga);
+            for (int gg = 0; gg < kG; ++gg) {
+                valid[gg] = pm != 0ull;  // wave-uniform
+                src[gg] = valid[gg] ? (int)__builtin_ctzll(pm) : src[0];
+                pm &= pm - 1;
+            }
+            // order-free part of the group
+            float dx[kG], dy[kG], G[kG], raw[kG], al[kG], om[kG], inv[kG], ga[kG];
+            bool use[kG], free_a[kG];
+#pragma unroll
+            for (int gg = 0; gg < kG; ++gg) {
+                const float4 fa = S.f0[src[gg]], fc = S.f1[src[gg]];
+                dx[gg] = px - fa.x;
+                dy[gg] = py - fa.y;
+                const float p2 = splat_exponent(fa.z, fa.w, fc.x, dx[gg], dy[gg]);
+                G[gg] = fast_exp2(p2);
+                raw[gg] = fc.y * G[gg];
+                al[gg] = fminf(k.alpha_max, raw[gg]);
+                om[gg] = 1.f - al[gg];
+                inv[gg] = __builtin_amdgcn_rcpf(om[gg]);
+                float d = g[0] * fc.z;
+#pragma unroll
+                for (int q = 0; q < kQ; ++q) {
+                    const float4 a4 = S.sa[q][src[gg]];
+                    d = fmaf(g[1 + 4 * q], a4.x, d);
+                    if (4 * q + 1 < kN) d = fmaf(g[2 + 4 * q], a4.y, d);
+                    if (4 * q + 2 < kN) d = fmaf(g[3 + 4 * q], a4.z, d);
+                    if (4 * q + 3 < kN) d = fmaf(g[4 + 4 * q], a4.w, d);
                 }
-                gP = fmaf(w, ga, gP);
-                const float dA = fmaf(-(gA - gP), __builtin_amdgcn_rcpf(1.f - al), T0 * ga);
+                ga[gg] = d;
+                // below the cutoff alpha < alpha_min is certain
+                use[gg] = valid[gg] & (p2 >= fc.w) & (al[gg] >= k.alpha_min);
                 // no gradient through alpha where the cap is active
-                const float dLdo = (comp & (raw <= k.alpha_max)) ? dA : 0.f;
-                const float dp = dLdo * raw;
-                float v32[32];
-                v32[0] = dLdo * G;  // GO
-                const float dpx = dp * dx, dpy = dp * dy;
-                v32[1] = dpx;       // GX
-                v32[2] = dpy;       // GY
-                v32[3] = dpx * dx;  // GQA
-                v32[4] = dpx * dy;  // GQB
-                v32[5] = dpy * dy;  // GQC
+                free_a[gg] = raw[gg] <= k.alpha_max;
+            }
+            // the front-to-back chain
+            bool any = false;
 #pragma unroll
-                for (int c = 0; c < 1 + kAuxMax; ++c) v32[6 + c] = c < nv ? w * g[c] : 0.f;  // depth, attributes
+            for (int gg = 0; gg < kG; ++gg) {
+                const float Tn = T * om[gg];
+                const bool stop = alive & use[gg] & (Tn < k.T_min);
+                const bool comp = alive & use[gg] & !stop;
+                const float w = comp ? al[gg] * T : 0.f;
+                gP = fmaf(w, ga[gg], gP);
+                const float dA = fmaf(gP - gA, inv[gg], T * ga[gg]);
+                const float dLdo = (comp & free_a[gg]) ? dA : 0.f;
+                const float dp = dLdo * raw[gg];
+                float *v = acc + gg * kVpr;
+                v[0] = dLdo * G[gg];  // GO
+                const float dpx = dp * dx[gg], dpy = dp * dy[gg];
+                v[1] = dpx;           // GX
+                v[2] = dpy;           // GY
+                v[3] = dpx * dx[gg];  // GQA
+                v[4] = dpx * dy[gg];  // GQB
+                v[5] = dpy * dy[gg];  // GQC
 #pragma unroll
-                for (int v = 7 + kAuxMax; v < 32; ++v) v32[v] = 0.f;
-                // lanes 2v, 2v + 1 hold the wave total of value v
-                const float tot = reduce_scatter32(v32);
+                for (int c = 0; c < kNv; ++c) v[6 + c] = w * g[c];  // depth, attributes
+                T = comp ? Tn : T;
+                alive = alive & !stop;
+                any = any | comp;
+            }
+            if (__ballot(any) != 0ull) {
+                const float tot = reduce_scatter64(acc);
+                // a record that composites nowhere has all sums exactly 0
                 if (my_slot && tot != 0.f) {
+                    int sl = src[0];
+#pragma unroll
+                    for (int gg = 1; gg < kG; ++gg) sl = my_g == gg ? src[gg] : sl;
                     const uint32_t r = S.rid[sl];
                     const int64_t gi = S.gid[sl];
-                    if (vi < 6) {
-                        const int row = vi == 0 ? GO : (vi == 1 ? GX : (vi == 2 ? GY : GQA + (vi - 3)));
+                    if (my_v < 6) {
+                        const int row = my_v == 0 ? GO : (my_v == 1 ? GX : (my_v == 2 ? GY : GQA + (my_v - 3)));
                         atomicAdd(&grec[(size_t)r * kGradStride + row], tot);
-                    } else if (vi == 6) {
+                    } else if (my_v == 6) {
                         atomicAdd(&gmean[gi], tot * cam.R[6]);
                         atomicAdd(&gmean[b.g.n + gi], tot * cam.R[7]);
                         atomicAdd(&gmean[2 * b.g.n + gi], tot * cam.R[8]);
                     } else {
-                        atomicAdd(&gattr[gi * attr_stride(n_attr) + (vi - 7)], tot);
+                        atomicAdd(&gattr[gi * attr_stride(kN) + (my_v - 7)], tot);
                     }
                 }
             }
-            if (__ballot(alive) == 0ull) break;
+            if (__ballot(alive) == 0ull) break;  // every pixel of the wave is done
         }
     }
 }
@@ -337,9 +372,20 @@ hipError_t launch_aux_bwd(const ivrgs_batch &b, const Consts &k, int64_t n_tiles
                           hipStream_t s) {
     if (n_tiles == 0) return hipSuccess;
     TimedScope ts(TK_AUX, s);
-    hipLaunchKernelGGL(k_aux_bwd, dim3((unsigned)n_tiles), dim3(kTilePix), 0, s, b, k,
-                       reinterpret_cast<const float4 *>(rec), starts, sorted, n_tiles, attr, n_attr, aux, grad_aux,
-                       grec, grad_attr, grad_mean);
+    const float4 *rec4 = reinterpret_cast<const float4 *>(rec);
+    switch (n_attr) {
+#define IVRGS_AUX_BWD(N)                                                                                       \
+    case N:                                                                                                    \
+        hipLaunchKernelGGL(k_aux_bwd<N>, dim3((unsigned)n_tiles), dim3(kTilePix), 0, s, b, k, rec4, starts, sorted, \
+                           n_tiles, attr, aux, grad_aux, grec, grad_attr, grad_mean);                          \
+        break;
+        IVRGS_AUX_BWD(0) IVRGS_AUX_BWD(1) IVRGS_AUX_BWD(2) IVRGS_AUX_BWD(3) IVRGS_AUX_BWD(4) IVRGS_AUX_BWD(5)
+        IVRGS_AUX_BWD(6) IVRGS_AUX_BWD(7) IVRGS_AUX_BWD(8) IVRGS_AUX_BWD(9) IVRGS_AUX_BWD(10) IVRGS_AUX_BWD(11)
+        IVRGS_AUX_BWD(12) IVRGS_AUX_BWD(13) IVRGS_AUX_BWD(14) IVRGS_AUX_BWD(15)
+#undef IVRGS_AUX_BWD
+        default:
+            return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

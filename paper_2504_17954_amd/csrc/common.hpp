@@ -219,4 +219,45 @@ __device__ __forceinline__ float reduce_scatter32(float v[32]) {
     return e + IVRGS_DPP(e, 0xB1);           // quad_perm [1,0,3,2], partner lane ^ 1
 }
 
+// The same butterfly over 64 values, one more level: lane l returns the
+// wave's total of v[l].
+__device__ __forceinline__ float reduce_scatter64(float v[64]) {
+    const int lane = lane_id();
+    float a[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[k]), __float_as_uint(v[k + 32]), false,
+                                                        false);
+        a[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    float b[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a[k]), __float_as_uint(a[k + 16]), false,
+                                                        false);
+        b[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    const bool hi3 = (lane >> 3) & 1, hi2 = (lane >> 2) & 1, hi1 = (lane >> 1) & 1, hi0 = lane & 1;
+    float c[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const float keep = hi3 ? b[k + 8] : b[k], send = hi3 ? b[k] : b[k + 8];
+        c[k] = keep + IVRGS_DPP(send, 0x128);  // row_ror:8, partner lane ^ 8
+    }
+    float d[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float keep = hi2 ? c[k + 4] : c[k], send = hi2 ? c[k] : c[k + 4];
+        d[k] = keep + IVRGS_DPP(send, 0x141);  // row_half_mirror, partner 7 - i
+    }
+    float e[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float keep = hi1 ? d[k + 2] : d[k], send = hi1 ? d[k] : d[k + 2];
+        e[k] = keep + IVRGS_DPP(send, 0x4E);  // quad_perm [2,3,0,1], partner lane ^ 2
+    }
+    const float keep = hi0 ? e[1] : e[0], send = hi0 ? e[0] : e[1];
+    return keep + IVRGS_DPP(send, 0xB1);  // quad_perm [1,0,3,2], partner lane ^ 1
+}
+
 }  // namespace ivrgs
