@@ -86,6 +86,7 @@ __device__ __forceinline__ uint32_t wave_prefix_sum(uint32_t u) {
 // ---------------------------------------------------------------------------
 // Depth order.
 constexpr int kSegThreads = 256;
+static_assert(kSegThreads == 256, "the depth sort's scans give every digit one thread");
 // Keys per thread (kItems) of the depth sort's segments: 16, segments of
 // 4096 keys, for large jobs; 4, segments of 1024, for jobs of at most
 // kSmallSegJob records, where four times the workgroups hide more of each
@@ -104,34 +105,18 @@ int seg_rows(const ivrgs_batch &b) {
     return (b.max_job_count + seg - 1) / seg;
 }
 
-// AND and OR of the depth keys of each job's visible records (rng[j] and
-// rng[n_jobs + j], preset to ~0 and 0).  Culled records carry the key ~0.
-__global__ void k_rng_init(uint32_t *__restrict__ rng, int n_jobs) {
-    for (int i = threadIdx.x; i < 2 * n_jobs; i += blockDim.x) rng[i] = i < n_jobs ? 0xFFFFFFFFu : 0u;
-}
-
-// One workgroup per segment of Seg<kItems>::kSeg keys, kItems loads per thread issued
-// together; the four waves combine in LDS so each workgroup adds one AND and
-// one OR (same-address atomics serialise in L2: one pair per segment).
+// The key range: the AND and the OR of each job's visible depth keys (rng[j]
+// and rng[n_jobs + j]; culled records carry the key ~0 and are left out).
+// A digit on which they agree is the same for every visible key.  The first
+// histogram pass also takes each segment's AND and OR (prng[j][segment] and
+// prng[n_jobs + j][segment]); the first column scan combines them.
 template <int kItems>
-__global__ __launch_bounds__(kSegThreads) void k_dkey_range(ivrgs_batch b, const uint32_t *__restrict__ depth,
-                                                            uint32_t *__restrict__ rng) {
-    __shared__ uint32_t sa[kSegThreads / 64], so[kSegThreads / 64];
-    const ivrgs_job job = b.jobs[blockIdx.y];
-    const int64_t base = (int64_t)blockIdx.x * Seg<kItems>::kSeg;
-    if (base >= job.gauss_count) return;
-    const int n = (int)min((int64_t)Seg<kItems>::kSeg, job.gauss_count - base);
-    const uint32_t *z = depth + job.rec_begin + base;
-    uint32_t a = 0xFFFFFFFFu, o = 0u;
-    uint32_t v[kItems];
-#pragma unroll
-    for (int u = 0; u < kItems; ++u) {
-        const int i = u * kSegThreads + threadIdx.x;
-        v[u] = i < n ? z[i] : 0xFFFFFFFFu;
-    }
+__device__ __forceinline__ void seg_range(const uint32_t (&v)[kItems], int n, uint32_t &a, uint32_t &o) {
+    a = 0xFFFFFFFFu;
+    o = 0u;
 #pragma unroll
     for (int u = 0; u < kItems; ++u)
-        if (v[u] != 0xFFFFFFFFu) {
+        if (u * kSegThreads + (int)threadIdx.x < n && v[u] != 0xFFFFFFFFu) {
             a &= v[u];
             o |= v[u];
         }
@@ -139,19 +124,6 @@ __global__ __launch_bounds__(kSegThreads) void k_dkey_range(ivrgs_batch b, const
     for (int d = 32; d >= 1; d >>= 1) {
         a &= __shfl_xor(a, d, 64);
         o |= __shfl_xor(o, d, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        sa[threadIdx.x >> 6] = a;
-        so[threadIdx.x >> 6] = o;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < kSegThreads / 64; ++w) {
-            a &= sa[w];
-            o |= so[w];
-        }
-        if (a != 0xFFFFFFFFu) atomicAnd(&rng[blockIdx.y], a);
-        if (o != 0u) atomicOr(&rng[b.n_jobs + blockIdx.y], o);
     }
 }
 
@@ -177,20 +149,25 @@ __device__ __forceinline__ const uint32_t *depth_order(const uint32_t *rng, int 
     return p == 0 ? nullptr : ((p - 1) & 1 ? val1 : val0);
 }
 
-// Per (job, segment): digit histogram into hist[job][digit][segment].
+// Per (job, segment): digit histogram into hist[job][digit][segment].  The
+// first pass (shift 0) runs before the key range is known: it counts every
+// segment and stores the segment's part of the range.
 template <int kItems>
 __global__ __launch_bounds__(kSegThreads) void k_dsort_hist(ivrgs_batch b, const uint32_t *__restrict__ depth,
                                                             const uint32_t *__restrict__ key0,
                                                             const uint32_t *__restrict__ key1,
                                                             const uint32_t *__restrict__ rng, int shift,
-                                                            uint32_t *__restrict__ hist, int n_seg) {
+                                                            uint32_t *__restrict__ hist, uint32_t *__restrict__ prng,
+                                                            int n_seg) {
     __shared__ uint32_t h[256];
+    __shared__ uint32_t sa[kSegThreads / 64], so[kSegThreads / 64];
     const ivrgs_job job = b.jobs[blockIdx.y];
     const int64_t base = (int64_t)blockIdx.x * Seg<kItems>::kSeg;
-    if (base >= job.gauss_count || !digit_varies(rng, b.n_jobs, blockIdx.y, shift)) return;
+    const bool first = shift == 0;
+    if (base >= job.gauss_count || (!first && !digit_varies(rng, b.n_jobs, blockIdx.y, shift))) return;
     h[threadIdx.x] = 0;
     __syncthreads();
-    const int before = passes_before(rng, b.n_jobs, blockIdx.y, shift);
+    const int before = first ? 0 : passes_before(rng, b.n_jobs, blockIdx.y, shift);
     const uint32_t *k = (before == 0 ? depth : ((before - 1) & 1 ? key1 : key0)) + job.rec_begin + base;
     const int n = (int)min((int64_t)Seg<kItems>::kSeg, job.gauss_count - base);
     uint32_t v[kItems];
@@ -202,8 +179,25 @@ __global__ __launch_bounds__(kSegThreads) void k_dsort_hist(ivrgs_batch b, const
 #pragma unroll
     for (int u = 0; u < kItems; ++u)
         if (u * kSegThreads + (int)threadIdx.x < n) atomicAdd(&h[(v[u] >> shift) & 255u], 1u);
+    if (first) {
+        uint32_t a, o;
+        seg_range<kItems>(v, n, a, o);
+        if ((threadIdx.x & 63) == 0) {
+            sa[threadIdx.x >> 6] = a;
+            so[threadIdx.x >> 6] = o;
+        }
+    }
     __syncthreads();
     hist[((int64_t)blockIdx.y * 256 + threadIdx.x) * n_seg + blockIdx.x] = h[threadIdx.x];
+    if (first && threadIdx.x == 0) {
+        uint32_t a = sa[0], o = so[0];
+        for (int w = 1; w < kSegThreads / 64; ++w) {
+            a &= sa[w];
+            o |= so[w];
+        }
+        prng[(int64_t)blockIdx.y * n_seg + blockIdx.x] = a;
+        prng[((int64_t)b.n_jobs + blockIdx.y) * n_seg + blockIdx.x] = o;
+    }
 }
 
 // Exclusive prefix of 64-bit values over a workgroup of 1024 threads.
@@ -230,17 +224,39 @@ __device__ uint64_t block_exclusive_scan_1024(uint64_t v, uint64_t *tmp /* >= 16
 // Per (job, digit), one wave: exclusive scan of the digit's counts over the
 // job's segments (contiguous, in place) and the digit's total into
 // tot[job][digit].  The counts of up to kColBlock x 64 segments are loaded
-// before any is scanned, so a column pays one load latency per block.
+// before any is scanned, so a column pays one load latency per block.  The
+// first pass combines the segments' key ranges first (every wave for
+// itself; workgroup 0 of the job stores the range for the later launches).
 constexpr int kColBlock = 16;
 template <int kItems>
-__global__ __launch_bounds__(256) void k_dsort_colscan(ivrgs_batch b, const uint32_t *__restrict__ rng, int shift,
+__global__ __launch_bounds__(256) void k_dsort_colscan(ivrgs_batch b, uint32_t *__restrict__ rng, int shift,
                                                        uint32_t *__restrict__ hist, uint32_t *__restrict__ tot,
-                                                       int n_seg) {
+                                                       const uint32_t *__restrict__ prng, int n_seg) {
     const int d = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const ivrgs_job job = b.jobs[blockIdx.y];
     const int rows = (job.gauss_count + Seg<kItems>::kSeg - 1) / Seg<kItems>::kSeg;
-    if (rows == 0 || !digit_varies(rng, b.n_jobs, blockIdx.y, shift)) return;
+    bool varies;
+    if (shift == 0) {
+        uint32_t a = 0xFFFFFFFFu, o = 0u;
+        for (int c = lane; c < rows; c += 64) {
+            a &= prng[(int64_t)blockIdx.y * n_seg + c];
+            o |= prng[((int64_t)b.n_jobs + blockIdx.y) * n_seg + c];
+        }
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            a &= __shfl_xor(a, m, 64);
+            o |= __shfl_xor(o, m, 64);
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            rng[blockIdx.y] = a;
+            rng[b.n_jobs + blockIdx.y] = o;
+        }
+        varies = ((a ^ o) & 255u) != 0u;
+    } else {
+        varies = digit_varies(rng, b.n_jobs, blockIdx.y, shift);
+    }
+    if (rows == 0 || !varies) return;
     uint32_t *col = hist + ((int64_t)blockIdx.y * 256 + d) * n_seg;
     uint32_t carry = 0;
     for (int base = 0; base < rows; base += 64 * kColBlock) {
@@ -263,10 +279,13 @@ __global__ __launch_bounds__(256) void k_dsort_colscan(ivrgs_batch b, const uint
 }
 
 // Per (job, segment): stable scatter of the segment's (key, id) pairs by
-// digit.  Wave w owns the contiguous part [w * Seg<kItems>::kWaveItems, ...) of the
-// segment and ranks equal digits by lane inside each step of 64, so the
-// order within a digit is the input order.  A digit that is constant over
-// the job leaves the pairs where they are (see passes_before).
+// digit.  Wave w owns the contiguous part [w * Seg<kItems>::kWaveItems, ...)
+// of the segment and ranks equal digits by lane inside each step of 64, so
+// the order within a digit is the input order.  The pairs are first placed
+// in LDS in the segment's digit order; the workgroup then writes them out
+// in that order, so consecutive lanes store to consecutive addresses inside
+// each digit's run.  A digit that is constant over the job leaves the pairs
+// where they are (see passes_before).
 template <int kItems>
 __global__ __launch_bounds__(kSegThreads) void k_dsort_scatter(ivrgs_batch b, const uint32_t *__restrict__ depth,
                                                                uint32_t *__restrict__ key0,
@@ -276,8 +295,11 @@ __global__ __launch_bounds__(kSegThreads) void k_dsort_scatter(ivrgs_batch b, co
                                                                const uint32_t *__restrict__ rng, int shift,
                                                                const uint32_t *__restrict__ hist,
                                                                const uint32_t *__restrict__ tot, int n_seg) {
-    __shared__ uint32_t wh[kSegThreads / 64][256];  // per wave: count, then start, per digit
-    __shared__ uint32_t wsum[kSegThreads / 64];
+    constexpr int kWaves = kSegThreads / 64;
+    __shared__ uint32_t wh[kWaves][256];    // per wave: count, then place in the segment, per digit
+    __shared__ uint32_t delta[256];         // per digit: place in the job minus place in the segment
+    __shared__ uint32_t wsum[kWaves], wcnt[kWaves];
+    __shared__ uint2 kv[Seg<kItems>::kSeg];  // the segment in digit order
     const ivrgs_job job = b.jobs[blockIdx.y];
     const int64_t base = (int64_t)blockIdx.x * Seg<kItems>::kSeg;
     if (base >= job.gauss_count) return;
@@ -290,6 +312,11 @@ __global__ __launch_bounds__(kSegThreads) void k_dsort_scatter(ivrgs_batch b, co
     uint32_t *dk = to1 ? key1 : key0, *dv = to1 ? val1 : val0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int w0 = wave * Seg<kItems>::kWaveItems;
+    // thread d: digit d's total in the job and this segment's offset inside
+    // the digit (loaded together with the keys)
+    const int d = threadIdx.x;
+    const uint32_t t = tot[(int64_t)blockIdx.y * 256 + d];
+    const uint32_t seg_off = hist[((int64_t)blockIdx.y * 256 + d) * n_seg + blockIdx.x];
     uint32_t kk[kItems], vv[kItems];
 #pragma unroll
     for (int u = 0; u < kItems; ++u) {
@@ -297,38 +324,49 @@ __global__ __launch_bounds__(kSegThreads) void k_dsort_scatter(ivrgs_batch b, co
         kk[u] = i < n ? sk[off + i] : 0u;
         vv[u] = i < n ? (first ? (uint32_t)(off + i) : sv[off + i]) : 0u;
     }
-    for (int d = lane; d < 256; d += 64) wh[wave][d] = 0;
+    for (int q = lane; q < 256; q += 64) wh[wave][q] = 0;
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < kItems; ++u)
         if (w0 + u * 64 + lane < n) atomicAdd(&wh[wave][(kk[u] >> shift) & 255u], 1u);
     __syncthreads();
     {
-        // thread d: start of digit d in the job (exclusive scan of the digit
-        // totals), plus this segment's offset inside the digit, plus the
-        // counts of the waves before
-        const int d = threadIdx.x;
-        const uint32_t t = tot[(int64_t)blockIdx.y * 256 + d];
-        uint32_t incl = t;
+        // thread d: digit d's place in the segment (scan of the segment's
+        // digit counts) and in the job (scan of the digit totals, plus the
+        // segment's offset), then each wave's first place
+        uint32_t c[kWaves], cs = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            c[w] = wh[w][d];
+            cs += c[w];
+        }
+        uint32_t it = t, ic = cs;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t u = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += u;
+            const uint32_t ut = __shfl_up(it, o, 64), uc = __shfl_up(ic, o, 64);
+            if (lane >= o) {
+                it += ut;
+                ic += uc;
+            }
         }
-        if (lane == 63) wsum[wave] = incl;
+        if (lane == 63) {
+            wsum[wave] = it;
+            wcnt[wave] = ic;
+        }
         __syncthreads();
-        uint32_t digit_start = incl - t;
-        for (int w = 0; w < wave; ++w) digit_start += wsum[w];
-        uint32_t run = digit_start + hist[((int64_t)blockIdx.y * 256 + d) * n_seg + blockIdx.x];
+        uint32_t gstart = it - t + seg_off, lstart = ic - cs;
+        for (int w = 0; w < wave; ++w) {
+            gstart += wsum[w];
+            lstart += wcnt[w];
+        }
+        delta[d] = gstart - lstart;
 #pragma unroll
-        for (int w = 0; w < kSegThreads / 64; ++w) {
-            const uint32_t c = wh[w][d];
-            wh[w][d] = run;
-            run += c;
+        for (int w = 0; w < kWaves; ++w) {
+            wh[w][d] = lstart;
+            lstart += c[w];
         }
     }
     __syncthreads();
-    uint32_t *dkj = dk + job.rec_begin, *dvj = dv + job.rec_begin;
 #pragma unroll
     for (int u = 0; u < kItems; ++u) {
         if (w0 + u * 64 < n) {  // wave-uniform
@@ -337,11 +375,20 @@ __global__ __launch_bounds__(kSegThreads) void k_dsort_scatter(ivrgs_batch b, co
             const uint64_t m = match_bits<8>(dg, 8, __ballot(act));
             const uint32_t rank = lanes_below(m);
             const uint32_t pos = wh[wave][dg] + rank;
-            if (act) {
-                dkj[pos] = kk[u];
-                dvj[pos] = vv[u];
-            }
+            if (act) kv[pos] = make_uint2(kk[u], vv[u]);
             if (act && rank == 0) wh[wave][dg] += (uint32_t)__popcll(m);
+        }
+    }
+    __syncthreads();
+    uint32_t *dkj = dk + job.rec_begin, *dvj = dv + job.rec_begin;
+#pragma unroll
+    for (int u = 0; u < kItems; ++u) {
+        const int i = u * kSegThreads + threadIdx.x;
+        if (i < n) {
+            const uint2 p = kv[i];
+            const uint32_t g = delta[(p.x >> shift) & 255u] + (uint32_t)i;
+            dkj[g] = p.x;
+            dvj[g] = p.y;
         }
     }
 }
@@ -1039,20 +1086,24 @@ size_t col_part_words(const ivrgs_batch &b, int width, int chunk) {
     return (size_t)b.n_jobs * ((n_chunks + seg - 1) / seg) * (size_t)width;
 }
 
-size_t depth_sort_hist_words(const ivrgs_batch &b) { return (size_t)b.n_jobs * 256 * ((size_t)seg_rows(b) + 1); }
+// Per job: 256 digit counts per segment, the 256 digit totals, and the
+// segments' key ranges (two words each).
+size_t depth_sort_hist_words(const ivrgs_batch &b) {
+    return (size_t)b.n_jobs * (256 * ((size_t)seg_rows(b) + 1) + 2 * (size_t)seg_rows(b));
+}
 
-// Key range and the passes of the depth sort over varying digits (a pass
-// on a constant digit returns at once).
+// The passes of the depth sort (the first also takes the key range; a later
+// pass on a constant digit returns at once).
 template <int kItems>
 void launch_depth_sort(const ivrgs_batch &b, const uint32_t *depth, const BinWork &w, uint32_t *tot, int n_seg,
                        hipStream_t s) {
-    hipLaunchKernelGGL(k_dkey_range<kItems>, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, depth, w.rng);
+    uint32_t *prng = tot + (size_t)b.n_jobs * 256;
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 8 * pass;
         hipLaunchKernelGGL(k_dsort_hist<kItems>, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, depth, w.key[0],
-                           w.key[1], w.rng, shift, w.hist, n_seg);
+                           w.key[1], w.rng, shift, w.hist, prng, n_seg);
         hipLaunchKernelGGL(k_dsort_colscan<kItems>, dim3(64, b.n_jobs), dim3(256), 0, s, b, w.rng, shift, w.hist,
-                           tot, n_seg);
+                           tot, prng, n_seg);
         hipLaunchKernelGGL(k_dsort_scatter<kItems>, dim3(n_seg, b.n_jobs), dim3(kSegThreads), 0, s, b, depth,
                            w.key[0], w.val[0], w.key[1], w.val[1], w.rng, shift, w.hist, tot, n_seg);
     }
@@ -1070,7 +1121,6 @@ hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *r
     uint32_t *tot = w.hist + (size_t)b.n_jobs * 256 * n_seg;
     if (n_seg > 0) {
         TimedScope ts(TK_SORT, s);
-        hipLaunchKernelGGL(k_rng_init, dim3(1), dim3(256), 0, s, w.rng, b.n_jobs);
         if (seg_items(b) == 4)
             launch_depth_sort<4>(b, depth, w, tot, n_seg, s);
         else
