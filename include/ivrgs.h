@@ -570,6 +570,43 @@ ivrgs_status ivrgs_render_aux_bwd(const ivrgs_batch *batch, const ivrgs_params *
                                   ivrgs_gaussians_mut *grads, void *workspace, size_t workspace_bytes,
                                   void *stream);
 
+/* ---- Attribute rows of the editable stage (Sec. 4.3; Eq. 5) ---------------
+ * The rows that the maps of the editable-stage losses composite: per
+ * Gaussian g, attr[g * 12 + c] holds the unit normal (c = 0..2: the normal
+ * plane divided by its Euclidean length, the length clamped below at
+ * 1e-12), delta-c (c = 3..5: the colour plane of a basic model), k_a, k_d,
+ * k_s and beta (c = 6..9: the shade plane), then two zero pad entries; that
+ * is the layout ivrgs_render_aux_fwd takes with n_attr = 10.  Planes are
+ * device [k][n] (component-major), attr device [n][12], 16-byte aligned.
+ * n = 0 is a no-op; IVRGS_E_INVALID for n < 0, a null pointer or an
+ * unaligned attr. */
+ivrgs_status ivrgs_editable_attr_fwd(const float *normal, const float *color, const float *shade, int64_t n,
+                                     float *attr, void *stream);
+
+/* Backward of the rows for dL/d(rows) grad_attr (device [n][12], 16-byte
+ * aligned; the pad entries are not read): ADDS into grad_normal [3][n]
+ * (the normalisation's derivative, (I - u u^T) / length with u the unit
+ * normal, or I / 1e-12 where the length is at the floor), grad_color [3][n]
+ * and grad_shade [4][n].  normal: the plane the rows were made from. */
+ivrgs_status ivrgs_editable_attr_bwd(const float *normal, int64_t n, const float *grad_attr, float *grad_normal,
+                                     float *grad_color, float *grad_shade, void *stream);
+
+/* The image's backward and the maps' backward in one call (the training
+ * step of the editable stage differentiates both; Eq. 2 and Eq. 5): the
+ * result of ivrgs_render_bwd for dl_drgba plus that of ivrgs_render_aux_bwd
+ * for grad_aux, summed into one set of record gradients that one projection
+ * backward takes to grads.  grads is WRITTEN as by ivrgs_render_bwd (no
+ * clearing needed); grad_attr (device [g.n][S], S = n_attr rounded up to a
+ * multiple of 4) is cleared, then written, pad entries included.  Arguments
+ * as in those two calls, over the same batch, params, bins and workspace;
+ * IVRGS_E_UNSUPPORTED with IVRGS_FLAG_DETERMINISTIC_BWD (the maps' sums are
+ * float atomics). */
+ivrgs_status ivrgs_render_bwd_aux(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
+                                  const ivrgs_bins *bins, const float *out_rgba, const float *dl_drgba,
+                                  const float *attr, int32_t n_attr, const float *aux, const float *grad_aux,
+                                  float *grad_attr, ivrgs_gaussians_mut *grads, void *workspace,
+                                  size_t workspace_bytes, void *stream);
+
 /* ---- SSIM term of the photometric loss (Sec. 4.2; appendix weights) -------
  * Structural similarity of an image x against a target y, both device
  * [channels][height][width] float32, contiguous: per channel, every valid

@@ -152,6 +152,19 @@ def render(planes_t: dict, cam_row, params: Params, model_id=None, edit_rows=Non
     return out, order, sig
 
 
+NORMAL_FLOOR = 1e-12  # lower clamp of a normal's length before it is divided out
+
+
+def editable_attributes(normal, color, shade):
+    """Attribute planes [10, n] that the editable-stage maps composite
+    (Sec. 4.3; the normal map of Eq. 5): the unit normal (the normal plane
+    over its Euclidean length, clamped below at NORMAL_FLOOR), delta-c (the
+    colour plane of a basic model) and k_a, k_d, k_s, beta (the shade
+    plane).  float64 tensors [k, n]; differentiable by autograd."""
+    length = normal.norm(dim=0, keepdim=True).clamp_min(NORMAL_FLOOR)
+    return torch.cat([normal / length, color, shade])
+
+
 def to_tensors(planes: dict, requires_grad: bool = False) -> dict:
     return {k: torch.tensor(np.asarray(planes[k], np.float64), requires_grad=requires_grad)
             for k in PLANES}

@@ -73,14 +73,104 @@ def render_aux(planes: dict, attr: torch.Tensor, cams_t, jobs: Jobs, renderer: R
 
 
 EDITABLE_ATTRS = 10  # unit normal 3, delta-c 3, k_a, k_d, k_s, beta
+EDITABLE_STRIDE = 12  # row stride of the editable attribute rows
+
+
+def _check_editable_planes(normal, color, shade):
+    n = int(normal.shape[1]) if normal.dim() == 2 else -1
+    for name, t, d in (("normal", normal, 3), ("color", color, 3), ("shade", shade, 4)):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and tuple(t.shape) == (d, n)):
+            raise ValueError(f"{name}: expected a contiguous float32 device tensor [{d}, n]")
+    return n
+
+
+class _EditAttrFn(torch.autograd.Function):
+    """Attribute rows [n, 12] from the normal, colour and shade planes
+    (ivrgs_editable_attr_fwd) and their backward (ivrgs_editable_attr_bwd)."""
+
+    @staticmethod
+    def forward(ctx, normal, color, shade):
+        n = _check_editable_planes(normal, color, shade)
+        attr = torch.empty((n, EDITABLE_STRIDE), dtype=torch.float32, device=normal.device)
+        N.ivrgs_editable_attr_fwd(normal.data_ptr(), color.data_ptr(), shade.data_ptr(), n, attr.data_ptr(),
+                                  _stream())
+        ctx.save_for_backward(normal)
+        return attr
+
+    @staticmethod
+    def backward(ctx, g):
+        (normal,) = ctx.saved_tensors
+        n = int(normal.shape[1])
+        g = g.contiguous()
+        gn = torch.zeros_like(normal)
+        gc = torch.zeros((3, n), dtype=torch.float32, device=normal.device)
+        gs = torch.zeros((4, n), dtype=torch.float32, device=normal.device)
+        N.ivrgs_editable_attr_bwd(normal.data_ptr(), n, g.data_ptr(), gn.data_ptr(), gc.data_ptr(), gs.data_ptr(),
+                                  _stream())
+        return gn, gc, gs
 
 
 def editable_attributes(planes: dict) -> torch.Tensor:
     """The attribute rows of the editable-Gaussian training losses, [n, 12]
     (EDITABLE_ATTRS values and two pad columns): the unit normal (3),
     delta-c (3, the colour plane of a basic model), k_a, k_d, k_s, beta —
-    differentiable in the planes."""
-    nrm = planes["normal"]
-    nrm = nrm / nrm.norm(dim=0, keepdim=True).clamp_min(1e-12)
-    pad = torch.zeros((2, nrm.shape[1]), dtype=nrm.dtype, device=nrm.device)
-    return torch.cat([nrm, planes["color"], planes["shade"], pad]).t().contiguous()
+    made by the HIP kernel, differentiable in the planes."""
+    return _EditAttrFn.apply(planes["normal"], planes["color"], planes["shade"])
+
+
+class _EditableFn(torch.autograd.Function):
+    """The image and the eleven maps of the editable stage from one
+    projection and binning.  Backward: one call takes the image's and the
+    maps' gradients to the planes and the attribute rows
+    (ivrgs_render_bwd_aux); the rows' gradient then goes back to the normal,
+    colour and shade planes (ivrgs_editable_attr_bwd), so the planes get one
+    gradient each."""
+
+    @staticmethod
+    def forward(ctx, renderer, cams_t, jobs, edits_t, *planes):
+        pl = dict(zip(PLANES, planes))
+        rgba = renderer.forward(pl, cams_t, jobs, None, edits_t)
+        batch = renderer.make_batch(pl, None, edits_t, cams_t, jobs)
+        proj, bins = renderer._structs(batch)
+        n = int(pl["mean"].shape[1])
+        attr = torch.empty((n, EDITABLE_STRIDE), dtype=torch.float32, device=renderer.device)
+        N.ivrgs_editable_attr_fwd(pl["normal"].data_ptr(), pl["color"].data_ptr(), pl["shade"].data_ptr(), n,
+                                  attr.data_ptr(), _stream())
+        s = renderer.settings
+        maps = torch.empty((jobs.n_jobs, 1 + EDITABLE_ATTRS, s.height, s.width), dtype=torch.float32,
+                           device=renderer.device)
+        N.ivrgs_render_aux_fwd(batch, s.params(), proj, bins, attr.data_ptr(), EDITABLE_ATTRS, maps.data_ptr(),
+                               _stream())
+        ctx.renderer, ctx.jobs, ctx.generation = renderer, jobs, renderer.generation
+        ctx.save_for_backward(cams_t, edits_t, rgba, attr, maps, *planes)
+        return rgba, maps
+
+    @staticmethod
+    def backward(ctx, g_rgba, g_maps):
+        saved = ctx.saved_tensors
+        cams_t, edits_t, rgba, attr, maps = saved[:5]
+        planes = dict(zip(PLANES, saved[5:]))
+        r = ctx.renderer
+        n = int(planes["mean"].shape[1])
+        batch = r.make_batch(planes, None, edits_t, cams_t, ctx.jobs)
+        proj, bins = r.prepare_backward(batch, rebin=r.generation != ctx.generation)
+        grads = {k: torch.empty((d, n), dtype=torch.float32, device=r.device) for k, d in PLANE_DIMS.items()}
+        gattr = torch.empty_like(attr)
+        g = N.ivrgs_gaussians(n, *[grads[k].data_ptr() for k in PLANES], None)
+        N.ivrgs_render_bwd_aux(batch, r.settings.params(), proj, bins, rgba.data_ptr(),
+                               g_rgba.contiguous().data_ptr(), attr.data_ptr(), EDITABLE_ATTRS, maps.data_ptr(),
+                               g_maps.contiguous().data_ptr(), gattr.data_ptr(), g, r.ws.data_ptr(), r.ws.numel(),
+                               _stream())
+        N.ivrgs_editable_attr_bwd(planes["normal"].data_ptr(), n, gattr.data_ptr(), grads["normal"].data_ptr(),
+                                  grads["color"].data_ptr(), grads["shade"].data_ptr(), _stream())
+        return (None, None, None, None, *[grads[k] for k in PLANES])
+
+
+def render_editable(planes: dict, cams_t, jobs: Jobs, renderer: Renderer, edits_t=None):
+    """Differentiable image [n_jobs, 4, H, W] and editable-stage maps
+    [n_jobs, 11, H, W] (depth, unit normal, delta-c, k_a, k_d, k_s, beta) of
+    the job batch, from one binning; the same values as rasterize followed
+    by render_aux over editable_attributes."""
+    if edits_t is None:
+        edits_t = default_edits(renderer.device)
+    return _EditableFn.apply(renderer, cams_t, jobs, edits_t, *[planes[k] for k in PLANES])

@@ -408,9 +408,30 @@ ivrgs_status ivrgs_render_aux_bwd(const ivrgs_batch *batch, const ivrgs_params *
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(grec), kGradStride * batch->n_records, 0u, s);
     if (e == hipSuccess)
         e = launch_aux_bwd(*batch, k, n_tiles, proj->rec, bins->tile_start, bins->sorted, attr, n_attr, aux, grad_aux,
-                           grec, grad_attr, grads->mean, s);
-    if (e == hipSuccess) e = launch_project_bwd(*batch, k, proj->rect, grec, *grads, true, false, s);
+                           grec, grad_attr, s);
+    if (e == hipSuccess) e = launch_project_bwd(*batch, k, proj->rect, grec, *grads, true, false, s, false, true);
     return hip_status(e);
+}
+
+ivrgs_status ivrgs_editable_attr_fwd(const float *normal, const float *color, const float *shade, int64_t n,
+                                     float *attr, void *stream) {
+    if (n < 0) return IVRGS_E_INVALID;
+    if (n == 0) return IVRGS_OK;
+    if (!normal || !color || !shade || !attr || (reinterpret_cast<uintptr_t>(attr) & 15u)) return IVRGS_E_INVALID;
+    if ((n + 255) / 256 > (int64_t)UINT32_MAX) return IVRGS_E_SHAPE;
+    return hip_status(launch_edit_attr_fwd(normal, color, shade, n, attr, reinterpret_cast<hipStream_t>(stream)));
+}
+
+ivrgs_status ivrgs_editable_attr_bwd(const float *normal, int64_t n, const float *grad_attr, float *grad_normal,
+                                     float *grad_color, float *grad_shade, void *stream) {
+    if (n < 0) return IVRGS_E_INVALID;
+    if (n == 0) return IVRGS_OK;
+    if (!normal || !grad_attr || !grad_normal || !grad_color || !grad_shade ||
+        (reinterpret_cast<uintptr_t>(grad_attr) & 15u))
+        return IVRGS_E_INVALID;
+    if ((n + 255) / 256 > (int64_t)UINT32_MAX) return IVRGS_E_SHAPE;
+    return hip_status(launch_edit_attr_bwd(normal, n, grad_attr, grad_normal, grad_color, grad_shade,
+                                           reinterpret_cast<hipStream_t>(stream)));
 }
 
 ivrgs_status ivrgs_sh_color(const float *sh, int32_t degree, const float *mean, int64_t n,
@@ -700,9 +721,24 @@ ivrgs_status ivrgs_render_fwd(const ivrgs_batch *batch, const ivrgs_params *para
                                         params->persist_per_cu, ckpt, reinterpret_cast<hipStream_t>(stream)));
 }
 
-ivrgs_status ivrgs_render_bwd(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
-                              const ivrgs_bins *bins, const float *out_rgba, const float *dl_drgba,
-                              ivrgs_gaussians_mut *grads, void *workspace, size_t workspace_bytes, void *stream) {
+}  // extern "C"
+
+namespace ivrgs {
+namespace {
+// The maps' part of a combined backward (ivrgs_render_bwd_aux).
+struct AuxBwdArgs {
+    const float *attr, *aux, *grad_aux;
+    float *grad_attr;
+    int n_attr;
+};
+
+// The image's backward, and with `ax` the maps' in the same pass over the
+// record-gradient rows: clear the rows (and the attribute gradients), the
+// image walk, the maps' walk, one projection backward.
+ivrgs_status render_bwd_run(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
+                            const ivrgs_bins *bins, const float *out_rgba, const float *dl_drgba,
+                            ivrgs_gaussians_mut *grads, const AuxBwdArgs *ax, void *workspace, size_t workspace_bytes,
+                            void *stream) {
     ivrgs_status st = check_batch(batch);
     if (st != IVRGS_OK) return st;
     if ((st = check_params(params)) != IVRGS_OK) return st;
@@ -725,8 +761,13 @@ ivrgs_status ivrgs_render_bwd(const ivrgs_batch *batch, const ivrgs_params *para
         dw.scale = reinterpret_cast<float *>(d);
     }
     // the deterministic walk writes every record gradient itself
-    hipError_t e = det ? hipSuccess
-                       : launch_fill_u32(reinterpret_cast<uint32_t *>(grec), kGradStride * batch->n_records, 0u, s);
+    hipError_t e = hipSuccess;
+    const int64_t n_grec = kGradStride * batch->n_records;
+    if (ax)
+        e = launch_fill2_u32(reinterpret_cast<uint32_t *>(grec), n_grec, reinterpret_cast<uint32_t *>(ax->grad_attr),
+                             ax->n_attr > 0 ? batch->g.n * (int64_t)((ax->n_attr + 3) / 4 * 4) : 0, 0u, s);
+    else if (!det)
+        e = launch_fill_u32(reinterpret_cast<uint32_t *>(grec), n_grec, 0u, s);
     if (e == hipSuccess)
         e = launch_render_bwd(k, pick_px(params->bwd_px, 1), n_tiles, proj->rec, bins->tile_start, bins->sorted,
                               out_rgba, dl_drgba, grec,
@@ -737,6 +778,9 @@ ivrgs_status ivrgs_render_bwd(const ivrgs_batch *batch, const ivrgs_params *para
                               L.ckpt_bytes ? reinterpret_cast<const float *>(static_cast<char *>(workspace) + L.ckpt)
                                            : nullptr,
                               det ? &dw : nullptr, batch->n_records, s);
+    if (e == hipSuccess && ax)
+        e = launch_aux_bwd(*batch, k, n_tiles, proj->rec, bins->tile_start, bins->sorted, ax->attr, ax->n_attr,
+                           ax->aux, ax->grad_aux, grec, ax->grad_attr, s);
     // One job over the whole set (its range lies in [0, n) and has n
     // records) writes every Gaussian's gradient, zeros included; otherwise
     // the planes are cleared first and, when several jobs may share a
@@ -749,8 +793,33 @@ ivrgs_status ivrgs_render_bwd(const ivrgs_batch *batch, const ivrgs_params *para
     const int dims[7] = {3, 3, 4, 1, 3, 3, 4};
     for (int p = 0; p < 7 && e == hipSuccess && !dense; ++p)
         e = launch_fill_u32(reinterpret_cast<uint32_t *>(planes[p]), dims[p] * n, 0u, s);
-    if (e == hipSuccess) e = launch_project_bwd(*batch, k, proj->rect, grec, *grads, shared, dense, s, det);
+    if (e == hipSuccess)
+        e = launch_project_bwd(*batch, k, proj->rect, grec, *grads, shared, dense, s, det, ax != nullptr);
     return hip_status(e);
+}
+}  // namespace
+}  // namespace ivrgs
+
+extern "C" {
+
+ivrgs_status ivrgs_render_bwd(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
+                              const ivrgs_bins *bins, const float *out_rgba, const float *dl_drgba,
+                              ivrgs_gaussians_mut *grads, void *workspace, size_t workspace_bytes, void *stream) {
+    return render_bwd_run(batch, params, proj, bins, out_rgba, dl_drgba, grads, nullptr, workspace, workspace_bytes,
+                          stream);
+}
+
+ivrgs_status ivrgs_render_bwd_aux(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
+                                  const ivrgs_bins *bins, const float *out_rgba, const float *dl_drgba,
+                                  const float *attr, int32_t n_attr, const float *aux, const float *grad_aux,
+                                  float *grad_attr, ivrgs_gaussians_mut *grads, void *workspace,
+                                  size_t workspace_bytes, void *stream) {
+    if (!params || !aux || !grad_aux || n_attr < 0 || n_attr > kAuxMax) return IVRGS_E_INVALID;
+    if (n_attr > 0 && (!attr || !grad_attr || (reinterpret_cast<uintptr_t>(attr) & 15u))) return IVRGS_E_INVALID;
+    if (params->flags & IVRGS_FLAG_DETERMINISTIC_BWD) return IVRGS_E_UNSUPPORTED;
+    const AuxBwdArgs ax{attr, aux, grad_aux, grad_attr, n_attr};
+    return render_bwd_run(batch, params, proj, bins, out_rgba, dl_drgba, grads, &ax, workspace, workspace_bytes,
+                          stream);
 }
 
 void ivrgs_timing_enable(uint32_t kinds) {

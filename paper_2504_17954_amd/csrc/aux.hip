@@ -204,16 +204,16 @@ __global__ __launch_bounds__(kTilePix) void k_aux_fwd(ivrgs_batch b, Consts k, c
 // of the group first, then the front-to-back chain, then one reduce-scatter
 // of the group's values; lane v adds value v % (7 + kN) of record v / (7 +
 // kN) to the record gradients (for the projection backward), the attribute
-// gradients or, for the depth, the mean gradient (depth = row 3 of R
-// applied to the mean, plus t).
+// gradients or, for the depth, the record's depth slot GZ (the projection
+// backward takes it to the mean: depth = row 3 of R applied to the mean,
+// plus t).
 template <int kN>
 __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, const float4 *__restrict__ rec,
                                                       const uint32_t *__restrict__ starts,
                                                       const uint32_t *__restrict__ sorted, int64_t n_tiles,
                                                       const float *__restrict__ attr,
                                                       const float *__restrict__ aux, const float *__restrict__ gaux,
-                                                      float *__restrict__ grec, float *__restrict__ gattr,
-                                                      float *__restrict__ gmean) {
+                                                      float *__restrict__ grec, float *__restrict__ gattr) {
     constexpr int kNv = 1 + kN;                              // depth, attributes
     constexpr int kVpr = 6 + kNv;                            // values per record
     constexpr int kG = 64 / kVpr < 4 ? 64 / kVpr : 4;        // records per reduce-scatter
@@ -244,7 +244,6 @@ __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, c
     bool any_g = false;
 #pragma unroll
     for (int c = 0; c < kNv; ++c) any_g |= g[c] != 0.f;
-    const ivrgs_camera &cam = b.cameras[job.camera];
     float T = 1.f, gP = 0.f;
     bool alive = inside & any_g;
     const uint32_t start = starts[tile], end = starts[tile + 1];
@@ -341,9 +340,7 @@ __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, c
                         const int row = my_v == 0 ? GO : (my_v == 1 ? GX : (my_v == 2 ? GY : GQA + (my_v - 3)));
                         atomicAdd(&grec[(size_t)r * kGradStride + row], tot);
                     } else if (my_v == 6) {
-                        atomicAdd(&gmean[gi], tot * cam.R[6]);
-                        atomicAdd(&gmean[b.g.n + gi], tot * cam.R[7]);
-                        atomicAdd(&gmean[2 * b.g.n + gi], tot * cam.R[8]);
+                        atomicAdd(&grec[(size_t)r * kGradStride + GZ], tot);
                     } else {
                         atomicAdd(&gattr[gi * attr_stride(kN) + (my_v - 7)], tot);
                     }
@@ -352,6 +349,60 @@ __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, c
             if (__ballot(alive) == 0ull) break;  // every pixel of the wave is done
         }
     }
+}
+
+// Attribute rows of the editable stage, one thread per Gaussian: the unit
+// normal (the length clamped below at kNormalFloor), delta-c, k_a, k_d,
+// k_s, beta and two zero pad entries, as three 16-byte stores.
+constexpr float kNormalFloor = 1e-12f;
+constexpr int kEditAttrStride = 12;
+
+__global__ __launch_bounds__(256) void k_edit_attr_fwd(const float *__restrict__ normal,
+                                                       const float *__restrict__ color,
+                                                       const float *__restrict__ shade, int64_t n,
+                                                       float4 *__restrict__ attr) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float nx = normal[i], ny = normal[n + i], nz = normal[2 * n + i];
+    const float inv = 1.f / fmaxf(sqrtf(fmaf(nz, nz, fmaf(ny, ny, nx * nx))), kNormalFloor);
+    float4 *row = attr + 3 * i;
+    row[0] = make_float4(nx * inv, ny * inv, nz * inv, color[i]);
+    row[1] = make_float4(color[n + i], color[2 * n + i], shade[i], shade[n + i]);
+    row[2] = make_float4(shade[2 * n + i], shade[3 * n + i], 0.f, 0.f);
+}
+
+// Backward of the rows: with u the unit normal and L the (clamped) length,
+// d u / d normal = (I - u u^T) / L above the floor and I / floor at it.
+// Adds into the plane gradients (each Gaussian once).
+__global__ __launch_bounds__(256) void k_edit_attr_bwd(const float *__restrict__ normal, int64_t n,
+                                                       const float4 *__restrict__ grad_attr,
+                                                       float *__restrict__ gnormal, float *__restrict__ gcolor,
+                                                       float *__restrict__ gshade) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float nx = normal[i], ny = normal[n + i], nz = normal[2 * n + i];
+    const float len = sqrtf(fmaf(nz, nz, fmaf(ny, ny, nx * nx)));
+    const bool above = len > kNormalFloor;
+    const float inv = 1.f / (above ? len : kNormalFloor);
+    const float4 a = grad_attr[3 * i], b = grad_attr[3 * i + 1], c = grad_attr[3 * i + 2];
+    float gx = a.x, gy = a.y, gz = a.z;
+    if (above) {
+        const float ux = nx * inv, uy = ny * inv, uz = nz * inv;
+        const float dot = fmaf(uz, gz, fmaf(uy, gy, ux * gx));
+        gx = fmaf(-ux, dot, gx);
+        gy = fmaf(-uy, dot, gy);
+        gz = fmaf(-uz, dot, gz);
+    }
+    gnormal[i] += gx * inv;
+    gnormal[n + i] += gy * inv;
+    gnormal[2 * n + i] += gz * inv;
+    gcolor[i] += a.w;
+    gcolor[n + i] += b.x;
+    gcolor[2 * n + i] += b.y;
+    gshade[i] += b.z;
+    gshade[n + i] += b.w;
+    gshade[2 * n + i] += c.x;
+    gshade[3 * n + i] += c.y;
 }
 
 }  // namespace
@@ -368,7 +419,7 @@ hipError_t launch_aux_fwd(const ivrgs_batch &b, const Consts &k, int64_t n_tiles
 
 hipError_t launch_aux_bwd(const ivrgs_batch &b, const Consts &k, int64_t n_tiles, const float *rec,
                           const uint32_t *starts, const uint32_t *sorted, const float *attr, int n_attr,
-                          const float *aux, const float *grad_aux, float *grec, float *grad_attr, float *grad_mean,
+                          const float *aux, const float *grad_aux, float *grec, float *grad_attr,
                           hipStream_t s) {
     if (n_tiles == 0) return hipSuccess;
     TimedScope ts(TK_AUX, s);
@@ -377,7 +428,7 @@ hipError_t launch_aux_bwd(const ivrgs_batch &b, const Consts &k, int64_t n_tiles
 #define IVRGS_AUX_BWD(N)                                                                                       \
     case N:                                                                                                    \
         hipLaunchKernelGGL(k_aux_bwd<N>, dim3((unsigned)n_tiles), dim3(kTilePix), 0, s, b, k, rec4, starts, sorted, \
-                           n_tiles, attr, aux, grad_aux, grec, grad_attr, grad_mean);                          \
+                           n_tiles, attr, aux, grad_aux, grec, grad_attr);                                     \
         break;
         IVRGS_AUX_BWD(0) IVRGS_AUX_BWD(1) IVRGS_AUX_BWD(2) IVRGS_AUX_BWD(3) IVRGS_AUX_BWD(4) IVRGS_AUX_BWD(5)
         IVRGS_AUX_BWD(6) IVRGS_AUX_BWD(7) IVRGS_AUX_BWD(8) IVRGS_AUX_BWD(9) IVRGS_AUX_BWD(10) IVRGS_AUX_BWD(11)
@@ -386,6 +437,24 @@ hipError_t launch_aux_bwd(const ivrgs_batch &b, const Consts &k, int64_t n_tiles
         default:
             return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_edit_attr_fwd(const float *normal, const float *color, const float *shade, int64_t n, float *attr,
+                                hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    TimedScope ts(TK_AUX, s);
+    hipLaunchKernelGGL(k_edit_attr_fwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, normal, color, shade, n,
+                       reinterpret_cast<float4 *>(attr));
+    return hipGetLastError();
+}
+
+hipError_t launch_edit_attr_bwd(const float *normal, int64_t n, const float *grad_attr, float *grad_normal,
+                                float *grad_color, float *grad_shade, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    TimedScope ts(TK_AUX, s);
+    hipLaunchKernelGGL(k_edit_attr_bwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, normal, n,
+                       reinterpret_cast<const float4 *>(grad_attr), grad_normal, grad_color, grad_shade);
     return hipGetLastError();
 }
 

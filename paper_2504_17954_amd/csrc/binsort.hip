@@ -28,6 +28,16 @@ __global__ void k_fill_u32(uint32_t *__restrict__ p, int64_t n, uint32_t v) {
         p[i] = v;
 }
 
+// Two buffers in one launch: p[0, n) and q[0, m).
+__global__ void k_fill2_u32(uint32_t *__restrict__ p, int64_t n, uint32_t *__restrict__ q, int64_t m, uint32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n + m; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < n)
+            p[i] = v;
+        else
+            q[i - n] = v;
+    }
+}
+
 __device__ __forceinline__ void unpack_rect(uint2 rc, int &x0, int &y0, int &x1, int &y1) {
     x0 = rc.x & 0xFFFF;
     y0 = rc.x >> 16;
@@ -530,44 +540,34 @@ __global__ __launch_bounds__(256) void k_col_sum(ivrgs_batch b, Consts k, const 
     part[((int64_t)blockIdx.z * n_part + blockIdx.y) * k.tiles_per_job + t] = sum;
 }
 
-constexpr int kPartUnroll = 16;
-
-__global__ __launch_bounds__(256) void k_col_part_scan(ivrgs_batch b, Consts k, uint32_t *__restrict__ part,
-                                                       int n_part, uint32_t *__restrict__ tile_counts) {
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= k.tiles_per_job) return;
-    uint32_t *p = part + (int64_t)blockIdx.y * n_part * k.tiles_per_job + t;
-    uint32_t run = 0;
-    int i = 0;
-    // loads issued kPartUnroll at a time: one memory round trip per batch
-    for (; i + kPartUnroll <= n_part; i += kPartUnroll) {
-        uint32_t v[kPartUnroll];
-#pragma unroll
-        for (int u = 0; u < kPartUnroll; ++u) v[u] = p[(int64_t)(i + u) * k.tiles_per_job];
-#pragma unroll
-        for (int u = 0; u < kPartUnroll; ++u) {
-            p[(int64_t)(i + u) * k.tiles_per_job] = run;
-            run += v[u];
-        }
-    }
-    for (; i < n_part; ++i) {
-        const uint32_t v = p[(int64_t)i * k.tiles_per_job];
-        p[(int64_t)i * k.tiles_per_job] = run;
-        run += v;
-    }
-    tile_counts[(int64_t)blockIdx.y * k.tiles_per_job + t] = run;
-}
-
+// Per column (block of the job) and segment of chunks: the segment's start
+// is the sum of the column's partials of the segments before it (at most 64,
+// loaded together); the last segment also writes the column's total.  Then
+// the counts of the segment's chunks become their exclusive starts.
 __global__ __launch_bounds__(256) void k_col_apply(ivrgs_batch b, Consts k, uint32_t *__restrict__ counts, int chunk,
                                                    int n_chunks, int seg, const uint32_t *__restrict__ part,
-                                                   int n_part) {
+                                                   int n_part, uint32_t *__restrict__ tile_counts) {
     const int t = blockIdx.x * 256 + threadIdx.x;
     if (t >= k.tiles_per_job) return;
     const ivrgs_job job = b.jobs[blockIdx.z];
     const int rows = (job.gauss_count + chunk - 1) / chunk;
     const int r0 = blockIdx.y * seg, r1 = min(r0 + seg, rows);
     uint32_t *col = counts + (int64_t)blockIdx.z * n_chunks * k.tiles_per_job + t;
-    uint32_t run = part[((int64_t)blockIdx.z * n_part + blockIdx.y) * k.tiles_per_job + t];
+    const uint32_t *pp = part + (int64_t)blockIdx.z * n_part * k.tiles_per_job + t;
+    uint32_t run = 0;
+    {
+        uint32_t v[kColUnroll];
+        int q = 0;
+        for (; q + kColUnroll <= (int)blockIdx.y; q += kColUnroll) {
+#pragma unroll
+            for (int u = 0; u < kColUnroll; ++u) v[u] = pp[(int64_t)(q + u) * k.tiles_per_job];
+#pragma unroll
+            for (int u = 0; u < kColUnroll; ++u) run += v[u];
+        }
+        for (; q < (int)blockIdx.y; ++q) run += pp[(int64_t)q * k.tiles_per_job];
+    }
+    if ((int)blockIdx.y == n_part - 1)
+        tile_counts[(int64_t)blockIdx.z * k.tiles_per_job + t] = run + pp[(int64_t)blockIdx.y * k.tiles_per_job];
     int r = r0;
     for (; r + kColUnroll <= r1; r += kColUnroll) {
         uint32_t v[kColUnroll];
@@ -1072,6 +1072,17 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_fill2_u32(uint32_t *p, int64_t n, uint32_t *q, int64_t m, uint32_t v, hipStream_t s) {
+    if (n <= 0 && m <= 0) return hipSuccess;
+    n = n > 0 ? n : 0;
+    m = m > 0 ? m : 0;
+    const int64_t want = (n + m + 255) / 256;
+    const int64_t blocks = want < 4096 ? want : 4096;
+    TimedScope ts(TK_FILL, s);
+    hipLaunchKernelGGL(k_fill2_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, q, m, v);
+    return hipGetLastError();
+}
+
 int chunk_rows(const ivrgs_batch &b, int chunk) { return (b.max_job_count + chunk - 1) / chunk; }
 
 // Chunks per segment of the column scan: about 32, and at most 64 segments.
@@ -1142,10 +1153,8 @@ hipError_t launch_bin_sort(const ivrgs_batch &b, const Consts &k, const float *r
             const unsigned tg = (unsigned)((sg.n_sb + 255) / 256);
             hipLaunchKernelGGL(k_col_sum, dim3(tg, (unsigned)n_part, (unsigned)b.n_jobs), dim3(256), 0, s, b, kb,
                                w.counts, chunk, n_chunks, seg, w.part, n_part);
-            hipLaunchKernelGGL(k_col_part_scan, dim3(tg, (unsigned)b.n_jobs), dim3(256), 0, s, b, kb, w.part, n_part,
-                               w.sb_len);
             hipLaunchKernelGGL(k_col_apply, dim3(tg, (unsigned)n_part, (unsigned)b.n_jobs), dim3(256), 0, s, b, kb,
-                               w.counts, chunk, n_chunks, seg, w.part, n_part);
+                               w.counts, chunk, n_chunks, seg, w.part, n_part, w.sb_len);
         } else {
             hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, w.sb_len, n_all, 0u);
         }

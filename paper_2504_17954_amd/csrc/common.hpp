@@ -12,8 +12,8 @@ constexpr int kTile = 16;             // tile edge in pixels
 constexpr int kTilePix = kTile * kTile;
 constexpr int kRecWords = 16;         // floats per projected record: one 64-byte row
 constexpr int kRecVec = kRecWords / 4;  // float4 per record
-constexpr int kGradRec = 9;           // record-gradient components
-constexpr int kGradStride = 9;        // floats between the gradient rows of consecutive records
+constexpr int kGradRec = 9;           // record-gradient components of the image
+constexpr int kGradStride = 10;       // floats between the gradient rows of consecutive records
 
 // Long tile lists are cut for the backward: a list of more than kSplitMin
 // records becomes up to kSplitMax segments of equal length (a multiple of 64
@@ -43,8 +43,11 @@ enum { RX = 0, RY, RQA, RQB, RQC, RO, RCR, RCG, RCB, RZ, RCUT, RPAD, RRECT0, RRE
 // centre - screen mean and D = dL/do' * o' G summed over the record's
 // composited pixels: GX, GY = sum D dx, sum D dy; GQA, GQB, GQC = sum D dx^2,
 // D dx dy, D dy^2 (moments; the conic and ln 2 are applied once per record
-// by the projection backward); GO = dL/do'; GCR..GCB = dL/d(rgb).
-enum { GX = 0, GY, GQA, GQB, GQC, GO, GCR, GCG, GCB };
+// by the projection backward); GO = dL/do'; GCR..GCB = dL/d(rgb).  GZ, past
+// the image's components, is dL/d(depth) of the auxiliary maps (their depth
+// channel composites each record's camera-space depth).
+enum { GX = 0, GY, GQA, GQB, GQC, GO, GCR, GCG, GCB, GZ };
+static_assert(GZ == kGradRec && GZ < kGradStride, "the depth slot follows the image's components");
 
 // Compositing constants passed by value to kernels.
 struct Consts {

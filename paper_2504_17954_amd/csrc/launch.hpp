@@ -48,10 +48,11 @@ hipError_t launch_project(const ivrgs_batch &b, const Consts &k, float *rec, uin
                           int64_t *nonfinite, hipStream_t s);
 // atomic: several jobs may share a Gaussian; job_order: then add the jobs'
 // gradients one launch per job, in job order, instead of with atomics (the
-// sums are then reproducible bit for bit).
+// sums are then reproducible bit for bit).  depth: the record-gradient rows
+// carry the auxiliary maps' depth gradient (slot GZ) too.
 hipError_t launch_project_bwd(const ivrgs_batch &b, const Consts &k, const uint32_t *rect, const float *grec,
                               const ivrgs_gaussians_mut &out, bool atomic, bool dense, hipStream_t s,
-                              bool job_order = false);
+                              bool job_order = false, bool depth = false);
 // Models model0 .. model0 + count - 1 (count <= kComposeModels) in one
 // launch: src[j] goes to out[offset[j] ...).  host_e != nullptr: edit values
 // from the host rows host_e[j]; else from dev_table[model0 + j].
@@ -66,6 +67,7 @@ struct ExploreOpts {
 hipError_t launch_explore_step(const float *edit_grad, const float *light_grad, int n_models, const ExploreOpts &o,
                                float *state, ivrgs_model_edit *rows, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_fill2_u32(uint32_t *p, int64_t n, uint32_t *q, int64_t m, uint32_t v, hipStream_t s);
 hipError_t launch_light_bwd(const ivrgs_batch &b, const Consts &k, const uint32_t *rect, const float *grec,
                             float *out, hipStream_t s);
 hipError_t launch_compose_bwd(const ivrgs_gaussians &src, int64_t offset, const ivrgs_gaussians_mut &grads,
@@ -127,8 +129,13 @@ hipError_t launch_aux_fwd(const ivrgs_batch &b, const Consts &k, int64_t n_tiles
                           hipStream_t s);
 hipError_t launch_aux_bwd(const ivrgs_batch &b, const Consts &k, int64_t n_tiles, const float *rec,
                           const uint32_t *starts, const uint32_t *sorted, const float *attr, int n_attr,
-                          const float *aux, const float *grad_aux, float *grec, float *grad_attr, float *grad_mean,
-                          hipStream_t s);
+                          const float *aux, const float *grad_aux, float *grec, float *grad_attr, hipStream_t s);
+// Attribute rows [n][12] of the editable stage from the normal, colour and
+// shade planes, and their backward (adds into the plane gradients).
+hipError_t launch_edit_attr_fwd(const float *normal, const float *color, const float *shade, int64_t n, float *attr,
+                                hipStream_t s);
+hipError_t launch_edit_attr_bwd(const float *normal, int64_t n, const float *grad_attr, float *grad_normal,
+                                float *grad_color, float *grad_shade, hipStream_t s);
 
 // SSIM of an image against its target over valid 11x11 Gaussian windows
 // (sigma 1.5), and its gradient with respect to the image.

@@ -362,9 +362,11 @@ __device__ __forceinline__ void shade_bwd(const GIn &a, const Fwd &f, const floa
 // kOut: how a Gaussian's gradient reaches `out`: stored (kOutStore), added
 // with float atomics (kOutAtomic: several jobs of one launch may share it) or
 // added without atomics (kOutAccum: one launch per job, in job order, so the
-// sums do not depend on the order of the atomics).
+// sums do not depend on the order of the atomics).  kDepth: the rows also
+// carry dL/d(depth) of the auxiliary maps (slot GZ), which reaches the mean
+// through the camera-space depth.
 enum { kOutStore = 0, kOutAtomic = 1, kOutAccum = 2 };
-template <int kOut, bool kDense>
+template <int kOut, bool kDense, bool kDepth>
 __global__ __launch_bounds__(256) void k_project_bwd(ivrgs_batch b, Consts k, const uint2 *__restrict__ rect,
                                                      const float *__restrict__ grec, ivrgs_gaussians_mut out) {
     static_assert(!(kOut != kOutStore && kDense), "dense output is written, not accumulated");
@@ -398,7 +400,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(ivrgs_batch b, Consts k, co
     float gr[kGradRec];
 #pragma unroll
     for (int i = 0; i < kGradRec; ++i) gr[i] = grec[r * kGradStride + i];
-    bool any = false;
+    const float gz = kDepth ? grec[r * kGradStride + GZ] : 0.f;
+    bool any = gz != 0.f;
 #pragma unroll
     for (int i = 0; i < kGradRec; ++i) any |= gr[i] != 0.f;
     if (!any) {
@@ -488,7 +491,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(ivrgs_batch b, Consts k, co
     gt[1] = gJ[5] * (-cam.fy * iz2) + gmy * cam.fy * iz;
     gt[2] = gJ[0] * (-cam.fx * iz2) + gJ[2] * (2.f * cam.fx * f.t[0] * iz3) + gJ[4] * (-cam.fy * iz2) +
             gJ[5] * (2.f * cam.fy * f.t[1] * iz3) - gmx * cam.fx * f.t[0] * iz2 -
-            gmy * cam.fy * f.t[1] * iz2;
+            gmy * cam.fy * f.t[1] * iz2 + gz;
 #pragma unroll
     for (int i = 0; i < 3; ++i) g_mu[i] += cam.R[0 * 3 + i] * gt[0] + cam.R[1 * 3 + i] * gt[1] + cam.R[2 * 3 + i] * gt[2];
 
@@ -848,13 +851,11 @@ hipError_t launch_project(const ivrgs_batch &b, const Consts &k, float *rec, uin
     return hipGetLastError();
 }
 
-hipError_t launch_project_bwd(const ivrgs_batch &b, const Consts &k, const uint32_t *rect, const float *grec,
-                              const ivrgs_gaussians_mut &out, bool atomic, bool dense, hipStream_t s,
-                              bool job_order) {
-    if (b.n_jobs == 0 || b.max_job_count == 0) return hipSuccess;
+template <bool kDepth>
+static void project_bwd_variant(const ivrgs_batch &b, const Consts &k, const uint2 *rc, const float *grec,
+                                const ivrgs_gaussians_mut &out, bool atomic, bool dense, hipStream_t s,
+                                bool job_order) {
     dim3 grid((b.max_job_count + 255) / 256, b.n_jobs);
-    const uint2 *rc = reinterpret_cast<const uint2 *>(rect);
-    TimedScope ts(TK_PROJECT_BWD, s);
     if (atomic && job_order) {
         // one launch per job, in job order, each adding its Gaussians'
         // gradients (a job lists a Gaussian at most once)
@@ -862,16 +863,28 @@ hipError_t launch_project_bwd(const ivrgs_batch &b, const Consts &k, const uint3
             ivrgs_batch bj = b;
             bj.jobs = b.jobs + j;
             bj.n_jobs = 1;
-            hipLaunchKernelGGL((k_project_bwd<kOutAccum, false>), dim3(grid.x, 1), dim3(256), 0, s, bj, k, rc, grec,
-                               out);
+            hipLaunchKernelGGL((k_project_bwd<kOutAccum, false, kDepth>), dim3(grid.x, 1), dim3(256), 0, s, bj, k,
+                               rc, grec, out);
         }
     } else if (atomic) {
-        hipLaunchKernelGGL((k_project_bwd<kOutAtomic, false>), grid, dim3(256), 0, s, b, k, rc, grec, out);
+        hipLaunchKernelGGL((k_project_bwd<kOutAtomic, false, kDepth>), grid, dim3(256), 0, s, b, k, rc, grec, out);
     } else if (dense) {
-        hipLaunchKernelGGL((k_project_bwd<kOutStore, true>), grid, dim3(256), 0, s, b, k, rc, grec, out);
+        hipLaunchKernelGGL((k_project_bwd<kOutStore, true, kDepth>), grid, dim3(256), 0, s, b, k, rc, grec, out);
     } else {
-        hipLaunchKernelGGL((k_project_bwd<kOutStore, false>), grid, dim3(256), 0, s, b, k, rc, grec, out);
+        hipLaunchKernelGGL((k_project_bwd<kOutStore, false, kDepth>), grid, dim3(256), 0, s, b, k, rc, grec, out);
     }
+}
+
+hipError_t launch_project_bwd(const ivrgs_batch &b, const Consts &k, const uint32_t *rect, const float *grec,
+                              const ivrgs_gaussians_mut &out, bool atomic, bool dense, hipStream_t s,
+                              bool job_order, bool depth) {
+    if (b.n_jobs == 0 || b.max_job_count == 0) return hipSuccess;
+    const uint2 *rc = reinterpret_cast<const uint2 *>(rect);
+    TimedScope ts(TK_PROJECT_BWD, s);
+    if (depth)
+        project_bwd_variant<true>(b, k, rc, grec, out, atomic, dense, s, job_order);
+    else
+        project_bwd_variant<false>(b, k, rc, grec, out, atomic, dense, s, job_order);
     return hipGetLastError();
 }
 

@@ -941,12 +941,12 @@ __global__ __launch_bounds__(kGradRec * 64) void k_det_scale(const uint32_t *__r
 }
 
 // Deterministic mode, after the second walk: the FP32 record gradients from
-// their integer sums.
+// their integer sums (the slots past the image's components are cleared).
 __global__ void k_det_finish(const unsigned long long *__restrict__ gfix, const float *__restrict__ scale,
                              int64_t n, float *__restrict__ grec) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int v = (int)(i % kGradRec);
-        grec[i] = (float)((double)(long long)gfix[i] * (double)scale[kGradRec + v]);
+        const int v = (int)(i % kGradStride);
+        grec[i] = v < kGradRec ? (float)((double)(long long)gfix[i] * (double)scale[kGradRec + v]) : 0.f;
     }
 }
 

@@ -240,12 +240,75 @@ def base_loss(rgba, target, depth, normal_map, cam) -> torch.Tensor:
     return photometric(rgba, target) + W_REG * t[0]
 
 
-def editable_loss(rgba, target, maps, opacity, cam) -> torch.Tensor:
+_WEIGHTS = {}
+
+
+def _editable_weights(device, lam: float) -> torch.Tensor:
+    """Device weights of [SSIM, L1, normal consistency, sparsity,
+    smoothness, opacity L1] in the editable-stage loss (its constant lam
+    added separately)."""
+    key = (str(device), float(lam))
+    if key not in _WEIGHTS:
+        _WEIGHTS[key] = torch.tensor([-lam, 1.0 - lam, W_REG, W_REG, W_REG, W_OPACITY], dtype=torch.float32,
+                                     device=device)
+    return _WEIGHTS[key]
+
+
+class _EditableLossFn(torch.autograd.Function):
+    """The editable-stage loss of one view: the SSIM and L1 kernels and the
+    regulariser kernels write their terms into one device vector, which one
+    dot product with the weights combines.  Backward: the photometric
+    gradient of the image, and the regularisers' gradients of the normal,
+    offset-colour and shading maps and the opacities (none to the depth
+    map, the alpha map or the target)."""
+
+    @staticmethod
+    def forward(ctx, rgba, target, maps, opacity, cam, lam):
+        c, h, w = (int(v) for v in rgba.shape)
+        dev = rgba.device
+        nbytes = N.ivrgs_ssim_workspace_size(c, h, w)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        # [SSIM, L1, the four regulariser terms, valid-pixel count, unused]
+        terms = torch.empty(8, dtype=torch.float32, device=dev)
+        base = terms.data_ptr()
+        N.ivrgs_ssim_fwd(rgba.data_ptr(), target.data_ptr(), c, h, w, base, ws.data_ptr(), nbytes, _stream())
+        l1w = torch.empty(N.ivrgs_l1_workspace_size(rgba.numel()), dtype=torch.uint8, device=dev)
+        N.ivrgs_l1_fwd(rgba.data_ptr(), target.data_ptr(), rgba.numel(), base + 4, l1w.data_ptr(), l1w.numel(),
+                       _stream())
+        m = _reg_maps(maps[0], rgba[3], maps[1:4], maps[4:7], maps[7:11], target[:3], opacity)
+        rws = torch.empty(max(N.ivrgs_reg_workspace_size(m), 1), dtype=torch.uint8, device=dev)
+        N.ivrgs_reg_fwd(m, camera_struct(cam), base + 8, None, rws.data_ptr(), rws.numel(), _stream())
+        wv = _editable_weights(dev, lam)
+        ctx.cam, ctx.lam = cam, lam
+        ctx.save_for_backward(rgba, target, maps, opacity, ws, terms, wv)
+        return torch.dot(terms[:6], wv) + lam
+
+    @staticmethod
+    def backward(ctx, g):
+        rgba, target, maps, opacity, ws, terms, wv = ctx.saved_tensors
+        c, h, w = (int(v) for v in rgba.shape)
+        gx = torch.empty_like(rgba)
+        N.ivrgs_photometric_grad(rgba.data_ptr(), target.data_ptr(), c, h, w, ctx.lam, gx.data_ptr(),
+                                 ws.data_ptr(), ws.numel(), _stream())
+        gx.mul_(g)
+        g_terms = (wv[2:] * g).contiguous()
+        gmaps = torch.empty_like(maps)
+        gmaps[0].zero_()
+        gop = torch.empty_like(opacity)
+        m = _reg_maps(maps[0], rgba[3], maps[1:4], maps[4:7], maps[7:11], target[:3], opacity)
+        N.ivrgs_reg_bwd(m, camera_struct(ctx.cam), terms.data_ptr() + 8, g_terms.data_ptr(),
+                        gmaps[1].data_ptr(), gmaps[4].data_ptr(), gmaps[7].data_ptr(), gop.data_ptr(), _stream())
+        return gx, None, gmaps, gop, None, None
+
+
+def editable_loss(rgba, target, maps, opacity, cam, lam: float = 0.2) -> torch.Tensor:
     """Editable stage: the base loss plus 0.1 opacity L1 and 0.01 (offset-
-    colour sparsity + bilateral smoothness of the four shading maps).  maps
-    [11, H, W] from aux.render_aux with aux.editable_attributes: depth, unit
-    normal (3), delta-c (3), k_a, k_d, k_s, beta."""
-    t = regularisers(maps[0], rgba[3], cam, normal=maps[1:4], delta_c=maps[4:7], shade=maps[7:11],
-                     target=target[:3], opacity=opacity)
-    w = torch.tensor([W_REG, W_REG, W_REG, W_OPACITY], dtype=torch.float32, device=t.device)
-    return photometric(rgba, target) + (t * w).sum()
+    colour sparsity + bilateral smoothness of the four shading maps).  rgba
+    [4, H, W] and target [4, H, W]; maps [11, H, W] from aux.render_editable
+    (or aux.render_aux with aux.editable_attributes): depth, unit normal (3),
+    delta-c (3), k_a, k_d, k_s, beta; opacity the Gaussians' opacities."""
+    _check_pair(rgba, target)
+    if maps.dim() != 3 or maps.shape[0] != 11 or tuple(maps.shape[1:]) != tuple(rgba.shape[1:]):
+        raise ValueError("maps: expected [11, H, W] of the image's size")
+    return _EditableLossFn.apply(rgba.contiguous(), target.detach().contiguous(), maps.contiguous(),
+                                 opacity.reshape(-1).contiguous(), cam, float(lam))

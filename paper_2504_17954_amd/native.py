@@ -30,7 +30,8 @@ EXPORTS = ("ivrgs_workspace_size", "ivrgs_tiles_per_job", "ivrgs_compose", "ivrg
            "ivrgs_get_error", "ivrgs_ssim_workspace_size", "ivrgs_ssim_fwd", "ivrgs_ssim_bwd",
            "ivrgs_vq_fit_batch_workspace_size", "ivrgs_vq_fit_batch", "ivrgs_photometric_grad",
            "ivrgs_reg_workspace_size", "ivrgs_reg_fwd", "ivrgs_reg_bwd", "ivrgs_bin_sort_noalloc",
-           "ivrgs_l1_workspace_size", "ivrgs_l1_fwd", "ivrgs_l1_bwd")
+           "ivrgs_l1_workspace_size", "ivrgs_l1_fwd", "ivrgs_l1_bwd", "ivrgs_editable_attr_fwd",
+           "ivrgs_editable_attr_bwd", "ivrgs_render_bwd_aux")
 NOALLOC_SCRATCH_BYTES = 64 << 20
 TIMING_KINDS = ("project", "tile_count", "scatter", "depth_sort", "render_fwd", "render_bwd",
                 "project_bwd", "compose", "fill", "cull", "edit_bwd", "vq", "sh", "aux")
@@ -185,6 +186,12 @@ def load(path: str = LIB_PATH):
     lib.ivrgs_render_aux_fwd.restype = C.c_int
     lib.ivrgs_render_aux_bwd.argtypes = [P, P, P, P, P, C.c_int32, P, P, P, P, P, C.c_size_t, P]
     lib.ivrgs_render_aux_bwd.restype = C.c_int
+    lib.ivrgs_render_bwd_aux.argtypes = [P, P, P, P, P, P, P, C.c_int32, P, P, P, P, P, C.c_size_t, P]
+    lib.ivrgs_render_bwd_aux.restype = C.c_int
+    lib.ivrgs_editable_attr_fwd.argtypes = [P, P, P, C.c_int64, P, P]
+    lib.ivrgs_editable_attr_fwd.restype = C.c_int
+    lib.ivrgs_editable_attr_bwd.argtypes = [P, C.c_int64, P, P, P, P, P]
+    lib.ivrgs_editable_attr_bwd.restype = C.c_int
     I32 = C.c_int32
     lib.ivrgs_ssim_workspace_size.argtypes = [I32, I32, I32]
     lib.ivrgs_ssim_workspace_size.restype = C.c_size_t
@@ -323,6 +330,24 @@ def ivrgs_render_aux_bwd(batch, params, proj, bins, attr_ptr, n_attr: int, aux_p
     check(load().ivrgs_render_aux_bwd(ref(batch), ref(params), ref(proj), ref(bins), attr_ptr, n_attr, aux_ptr,
                                       grad_aux_ptr, grad_attr_ptr, ref(grads), ws_ptr, ws_bytes, stream),
           "ivrgs_render_aux_bwd")
+
+
+def ivrgs_render_bwd_aux(batch, params, proj, bins, rgba_ptr, dl_ptr, attr_ptr, n_attr: int, aux_ptr, grad_aux_ptr,
+                         grad_attr_ptr, grads, ws_ptr, ws_bytes, stream):
+    check(load().ivrgs_render_bwd_aux(ref(batch), ref(params), ref(proj), ref(bins), rgba_ptr, dl_ptr, attr_ptr,
+                                      n_attr, aux_ptr, grad_aux_ptr, grad_attr_ptr, ref(grads), ws_ptr, ws_bytes,
+                                      stream), "ivrgs_render_bwd_aux")
+
+
+def ivrgs_editable_attr_fwd(normal_ptr, color_ptr, shade_ptr, n: int, attr_ptr, stream):
+    check(load().ivrgs_editable_attr_fwd(normal_ptr, color_ptr, shade_ptr, C.c_int64(n), attr_ptr, stream),
+          "ivrgs_editable_attr_fwd")
+
+
+def ivrgs_editable_attr_bwd(normal_ptr, n: int, grad_attr_ptr, grad_normal_ptr, grad_color_ptr, grad_shade_ptr,
+                            stream):
+    check(load().ivrgs_editable_attr_bwd(normal_ptr, C.c_int64(n), grad_attr_ptr, grad_normal_ptr, grad_color_ptr,
+                                         grad_shade_ptr, stream), "ivrgs_editable_attr_bwd")
 
 
 def ivrgs_get_error(bins, stream) -> tuple[int, int]:

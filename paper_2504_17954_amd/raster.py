@@ -314,22 +314,30 @@ class Renderer:
         self._key = (id(batch), self.generation)
         return (rgba, maxw) if want_maxw else rgba
 
-    def backward(self, planes, cams_t, jobs: Jobs, rgba, dl, model_id=None, edits_t=None,
-                 gauss_index=None, rebin: bool = False, grads=None):
-        batch = self.make_batch(planes, model_id, edits_t, cams_t, jobs, gauss_index)
+    def prepare_backward(self, batch, rebin: bool = False):
+        """The projection and bins a backward of `batch` reads, with the
+        forward's list checkpoints in the workspace: with rebin (the buffers
+        were reused since the forward) the records and bins are recomputed,
+        and the checkpoints are when they are not those of this binning (the
+        recomputed image comes out bit-identical and is discarded)."""
         if rebin:
-            # recompute what the backward reads besides the image: the
-            # records, the bins and the list checkpoints of the forward (its
-            # image comes out bit-identical and is discarded)
             proj, bins = self.project_and_bin(batch)
         else:
             self._ensure(batch)
             proj, bins = self._structs(batch)
         if rebin or self._ckpt_generation != self.generation:
-            scratch = torch.empty_like(rgba)
-            N.ivrgs_render_fwd(batch, self.settings.params(), proj, bins, scratch.data_ptr(), None,
+            s = self.settings
+            scratch = torch.empty((int(batch.n_jobs), 4, s.height, s.width), dtype=torch.float32,
+                                  device=self.device)
+            N.ivrgs_render_fwd(batch, s.params(), proj, bins, scratch.data_ptr(), None,
                                self.ws.data_ptr(), self.ws.numel(), _stream())
             self._ckpt_generation = self.generation
+        return proj, bins
+
+    def backward(self, planes, cams_t, jobs: Jobs, rgba, dl, model_id=None, edits_t=None,
+                 gauss_index=None, rebin: bool = False, grads=None):
+        batch = self.make_batch(planes, model_id, edits_t, cams_t, jobs, gauss_index)
+        proj, bins = self.prepare_backward(batch, rebin)
         n = batch.g.n
         if grads is None:
             grads = {k: torch.empty((d, n), dtype=torch.float32, device=self.device)

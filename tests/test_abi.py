@@ -49,6 +49,19 @@ def test_host_validation(lib):
     assert lib.ivrgs_bin_sort(N.ref(b), N.ref(p), None, None, None, 0, None) == N.E_INVALID
     assert lib.ivrgs_render_fwd(N.ref(b), N.ref(p), None, None, None, None, None, 0, None) == N.E_INVALID
     assert lib.ivrgs_render_bwd(N.ref(b), N.ref(p), None, None, None, None, None, None, 0, None) == N.E_INVALID
+    fake = C.c_void_p(256)  # non-null placeholder, never dereferenced
+    assert lib.ivrgs_render_bwd_aux(N.ref(b), N.ref(p), None, None, None, None, None, 0, None, fake, None, None,
+                                    None, 0, None) == N.E_INVALID  # no maps
+    assert lib.ivrgs_render_bwd_aux(N.ref(b), N.ref(p), None, None, None, None, None, 16, fake, fake, None, None,
+                                    None, 0, None) == N.E_INVALID  # more than 15 attributes
+    assert lib.ivrgs_render_bwd_aux(N.ref(b), N.ref(p), None, None, None, None, C.c_void_p(260), 3, fake, fake,
+                                    fake, None, None, 0, None) == N.E_INVALID  # unaligned rows
+    pd = N.ivrgs_params.from_buffer_copy(p)
+    pd.flags = N.FLAG_DETERMINISTIC_BWD
+    assert lib.ivrgs_render_bwd_aux(N.ref(b), N.ref(pd), None, None, None, None, None, 0, fake, fake, None, None,
+                                    None, 0, None) == N.E_UNSUPPORTED
+    assert lib.ivrgs_render_bwd_aux(N.ref(b), N.ref(p), None, None, None, None, None, 0, fake, fake, None, None,
+                                    None, 0, None) == N.E_INVALID  # no batch contents, no outputs
     assert lib.ivrgs_compose(None, 0, None, None, None) == N.E_INVALID
     p2 = N.ivrgs_params.from_buffer_copy(p)
     p2.tile = 8
@@ -67,8 +80,8 @@ def test_host_validation(lib):
     assert lib.ivrgs_project(N.ref(b), N.ref(p), None, None) == N.E_SHAPE
     b.n_jobs = 2
     ws = N.ivrgs_workspace_size(b, p, 1000)
-    # two (key, id) arrays per record for the depth order, 9 gradient floats per record
-    assert ws >= 4 * 4 * 20 + 9 * 4 * 20
+    # two (key, id) arrays per record for the depth order, 10 gradient floats per record
+    assert ws >= 4 * 4 * 20 + 10 * 4 * 20
     # the block entries of the binning (8 bytes each, capacity / 2 of them
     # besides a fixed part) and, per 256 of them, a part's block and 16 tile
     # counts (68 bytes) grow with the pair capacity
@@ -107,6 +120,14 @@ def test_host_validation_of_ssim_and_error_query(lib):
     assert lib.ivrgs_l1_fwd(fake, fake, 10 ** 6, fake, fake, 8, None) == N.E_CAPACITY
     assert lib.ivrgs_l1_bwd(fake, fake, 10, None, fake, None) == N.E_INVALID
     assert lib.ivrgs_l1_bwd(fake, fake, -1, fake, fake, None) == N.E_SHAPE
+    # the editable stage's attribute rows: 16-byte aligned rows, n = 0 a no-op
+    assert lib.ivrgs_editable_attr_fwd(fake, fake, fake, -1, fake, None) == N.E_INVALID
+    assert lib.ivrgs_editable_attr_fwd(None, fake, fake, 10, fake, None) == N.E_INVALID
+    assert lib.ivrgs_editable_attr_fwd(fake, fake, fake, 10, P(260), None) == N.E_INVALID
+    assert lib.ivrgs_editable_attr_fwd(None, None, None, 0, None, None) == N.OK
+    assert lib.ivrgs_editable_attr_bwd(fake, 10, P(264), fake, fake, fake, None) == N.E_INVALID
+    assert lib.ivrgs_editable_attr_bwd(fake, 10, fake, None, fake, fake, None) == N.E_INVALID
+    assert lib.ivrgs_editable_attr_bwd(fake, -3, fake, fake, fake, fake, None) == N.E_INVALID
     out = C.c_int64(0)
     assert lib.ivrgs_get_error(None, None, C.cast(C.byref(out), P), None) == N.E_INVALID
     bins = N.ivrgs_bins(0, 0, 0, 0)  # no status word

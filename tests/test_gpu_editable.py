@@ -1,0 +1,168 @@
+"""The editable stage's fused path against the FP64 oracles, through the C
+ABI: the attribute rows (ivrgs_editable_attr_fwd / _bwd) against the dense
+oracle's definition and its autograd; the image and the eleven maps of
+aux.render_editable, and the gradients of the planes through both, against
+the dense oracle (Eq. 2, Eq. 5, Sec. 4.3); the fused editable-stage loss
+(L1 + SSIM of Sec. 4.2 plus the regularisers of Eq. 6-7 and Sec. 4.3, the
+appendix weights) against the photometric and regulariser oracles.
+
+Tolerances: rows within 2e-7 absolute (unit vectors, FP32 division); row
+gradients 1e-5 relative plus 1e-6 of the largest entry; maps and gradients
+at the bars of the auxiliary-map and regulariser tests (maps 1e-4 of each
+channel's scale; gradients 1e-3 relative plus 1e-5 of the largest entry;
+pixels with an ambiguous decision in the C oracle carry no upstream
+gradient, and Gaussians at an alpha kink are left out)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle import dense as D
+from oracle import explore as OX
+from oracle import regularisers as G
+from paper_2504_17954_amd import aux as AX
+from paper_2504_17954_amd import inputs as I
+from paper_2504_17954_amd import losses as L
+from paper_2504_17954_amd import native as N
+from paper_2504_17954_amd import raster as R
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available()
+    N.load()
+    return torch.device("cuda:0")
+
+
+def check_grad(a, b, what, rel=1e-3, floor=1e-5):
+    tol = rel * np.abs(b) + floor * np.abs(b).max() + 1e-30
+    bad = np.abs(a - b) > tol
+    say(f"  {what}: max|g| {np.abs(b).max():.3e}, outside {int(bad.sum())} / {b.size}, "
+        f"worst {(np.abs(a - b) / tol).max():.3f}")
+    assert not bad.any(), np.argwhere(bad)[:5]
+
+
+@pytest.mark.parametrize("n", [1, 1000, 70_001])
+def test_attr_rows_match_oracle(dev, n):
+    """Rows and their backward for normals of every scale, one of them
+    zero (the floor) and one tiny; the pad entries are zero."""
+    rng = np.random.default_rng(n)
+    nrm = rng.normal(size=(3, n)) * np.exp(rng.uniform(-6, 3, n))
+    nrm[:, 0] = 0.0
+    if n > 1:
+        nrm[:, 1] = (1e-20, -2e-20, 0.5e-20)
+    col = rng.uniform(-1, 1, (3, n))
+    sh = rng.uniform(0, 1, (4, n))
+    f32 = [a.astype(np.float32) for a in (nrm, col, sh)]
+    t64 = [torch.tensor(a.astype(np.float64), requires_grad=True) for a in f32]
+    ref = D.editable_attributes(*t64)
+    ga = rng.normal(size=(10, n))
+    (ref * torch.from_numpy(ga)).sum().backward()
+    pd = [torch.from_numpy(a).to(dev).requires_grad_(True) for a in f32]
+    say(f"attribute rows, {n} Gaussians")
+    rows = AX.editable_attributes(dict(zip(("normal", "color", "shade"), pd)))
+    got = rows.detach().cpu().numpy()
+    assert got.shape == (n, 12)
+    assert np.all(got[:, 10:] == 0.0)
+    err = np.abs(got[:, :10].T - ref.detach().numpy()).max()
+    say(f"  rows max err {err:.3e}")
+    assert err <= 2e-7
+    gfull = np.zeros((n, 12), np.float32)
+    gfull[:, :10] = ga.T
+    gfull[:, 10:] = 1e30  # pad entries: not read
+    rows.backward(torch.from_numpy(gfull).to(dev))
+    for name, p, r in zip(("normal", "color", "shade"), pd, t64):
+        check_grad(p.grad.cpu().numpy(), r.grad.numpy(), f"d/d{name}", rel=1e-5, floor=1e-6)
+
+
+def small(n, seed, width=40, height=32):
+    m = I.small_scene(n, seed, log_scale_mu=-2.6)
+    planes = I.plain_planes(m)
+    cam = I.look_at((0.3, -3.6, 0.9), width=width, height=height)
+    return planes, cam, O.Params(width, height)
+
+
+@pytest.mark.parametrize("n,seed", [(150, 61), (400, 62)])
+def test_render_editable_matches_dense_oracle(dev, n, seed):
+    """Image and maps from one binning, and the gradient of every plane of
+    sum(G_img * image) + sum(G_maps * maps), against the dense oracle's
+    render with the oracle's attribute rows and its autograd."""
+    planes, cam, prm = small(n, seed)
+    cref = O.render(planes, cam, prm)
+    ok = cref["flags"] == 0
+    p = O.project(planes, cam, prm)
+    kink = (np.abs(p[:, 19]) < 1e-5) | (np.abs(p[:, 20]) < 1e-3)
+    pt = D.to_tensors(planes, requires_grad=True)
+    at = D.editable_attributes(pt["normal"], pt["color"], pt["shade"])
+    rgba_ref, _, _, maps_ref = D.render(pt, cam.row(), prm, attr_t=at)
+    rng = np.random.default_rng(seed)
+    Gi = rng.normal(size=rgba_ref.shape) * ok[None]
+    Gm = rng.normal(size=maps_ref.shape) * ok[None]
+    ((rgba_ref * torch.from_numpy(Gi)).sum() + (maps_ref * torch.from_numpy(Gm)).sum()).backward()
+
+    pd = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev).requires_grad_(True) for k, v in planes.items()}
+    rnd = R.Renderer(R.Settings(prm.width, prm.height))
+    say(f"render_editable, {n} Gaussians")
+    rgba, maps = AX.render_editable(pd, R.camera_table([cam]), R.Jobs.single(n), rnd)
+    img = rgba.detach().cpu().numpy()[0]
+    err_i = np.abs(img - rgba_ref.detach().numpy())[:, ok].max()
+    got = maps.detach().cpu().numpy()[0]
+    refm = maps_ref.detach().numpy()
+    scale = np.concatenate([[np.abs(refm[0]).max()], np.abs(at.detach().numpy()).max(axis=1)])
+    err_m = np.abs(got - refm)[:, ok].max(axis=1)
+    say(f"  image err {err_i:.2e}; map errors {np.array2string(err_m, precision=2)}")
+    assert err_i <= 1e-4
+    assert np.all(err_m <= 1e-4 * np.maximum(scale, 1.0))
+    ((rgba * torch.from_numpy(Gi[None].astype(np.float32)).to(dev)).sum()
+     + (maps * torch.from_numpy(Gm[None].astype(np.float32)).to(dev)).sum()).backward()
+    for k in R.PLANES:
+        check_grad(pd[k].grad.cpu().numpy()[:, ~kink], pt[k].grad.numpy()[:, ~kink], f"d/d{k}")
+
+
+@pytest.mark.parametrize("H,W,seed", [(37, 53, 4), (96, 130, 5)])
+def test_editable_loss_matches_oracle(dev, H, W, seed):
+    """The fused editable-stage loss: its value, and its gradients with
+    respect to the image, the maps (none to the depth channel) and the
+    opacities, against (1 - lam) L1 + lam (1 - SSIM) of the photometric
+    oracle plus the appendix-weighted regulariser oracle."""
+    lam = 0.2
+    cam = I.look_at((0.3, -3.5, 0.6), width=W, height=H)
+    m = I.view_maps(H, W, seed, n_gauss=500 + seed)
+    rng = np.random.default_rng(seed)
+    rgba = np.concatenate([rng.uniform(0, 1, (3, H, W)), m["alpha"][None]]).astype(np.float32)
+    target = np.concatenate([m["target"], rng.uniform(0, 1, (1, H, W))]).astype(np.float32)
+    maps = np.concatenate([m["depth"][None], m["normal"], m["delta_c"], m["shade"]]).astype(np.float32)
+    w = np.array([L.W_REG, L.W_REG, L.W_REG, L.W_OPACITY])
+    phot, gphot = OX.photometric(rgba.astype(np.float64), target.astype(np.float64), lam)
+    ref = G.terms(m["depth"], m["alpha"], m["normal"], m["delta_c"], m["shade"], m["target"], m["opacity"], cam,
+                  grad_terms=w)
+    want = phot + float(np.dot(w, ref["terms"]))
+
+    x = torch.from_numpy(rgba).to(dev).requires_grad_(True)
+    mp = torch.from_numpy(maps).to(dev).requires_grad_(True)
+    op = torch.from_numpy(m["opacity"]).to(dev).requires_grad_(True)
+    say(f"editable loss {H}x{W}")
+    loss = L.editable_loss(x, torch.from_numpy(target).to(dev), mp, op, cam, lam)
+    loss.backward()
+    got = float(loss.detach())
+    say(f"  loss {got:.7f} vs {want:.7f}")
+    assert abs(got - want) <= 1e-5 * abs(want) + 2e-5 * L.W_REG
+    check_grad(x.grad.cpu().numpy(), gphot, "d/dimage")
+    gm = mp.grad.cpu().numpy()
+    assert np.all(gm[0] == 0.0)
+    nrm = m["normal"].astype(np.float64)
+    lgap = np.linalg.norm(nrm / np.linalg.norm(nrm, axis=0) - ref["pseudo_normal"], axis=0)
+    keep = ~(ref["valid"] & (lgap < 0.05))
+    check_grad(gm[1:4][:, keep], ref["grad_normal"][:, keep], "d/dnormal map")
+    check_grad(gm[4:7], ref["grad_delta_c"], "d/ddelta-c map")
+    check_grad(gm[7:11], ref["grad_shade"], "d/dshade maps")
+    check_grad(op.grad.cpu().numpy(), ref["grad_opacity"], "d/dopacity")
