@@ -151,7 +151,7 @@ __global__ __launch_bounds__(kTilePix) void k_aux_fwd(ivrgs_batch b, Consts k, c
                 src[g] = valid ? sl + g : sl;
                 const float4 fa = S.f0[src[g]], fc = S.f1[src[g]];
                 const float p2 = splat_exponent(fa.z, fa.w, fc.x, px - fa.x, py - fa.y);
-                pass[g] = valid & (p2 >= fc.w);  // below the cutoff alpha < alpha_min is certain
+                pass[g] = valid;  // the alpha test decides (below the cutoff alpha < alpha_min)
                 al[g] = fminf(k.alpha_max, fc.y * fast_exp2(p2));
             }
             bool any = false;
@@ -296,8 +296,9 @@ __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, c
                     if (4 * q + 3 < kN) d = fmaf(g[4 + 4 * q], a4.w, d);
                 }
                 ga[gg] = d;
-                // below the cutoff alpha < alpha_min is certain
-                use[gg] = valid[gg] & (p2 >= fc.w) & (al[gg] >= k.alpha_min);
+                // the alpha test alone (below the cutoff alpha < alpha_min
+                // is certain: the two decide the same)
+                use[gg] = valid[gg] & (al[gg] >= k.alpha_min);
                 // no gradient through alpha where the cap is active
                 free_a[gg] = raw[gg] <= k.alpha_max;
             }
@@ -312,9 +313,9 @@ __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, c
                 gP = fmaf(w, ga[gg], gP);
                 const float dA = fmaf(gP - gA, inv[gg], T * ga[gg]);
                 const float dLdo = (comp & free_a[gg]) ? dA : 0.f;
-                const float dp = dLdo * raw[gg];
+                const float dp = dLdo * G[gg];  // D without the factor o'
                 float *v = acc + gg * kVpr;
-                v[0] = dLdo * G[gg];  // GO
+                v[0] = dp;  // GO
                 const float dpx = dp * dx[gg], dpy = dp * dy[gg];
                 v[1] = dpx;           // GX
                 v[2] = dpy;           // GY

@@ -40,10 +40,11 @@ constexpr float kLn2 = 0.6931471805599453f;
 // Record word indices.
 enum { RX = 0, RY, RQA, RQB, RQC, RO, RCR, RCG, RCB, RZ, RCUT, RPAD, RRECT0, RRECT1, RPAD1, RPAD2 };
 // Record-gradient rows (kGradStride floats per record).  With d = pixel
-// centre - screen mean and D = dL/do' * o' G summed over the record's
-// composited pixels: GX, GY = sum D dx, sum D dy; GQA, GQB, GQC = sum D dx^2,
-// D dx dy, D dy^2 (moments; the conic and ln 2 are applied once per record
-// by the projection backward); GO = dL/do'; GCR..GCB = dL/d(rgb).  GZ, past
+// centre - screen mean and D = dL/do'' * G (o'' = o' G the record's power at
+// the pixel, o' its opacity) summed over the record's composited pixels:
+// GX, GY = sum D dx, sum D dy; GQA, GQB, GQC = sum D dx^2, D dx dy, D dy^2
+// (moments; the opacity o', the conic and ln 2 are applied once per record
+// by the projection backward); GO = dL/do' = sum D; GCR..GCB = dL/d(rgb).  GZ, past
 // the image's components, is dL/d(depth) of the auxiliary maps (their depth
 // channel composites each record's camera-space depth).
 enum { GX = 0, GY, GQA, GQB, GQC, GO, GCR, GCG, GCB, GZ };

@@ -419,6 +419,9 @@ __global__ __launch_bounds__(256) void k_project_bwd(ivrgs_batch b, Consts k, co
     camera_center(cam, cpos);
     Fwd f;
     forward_gaussian(a, cam, cpos, e, k.lowpass, f);
+    // the moments were summed without the record's opacity factor
+#pragma unroll
+    for (int i = GX; i <= GQC; ++i) gr[i] *= a.o;
 
     float g_mu[3] = {0.f, 0.f, 0.f}, g_ls[3], g_q[4], g_n[3], g_c[3], g_k[4];
     const float g_o = gr[GO];

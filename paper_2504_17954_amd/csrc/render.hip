@@ -317,8 +317,10 @@ __device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__r
                 src[g] = valid ? sl + g : sl;
                 const float4 a = slots.f[src[g]][0], b = slots.f[src[g]][1], c = slots.f[src[g]][2];
                 const float p2 = splat_exponent(a.z, a.w, b.x, px - a.x, py - a.y);
-                // below the cutoff alpha < alpha_min is certain
-                pass[g] = valid & (p2 >= b.y);
+                // no separate cutoff test: below the cutoff (1e-3 under
+                // log2(alpha_min / o')) alpha < alpha_min is certain, so the
+                // alpha test below decides the same
+                pass[g] = valid;
                 al[g] = fminf(k.alpha_max, b.z * fast_exp2(p2));
                 cr[g] = b.w;
                 cg[g] = c.x;
@@ -658,9 +660,9 @@ __device__ __forceinline__ void bwd_tile_wave(const Consts &k, const float4 *__r
                     ag[GCR] = fmaf(w, g0[j], ag[GCR]);
                     ag[GCG] = fmaf(w, g1[j], ag[GCG]);
                     ag[GCB] = fmaf(w, g2[j], ag[GCB]);
-                    ag[GO] = fmaf(dLdo, G, ag[GO]);
-                    // moments of dL/dG G about the mean (see GX .. GQC)
-                    const float dp = dLdo * raw;
+                    // moments of dL/do' G about the mean (see GX .. GQC)
+                    const float dp = dLdo * G;
+                    ag[GO] += dp;
                     ag[GQA] = fmaf(dp, dx[j] * dx[j], ag[GQA]);
                     ag[GQB] = fmaf(dp, dx[j] * dy[j], ag[GQB]);
                     ag[GQC] = fmaf(dp, dy[j] * dy[j], ag[GQC]);
@@ -827,8 +829,9 @@ __device__ __forceinline__ void bwd_tile_quad(const Consts &k, const float4 *__r
                 om[g] = 1.f - al[g];
                 inv[g] = __builtin_amdgcn_rcpf(om[g]);
                 gc[g] = fmaf(g2, c.y, fmaf(g1, c.x, g0 * b.w));
-                // below the cutoff alpha < alpha_min is certain
-                use[g] = valid[g] & (p2 >= b.y) & (al[g] >= k.alpha_min);
+                // the alpha test alone (below the cutoff alpha < alpha_min
+                // is certain: the two decide the same)
+                use[g] = valid[g] & (al[g] >= k.alpha_min);
                 // no gradient through alpha where the cap is active
                 free_a[g] = raw[g] <= k.alpha_max;
                 idf[g] = c.z;
@@ -845,12 +848,13 @@ __device__ __forceinline__ void bwd_tile_quad(const Consts &k, const float4 *__r
                 gP = fmaf(w, gc[g], gP);
                 const float dLda = fmaf(gP - goA, inv[g], T * gc[g]);
                 const float dLdo = (comp & free_a[g]) ? dLda : 0.f;
-                const float dp = dLdo * raw[g];
+                // D without the factor o' (the projection backward applies it)
+                const float dp = dLdo * G[g];
                 float *ag = acc + g * kGradRec;
                 ag[GCR] = w * g0;
                 ag[GCG] = w * g1;
                 ag[GCB] = w * g2;
-                ag[GO] = dLdo * G[g];
+                ag[GO] = dp;
                 // moments of dL/dG G about the mean (see GX .. GQC)
                 const float dpx = dp * dx[g], dpy = dp * dy[g];
                 ag[GX] = dpx;
