@@ -659,6 +659,28 @@ ivrgs_status ivrgs_photometric_grad(const float *x, const float *y, int32_t chan
                                     int32_t width, float lam, float *grad_x, const void *workspace,
                                     size_t workspace_bytes, void *stream);
 
+/* Both means of the photometric loss in one pass over x and y (Sec. 4.2):
+ * out_means (device float[2]) gets the mean SSIM as above and, in [1], the
+ * mean |x - y| over all channels x height x width values (per workgroup an
+ * FP32 sum over its pixels, the workgroups added in FP64 in a fixed order:
+ * deterministic).  Workspace: ivrgs_photometric_workspace_size bytes (that
+ * of ivrgs_ssim_fwd plus one float per workgroup; 0 for invalid shapes),
+ * laid out so that ivrgs_photometric_grad and ivrgs_photometric_grad_dev
+ * take it as an SSIM forward's.  Errors as ivrgs_ssim_fwd. */
+size_t ivrgs_photometric_workspace_size(int32_t channels, int32_t height, int32_t width);
+ivrgs_status ivrgs_photometric_fwd(const float *x, const float *y, int32_t channels, int32_t height, int32_t width,
+                                   float *out_means, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Gradient with respect to x of weights[0] * (mean SSIM) + weights[1] *
+ * (mean |x - y|), weights device float[2] (a training loop's upstream
+ * gradient times the loss weights, never read on the host): the L1 + D-SSIM
+ * loss of ivrgs_photometric_grad with lam is weights (-lam, 1 - lam).  Same
+ * workspace, layout and error behaviour as ivrgs_photometric_grad; grad_x
+ * overwritten.  One launch. */
+ivrgs_status ivrgs_photometric_grad_dev(const float *x, const float *y, int32_t channels, int32_t height,
+                                        int32_t width, const float *weights, float *grad_x, const void *workspace,
+                                        size_t workspace_bytes, void *stream);
+
 /* ---- Training regularisers on the rendered maps (Eq. 5-7, Sec. 4.3) -------
  * The editable stage's regularisers of one view (the appendix weights them
  * 0.01 each, the opacity L1 0.1):
@@ -705,10 +727,12 @@ ivrgs_status ivrgs_reg_fwd(const ivrgs_reg_maps *maps, const ivrgs_camera *camer
  * terms: the out_terms of the forward on the same maps) with respect to the
  * normal map, the offset-colour map, the shading maps and the opacities;
  * each output (device, the layout of its input, or NULL to skip) is
- * overwritten.  The depth, alpha and target get no gradient.  One launch. */
+ * overwritten.  The depth, alpha and target get no gradient; grad_depth
+ * (device [H][W], or NULL) is written with zeros, for a caller whose maps'
+ * gradient is one buffer with the depth channel in it.  One launch. */
 ivrgs_status ivrgs_reg_bwd(const ivrgs_reg_maps *maps, const ivrgs_camera *camera, const float *terms,
                            const float *grad_terms, float *grad_normal, float *grad_delta_c, float *grad_shade,
-                           float *grad_opacity, void *stream);
+                           float *grad_opacity, float *grad_depth, void *stream);
 
 /* ---- SH colour (base 3DGS, Sec. 3 and Sec. 4.2) ---------------------------
  * The base model's view-dependent colour is parameterised by spherical-

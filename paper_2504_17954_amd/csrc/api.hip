@@ -492,6 +492,31 @@ ivrgs_status ivrgs_photometric_grad(const float *x, const float *y, int32_t chan
                                               reinterpret_cast<hipStream_t>(stream)));
 }
 
+size_t ivrgs_photometric_workspace_size(int32_t channels, int32_t height, int32_t width) {
+    if (!ssim_shape_ok(channels, height, width)) return 0;
+    return sizeof(float) * photometric_workspace_floats(channels, height, width);
+}
+
+ivrgs_status ivrgs_photometric_fwd(const float *x, const float *y, int32_t channels, int32_t height, int32_t width,
+                                   float *out_means, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!x || !y || !out_means || !workspace) return IVRGS_E_INVALID;
+    if (!ssim_shape_ok(channels, height, width)) return IVRGS_E_SHAPE;
+    if (workspace_bytes < ivrgs_photometric_workspace_size(channels, height, width)) return IVRGS_E_CAPACITY;
+    return hip_status(launch_photometric_fwd(x, y, channels, height, width, out_means,
+                                             static_cast<float *>(workspace), reinterpret_cast<hipStream_t>(stream)));
+}
+
+ivrgs_status ivrgs_photometric_grad_dev(const float *x, const float *y, int32_t channels, int32_t height,
+                                        int32_t width, const float *weights, float *grad_x, const void *workspace,
+                                        size_t workspace_bytes, void *stream) {
+    if (!x || !y || !weights || !grad_x || !workspace) return IVRGS_E_INVALID;
+    if (!ssim_shape_ok(channels, height, width)) return IVRGS_E_SHAPE;
+    if (workspace_bytes < ivrgs_ssim_workspace_size(channels, height, width)) return IVRGS_E_CAPACITY;
+    return hip_status(launch_photometric_grad_dev(x, y, channels, height, width, weights, grad_x,
+                                                  static_cast<const float *>(workspace),
+                                                  reinterpret_cast<hipStream_t>(stream)));
+}
+
 size_t ivrgs_l1_workspace_size(int64_t n) { return n > 0 ? sizeof(double) * (size_t)l1_blocks(n) : 0; }
 
 ivrgs_status ivrgs_l1_fwd(const float *x, const float *y, int64_t n, float *out_mean, void *workspace,
@@ -908,7 +933,7 @@ ivrgs_status ivrgs_reg_fwd(const ivrgs_reg_maps *maps, const ivrgs_camera *camer
 
 ivrgs_status ivrgs_reg_bwd(const ivrgs_reg_maps *maps, const ivrgs_camera *camera, const float *terms,
                            const float *grad_terms, float *grad_normal, float *grad_delta_c, float *grad_shade,
-                           float *grad_opacity, void *stream) {
+                           float *grad_opacity, float *grad_depth, void *stream) {
     const ivrgs_status st = check_reg_maps(maps);
     if (st != IVRGS_OK) return st;
     if (!camera || !terms || !grad_terms) return IVRGS_E_INVALID;
@@ -916,7 +941,7 @@ ivrgs_status ivrgs_reg_bwd(const ivrgs_reg_maps *maps, const ivrgs_camera *camer
         (grad_opacity && !maps->opacity))
         return IVRGS_E_INVALID;
     return hip_status(launch_reg_bwd(*maps, *camera, terms, grad_terms, grad_normal, grad_delta_c, grad_shade,
-                                     grad_opacity, reinterpret_cast<hipStream_t>(stream)));
+                                     grad_opacity, grad_depth, reinterpret_cast<hipStream_t>(stream)));
 }
 
 int32_t ivrgs_struct_size(int32_t which) {

@@ -155,13 +155,21 @@ hipError_t launch_l1_bwd(const float *x, const float *y, int64_t n, const float 
                          hipStream_t s);
 hipError_t launch_photometric_grad(const float *x, const float *y, int channels, int H, int W, float lam,
                                    float *grad_x, const float *ws, hipStream_t s);
+// SSIM and L1 means in one pass over x and y (out[0], out[1]); the workspace
+// is the SSIM forward's plus one L1 partial per workgroup.
+size_t photometric_workspace_floats(int channels, int H, int W);
+hipError_t launch_photometric_fwd(const float *x, const float *y, int channels, int H, int W, float *out, float *ws,
+                                  hipStream_t s);
+// Gradient of weights[0] mean SSIM + weights[1] mean |x - y| (device weights).
+hipError_t launch_photometric_grad_dev(const float *x, const float *y, int channels, int H, int W,
+                                       const float *weights, float *grad_x, const float *ws, hipStream_t s);
 // Training regularisers on the rendered maps of one view (normal
 // consistency, offset-colour sparsity, bilateral smoothness, opacity L1).
 size_t reg_workspace_bytes(const ivrgs_reg_maps &m);
 hipError_t launch_reg_fwd(const ivrgs_reg_maps &m, const ivrgs_camera &cam, float *terms, float *pseudo, void *ws,
                           hipStream_t s);
 hipError_t launch_reg_bwd(const ivrgs_reg_maps &m, const ivrgs_camera &cam, const float *terms, const float *gterm,
-                          float *g_normal, float *g_dc, float *g_shade, float *g_op, hipStream_t s);
+                          float *g_normal, float *g_dc, float *g_shade, float *g_op, float *g_depth, hipStream_t s);
 hipError_t launch_work_queue(const uint32_t *starts, int64_t n_tiles, uint32_t *queue, hipStream_t s);
 
 }  // namespace ivrgs

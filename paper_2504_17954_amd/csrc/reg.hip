@@ -203,11 +203,12 @@ __global__ __launch_bounds__(kRegBlock) void k_reg_reduce(const float *__restric
 
 // Gradients of sum_k g[k] term_k (g = grad_terms, device) with respect to the
 // normal, offset-colour and shading maps and the opacities; the valid pixel
-// count is the forward's terms[4].  Outputs are overwritten.
+// count is the forward's terms[4].  Outputs are overwritten; g_depth (the
+// depth map gets no gradient) with zeros.
 __global__ __launch_bounds__(kRegBlock) void k_reg_bwd(RegView v, int64_t pix_blocks, const float *__restrict__ terms,
                                                        const float *__restrict__ gterm, float *__restrict__ g_normal,
                                                        float *__restrict__ g_dc, float *__restrict__ g_shade,
-                                                       float *__restrict__ g_op) {
+                                                       float *__restrict__ g_op, float *__restrict__ g_depth) {
     const int64_t plane = (int64_t)v.H * v.W;
     if ((int64_t)blockIdx.x >= pix_blocks) {
         const int64_t i = ((int64_t)blockIdx.x - pix_blocks) * kRegBlock + threadIdx.x;
@@ -217,6 +218,7 @@ __global__ __launch_bounds__(kRegBlock) void k_reg_bwd(RegView v, int64_t pix_bl
     const int64_t p = (int64_t)blockIdx.x * kRegBlock + threadIdx.x;
     if (p >= plane) return;
     const int y = (int)(p / v.W), x = (int)(p - (int64_t)y * v.W);
+    if (g_depth) g_depth[p] = 0.f;
     if (g_normal) {
         float g[3] = {0.f, 0.f, 0.f};
         const float cnt = terms[4];
@@ -318,11 +320,11 @@ hipError_t launch_reg_fwd(const ivrgs_reg_maps &m, const ivrgs_camera &cam, floa
 }
 
 hipError_t launch_reg_bwd(const ivrgs_reg_maps &m, const ivrgs_camera &cam, const float *terms, const float *gterm,
-                          float *g_normal, float *g_dc, float *g_shade, float *g_op, hipStream_t s) {
+                          float *g_normal, float *g_dc, float *g_shade, float *g_op, float *g_depth, hipStream_t s) {
     const RegView v = make_view(m, cam);
     const int64_t pb = pixel_blocks(m), blocks = pb + gauss_blocks(m);
     hipLaunchKernelGGL(k_reg_bwd, dim3((unsigned)blocks), dim3(kRegBlock), 0, s, v, pb, terms, gterm, g_normal,
-                       g_dc, g_shade, g_op);
+                       g_dc, g_shade, g_op, g_depth);
     return hipGetLastError();
 }
 

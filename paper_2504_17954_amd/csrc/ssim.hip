@@ -39,10 +39,10 @@ constexpr float kC1 = 0.01f * 0.01f, kC2 = 0.03f * 0.03f;
 
 __global__ __launch_bounds__(256) void k_ssim_fwd(const float *__restrict__ x, const float *__restrict__ y, int H,
                                                   int W, SsimTaps taps, float *__restrict__ abc,
-                                                  float *__restrict__ partial) {
+                                                  float *__restrict__ partial, float *__restrict__ partial_l1) {
     __shared__ float sx[kReg][kReg + 1], sy[kReg][kReg + 1];
     __shared__ float hs[5][kReg][kSsimTile];
-    __shared__ float wsum[4];
+    __shared__ float wsum[4], wl1[4];
     const int Ho = H - kWin + 1, Wo = W - kWin + 1;
     const int ox0 = blockIdx.x * kSsimTile, oy0 = blockIdx.y * kSsimTile, c = blockIdx.z;
     const int64_t plane = (int64_t)H * W;
@@ -101,30 +101,62 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float *__restrict__ x, c
         o[wp + at] = B;
         o[2 * wp + at] = C;
     }
-    // workgroup sum of S, lanes then waves in a fixed order
+    // the L1 term over the pixels this workgroup owns: its 16x16 tile, and
+    // for the last tile of a row or column also the pixels past it (at most
+    // 26 in all, inside the staged region)
+    float l1 = 0.0f;
+    if (partial_l1) {
+        const int nx = (blockIdx.x + 1 == gridDim.x) ? W - ox0 : kSsimTile;
+        const int ny = (blockIdx.y + 1 == gridDim.y) ? H - oy0 : kSsimTile;
+        for (int i = t; i < nx * ny; i += 256) {
+            const int r = i / nx, q = i - r * nx;
+            l1 += fabsf(sx[r][q] - sy[r][q]);
+        }
+    }
+    // workgroup sums of S and of |x - y|, lanes then waves in a fixed order
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) S += __shfl_xor(S, d, 64);
-    if ((t & 63) == 0) wsum[t >> 6] = S;
+    for (int d = 32; d >= 1; d >>= 1) {
+        S += __shfl_xor(S, d, 64);
+        l1 += __shfl_xor(l1, d, 64);
+    }
+    if ((t & 63) == 0) {
+        wsum[t >> 6] = S;
+        wl1[t >> 6] = l1;
+    }
     __syncthreads();
-    if (t == 0)
-        partial[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] =
-            ((wsum[0] + wsum[1]) + (wsum[2] + wsum[3]));
+    if (t == 0) {
+        const int64_t b = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        partial[b] = ((wsum[0] + wsum[1]) + (wsum[2] + wsum[3]));
+        if (partial_l1) partial_l1[b] = ((wl1[0] + wl1[1]) + (wl1[2] + wl1[3]));
+    }
 }
 
 // One workgroup: the partials in a fixed order (FP64), divided by the
-// number of windows.
-__global__ __launch_bounds__(256) void k_ssim_reduce(const float *__restrict__ partial, int64_t n, double inv,
-                                                     float *__restrict__ out) {
-    __shared__ double red[256];
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 256) s += (double)partial[i];
+// number of windows; with partial_l1, also the L1 partials divided by the
+// number of values, into out[1].
+__global__ __launch_bounds__(256) void k_ssim_reduce(const float *__restrict__ partial,
+                                                     const float *__restrict__ partial_l1, int64_t n, double inv,
+                                                     double inv_n, float *__restrict__ out) {
+    __shared__ double red[256], red1[256];
+    double s = 0.0, s1 = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        s += (double)partial[i];
+        if (partial_l1) s1 += (double)partial_l1[i];
+    }
     red[threadIdx.x] = s;
+    red1[threadIdx.x] = s1;
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        if ((int)threadIdx.x < w) {
+            red[threadIdx.x] += red[threadIdx.x + w];
+            red1[threadIdx.x] += red1[threadIdx.x + w];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[0] = (float)(red[0] * inv);
+    if (threadIdx.x == 0) {
+        out[0] = (float)(red[0] * inv);
+        if (partial_l1) out[1] = (float)(red1[0] * inv_n);
+    }
 }
 
 // Pixel tile [qy0, qy0 + 16) x [qx0, qx0 + 16): the windows that cover it
@@ -135,7 +167,8 @@ __global__ __launch_bounds__(256) void k_ssim_reduce(const float *__restrict__ p
 __global__ __launch_bounds__(256) void k_ssim_bwd(const float *__restrict__ x, const float *__restrict__ y, int H,
                                                   int W, SsimTaps taps, const float *__restrict__ abc,
                                                   const float *__restrict__ grad_mean, double inv,
-                                                  float ssim_w, float l1_w, float *__restrict__ grad_x) {
+                                                  float ssim_w, float l1_w, const float *__restrict__ dev_w,
+                                                  double inv_n, float *__restrict__ grad_x) {
     __shared__ float sa[3][kReg][kReg + 1];
     __shared__ float hs[3][kReg][kSsimTile];
     const int Ho = H - kWin + 1, Wo = W - kWin + 1;
@@ -181,8 +214,12 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float *__restrict__ x, c
     }
     const int64_t at = (int64_t)c * H * W + (int64_t)qy * W + qx;
     const float xq = x[at], yq = y[at];
-    // dL/d(mean SSIM) from the device (ivrgs_ssim_bwd) or the host weight
-    const float scale = (float)((grad_mean ? (double)grad_mean[0] : (double)ssim_w) * inv);
+    // dL/d(mean SSIM) from the device (ivrgs_ssim_bwd; dev_w[0] of
+    // ivrgs_photometric_grad_dev) or the host weight; the L1 weight per value
+    // from the host or dev_w[1]
+    const float scale =
+        (float)((grad_mean ? (double)grad_mean[0] : (dev_w ? (double)dev_w[0] : (double)ssim_w)) * inv);
+    if (dev_w) l1_w = (float)((double)dev_w[1] * inv_n);
     float gq = scale * (bA + 2.0f * xq * bB + yq * bC);
     // the L1 term: l1_w sign(x - y), with sign(0) = 0
     if (l1_w != 0.0f) gq = fmaf(l1_w, (float)((xq > yq) - (xq < yq)), gq);
@@ -215,10 +252,28 @@ hipError_t launch_ssim_fwd(const float *x, const float *y, int channels, int H, 
     const int Ho = H - kWin + 1, Wo = W - kWin + 1;
     const dim3 grid((Wo + kSsimTile - 1) / kSsimTile, (Ho + kSsimTile - 1) / kSsimTile, channels);
     float *abc = ws, *partial = ws + (size_t)3 * channels * Ho * Wo;
-    hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, s, x, y, H, W, ssim_taps(), abc, partial);
+    hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, s, x, y, H, W, ssim_taps(), abc, partial, nullptr);
     const int64_t n = (int64_t)grid.x * grid.y * grid.z;
-    hipLaunchKernelGGL(k_ssim_reduce, dim3(1), dim3(256), 0, s, partial, n,
-                       1.0 / ((double)channels * Ho * Wo), out);
+    hipLaunchKernelGGL(k_ssim_reduce, dim3(1), dim3(256), 0, s, partial, nullptr, n,
+                       1.0 / ((double)channels * Ho * Wo), 0.0, out);
+    return hipGetLastError();
+}
+
+size_t photometric_workspace_floats(int channels, int H, int W) {
+    const int64_t Ho = H - kWin + 1, Wo = W - kWin + 1;
+    const int64_t blocks = (int64_t)channels * ((Ho + kSsimTile - 1) / kSsimTile) * ((Wo + kSsimTile - 1) / kSsimTile);
+    return ssim_workspace_floats(channels, H, W) + (size_t)blocks;
+}
+
+hipError_t launch_photometric_fwd(const float *x, const float *y, int channels, int H, int W, float *out, float *ws,
+                                  hipStream_t s) {
+    const int Ho = H - kWin + 1, Wo = W - kWin + 1;
+    const dim3 grid((Wo + kSsimTile - 1) / kSsimTile, (Ho + kSsimTile - 1) / kSsimTile, channels);
+    const int64_t n = (int64_t)grid.x * grid.y * grid.z;
+    float *abc = ws, *partial = ws + (size_t)3 * channels * Ho * Wo, *partial_l1 = partial + n;
+    hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, s, x, y, H, W, ssim_taps(), abc, partial, partial_l1);
+    hipLaunchKernelGGL(k_ssim_reduce, dim3(1), dim3(256), 0, s, partial, partial_l1, n,
+                       1.0 / ((double)channels * Ho * Wo), 1.0 / ((double)channels * H * W), out);
     return hipGetLastError();
 }
 
@@ -227,7 +282,17 @@ hipError_t launch_ssim_bwd(const float *x, const float *y, int channels, int H, 
     const int Ho = H - kWin + 1, Wo = W - kWin + 1;
     const dim3 grid((W + kSsimTile - 1) / kSsimTile, (H + kSsimTile - 1) / kSsimTile, channels);
     hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, s, x, y, H, W, ssim_taps(), ws, grad_mean,
-                       1.0 / ((double)channels * Ho * Wo), 0.0f, 0.0f, grad_x);
+                       1.0 / ((double)channels * Ho * Wo), 0.0f, 0.0f, nullptr, 0.0, grad_x);
+    return hipGetLastError();
+}
+
+hipError_t launch_photometric_grad_dev(const float *x, const float *y, int channels, int H, int W,
+                                       const float *weights, float *grad_x, const float *ws, hipStream_t s) {
+    const int Ho = H - kWin + 1, Wo = W - kWin + 1;
+    const dim3 grid((W + kSsimTile - 1) / kSsimTile, (H + kSsimTile - 1) / kSsimTile, channels);
+    hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, s, x, y, H, W, ssim_taps(), ws, nullptr,
+                       1.0 / ((double)channels * Ho * Wo), 0.0f, 0.0f, weights, 1.0 / ((double)channels * H * W),
+                       grad_x);
     return hipGetLastError();
 }
 
@@ -239,7 +304,7 @@ hipError_t launch_photometric_grad(const float *x, const float *y, int channels,
     // with weight -lam, each |x - y| with (1 - lam) / (channels H W)
     const float l1_w = (float)((1.0 - (double)lam) / ((double)channels * H * W));
     hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, s, x, y, H, W, ssim_taps(), ws, nullptr,
-                       1.0 / ((double)channels * Ho * Wo), -lam, l1_w, grad_x);
+                       1.0 / ((double)channels * Ho * Wo), -lam, l1_w, nullptr, 0.0, grad_x);
     return hipGetLastError();
 }
 

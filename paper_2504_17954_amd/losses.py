@@ -255,31 +255,31 @@ def _editable_weights(device, lam: float) -> torch.Tensor:
 
 
 class _EditableLossFn(torch.autograd.Function):
-    """The editable-stage loss of one view: the SSIM and L1 kernels and the
-    regulariser kernels write their terms into one device vector, which one
-    dot product with the weights combines.  Backward: the photometric
-    gradient of the image, and the regularisers' gradients of the normal,
-    offset-colour and shading maps and the opacities (none to the depth
-    map, the alpha map or the target)."""
+    """The editable-stage loss of one view: one kernel pass gives the SSIM
+    and L1 means (ivrgs_photometric_fwd), the regulariser kernels add their
+    four terms into the same device vector, and one dot product with the
+    weights combines them.  Backward: the upstream gradient times the
+    weights (one device vector), the photometric gradient of the image with
+    those weights (ivrgs_photometric_grad_dev) and the regularisers'
+    gradients of the maps (written into one buffer, zeros for the depth
+    channel) and the opacities."""
 
     @staticmethod
     def forward(ctx, rgba, target, maps, opacity, cam, lam):
         c, h, w = (int(v) for v in rgba.shape)
         dev = rgba.device
-        nbytes = N.ivrgs_ssim_workspace_size(c, h, w)
+        nbytes = N.ivrgs_photometric_workspace_size(c, h, w)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         # [SSIM, L1, the four regulariser terms, valid-pixel count, unused]
         terms = torch.empty(8, dtype=torch.float32, device=dev)
         base = terms.data_ptr()
-        N.ivrgs_ssim_fwd(rgba.data_ptr(), target.data_ptr(), c, h, w, base, ws.data_ptr(), nbytes, _stream())
-        l1w = torch.empty(N.ivrgs_l1_workspace_size(rgba.numel()), dtype=torch.uint8, device=dev)
-        N.ivrgs_l1_fwd(rgba.data_ptr(), target.data_ptr(), rgba.numel(), base + 4, l1w.data_ptr(), l1w.numel(),
-                       _stream())
+        N.ivrgs_photometric_fwd(rgba.data_ptr(), target.data_ptr(), c, h, w, base, ws.data_ptr(), nbytes,
+                                _stream())
         m = _reg_maps(maps[0], rgba[3], maps[1:4], maps[4:7], maps[7:11], target[:3], opacity)
         rws = torch.empty(max(N.ivrgs_reg_workspace_size(m), 1), dtype=torch.uint8, device=dev)
         N.ivrgs_reg_fwd(m, camera_struct(cam), base + 8, None, rws.data_ptr(), rws.numel(), _stream())
         wv = _editable_weights(dev, lam)
-        ctx.cam, ctx.lam = cam, lam
+        ctx.cam = cam
         ctx.save_for_backward(rgba, target, maps, opacity, ws, terms, wv)
         return torch.dot(terms[:6], wv) + lam
 
@@ -287,17 +287,16 @@ class _EditableLossFn(torch.autograd.Function):
     def backward(ctx, g):
         rgba, target, maps, opacity, ws, terms, wv = ctx.saved_tensors
         c, h, w = (int(v) for v in rgba.shape)
+        gw = wv * g  # dL/d(each term)
         gx = torch.empty_like(rgba)
-        N.ivrgs_photometric_grad(rgba.data_ptr(), target.data_ptr(), c, h, w, ctx.lam, gx.data_ptr(),
-                                 ws.data_ptr(), ws.numel(), _stream())
-        gx.mul_(g)
-        g_terms = (wv[2:] * g).contiguous()
+        N.ivrgs_photometric_grad_dev(rgba.data_ptr(), target.data_ptr(), c, h, w, gw.data_ptr(), gx.data_ptr(),
+                                     ws.data_ptr(), ws.numel(), _stream())
         gmaps = torch.empty_like(maps)
-        gmaps[0].zero_()
         gop = torch.empty_like(opacity)
         m = _reg_maps(maps[0], rgba[3], maps[1:4], maps[4:7], maps[7:11], target[:3], opacity)
-        N.ivrgs_reg_bwd(m, camera_struct(ctx.cam), terms.data_ptr() + 8, g_terms.data_ptr(),
-                        gmaps[1].data_ptr(), gmaps[4].data_ptr(), gmaps[7].data_ptr(), gop.data_ptr(), _stream())
+        N.ivrgs_reg_bwd(m, camera_struct(ctx.cam), terms.data_ptr() + 8, gw.data_ptr() + 8,
+                        gmaps[1].data_ptr(), gmaps[4].data_ptr(), gmaps[7].data_ptr(), gop.data_ptr(), _stream(),
+                        gmaps[0].data_ptr())
         return gx, None, gmaps, gop, None, None
 
 

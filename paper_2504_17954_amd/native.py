@@ -31,7 +31,8 @@ EXPORTS = ("ivrgs_workspace_size", "ivrgs_tiles_per_job", "ivrgs_compose", "ivrg
            "ivrgs_vq_fit_batch_workspace_size", "ivrgs_vq_fit_batch", "ivrgs_photometric_grad",
            "ivrgs_reg_workspace_size", "ivrgs_reg_fwd", "ivrgs_reg_bwd", "ivrgs_bin_sort_noalloc",
            "ivrgs_l1_workspace_size", "ivrgs_l1_fwd", "ivrgs_l1_bwd", "ivrgs_editable_attr_fwd",
-           "ivrgs_editable_attr_bwd", "ivrgs_render_bwd_aux")
+           "ivrgs_editable_attr_bwd", "ivrgs_render_bwd_aux",
+           "ivrgs_photometric_workspace_size", "ivrgs_photometric_fwd", "ivrgs_photometric_grad_dev")
 NOALLOC_SCRATCH_BYTES = 64 << 20
 TIMING_KINDS = ("project", "tile_count", "scatter", "depth_sort", "render_fwd", "render_bwd",
                 "project_bwd", "compose", "fill", "cull", "edit_bwd", "vq", "sh", "aux")
@@ -201,6 +202,12 @@ def load(path: str = LIB_PATH):
     lib.ivrgs_ssim_bwd.restype = C.c_int
     lib.ivrgs_photometric_grad.argtypes = [P, P, I32, I32, I32, C.c_float, P, P, C.c_size_t, P]
     lib.ivrgs_photometric_grad.restype = C.c_int
+    lib.ivrgs_photometric_workspace_size.argtypes = [I32, I32, I32]
+    lib.ivrgs_photometric_workspace_size.restype = C.c_size_t
+    lib.ivrgs_photometric_fwd.argtypes = [P, P, I32, I32, I32, P, P, C.c_size_t, P]
+    lib.ivrgs_photometric_fwd.restype = C.c_int
+    lib.ivrgs_photometric_grad_dev.argtypes = [P, P, I32, I32, I32, P, P, P, C.c_size_t, P]
+    lib.ivrgs_photometric_grad_dev.restype = C.c_int
     lib.ivrgs_l1_workspace_size.argtypes = [C.c_int64]
     lib.ivrgs_l1_workspace_size.restype = C.c_size_t
     lib.ivrgs_l1_fwd.argtypes = [P, P, C.c_int64, P, P, C.c_size_t, P]
@@ -211,7 +218,7 @@ def load(path: str = LIB_PATH):
     lib.ivrgs_reg_workspace_size.restype = C.c_size_t
     lib.ivrgs_reg_fwd.argtypes = [P, P, P, P, P, C.c_size_t, P]
     lib.ivrgs_reg_fwd.restype = C.c_int
-    lib.ivrgs_reg_bwd.argtypes = [P, P, P, P, P, P, P, P, P]
+    lib.ivrgs_reg_bwd.argtypes = [P, P, P, P, P, P, P, P, P, P]
     lib.ivrgs_reg_bwd.restype = C.c_int
     lib.ivrgs_get_error.argtypes = [P, P, P, P]
     lib.ivrgs_get_error.restype = C.c_int
@@ -375,6 +382,21 @@ def ivrgs_ssim_bwd(x_ptr, y_ptr, channels: int, height: int, width: int, grad_me
                                 ws_bytes, stream), "ivrgs_ssim_bwd")
 
 
+def ivrgs_photometric_workspace_size(channels: int, height: int, width: int) -> int:
+    return int(load().ivrgs_photometric_workspace_size(channels, height, width))
+
+
+def ivrgs_photometric_fwd(x_ptr, y_ptr, channels: int, height: int, width: int, out_ptr, ws_ptr, ws_bytes, stream):
+    check(load().ivrgs_photometric_fwd(x_ptr, y_ptr, channels, height, width, out_ptr, ws_ptr, ws_bytes, stream),
+          "ivrgs_photometric_fwd")
+
+
+def ivrgs_photometric_grad_dev(x_ptr, y_ptr, channels: int, height: int, width: int, weights_ptr, grad_x_ptr,
+                               ws_ptr, ws_bytes, stream):
+    check(load().ivrgs_photometric_grad_dev(x_ptr, y_ptr, channels, height, width, weights_ptr, grad_x_ptr, ws_ptr,
+                                            ws_bytes, stream), "ivrgs_photometric_grad_dev")
+
+
 def ivrgs_photometric_grad(x_ptr, y_ptr, channels: int, height: int, width: int, lam: float, grad_x_ptr,
                            ws_ptr, ws_bytes, stream):
     check(load().ivrgs_photometric_grad(x_ptr, y_ptr, channels, height, width, lam, grad_x_ptr, ws_ptr,
@@ -402,9 +424,10 @@ def ivrgs_reg_fwd(maps, camera, terms_ptr, pseudo_ptr, ws_ptr, ws_bytes, stream)
           "ivrgs_reg_fwd")
 
 
-def ivrgs_reg_bwd(maps, camera, terms_ptr, grad_terms_ptr, g_normal_ptr, g_dc_ptr, g_shade_ptr, g_op_ptr, stream):
+def ivrgs_reg_bwd(maps, camera, terms_ptr, grad_terms_ptr, g_normal_ptr, g_dc_ptr, g_shade_ptr, g_op_ptr, stream,
+                  g_depth_ptr=None):
     check(load().ivrgs_reg_bwd(ref(maps), ref(camera), terms_ptr, grad_terms_ptr, g_normal_ptr, g_dc_ptr,
-                               g_shade_ptr, g_op_ptr, stream), "ivrgs_reg_bwd")
+                               g_shade_ptr, g_op_ptr, g_depth_ptr, stream), "ivrgs_reg_bwd")
 
 
 def ivrgs_project(batch, params, proj, stream):

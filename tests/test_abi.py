@@ -120,6 +120,14 @@ def test_host_validation_of_ssim_and_error_query(lib):
     assert lib.ivrgs_l1_fwd(fake, fake, 10 ** 6, fake, fake, 8, None) == N.E_CAPACITY
     assert lib.ivrgs_l1_bwd(fake, fake, 10, None, fake, None) == N.E_INVALID
     assert lib.ivrgs_l1_bwd(fake, fake, -1, fake, fake, None) == N.E_SHAPE
+    # the photometric pass: the SSIM workspace plus one L1 partial per workgroup of windows
+    assert N.ivrgs_photometric_workspace_size(4, 800, 800) == 4 * (3 * 4 * 790 * 790 + 2 * 4 * 50 * 50)
+    assert N.ivrgs_photometric_workspace_size(2, 10, 40) == 0
+    assert lib.ivrgs_photometric_fwd(None, fake, 1, 20, 20, fake, fake, 1 << 20, None) == N.E_INVALID
+    assert lib.ivrgs_photometric_fwd(fake, fake, 1, 20, 9, fake, fake, 1 << 20, None) == N.E_SHAPE
+    assert lib.ivrgs_photometric_fwd(fake, fake, 1, 20, 20, fake, fake, 16, None) == N.E_CAPACITY
+    assert lib.ivrgs_photometric_grad_dev(fake, fake, 1, 20, 20, None, fake, fake, 1 << 20, None) == N.E_INVALID
+    assert lib.ivrgs_photometric_grad_dev(fake, fake, 1, 20, 20, fake, fake, fake, 16, None) == N.E_CAPACITY
     # the editable stage's attribute rows: 16-byte aligned rows, n = 0 a no-op
     assert lib.ivrgs_editable_attr_fwd(fake, fake, fake, -1, fake, None) == N.E_INVALID
     assert lib.ivrgs_editable_attr_fwd(None, fake, fake, 10, fake, None) == N.E_INVALID

@@ -60,9 +60,12 @@ def run_gpu(dev, m, cam, gterm, keys=("normal", "delta_c", "shade", "opacity")):
     N.ivrgs_reg_fwd(maps, c, terms.data_ptr(), pn.data_ptr(), ws.data_ptr(), ws.numel(), s)
     g = torch.tensor(gterm, dtype=torch.float32, device=dev)
     outs = {k: torch.full_like(d[k], float("nan")) for k in keys}
+    gdepth = torch.full_like(d["depth"], float("nan"))
     N.ivrgs_reg_bwd(maps, c, terms.data_ptr(), g.data_ptr(),
-                    *[outs[k].data_ptr() if k in outs else None for k in ("normal", "delta_c", "shade", "opacity")], s)
+                    *[outs[k].data_ptr() if k in outs else None for k in ("normal", "delta_c", "shade", "opacity")], s,
+                    gdepth.data_ptr())
     torch.cuda.synchronize()
+    assert bool((gdepth == 0).all())  # no gradient to the depth map: written as zeros
     return terms.cpu().numpy(), pn.cpu().numpy(), {k: v.cpu().numpy() for k, v in outs.items()}
 
 
@@ -131,7 +134,7 @@ def test_regularisers_edge_cases(dev):
     assert lib.ivrgs_reg_workspace_size(N.ref(maps)) == 0
     maps.shade = None
     assert lib.ivrgs_reg_bwd(N.ref(maps), N.ref(L.camera_struct(cam)), 1, 1, 1, None, None, None,
-                             None) == N.E_INVALID
+                             None, None) == N.E_INVALID
 
 
 def test_editable_loss_regularisers_autograd(dev):

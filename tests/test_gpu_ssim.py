@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle as O
 from oracle import explore as OX
 from oracle import ssim as OS
 from paper_2504_17954_amd import losses as L
@@ -149,3 +150,40 @@ def test_photometric_grad_argument_errors(dev):
         N.ivrgs_photometric_grad(x.data_ptr(), x.data_ptr(), 4, 20, 9, 0.2, x.data_ptr(), ws.data_ptr(),
                                  nbytes, None)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("shape,seed", [((3, 11, 11), 21), ((4, 40, 52), 22), ((2, 27, 100), 23),
+                                        ((4, 171, 202), 24)])
+def test_photometric_fwd_and_device_weights_match_oracle(dev, shape, seed):
+    """ivrgs_photometric_fwd: the SSIM mean and the L1 mean from one pass
+    (the L1 over every pixel, the rows and columns past the last tile of
+    windows included) against the oracles; ivrgs_photometric_grad_dev: the
+    gradient of w0 SSIM + w1 L1 with the weights read on the device."""
+    x, y = pair(shape, seed)
+    y[:, :2, :3] = x[:, :2, :3]  # exact ties: sign(0) = 0 on both sides
+    c, h, w = shape
+    x64, y64 = x.astype(np.float64), y.astype(np.float64)
+    s_want, ds = OS.ssim_and_grad(x64, y64)
+    l1_want = O.l1_loss(x64, y64)
+    _, dl1 = OX.photometric(x64, y64, 0.0)  # gradient of the L1 mean
+    xd, yd = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+    nbytes = N.ivrgs_photometric_workspace_size(c, h, w)
+    assert nbytes >= N.ivrgs_ssim_workspace_size(c, h, w)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    out = torch.full((2,), float("nan"), device=dev)
+    N.ivrgs_photometric_fwd(xd.data_ptr(), yd.data_ptr(), c, h, w, out.data_ptr(), ws.data_ptr(), nbytes, None)
+    wts = (-0.37, 1.9)
+    wd = torch.tensor(wts, dtype=torch.float32, device=dev)
+    g = torch.full_like(xd, float("nan"))
+    N.ivrgs_photometric_grad_dev(xd.data_ptr(), yd.data_ptr(), c, h, w, wd.data_ptr(), g.data_ptr(),
+                                 ws.data_ptr(), nbytes, None)
+    s_got, l1_got = (float(v) for v in out.cpu())
+    say(f"photometric {shape}: SSIM {s_got:.7f} vs {s_want:.7f}, L1 {l1_got:.7f} vs {l1_want:.7f}")
+    assert abs(s_got - s_want) <= 1e-5
+    assert abs(l1_got - l1_want) <= 1e-5 * l1_want
+    gwant = wts[0] * ds + wts[1] * dl1
+    g = g.cpu().numpy()
+    tol = 1e-3 * np.abs(gwant) + 1e-5 * np.abs(gwant).max()
+    bad = np.abs(g - gwant) > tol
+    say(f"  gradient outside {bad.sum()} / {g.size}, worst {(np.abs(g - gwant) / tol).max():.3f}")
+    assert not bad.any()
