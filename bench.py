@@ -264,19 +264,27 @@ def main():
     log(f"fwd+bwd: {ms_step:.3f} ms/step, {value:.1f} it/s")
 
     # --------------------------------------------- algorithmic counts per view
+    # per view of the timed region (the rates below), and over every step of
+    # the run, warm-up and per-kernel pass included (what a profiler's
+    # per-dispatch averages over the whole run divide by)
     counts = {"pairs": [], "evaluated": [], "composited": []}
     cnt_settings = R.Settings(**{**rnd.settings.__dict__})
     cnt_settings.flags = N.FLAG_COUNT_EVAL
     cnt = R.Renderer(cnt_settings, capacity=rnd.capacity, check="sync")
+    run_views = [i % args.views for i in range(args.warmup + cal_steps)] + views
+    by_view = {}
     with torch.no_grad():
-        for v in sorted(set(views)):
+        for v in sorted(set(run_views)):
             cnt.forward({k: t.detach() for k, t in composed.items()}, cams_t, jobs[v], model_id=mid,
                         edits_t=edits_t)
             st = cnt.status.cpu().numpy()
-            counts["pairs"].append(int(st[0]))
-            counts["evaluated"].append(int(st[2]))
-            counts["composited"].append(int(st[3]))
+            by_view[v] = (int(st[0]), int(st[2]), int(st[3]))
+    for v in views:
+        counts["pairs"].append(by_view[v][0])
+        counts["evaluated"].append(by_view[v][1])
+        counts["composited"].append(by_view[v][2])
     per_view = {k: float(np.mean(v)) for k, v in counts.items()}
+    evaluated_run = float(np.mean([by_view[v][1] for v in run_views]))
     avg = {k: (ms / max(nl, 1), nl) for k, (ms, nl) in kern.items()}
     log("kernels (avg ms, launches; untimed pass): " + ", ".join(f"{k} {a:.4f}/{nl}" for k, (a, nl) in avg.items()
                                                                  if nl))
@@ -354,6 +362,7 @@ def main():
                    "views": args.views, "views_per_step": 1,
                    "pairs_per_view": round(per_view["pairs"]),
                    "evaluated_per_view": round(per_view["evaluated"]),
+                   "evaluated_per_step_of_run": round(evaluated_run),
                    "composited_per_view": round(per_view["composited"]),
                    "launch_shape": tuned},
         "roofline": roofline,

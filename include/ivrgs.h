@@ -591,6 +591,18 @@ ivrgs_status ivrgs_editable_attr_fwd(const float *normal, const float *color, co
 ivrgs_status ivrgs_editable_attr_bwd(const float *normal, int64_t n, const float *grad_attr, float *grad_normal,
                                      float *grad_color, float *grad_shade, void *stream);
 
+/* The image and the maps in one walk over the lists (the forward of a
+ * training step that reads both; Eq. 2 and Eq. 5): writes out_rgba exactly as
+ * ivrgs_render_fwd with one pixel per lane would (the same image, and the
+ * same list checkpoints in the workspace for the backward) and out_aux as
+ * ivrgs_render_aux_fwd (same layout and meaning; attr as there).  The
+ * workspace is needed when the render workspace holds checkpoints (long
+ * lists); IVRGS_E_CAPACITY if it is missing or small then.  IVRGS_E_INVALID
+ * for n_attr outside 0..15, a null output or unaligned attr. */
+ivrgs_status ivrgs_render_fwd_aux(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
+                                  const ivrgs_bins *bins, const float *attr, int32_t n_attr, float *out_rgba,
+                                  float *out_aux, void *workspace, size_t workspace_bytes, void *stream);
+
 /* The image's backward and the maps' backward in one call (the training
  * step of the editable stage differentiates both; Eq. 2 and Eq. 5): the
  * result of ivrgs_render_bwd for dl_drgba plus that of ivrgs_render_aux_bwd

@@ -120,7 +120,7 @@ def editable_attributes(planes: dict) -> torch.Tensor:
 
 class _EditableFn(torch.autograd.Function):
     """The image and the eleven maps of the editable stage from one
-    projection and binning.  Backward: one call takes the image's and the
+    projection and binning, in one walk (ivrgs_render_fwd_aux).  Backward: one call takes the image's and the
     maps' gradients to the planes and the attribute rows
     (ivrgs_render_bwd_aux); the rows' gradient then goes back to the normal,
     colour and shade planes (ivrgs_editable_attr_bwd), so the planes get one
@@ -129,18 +129,11 @@ class _EditableFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, renderer, cams_t, jobs, edits_t, *planes):
         pl = dict(zip(PLANES, planes))
-        rgba = renderer.forward(pl, cams_t, jobs, None, edits_t)
-        batch = renderer.make_batch(pl, None, edits_t, cams_t, jobs)
-        proj, bins = renderer._structs(batch)
         n = int(pl["mean"].shape[1])
         attr = torch.empty((n, EDITABLE_STRIDE), dtype=torch.float32, device=renderer.device)
         N.ivrgs_editable_attr_fwd(pl["normal"].data_ptr(), pl["color"].data_ptr(), pl["shade"].data_ptr(), n,
                                   attr.data_ptr(), _stream())
-        s = renderer.settings
-        maps = torch.empty((jobs.n_jobs, 1 + EDITABLE_ATTRS, s.height, s.width), dtype=torch.float32,
-                           device=renderer.device)
-        N.ivrgs_render_aux_fwd(batch, s.params(), proj, bins, attr.data_ptr(), EDITABLE_ATTRS, maps.data_ptr(),
-                               _stream())
+        rgba, maps = renderer.forward_maps(pl, cams_t, jobs, attr, EDITABLE_ATTRS, edits_t)
         ctx.renderer, ctx.jobs, ctx.generation = renderer, jobs, renderer.generation
         ctx.save_for_backward(cams_t, edits_t, rgba, attr, maps, *planes)
         return rgba, maps

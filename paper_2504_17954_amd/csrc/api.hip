@@ -827,6 +827,25 @@ ivrgs_status render_bwd_run(const ivrgs_batch *batch, const ivrgs_params *params
 
 extern "C" {
 
+ivrgs_status ivrgs_render_fwd_aux(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
+                                  const ivrgs_bins *bins, const float *attr, int32_t n_attr, float *out_rgba,
+                                  float *out_aux, void *workspace, size_t workspace_bytes, void *stream) {
+    ivrgs_status st = check_batch(batch);
+    if (st != IVRGS_OK) return st;
+    if ((st = check_params(params)) != IVRGS_OK) return st;
+    if (!proj || !bins || !bins->tile_start || !out_rgba || !out_aux || n_attr < 0 || n_attr > kAuxMax)
+        return IVRGS_E_INVALID;
+    if (n_attr > 0 && (!attr || (reinterpret_cast<uintptr_t>(attr) & 15u))) return IVRGS_E_INVALID;
+    const Consts k = make_consts(*params);
+    const Layout L = layout(*batch, *params);
+    if (L.ckpt_bytes && (!workspace || workspace_bytes < L.total)) return IVRGS_E_CAPACITY;
+    float *ckpt = L.ckpt_bytes ? reinterpret_cast<float *>(static_cast<char *>(workspace) + L.ckpt) : nullptr;
+    return hip_status(launch_render_fwd_maps(k, (int64_t)batch->n_jobs * k.tiles_per_job, proj->rec,
+                                             bins->tile_start, bins->sorted, out_rgba, ckpt, batch->jobs,
+                                             batch->gauss_index, attr, n_attr, out_aux,
+                                             reinterpret_cast<hipStream_t>(stream)));
+}
+
 ivrgs_status ivrgs_render_bwd(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
                               const ivrgs_bins *bins, const float *out_rgba, const float *dl_drgba,
                               ivrgs_gaussians_mut *grads, void *workspace, size_t workspace_bytes, void *stream) {

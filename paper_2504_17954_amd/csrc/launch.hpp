@@ -84,6 +84,13 @@ hipError_t set_bin_lds_limit(size_t bytes);
 hipError_t launch_render_fwd(const Consts &k, int px, int64_t n_tiles, const float *rec, const uint32_t *starts,
                              const uint32_t *sorted, float *out, float *maxw, int64_t *status, bool count,
                              uint32_t *queue, int per_cu, float *ckpt, hipStream_t s);
+// The image and the auxiliary maps (depth and n_attr <= 15 attributes, rows
+// of n_attr rounded up to 4 floats) in one walk, one pixel per lane, with the
+// list checkpoints of the image's backward when ckpt is given.
+hipError_t launch_render_fwd_maps(const Consts &k, int64_t n_tiles, const float *rec, const uint32_t *starts,
+                                  const uint32_t *sorted, float *out, float *ckpt, const ivrgs_job *jobs,
+                                  const int32_t *gauss_index, const float *attr, int n_attr, float *aux,
+                                  hipStream_t s);
 // Buffers of the deterministic backward (IVRGS_FLAG_DETERMINISTIC_BWD):
 // probe [n_tiles][kGradRec] words, scale 2 * kGradRec floats, gfix
 // [n_records][kGradStride] 64-bit integer sums.

@@ -209,6 +209,20 @@ struct WaveSlots {
     float4 f[64][3];
 };
 
+// The auxiliary maps composited in the image's walk: per compacted record up
+// to four float4 of its attribute row (the depth rides in the record's third
+// float4, in place of the lane index that only the counting walk reads).
+struct MapSlots {
+    float4 a[64][4];
+};
+struct MapsArgs {
+    const ivrgs_job *jobs;
+    const int32_t *gauss_index;
+    const float4 *attr;  // rows of 4 kA floats per Gaussian
+    float *aux;          // [n_jobs][1 + n_attr][H][W]
+    int n_attr;
+};
+
 // Compacts the records of lanes with `touch` (ballot m) into the wave's
 // slots, in lane order; returns their number.
 __device__ __forceinline__ int compact_records(WaveSlots &slots, uint64_t m, bool touch, float4 r0, float4 r1,
@@ -237,12 +251,18 @@ __device__ __forceinline__ int compact_records(WaveSlots &slots, uint64_t m, boo
 // ckpt != nullptr: at every cut of the tile's list (split_of) the wave stores
 // each pixel's state before the cut, (T, C) with T = -1 for a pixel that has
 // already terminated, for the backward's segments.
-template <bool kMaxw, bool kCount>
+//
+// kA >= 0: the walk also composites the auxiliary maps with the same weights:
+// the record's depth and the kA float4 of its attribute row (the first
+// mp.n_attr values), written to mp.aux; no background term for the maps.
+template <bool kMaxw, bool kCount, int kA = -1>
 __device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__restrict__ rec,
                                               const uint32_t *__restrict__ starts,
                                               const uint32_t *__restrict__ sorted, float *__restrict__ out,
                                               float *__restrict__ maxw, int64_t *__restrict__ status, int64_t tile,
-                                              float4 *__restrict__ ckpt, WaveSlots &slots) {
+                                              float4 *__restrict__ ckpt, WaveSlots &slots,
+                                              const MapsArgs *mp = nullptr, MapSlots *ms = nullptr) {
+    static_assert(kA < 0 || !kCount, "the maps take the lane-index field of the counting walk");
     const TileGeom tg = tile_geom(k, tile);
     const uint32_t start = starts[tile], end = starts[tile + 1];
     walk_priority(end - start);
@@ -255,6 +275,14 @@ __device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__r
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
     uint32_t stop_at = end;  // list position of this pixel's terminating record
     uint32_t composited = 0;
+    // the maps: depth, then the attributes
+    constexpr int kAq = kA > 0 ? kA : 1;
+    float Dm = 0.f, Mv[4 * kAq];
+#pragma unroll
+    for (int c = 0; c < 4 * kAq; ++c) Mv[c] = 0.f;
+    float4 na[kAq], ca[kAq];
+    ivrgs_job job_m{};
+    if constexpr (kA >= 0) job_m = mp->jobs[tg.job];
 
     // Two-stage software pipeline over steps of 64 records: while one step
     // is composited, the records of the next are gathered with ids loaded a
@@ -271,6 +299,11 @@ __device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__r
             n0 = rec[kRecVec * (size_t)nid];
             n1 = rec[kRecVec * (size_t)nid + 1];
             n2 = rec[kRecVec * (size_t)nid + 2];
+            if constexpr (kA > 0) {
+                const int64_t gid = job_gaussian(job_m, mp->gauss_index, (int)(nid - job_m.rec_begin));
+#pragma unroll
+                for (int q = 0; q < kA; ++q) na[q] = mp->attr[(size_t)gid * kA + q];
+            }
         }
     };
     if (start < end) {
@@ -292,6 +325,10 @@ __device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__r
         const PixBox bx = alive_box(live, sx, sy);
         const float4 r0 = n0, r1 = n1, r2 = n2;
         const uint32_t rid = nid;
+        if constexpr (kA > 0) {
+#pragma unroll
+            for (int q = 0; q < kA; ++q) ca[q] = na[q];
+        }
         bool touch = false;
         if (base + lane < end) touch = box_hit(make_hit_test(r0, r1, r2), bx.x0, bx.y0, bx.w, bx.h);
         if (base + 64 < end) load_recs(base + 64);
@@ -299,6 +336,17 @@ __device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__r
         const uint64_t m = __ballot(touch);
         if (m == 0ull) continue;
         const int cnt = compact_records(slots, m, touch, r0, r1, r2, rid, lane);
+        if constexpr (kA >= 0) {
+            // the record's depth in place of its lane, and its attribute row
+            if (touch) {
+                const int slot =
+                    __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                slots.f[slot][2].w = r2.y;
+#pragma unroll
+                for (int q = 0; q < kA; ++q) ms->a[slot][q] = ca[q];
+            }
+            wave_lds_sync();
+        }
         // Records are visited in groups of kGroupFwd.  Phase 1 computes, with
         // no branch, everything that does not depend on the compositing
         // order (fields read from LDS at one address for the whole wave,
@@ -337,6 +385,17 @@ __device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__r
                 C0 = fmaf(w, cr[g], C0);
                 C1 = fmaf(w, cg[g], C1);
                 C2 = fmaf(w, cb[g], C2);
+                if constexpr (kA >= 0) {
+                    Dm = fmaf(w, slots.f[src[g]][2].w, Dm);
+#pragma unroll
+                    for (int q = 0; q < kA; ++q) {
+                        const float4 a4 = ms->a[src[g]][q];
+                        Mv[4 * q] = fmaf(w, a4.x, Mv[4 * q]);
+                        Mv[4 * q + 1] = fmaf(w, a4.y, Mv[4 * q + 1]);
+                        Mv[4 * q + 2] = fmaf(w, a4.z, Mv[4 * q + 2]);
+                        Mv[4 * q + 3] = fmaf(w, a4.w, Mv[4 * q + 3]);
+                    }
+                }
                 T = comp ? Tn : T;
                 if (kCount) {
                     composited += comp ? 1u : 0u;
@@ -363,6 +422,14 @@ __device__ __forceinline__ void fwd_tile_wave(const Consts &k, const float4 *__r
         img[plane + o] = C1 + T * k.bg1;
         img[2 * plane + o] = C2 + T * k.bg2;
         img[3 * plane + o] = 1.f - T;
+        if constexpr (kA >= 0) {
+            const int nc = 1 + mp->n_attr;
+            float *am = mp->aux + (size_t)tg.job * nc * plane + o;
+            am[0] = Dm;
+#pragma unroll
+            for (int c = 0; c < 4 * kAq; ++c)
+                if (kA > 0 && c < mp->n_attr) am[(size_t)(1 + c) * plane] = Mv[c];
+        }
         if (kCount) {
             // every list entry up to and including the terminating one is an
             // evaluation of the plain walk, skipped or not
@@ -387,6 +454,21 @@ __global__ __launch_bounds__(kTilePix / PX) void k_render_fwd(Consts k, const fl
                                      slots[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
     }
     else fwd_tile<PX, kMaxw, kCount>(k, rec, starts, sorted, out, maxw, status, blockIdx.x);
+}
+
+// The image and the auxiliary maps in one walk (one pixel per lane).
+template <int kA>
+__global__ __launch_bounds__(kTilePix) void k_render_fwd_maps(Consts k, const float4 *__restrict__ rec,
+                                                              const uint32_t *__restrict__ starts,
+                                                              const uint32_t *__restrict__ sorted, int64_t n_tiles,
+                                                              float *__restrict__ out, float4 *__restrict__ ckpt,
+                                                              MapsArgs mp) {
+    if (starts[n_tiles] == 0xFFFFFFFFu) return;
+    __shared__ WaveSlots slots[kTilePix / 64];
+    __shared__ MapSlots mslots[kA > 0 ? kTilePix / 64 : 1];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    fwd_tile_wave<false, false, kA>(k, rec, starts, sorted, out, nullptr, nullptr, blockIdx.x, ckpt, slots[wave], &mp,
+                                    &mslots[kA > 0 ? wave : 0]);
 }
 
 // Persistent variant: a fixed grid pops tiles from queue[2 ..] (heaviest
@@ -1031,6 +1113,27 @@ hipError_t launch_render_fwd(const Consts &k, int px, int64_t n_tiles, const flo
     case 1: fwd_variant<1>(mw, count, queue ? persistent_grid_fwd<1>(mw, count, per_cu) : dim3((unsigned)n_tiles), s, k, r4, starts, sorted, n_tiles, out, maxw, status, queue, ck); break;
     case 2: fwd_variant<2>(mw, count, queue ? persistent_grid_fwd<2>(mw, count, per_cu) : dim3((unsigned)n_tiles), s, k, r4, starts, sorted, n_tiles, out, maxw, status, queue, nullptr); break;
     default: fwd_variant<4>(mw, count, queue ? persistent_grid_fwd<4>(mw, count, per_cu) : dim3((unsigned)n_tiles), s, k, r4, starts, sorted, n_tiles, out, maxw, status, queue, nullptr); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_render_fwd_maps(const Consts &k, int64_t n_tiles, const float *rec, const uint32_t *starts,
+                                  const uint32_t *sorted, float *out, float *ckpt, const ivrgs_job *jobs,
+                                  const int32_t *gauss_index, const float *attr, int n_attr, float *aux,
+                                  hipStream_t s) {
+    if (n_tiles == 0) return hipSuccess;
+    const float4 *r4 = reinterpret_cast<const float4 *>(rec);
+    float4 *ck = reinterpret_cast<float4 *>(ckpt);
+    const MapsArgs mp{jobs, gauss_index, reinterpret_cast<const float4 *>(attr), aux, n_attr};
+    const dim3 grid((unsigned)n_tiles), block(kTilePix);
+    TimedScope ts(TK_FWD, s);
+    switch ((n_attr + 3) / 4) {
+    case 0: hipLaunchKernelGGL(k_render_fwd_maps<0>, grid, block, 0, s, k, r4, starts, sorted, n_tiles, out, ck, mp); break;
+    case 1: hipLaunchKernelGGL(k_render_fwd_maps<1>, grid, block, 0, s, k, r4, starts, sorted, n_tiles, out, ck, mp); break;
+    case 2: hipLaunchKernelGGL(k_render_fwd_maps<2>, grid, block, 0, s, k, r4, starts, sorted, n_tiles, out, ck, mp); break;
+    case 3: hipLaunchKernelGGL(k_render_fwd_maps<3>, grid, block, 0, s, k, r4, starts, sorted, n_tiles, out, ck, mp); break;
+    case 4: hipLaunchKernelGGL(k_render_fwd_maps<4>, grid, block, 0, s, k, r4, starts, sorted, n_tiles, out, ck, mp); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -32,7 +32,8 @@ EXPORTS = ("ivrgs_workspace_size", "ivrgs_tiles_per_job", "ivrgs_compose", "ivrg
            "ivrgs_reg_workspace_size", "ivrgs_reg_fwd", "ivrgs_reg_bwd", "ivrgs_bin_sort_noalloc",
            "ivrgs_l1_workspace_size", "ivrgs_l1_fwd", "ivrgs_l1_bwd", "ivrgs_editable_attr_fwd",
            "ivrgs_editable_attr_bwd", "ivrgs_render_bwd_aux",
-           "ivrgs_photometric_workspace_size", "ivrgs_photometric_fwd", "ivrgs_photometric_grad_dev")
+           "ivrgs_photometric_workspace_size", "ivrgs_photometric_fwd", "ivrgs_photometric_grad_dev",
+           "ivrgs_render_fwd_aux")
 NOALLOC_SCRATCH_BYTES = 64 << 20
 TIMING_KINDS = ("project", "tile_count", "scatter", "depth_sort", "render_fwd", "render_bwd",
                 "project_bwd", "compose", "fill", "cull", "edit_bwd", "vq", "sh", "aux")
@@ -187,6 +188,8 @@ def load(path: str = LIB_PATH):
     lib.ivrgs_render_aux_fwd.restype = C.c_int
     lib.ivrgs_render_aux_bwd.argtypes = [P, P, P, P, P, C.c_int32, P, P, P, P, P, C.c_size_t, P]
     lib.ivrgs_render_aux_bwd.restype = C.c_int
+    lib.ivrgs_render_fwd_aux.argtypes = [P, P, P, P, P, C.c_int32, P, P, P, C.c_size_t, P]
+    lib.ivrgs_render_fwd_aux.restype = C.c_int
     lib.ivrgs_render_bwd_aux.argtypes = [P, P, P, P, P, P, P, C.c_int32, P, P, P, P, P, C.c_size_t, P]
     lib.ivrgs_render_bwd_aux.restype = C.c_int
     lib.ivrgs_editable_attr_fwd.argtypes = [P, P, P, C.c_int64, P, P]
@@ -337,6 +340,12 @@ def ivrgs_render_aux_bwd(batch, params, proj, bins, attr_ptr, n_attr: int, aux_p
     check(load().ivrgs_render_aux_bwd(ref(batch), ref(params), ref(proj), ref(bins), attr_ptr, n_attr, aux_ptr,
                                       grad_aux_ptr, grad_attr_ptr, ref(grads), ws_ptr, ws_bytes, stream),
           "ivrgs_render_aux_bwd")
+
+
+def ivrgs_render_fwd_aux(batch, params, proj, bins, attr_ptr, n_attr: int, rgba_ptr, aux_ptr, ws_ptr, ws_bytes,
+                         stream):
+    check(load().ivrgs_render_fwd_aux(ref(batch), ref(params), ref(proj), ref(bins), attr_ptr, n_attr, rgba_ptr,
+                                      aux_ptr, ws_ptr, ws_bytes, stream), "ivrgs_render_fwd_aux")
 
 
 def ivrgs_render_bwd_aux(batch, params, proj, bins, rgba_ptr, dl_ptr, attr_ptr, n_attr: int, aux_ptr, grad_aux_ptr,

@@ -314,6 +314,23 @@ class Renderer:
         self._key = (id(batch), self.generation)
         return (rgba, maxw) if want_maxw else rgba
 
+    def forward_maps(self, planes, cams_t, jobs: Jobs, attr, n_attr: int, edits_t=None):
+        """Project, bin, then the image and the auxiliary maps (depth and the
+        first n_attr columns of the attribute rows attr [n, S]) in one walk
+        (ivrgs_render_fwd_aux); the image is the one forward() gives, and the
+        workspace holds its list checkpoints for the backward.  Returns
+        (rgba [n_jobs, 4, H, W], maps [n_jobs, 1 + n_attr, H, W])."""
+        batch = self.make_batch(planes, None, edits_t, cams_t, jobs)
+        proj, bins = self.project_and_bin(batch)
+        s = self.settings
+        rgba = torch.empty((jobs.n_jobs, 4, s.height, s.width), dtype=torch.float32, device=self.device)
+        maps = torch.empty((jobs.n_jobs, 1 + n_attr, s.height, s.width), dtype=torch.float32, device=self.device)
+        N.ivrgs_render_fwd_aux(batch, s.params(), proj, bins, attr.data_ptr() if n_attr else None, n_attr,
+                               rgba.data_ptr(), maps.data_ptr(), self.ws.data_ptr(), self.ws.numel(), _stream())
+        self._ckpt_generation = self.generation
+        self._key = (id(batch), self.generation)
+        return rgba, maps
+
     def prepare_backward(self, batch, rebin: bool = False):
         """The projection and bins a backward of `batch` reads, with the
         forward's list checkpoints in the workspace: with rebin (the buffers

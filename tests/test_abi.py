@@ -56,6 +56,8 @@ def test_host_validation(lib):
                                     None, 0, None) == N.E_INVALID  # more than 15 attributes
     assert lib.ivrgs_render_bwd_aux(N.ref(b), N.ref(p), None, None, None, None, C.c_void_p(260), 3, fake, fake,
                                     fake, None, None, 0, None) == N.E_INVALID  # unaligned rows
+    assert lib.ivrgs_render_fwd_aux(N.ref(b), N.ref(p), None, None, None, 0, fake, fake, None, 0,
+                                    None) == N.E_INVALID  # no projection or bins
     pd = N.ivrgs_params.from_buffer_copy(p)
     pd.flags = N.FLAG_DETERMINISTIC_BWD
     assert lib.ivrgs_render_bwd_aux(N.ref(b), N.ref(pd), None, None, None, None, None, 0, fake, fake, None, None,

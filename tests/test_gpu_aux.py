@@ -19,6 +19,7 @@ import oracle as O
 from oracle import dense as D
 from paper_2504_17954_amd import aux as AX
 from paper_2504_17954_amd import inputs as I
+from paper_2504_17954_amd import native as N
 from paper_2504_17954_amd import raster as R
 
 pytestmark = pytest.mark.gpu
@@ -207,3 +208,54 @@ def test_maps_reuse_the_image_bins(dev):
     for k in a[2]:
         np.testing.assert_allclose(a[2][k], b[2][k], rtol=1e-5, atol=1e-6 * max(np.abs(b[2][k]).max(), 1e-30))
     np.testing.assert_allclose(a[3], b[3], rtol=1e-5, atol=1e-6 * np.abs(b[3]).max())
+
+
+@pytest.mark.parametrize("n_attr", [0, 3, 10, 15])
+def test_one_walk_image_and_maps_equal_the_two_walks(dev, n_attr):
+    """ivrgs_render_fwd_aux against ivrgs_render_fwd (one pixel per lane)
+    and ivrgs_render_aux_fwd on the same bins: the same image bit for bit,
+    and the same maps (the same weights and additions in list order).  Two
+    jobs over overlapping ranges, and a view of 30k Gaussians at 160x144
+    whose lists are long enough to be cut for the backward (the checkpoints
+    are then checked through a backward: identical gradients)."""
+    for case in ("two_jobs", "long_lists"):
+        if case == "two_jobs":
+            n = 300
+            planes, cam0, prm = small(n, 45)
+            cam1 = I.look_at((-2.0, -3.0, 1.5), width=prm.width, height=prm.height)
+            cams, jobs = [cam0, cam1], R.Jobs.ranges([0, 1], [0, 80], [n, n - 80])
+            W, H = prm.width, prm.height
+        else:
+            m = I.small_scene(30_000, 812, log_scale_mu=-3.4)
+            planes = I.plain_planes(m)
+            n, W, H = m.n, 160, 144
+            cams, jobs = [I.look_at((0.2, -3.0, 0.6), width=W, height=H)], R.Jobs.single(m.n)
+        rng = np.random.default_rng(n_attr + 7)
+        S = (n_attr + 3) // 4 * 4
+        rows = np.zeros((n, S), np.float32)
+        rows[:, :n_attr] = rng.normal(size=(n, n_attr))
+        pd = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in planes.items()}
+        ad = torch.from_numpy(rows).to(dev)
+        cams_t = R.camera_table(cams, dev)
+        edits = R.default_edits(dev)
+        say(f"one walk vs two, {case}, n_attr={n_attr}")
+        rnd = R.Renderer(R.Settings(W, H, fwd_px=1, bwd_px=1))
+        img1, maps1 = rnd.forward_maps(pd, cams_t, jobs, ad, n_attr, edits)
+        dl = torch.from_numpy(rng.normal(size=tuple(img1.shape)).astype(np.float32)).to(dev)
+        g1 = rnd.backward(pd, cams_t, jobs, img1, dl, edits_t=edits)
+        g1 = {k: v.clone() for k, v in g1.items()}
+        img2 = rnd.forward(pd, cams_t, jobs, edits_t=edits)
+        batch = rnd.make_batch(pd, None, edits, cams_t, jobs)
+        proj, bins = rnd._structs(batch)
+        maps2 = torch.empty_like(maps1)
+        N.ivrgs_render_aux_fwd(batch, rnd.settings.params(), proj, bins, ad.data_ptr() if n_attr else None, n_attr,
+                               maps2.data_ptr(), None)
+        g2 = rnd.backward(pd, cams_t, jobs, img2, dl, edits_t=edits)
+        torch.cuda.synchronize()
+        assert torch.equal(img1, img2)
+        err = (maps1 - maps2).abs().max().item()
+        say(f"  image identical; maps max diff {err:.3e}")
+        assert err <= 1e-6 * max(1.0, maps2.abs().max().item())
+        for k in R.PLANES:  # float atomics: equal to rounding
+            a, b = g1[k].cpu().numpy(), g2[k].cpu().numpy()
+            assert np.all(np.abs(a - b) <= 1e-4 * np.abs(b) + 1e-5 * np.abs(b).max() + 1e-30), k
