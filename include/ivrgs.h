@@ -606,8 +606,9 @@ ivrgs_status ivrgs_render_fwd_aux(const ivrgs_batch *batch, const ivrgs_params *
 /* The image's backward and the maps' backward in one call (the training
  * step of the editable stage differentiates both; Eq. 2 and Eq. 5): the
  * result of ivrgs_render_bwd for dl_drgba plus that of ivrgs_render_aux_bwd
- * for grad_aux, summed into one set of record gradients that one projection
- * backward takes to grads.  grads is WRITTEN as by ivrgs_render_bwd (no
+ * for grad_aux, from one walk over the lists (the image's colour is three
+ * more channels of the maps' walk), summed into one set of record gradients
+ * that one projection backward takes to grads.  grads is WRITTEN as by ivrgs_render_bwd (no
  * clearing needed); grad_attr (device [g.n][S], S = n_attr rounded up to a
  * multiple of 4) is cleared, then written, pad entries included.  Arguments
  * as in those two calls, over the same batch, params, bins and workspace;

@@ -757,9 +757,9 @@ struct AuxBwdArgs {
     int n_attr;
 };
 
-// The image's backward, and with `ax` the maps' in the same pass over the
-// record-gradient rows: clear the rows (and the attribute gradients), the
-// image walk, the maps' walk, one projection backward.
+// The image's backward, and with `ax` the maps' too in the same walk: clear
+// the record-gradient rows (and the attribute gradients), one walk, one
+// projection backward.
 ivrgs_status render_bwd_run(const ivrgs_batch *batch, const ivrgs_params *params, const ivrgs_projected *proj,
                             const ivrgs_bins *bins, const float *out_rgba, const float *dl_drgba,
                             ivrgs_gaussians_mut *grads, const AuxBwdArgs *ax, void *workspace, size_t workspace_bytes,
@@ -793,7 +793,7 @@ ivrgs_status render_bwd_run(const ivrgs_batch *batch, const ivrgs_params *params
                              ax->n_attr > 0 ? batch->g.n * (int64_t)((ax->n_attr + 3) / 4 * 4) : 0, 0u, s);
     else if (!det)
         e = launch_fill_u32(reinterpret_cast<uint32_t *>(grec), n_grec, 0u, s);
-    if (e == hipSuccess)
+    if (e == hipSuccess && !ax)
         e = launch_render_bwd(k, pick_px(params->bwd_px, 1), n_tiles, proj->rec, bins->tile_start, bins->sorted,
                               out_rgba, dl_drgba, grec,
                               (params->flags & IVRGS_FLAG_PERSISTENT)
@@ -803,9 +803,11 @@ ivrgs_status render_bwd_run(const ivrgs_batch *batch, const ivrgs_params *params
                               L.ckpt_bytes ? reinterpret_cast<const float *>(static_cast<char *>(workspace) + L.ckpt)
                                            : nullptr,
                               det ? &dw : nullptr, batch->n_records, s);
+    // with the maps: one walk for both backwards (the image's colour as
+    // three more channels of the maps' walk)
     if (e == hipSuccess && ax)
         e = launch_aux_bwd(*batch, k, n_tiles, proj->rec, bins->tile_start, bins->sorted, ax->attr, ax->n_attr,
-                           ax->aux, ax->grad_aux, grec, ax->grad_attr, s);
+                           ax->aux, ax->grad_aux, grec, ax->grad_attr, s, out_rgba, dl_drgba);
     // One job over the whole set (its range lies in [0, n) and has n
     // records) writes every Gaussian's gradient, zeros included; otherwise
     // the planes are cleared first and, when several jobs may share a

@@ -20,7 +20,9 @@ namespace ivrgs {
 
 namespace {
 
-constexpr int kAuxAcc = 7 + kAuxMax;  // per-record sums of the backward: GO, GX, GY, GQA..GQC, depth, attributes
+// per-record sums of the backward: GO, GX, GY, GQA..GQC, the image's colour
+// (when the image's backward is folded in), depth, attributes
+constexpr int kAuxAcc = 7 + 3 + kAuxMax;
 static_assert(2 * kAuxAcc <= 64, "at least two records per reduce-scatter of 64 values");
 
 // Per-wave LDS: the compacted records of one step.
@@ -33,6 +35,7 @@ struct AuxSlots {
     float4 f0[64];             // mean x, mean y, qa, qb
     float4 f1[64];             // qc, opacity, depth, cutoff
     float4 sa[kAuxQuads][64];  // attribute row, four at a time
+    float4 fc[64];             // the image's colour r, g, b (the backward with the image folded in)
     uint32_t rid[64], gid[64];
 };
 
@@ -93,6 +96,7 @@ struct AuxWalk {
             const int slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
             S.f0[slot] = r0;
             S.f1[slot] = make_float4(r1.x, r1.y, r2.y, r2.z);
+            S.fc[slot] = make_float4(r1.z, r1.w, r2.x, 0.f);
 #pragma unroll
             for (int q = 0; q < kAuxQuads; ++q)
                 if (4 * q < n_attr) S.sa[q][slot] = a[q];
@@ -200,22 +204,31 @@ __global__ __launch_bounds__(kTilePix) void k_aux_fwd(ivrgs_batch b, Consts k, c
 // same record-gradient moments as the image backward.  Records are visited
 // kG at a time (kN attributes: kG = min(4, 64 / (7 + kN)) records of 7 + kN
 // values fill one 64-value reduce-scatter): the order-free part (offset,
-// exponent, alpha, 1 / (1 - alpha), ga, the cutoff, alpha-min and cap tests)
+// exponent, alpha, 1 / (1 - alpha), ga, the alpha-min and cap tests)
 // of the group first, then the front-to-back chain, then one reduce-scatter
 // of the group's values; lane v adds value v % (7 + kN) of record v / (7 +
 // kN) to the record gradients (for the projection backward), the attribute
 // gradients or, for the depth, the record's depth slot GZ (the projection
 // backward takes it to the mean: depth = row 3 of R applied to the mean,
 // plus t).
-template <int kN>
+//
+// kImg: the image's backward in the same walk.  Its colour is three more
+// channels with gradient dL/d(rgb) of the image (rgba, dl), its alpha
+// channel and background enter through g . out - dL/dA T_final, the same
+// terms as the image backward's; the moments then come from the summed
+// dL/dalpha, and the three colour sums go to the record gradients
+// GCR..GCB.
+template <int kN, bool kImg>
 __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, const float4 *__restrict__ rec,
                                                       const uint32_t *__restrict__ starts,
                                                       const uint32_t *__restrict__ sorted, int64_t n_tiles,
                                                       const float *__restrict__ attr,
                                                       const float *__restrict__ aux, const float *__restrict__ gaux,
+                                                      const float *__restrict__ rgba, const float *__restrict__ dl,
                                                       float *__restrict__ grec, float *__restrict__ gattr) {
+    constexpr int kNi = kImg ? 3 : 0;                        // the image's colour channels
     constexpr int kNv = 1 + kN;                              // depth, attributes
-    constexpr int kVpr = 6 + kNv;                            // values per record
+    constexpr int kVpr = 6 + kNi + kNv;                      // values per record
     constexpr int kG = 64 / kVpr < 4 ? 64 / kVpr : 4;        // records per reduce-scatter
     constexpr int kQ = (kN + 3) / 4;                         // float4s of an attribute row
     if (starts[n_tiles] == 0xFFFFFFFFu) return;
@@ -244,6 +257,21 @@ __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, c
     bool any_g = false;
 #pragma unroll
     for (int c = 0; c < kNv; ++c) any_g |= g[c] != 0.f;
+    // the image: gradient of its colour, and g . out - dL/dA T_final
+    float gi0 = 0.f, gi1 = 0.f, gi2 = 0.f;
+    if constexpr (kImg) {
+        if (inside) {
+            const int64_t plane = (int64_t)k.width * k.height;
+            const int64_t o = (int64_t)ji * 4 * plane + (int64_t)y * k.width + x;
+            gi0 = dl[o];
+            gi1 = dl[plane + o];
+            gi2 = dl[2 * plane + o];
+            const float gAi = dl[3 * plane + o];
+            const float go = fmaf(gi2, rgba[2 * plane + o], fmaf(gi1, rgba[plane + o], gi0 * rgba[o]));
+            gA += go - gAi * (1.f - rgba[3 * plane + o]);
+            any_g |= (gi0 != 0.f) | (gi1 != 0.f) | (gi2 != 0.f) | (gAi != 0.f);
+        }
+    }
     float T = 1.f, gP = 0.f;
     bool alive = inside & any_g;
     const uint32_t start = starts[tile], end = starts[tile + 1];
@@ -295,6 +323,10 @@ __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, c
                     if (4 * q + 2 < kN) d = fmaf(g[3 + 4 * q], a4.z, d);
                     if (4 * q + 3 < kN) d = fmaf(g[4 + 4 * q], a4.w, d);
                 }
+                if constexpr (kImg) {
+                    const float4 c4 = S.fc[src[gg]];
+                    d = fmaf(gi2, c4.z, fmaf(gi1, c4.y, fmaf(gi0, c4.x, d)));
+                }
                 ga[gg] = d;
                 // the alpha test alone (below the cutoff alpha < alpha_min
                 // is certain: the two decide the same)
@@ -322,8 +354,13 @@ __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, c
                 v[3] = dpx * dx[gg];  // GQA
                 v[4] = dpx * dy[gg];  // GQB
                 v[5] = dpy * dy[gg];  // GQC
+                if constexpr (kImg) {
+                    v[6] = w * gi0;  // GCR .. GCB
+                    v[7] = w * gi1;
+                    v[8] = w * gi2;
+                }
 #pragma unroll
-                for (int c = 0; c < kNv; ++c) v[6 + c] = w * g[c];  // depth, attributes
+                for (int c = 0; c < kNv; ++c) v[6 + kNi + c] = w * g[c];  // depth, attributes
                 T = comp ? Tn : T;
                 alive = alive & !stop;
                 any = any | comp;
@@ -340,10 +377,12 @@ __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, c
                     if (my_v < 6) {
                         const int row = my_v == 0 ? GO : (my_v == 1 ? GX : (my_v == 2 ? GY : GQA + (my_v - 3)));
                         atomicAdd(&grec[(size_t)r * kGradStride + row], tot);
-                    } else if (my_v == 6) {
+                    } else if (my_v < 6 + kNi) {
+                        atomicAdd(&grec[(size_t)r * kGradStride + GCR + (my_v - 6)], tot);
+                    } else if (my_v == 6 + kNi) {
                         atomicAdd(&grec[(size_t)r * kGradStride + GZ], tot);
                     } else {
-                        atomicAdd(&gattr[gi * attr_stride(kN) + (my_v - 7)], tot);
+                        atomicAdd(&gattr[gi * attr_stride(kN) + (my_v - 7 - kNi)], tot);
                     }
                 }
             }
@@ -421,15 +460,20 @@ hipError_t launch_aux_fwd(const ivrgs_batch &b, const Consts &k, int64_t n_tiles
 hipError_t launch_aux_bwd(const ivrgs_batch &b, const Consts &k, int64_t n_tiles, const float *rec,
                           const uint32_t *starts, const uint32_t *sorted, const float *attr, int n_attr,
                           const float *aux, const float *grad_aux, float *grec, float *grad_attr,
-                          hipStream_t s) {
+                          hipStream_t s, const float *rgba, const float *dl) {
     if (n_tiles == 0) return hipSuccess;
     TimedScope ts(TK_AUX, s);
     const float4 *rec4 = reinterpret_cast<const float4 *>(rec);
+    const bool img = rgba != nullptr;
     switch (n_attr) {
 #define IVRGS_AUX_BWD(N)                                                                                       \
     case N:                                                                                                    \
-        hipLaunchKernelGGL(k_aux_bwd<N>, dim3((unsigned)n_tiles), dim3(kTilePix), 0, s, b, k, rec4, starts, sorted, \
-                           n_tiles, attr, aux, grad_aux, grec, grad_attr);                                     \
+        if (img)                                                                                               \
+            hipLaunchKernelGGL((k_aux_bwd<N, true>), dim3((unsigned)n_tiles), dim3(kTilePix), 0, s, b, k, rec4,  \
+                               starts, sorted, n_tiles, attr, aux, grad_aux, rgba, dl, grec, grad_attr);         \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_aux_bwd<N, false>), dim3((unsigned)n_tiles), dim3(kTilePix), 0, s, b, k, rec4, \
+                               starts, sorted, n_tiles, attr, aux, grad_aux, nullptr, nullptr, grec, grad_attr); \
         break;
         IVRGS_AUX_BWD(0) IVRGS_AUX_BWD(1) IVRGS_AUX_BWD(2) IVRGS_AUX_BWD(3) IVRGS_AUX_BWD(4) IVRGS_AUX_BWD(5)
         IVRGS_AUX_BWD(6) IVRGS_AUX_BWD(7) IVRGS_AUX_BWD(8) IVRGS_AUX_BWD(9) IVRGS_AUX_BWD(10) IVRGS_AUX_BWD(11)

@@ -136,7 +136,10 @@ hipError_t launch_aux_fwd(const ivrgs_batch &b, const Consts &k, int64_t n_tiles
                           hipStream_t s);
 hipError_t launch_aux_bwd(const ivrgs_batch &b, const Consts &k, int64_t n_tiles, const float *rec,
                           const uint32_t *starts, const uint32_t *sorted, const float *attr, int n_attr,
-                          const float *aux, const float *grad_aux, float *grec, float *grad_attr, hipStream_t s);
+                          const float *aux, const float *grad_aux, float *grec, float *grad_attr, hipStream_t s,
+                          const float *rgba = nullptr, const float *dl = nullptr);
+// (rgba, dl: the image and dL/d(image), or null: with them the image's
+// backward runs in the same walk, its colour sums into GCR..GCB.)
 // Attribute rows [n][12] of the editable stage from the normal, colour and
 // shade planes, and their backward (adds into the plane gradients).
 hipError_t launch_edit_attr_fwd(const float *normal, const float *color, const float *shade, int64_t n, float *attr,

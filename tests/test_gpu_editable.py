@@ -166,3 +166,52 @@ def test_editable_loss_matches_oracle(dev, H, W, seed):
     check_grad(gm[4:7], ref["grad_delta_c"], "d/ddelta-c map")
     check_grad(gm[7:11], ref["grad_shade"], "d/dshade maps")
     check_grad(op.grad.cpu().numpy(), ref["grad_opacity"], "d/dopacity")
+
+
+def test_combined_backward_equals_the_two_backwards(dev):
+    """ivrgs_render_bwd_aux (one walk for the image's and the maps'
+    backward) against ivrgs_render_bwd plus ivrgs_render_aux_bwd on the same
+    bins, 30k Gaussians at 160x144 (lists of thousands of records, which the
+    image's own backward cuts into segments): every plane's gradient and
+    the attribute rows' gradient to rounding (float atomics on both sides)."""
+    m = I.small_scene(30_000, 813, log_scale_mu=-3.4)
+    planes = I.plain_planes(m)
+    n, W, H = m.n, 160, 144
+    cam = I.look_at((0.2, -3.0, 0.6), width=W, height=H)
+    pd = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in planes.items()}
+    cams_t, jobs, edits = R.camera_table([cam], dev), R.Jobs.single(n), R.default_edits(dev)
+    rnd = R.Renderer(R.Settings(W, H))
+    attr = AX.editable_attributes(pd).detach().contiguous()
+    rgba, maps = rnd.forward_maps(pd, cams_t, jobs, attr, AX.EDITABLE_ATTRS, edits)
+    rng = np.random.default_rng(14)
+    dl = torch.from_numpy(rng.normal(size=tuple(rgba.shape)).astype(np.float32)).to(dev)
+    gm = torch.from_numpy(rng.normal(size=tuple(maps.shape)).astype(np.float32)).to(dev)
+    batch = rnd.make_batch(pd, None, edits, cams_t, jobs)
+    proj, bins = rnd._structs(batch)
+    prm = rnd.settings.params()
+    s = torch.cuda.current_stream().cuda_stream
+
+    def planes_out():
+        return {k: torch.full((d, n), float("nan"), device=dev) for k, d in R.PLANE_DIMS.items()}
+
+    say("combined backward vs two backwards, 30k Gaussians, 160x144")
+    g1, ga1 = planes_out(), torch.full_like(attr, float("nan"))
+    N.ivrgs_render_bwd_aux(batch, prm, proj, bins, rgba.data_ptr(), dl.data_ptr(), attr.data_ptr(),
+                           AX.EDITABLE_ATTRS, maps.data_ptr(), gm.data_ptr(), ga1.data_ptr(),
+                           N.ivrgs_gaussians(n, *[g1[k].data_ptr() for k in R.PLANES], None), rnd.ws.data_ptr(),
+                           rnd.ws.numel(), s)
+    g2 = planes_out()
+    N.ivrgs_render_bwd(batch, prm, proj, bins, rgba.data_ptr(), dl.data_ptr(),
+                       N.ivrgs_gaussians(n, *[g2[k].data_ptr() for k in R.PLANES], None), rnd.ws.data_ptr(),
+                       rnd.ws.numel(), s)
+    ga2 = torch.zeros_like(attr)
+    N.ivrgs_render_aux_bwd(batch, prm, proj, bins, attr.data_ptr(), AX.EDITABLE_ATTRS, maps.data_ptr(),
+                           gm.data_ptr(), ga2.data_ptr(),
+                           N.ivrgs_gaussians(n, *[g2[k].data_ptr() for k in R.PLANES], None), rnd.ws.data_ptr(),
+                           rnd.ws.numel(), s)
+    torch.cuda.synchronize()
+    for k in R.PLANES:
+        check_grad(g1[k].cpu().numpy(), g2[k].cpu().numpy(), f"d/d{k}", rel=1e-4, floor=1e-5)
+    a1, a2 = ga1.cpu().numpy(), ga2.cpu().numpy()
+    assert np.all(a1[:, 10:] == 0.0)
+    check_grad(a1[:, :10], a2[:, :10], "d/dattr", rel=1e-4, floor=1e-5)
