@@ -205,8 +205,10 @@ __device__ __forceinline__ void fwd_tile(const Consts &k, const float4 *__restri
 // 64 that can reach the wave's pixels, compacted in list order, three float4
 // each: (x, y, qa, qb), (qc, cutoff, opacity, r), (g, b, id, lane of the
 // record in its step).
+// The backward reads its groups of three at fixed offsets from the group's
+// first slot, so a group that starts at slot 63 reads two spare slots.
 struct WaveSlots {
-    float4 f[64][3];
+    float4 f[64 + 2][3];
 };
 
 // The auxiliary maps composited in the image's walk: per compacted record up
@@ -850,6 +852,12 @@ __device__ __forceinline__ void bwd_tile_quad(const Consts &k, const float4 *__r
     SinkLane<kMode> out;
     out.init(sink, my_v);
     float acc[32];
+    // every slot starts as the zero record (opacity 0: no power anywhere)
+    {
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        slots.f[lane][0] = slots.f[lane][1] = slots.f[lane][2] = z;
+        if (lane < 2) slots.f[64 + lane][0] = slots.f[64 + lane][1] = slots.f[64 + lane][2] = z;
+    }
 
     // the two-stage gather pipeline of fwd_tile_wave
     float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0, n2 = n0;
@@ -885,15 +893,18 @@ __device__ __forceinline__ void bwd_tile_quad(const Consts &k, const float4 *__r
         // every compacted record is visited: the cutoff test is part of its
         // order-free work (a separate pass to drop the records that pass at no
         // live pixel costs more than it saves)
-        uint64_t pm = cnt == 64 ? ~0ull : ((1ull << cnt) - 1ull);
-        while (pm) {
+        // the compacted records are slots 0 .. cnt - 1, in list order: a group
+        // is kGroup consecutive slots (one address for the group, the records
+        // at fixed offsets from it)
+        for (int sl = 0; sl < cnt; sl += kGroup) {
             int src[kGroup];
             bool valid[kGroup];
 #pragma unroll
             for (int g = 0; g < kGroup; ++g) {
-                valid[g] = pm != 0ull;  // wave-uniform
-                src[g] = valid[g] ? (int)__builtin_ctzll(pm) : src[0];
-                pm &= pm - 1;
+                valid[g] = sl + g < cnt;  // wave-uniform
+                // a slot past the step's records holds a finite record (an
+                // earlier step's, or the zero record): its terms are masked
+                src[g] = sl + g;
             }
             // order-free part of the three records: everything but T
             float dx[kGroup], dy[kGroup], G[kGroup], raw[kGroup], al[kGroup], om[kGroup], inv[kGroup], gc[kGroup];
