@@ -687,7 +687,8 @@ ivrgs_status ivrgs_photometric_fwd(const float *x, const float *y, int32_t chann
 /* Gradient with respect to x of weights[0] * (mean SSIM) + weights[1] *
  * (mean |x - y|), weights device float[2] (a training loop's upstream
  * gradient times the loss weights, never read on the host): the L1 + D-SSIM
- * loss of ivrgs_photometric_grad with lam is weights (-lam, 1 - lam).  Same
+ * photometric loss of Sec. 4.2 (ivrgs_photometric_grad with lam) is weights
+ * (-lam, 1 - lam).  Same
  * workspace, layout and error behaviour as ivrgs_photometric_grad; grad_x
  * overwritten.  One launch. */
 ivrgs_status ivrgs_photometric_grad_dev(const float *x, const float *y, int32_t channels, int32_t height,
