@@ -31,11 +31,14 @@ constexpr int kAuxQuads = (kAuxMax + 3) / 4;  // float4s per attribute row
 // Row stride of the attributes: n_attr rounded up to a multiple of 4.
 __host__ __device__ __forceinline__ int attr_stride(int n_attr) { return (n_attr + 3) & ~3; }
 
+// The backward reads a group of up to four records at fixed offsets from
+// its first slot, so a group that starts at slot 63 reads three spare slots.
+constexpr int kAuxSlots = 64 + 3;
 struct AuxSlots {
-    float4 f0[64];             // mean x, mean y, qa, qb
-    float4 f1[64];             // qc, opacity, depth, cutoff
-    float4 sa[kAuxQuads][64];  // attribute row, four at a time
-    float4 fc[64];             // the image's colour r, g, b (the backward with the image folded in)
+    float4 f0[kAuxSlots];             // mean x, mean y, qa, qb
+    float4 f1[kAuxSlots];             // qc, opacity, depth, cutoff
+    float4 sa[kAuxQuads][kAuxSlots];  // attribute row, four at a time
+    float4 fc[kAuxSlots];             // the image's colour r, g, b (the backward with the image folded in)
     uint32_t rid[64], gid[64];
 };
 
@@ -281,6 +284,13 @@ __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, c
 #pragma unroll
     for (int q = kG * kVpr; q < 64; ++q) acc[q] = 0.f;  // never written
     AuxWalk W(b, job, rec, sorted, attr, kN, lane, end);
+    // every slot starts as the zero record (opacity 0: no power anywhere)
+    for (int i = lane; i < kAuxSlots; i += 64) {
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        S.f0[i] = S.f1[i] = S.fc[i] = z;
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) S.sa[q][i] = z;
+    }
     if (start < end) {
         W.load_ids(start);
         W.load_recs(start);
@@ -290,15 +300,17 @@ __global__ __launch_bounds__(kTilePix) void k_aux_bwd(ivrgs_batch b, Consts k, c
         const uint64_t live = __ballot(alive);
         if (live == 0ull) break;
         const int cnt = W.step(base, alive_box(live, sx, sy), S);
-        uint64_t pm = cnt == 64 ? ~0ull : ((1ull << cnt) - 1ull);
-        while (pm) {
+        // the compacted records are slots 0 .. cnt - 1, in list order: a group
+        // is kG consecutive slots, read at fixed offsets from its first
+        for (int sl = 0; sl < cnt; sl += kG) {
             int src[kG];
             bool valid[kG];
 #pragma unroll
             for (int gg = 0; gg < kG; ++gg) {
-                valid[gg] = pm != 0ull;  // wave-uniform
-                src[gg] = valid[gg] ? (int)__builtin_ctzll(pm) : src[0];
-                pm &= pm - 1;
+                valid[gg] = sl + gg < cnt;  // wave-uniform
+                // a slot past the step's records holds a finite record (an
+                // earlier step's, or the zero record): its terms are masked
+                src[gg] = sl + gg;
             }
             // order-free part of the group
             float dx[kG], dy[kG], G[kG], raw[kG], al[kG], om[kG], inv[kG], ga[kG];
